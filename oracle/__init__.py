@@ -1,0 +1,171 @@
+"""CPU oracle — TEST INFRASTRUCTURE ONLY.
+
+A plain, slow C implementation (``oracle.c``) of what the LSH similarity
+search of Rong et al. (VLDB 2018) computes: MinHash / Min-Max signatures and
+band keys (section 6.1, section 6.2, Appendix D Algorithm 1), hash tables,
+the occurrence filter (section 6.5), self-match exclusion (section 7.1) and
+per-pair vote counts (section 6.1 "Search", section 7.2 triplets).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU path.
+The readings taken where the paper is silent are listed in ``oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+P = 2**31 - 1
+MINHASH, MINMAX = 0, 1
+
+
+def build() -> str:
+    tmp = _SO + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", _SRC, "-o", tmp])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in
+                ("n_out", "e_raw", "e_voted", "n_distinct", "n_flagged", "max_bucket")]
+
+
+_LIB = None
+_vp, _u32, _u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        lib.orc_splitmix64_stream.argtypes = [_u64, _u32, _vp]
+        lib.orc_make_hash.argtypes = [_u64, _u32, _vp, _vp]
+        lib.orc_hash.argtypes = [_u32, _u32, _u32]
+        lib.orc_hash.restype = _u32
+        lib.orc_key_bits.argtypes = [_u32]
+        lib.orc_key_bits.restype = _u32
+        lib.orc_band_key.argtypes = [_vp, _u32, _u32]
+        lib.orc_band_key.restype = _u64
+        lib.orc_signatures.argtypes = [_u32, _u32, _u32, _u32, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp]
+        lib.orc_signatures.restype = ctypes.c_int
+        lib.orc_search_keys.argtypes = [_u32, _u64, _vp, _u32, _u32, _u32, _u32,
+                                        ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                        ctypes.POINTER(_Stats), _vp]
+        lib.orc_search_keys.restype = ctypes.c_int
+        lib.orc_pair_votes.argtypes = [_u32, _u64, _vp, _u64, _u64]
+        lib.orc_pair_votes.restype = _u32
+        lib.orc_free.argtypes = [_vp]
+        _LIB = lib
+    return _LIB
+
+
+@dataclass
+class Stats:
+    n_out: int
+    e_raw: int
+    e_voted: int
+    n_distinct: int
+    n_flagged: int
+    max_bucket: int
+
+
+def splitmix64_stream(seed: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint64)
+    _lib().orc_splitmix64_stream(seed, count, out.ctypes.data)
+    return out
+
+
+def n_funcs(t: int, r: int, scheme: int) -> int:
+    return t * r if scheme == MINHASH else t * (r // 2)
+
+
+def make_hash(seed: int, nf: int):
+    a = np.empty(nf, dtype=np.uint32)
+    b = np.empty(nf, dtype=np.uint32)
+    _lib().orc_make_hash(seed, nf, a.ctypes.data, b.ctypes.data)
+    return a, b
+
+
+def hash_value(a: int, b: int, x: int) -> int:
+    return int(_lib().orc_hash(a, b, x))
+
+
+def key_bits(dim: int) -> int:
+    return int(_lib().orc_key_bits(dim))
+
+
+def band_key(argx, dim: int) -> int:
+    arr = np.ascontiguousarray(argx, dtype=np.uint32)
+    return int(_lib().orc_band_key(arr.ctypes.data, len(arr), dim))
+
+
+def _rows(rows):
+    """Accept a uint16[n, nnz] array (fixed nnz) or a (indices, offsets) pair."""
+    if isinstance(rows, tuple):
+        ind, off = rows
+        ind = np.ascontiguousarray(ind, dtype=np.uint16)
+        off = np.ascontiguousarray(off, dtype=np.uint64)
+        return ind, off, len(off) - 1, 0
+    rows = np.ascontiguousarray(rows, dtype=np.uint16)
+    return rows, None, rows.shape[0], rows.shape[1]
+
+
+def signatures(rows, dim: int, t: int, r: int, scheme: int, a, b, with_values: bool = False):
+    """keys uint64[t, n]; with ``with_values`` also the values uint32[n, t, r]."""
+    ind, off, n, nnz = _rows(rows)
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    b = np.ascontiguousarray(b, dtype=np.uint32)
+    keys = np.empty((t, n), dtype=np.uint64)
+    sigs = np.empty((n, t, r), dtype=np.uint32) if with_values else None
+    rc = _lib().orc_signatures(dim, t, r, scheme, a.ctypes.data, b.ctypes.data, n,
+                               off.ctypes.data if off is not None else None, nnz, ind.ctypes.data,
+                               keys.ctypes.data, sigs.ctypes.data if with_values else None)
+    if rc != 0:
+        raise ValueError("oracle: invalid hash parameters or fingerprints")
+    return (keys, sigs) if with_values else keys
+
+
+def search_keys(keys: np.ndarray, min_lag: int, min_votes: int, occ_num: int = 0, occ_den: int = 0,
+                want_flags: bool = False):
+    """(i, j, votes, Stats[, flags]) from table-major band keys uint64[t, n]."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    t, n = keys.shape
+    pi, pj, pv = _vp(), _vp(), _vp()
+    st = _Stats()
+    flags = np.empty(n, dtype=np.uint8) if want_flags else None
+    rc = _lib().orc_search_keys(t, n, keys.ctypes.data, min_lag, min_votes, occ_num, occ_den,
+                                ctypes.byref(pi), ctypes.byref(pj), ctypes.byref(pv), ctypes.byref(st),
+                                flags.ctypes.data if want_flags else None)
+    if rc != 0:
+        raise ValueError("oracle: invalid search parameters")
+    m = st.n_out
+    oi = np.ctypeslib.as_array(ctypes.cast(pi, ctypes.POINTER(ctypes.c_uint32)), (m,)).copy() if m else np.empty(0, np.uint32)
+    oj = np.ctypeslib.as_array(ctypes.cast(pj, ctypes.POINTER(ctypes.c_uint32)), (m,)).copy() if m else np.empty(0, np.uint32)
+    ov = np.ctypeslib.as_array(ctypes.cast(pv, ctypes.POINTER(ctypes.c_uint8)), (m,)).copy() if m else np.empty(0, np.uint8)
+    for p in (pi, pj, pv):
+        _lib().orc_free(p)
+    stats = Stats(*[int(getattr(st, f)) for f, _ in _Stats._fields_])
+    return (oi, oj, ov, stats, flags) if want_flags else (oi, oj, ov, stats)
+
+
+def search(rows, dim: int, t: int, r: int, scheme: int, a, b, min_lag: int, min_votes: int,
+           occ_num: int = 0, occ_den: int = 0):
+    keys = signatures(rows, dim, t, r, scheme, a, b)
+    return search_keys(keys, min_lag, min_votes, occ_num, occ_den)
+
+
+def pair_votes(keys: np.ndarray, i: int, j: int) -> int:
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    t, n = keys.shape
+    return int(_lib().orc_pair_votes(t, n, keys.ctypes.data, i, j))

@@ -1,0 +1,143 @@
+"""Seeded synthetic fingerprint workloads shared by the oracle and the GPU path.
+
+The arithmetic lives in ``synth.c`` (compiled to ``libsynth.so``); this module
+only marshals arguments.  Nothing here computes signatures, buckets or votes.
+
+Workload recipes (sizes, seeds and structure of each configuration) are named
+after what they model:
+
+* ``tiny_uniform``   20,000 independent uniform 200-of-4096 fingerprints with
+                     50 events copied into 5 slots each, every copy keeping
+                     160 of the template's 200 bits.
+* ``station``        one station at a 1 s lag: a Markov background in which
+                     each fingerprint keeps 140 of the previous one's 200
+                     bits, plus repeating sources with 3-40 copies whose
+                     Jaccard similarity to the template is drawn from
+                     U[0.4, 0.9] per copy.  90 days = 7,776,000 rows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libsynth.so")
+_SRC = os.path.join(_HERE, "synth.c")
+
+
+def build() -> str:
+    """Compile ``libsynth.so`` in place (always recompiles)."""
+    tmp = _SO + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", _SRC, "-o", tmp])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class _Spec(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64),
+        ("dim", ctypes.c_uint32),
+        ("nnz", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+        ("markov_keep", ctypes.c_uint32),
+        ("n_sources", ctypes.c_uint32),
+        ("rep_min", ctypes.c_uint32),
+        ("rep_max", ctypes.c_uint32),
+        ("plant_keep", ctypes.c_uint32),
+        ("jac_lo_milli", ctypes.c_uint32),
+        ("jac_hi_milli", ctypes.c_uint32),
+        ("noise_permille", ctypes.c_uint32),
+        ("noise_keep", ctypes.c_uint32),
+    ]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        lib.synth_generate_range.argtypes = [ctypes.POINTER(_Spec), ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+        lib.synth_generate_range.restype = ctypes.c_int
+        lib.synth_planted_count.argtypes = [ctypes.POINTER(_Spec)]
+        lib.synth_planted_count.restype = ctypes.c_uint64
+        _LIB = lib
+    return _LIB
+
+
+@dataclass(frozen=True)
+class Spec:
+    n: int
+    dim: int = 4096
+    nnz: int = 200
+    seed: int = 0
+    markov_keep: int = 0
+    n_sources: int = 0
+    rep_min: int = 1
+    rep_max: int = 1
+    plant_keep: int = 0
+    jac_lo_milli: int = 0
+    jac_hi_milli: int = 0
+    noise_permille: int = 0
+    noise_keep: int = 0
+
+    def _c(self) -> _Spec:
+        return _Spec(*[getattr(self, f) for f, _ in _Spec._fields_])
+
+
+def generate(spec: Spec, lo: int = 0, hi: int | None = None, labels: bool = False):
+    """Rows [lo, hi) of ``spec`` as a C-ordered ``uint16[hi-lo, nnz]`` array
+    (sorted indices per row); with ``labels`` also ``int32[hi-lo]`` holding -1
+    (background), the planted source id, or -2 (noise copy)."""
+    hi = spec.n if hi is None else hi
+    rows = np.empty((hi - lo, spec.nnz), dtype=np.uint16)
+    lab = np.empty(hi - lo, dtype=np.int32) if labels else None
+    c = spec._c()
+    rc = _lib().synth_generate_range(ctypes.byref(c), lo, hi, rows.ctypes.data,
+                                     lab.ctypes.data if labels else None)
+    if rc != 0:
+        raise ValueError(f"synth: invalid spec {spec} (code {rc})")
+    return (rows, lab) if labels else rows
+
+
+def planted_count(spec: Spec) -> int:
+    c = spec._c()
+    return int(_lib().synth_planted_count(ctypes.byref(c)))
+
+
+# --------------------------------------------------------------------------
+# Workload recipes
+# --------------------------------------------------------------------------
+DAY = 86_400
+STATION_90D = 90 * DAY          # 7,776,000 fingerprints at a 1 s lag
+STATION_180D = 180 * DAY        # 15,552,000
+STATION_5Y = 157_788_000        # 5 x 365.25 days
+CHUNK = 3_600                   # one hour of fingerprints at a 1 s lag
+BATCH_LENGTHS_M = (1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16)
+
+
+def tiny_uniform(n: int = 20_000, seed: int = 101) -> Spec:
+    """Independent uniform background with 50 events x 5 copies keeping 80 %."""
+    return Spec(n=n, seed=seed, n_sources=50, rep_min=5, rep_max=5, plant_keep=160)
+
+
+def station(n: int = STATION_90D, seed: int = 102, sources_per_90d: int = 2000) -> Spec:
+    """Markov background (70 % kept) with repeating sources, J ~ U[0.4, 0.9].
+    The source count scales with length (2,000 per 90 days by default)."""
+    ns = max(1, round(sources_per_90d * n / STATION_90D))
+    return Spec(n=n, seed=seed, markov_keep=140, n_sources=ns, rep_min=3, rep_max=40,
+                jac_lo_milli=400, jac_hi_milli=900)
+
+
+def with_noise(spec: Spec, permille: int = 50, keep: int = 190) -> Spec:
+    """Test-only variant: a repeating-noise source fills `permille` of all
+    slots with copies keeping `keep` of its bits (drives the occurrence filter)."""
+    return replace(spec, noise_permille=permille, noise_keep=keep)
