@@ -1,0 +1,185 @@
+/*
+ * fast_lsh — MinHash / Min-Max LSH similarity search for binary waveform
+ * fingerprints on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the similarity-search stage of the FAST earthquake-detection
+ * pipeline as scaled by Rong et al., "Locality-Sensitive Hashing for
+ * Earthquake Detection: A Case Study of Scaling Data-Driven Science",
+ * VLDB 2018:
+ *   - every fingerprint (a sparse binary vector, given as the sorted list of
+ *     its non-zero element indices) gets one band key per hash table, made
+ *     of r MinHash (section 6.1) or Min-Max (section 6.2) values;
+ *   - fingerprints with equal band keys share that table's bucket
+ *     (section 6.1 "Hash table construction");
+ *   - a pair's vote count is the number of tables in which the two share a
+ *     bucket; pairs with at least `min_votes` votes are reported, the count
+ *     standing in for similarity (section 6.1 "Search", section 6.3 S-curve,
+ *     section 7.2 triplets);
+ *   - pairs closer than `min_lag` fingerprints are self-matches and dropped
+ *     (section 7.1);
+ *   - the occurrence filter excludes every fingerprint that lands in an
+ *     over-full bucket (section 6.5).
+ *
+ * Definitions fixed by this library where the paper leaves them open:
+ *   - hash function f: h_f(x) = (a_f * x + b_f) mod (2^31 - 1), x the 0-based
+ *     element index, a_f in [1, 2^31 - 2], b_f in [0, 2^31 - 2];
+ *   - MinHash: table u, row s uses function u*r + s (F = t*r functions).
+ *     Min-Max: table u uses functions u*r/2 + q; row 2q is the minimum and
+ *     row 2q+1 the maximum of that function (F = t*r/2; r must be even);
+ *   - band key: the r element indices attaining the r values, each in
+ *     b = ceil(log2 dim) bits, row s at bit b*s (lossless when b*r <= 64,
+ *     so equal keys means equal values).  For b*r > 64 the key is the chain
+ *     k_0 = 0, k_{s+1} = fmix64(k_s + x_s + 1) (murmur3's 64-bit finaliser);
+ *   - occurrence filter: fingerprint i is excluded when, in some table, its
+ *     bucket holds more than occ_num/occ_den of the n fingerprints
+ *     (size * occ_den > n * occ_num, sizes counted before exclusion); an
+ *     excluded fingerprint is part of no pair in any table;
+ *   - output: pairs (i, j) with i < j, j - i >= min_lag, neither excluded,
+ *     votes >= min_votes, sorted by (i, j).  The paper's triplet
+ *     (dt, idx1, sim) is (j - i, i, votes).
+ *
+ * Conventions for every entry point:
+ *   - Bulk arrays (fingerprint indices, offsets, keys, outputs) are DEVICE
+ *     pointers on the context's device; small parameter arrays (hash a/b,
+ *     stats) are HOST pointers.  The caller owns all of them.  The library
+ *     owns only its context workspace.
+ *   - Work is ordered on the context's HIP stream.  Calls that return counts
+ *     (search) synchronise that stream before returning.
+ *   - Return value: FAST_LSH_OK or an error code; fast_lsh_last_error()
+ *     gives a message for the calling thread.  On error no output buffer is
+ *     guaranteed to hold anything meaningful.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef FAST_LSH_H
+#define FAST_LSH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FAST_LSH_OK = 0,
+  FAST_LSH_E_INVALID = 1,  /* bad argument or bad fingerprint data            */
+  FAST_LSH_E_NOMEM = 2,    /* workspace would exceed the context's HBM budget */
+  FAST_LSH_E_CAPACITY = 3, /* more output pairs than the caller's capacity    */
+  FAST_LSH_E_DEVICE = 4,   /* a HIP runtime call failed                       */
+  FAST_LSH_E_BUSY = 5      /* asynchronous work not finished yet              */
+};
+
+enum { FAST_LSH_MINHASH = 0, FAST_LSH_MINMAX = 1 };
+
+typedef struct fast_lsh_ctx fast_lsh_ctx;
+
+/* Hash family for t tables of r rows (section 6.1, section 6.3 parameters
+ * k = r, t; section 6.2 Min-Max).  a and b are HOST arrays of F entries. */
+typedef struct {
+  uint32_t dim;        /* d: fingerprint dimension, 2..65536                 */
+  uint32_t num_tables; /* t: 1..255                                          */
+  uint32_t band_rows;  /* r: values per band key, 1..64 (even for Min-Max)  */
+  uint32_t scheme;     /* FAST_LSH_MINHASH or FAST_LSH_MINMAX                */
+  const uint32_t *a;   /* host, F entries, each in [1, 2^31 - 2]             */
+  const uint32_t *b;   /* host, F entries, each in [0, 2^31 - 2]             */
+} fast_lsh_hash;
+
+/* n fingerprints as index lists.  offsets == NULL: row i is
+ * indices[i*fixed_nnz .. (i+1)*fixed_nnz).  Otherwise row i is
+ * indices[offsets[i] .. offsets[i+1]) (offsets has n+1 entries).  Every row
+ * must be non-empty and every index < dim; the order of indices within a row
+ * does not matter. */
+typedef struct {
+  const uint16_t *indices; /* device */
+  const uint64_t *offsets; /* device, n+1 entries, or NULL                   */
+  uint32_t fixed_nnz;      /* row length when offsets == NULL                */
+  uint32_t reserved;
+  uint64_t n;              /* number of fingerprints, < 2^31                 */
+} fast_lsh_fps;
+
+/* Search filters: self-match lag (section 7.1), vote threshold (section 6.1,
+ * "at least m of t" in section 6.3), occurrence filter (section 6.5;
+ * occ_den == 0 switches it off). */
+typedef struct {
+  uint32_t min_lag;   /* L: keep pairs with j - i >= L                       */
+  uint32_t min_votes; /* v >= 1                                              */
+  uint32_t occ_num;
+  uint32_t occ_den;
+} fast_lsh_filter;
+
+/* Counters of one search (all exact):
+ *   n_out       pairs reported (votes >= v);
+ *   e_raw       sum over tables and buckets of C(size, 2), before any filter
+ *               (the candidate comparisons a plain LSH query loop performs);
+ *   e_voted     sum of votes over all pairs that pass lag and exclusion;
+ *   n_distinct  number of such pairs with at least one vote (computed only
+ *               when the search is asked for it, else UINT64_MAX);
+ *   n_flagged   fingerprints excluded by the occurrence filter;
+ *   max_bucket  largest bucket over all tables, before any filter. */
+typedef struct {
+  uint64_t n_out, e_raw, e_voted, n_distinct, n_flagged, max_bucket;
+} fast_lsh_stats;
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int fast_lsh_version(void);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *fast_lsh_last_error(void);
+
+/* Create a context on HIP device `device`, ordering work on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  `hbm_budget` bounds the
+ * workspace the context may allocate, in bytes (0 = no bound beyond the
+ * device's free memory).  *out receives the context. */
+int fast_lsh_ctx_create(int device, void *hip_stream, uint64_t hbm_budget, fast_lsh_ctx **out);
+
+/* Release the context and its workspace (NULL is ignored). */
+void fast_lsh_ctx_destroy(fast_lsh_ctx *ctx);
+
+/* Hash mappings from a seed (the role of single_hash in Appendix D,
+ * Algorithm 1): splitmix64 seeded with `seed` (Steele, Lea & Flood 2014);
+ * for f = 0..n_funcs-1 in order: a[f] = 1 + next() mod (2^31 - 2),
+ * b[f] = next() mod (2^31 - 1).  a and b are HOST arrays of n_funcs entries.
+ * Host-only; needs no context. */
+int fast_lsh_make_hash(uint64_t seed, uint32_t n_funcs, uint32_t *a, uint32_t *b);
+
+/* Signatures (section 6.1; section 6.2; Appendix D, Algorithm 1
+ * minmax_batch) for tables [table_begin, table_begin + table_count).
+ *   keys  device, uint64[table_count][n]: keys[u][i] is the band key of
+ *         fingerprint i in table table_begin + u;
+ *   sigs  device, uint32[n][table_count][r] or NULL: the r hash values of
+ *         each band key in row order (min / max for Min-Max).
+ * E_INVALID for bad parameters, an empty row or an index >= dim. */
+int fast_lsh_signatures(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *fps,
+                        uint32_t table_begin, uint32_t table_count, uint64_t *keys, uint32_t *sigs);
+
+/* Flags for fast_lsh_search_ex. */
+enum { FAST_LSH_WANT_DISTINCT = 1 };
+
+/* Full similarity search (section 6.1 "Search"; filters of sections 6.5 and
+ * 7.1): writes the sorted pairs to out_i, out_j (device uint32) and
+ * out_votes (device uint8), at most `capacity` of them, and the counters to
+ * *stats (host, may be NULL).  Blocking.
+ * If more than `capacity` pairs qualify the call returns E_CAPACITY with
+ * stats->n_out set; the result stays in the context until its next search,
+ * so fast_lsh_copy_result can fetch it into larger buffers.
+ * The band key must fit 64 bits (ceil(log2 dim) * r <= 64). */
+int fast_lsh_search(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *fps,
+                    const fast_lsh_filter *filter, uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes,
+                    uint64_t capacity, fast_lsh_stats *stats);
+
+/* fast_lsh_search with option flags (FAST_LSH_WANT_DISTINCT also computes
+ * stats->n_distinct, which costs a full comparison of every candidate). */
+int fast_lsh_search_ex(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *fps,
+                       const fast_lsh_filter *filter, uint32_t flags, uint32_t *out_i, uint32_t *out_j,
+                       uint8_t *out_votes, uint64_t capacity, fast_lsh_stats *stats);
+
+/* Copy the last search's result (kept in the context) into caller buffers
+ * with room for `capacity` pairs.  E_CAPACITY if it still does not fit,
+ * E_INVALID if there is no result. */
+int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes,
+                         uint64_t capacity);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FAST_LSH_H */

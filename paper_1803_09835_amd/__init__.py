@@ -1,0 +1,13 @@
+"""MinHash / Min-Max LSH similarity search on MI355X (gfx950).
+
+The hot path of the FAST earthquake-detection pipeline as scaled by Rong et
+al. (VLDB 2018): signatures, band keys, hash-table buckets, the occurrence
+filter, self-match exclusion and per-pair votes, all in hand-written HIP
+kernels behind the C-ABI of include/fast_lsh.h.  This package is the thin
+Python binding over that library.
+"""
+from .fast_lsh import (MINHASH, MINMAX, FastLSH, FastLshError, Stats, library, make_hash, n_funcs,
+                       to_device_rows)
+
+__all__ = ["MINHASH", "MINMAX", "FastLSH", "FastLshError", "Stats", "library", "make_hash", "n_funcs",
+           "to_device_rows"]

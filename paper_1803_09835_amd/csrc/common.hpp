@@ -1,0 +1,125 @@
+// Shared device helpers and launch-argument structs of the fast_lsh HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fl {
+
+constexpr uint32_t kP = 0x7FFFFFFFu;  // Mersenne prime 2^31 - 1 of the hash family
+
+// --------------------------------------------------------------------------
+// Universal hash h(x) = (a x + b) mod p evaluated from pre-doubled
+// parameters a2 = 2a, b2 = 2b (both < 2^32).  With y = a x + b < 2^48,
+// Y = a2 x + b2 = 2y, so the low word of Y shifted right by one is y & p and
+// the high word is y >> 31; their sum is congruent to y mod p and below
+// 2^31 + 2^17, so one conditional subtraction (done as an unsigned min with
+// the wrapped difference) gives the canonical residue.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t hash_mod(uint32_t a2, uint32_t b2, uint32_t x) {
+  uint64_t y2 = (uint64_t)a2 * x + b2;
+  uint32_t s = ((uint32_t)y2 >> 1) + (uint32_t)(y2 >> 32);
+  return min(s, s - kP);
+}
+
+// (u * w) mod p for u, w < p, canonical.
+__device__ __forceinline__ uint32_t mul_mod(uint32_t u, uint32_t w) {
+  uint64_t z = (uint64_t)u * w;  // < 2^62
+  uint32_t s = ((uint32_t)z & kP) + (uint32_t)(z >> 31);  // < 2^32
+  s = s >= kP ? s - kP : s;
+  s = s >= kP ? s - kP : s;
+  return s;
+}
+
+// murmur3 64-bit finaliser: a bijection of 64-bit words.  Used (1) for the
+// chained band key when the packed key would not fit 64 bits and (2) to
+// spread band keys uniformly before grouping (equal keys stay equal).
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+// --------------------------------------------------------------------------
+// Launch arguments
+// --------------------------------------------------------------------------
+struct SigArgs {
+  const uint16_t* ind;   // fingerprint indices
+  const uint64_t* off;   // n+1 offsets or nullptr (fixed nnz)
+  uint64_t n;
+  uint32_t nnz;          // fixed row length when off == nullptr
+  uint32_t dim;
+  uint32_t r;            // rows per band key
+  uint32_t fpt;          // functions per table (r or r/2)
+  uint32_t table_begin;
+  uint32_t table_count;
+  uint32_t kbits;        // ceil(log2 dim)
+  uint32_t packed;       // 1: key = packed indices; 0: chained fmix64
+  uint32_t vec_load;     // 1: rows are CAP halfwords, 16-byte aligned
+  const uint32_t* a2;    // per function: 2a
+  const uint32_t* b2;    // 2b
+  const uint32_t* ainv;  // a^-1 mod p
+  const uint32_t* b;     // b
+  uint64_t* keys;        // [table_count][n] band keys, or nullptr
+  uint32_t* sigs;        // [n][table_count][r] values, or nullptr
+  uint64_t* mkeys;       // [table_count][n] fmix64(band key), or nullptr
+  uint16_t* rows;        // sub-key rows [G][n][row_hw] (low 16 bits of fmix64), or nullptr
+  uint32_t tables_per_group;
+  uint32_t row_hw;       // halfwords per row (even)
+  int* err;              // set to 1 on an empty row or an index >= dim
+};
+
+struct BucketArgs {
+  const uint64_t* keys;  // sorted by the top 16 bits, [S][n]
+  uint32_t* vals;        // ids, same order; rewritten sorted by (key, id)
+  uint64_t n;
+  uint32_t chunk;
+  // occurrence filter: station of an id found from station_base (nstation+1 entries)
+  const uint64_t* station_base;
+  uint32_t nstation;
+  uint32_t occ_num, occ_den;
+  uint8_t* flags;        // per fingerprint
+  uint32_t small_max;    // buckets of size <= small_max go to the small list
+  uint2* small_desc;     // {pos, seg<<16 | size}
+  uint32_t* small_count;
+  uint4* big_desc;       // {pos, seg, size, 0}
+  uint32_t* big_count;
+  uint4* bin_desc;       // oversized bins {lo, hi, seg, 0}
+  uint32_t* bin_count;
+  unsigned long long* e_raw;
+  unsigned int* max_bucket;
+};
+
+struct PairArgs {
+  const uint32_t* order;      // bucket members by position [S][n]
+  const uint8_t* flags;
+  const uint16_t* rows;       // sub-key rows [G][n][row_hw]
+  const uint64_t* mkeys;      // exact keys [t][n]
+  uint64_t n;
+  uint32_t t, G, tables_per_group, row_hw;
+  uint32_t min_lag, min_votes, need;
+  uint32_t want_distinct;
+  uint32_t* out_i;
+  uint32_t* out_j;
+  uint8_t* out_v;
+  unsigned int* out_count;
+  uint32_t out_cap;
+  unsigned long long* e_voted;
+  unsigned long long* n_distinct;
+};
+
+struct SmallCfg {
+  uint32_t memb_max;  // members staged per workgroup
+  uint32_t nb_max;    // buckets per workgroup
+  uint32_t rswl;      // LDS row stride in dwords (odd)
+  uint32_t mb;        // member budget that partitions the descriptor list
+};
+
+struct TileUnit {
+  uint32_t bucket, ta, tb, pad;
+};
+
+}  // namespace fl

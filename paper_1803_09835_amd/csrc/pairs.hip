@@ -1,0 +1,439 @@
+// Candidate pairs and votes (section 6.1 "Search"; section 7.1 self-match
+// exclusion; section 6.5 occurrence filter; section 6.3 "at least m of t").
+//
+// The search never builds a global (i, j) -> votes map.  Every in-bucket pair
+// of table u is checked where it is found: each fingerprint carries a row of
+// 16-bit sub-keys (low bits of the mixed band key), one per table, split into
+// G contiguous table groups.  A pair with at least v votes shares buckets in
+// at least need = ceil(v / G) tables of some group (pigeonhole), so table u
+// only has to compare the sub-keys of its own group; equal band keys always
+// have equal sub-keys, so a pair below `need` there cannot be the pair's
+// reporting table and is dropped exactly.  The rare survivors compute the
+// exact shared-table set S from the full mixed keys and are reported only
+// by their owner: the smallest table of the first group holding at least
+// `need` tables of S.  Every qualifying pair is therefore reported once,
+// with its exact vote count |S|, and no atomics are spent on votes.
+#include "common.hpp"
+
+namespace fl {
+
+constexpr int kPT = 256;
+
+__device__ __forceinline__ void tri_decode(uint32_t m, uint32_t q, uint32_t& x, uint32_t& y) {
+  // Row x of the upper triangle holds m-1-x pairs; S(x) = x*m - x(x+1)/2 precede it.
+  const float fm = 2.0f * (float)m - 1.0f;
+  const float disc = fm * fm - 8.0f * (float)q;
+  int xx = (int)((fm - sqrtf(fmaxf(disc, 0.0f))) * 0.5f);
+  const int top = (int)m - 2;
+  xx = xx < 0 ? 0 : (xx > top ? top : xx);
+  auto S = [m](int r) { return (uint32_t)r * m - (uint32_t)(r * (r + 1) / 2); };
+  while (xx > 0 && S(xx) > q) --xx;
+  while (xx < top && S(xx + 1) <= q) ++xx;
+  x = (uint32_t)xx;
+  y = q - S(xx) + (uint32_t)xx + 1;
+}
+
+__device__ __forceinline__ uint32_t eq_halves(uint32_t a, uint32_t b) {
+  const uint32_t x = a ^ b;
+  return (uint32_t)((x & 0xFFFFu) == 0) + (uint32_t)((x >> 16) == 0);
+}
+
+// Exact shared tables of (i, j) from global rows and mixed keys; reports the
+// pair if table u is its owner.  Returns nothing; writes the output.
+__device__ __noinline__ void exact_and_report(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
+  const uint32_t rsw = a.row_hw / 2;
+  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
+  uint32_t votes = 0, owner = 0xFFFFFFFFu;
+  for (uint32_t g = 0; g < a.G; ++g) {
+    const uint32_t* ri = R + ((uint64_t)g * a.n + i) * rsw;
+    const uint32_t* rj = R + ((uint64_t)g * a.n + j) * rsw;
+    uint32_t cnt = 0, minu = 0xFFFFFFFFu;
+    for (uint32_t w = 0; w < rsw; ++w) {
+      const uint32_t x = ri[w] ^ rj[w];
+      for (uint32_t h = 0; h < 2; ++h) {
+        const uint32_t slot = 2 * w + h;
+        const uint32_t tab = g * a.tables_per_group + slot;
+        if (slot >= a.tables_per_group || tab >= a.t) continue;
+        if (((x >> (16 * h)) & 0xFFFFu) != 0) continue;
+        if (a.mkeys[(uint64_t)tab * a.n + i] == a.mkeys[(uint64_t)tab * a.n + j]) {
+          ++cnt;
+          minu = tab < minu ? tab : minu;
+        }
+      }
+    }
+    votes += cnt;
+    if (owner == 0xFFFFFFFFu && cnt >= a.need) owner = minu;
+  }
+  if (owner == u && votes >= a.min_votes) {
+    const uint32_t q = atomicAdd(a.out_count, 1u);
+    if (q < a.out_cap) {
+      a.out_i[q] = i;
+      a.out_j[q] = j;
+      a.out_v[q] = (uint8_t)votes;
+    }
+  }
+}
+
+// True when no table below u exactly shares a bucket with (i, j) (G == 1:
+// one group, slot == table).
+__device__ __noinline__ bool first_shared_is(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
+  const uint32_t rsw = a.row_hw / 2;
+  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
+  const uint32_t* ri = R + (uint64_t)i * rsw;
+  const uint32_t* rj = R + (uint64_t)j * rsw;
+  for (uint32_t tab = 0; tab < u; ++tab) {
+    const uint32_t x = ri[tab >> 1] ^ rj[tab >> 1];
+    if (((x >> (16 * (tab & 1))) & 0xFFFFu) != 0) continue;
+    if (a.mkeys[(uint64_t)tab * a.n + i] == a.mkeys[(uint64_t)tab * a.n + j]) return false;
+  }
+  return true;
+}
+
+struct PairTally {
+  unsigned long long ev, nd;
+};
+
+// One in-bucket pair of table u: i < j are ids, ra / rb their staged rows
+// (this table's group) in LDS.
+__device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j, const uint32_t* ra,
+                                           const uint32_t* rb, uint32_t rsw, uint32_t pad, PairTally& tl) {
+  if (j - i < a.min_lag) return;
+  ++tl.ev;
+  uint32_t eq = 0;
+  if (a.want_distinct) {
+    // G == 1: also count equal sub-keys below table u.
+    uint32_t below = 0;
+    for (uint32_t w = 0; w < rsw; ++w) {
+      const uint32_t x = ra[w] ^ rb[w];
+      const uint32_t e0 = (x & 0xFFFFu) == 0, e1 = (x >> 16) == 0;
+      eq += e0 + e1;
+      below += (2 * w < u ? e0 : 0u) + (2 * w + 1 < u ? e1 : 0u);
+    }
+    if (below == 0 || first_shared_is(a, u, i, j)) ++tl.nd;
+  } else {
+#pragma unroll 4
+    for (uint32_t w = 0; w < rsw; ++w) eq += eq_halves(ra[w], rb[w]);
+  }
+  if (eq - pad >= a.need) exact_and_report(a, u, i, j);
+}
+
+__device__ void flush_tally(const PairArgs& a, PairTally tl) {
+  unsigned long long ev = tl.ev, nd = tl.nd;
+  for (int o = 32; o > 0; o >>= 1) {
+    ev += __shfl_xor(ev, o, 64);
+    nd += __shfl_xor(nd, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (ev) atomicAdd(a.e_voted, ev);
+    if (nd) atomicAdd(a.n_distinct, nd);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T block_scan_excl(T v, T* ws, T* total) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  T inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += y;
+  }
+  if (lane == 63) ws[wave] = inc;
+  __syncthreads();
+  T add = 0, all = 0;
+  for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
+    if (w < wave) add += ws[w];
+    all += ws[w];
+  }
+  __syncthreads();
+  *total = all;
+  return add + inc - v;
+}
+
+// Buckets of at most small_max members, partitioned by a prefix sum of their
+// sizes so that every workgroup stages about `mb` members.
+__global__ __launch_bounds__(kPT) void k_pairs_small(PairArgs a, const uint2* desc, const uint64_t* prefix,
+                                                     uint32_t ndesc, SmallCfg cfg) {
+  extern __shared__ uint32_t smem[];
+  uint32_t* lrows = smem;
+  uint32_t* lids = lrows + cfg.memb_max * cfg.rswl;
+  uint32_t* bofs = lids + cfg.memb_max;
+  uint32_t* bpof = bofs + cfg.nb_max + 1;
+  uint32_t* bcnt = bpof + cfg.nb_max + 1;
+  uint32_t* bseg = bcnt + cfg.nb_max;
+  uint32_t* bpos = bseg + cfg.nb_max;
+  uint8_t* lg = reinterpret_cast<uint8_t*>(bpos + cfg.nb_max);
+  __shared__ uint32_t ws[8];
+  __shared__ uint32_t s_range[2];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t rsw = a.row_hw / 2;
+
+  if (tid < 2) {
+    const uint64_t target = (uint64_t)(blockIdx.x + tid) * cfg.mb;
+    uint32_t L = 0, R = ndesc;
+    while (L < R) {
+      const uint32_t M = (L + R) / 2;
+      if (prefix[M] >= target) R = M; else L = M + 1;
+    }
+    s_range[tid] = L;
+  }
+  __syncthreads();
+  const uint32_t k_lo = s_range[0], nb = s_range[1] - s_range[0];
+  // A: unflagged member count per bucket
+  for (uint32_t b = tid; b < nb; b += kPT) {
+    const uint2 d = desc[k_lo + b];
+    const uint32_t seg = d.y >> 16, size = d.y & 0xFFFFu;
+    const uint32_t* ord = a.order + (uint64_t)seg * a.n + d.x;
+    uint32_t c = 0;
+    for (uint32_t q = 0; q < size; ++q) c += a.flags[ord[q]] == 0;
+    bcnt[b] = c;
+    bseg[b] = seg;
+    bpos[b] = d.x;
+  }
+  __syncthreads();
+  uint32_t mcarry = 0, pcarry = 0;
+  for (uint32_t b0 = 0; b0 < nb; b0 += kPT) {
+    const uint32_t b = b0 + tid;
+    const uint32_t c = b < nb ? bcnt[b] : 0u;
+    uint32_t tm, tp;
+    const uint32_t xm = block_scan_excl<uint32_t>(c, ws, &tm);
+    const uint32_t xp = block_scan_excl<uint32_t>(c * (c - (c > 0)) / 2, ws, &tp);
+    if (b < nb) {
+      bofs[b] = mcarry + xm;
+      bpof[b] = pcarry + xp;
+    }
+    mcarry += tm;
+    pcarry += tp;
+  }
+  if (tid == 0) {
+    bofs[nb] = mcarry;
+    bpof[nb] = pcarry;
+  }
+  __syncthreads();
+  // B: compacted member ids and their row group
+  for (uint32_t b = tid; b < nb; b += kPT) {
+    const uint32_t seg = bseg[b];
+    const uint32_t size = desc[k_lo + b].y & 0xFFFFu;
+    const uint32_t* ord = a.order + (uint64_t)seg * a.n + bpos[b];
+    uint32_t o = bofs[b];
+    const uint8_t g = (uint8_t)(seg / a.tables_per_group);
+    for (uint32_t q = 0; q < size; ++q) {
+      const uint32_t id = ord[q];
+      if (a.flags[id] == 0) {
+        lids[o] = id;
+        lg[o] = g;
+        ++o;
+      }
+    }
+  }
+  __syncthreads();
+  // C: stage rows
+  const uint32_t M = mcarry;
+  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
+  for (uint32_t idx = tid; idx < M * rsw; idx += kPT) {
+    const uint32_t m = idx / rsw, w = idx - m * rsw;
+    lrows[m * cfg.rswl + w] = R[((uint64_t)lg[m] * a.n + lids[m]) * rsw + w];
+  }
+  __syncthreads();
+  // D: pairs
+  PairTally tl{0ull, 0ull};
+  const uint32_t P = pcarry;
+  for (uint32_t p = tid; p < P; p += kPT) {
+    uint32_t L = 0, Rr = nb;  // last bucket with bpof <= p
+    while (Rr - L > 1) {
+      const uint32_t Mm = (L + Rr) / 2;
+      if (bpof[Mm] <= p) L = Mm; else Rr = Mm;
+    }
+    const uint32_t b = L;
+    uint32_t x, y;
+    tri_decode(bcnt[b], p - bpof[b], x, y);
+    const uint32_t o = bofs[b];
+    const uint32_t u = bseg[b];
+    const uint32_t g = u / a.tables_per_group;
+    const uint32_t valid = min(a.tables_per_group, a.t - g * a.tables_per_group);
+    visit_pair(a, u, lids[o + x], lids[o + y], lrows + (o + x) * cfg.rswl, lrows + (o + y) * cfg.rswl, rsw,
+               2 * rsw - valid, tl);
+  }
+  flush_tally(a, tl);
+}
+
+// Unflagged members of each large bucket, compacted in order.
+__global__ __launch_bounds__(kPT) void k_compact_big(PairArgs a, const uint4* big, const uint64_t* cofs,
+                                                     uint32_t* ids, uint32_t* cnt) {
+  __shared__ uint32_t ws[8];
+  __shared__ uint32_t s_carry;
+  const uint4 d = big[blockIdx.x];
+  const uint32_t* ord = a.order + (uint64_t)d.y * a.n + d.x;
+  uint32_t* out = ids + cofs[blockIdx.x];
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (uint32_t c = 0; c < d.z; c += kPT) {
+    const uint32_t q = c + threadIdx.x;
+    const uint32_t id = q < d.z ? ord[q] : 0u;
+    const uint32_t keep = (q < d.z && a.flags[id] == 0) ? 1u : 0u;
+    uint32_t tot;
+    const uint32_t x = block_scan_excl<uint32_t>(keep, ws, &tot);
+    const uint32_t carry = s_carry;
+    if (keep) out[carry + x] = id;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[blockIdx.x] = s_carry;
+}
+
+// One tile (ta, tb) of the upper triangle of a large bucket's pair matrix.
+__global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* units, const uint4* big,
+                                                    const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
+                                                    uint32_t tb_size, uint32_t rswl) {
+  extern __shared__ uint32_t smem[];
+  const TileUnit un = units[blockIdx.x];
+  const uint32_t rsw = a.row_hw / 2;
+  const uint32_t seg = big[un.bucket].y;
+  const uint32_t* bid = ids + cofs[un.bucket];
+  const uint32_t m = cnt[un.bucket];
+  const uint32_t a0 = un.ta * tb_size, b0 = un.tb * tb_size;
+  const uint32_t na = min(tb_size, m - a0);
+  const bool diag = un.ta == un.tb;
+  const uint32_t nbm = diag ? 0u : min(tb_size, m - b0);
+  uint32_t* rowsA = smem;
+  uint32_t* rowsB = rowsA + tb_size * rswl;
+  uint32_t* idsA = rowsB + tb_size * rswl;
+  uint32_t* idsB = idsA + tb_size;
+  const uint32_t g = seg / a.tables_per_group;
+  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
+  for (uint32_t q = threadIdx.x; q < na; q += kPT) idsA[q] = bid[a0 + q];
+  for (uint32_t q = threadIdx.x; q < nbm; q += kPT) idsB[q] = bid[b0 + q];
+  __syncthreads();
+  for (uint32_t idx = threadIdx.x; idx < na * rsw; idx += kPT) {
+    const uint32_t q = idx / rsw, w = idx - q * rsw;
+    rowsA[q * rswl + w] = R[((uint64_t)g * a.n + idsA[q]) * rsw + w];
+  }
+  for (uint32_t idx = threadIdx.x; idx < nbm * rsw; idx += kPT) {
+    const uint32_t q = idx / rsw, w = idx - q * rsw;
+    rowsB[q * rswl + w] = R[((uint64_t)g * a.n + idsB[q]) * rsw + w];
+  }
+  __syncthreads();
+  const uint32_t valid = min(a.tables_per_group, a.t - g * a.tables_per_group);
+  const uint32_t pad = 2 * rsw - valid;
+  PairTally tl{0ull, 0ull};
+  if (diag) {
+    const uint32_t P = na * (na - 1) / 2;
+    for (uint32_t p = threadIdx.x; p < P; p += kPT) {
+      uint32_t x, y;
+      tri_decode(na, p, x, y);
+      visit_pair(a, seg, idsA[x], idsA[y], rowsA + x * rswl, rowsA + y * rswl, rsw, pad, tl);
+    }
+  } else {
+    const uint32_t P = na * nbm;
+    for (uint32_t p = threadIdx.x; p < P; p += kPT) {
+      const uint32_t x = p / nbm, y = p - x * nbm;
+      visit_pair(a, seg, idsA[x], idsB[y], rowsA + x * rswl, rowsB + y * rswl, rsw, pad, tl);
+    }
+  }
+  flush_tally(a, tl);
+}
+
+// Split sorted (i << 32 | j, votes) records into the caller's arrays.
+__global__ __launch_bounds__(kPT) void k_split_out(const uint64_t* key, const uint32_t* val, uint64_t count,
+                                                   uint32_t* oi, uint32_t* oj, uint8_t* ov) {
+  for (uint64_t e = (uint64_t)blockIdx.x * kPT + threadIdx.x; e < count; e += (uint64_t)gridDim.x * kPT) {
+    const uint64_t k = key[e];
+    oi[e] = (uint32_t)(k >> 32);
+    oj[e] = (uint32_t)k;
+    ov[e] = (uint8_t)val[e];
+  }
+}
+
+__global__ __launch_bounds__(kPT) void k_pack_out(const uint32_t* oi, const uint32_t* oj, const uint8_t* ov,
+                                                  uint64_t count, uint64_t* key, uint32_t* val) {
+  for (uint64_t e = (uint64_t)blockIdx.x * kPT + threadIdx.x; e < count; e += (uint64_t)gridDim.x * kPT) {
+    key[e] = ((uint64_t)oi[e] << 32) | oj[e];
+    val[e] = ov[e];
+  }
+}
+
+__global__ __launch_bounds__(kPT) void k_desc_sizes(const uint2* desc, uint32_t count, uint64_t* sizes) {
+  for (uint32_t e = blockIdx.x * kPT + threadIdx.x; e < count; e += gridDim.x * kPT) sizes[e] = desc[e].y & 0xFFFFu;
+}
+
+__global__ __launch_bounds__(kPT) void k_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out) {
+  unsigned long long c = 0;
+  for (uint64_t e = (uint64_t)blockIdx.x * kPT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * kPT) c += flags[e] != 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPT) void k_fill(T* p, uint64_t count, T v) {
+  for (uint64_t e = (uint64_t)blockIdx.x * kPT + threadIdx.x; e < count; e += (uint64_t)gridDim.x * kPT) p[e] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+static unsigned grid_for(uint64_t count) {
+  const uint64_t b = (count + kPT - 1) / kPT;
+  return (unsigned)(b == 0 ? 1 : (b < 65535 ? b : 65535));
+}
+
+size_t small_smem_bytes(const SmallCfg& c) {
+  return (size_t)c.memb_max * c.rswl * 4 + (size_t)c.memb_max * 4 + (size_t)(c.nb_max + 1) * 8 +
+         (size_t)c.nb_max * 12 + c.memb_max + 16;
+}
+
+void launch_pairs_small(const PairArgs& a, const uint2* desc, const uint64_t* prefix, uint32_t ndesc,
+                        uint64_t total_members, const SmallCfg& c, hipStream_t s) {
+  if (ndesc == 0) return;
+  const uint64_t nwg = (total_members + c.mb - 1) / c.mb;
+  hipLaunchKernelGGL(k_pairs_small, dim3((unsigned)nwg), dim3(kPT), small_smem_bytes(c), s, a, desc, prefix, ndesc,
+                     c);
+}
+
+void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, const uint64_t* cofs, uint32_t* ids,
+                        uint32_t* cnt, hipStream_t s) {
+  if (nbig == 0) return;
+  hipLaunchKernelGGL(k_compact_big, dim3(nbig), dim3(kPT), 0, s, a, big, cofs, ids, cnt);
+}
+
+void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits, const uint4* big,
+                       const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt, uint32_t tb_size,
+                       uint32_t rswl, hipStream_t s) {
+  if (nunits == 0) return;
+  const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
+  hipLaunchKernelGGL(k_pairs_tile, dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl);
+}
+
+void launch_split_out(const uint64_t* key, const uint32_t* val, uint64_t count, uint32_t* oi, uint32_t* oj,
+                      uint8_t* ov, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_split_out, dim3(grid_for(count)), dim3(kPT), 0, s, key, val, count, oi, oj, ov);
+}
+
+void launch_pack_out(const uint32_t* oi, const uint32_t* oj, const uint8_t* ov, uint64_t count, uint64_t* key,
+                     uint32_t* val, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_pack_out, dim3(grid_for(count)), dim3(kPT), 0, s, oi, oj, ov, count, key, val);
+}
+
+void launch_desc_sizes(const uint2* desc, uint32_t count, uint64_t* sizes, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_desc_sizes, dim3(grid_for(count)), dim3(kPT), 0, s, desc, count, sizes);
+}
+
+void launch_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_count_flags, dim3(grid_for(n) < 4096 ? grid_for(n) : 4096), dim3(kPT), 0, s, flags, n, out);
+}
+
+void fill_u8(uint8_t* p, uint64_t count, uint8_t v, hipStream_t s) {
+  if (count) hipLaunchKernelGGL((k_fill<uint8_t>), dim3(grid_for(count)), dim3(kPT), 0, s, p, count, v);
+}
+void fill_u32(uint32_t* p, uint64_t count, uint32_t v, hipStream_t s) {
+  if (count) hipLaunchKernelGGL((k_fill<uint32_t>), dim3(grid_for(count)), dim3(kPT), 0, s, p, count, v);
+}
+void fill_u64(uint64_t* p, uint64_t count, uint64_t v, hipStream_t s) {
+  if (count) hipLaunchKernelGGL((k_fill<uint64_t>), dim3(grid_for(count)), dim3(kPT), 0, s, p, count, v);
+}
+
+}  // namespace fl

@@ -1,0 +1,251 @@
+// Signature kernels: MinHash (section 6.1) and Min-Max (section 6.2) values
+// over sparse binary fingerprints and the band key of every table.
+//
+// Layout choice for gfx950: one fingerprint per lane.  The lane keeps the
+// fingerprint's element indices in VGPRs (two 16-bit indices per register),
+// so the inner loop is pure integer VALU work: the hash parameters of the
+// current function are wave-uniform (scalar loads), no reductions across
+// lanes are needed, and the 64 keys a wave produces for one table are 64
+// consecutive 8-byte words (one coalesced store).  Every function's
+// arguments are recovered after the loop from its min/max values by the
+// inverse of the hash (x = (v - b) a^-1 mod p), so the loop carries only the
+// 32-bit extremes.  This keeps the paper's dimension-major loop order
+// (Appendix D, Algorithm 1): each set element is read once per function
+// pair, here from registers.
+#include "common.hpp"
+
+namespace fl {
+
+template <bool MINMAX>
+struct PairAcc {
+  uint32_t mnA, mxA, mnB, mxB;
+  __device__ __forceinline__ void init() {
+    mnA = mnB = 0xFFFFFFFFu;
+    mxA = mxB = 0u;
+  }
+  __device__ __forceinline__ void add(uint32_t a2A, uint32_t b2A, uint32_t a2B, uint32_t b2B, uint32_t v) {
+    const uint32_t x0 = v & 0xFFFFu, x1 = v >> 16;
+    const uint32_t hA0 = hash_mod(a2A, b2A, x0), hA1 = hash_mod(a2A, b2A, x1);
+    const uint32_t hB0 = hash_mod(a2B, b2B, x0), hB1 = hash_mod(a2B, b2B, x1);
+    mnA = min(mnA, min(hA0, hA1));
+    mnB = min(mnB, min(hB0, hB1));
+    if (MINMAX) {
+      mxA = max(mxA, max(hA0, hA1));
+      mxB = max(mxB, max(hB0, hB1));
+      // Serialise the running extremes: otherwise the compiler regroups the
+      // min and max reductions into separate trees and keeps every hash
+      // value of the row alive in registers.
+      asm volatile("" : "+v"(mnA), "+v"(mxA), "+v"(mnB), "+v"(mxB));
+    } else {
+      asm volatile("" : "+v"(mnA), "+v"(mnB));
+    }
+  }
+};
+
+struct KeyBuilder {
+  uint64_t key;
+  uint32_t row;
+  __device__ __forceinline__ void put(const SigArgs& a, uint32_t f, uint32_t v, uint64_t i, uint32_t u, bool live) {
+    const uint32_t bf = a.b[f];
+    const uint32_t d = v >= bf ? v - bf : v + kP - bf;
+    const uint32_t x = mul_mod(d, a.ainv[f]);
+    if (a.packed)
+      key |= (uint64_t)x << (a.kbits * row);
+    else
+      key = fmix64(key + x + 1);
+    if (a.sigs && live) a.sigs[(i * a.table_count + u) * a.r + row] = v;
+    ++row;
+  }
+};
+
+__device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint64_t i, uint32_t u) {
+  const uint32_t tab = a.table_begin + u;
+  if (a.keys) a.keys[(uint64_t)u * a.n + i] = key;
+  if (a.mkeys || a.rows) {
+    const uint64_t m = fmix64(key);
+    if (a.mkeys) a.mkeys[(uint64_t)u * a.n + i] = m;
+    if (a.rows) {
+      const uint32_t g = tab / a.tables_per_group, slot = tab - g * a.tables_per_group;
+      a.rows[((uint64_t)g * a.n + i) * a.row_hw + slot] = (uint16_t)m;
+    }
+  }
+}
+
+// CAP: most indices a row may hold (rows shorter than CAP are padded with
+// their first index, which leaves every min and max unchanged).  Rows are
+// fixed-length with an even length and 4-byte aligned (other layouts take
+// k_sig_long).
+template <int CAP, bool MINMAX>
+__global__ __launch_bounds__(256) void k_sig(SigArgs a) {
+  constexpr int W = CAP / 2;
+  const uint64_t gi = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = gi < a.n;
+  const uint64_t i = live ? gi : a.n - 1;
+  uint64_t lo, len;
+  if (a.off) {
+    lo = a.off[i];
+    len = a.off[i + 1] - lo;
+  } else {
+    lo = i * a.nnz;
+    len = a.nnz;
+  }
+  bool bad = (len == 0) || (len > (uint64_t)CAP);
+  uint32_t xs[W];
+  if (a.vec_load) {
+    const uint4* p = reinterpret_cast<const uint4*>(a.ind + lo);
+#pragma unroll
+    for (int q = 0; q < CAP / 8; ++q) {
+      const uint4 v = p[q];
+      xs[4 * q + 0] = v.x;
+      xs[4 * q + 1] = v.y;
+      xs[4 * q + 2] = v.z;
+      xs[4 * q + 3] = v.w;
+    }
+  } else {
+    // Fixed even row length below CAP, 4-byte aligned rows: dword loads,
+    // the tail padded with the row's first index.
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(a.ind + lo);
+    const uint32_t half = (uint32_t)(len / 2);
+    const uint32_t first = len ? (uint32_t)a.ind[lo] * 0x10001u : 0u;
+#pragma unroll
+    for (int w = 0; w < W; ++w) xs[w] = (uint32_t)w < half ? p[w] : first;
+  }
+  uint32_t top = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) top = max(top, max(xs[w] & 0xFFFFu, xs[w] >> 16));
+  if (top >= a.dim) bad = true;
+  if (live && bad) *a.err = 1;
+
+  for (uint32_t u = 0; u < a.table_count; ++u) {
+    const uint32_t f0 = (a.table_begin + u) * a.fpt;
+    KeyBuilder kb{0ull, 0u};
+    for (uint32_t q = 0; q < a.fpt; q += 2) {
+      const uint32_t fA = f0 + q;
+      const bool two = q + 1 < a.fpt;
+      const uint32_t fB = two ? fA + 1 : fA;
+      const uint32_t a2A = a.a2[fA], b2A = a.b2[fA], a2B = a.a2[fB], b2B = a.b2[fB];
+      PairAcc<MINMAX> acc;
+      acc.init();
+      // Keep the indices packed: without this the compiler hoists the 16-bit
+      // unpacking out of the table loop and doubles the live registers.
+#pragma unroll
+      for (int w = 0; w < W; ++w) asm volatile("" : "+v"(xs[w]));
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc.add(a2A, b2A, a2B, b2B, xs[w]);
+      kb.put(a, fA, acc.mnA, i, u, live);
+      if (MINMAX) kb.put(a, fA, acc.mxA, i, u, live);
+      if (two) {
+        kb.put(a, fB, acc.mnB, i, u, live);
+        if (MINMAX) kb.put(a, fB, acc.mxB, i, u, live);
+      }
+    }
+    if (live) store_table(a, kb.key, i, u);
+  }
+}
+
+// Rows longer than the largest register-resident capacity: indices are read
+// from memory once per function pair.
+template <bool MINMAX>
+__global__ __launch_bounds__(256) void k_sig_long(SigArgs a) {
+  const uint64_t gi = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = gi < a.n;
+  const uint64_t i = live ? gi : a.n - 1;
+  uint64_t lo, len;
+  if (a.off) {
+    lo = a.off[i];
+    len = a.off[i + 1] - lo;
+  } else {
+    lo = i * a.nnz;
+    len = a.nnz;
+  }
+  bool bad = len == 0;
+  for (uint64_t k = 0; k < len; ++k)
+    if (a.ind[lo + k] >= a.dim) bad = true;
+  if (live && bad) *a.err = 1;  // (empty rows never reach this kernel: the host rejects them)
+
+  for (uint32_t u = 0; u < a.table_count; ++u) {
+    const uint32_t f0 = (a.table_begin + u) * a.fpt;
+    KeyBuilder kb{0ull, 0u};
+    for (uint32_t q = 0; q < a.fpt; q += 2) {
+      const uint32_t fA = f0 + q;
+      const bool two = q + 1 < a.fpt;
+      const uint32_t fB = two ? fA + 1 : fA;
+      const uint32_t a2A = a.a2[fA], b2A = a.b2[fA], a2B = a.a2[fB], b2B = a.b2[fB];
+      PairAcc<MINMAX> acc;
+      acc.init();
+      for (uint64_t k = 0; k < len; k += 2) {
+        const uint32_t x0 = a.ind[lo + k];
+        const uint32_t x1 = k + 1 < len ? a.ind[lo + k + 1] : x0;
+        acc.add(a2A, b2A, a2B, b2B, x0 | (x1 << 16));
+      }
+      kb.put(a, fA, acc.mnA, i, u, live);
+      if (MINMAX) kb.put(a, fA, acc.mxA, i, u, live);
+      if (two) {
+        kb.put(a, fB, acc.mnB, i, u, live);
+        if (MINMAX) kb.put(a, fB, acc.mxB, i, u, live);
+      }
+    }
+    if (live) store_table(a, kb.key, i, u);
+  }
+}
+
+// Largest and smallest row length of a ragged set (for kernel selection and
+// the empty-row check).
+__global__ __launch_bounds__(256) void k_row_len_range(const uint64_t* off, uint64_t n, unsigned long long* out) {
+  uint64_t mx = 0, mn = ~0ull;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    const uint64_t L = off[i + 1] - off[i];
+    mx = L > mx ? L : mx;
+    mn = L < mn ? L : mn;
+  }
+  for (int s = 32; s > 0; s >>= 1) {
+    const uint64_t omx = __shfl_xor(mx, s, 64), omn = __shfl_xor(mn, s, 64);
+    mx = omx > mx ? omx : mx;
+    mn = omn < mn ? omn : mn;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out + 0, (unsigned long long)mx);
+    atomicMin(out + 1, (unsigned long long)mn);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launcher
+// ---------------------------------------------------------------------------
+static const int kCaps[] = {16, 32, 64, 128, 200, 256};
+
+int sig_capacity_for(uint64_t max_len) {
+  for (int c : kCaps)
+    if ((uint64_t)c >= max_len) return c;
+  return 0;  // long-row kernel
+}
+
+template <bool MM>
+static void launch_cap(int cap, dim3 g, dim3 b, hipStream_t s, const SigArgs& a) {
+  switch (cap) {
+    case 16: hipLaunchKernelGGL((k_sig<16, MM>), g, b, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_sig<32, MM>), g, b, 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_sig<64, MM>), g, b, 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_sig<128, MM>), g, b, 0, s, a); break;
+    case 200: hipLaunchKernelGGL((k_sig<200, MM>), g, b, 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sig<256, MM>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_sig_long<MM>), g, b, 0, s, a); break;
+  }
+}
+
+void launch_sig(int cap, bool minmax, const SigArgs& a, hipStream_t s) {
+  if (a.n == 0) return;
+  const dim3 g((unsigned)((a.n + 255) / 256)), b(256);
+  if (minmax)
+    launch_cap<true>(cap, g, b, s, a);
+  else
+    launch_cap<false>(cap, g, b, s, a);
+}
+
+void launch_row_len_range(const uint64_t* off, uint64_t n, unsigned long long* out, hipStream_t s) {
+  const uint64_t blocks = (n + 255) / 256;
+  const unsigned g = (unsigned)(blocks < 4096 ? (blocks ? blocks : 1) : 4096);
+  hipLaunchKernelGGL(k_row_len_range, dim3(g), dim3(256), 0, s, off, n, out);
+}
+
+}  // namespace fl

@@ -1,0 +1,595 @@
+// Grouping of band keys into hash-table buckets (section 6.1 "Hash table
+// construction").
+//
+// Every table's (key, id) pairs are grouped by two stable least-significant-
+// digit radix passes over the top 16 bits of fmix64(band key) (the mix
+// spreads the highly skewed packed-argmin keys evenly), which leaves each of
+// the 65,536 bins contiguous with its ids ascending.  A bin then holds a few
+// whole buckets (about N/65,536 elements), small enough to be sorted by the
+// full (key, id) inside LDS, where bucket boundaries, sizes, the raw
+// candidate count and the occurrence filter are derived in the same pass.
+// Bins too large for LDS (huge buckets) take a slower single-workgroup path.
+//
+// Radix pass = tile histogram -> segmented exclusive scan -> stable scatter.
+// The scatter ranks equal digits inside a wavefront with eight 64-lane
+// ballots (no LDS atomics, so the ranking is deterministic and stable), then
+// stages the tile in LDS in digit order so that global writes are runs of
+// consecutive addresses.
+#include "common.hpp"
+
+namespace fl {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;  // 4096
+constexpr int kRadix = 256;
+constexpr int kScanBlock = 4096;
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }
+
+// Lanes of the wave whose 8-bit digit equals this lane's.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d) {
+  uint64_t peers = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint32_t bit = (d >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    peers &= bit ? bal : ~bal;
+  }
+  return peers;
+}
+
+// ---------------------------------------------------------------------------
+// Radix pass kernels.  Segment s occupies [s*n, (s+1)*n) of every array.
+// vin == nullptr means the value of element e is e (its id).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t* keys, uint64_t n, uint32_t shift,
+                                                   uint32_t* hist, uint32_t ntiles) {
+  __shared__ uint32_t cnt[4][kRadix];
+  const uint32_t tid = threadIdx.x, wave = tid >> 6;
+  for (uint32_t q = tid; q < 4 * kRadix; q += kThreads) (&cnt[0][0])[q] = 0;
+  __syncthreads();
+  const uint64_t seg = blockIdx.y, tile = blockIdx.x;
+  const uint64_t* K = keys + seg * n;
+  const uint64_t e0 = tile * kTile;
+#pragma unroll 4
+  for (int k = 0; k < kItems; ++k) {
+    const uint64_t e = e0 + (uint64_t)k * kThreads + tid;
+    if (e < n) atomicAdd(&cnt[wave][(K[e] >> shift) & 0xFF], 1u);
+  }
+  __syncthreads();
+  const uint32_t d = tid;
+  hist[(seg * kRadix + d) * ntiles + tile] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                      uint32_t* vout, uint64_t n, uint32_t shift,
+                                                      const uint32_t* hist, uint32_t ntiles) {
+  __shared__ uint32_t wcnt[4][kRadix];
+  __shared__ uint32_t tstart[kRadix];
+  __shared__ uint32_t gbase[kRadix];
+  __shared__ uint32_t wsum[4];
+  __shared__ uint64_t sk[kTile];
+  __shared__ uint32_t sv[kTile];
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (uint32_t q = tid; q < 4 * kRadix; q += kThreads) (&wcnt[0][0])[q] = 0;
+  __syncthreads();
+  const uint64_t seg = blockIdx.y, tile = blockIdx.x;
+  const uint64_t* K = kin + seg * n;
+  const uint32_t* V = vin ? vin + seg * n : nullptr;
+  const uint64_t e0 = tile * kTile + (uint64_t)wave * (kTile / 4);
+  const uint64_t lt = lanemask_lt();
+
+  uint64_t key[kItems];
+  uint32_t val[kItems], rank[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint64_t e = e0 + (uint64_t)k * 64 + lane;
+    const bool ok = e < n;
+    key[k] = ok ? K[e] : ~0ull;
+    val[k] = ok ? (V ? V[e] : (uint32_t)e) : 0u;
+    const uint32_t d = ok ? (uint32_t)(key[k] >> shift) & 0xFF : 0xFFu;
+    const uint64_t peers = match_digit(d);
+    const uint32_t before = __popcll(peers & lt);
+    const uint32_t base = wcnt[wave][d];
+    rank[k] = base + before;
+    if ((peers >> lane) == 1ull) wcnt[wave][d] = base + __popcll(peers);  // highest lane of the group
+  }
+  __syncthreads();
+  // Per digit: prefix over waves, tile total, then the tile-level digit start.
+  uint32_t tot;
+  {
+    const uint32_t d = tid;
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t c = wcnt[w][d];
+      wcnt[w][d] = s;
+      s += c;
+    }
+    tot = s;
+    gbase[d] = hist[(seg * kRadix + d) * ntiles + tile];
+  }
+  // exclusive scan of tot over the 256 digits
+  uint32_t inc = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += y;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  {
+    uint32_t add = 0;
+    for (uint32_t w = 0; w < wave; ++w) add += wsum[w];
+    tstart[tid] = add + inc - tot;
+  }
+  __syncthreads();
+  const uint64_t tile0 = tile * kTile;
+  const uint32_t nvalid = (uint32_t)((n - tile0) < (uint64_t)kTile ? (n - tile0) : (uint64_t)kTile);
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const uint64_t e = e0 + (uint64_t)k * 64 + lane;
+    if (e < n) {
+      const uint32_t d = (uint32_t)(key[k] >> shift) & 0xFF;
+      const uint32_t pos = tstart[d] + wcnt[wave][d] + rank[k];
+      sk[pos] = key[k];
+      sv[pos] = val[k];
+    }
+  }
+  __syncthreads();
+  uint64_t* KO = kout + seg * n;
+  uint32_t* VO = vout + seg * n;
+  for (uint32_t q = tid; q < nvalid; q += kThreads) {
+    const uint64_t k = sk[q];
+    const uint32_t d = (uint32_t)(k >> shift) & 0xFF;
+    const uint64_t g = (uint64_t)gbase[d] + (q - tstart[d]);
+    KO[g] = k;
+    VO[g] = sv[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segmented exclusive scan: S segments of len elements each, in blocks of
+// kScanBlock.  (1) block sums, (2) per-segment scan of block sums by one
+// workgroup, (3) block-local scan plus block offset.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* wsum, T* total) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  T inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += y;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  T add = 0, all = 0;
+  for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
+    if (w < wave) add += wsum[w];
+    all += wsum[w];
+  }
+  __syncthreads();
+  if (total) *total = all;
+  return add + inc - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_sums(const T* data, uint64_t len, T* sums, uint32_t nblk) {
+  const uint64_t seg = blockIdx.y, blk = blockIdx.x;
+  const T* d = data + seg * len;
+  const uint64_t b0 = blk * (uint64_t)kScanBlock;
+  T s = 0;
+  for (uint32_t q = threadIdx.x; q < kScanBlock; q += kThreads) {
+    const uint64_t e = b0 + q;
+    if (e < len) s += d[e];
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ T ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) sums[seg * nblk + blk] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_blocksums(T* sums, uint32_t nblk, T* seg_total) {
+  __shared__ T ws[4];
+  __shared__ T carry;
+  const uint64_t seg = blockIdx.x;
+  T* s = sums + seg * nblk;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < nblk; b0 += kThreads) {
+    const uint32_t b = b0 + threadIdx.x;
+    const T v = b < nblk ? s[b] : (T)0;
+    T tot;
+    const T ex = block_excl_scan<T>(v, ws, &tot);
+    const T c = carry;
+    if (b < nblk) s[b] = c + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c + tot;
+    __syncthreads();
+  }
+  if (seg_total && threadIdx.x == 0) seg_total[seg] = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t len, const T* sums, uint32_t nblk) {
+  __shared__ T ws[4];
+  const uint64_t seg = blockIdx.y, blk = blockIdx.x;
+  T* d = data + seg * len;
+  const uint64_t b0 = blk * (uint64_t)kScanBlock;
+  constexpr int per = kScanBlock / kThreads;  // 16 consecutive elements per thread
+  T v[per];
+  T s = 0;
+  const uint64_t base = b0 + (uint64_t)threadIdx.x * per;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    const uint64_t e = base + q;
+    v[q] = e < len ? d[e] : (T)0;
+    s += v[q];
+  }
+  T tot;
+  T ex = block_excl_scan<T>(s, ws, &tot) + sums[seg * nblk + blk];
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    const uint64_t e = base + q;
+    if (e < len) d[e] = ex;
+    ex += v[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Buckets from the bin-sorted order.
+// ---------------------------------------------------------------------------
+constexpr int kBinCap = 4096;
+
+__device__ __forceinline__ bool kv_less(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb) {
+  return ka < kb || (ka == kb && va < vb);
+}
+
+// In-LDS bitonic sort of P2 (a power of two) (key, id) pairs.
+__device__ void bitonic_sort(uint64_t* sk, uint32_t* sv, uint32_t P2) {
+  for (uint32_t k = 2; k <= P2; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t t = threadIdx.x; t < P2 / 2; t += blockDim.x) {
+        const uint32_t i = 2 * j * (t / j) + (t % j);
+        const uint32_t l = i + j;
+        const bool up = (i & k) == 0;
+        const uint64_t ki = sk[i], kl = sk[l];
+        const uint32_t vi = sv[i], vl = sv[l];
+        const bool gt = kv_less(kl, vl, ki, vi);
+        if (gt == up) {
+          sk[i] = kl; sv[i] = vl;
+          sk[l] = ki; sv[l] = vi;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t station_size(const BucketArgs& a, uint32_t id) {
+  uint32_t s = 0;
+  while (s + 1 < a.nstation && a.station_base[s + 1] <= id) ++s;
+  return a.station_base[s + 1] - a.station_base[s];
+}
+
+struct BucketTotals {
+  unsigned long long e_raw;
+  unsigned int max_bucket;
+};
+
+// Account one bucket (run of equal keys) of `size` members; ids(q) gives the
+// q-th member.  Returns the descriptor class: 0 none, 1 small, 2 big.
+template <typename IdAt>
+__device__ __forceinline__ int bucket_account(const BucketArgs& a, uint64_t size, IdAt ids, uint32_t first_id,
+                                              BucketTotals& tot) {
+  tot.e_raw += (unsigned long long)(size * (size - 1) / 2);
+  if (size > tot.max_bucket) tot.max_bucket = (unsigned int)size;
+  if (a.occ_den) {
+    const uint64_t ns = station_size(a, first_id);
+    if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num)
+      for (uint64_t q = 0; q < size; ++q) a.flags[ids(q)] = 1;
+  }
+  if (size < 2) return 0;
+  return size <= a.small_max ? 1 : 2;
+}
+
+__device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
+  unsigned long long e = tot.e_raw;
+  unsigned int m = tot.max_bucket;
+  for (int o = 32; o > 0; o >>= 1) {
+    e += __shfl_xor(e, o, 64);
+    const unsigned int om = __shfl_xor(m, o, 64);
+    m = om > m ? om : m;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (e) atomicAdd(a.e_raw, e);
+    atomicMax(a.max_bucket, m);
+  }
+}
+
+// Sort [lo, hi) of segment seg (hi - lo <= kBinCap, whole bins) in LDS by
+// (key, id), write the ids back in that order, and account every bucket.
+__device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uint64_t hi, uint64_t* sk,
+                             uint32_t* sv, uint32_t* sh, BucketTotals& tot) {
+  const uint64_t* K = a.keys + (uint64_t)seg * a.n;
+  uint32_t* V = a.vals + (uint64_t)seg * a.n;
+  const uint32_t m = (uint32_t)(hi - lo);
+  uint32_t P2 = 1;
+  while (P2 < m) P2 <<= 1;
+  for (uint32_t e = threadIdx.x; e < P2; e += blockDim.x) {
+    if (e < m) {
+      sk[e] = K[lo + e];
+      sv[e] = V[lo + e];
+    } else {
+      sk[e] = ~0ull;
+      sv[e] = ~0u;
+    }
+  }
+  __syncthreads();
+  bitonic_sort(sk, sv, P2);
+  for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) V[lo + e] = sv[e];
+  // Buckets: pass 1 counts descriptors per thread, pass 2 writes them.
+  uint32_t nsmall = 0, nbig = 0;
+  for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
+    if (e > 0 && sk[e] == sk[e - 1]) continue;
+    uint32_t f = e + 1;
+    while (f < m && sk[f] == sk[e]) ++f;
+    const int cls = bucket_account(a, f - e, [&](uint64_t q) { return sv[e + q]; }, sv[e], tot);
+    nsmall += cls == 1;
+    nbig += cls == 2;
+  }
+  uint32_t* ws = sh;       // 4 entries
+  uint32_t* base = sh + 4; // 2 entries
+  uint32_t tsmall, tbig;
+  const uint32_t xs = block_excl_scan<uint32_t>(nsmall, ws, &tsmall);
+  const uint32_t xb = block_excl_scan<uint32_t>(nbig, ws, &tbig);
+  if (threadIdx.x == 0) {
+    base[0] = tsmall ? atomicAdd(a.small_count, tsmall) : 0;
+    base[1] = tbig ? atomicAdd(a.big_count, tbig) : 0;
+  }
+  __syncthreads();
+  uint32_t ps = base[0] + xs, pb = base[1] + xb;
+  if (nsmall | nbig) {
+    for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
+      if (e > 0 && sk[e] == sk[e - 1]) continue;
+      uint32_t f = e + 1;
+      while (f < m && sk[f] == sk[e]) ++f;
+      const uint32_t size = f - e;
+      if (size < 2) continue;
+      const uint32_t pos = (uint32_t)(lo + e);
+      if (size <= a.small_max)
+        a.small_desc[ps++] = make_uint2(pos, (seg << 16) | size);
+      else
+        a.big_desc[pb++] = make_uint4(pos, seg, size, 0);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
+  __shared__ uint64_t sk[kBinCap];
+  __shared__ uint32_t sv[kBinCap];
+  __shared__ uint32_t sh[16];
+  __shared__ unsigned long long s_hi;
+  __shared__ int s_first, s_last;
+  const uint32_t seg = blockIdx.y;
+  const uint64_t n = a.n;
+  const uint64_t c0 = (uint64_t)blockIdx.x * a.chunk;
+  const uint64_t c1 = c0 + a.chunk < n ? c0 + a.chunk : n;
+  const uint64_t* K = a.keys + (uint64_t)seg * n;
+  if (threadIdx.x == 0) {
+    s_first = 0x7FFFFFFF;
+    s_last = -1;
+    s_hi = ~0ull;
+  }
+  __syncthreads();
+  for (uint64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
+    if (p == 0 || (K[p] >> 48) != (K[p - 1] >> 48)) {
+      atomicMin(&s_first, (int)(p - c0));
+      atomicMax(&s_last, (int)(p - c0));
+    }
+  }
+  __syncthreads();
+  if (s_first == 0x7FFFFFFF) return;  // no bin starts in this chunk
+  const uint64_t lo = c0 + (uint64_t)s_first, last = c0 + (uint64_t)s_last;
+  // End of the last bin that starts in this chunk.
+  if (c1 == n) {
+    if (threadIdx.x == 0) s_hi = n;
+  } else {
+    const uint64_t binlast = K[c1 - 1] >> 48;
+    const uint64_t p = c1 + threadIdx.x;
+    if (p < n && (K[p] >> 48) != binlast) atomicMin(&s_hi, (unsigned long long)p);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_hi == ~0ull) {
+      uint64_t L = c1 + blockDim.x < n ? c1 + blockDim.x : n, R = n;  // first p in [L, R) with bin(p) > binlast
+      while (L < R) {
+        const uint64_t M = (L + R) / 2;
+        if ((K[M] >> 48) > binlast) R = M; else L = M + 1;
+      }
+      s_hi = L;
+    }
+  }
+  __syncthreads();
+  const uint64_t hi = s_hi;
+  BucketTotals tot{0ull, 0u};
+  if (hi - lo <= (uint64_t)kBinCap) {
+    process_bins(a, seg, lo, hi, sk, sv, sh, tot);
+  } else {
+    if (last > lo) process_bins(a, seg, lo, last, sk, sv, sh, tot);
+    if (hi - last <= (uint64_t)kBinCap) {
+      process_bins(a, seg, last, hi, sk, sv, sh, tot);
+    } else if (threadIdx.x == 0) {
+      const uint32_t q = atomicAdd(a.bin_count, 1u);
+      a.bin_desc[q] = make_uint4((uint32_t)last, (uint32_t)hi, seg, 0);
+    }
+  }
+  flush_totals(a, tot);
+}
+
+// ---------------------------------------------------------------------------
+// Oversized bins: one workgroup sorts [lo, hi) by the low 48 key bits with
+// stable 8-bit LSD passes through the scratch arrays (ids stay ascending
+// within equal keys) and then accounts the buckets.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* bins, uint64_t* tk, uint32_t* tv) {
+  __shared__ uint32_t cnt[kRadix];
+  __shared__ uint32_t wc[4][kRadix];
+  __shared__ uint32_t ws[8];
+  __shared__ uint64_t kmin, kmax;
+  __shared__ uint32_t heads[kThreads];
+  __shared__ uint32_t s_carry;
+  const uint4 bd = bins[blockIdx.x];
+  const uint64_t lo = bd.x, hi = bd.y;
+  const uint32_t seg = bd.z;
+  const uint64_t off = (uint64_t)seg * a.n;
+  uint64_t* K = const_cast<uint64_t*>(a.keys) + off;
+  uint32_t* V = a.vals + off;
+  uint64_t* TK = tk + off;
+  uint32_t* TV = tv + off;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  if (tid == 0) { kmin = ~0ull; kmax = 0; }
+  __syncthreads();
+  {
+    uint64_t mn = ~0ull, mx = 0;
+    for (uint64_t p = lo + tid; p < hi; p += kThreads) {
+      const uint64_t k = K[p];
+      mn = k < mn ? k : mn;
+      mx = k > mx ? k : mx;
+    }
+    atomicMin((unsigned long long*)&kmin, (unsigned long long)mn);
+    atomicMax((unsigned long long*)&kmax, (unsigned long long)mx);
+  }
+  __syncthreads();
+  if (kmin != kmax) {
+    uint64_t *sK = K, *dK = TK;
+    uint32_t *sV = V, *dV = TV;
+    for (uint32_t shift = 0; shift < 48; shift += 8) {
+      for (uint32_t d = tid; d < kRadix; d += kThreads) cnt[d] = 0;
+      __syncthreads();
+      for (uint64_t p = lo + tid; p < hi; p += kThreads) atomicAdd(&cnt[(sK[p] >> shift) & 0xFF], 1u);
+      __syncthreads();
+      {
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<uint32_t>(cnt[tid], ws, &tot);
+        __syncthreads();
+        cnt[tid] = ex;  // running output offset of each digit
+      }
+      __syncthreads();
+      const uint64_t lt = lanemask_lt();
+      for (uint64_t c = lo; c < hi; c += kThreads) {
+        for (uint32_t q = tid; q < 4 * kRadix; q += kThreads) (&wc[0][0])[q] = 0;
+        __syncthreads();
+        const uint64_t p = c + tid;
+        const bool ok = p < hi;
+        const uint64_t k = ok ? sK[p] : ~0ull;
+        const uint32_t v = ok ? sV[p] : 0u;
+        const uint32_t d = ok ? (uint32_t)(k >> shift) & 0xFF : 0xFFu;
+        const uint64_t peers = match_digit(d);
+        const uint32_t before = __popcll(peers & lt);
+        if ((peers >> lane) == 1ull) wc[wave][d] = __popcll(peers);
+        __syncthreads();
+        uint32_t cross = 0;
+        for (uint32_t w = 0; w < wave; ++w) cross += wc[w][d];
+        if (ok) {
+          const uint64_t dst = lo + cnt[d] + cross + before;
+          dK[dst] = k;
+          dV[dst] = v;
+        }
+        __syncthreads();
+        {
+          const uint32_t dd = tid;
+          cnt[dd] += wc[0][dd] + wc[1][dd] + wc[2][dd] + wc[3][dd];
+        }
+        __syncthreads();
+      }
+      uint64_t* t1 = sK; sK = dK; dK = t1;
+      uint32_t* t2 = sV; sV = dV; dV = t2;
+    }
+    // six passes: the data is back in K / V
+  }
+  // Account buckets, scanning the range in chunks of kThreads with the
+  // currently open run carried across chunks.
+  BucketTotals tot{0ull, 0u};
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  auto emit = [&](uint64_t s, uint64_t e) {
+    const int cls = bucket_account(a, e - s, [&](uint64_t q) { return V[s + q]; }, V[s], tot);
+    if (cls == 1) {
+      const uint32_t q = atomicAdd(a.small_count, 1u);
+      a.small_desc[q] = make_uint2((uint32_t)s, (seg << 16) | (uint32_t)(e - s));
+    } else if (cls == 2) {
+      const uint32_t q = atomicAdd(a.big_count, 1u);
+      a.big_desc[q] = make_uint4((uint32_t)s, seg, (uint32_t)(e - s), 0);
+    }
+  };
+  for (uint64_t c = lo; c < hi; c += kThreads) {
+    const uint64_t p = c + tid;
+    const uint32_t h = (p < hi && p > lo && K[p] != K[p - 1]) ? 1u : 0u;
+    uint32_t nh;
+    const uint32_t x = block_excl_scan<uint32_t>(h, ws, &nh);
+    if (h) heads[x] = (uint32_t)(p - lo);
+    __syncthreads();
+    const uint32_t carry = s_carry;
+    for (uint32_t q = tid; q < nh; q += kThreads) {
+      const uint64_t s = lo + (q == 0 ? carry : heads[q - 1]);
+      emit(s, lo + heads[q]);
+    }
+    __syncthreads();
+    if (tid == 0 && nh) s_carry = heads[nh - 1];
+    __syncthreads();
+  }
+  if (tid == 0) emit(lo + s_carry, hi);
+  flush_totals(a, tot);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+uint32_t radix_tiles(uint64_t n) { return (uint32_t)((n + kTile - 1) / kTile); }
+
+template <typename T>
+static void seg_scan(T* data, uint64_t len, uint32_t S, T* sums, T* seg_total, hipStream_t s) {
+  const uint32_t nblk = (uint32_t)((len + kScanBlock - 1) / kScanBlock);
+  if (nblk == 0) return;
+  hipLaunchKernelGGL((k_scan_sums<T>), dim3(nblk, S), dim3(kThreads), 0, s, data, len, sums, nblk);
+  hipLaunchKernelGGL((k_scan_blocksums<T>), dim3(S), dim3(kThreads), 0, s, sums, nblk, seg_total);
+  hipLaunchKernelGGL((k_scan_apply<T>), dim3(nblk, S), dim3(kThreads), 0, s, data, len, sums, nblk);
+}
+
+uint64_t scan_sums_elems(uint64_t len, uint32_t S) { return ((len + kScanBlock - 1) / kScanBlock) * S + 1; }
+
+void scan_u32(uint32_t* data, uint64_t len, uint32_t S, uint32_t* sums, uint32_t* seg_total, hipStream_t s) {
+  seg_scan<uint32_t>(data, len, S, sums, seg_total, s);
+}
+void scan_u64(uint64_t* data, uint64_t len, uint32_t S, uint64_t* sums, uint64_t* seg_total, hipStream_t s) {
+  seg_scan<uint64_t>(reinterpret_cast<uint64_t*>(data), len, S, sums, seg_total, s);
+}
+
+// One stable pass by the 8-bit digit at `shift`.
+void radix_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, uint64_t n, uint32_t S,
+                uint32_t shift, uint32_t* hist, uint32_t* sums, hipStream_t s) {
+  if (n == 0) return;
+  const uint32_t nt = radix_tiles(n);
+  hipLaunchKernelGGL(k_hist, dim3(nt, S), dim3(kThreads), 0, s, kin, n, shift, hist, nt);
+  seg_scan<uint32_t>(hist, (uint64_t)kRadix * nt, S, sums, nullptr, s);
+  hipLaunchKernelGGL(k_scatter, dim3(nt, S), dim3(kThreads), 0, s, kin, vin, kout, vout, n, shift, hist, nt);
+}
+
+void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s) {
+  if (a.n == 0) return;
+  const uint32_t nch = (uint32_t)((a.n + a.chunk - 1) / a.chunk);
+  hipLaunchKernelGGL(k_bucket, dim3(nch, S), dim3(kThreads), 0, s, a);
+}
+
+void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t nbins, uint64_t* tk, uint32_t* tv,
+                   hipStream_t s) {
+  if (nbins == 0) return;
+  hipLaunchKernelGGL(k_bigbin, dim3(nbins), dim3(kThreads), 0, s, a, bins, tk, tv);
+}
+
+}  // namespace fl

@@ -1,0 +1,183 @@
+"""Python binding of the fast_lsh C-ABI (include/fast_lsh.h).
+
+Argument marshalling only: every step of the search runs in the HIP library
+``libfast_lsh.so``.  PyTorch supplies device memory and the stream.  There is
+no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfast_lsh.so")
+
+OK, E_INVALID, E_NOMEM, E_CAPACITY, E_DEVICE, E_BUSY = range(6)
+MINHASH, MINMAX = 0, 1
+WANT_DISTINCT = 1
+
+_vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+
+
+class Hash(ctypes.Structure):
+    _fields_ = [("dim", _u32), ("num_tables", _u32), ("band_rows", _u32), ("scheme", _u32),
+                ("a", _vp), ("b", _vp)]
+
+
+class Fps(ctypes.Structure):
+    _fields_ = [("indices", _vp), ("offsets", _vp), ("fixed_nnz", _u32), ("reserved", _u32), ("n", _u64)]
+
+
+class Filter(ctypes.Structure):
+    _fields_ = [("min_lag", _u32), ("min_votes", _u32), ("occ_num", _u32), ("occ_den", _u32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(f, _u64) for f in ("n_out", "e_raw", "e_voted", "n_distinct", "n_flagged", "max_bucket")]
+
+
+@dataclass
+class Stats:
+    n_out: int
+    e_raw: int
+    e_voted: int
+    n_distinct: int
+    n_flagged: int
+    max_bucket: int
+
+
+class FastLshError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fast_lsh error {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def library():
+    """Load libfast_lsh.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise FastLshError(E_DEVICE, f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.fast_lsh_version.restype = _i32
+        lib.fast_lsh_last_error.restype = ctypes.c_char_p
+        lib.fast_lsh_ctx_create.argtypes = [_i32, _vp, _u64, ctypes.POINTER(_vp)]
+        lib.fast_lsh_ctx_destroy.argtypes = [_vp]
+        lib.fast_lsh_make_hash.argtypes = [_u64, _u32, _vp, _vp]
+        lib.fast_lsh_signatures.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps), _u32, _u32, _vp, _vp]
+        lib.fast_lsh_search.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps), ctypes.POINTER(Filter),
+                                        _vp, _vp, _vp, _u64, ctypes.POINTER(_Stats)]
+        lib.fast_lsh_search_ex.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps), ctypes.POINTER(Filter),
+                                           _u32, _vp, _vp, _vp, _u64, ctypes.POINTER(_Stats)]
+        lib.fast_lsh_copy_result.argtypes = [_vp, _vp, _vp, _vp, _u64]
+        _LIB = lib
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise FastLshError(rc, library().fast_lsh_last_error().decode())
+
+
+def n_funcs(t: int, r: int, scheme: int) -> int:
+    return t * r if scheme == MINHASH else t * (r // 2)
+
+
+def make_hash(seed: int, nf: int):
+    """(a, b) uint32 arrays of the seeded hash family (host-side)."""
+    a = np.empty(nf, np.uint32)
+    b = np.empty(nf, np.uint32)
+    _check(library().fast_lsh_make_hash(seed, nf, a.ctypes.data, b.ctypes.data))
+    return a, b
+
+
+def _hash_struct(dim, t, r, scheme, a, b):
+    a = np.ascontiguousarray(a, np.uint32)
+    b = np.ascontiguousarray(b, np.uint32)
+    h = Hash(dim, t, r, scheme, a.ctypes.data, b.ctypes.data)
+    return h, (a, b)
+
+
+def _fps_struct(rows):
+    """rows: a CUDA tensor [n, nnz] of 16-bit indices, or (indices, offsets)
+    CUDA tensors (16-bit indices, 64-bit offsets with n+1 entries)."""
+    if isinstance(rows, tuple):
+        ind, off = rows
+        assert ind.is_cuda and off.is_cuda and ind.element_size() == 2 and off.element_size() == 8
+        n = off.numel() - 1
+        return Fps(ind.data_ptr(), off.data_ptr(), 0, 0, n), (ind, off)
+    assert rows.is_cuda and rows.element_size() == 2 and rows.dim() == 2 and rows.is_contiguous()
+    return Fps(rows.data_ptr(), None, rows.shape[1], 0, rows.shape[0]), (rows,)
+
+
+def to_device_rows(rows_np: np.ndarray, device="cuda") -> torch.Tensor:
+    """uint16 numpy rows -> int16 CUDA tensor with the same bits."""
+    return torch.from_numpy(np.ascontiguousarray(rows_np).view(np.int16)).to(device)
+
+
+class FastLSH:
+    """One library context on a device, ordered on a torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None, hbm_budget: int = 0):
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        ctx = _vp()
+        _check(library().fast_lsh_ctx_create(device, self.stream.cuda_stream, hbm_budget, ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            library().fast_lsh_ctx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def signatures(self, rows, dim, t, r, scheme, a, b, table_begin=0, table_count=None, with_values=False):
+        """Band keys as int64 [table_count, n] (uint64 bit pattern); with
+        ``with_values`` also the hash values int32 [n, table_count, r]."""
+        tc = t - table_begin if table_count is None else table_count
+        h, keep = _hash_struct(dim, t, r, scheme, a, b)
+        f, keep2 = _fps_struct(rows)
+        dev = torch.device("cuda", self.device)
+        keys = torch.empty((tc, f.n), dtype=torch.int64, device=dev)
+        sigs = torch.empty((f.n, tc, r), dtype=torch.int32, device=dev) if with_values else None
+        _check(library().fast_lsh_signatures(self._ctx, ctypes.byref(h), ctypes.byref(f), table_begin, tc,
+                                             keys.data_ptr(), sigs.data_ptr() if with_values else None))
+        return (keys, sigs) if with_values else keys
+
+    def search(self, rows, dim, t, r, scheme, a, b, min_lag, min_votes, occ_num=0, occ_den=0,
+               want_distinct=False, capacity: int | None = None):
+        """Sorted (i, j, votes) CUDA tensors (int32, int32, uint8) and Stats."""
+        h, keep = _hash_struct(dim, t, r, scheme, a, b)
+        f, keep2 = _fps_struct(rows)
+        flt = Filter(min_lag, min_votes, occ_num, occ_den)
+        dev = torch.device("cuda", self.device)
+        cap = max(1, f.n // 4) if capacity is None else capacity
+        oi = torch.empty(cap, dtype=torch.int32, device=dev)
+        oj = torch.empty(cap, dtype=torch.int32, device=dev)
+        ov = torch.empty(cap, dtype=torch.uint8, device=dev)
+        st = _Stats()
+        rc = library().fast_lsh_search_ex(self._ctx, ctypes.byref(h), ctypes.byref(f), ctypes.byref(flt),
+                                          WANT_DISTINCT if want_distinct else 0, oi.data_ptr(), oj.data_ptr(),
+                                          ov.data_ptr(), cap, ctypes.byref(st))
+        if rc == E_CAPACITY and capacity is None:
+            cap = st.n_out
+            oi = torch.empty(cap, dtype=torch.int32, device=dev)
+            oj = torch.empty(cap, dtype=torch.int32, device=dev)
+            ov = torch.empty(cap, dtype=torch.uint8, device=dev)
+            rc = library().fast_lsh_copy_result(self._ctx, oi.data_ptr(), oj.data_ptr(), ov.data_ptr(), cap)
+        _check(rc)
+        m = st.n_out
+        stats = Stats(*[int(getattr(st, k)) for k, _ in _Stats._fields_])
+        return oi[:m], oj[:m], ov[:m], stats

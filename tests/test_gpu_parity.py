@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Every comparison is exact (integers only): band keys and hash values bit for
+bit, pair lists (i, j, votes) element by element, and all counters.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1803_09835_amd as fl  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fl.FastLSH(0)
+    yield c
+    c.close()
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def _rows_dev(rows):
+    if isinstance(rows, tuple):
+        ind, off = rows
+        return (torch.from_numpy(ind.view(np.int16)).cuda(), torch.from_numpy(off.view(np.int64)).cuda())
+    return fl.to_device_rows(rows)
+
+
+# ---------------------------------------------------------------------------
+# Hash parameters and signatures
+# ---------------------------------------------------------------------------
+def test_make_hash_matches_oracle():
+    for seed in (0, 201, 202, 2**63 + 5):
+        a, b = fl.make_hash(seed, 1000)
+        oa, ob = oracle.make_hash(seed, 1000)
+        assert (a == oa).all() and (b == ob).all()
+
+
+def _ragged(n, dim, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(lo, hi + 1, n)
+    rows = [np.sort(rng.choice(dim, L, replace=False)).astype(np.uint16) for L in lens]
+    return np.concatenate(rows), np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+
+
+def _fixed(n, dim, nnz, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([np.sort(rng.choice(dim, nnz, replace=False)) for _ in range(n)]).astype(np.uint16)
+
+
+SIG_CASES = [
+    # name, rows factory, dim, t, r, scheme
+    ("station-minmax-nnz200", lambda: synth.generate(synth.station(n=3000, seed=11)), 4096, 100, 4, fl.MINMAX),
+    ("uniform-minhash-nnz200", lambda: synth.generate(synth.tiny_uniform(n=3001, seed=12)), 4096, 20, 4, fl.MINHASH),
+    ("nnz100-dword-path", lambda: _fixed(777, 4096, 100, 13), 4096, 30, 4, fl.MINMAX),
+    ("nnz16", lambda: _fixed(300, 1000, 16, 14), 1000, 8, 2, fl.MINHASH),
+    ("nnz37-odd-long-path", lambda: _fixed(500, 4096, 37, 15), 4096, 12, 4, fl.MINHASH),
+    ("nnz300-long-path", lambda: _fixed(200, 4096, 300, 16), 4096, 10, 4, fl.MINMAX),
+    ("ragged", lambda: _ragged(400, 2048, 1, 90, 17), 2048, 16, 4, fl.MINMAX),
+    ("dim16-r3", lambda: _fixed(300, 16, 6, 18), 16, 9, 3, fl.MINHASH),
+    ("dim65536-r4-full64", lambda: _fixed(300, 65536, 64, 19), 65536, 7, 4, fl.MINMAX),
+    ("dim8192-r8-chained", lambda: _fixed(300, 8192, 128, 20), 8192, 6, 8, fl.MINMAX),
+]
+
+
+@pytest.mark.parametrize("name,make,dim,t,r,scheme", SIG_CASES, ids=[c[0] for c in SIG_CASES])
+def test_signatures_bit_exact(ctx, name, make, dim, t, r, scheme):
+    rows = make()
+    say(f"[sig] {name}")
+    nf = fl.n_funcs(t, r, scheme)
+    a, b = fl.make_hash(900 + t * r, nf)
+    keys, vals = ctx.signatures(_rows_dev(rows), dim, t, r, scheme, a, b, with_values=True)
+    torch.cuda.synchronize()
+    okeys, ovals = oracle.signatures(rows, dim, t, r, scheme, a, b, with_values=True)
+    assert np.array_equal(_u64(keys), okeys)
+    assert np.array_equal(vals.cpu().numpy().view(np.uint32), ovals)
+
+
+def test_signatures_table_range(ctx):
+    rows = synth.generate(synth.station(n=1000, seed=21))
+    a, b = fl.make_hash(5, 100)
+    okeys = oracle.signatures(rows, 4096, 50, 4, oracle.MINMAX, a, b)
+    keys = ctx.signatures(_rows_dev(rows), 4096, 50, 4, fl.MINMAX, a, b, table_begin=17, table_count=9)
+    assert np.array_equal(_u64(keys), okeys[17:26])
+
+
+def test_signatures_reject_bad_input(ctx):
+    a, b = fl.make_hash(1, 40)
+    bad = _fixed(64, 4096, 200, 22)
+    bad[10, 5] = 4096  # index >= dim
+    with pytest.raises(fl.FastLshError) as e:
+        ctx.signatures(_rows_dev(bad), 4096, 20, 4, fl.MINMAX, a, b)
+    assert e.value.code == 1
+    ind, off = _ragged(50, 512, 1, 10, 23)
+    off[7] = off[8]  # empty row 7
+    off = off.copy()
+    with pytest.raises(fl.FastLshError):
+        ctx.signatures(_rows_dev((ind, off)), 512, 20, 4, fl.MINMAX, a, b)
+    with pytest.raises(fl.FastLshError):
+        ctx.signatures(_rows_dev(_fixed(10, 64, 4, 24)), 64, 20, 3, fl.MINMAX, a, b)  # odd r, Min-Max
+    bad_a = a.copy()
+    bad_a[3] = 0
+    with pytest.raises(fl.FastLshError):
+        ctx.signatures(_rows_dev(_fixed(10, 64, 4, 24)), 64, 20, 4, fl.MINMAX, bad_a, b)
+
+
+# ---------------------------------------------------------------------------
+# Search
+# ---------------------------------------------------------------------------
+def _compare(ctx, rows, dim, t, r, scheme, seed, L, v, num=0, den=0, distinct=False, label=""):
+    say(f"[search] {label} n={len(rows) if not isinstance(rows, tuple) else len(rows[1]) - 1} t={t} r={r} "
+        f"scheme={scheme} L={L} v={v} occ={num}/{den} distinct={distinct}")
+    nf = fl.n_funcs(t, r, scheme)
+    a, b = fl.make_hash(seed, nf)
+    gi, gj, gv, gst = ctx.search(_rows_dev(rows), dim, t, r, scheme, a, b, L, v, num, den, want_distinct=distinct)
+    torch.cuda.synchronize()
+    keys = oracle.signatures(rows, dim, t, r, scheme, a, b)
+    ei, ej, ev, est = oracle.search_keys(keys, L, v, num, den)
+    gi = gi.cpu().numpy().view(np.uint32)
+    gj = gj.cpu().numpy().view(np.uint32)
+    gv = gv.cpu().numpy()
+    assert len(gi) == len(ei), (len(gi), len(ei))
+    assert np.array_equal(gi, ei)
+    assert np.array_equal(gj, ej)
+    assert np.array_equal(gv, ev)
+    want = dict(est.__dict__)
+    got = dict(gst.__dict__)
+    if not distinct:
+        assert got.pop("n_distinct") == 2**64 - 1
+        want.pop("n_distinct")
+    assert got == want
+    return gst
+
+
+def test_search_tiny_uniform_full(ctx):
+    rows = synth.generate(synth.tiny_uniform())
+    st = _compare(ctx, rows, 4096, 20, 4, fl.MINHASH, 201, 5, 2, label="tiny-uniform-20k")
+    assert st.n_out > 50
+    _compare(ctx, rows, 4096, 20, 4, fl.MINHASH, 201, 5, 2, distinct=True, label="tiny-uniform-20k")
+
+
+@pytest.mark.parametrize("n", [50_000, 200_000])
+def test_search_station(ctx, n):
+    rows = synth.generate(synth.station(n=n, seed=102))
+    st = _compare(ctx, rows, 4096, 100, 4, fl.MINMAX, 202, 5, 4, 1, 100, label="station")
+    assert st.n_out > 0
+    if n == 50_000:
+        _compare(ctx, rows, 4096, 100, 4, fl.MINMAX, 202, 5, 4, 1, 100, distinct=True, label="station")
+
+
+def test_search_station_minhash_v3(ctx):
+    rows = synth.generate(synth.station(n=60_000, seed=31))
+    _compare(ctx, rows, 4096, 40, 4, fl.MINHASH, 33, 5, 3, label="station-minhash")
+
+
+@pytest.mark.parametrize("num,den", [(1, 100), (0, 0)])
+def test_search_repeating_noise(ctx, num, den):
+    # 5 % of slots are 95 %-copies of one noise template: huge buckets that the
+    # occurrence filter removes, or (filter off) the large-bucket tile path.
+    rows = synth.generate(synth.with_noise(synth.station(n=30_000, seed=41), 50, 190))
+    st = _compare(ctx, rows, 4096, 100, 4, fl.MINMAX, 42, 5, 4, num, den, label="noise")
+    assert st.max_bucket > 300
+    if den:
+        assert st.n_flagged > 1000
+
+
+def test_search_huge_bins(ctx):
+    # Every fingerprint identical: one bucket of n in every table (oversized
+    # bins, the single-workgroup sort path and tiled pairs).
+    rows = np.repeat(_fixed(1, 4096, 200, 43), 5000, axis=0)
+    st = _compare(ctx, rows, 4096, 3, 4, fl.MINMAX, 44, 100, 2, label="identical")
+    assert st.max_bucket == 5000 and st.n_out == (5000 - 100) * (5000 - 99) // 2
+
+
+def test_search_mixed_huge_bins(ctx):
+    # Half the rows identical (one giant bucket per table), the rest random:
+    # oversized bins that also hold other keys.
+    rows = _fixed(9000, 256, 8, 45)
+    rows[::2] = rows[0]
+    _compare(ctx, rows, 256, 4, 2, fl.MINHASH, 46, 1, 2, label="mixed-identical")
+
+
+EDGE = [
+    ("n1", lambda: _fixed(1, 4096, 200, 50), 4096, 10, 4, fl.MINMAX, 5, 2),
+    ("n2-identical", lambda: np.repeat(_fixed(1, 4096, 200, 51), 2, axis=0), 4096, 10, 4, fl.MINMAX, 1, 10),
+    ("t1-v1", lambda: _fixed(3000, 64, 4, 52), 64, 1, 2, fl.MINHASH, 0, 1),
+    ("v1-lag0", lambda: _fixed(2000, 128, 6, 53), 128, 8, 2, fl.MINMAX, 0, 1),
+    ("v-above-t", lambda: _fixed(2000, 128, 6, 54), 128, 3, 2, fl.MINMAX, 0, 4),
+    ("lag-huge", lambda: _fixed(2000, 128, 6, 55), 128, 8, 2, fl.MINMAX, 1500, 1),
+    ("ragged", lambda: _ragged(3000, 512, 1, 40, 56), 512, 12, 2, fl.MINMAX, 3, 2),
+    ("odd-nnz", lambda: _fixed(3000, 256, 7, 57), 256, 12, 2, fl.MINHASH, 3, 3),
+    ("t255", lambda: _fixed(1500, 128, 5, 58), 128, 255, 1, fl.MINHASH, 2, 30),
+]
+
+
+@pytest.mark.parametrize("name,make,dim,t,r,scheme,L,v", EDGE, ids=[e[0] for e in EDGE])
+def test_search_edge_cases(ctx, name, make, dim, t, r, scheme, L, v):
+    rows = make()
+    _compare(ctx, rows, dim, t, r, scheme, 60, L, v, label=name)
+    _compare(ctx, rows, dim, t, r, scheme, 60, L, v, distinct=True, label=name)
+
+
+def test_search_empty(ctx):
+    a, b = fl.make_hash(1, 40)
+    empty = torch.empty((0, 200), dtype=torch.int16, device="cuda")
+    gi, gj, gv, st = ctx.search(empty, 4096, 20, 2, fl.MINHASH, a, b, 5, 2)
+    assert len(gi) == 0 and st.n_out == 0 and st.e_raw == 0
+
+
+def test_search_capacity_and_copy(ctx):
+    rows = synth.generate(synth.tiny_uniform(n=20_000, seed=61))
+    a, b = fl.make_hash(62, 80)
+    gi, gj, gv, st = ctx.search(fl.to_device_rows(rows), 4096, 20, 4, fl.MINHASH, a, b, 5, 1)
+    assert st.n_out > 10
+    with pytest.raises(fl.FastLshError) as e:
+        ctx.search(fl.to_device_rows(rows), 4096, 20, 4, fl.MINHASH, a, b, 5, 1, capacity=5)
+    assert e.value.code == 3
+    # the result stays in the context: copy it into a large enough buffer
+    cap = st.n_out
+    oi = torch.empty(cap, dtype=torch.int32, device="cuda")
+    oj = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ov = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    rc = fl.library().fast_lsh_copy_result(ctx._ctx, oi.data_ptr(), oj.data_ptr(), ov.data_ptr(), cap)
+    assert rc == 0
+    assert torch.equal(oi, gi) and torch.equal(oj, gj) and torch.equal(ov, gv)
+
+
+def test_search_deterministic(ctx):
+    rows = synth.generate(synth.station(n=100_000, seed=71))
+    a, b = fl.make_hash(72, 200)
+    outs = [ctx.search(fl.to_device_rows(rows), 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100) for _ in range(2)]
+    for x, y in zip(outs[0][:3], outs[1][:3]):
+        assert torch.equal(x, y)
+    assert outs[0][3] == outs[1][3]
+
+
+def test_search_rejects_bad_input(ctx):
+    a, b = fl.make_hash(1, 40)
+    bad = _fixed(100, 4096, 200, 81)
+    bad[3, 0] = 5000
+    with pytest.raises(fl.FastLshError) as e:
+        ctx.search(fl.to_device_rows(bad), 4096, 20, 2, fl.MINHASH, a, b, 5, 2)
+    assert e.value.code == 1
+    with pytest.raises(fl.FastLshError):
+        ctx.search(fl.to_device_rows(_fixed(10, 4096, 200, 82)), 4096, 20, 2, fl.MINHASH, a, b, 5, 0)
