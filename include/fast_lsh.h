@@ -178,6 +178,29 @@ int fast_lsh_search_ex(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_
 int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes,
                          uint64_t capacity);
 
+/* Stage timing.  While enabled, the context records a pair of HIP events on
+ * its stream around every kernel launch of the stages below and accumulates
+ * their elapsed times when each call completes.  Enabling resets the
+ * counters.  Stages: */
+enum {
+  FAST_LSH_STAGE_SIGNATURES = 0, /* signature kernel                          */
+  FAST_LSH_STAGE_GROUP = 1,      /* the two radix passes that bin every table */
+  FAST_LSH_STAGE_BUCKETS = 2,    /* per-bin sort, bucket sizes, filter flags  */
+  FAST_LSH_STAGE_BIG_BINS = 3,   /* bins too large for LDS                    */
+  FAST_LSH_STAGE_PAIRS = 4,      /* in-bucket pairs and votes, small buckets  */
+  FAST_LSH_STAGE_BIG_PAIRS = 5,  /* tiled pairs of large buckets              */
+  FAST_LSH_STAGE_OUTPUT = 6,     /* canonical sort of the reported pairs      */
+  FAST_LSH_PROFILE_STAGES = 8
+};
+
+typedef struct {
+  double ms[FAST_LSH_PROFILE_STAGES];         /* summed kernel time per stage */
+  uint64_t launches[FAST_LSH_PROFILE_STAGES]; /* timed intervals per stage    */
+} fast_lsh_profile;
+
+int fast_lsh_profile_enable(fast_lsh_ctx *ctx, int enable);
+int fast_lsh_profile_read(fast_lsh_ctx *ctx, fast_lsh_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

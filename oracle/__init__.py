@@ -66,6 +66,7 @@ def _lib():
         lib.orc_pair_votes.argtypes = [_u32, _u64, _vp, _u64, _u64]
         lib.orc_pair_votes.restype = _u32
         lib.orc_free.argtypes = [_vp]
+        lib.orc_max_threads.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -163,6 +164,10 @@ def search(rows, dim: int, t: int, r: int, scheme: int, a, b, min_lag: int, min_
            occ_num: int = 0, occ_den: int = 0):
     keys = signatures(rows, dim, t, r, scheme, a, b)
     return search_keys(keys, min_lag, min_votes, occ_num, occ_den)
+
+
+def max_threads() -> int:
+    return int(_lib().orc_max_threads())
 
 
 def pair_votes(keys: np.ndarray, i: int, j: int) -> int:

@@ -35,6 +35,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_P 2147483647ull /* 2^31 - 1 */
 
@@ -302,3 +305,12 @@ uint32_t orc_pair_votes(uint32_t t, uint64_t n, const uint64_t *keys, uint64_t i
 }
 
 void orc_free(void *p) { free(p); }
+
+/* Threads the OpenMP loops of the oracle use. */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

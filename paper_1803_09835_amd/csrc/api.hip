@@ -100,7 +100,43 @@ struct fast_lsh_ctx {
   std::vector<uint64_t> hstage;   // host staging for small uploads
   uint64_t res_count = 0;
   bool res_valid = false;
+  // stage timing (HIP events on the context stream around each launch)
+  static constexpr int kMaxRec = 256;
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  int rec_stage[kMaxRec];
+  int nrec = 0;
+  double prof_ms[FAST_LSH_PROFILE_STAGES] = {0};
+  uint64_t prof_launches[FAST_LSH_PROFILE_STAGES] = {0};
 };
+
+static void prof_begin(fast_lsh_ctx* c, int stage) {
+  if (!c->prof || c->nrec >= fast_lsh_ctx::kMaxRec) return;
+  if (c->ev.empty()) {
+    c->ev.resize(2 * fast_lsh_ctx::kMaxRec);
+    for (auto& e : c->ev) (void)hipEventCreate(&e);
+  }
+  c->rec_stage[c->nrec] = stage;
+  (void)hipEventRecord(c->ev[2 * c->nrec], c->stream);
+}
+
+static void prof_end(fast_lsh_ctx* c) {
+  if (!c->prof || c->nrec >= fast_lsh_ctx::kMaxRec) return;
+  (void)hipEventRecord(c->ev[2 * c->nrec + 1], c->stream);
+  ++c->nrec;
+}
+
+// Accumulate recorded intervals (the caller has synchronised the stream).
+static void prof_collect(fast_lsh_ctx* c) {
+  for (int k = 0; k < c->nrec; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) == hipSuccess) {
+      c->prof_ms[c->rec_stage[k]] += ms;
+      c->prof_launches[c->rec_stage[k]] += 1;
+    }
+  }
+  c->nrec = 0;
+}
 
 static int ws_get(fast_lsh_ctx* c, const char* name, size_t bytes, void** out) {
   Buf& b = c->ws[name];
@@ -302,6 +338,7 @@ void fast_lsh_ctx_destroy(fast_lsh_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
   for (auto& kv : c->ws)
     if (kv.second.p) (void)hipFree(kv.second.p);
   delete c;
@@ -342,10 +379,13 @@ int fast_lsh_signatures(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_
   a.vec_load = vec;
   a.keys = keys;
   a.sigs = sigs;
+  prof_begin(c, FAST_LSH_STAGE_SIGNATURES);
   launch_sig(cap, h->scheme == FAST_LSH_MINMAX, a, c->stream);
+  prof_end(c);
   LAUNCHCK();
   int herr = 0;
   RC(d2h(c, &herr, err));
+  prof_collect(c);
   if (herr) return fail(FAST_LSH_E_INVALID, "a fingerprint is empty or holds an index >= dim (%u)", h->dim);
   return FAST_LSH_OK;
 }
@@ -430,7 +470,9 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   sa.rows = rows;
   sa.tables_per_group = pl.TG;
   sa.row_hw = pl.row_hw;
+  prof_begin(c, FAST_LSH_STAGE_SIGNATURES);
   launch_sig(cap, h->scheme == FAST_LSH_MINMAX, sa, s);
+  prof_end(c);
   LAUNCHCK();
 
   // 2. two stable radix passes on the top 16 bits, all tables at once
@@ -438,9 +480,11 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   uint32_t *hist, *sums;
   RC(ws<uint32_t>(c, "hist", (uint64_t)256 * nt * t, &hist));
   RC(ws<uint32_t>(c, "sums", scan_sums_elems((uint64_t)256 * nt, t), &sums));
+  prof_begin(c, FAST_LSH_STAGE_GROUP);
   radix_pass(mkeys, nullptr, ak, av, n, t, 48, hist, sums, s);
   LAUNCHCK();
   radix_pass(ak, av, bk, bv, n, t, 56, hist, sums, s);
+  prof_end(c);
   LAUNCHCK();
 
   // 3. buckets
@@ -491,13 +535,17 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   ba.bin_count = &dc->bin_count;
   ba.e_raw = &dc->e_raw;
   ba.max_bucket = &dc->max_bucket;
+  prof_begin(c, FAST_LSH_STAGE_BUCKETS);
   launch_bucket(ba, t, s);
+  prof_end(c);
   LAUNCHCK();
   DevCounters hc;
   RC(d2h(c, &hc, dc));
   if (hc.err) return fail(FAST_LSH_E_INVALID, "a fingerprint is empty or holds an index >= dim (%u)", h->dim);
   if (hc.bin_count) {
+    prof_begin(c, FAST_LSH_STAGE_BIG_BINS);
     launch_bigbin(ba, bins, hc.bin_count, ak, av, s);
+    prof_end(c);
     LAUNCHCK();
   }
   launch_count_flags(fl8, n, &dc->n_flagged, s);
@@ -553,7 +601,9 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
       LAUNCHCK();
       uint64_t members = 0;
       RC(d2h(c, &members, total));
+      prof_begin(c, FAST_LSH_STAGE_PAIRS);
       launch_pairs_small(pa, sdesc, prefix, hc.small_count, members, sc, s);
+      prof_end(c);
       LAUNCHCK();
     }
     if (hc.big_count) {
@@ -588,7 +638,9 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
         RC(h2d(c, du, units.data(), units.size()));
         for (size_t u0 = 0; u0 < units.size(); u0 += 1u << 20) {
           const uint32_t cnt = (uint32_t)std::min<size_t>(1u << 20, units.size() - u0);
+          prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
           launch_pairs_tile(pa, du + u0, cnt, bdesc, dcofs, bids, bcnt, tb, rswl, s);
+          prof_end(c);
           LAUNCHCK();
         }
       }
@@ -625,7 +677,9 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
     for (uint32_t sh = 0; sh < nb; sh += 8) shifts.push_back(sh);
     for (uint32_t sh = 0; sh < nb; sh += 8) shifts.push_back(32 + sh);
     for (uint32_t sh : shifts) {
+      prof_begin(c, FAST_LSH_STAGE_OUTPUT);
       radix_pass(rk0, rv0, rk1, rv1, cnt, 1, sh, ohist, osums, s);
+      prof_end(c);
       LAUNCHCK();
       std::swap(rk0, rk1);
       std::swap(rv0, rv1);
@@ -645,6 +699,8 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
     (void)v0;
   }
 
+  HIPCK(hipStreamSynchronize(s));
+  prof_collect(c);
   fast_lsh_stats stv;
   stv.n_out = cnt;
   stv.e_raw = hc.e_raw;
@@ -657,6 +713,26 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
 }
 
 extern "C" {
+
+int fast_lsh_profile_enable(fast_lsh_ctx* c, int enable) {
+  if (!c) return fail(FAST_LSH_E_INVALID, "ctx is NULL");
+  c->prof = enable != 0;
+  c->nrec = 0;
+  for (int k = 0; k < FAST_LSH_PROFILE_STAGES; ++k) {
+    c->prof_ms[k] = 0;
+    c->prof_launches[k] = 0;
+  }
+  return FAST_LSH_OK;
+}
+
+int fast_lsh_profile_read(fast_lsh_ctx* c, fast_lsh_profile* out) {
+  if (!c || !out) return fail(FAST_LSH_E_INVALID, "ctx or out is NULL");
+  for (int k = 0; k < FAST_LSH_PROFILE_STAGES; ++k) {
+    out->ms[k] = c->prof_ms[k];
+    out->launches[k] = c->prof_launches[k];
+  }
+  return FAST_LSH_OK;
+}
 
 int fast_lsh_copy_result(fast_lsh_ctx* c, uint32_t* oi, uint32_t* oj, uint8_t* ov, uint64_t capacity) {
   if (!c) return fail(FAST_LSH_E_INVALID, "ctx is NULL");

@@ -40,6 +40,13 @@ class _Stats(ctypes.Structure):
     _fields_ = [(f, _u64) for f in ("n_out", "e_raw", "e_voted", "n_distinct", "n_flagged", "max_bucket")]
 
 
+PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pairs", "output", "reserved")
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8)]
+
+
 @dataclass
 class Stats:
     n_out: int
@@ -77,6 +84,8 @@ def library():
         lib.fast_lsh_search_ex.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps), ctypes.POINTER(Filter),
                                            _u32, _vp, _vp, _vp, _u64, ctypes.POINTER(_Stats)]
         lib.fast_lsh_copy_result.argtypes = [_vp, _vp, _vp, _vp, _u64]
+        lib.fast_lsh_profile_enable.argtypes = [_vp, _i32]
+        lib.fast_lsh_profile_read.argtypes = [_vp, ctypes.POINTER(_Profile)]
         _LIB = lib
     return _LIB
 
@@ -142,6 +151,16 @@ class FastLSH:
             self.close()
         except Exception:
             pass
+
+    def profile_enable(self, on: bool = True):
+        """Start (and reset) per-stage kernel timing with HIP events on the context stream."""
+        _check(library().fast_lsh_profile_enable(self._ctx, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{stage: (summed kernel ms, timed launches)} since profile_enable."""
+        p = _Profile()
+        _check(library().fast_lsh_profile_read(self._ctx, ctypes.byref(p)))
+        return {name: (p.ms[k], int(p.launches[k])) for k, name in enumerate(PROFILE_STAGES) if name != "reserved"}
 
     def signatures(self, rows, dim, t, r, scheme, a, b, table_begin=0, table_count=None, with_values=False):
         """Band keys as int64 [table_count, n] (uint64 bit pattern); with
