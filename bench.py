@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--n", type=int, default=7_776_000, help="fingerprints (default: 90 days at 1 s)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="fingerprints of the same workload the CPU oracle is timed on (0: skip)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, copy this many MiB device-to-device with a plain copy kernel "
+                         "(reference dispatch for HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -89,6 +92,12 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     st = out[3]
     value = N / (ms_per_step / 1000.0)

@@ -496,15 +496,17 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   c->hstage.assign({0ull, n});
   RC(h2d(c, sbase, c->hstage.data(), 2));
 
-  // Pair-stage shapes (LDS budget of 64 KB per workgroup).
+  // Pair-stage shapes: about 32 KB of LDS per workgroup so that several
+  // workgroups share a CU.
   SmallCfg sc;
   sc.rswl = pl.rsw | 1u;
-  const uint32_t per_member = sc.rswl * 4 + 15;
-  sc.memb_max = 65536 / per_member;
-  const uint32_t smax = std::min<uint32_t>(128, sc.memb_max / 2);
+  const uint32_t lds_budget = 32768;
+  const uint32_t per_member = sc.rswl * 4 + 4 + 8;
+  sc.memb_max = std::max<uint32_t>(16, lds_budget / per_member);
+  const uint32_t smax = std::min<uint32_t>(64, sc.memb_max / 2);
   sc.mb = sc.memb_max - smax + 1;
   sc.nb_max = sc.mb / 2 + 2;
-  while (small_smem_bytes(sc) > 65536 && sc.memb_max > 8) {
+  while (small_smem_bytes(sc) > lds_budget && sc.memb_max > 2 * smax) {
     --sc.memb_max;
     sc.mb = sc.memb_max - smax + 1;
     sc.nb_max = sc.mb / 2 + 2;
@@ -525,6 +527,7 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   ba.nstation = 1;
   ba.occ_num = flt->occ_num;
   ba.occ_den = flt->occ_den;
+  ba.min_lag = flt->min_lag;
   ba.flags = fl8;
   ba.small_max = smax;
   ba.small_desc = sdesc;

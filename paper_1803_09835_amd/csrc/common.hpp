@@ -81,6 +81,7 @@ struct BucketArgs {
   const uint64_t* station_base;
   uint32_t nstation;
   uint32_t occ_num, occ_den;
+  uint32_t min_lag;      // buckets whose id span is below this yield no pair
   uint8_t* flags;        // per fingerprint
   uint32_t small_max;    // buckets of size <= small_max go to the small list
   uint2* small_desc;     // {pos, seg<<16 | size}

@@ -40,7 +40,7 @@ __device__ __forceinline__ uint32_t eq_halves(uint32_t a, uint32_t b) {
 
 // Exact shared tables of (i, j) from global rows and mixed keys; reports the
 // pair if table u is its owner.  Returns nothing; writes the output.
-__device__ __noinline__ void exact_and_report(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
+__device__ __forceinline__ void exact_and_report(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
   const uint32_t rsw = a.row_hw / 2;
   const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
   uint32_t votes = 0, owner = 0xFFFFFFFFu;
@@ -76,7 +76,7 @@ __device__ __noinline__ void exact_and_report(const PairArgs& a, uint32_t u, uin
 
 // True when no table below u exactly shares a bucket with (i, j) (G == 1:
 // one group, slot == table).
-__device__ __noinline__ bool first_shared_is(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
+__device__ __forceinline__ bool first_shared_is(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
   const uint32_t rsw = a.row_hw / 2;
   const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
   const uint32_t* ri = R + (uint64_t)i * rsw;
@@ -93,26 +93,62 @@ struct PairTally {
   unsigned long long ev, nd;
 };
 
-// One in-bucket pair of table u: i < j are ids, ra / rb their staged rows
-// (this table's group) in LDS.
-__device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j, const uint32_t* ra,
-                                           const uint32_t* rb, uint32_t rsw, uint32_t pad, PairTally& tl) {
-  if (j - i < a.min_lag) return;
-  ++tl.ev;
-  uint32_t eq = 0;
-  if (a.want_distinct) {
-    // G == 1: also count equal sub-keys below table u.
-    uint32_t below = 0;
-    for (uint32_t w = 0; w < rsw; ++w) {
-      const uint32_t x = ra[w] ^ rb[w];
-      const uint32_t e0 = (x & 0xFFFFu) == 0, e1 = (x >> 16) == 0;
-      eq += e0 + e1;
-      below += (2 * w < u ? e0 : 0u) + (2 * w + 1 < u ? e1 : 0u);
+constexpr uint32_t kDead = 0xFFFFFFFFu;  // member excluded by the occurrence filter
+
+// Row of sub-keys of one member of table u's group.  RSW > 0: the row length
+// is a compile-time constant and the left row of a pair lives in registers;
+// RSW == 0: runtime length, both rows read from LDS.
+template <int RSW>
+struct RowReg {
+  uint32_t w[RSW > 0 ? RSW : 1];
+  const uint32_t* lds;
+  __device__ __forceinline__ void load(const uint32_t* src, uint32_t rsw) {
+    if (RSW > 0) {
+#pragma unroll
+      for (int k = 0; k < (RSW > 0 ? RSW : 1); ++k) w[k] = src[k];
+    } else {
+      lds = src;
     }
-    if (below == 0 || first_shared_is(a, u, i, j)) ++tl.nd;
-  } else {
+    (void)rsw;
+  }
+  // Number of equal 16-bit sub-keys against another row.
+  __device__ __forceinline__ uint32_t eq(const uint32_t* other, uint32_t rsw) const {
+    uint32_t e = 0;
+    if (RSW > 0) {
+#pragma unroll
+      for (int k = 0; k < (RSW > 0 ? RSW : 1); ++k) e += eq_halves(w[k], other[k]);
+    } else {
 #pragma unroll 4
-    for (uint32_t w = 0; w < rsw; ++w) eq += eq_halves(ra[w], rb[w]);
+      for (uint32_t k = 0; k < rsw; ++k) e += eq_halves(lds[k], other[k]);
+    }
+    return e;
+  }
+  // Equal sub-keys in slots below `u` (one group holding every table).
+  __device__ __forceinline__ uint32_t eq_below(const uint32_t* other, uint32_t rsw, uint32_t u) const {
+    uint32_t e = 0;
+    if (RSW > 0) {
+#pragma unroll
+      for (int k = 0; k < (RSW > 0 ? RSW : 1); ++k) e += below2(w[k] ^ other[k], (uint32_t)k, u);
+    } else {
+      for (uint32_t k = 0; k < rsw; ++k) e += below2(lds[k] ^ other[k], k, u);
+    }
+    return e;
+  }
+  __device__ __forceinline__ static uint32_t below2(uint32_t x, uint32_t k, uint32_t u) {
+    return (2 * k < u ? (uint32_t)((x & 0xFFFFu) == 0) : 0u) + (2 * k + 1 < u ? (uint32_t)((x >> 16) == 0) : 0u);
+  }
+};
+
+// One in-bucket pair of table u: i < j, `rx` the row of i, `ry` the row of j.
+template <int RSW>
+__device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
+                                           const RowReg<RSW>& rx, const uint32_t* ry, uint32_t rsw, uint32_t pad,
+                                           PairTally& tl) {
+  if (i == kDead || j == kDead || j - i < a.min_lag) return;
+  ++tl.ev;
+  const uint32_t eq = rx.eq(ry, rsw);
+  if (a.want_distinct) {
+    if (rx.eq_below(ry, rsw, u) == 0 || first_shared_is(a, u, i, j)) ++tl.nd;
   }
   if (eq - pad >= a.need) exact_and_report(a, u, i, j);
 }
@@ -150,23 +186,41 @@ __device__ __forceinline__ T block_scan_excl(T v, T* ws, T* total) {
   return add + inc - v;
 }
 
+// Last index b in [0, cnt) with arr[b] <= key (arr ascending, arr[0] <= key).
+__device__ __forceinline__ uint32_t last_le(const uint32_t* arr, uint32_t cnt, uint32_t key) {
+  uint32_t L = 0, R = cnt;
+  while (R - L > 1) {
+    const uint32_t M = (L + R) / 2;
+    if (arr[M] <= key) L = M; else R = M;
+  }
+  return L;
+}
+
+__device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uint32_t rsw) {
+  const uint32_t g = u / a.tables_per_group;
+  const uint32_t valid = min(a.tables_per_group, a.t - g * a.tables_per_group);
+  return 2 * rsw - valid;
+}
+
 // Buckets of at most small_max members, partitioned by a prefix sum of their
-// sizes so that every workgroup stages about `mb` members.
+// sizes so that every workgroup stages about `mb` members.  Members and rows
+// are staged in LDS in parallel; then every thread walks a contiguous range
+// of the workgroup's pairs (row-major within each bucket), keeping the left
+// row in registers.
+template <int RSW>
 __global__ __launch_bounds__(kPT) void k_pairs_small(PairArgs a, const uint2* desc, const uint64_t* prefix,
                                                      uint32_t ndesc, SmallCfg cfg) {
   extern __shared__ uint32_t smem[];
   uint32_t* lrows = smem;
   uint32_t* lids = lrows + cfg.memb_max * cfg.rswl;
-  uint32_t* bofs = lids + cfg.memb_max;
-  uint32_t* bpof = bofs + cfg.nb_max + 1;
-  uint32_t* bcnt = bpof + cfg.nb_max + 1;
-  uint32_t* bseg = bcnt + cfg.nb_max;
-  uint32_t* bpos = bseg + cfg.nb_max;
-  uint8_t* lg = reinterpret_cast<uint8_t*>(bpos + cfg.nb_max);
+  uint32_t* lpre = lids + cfg.memb_max;
+  uint32_t* bpof = lpre + cfg.nb_max + 1;
+  uint32_t* bpos = bpof + cfg.nb_max + 1;
+  uint32_t* bseg = bpos + cfg.nb_max;
   __shared__ uint32_t ws[8];
   __shared__ uint32_t s_range[2];
   const uint32_t tid = threadIdx.x;
-  const uint32_t rsw = a.row_hw / 2;
+  const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_hw / 2;
 
   if (tid < 2) {
     const uint64_t target = (uint64_t)(blockIdx.x + tid) * cfg.mb;
@@ -179,80 +233,75 @@ __global__ __launch_bounds__(kPT) void k_pairs_small(PairArgs a, const uint2* de
   }
   __syncthreads();
   const uint32_t k_lo = s_range[0], nb = s_range[1] - s_range[0];
-  // A: unflagged member count per bucket
-  for (uint32_t b = tid; b < nb; b += kPT) {
-    const uint2 d = desc[k_lo + b];
-    const uint32_t seg = d.y >> 16, size = d.y & 0xFFFFu;
-    const uint32_t* ord = a.order + (uint64_t)seg * a.n + d.x;
-    uint32_t c = 0;
-    for (uint32_t q = 0; q < size; ++q) c += a.flags[ord[q]] == 0;
-    bcnt[b] = c;
-    bseg[b] = seg;
-    bpos[b] = d.x;
-  }
-  __syncthreads();
   uint32_t mcarry = 0, pcarry = 0;
   for (uint32_t b0 = 0; b0 < nb; b0 += kPT) {
     const uint32_t b = b0 + tid;
-    const uint32_t c = b < nb ? bcnt[b] : 0u;
-    uint32_t tm, tp;
-    const uint32_t xm = block_scan_excl<uint32_t>(c, ws, &tm);
-    const uint32_t xp = block_scan_excl<uint32_t>(c * (c - (c > 0)) / 2, ws, &tp);
+    uint32_t size = 0;
     if (b < nb) {
-      bofs[b] = mcarry + xm;
+      const uint2 d = desc[k_lo + b];
+      size = d.y & 0xFFFFu;
+      bpos[b] = d.x;
+      bseg[b] = d.y >> 16;
+    }
+    uint32_t tm, tp;
+    const uint32_t xm = block_scan_excl<uint32_t>(size, ws, &tm);
+    const uint32_t xp = block_scan_excl<uint32_t>(size * (size - (size > 0)) / 2, ws, &tp);
+    if (b < nb) {
+      lpre[b] = mcarry + xm;
       bpof[b] = pcarry + xp;
     }
     mcarry += tm;
     pcarry += tp;
   }
   if (tid == 0) {
-    bofs[nb] = mcarry;
+    lpre[nb] = mcarry;
     bpof[nb] = pcarry;
   }
   __syncthreads();
-  // B: compacted member ids and their row group
-  for (uint32_t b = tid; b < nb; b += kPT) {
-    const uint32_t seg = bseg[b];
-    const uint32_t size = desc[k_lo + b].y & 0xFFFFu;
-    const uint32_t* ord = a.order + (uint64_t)seg * a.n + bpos[b];
-    uint32_t o = bofs[b];
-    const uint8_t g = (uint8_t)(seg / a.tables_per_group);
-    for (uint32_t q = 0; q < size; ++q) {
-      const uint32_t id = ord[q];
-      if (a.flags[id] == 0) {
-        lids[o] = id;
-        lg[o] = g;
-        ++o;
-      }
-    }
-  }
-  __syncthreads();
-  // C: stage rows
+  // Stage member ids (excluded members marked dead) and their rows.
   const uint32_t M = mcarry;
   const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
-  for (uint32_t idx = tid; idx < M * rsw; idx += kPT) {
-    const uint32_t m = idx / rsw, w = idx - m * rsw;
-    lrows[m * cfg.rswl + w] = R[((uint64_t)lg[m] * a.n + lids[m]) * rsw + w];
+  for (uint32_t m = tid; m < M; m += kPT) {
+    const uint32_t b = last_le(lpre, nb, m);
+    const uint32_t seg = bseg[b];
+    const uint32_t id = a.order[(uint64_t)seg * a.n + bpos[b] + (m - lpre[b])];
+    const bool dead = a.flags[id] != 0;
+    lids[m] = dead ? kDead : id;
+    const uint32_t* src = R + ((uint64_t)(seg / a.tables_per_group) * a.n + id) * rsw;
+    uint32_t* dst = lrows + m * cfg.rswl;
+    for (uint32_t w = 0; w < rsw; ++w) dst[w] = src[w];
   }
   __syncthreads();
-  // D: pairs
+  // Pairs: thread tid walks [p, pend).
   PairTally tl{0ull, 0ull};
   const uint32_t P = pcarry;
-  for (uint32_t p = tid; p < P; p += kPT) {
-    uint32_t L = 0, Rr = nb;  // last bucket with bpof <= p
-    while (Rr - L > 1) {
-      const uint32_t Mm = (L + Rr) / 2;
-      if (bpof[Mm] <= p) L = Mm; else Rr = Mm;
-    }
-    const uint32_t b = L;
+  const uint32_t per = (P + kPT - 1) / kPT;
+  uint32_t p = tid * per;
+  const uint32_t pend = min(P, p + per);
+  if (p < pend) {
+    uint32_t b = last_le(bpof, nb, p);
+    uint32_t base = lpre[b], m = lpre[b + 1] - base, u = bseg[b], pad = group_pad(a, u, rsw);
     uint32_t x, y;
-    tri_decode(bcnt[b], p - bpof[b], x, y);
-    const uint32_t o = bofs[b];
-    const uint32_t u = bseg[b];
-    const uint32_t g = u / a.tables_per_group;
-    const uint32_t valid = min(a.tables_per_group, a.t - g * a.tables_per_group);
-    visit_pair(a, u, lids[o + x], lids[o + y], lrows + (o + x) * cfg.rswl, lrows + (o + y) * cfg.rswl, rsw,
-               2 * rsw - valid, tl);
+    tri_decode(m, p - bpof[b], x, y);
+    uint32_t idx = lids[base + x];
+    RowReg<RSW> rx;
+    rx.load(lrows + (base + x) * cfg.rswl, rsw);
+    for (; p < pend; ++p) {
+      visit_pair<RSW>(a, u, idx, lids[base + y], rx, lrows + (base + y) * cfg.rswl, rsw, pad, tl);
+      if (++y == m) {
+        if (++x == m - 1) {
+          if (++b >= nb) break;
+          base = lpre[b];
+          m = lpre[b + 1] - base;
+          u = bseg[b];
+          pad = group_pad(a, u, rsw);
+          x = 0;
+        }
+        y = x + 1;
+        idx = lids[base + x];
+        rx.load(lrows + (base + x) * cfg.rswl, rsw);
+      }
+    }
   }
   flush_tally(a, tl);
 }
@@ -282,53 +331,66 @@ __global__ __launch_bounds__(kPT) void k_compact_big(PairArgs a, const uint4* bi
   if (threadIdx.x == 0) cnt[blockIdx.x] = s_carry;
 }
 
-// One tile (ta, tb) of the upper triangle of a large bucket's pair matrix.
+// One tile (ta, tb) of the upper triangle of a large bucket's pair matrix;
+// every thread walks a contiguous range of the tile's pairs.
+template <int RSW>
 __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* units, const uint4* big,
                                                     const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
                                                     uint32_t tb_size, uint32_t rswl) {
   extern __shared__ uint32_t smem[];
   const TileUnit un = units[blockIdx.x];
-  const uint32_t rsw = a.row_hw / 2;
+  const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_hw / 2;
   const uint32_t seg = big[un.bucket].y;
   const uint32_t* bid = ids + cofs[un.bucket];
   const uint32_t m = cnt[un.bucket];
   const uint32_t a0 = un.ta * tb_size, b0 = un.tb * tb_size;
   const uint32_t na = min(tb_size, m - a0);
   const bool diag = un.ta == un.tb;
-  const uint32_t nbm = diag ? 0u : min(tb_size, m - b0);
+  const uint32_t nbm = diag ? na : min(tb_size, m - b0);
   uint32_t* rowsA = smem;
-  uint32_t* rowsB = rowsA + tb_size * rswl;
-  uint32_t* idsA = rowsB + tb_size * rswl;
-  uint32_t* idsB = idsA + tb_size;
+  uint32_t* rowsB = diag ? rowsA : rowsA + tb_size * rswl;
+  uint32_t* idsA = smem + 2 * tb_size * rswl;
+  uint32_t* idsB = diag ? idsA : idsA + tb_size;
   const uint32_t g = seg / a.tables_per_group;
   const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
-  for (uint32_t q = threadIdx.x; q < na; q += kPT) idsA[q] = bid[a0 + q];
-  for (uint32_t q = threadIdx.x; q < nbm; q += kPT) idsB[q] = bid[b0 + q];
-  __syncthreads();
-  for (uint32_t idx = threadIdx.x; idx < na * rsw; idx += kPT) {
-    const uint32_t q = idx / rsw, w = idx - q * rsw;
-    rowsA[q * rswl + w] = R[((uint64_t)g * a.n + idsA[q]) * rsw + w];
+  for (uint32_t q = threadIdx.x; q < na; q += kPT) {
+    const uint32_t id = bid[a0 + q];
+    idsA[q] = id;
+    const uint32_t* src = R + ((uint64_t)g * a.n + id) * rsw;
+    for (uint32_t w = 0; w < rsw; ++w) rowsA[q * rswl + w] = src[w];
   }
-  for (uint32_t idx = threadIdx.x; idx < nbm * rsw; idx += kPT) {
-    const uint32_t q = idx / rsw, w = idx - q * rsw;
-    rowsB[q * rswl + w] = R[((uint64_t)g * a.n + idsB[q]) * rsw + w];
-  }
-  __syncthreads();
-  const uint32_t valid = min(a.tables_per_group, a.t - g * a.tables_per_group);
-  const uint32_t pad = 2 * rsw - valid;
-  PairTally tl{0ull, 0ull};
-  if (diag) {
-    const uint32_t P = na * (na - 1) / 2;
-    for (uint32_t p = threadIdx.x; p < P; p += kPT) {
-      uint32_t x, y;
-      tri_decode(na, p, x, y);
-      visit_pair(a, seg, idsA[x], idsA[y], rowsA + x * rswl, rowsA + y * rswl, rsw, pad, tl);
+  if (!diag) {
+    for (uint32_t q = threadIdx.x; q < nbm; q += kPT) {
+      const uint32_t id = bid[b0 + q];
+      idsB[q] = id;
+      const uint32_t* src = R + ((uint64_t)g * a.n + id) * rsw;
+      for (uint32_t w = 0; w < rsw; ++w) rowsB[q * rswl + w] = src[w];
     }
-  } else {
-    const uint32_t P = na * nbm;
-    for (uint32_t p = threadIdx.x; p < P; p += kPT) {
-      const uint32_t x = p / nbm, y = p - x * nbm;
-      visit_pair(a, seg, idsA[x], idsB[y], rowsA + x * rswl, rowsB + y * rswl, rsw, pad, tl);
+  }
+  __syncthreads();
+  const uint32_t pad = group_pad(a, seg, rsw);
+  PairTally tl{0ull, 0ull};
+  const uint32_t P = diag ? na * (na - 1) / 2 : na * nbm;
+  const uint32_t per = (P + kPT - 1) / kPT;
+  uint32_t p = threadIdx.x * per;
+  const uint32_t pend = min(P, p + per);
+  if (p < pend) {
+    uint32_t x, y;
+    if (diag) {
+      tri_decode(na, p, x, y);
+    } else {
+      x = p / nbm;
+      y = p - x * nbm;
+    }
+    RowReg<RSW> rx;
+    rx.load(rowsA + x * rswl, rsw);
+    for (; p < pend; ++p) {
+      visit_pair<RSW>(a, seg, idsA[x], idsB[y], rx, rowsB + y * rswl, rsw, pad, tl);
+      if (++y == nbm) {
+        ++x;
+        y = diag ? x + 1 : 0;
+        if (x < na) rx.load(rowsA + x * rswl, rsw);
+      }
     }
   }
   flush_tally(a, tl);
@@ -379,15 +441,19 @@ static unsigned grid_for(uint64_t count) {
 
 size_t small_smem_bytes(const SmallCfg& c) {
   return (size_t)c.memb_max * c.rswl * 4 + (size_t)c.memb_max * 4 + (size_t)(c.nb_max + 1) * 8 +
-         (size_t)c.nb_max * 12 + c.memb_max + 16;
+         (size_t)c.nb_max * 8 + 16;
 }
 
 void launch_pairs_small(const PairArgs& a, const uint2* desc, const uint64_t* prefix, uint32_t ndesc,
                         uint64_t total_members, const SmallCfg& c, hipStream_t s) {
   if (ndesc == 0) return;
   const uint64_t nwg = (total_members + c.mb - 1) / c.mb;
-  hipLaunchKernelGGL(k_pairs_small, dim3((unsigned)nwg), dim3(kPT), small_smem_bytes(c), s, a, desc, prefix, ndesc,
-                     c);
+  const size_t smem = small_smem_bytes(c);
+  switch (a.row_hw / 2) {
+    case 10: hipLaunchKernelGGL((k_pairs_small<10>), dim3((unsigned)nwg), dim3(kPT), smem, s, a, desc, prefix, ndesc, c); break;
+    case 17: hipLaunchKernelGGL((k_pairs_small<17>), dim3((unsigned)nwg), dim3(kPT), smem, s, a, desc, prefix, ndesc, c); break;
+    default: hipLaunchKernelGGL((k_pairs_small<0>), dim3((unsigned)nwg), dim3(kPT), smem, s, a, desc, prefix, ndesc, c); break;
+  }
 }
 
 void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, const uint64_t* cofs, uint32_t* ids,
@@ -401,7 +467,11 @@ void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits
                        uint32_t rswl, hipStream_t s) {
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
-  hipLaunchKernelGGL(k_pairs_tile, dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl);
+  switch (a.row_hw / 2) {
+    case 10: hipLaunchKernelGGL((k_pairs_tile<10>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
+    case 17: hipLaunchKernelGGL((k_pairs_tile<17>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
+    default: hipLaunchKernelGGL((k_pairs_tile<0>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
+  }
 }
 
 void launch_split_out(const uint64_t* key, const uint32_t* val, uint64_t count, uint32_t* oi, uint32_t* oj,

@@ -282,7 +282,10 @@ struct BucketTotals {
 };
 
 // Account one bucket (run of equal keys) of `size` members; ids(q) gives the
-// q-th member.  Returns the descriptor class: 0 none, 1 small, 2 big.
+// q-th member (ascending).  Returns the descriptor class: 0 none, 1 small,
+// 2 big.  Buckets that cannot hold a reportable pair get no descriptor: a
+// single member, every member excluded by the occurrence filter (the bucket
+// itself is over the threshold), or an id span below the lag.
 template <typename IdAt>
 __device__ __forceinline__ int bucket_account(const BucketArgs& a, uint64_t size, IdAt ids, uint32_t first_id,
                                               BucketTotals& tot) {
@@ -290,10 +293,22 @@ __device__ __forceinline__ int bucket_account(const BucketArgs& a, uint64_t size
   if (size > tot.max_bucket) tot.max_bucket = (unsigned int)size;
   if (a.occ_den) {
     const uint64_t ns = station_size(a, first_id);
-    if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num)
+    if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num) {
       for (uint64_t q = 0; q < size; ++q) a.flags[ids(q)] = 1;
+      return 0;
+    }
   }
-  if (size < 2) return 0;
+  if (size < 2 || ids(size - 1) - first_id < a.min_lag) return 0;
+  return size <= a.small_max ? 1 : 2;
+}
+
+// The descriptor class bucket_account returns, without side effects.
+__device__ __forceinline__ int bucket_class(const BucketArgs& a, uint64_t size, uint32_t first_id, uint32_t last_id) {
+  if (a.occ_den) {
+    const uint64_t ns = station_size(a, first_id);
+    if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num) return 0;
+  }
+  if (size < 2 || last_id - first_id < a.min_lag) return 0;
   return size <= a.small_max ? 1 : 2;
 }
 
@@ -359,11 +374,11 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
       uint32_t f = e + 1;
       while (f < m && sk[f] == sk[e]) ++f;
       const uint32_t size = f - e;
-      if (size < 2) continue;
+      const int cls = bucket_class(a, size, sv[e], sv[f - 1]);
       const uint32_t pos = (uint32_t)(lo + e);
-      if (size <= a.small_max)
+      if (cls == 1)
         a.small_desc[ps++] = make_uint2(pos, (seg << 16) | size);
-      else
+      else if (cls == 2)
         a.big_desc[pb++] = make_uint4(pos, seg, size, 0);
     }
   }
