@@ -404,6 +404,15 @@ struct Plan {
   uint32_t t, G, TG, row_hw, rsw, need;
 };
 
+// Bits of the mixed key the radix passes bin on: a multiple of 8 large enough
+// that an average bin holds at most about 32 elements.
+static uint32_t bin_bits(uint64_t n) {
+  uint32_t need = 0;
+  while ((32ull << need) < n) ++need;
+  uint32_t B = (need + 7) / 8 * 8;
+  return std::min<uint32_t>(32, std::max<uint32_t>(8, B));
+}
+
 static Plan make_plan(uint32_t t, uint32_t v, bool distinct) {
   Plan p;
   p.t = t;
@@ -475,17 +484,28 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   prof_end(c);
   LAUNCHCK();
 
-  // 2. two stable radix passes on the top 16 bits, all tables at once
+  // 2. stable radix passes on the top B bits, all tables at once
   const uint32_t nt = radix_tiles(n);
   uint32_t *hist, *sums;
   RC(ws<uint32_t>(c, "hist", (uint64_t)256 * nt * t, &hist));
   RC(ws<uint32_t>(c, "sums", scan_sums_elems((uint64_t)256 * nt, t), &sums));
+  const uint32_t B = bin_bits(n);
+  uint64_t *gk = ak, *gk2 = bk;
+  uint32_t *gv = av, *gv2 = bv;
   prof_begin(c, FAST_LSH_STAGE_GROUP);
-  radix_pass(mkeys, nullptr, ak, av, n, t, 48, hist, sums, s);
-  LAUNCHCK();
-  radix_pass(ak, av, bk, bv, n, t, 56, hist, sums, s);
+  for (uint32_t pass = 0; pass < B / 8; ++pass) {
+    const uint32_t shift = 64 - B + 8 * pass;
+    radix_pass(pass == 0 ? mkeys : gk2, pass == 0 ? nullptr : gv2, gk, gv, n, t, shift, hist, sums, s);
+    LAUNCHCK();
+    std::swap(gk, gk2);
+    std::swap(gv, gv2);
+  }
   prof_end(c);
-  LAUNCHCK();
+  // the sorted keys and ids are in (gk2, gv2); the other pair is scratch
+  uint64_t* sorted_k = gk2;
+  uint32_t* sorted_v = gv2;
+  uint64_t* scratch_k = gk;
+  uint32_t* scratch_v = gv;
 
   // 3. buckets
   uint8_t* fl8;
@@ -519,10 +539,11 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   RC(ws<uint4>(c, "bdesc", cap_big, &bdesc));
   RC(ws<uint4>(c, "bins", cap_bin, &bins));
   BucketArgs ba;
-  ba.keys = bk;
-  ba.vals = bv;
+  ba.keys = sorted_k;
+  ba.vals = sorted_v;
   ba.n = n;
-  ba.chunk = 3584;
+  ba.chunk = 1536;
+  ba.bin_shift = 64 - B;
   ba.station_base = sbase;
   ba.nstation = 1;
   ba.occ_num = flt->occ_num;
@@ -547,7 +568,7 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   if (hc.err) return fail(FAST_LSH_E_INVALID, "a fingerprint is empty or holds an index >= dim (%u)", h->dim);
   if (hc.bin_count) {
     prof_begin(c, FAST_LSH_STAGE_BIG_BINS);
-    launch_bigbin(ba, bins, hc.bin_count, ak, av, s);
+    launch_bigbin(ba, bins, hc.bin_count, scratch_k, scratch_v, s);
     prof_end(c);
     LAUNCHCK();
   }
@@ -557,7 +578,7 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
 
   // 4. pairs
   PairArgs pa;
-  pa.order = bv;
+  pa.order = sorted_v;
   pa.flags = fl8;
   pa.rows = rows;
   pa.mkeys = mkeys;

@@ -73,10 +73,11 @@ struct SigArgs {
 };
 
 struct BucketArgs {
-  const uint64_t* keys;  // sorted by the top 16 bits, [S][n]
+  const uint64_t* keys;  // sorted by the bin bits, [S][n]
   uint32_t* vals;        // ids, same order; rewritten sorted by (key, id)
   uint64_t n;
   uint32_t chunk;
+  uint32_t bin_shift;    // bin = key >> bin_shift (64 - B)
   // occurrence filter: station of an id found from station_base (nstation+1 entries)
   const uint64_t* station_base;
   uint32_t nstation;

@@ -1,14 +1,15 @@
 // Grouping of band keys into hash-table buckets (section 6.1 "Hash table
 // construction").
 //
-// Every table's (key, id) pairs are grouped by two stable least-significant-
-// digit radix passes over the top 16 bits of fmix64(band key) (the mix
-// spreads the highly skewed packed-argmin keys evenly), which leaves each of
-// the 65,536 bins contiguous with its ids ascending.  A bin then holds a few
-// whole buckets (about N/65,536 elements), small enough to be sorted by the
-// full (key, id) inside LDS, where bucket boundaries, sizes, the raw
-// candidate count and the occurrence filter are derived in the same pass.
-// Bins too large for LDS (huge buckets) take a slower single-workgroup path.
+// Every table's (key, id) pairs are grouped by stable least-significant-
+// digit radix passes over the top B bits of fmix64(band key) (the mix spreads
+// the highly skewed packed-argmin keys evenly; B is 8, 16, 24 or 32 so that
+// an average bin holds a few dozen elements at most), which leaves each bin
+// contiguous with its ids ascending.  A bin then holds a few whole buckets,
+// nearly always a single key; bins that mix keys are ranked by (key, id)
+// inside LDS.  Bucket boundaries, sizes, the raw candidate count and the
+// occurrence filter are derived in the same pass.  Bins too large for LDS
+// (huge buckets) take a slower single-workgroup path.
 //
 // Radix pass = tile histogram -> segmented exclusive scan -> stable scatter.
 // The scatter ranks equal digits inside a wavefront with eight 64-lane
@@ -243,31 +244,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t len, 
 // ---------------------------------------------------------------------------
 // Buckets from the bin-sorted order.
 // ---------------------------------------------------------------------------
-constexpr int kBinCap = 4096;
+constexpr int kBinCap = 2048;
 
 __device__ __forceinline__ bool kv_less(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb) {
   return ka < kb || (ka == kb && va < vb);
-}
-
-// In-LDS bitonic sort of P2 (a power of two) (key, id) pairs.
-__device__ void bitonic_sort(uint64_t* sk, uint32_t* sv, uint32_t P2) {
-  for (uint32_t k = 2; k <= P2; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t t = threadIdx.x; t < P2 / 2; t += blockDim.x) {
-        const uint32_t i = 2 * j * (t / j) + (t % j);
-        const uint32_t l = i + j;
-        const bool up = (i & k) == 0;
-        const uint64_t ki = sk[i], kl = sk[l];
-        const uint32_t vi = sv[i], vl = sv[l];
-        const bool gt = kv_less(kl, vl, ki, vi);
-        if (gt == up) {
-          sk[i] = kl; sv[i] = vl;
-          sk[l] = ki; sv[l] = vi;
-        }
-      }
-      __syncthreads();
-    }
-  }
 }
 
 __device__ __forceinline__ uint64_t station_size(const BucketArgs& a, uint32_t id) {
@@ -326,26 +306,106 @@ __device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
   }
 }
 
-// Sort [lo, hi) of segment seg (hi - lo <= kBinCap, whole bins) in LDS by
-// (key, id), write the ids back in that order, and account every bucket.
+// Order [lo, hi) of segment seg (hi - lo <= kBinCap, whole bins) by
+// (key, id) in LDS, write the ids back in that order, and account every
+// bucket.  Elements arrive grouped by bin with ids ascending inside a bin,
+// so a bin holding a single key is already in order; only bins that mix
+// keys are ranked, by counting the (key, position) pairs below each element.
 __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uint64_t hi, uint64_t* sk,
-                             uint32_t* sv, uint32_t* sh, BucketTotals& tot) {
+                             uint32_t* sv, uint16_t* bs, uint16_t* be, uint16_t* np, uint8_t* mixed, uint32_t* sh,
+                             BucketTotals& tot) {
   const uint64_t* K = a.keys + (uint64_t)seg * a.n;
   uint32_t* V = a.vals + (uint64_t)seg * a.n;
   const uint32_t m = (uint32_t)(hi - lo);
-  uint32_t P2 = 1;
-  while (P2 < m) P2 <<= 1;
-  for (uint32_t e = threadIdx.x; e < P2; e += blockDim.x) {
+  const uint32_t bsh = a.bin_shift;
+  constexpr uint32_t kPer = kBinCap / kThreads;  // elements per thread, consecutive
+  const uint32_t e0 = threadIdx.x * kPer;
+  // Load, and each thread's running bin start over its consecutive elements.
+  uint32_t run = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t e = e0 + q;
     if (e < m) {
-      sk[e] = K[lo + e];
+      const uint64_t k = K[lo + e];
+      sk[e] = k;
       sv[e] = V[lo + e];
-    } else {
-      sk[e] = ~0ull;
-      sv[e] = ~0u;
+      mixed[e] = 0;
     }
   }
   __syncthreads();
-  bitonic_sort(sk, sv, P2);
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t e = e0 + q;
+    if (e < m && (e == 0 || (sk[e] >> bsh) != (sk[e - 1] >> bsh))) run = e;
+  }
+  // Exclusive max-scan of the per-thread last head gives the open bin start.
+  uint32_t carry = run;
+  {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = carry;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, 64);
+      if (lane >= (uint32_t)o) inc = max(inc, y);
+    }
+    if (lane == 63) sh[8 + wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w) before = max(before, sh[8 + w]);
+    const uint32_t prev = __shfl_up(inc, 1, 64);
+    carry = max(before, lane ? prev : 0u);
+    __syncthreads();
+  }
+  uint32_t cur = carry;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t e = e0 + q;
+    if (e < m) {
+      if (e == 0 || (sk[e] >> bsh) != (sk[e - 1] >> bsh)) cur = e;
+      bs[e] = (uint16_t)cur;
+      if (e + 1 == m || (sk[e + 1] >> bsh) != (sk[e] >> bsh)) be[cur] = (uint16_t)(e + 1);
+      if (sk[e] != sk[cur]) mixed[cur] = 1;
+    }
+  }
+  __syncthreads();
+  // Rank inside mixed bins.
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t e = e0 + q;
+    if (e < m) {
+      const uint32_t b0 = bs[e];
+      uint32_t pos = e;
+      if (mixed[b0]) {
+        const uint32_t b1 = be[b0];
+        const uint64_t k = sk[e];
+        pos = b0;
+        for (uint32_t f = b0; f < b1; ++f) {
+          const uint64_t kf = sk[f];
+          pos += (kf < k) || (kf == k && f < e);
+        }
+      }
+      np[e] = (uint16_t)pos;
+    }
+  }
+  __syncthreads();
+  uint64_t rk[kPer];
+  uint32_t rv[kPer];
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t e = e0 + q;
+    rk[q] = e < m ? sk[e] : 0ull;
+    rv[q] = e < m ? sv[e] : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t e = e0 + q;
+    if (e < m) {
+      sk[np[e]] = rk[q];
+      sv[np[e]] = rv[q];
+    }
+  }
+  __syncthreads();
   for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) V[lo + e] = sv[e];
   // Buckets: pass 1 counts descriptors per thread, pass 2 writes them.
   uint32_t nsmall = 0, nbig = 0;
@@ -388,10 +448,13 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
 __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
   __shared__ uint64_t sk[kBinCap];
   __shared__ uint32_t sv[kBinCap];
+  __shared__ uint16_t bs[kBinCap], be[kBinCap], np[kBinCap];
+  __shared__ uint8_t mixed[kBinCap];
   __shared__ uint32_t sh[16];
   __shared__ unsigned long long s_hi;
   __shared__ int s_first, s_last;
   const uint32_t seg = blockIdx.y;
+  const uint32_t bsh = a.bin_shift;
   const uint64_t n = a.n;
   const uint64_t c0 = (uint64_t)blockIdx.x * a.chunk;
   const uint64_t c1 = c0 + a.chunk < n ? c0 + a.chunk : n;
@@ -403,7 +466,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
   }
   __syncthreads();
   for (uint64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
-    if (p == 0 || (K[p] >> 48) != (K[p - 1] >> 48)) {
+    if (p == 0 || (K[p] >> bsh) != (K[p - 1] >> bsh)) {
       atomicMin(&s_first, (int)(p - c0));
       atomicMax(&s_last, (int)(p - c0));
     }
@@ -415,15 +478,15 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
   if (c1 == n) {
     if (threadIdx.x == 0) s_hi = n;
   } else {
-    const uint64_t binlast = K[c1 - 1] >> 48;
+    const uint64_t binlast = K[c1 - 1] >> bsh;
     const uint64_t p = c1 + threadIdx.x;
-    if (p < n && (K[p] >> 48) != binlast) atomicMin(&s_hi, (unsigned long long)p);
+    if (p < n && (K[p] >> bsh) != binlast) atomicMin(&s_hi, (unsigned long long)p);
     __syncthreads();
     if (threadIdx.x == 0 && s_hi == ~0ull) {
       uint64_t L = c1 + blockDim.x < n ? c1 + blockDim.x : n, R = n;  // first p in [L, R) with bin(p) > binlast
       while (L < R) {
         const uint64_t M = (L + R) / 2;
-        if ((K[M] >> 48) > binlast) R = M; else L = M + 1;
+        if ((K[M] >> bsh) > binlast) R = M; else L = M + 1;
       }
       s_hi = L;
     }
@@ -432,11 +495,11 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
   const uint64_t hi = s_hi;
   BucketTotals tot{0ull, 0u};
   if (hi - lo <= (uint64_t)kBinCap) {
-    process_bins(a, seg, lo, hi, sk, sv, sh, tot);
+    process_bins(a, seg, lo, hi, sk, sv, bs, be, np, mixed, sh, tot);
   } else {
-    if (last > lo) process_bins(a, seg, lo, last, sk, sv, sh, tot);
+    if (last > lo) process_bins(a, seg, lo, last, sk, sv, bs, be, np, mixed, sh, tot);
     if (hi - last <= (uint64_t)kBinCap) {
-      process_bins(a, seg, last, hi, sk, sv, sh, tot);
+      process_bins(a, seg, last, hi, sk, sv, bs, be, np, mixed, sh, tot);
     } else if (threadIdx.x == 0) {
       const uint32_t q = atomicAdd(a.bin_count, 1u);
       a.bin_desc[q] = make_uint4((uint32_t)last, (uint32_t)hi, seg, 0);
@@ -446,7 +509,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Oversized bins: one workgroup sorts [lo, hi) by the low 48 key bits with
+// Oversized bins: one workgroup sorts [lo, hi) by the key bits below the bin with
 // stable 8-bit LSD passes through the scratch arrays (ids stay ascending
 // within equal keys) and then accounts the buckets.
 // ---------------------------------------------------------------------------
@@ -483,7 +546,7 @@ __global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* 
   if (kmin != kmax) {
     uint64_t *sK = K, *dK = TK;
     uint32_t *sV = V, *dV = TV;
-    for (uint32_t shift = 0; shift < 48; shift += 8) {
+    for (uint32_t shift = 0; shift < a.bin_shift; shift += 8) {
       for (uint32_t d = tid; d < kRadix; d += kThreads) cnt[d] = 0;
       __syncthreads();
       for (uint64_t p = lo + tid; p < hi; p += kThreads) atomicAdd(&cnt[(sK[p] >> shift) & 0xFF], 1u);
@@ -525,7 +588,13 @@ __global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* 
       uint64_t* t1 = sK; sK = dK; dK = t1;
       uint32_t* t2 = sV; sV = dV; dV = t2;
     }
-    // six passes: the data is back in K / V
+    if (sK != K) {  // odd number of passes: the sorted data is in the scratch arrays
+      for (uint64_t p = lo + tid; p < hi; p += kThreads) {
+        K[p] = sK[p];
+        V[p] = sV[p];
+      }
+      __syncthreads();
+    }
   }
   // Account buckets, scanning the range in chunks of kThreads with the
   // currently open run carried across chunks.
