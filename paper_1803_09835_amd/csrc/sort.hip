@@ -44,52 +44,66 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d) {
 // Radix pass kernels.  Segment s occupies [s*n, (s+1)*n) of every array.
 // vin == nullptr means the value of element e is e (its id).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t* keys, uint64_t n, uint32_t shift,
-                                                   uint32_t* hist, uint32_t ntiles) {
-  __shared__ uint32_t cnt[4][kRadix];
+constexpr int kRThreads = 512;                 // radix-pass workgroup
+constexpr int kRItems = kTile / kRThreads;      // 8 elements per thread
+constexpr int kRWaves = kRThreads / 64;
+
+__global__ __launch_bounds__(kRThreads) void k_hist(const uint64_t* keys, uint64_t n, uint32_t shift,
+                                                    uint32_t* hist, uint32_t ntiles) {
+  __shared__ uint32_t cnt[kRWaves][kRadix];
   const uint32_t tid = threadIdx.x, wave = tid >> 6;
-  for (uint32_t q = tid; q < 4 * kRadix; q += kThreads) (&cnt[0][0])[q] = 0;
+  for (uint32_t q = tid; q < kRWaves * kRadix; q += kRThreads) (&cnt[0][0])[q] = 0;
   __syncthreads();
   const uint64_t seg = blockIdx.y, tile = blockIdx.x;
   const uint64_t* K = keys + seg * n;
   const uint64_t e0 = tile * kTile;
-#pragma unroll 4
-  for (int k = 0; k < kItems; ++k) {
-    const uint64_t e = e0 + (uint64_t)k * kThreads + tid;
+#pragma unroll
+  for (int k = 0; k < kRItems; ++k) {
+    const uint64_t e = e0 + (uint64_t)k * kRThreads + tid;
     if (e < n) atomicAdd(&cnt[wave][(K[e] >> shift) & 0xFF], 1u);
   }
   __syncthreads();
-  const uint32_t d = tid;
-  hist[(seg * kRadix + d) * ntiles + tile] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+  if (tid < kRadix) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kRWaves; ++w) t += cnt[w][tid];
+    hist[(seg * kRadix + tid) * ntiles + tile] = t;
+  }
 }
 
-__global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
-                                                      uint32_t* vout, uint64_t n, uint32_t shift,
-                                                      const uint32_t* hist, uint32_t ntiles) {
-  __shared__ uint32_t wcnt[4][kRadix];
+__global__ __launch_bounds__(kRThreads) void k_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                       uint32_t* vout, uint64_t n, uint32_t shift,
+                                                       const uint32_t* hist, uint32_t ntiles) {
+  __shared__ uint32_t wcnt[kRWaves][kRadix];
   __shared__ uint32_t tstart[kRadix];
   __shared__ uint32_t gbase[kRadix];
   __shared__ uint32_t wsum[4];
   __shared__ uint64_t sk[kTile];
   __shared__ uint32_t sv[kTile];
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (uint32_t q = tid; q < 4 * kRadix; q += kThreads) (&wcnt[0][0])[q] = 0;
+  for (uint32_t q = tid; q < kRWaves * kRadix; q += kRThreads) (&wcnt[0][0])[q] = 0;
   __syncthreads();
   const uint64_t seg = blockIdx.y, tile = blockIdx.x;
   const uint64_t* K = kin + seg * n;
   const uint32_t* V = vin ? vin + seg * n : nullptr;
-  const uint64_t e0 = tile * kTile + (uint64_t)wave * (kTile / 4);
+  // wave w owns the contiguous slice [w*512, (w+1)*512) of the tile, in
+  // kRItems steps of 64 elements: stable order is (wave, step, lane).
+  const uint64_t e0 = tile * kTile + (uint64_t)wave * (kTile / kRWaves);
   const uint64_t lt = lanemask_lt();
 
-  uint64_t key[kItems];
-  uint32_t val[kItems], rank[kItems];
+  uint64_t key[kRItems];
+  uint32_t val[kRItems], rank[kRItems];
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
+  for (int k = 0; k < kRItems; ++k) {
     const uint64_t e = e0 + (uint64_t)k * 64 + lane;
     const bool ok = e < n;
     key[k] = ok ? K[e] : ~0ull;
     val[k] = ok ? (V ? V[e] : (uint32_t)e) : 0u;
-    const uint32_t d = ok ? (uint32_t)(key[k] >> shift) & 0xFF : 0xFFu;
+  }
+#pragma unroll
+  for (int k = 0; k < kRItems; ++k) {
+    const uint64_t e = e0 + (uint64_t)k * 64 + lane;
+    const uint32_t d = e < n ? (uint32_t)(key[k] >> shift) & 0xFF : 0xFFu;
     const uint64_t peers = match_digit(d);
     const uint32_t before = __popcll(peers & lt);
     const uint32_t base = wcnt[wave][d];
@@ -97,30 +111,29 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t* kin, const
     if ((peers >> lane) == 1ull) wcnt[wave][d] = base + __popcll(peers);  // highest lane of the group
   }
   __syncthreads();
-  // Per digit: prefix over waves, tile total, then the tile-level digit start.
-  uint32_t tot;
-  {
-    const uint32_t d = tid;
+  // Per digit: prefix over waves and the tile total; then the tile-level
+  // digit start (exclusive scan over digits by the first four waves).
+  uint32_t tot = 0;
+  if (tid < kRadix) {
     uint32_t s = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const uint32_t c = wcnt[w][d];
-      wcnt[w][d] = s;
+    for (int w = 0; w < kRWaves; ++w) {
+      const uint32_t c = wcnt[w][tid];
+      wcnt[w][tid] = s;
       s += c;
     }
     tot = s;
-    gbase[d] = hist[(seg * kRadix + d) * ntiles + tile];
+    gbase[tid] = hist[(seg * kRadix + tid) * ntiles + tile];
   }
-  // exclusive scan of tot over the 256 digits
   uint32_t inc = tot;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t y = __shfl_up(inc, o, 64);
     if (lane >= (uint32_t)o) inc += y;
   }
-  if (lane == 63) wsum[wave] = inc;
+  if (tid < kRadix && lane == 63) wsum[wave] = inc;
   __syncthreads();
-  {
+  if (tid < kRadix) {
     uint32_t add = 0;
     for (uint32_t w = 0; w < wave; ++w) add += wsum[w];
     tstart[tid] = add + inc - tot;
@@ -129,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t* kin, const
   const uint64_t tile0 = tile * kTile;
   const uint32_t nvalid = (uint32_t)((n - tile0) < (uint64_t)kTile ? (n - tile0) : (uint64_t)kTile);
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
+  for (int k = 0; k < kRItems; ++k) {
     const uint64_t e = e0 + (uint64_t)k * 64 + lane;
     if (e < n) {
       const uint32_t d = (uint32_t)(key[k] >> shift) & 0xFF;
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t* kin, const
   __syncthreads();
   uint64_t* KO = kout + seg * n;
   uint32_t* VO = vout + seg * n;
-  for (uint32_t q = tid; q < nvalid; q += kThreads) {
+  for (uint32_t q = tid; q < nvalid; q += kRThreads) {
     const uint64_t k = sk[q];
     const uint32_t d = (uint32_t)(k >> shift) & 0xFF;
     const uint64_t g = (uint64_t)gbase[d] + (q - tstart[d]);
@@ -465,10 +478,21 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
     s_hi = ~0ull;
   }
   __syncthreads();
-  for (uint64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
-    if (p == 0 || (K[p] >> bsh) != (K[p - 1] >> bsh)) {
-      atomicMin(&s_first, (int)(p - c0));
-      atomicMax(&s_last, (int)(p - c0));
+  {
+    int first = 0x7FFFFFFF, lastp = -1;
+    for (uint64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
+      if (p == 0 || (K[p] >> bsh) != (K[p - 1] >> bsh)) {
+        first = min(first, (int)(p - c0));
+        lastp = max(lastp, (int)(p - c0));
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      first = min(first, __shfl_xor(first, o, 64));
+      lastp = max(lastp, __shfl_xor(lastp, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      if (first != 0x7FFFFFFF) atomicMin(&s_first, first);
+      if (lastp >= 0) atomicMax(&s_last, lastp);
     }
   }
   __syncthreads();
@@ -480,7 +504,12 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
   } else {
     const uint64_t binlast = K[c1 - 1] >> bsh;
     const uint64_t p = c1 + threadIdx.x;
-    if (p < n && (K[p] >> bsh) != binlast) atomicMin(&s_hi, (unsigned long long)p);
+    unsigned long long cand = (p < n && (K[p] >> bsh) != binlast) ? (unsigned long long)p : ~0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long oc = __shfl_xor(cand, o, 64);
+      cand = oc < cand ? oc : cand;
+    }
+    if ((threadIdx.x & 63) == 0 && cand != ~0ull) atomicMin(&s_hi, cand);
     __syncthreads();
     if (threadIdx.x == 0 && s_hi == ~0ull) {
       uint64_t L = c1 + blockDim.x < n ? c1 + blockDim.x : n, R = n;  // first p in [L, R) with bin(p) > binlast
@@ -659,9 +688,9 @@ void radix_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32
                 uint32_t shift, uint32_t* hist, uint32_t* sums, hipStream_t s) {
   if (n == 0) return;
   const uint32_t nt = radix_tiles(n);
-  hipLaunchKernelGGL(k_hist, dim3(nt, S), dim3(kThreads), 0, s, kin, n, shift, hist, nt);
+  hipLaunchKernelGGL(k_hist, dim3(nt, S), dim3(kRThreads), 0, s, kin, n, shift, hist, nt);
   seg_scan<uint32_t>(hist, (uint64_t)kRadix * nt, S, sums, nullptr, s);
-  hipLaunchKernelGGL(k_scatter, dim3(nt, S), dim3(kThreads), 0, s, kin, vin, kout, vout, n, shift, hist, nt);
+  hipLaunchKernelGGL(k_scatter, dim3(nt, S), dim3(kRThreads), 0, s, kin, vin, kout, vout, n, shift, hist, nt);
 }
 
 void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s) {
