@@ -532,7 +532,7 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
     sc.nb_max = sc.mb / 2 + 2;
   }
 
-  const uint64_t cap_small = tn / 2 + 1, cap_big = tn / (smax + 1) + 1, cap_bin = tn / 4096 + t + 1;
+  const uint64_t cap_small = tn / 2 + 1, cap_big = tn / (smax + 1) + 1, cap_bin = tn / 129 + t + 1;  // oversized bins and mixed bins above 128 elements
   uint2* sdesc;
   uint4 *bdesc, *bins;
   RC(ws<uint2>(c, "sdesc", cap_small, &sdesc));

@@ -78,8 +78,8 @@ __global__ __launch_bounds__(kRThreads) void k_scatter(const uint64_t* kin, cons
   __shared__ uint32_t tstart[kRadix];
   __shared__ uint32_t gbase[kRadix];
   __shared__ uint32_t wsum[4];
-  __shared__ uint64_t sk[kTile];
-  __shared__ uint32_t sv[kTile];
+  __shared__ uint64_t sk[kTile];  // staging: keys, then values
+  uint32_t* sv = reinterpret_cast<uint32_t*>(sk);
   const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (uint32_t q = tid; q < kRWaves * kRadix; q += kRThreads) (&wcnt[0][0])[q] = 0;
   __syncthreads();
@@ -141,25 +141,41 @@ __global__ __launch_bounds__(kRThreads) void k_scatter(const uint64_t* kin, cons
   __syncthreads();
   const uint64_t tile0 = tile * kTile;
   const uint32_t nvalid = (uint32_t)((n - tile0) < (uint64_t)kTile ? (n - tile0) : (uint64_t)kTile);
+  uint32_t pos[kRItems];
 #pragma unroll
   for (int k = 0; k < kRItems; ++k) {
     const uint64_t e = e0 + (uint64_t)k * 64 + lane;
     if (e < n) {
       const uint32_t d = (uint32_t)(key[k] >> shift) & 0xFF;
-      const uint32_t pos = tstart[d] + wcnt[wave][d] + rank[k];
-      sk[pos] = key[k];
-      sv[pos] = val[k];
+      pos[k] = tstart[d] + wcnt[wave][d] + rank[k];
+      sk[pos[k]] = key[k];
     }
   }
   __syncthreads();
   uint64_t* KO = kout + seg * n;
   uint32_t* VO = vout + seg * n;
-  for (uint32_t q = tid; q < nvalid; q += kRThreads) {
-    const uint64_t k = sk[q];
-    const uint32_t d = (uint32_t)(k >> shift) & 0xFF;
-    const uint64_t g = (uint64_t)gbase[d] + (q - tstart[d]);
-    KO[g] = k;
-    VO[g] = sv[q];
+  uint32_t gq[kRItems];  // global position of staged element tid + k*kRThreads
+#pragma unroll
+  for (int k = 0; k < kRItems; ++k) {
+    const uint32_t q = tid + k * kRThreads;
+    if (q < nvalid) {
+      const uint64_t kk = sk[q];
+      const uint32_t d = (uint32_t)(kk >> shift) & 0xFF;
+      gq[k] = gbase[d] + (q - tstart[d]);
+      KO[gq[k]] = kk;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRItems; ++k) {
+    const uint64_t e = e0 + (uint64_t)k * 64 + lane;
+    if (e < n) sv[pos[k]] = val[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRItems; ++k) {
+    const uint32_t q = tid + k * kRThreads;
+    if (q < nvalid) VO[gq[k]] = sv[q];
   }
 }
 
@@ -258,6 +274,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t len, 
 // Buckets from the bin-sorted order.
 // ---------------------------------------------------------------------------
 constexpr int kBinCap = 2048;
+constexpr uint32_t kRankMax = 128;  // largest mixed bin ranked in LDS
 
 __device__ __forceinline__ bool kv_less(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb) {
   return ka < kb || (ka == kb && va < vb);
@@ -381,6 +398,18 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
     }
   }
   __syncthreads();
+  // Mixed bins above kRankMax elements are left in id order and handed to
+  // the single-workgroup path (k_bigbin): ranking them here costs O(m^2).
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t e = e0 + q;
+    if (e < m && bs[e] == e && mixed[e] && be[e] - e > kRankMax) {
+      mixed[e] = 2;
+      const uint32_t slot = atomicAdd(a.bin_count, 1u);
+      a.bin_desc[slot] = make_uint4((uint32_t)(lo + e), (uint32_t)(lo + be[e]), seg, 0);
+    }
+  }
+  __syncthreads();
   // Rank inside mixed bins.
 #pragma unroll
   for (uint32_t q = 0; q < kPer; ++q) {
@@ -388,7 +417,7 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
     if (e < m) {
       const uint32_t b0 = bs[e];
       uint32_t pos = e;
-      if (mixed[b0]) {
+      if (mixed[b0] == 1) {
         const uint32_t b1 = be[b0];
         const uint64_t k = sk[e];
         pos = b0;
@@ -419,10 +448,13 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
     }
   }
   __syncthreads();
-  for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) V[lo + e] = sv[e];
+  for (uint32_t e = threadIdx.x; e < m; e += blockDim.x)
+    if (mixed[bs[e]] != 2) V[lo + e] = sv[e];
   // Buckets: pass 1 counts descriptors per thread, pass 2 writes them.
+  // (Positions inside a bin stay inside it, so bs[] still names the bin.)
   uint32_t nsmall = 0, nbig = 0;
   for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
+    if (mixed[bs[e]] == 2) continue;
     if (e > 0 && sk[e] == sk[e - 1]) continue;
     uint32_t f = e + 1;
     while (f < m && sk[f] == sk[e]) ++f;
@@ -443,6 +475,7 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
   uint32_t ps = base[0] + xs, pb = base[1] + xb;
   if (nsmall | nbig) {
     for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
+      if (mixed[bs[e]] == 2) continue;
       if (e > 0 && sk[e] == sk[e - 1]) continue;
       uint32_t f = e + 1;
       while (f < m && sk[f] == sk[e]) ++f;
