@@ -46,10 +46,14 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d) {
 // ---------------------------------------------------------------------------
 constexpr int kRThreads = 512;                 // radix-pass workgroup
 constexpr int kRItems = kTile / kRThreads;      // 8 elements per thread
-constexpr int kRWaves = kRThreads / 64;
 
-__global__ __launch_bounds__(kRThreads) void k_hist(const uint64_t* keys, uint64_t n, uint32_t shift,
-                                                    uint32_t* hist, uint32_t ntiles) {
+template <int THREADS = kRThreads, int ITEMS = kRItems>
+__global__ __launch_bounds__(THREADS) void k_hist(const uint64_t* keys, uint64_t n, uint32_t shift,
+                                                  uint32_t* hist, uint32_t ntiles) {
+  constexpr int kRWaves = THREADS / 64;
+  constexpr int kRThreads = THREADS;
+  constexpr int kRItems = ITEMS;
+  constexpr int kTile = THREADS * ITEMS;
   __shared__ uint32_t cnt[kRWaves][kRadix];
   const uint32_t tid = threadIdx.x, wave = tid >> 6;
   for (uint32_t q = tid; q < kRWaves * kRadix; q += kRThreads) (&cnt[0][0])[q] = 0;
@@ -71,9 +75,14 @@ __global__ __launch_bounds__(kRThreads) void k_hist(const uint64_t* keys, uint64
   }
 }
 
-__global__ __launch_bounds__(kRThreads) void k_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
-                                                       uint32_t* vout, uint64_t n, uint32_t shift,
-                                                       const uint32_t* hist, uint32_t ntiles) {
+template <int THREADS = kRThreads, int ITEMS = kRItems>
+__global__ __launch_bounds__(THREADS) void k_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                     uint32_t* vout, uint64_t n, uint32_t shift,
+                                                     const uint32_t* hist, uint32_t ntiles) {
+  constexpr int kRWaves = THREADS / 64;
+  constexpr int kRThreads = THREADS;
+  constexpr int kRItems = ITEMS;
+  constexpr int kTile = THREADS * ITEMS;
   __shared__ uint32_t wcnt[kRWaves][kRadix];
   __shared__ uint32_t tstart[kRadix];
   __shared__ uint32_t gbase[kRadix];
@@ -336,6 +345,18 @@ __device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
   }
 }
 
+// End of the run of equal keys starting at e inside bin b0: the bin's end
+// for a single-key bin, else a short scan (mixed bins here hold at most
+// kRankMax elements).
+__device__ __forceinline__ uint32_t run_end(const uint64_t* sk, uint32_t e, uint32_t b0, const uint16_t* be,
+                                            const uint8_t* mixed) {
+  const uint32_t b1 = be[b0];
+  if (!mixed[b0]) return b1;
+  uint32_t f = e + 1;
+  while (f < b1 && sk[f] == sk[e]) ++f;
+  return f;
+}
+
 // Order [lo, hi) of segment seg (hi - lo <= kBinCap, whole bins) by
 // (key, id) in LDS, write the ids back in that order, and account every
 // bucket.  Elements arrive grouped by bin with ids ascending inside a bin,
@@ -454,10 +475,10 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
   // (Positions inside a bin stay inside it, so bs[] still names the bin.)
   uint32_t nsmall = 0, nbig = 0;
   for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
-    if (mixed[bs[e]] == 2) continue;
+    const uint32_t b0 = bs[e];
+    if (mixed[b0] == 2) continue;
     if (e > 0 && sk[e] == sk[e - 1]) continue;
-    uint32_t f = e + 1;
-    while (f < m && sk[f] == sk[e]) ++f;
+    const uint32_t f = run_end(sk, e, b0, be, mixed);
     const int cls = bucket_account(a, f - e, [&](uint64_t q) { return sv[e + q]; }, sv[e], tot);
     nsmall += cls == 1;
     nbig += cls == 2;
@@ -475,10 +496,10 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
   uint32_t ps = base[0] + xs, pb = base[1] + xb;
   if (nsmall | nbig) {
     for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
-      if (mixed[bs[e]] == 2) continue;
+      const uint32_t b0 = bs[e];
+      if (mixed[b0] == 2) continue;
       if (e > 0 && sk[e] == sk[e - 1]) continue;
-      uint32_t f = e + 1;
-      while (f < m && sk[f] == sk[e]) ++f;
+      const uint32_t f = run_end(sk, e, b0, be, mixed);
       const uint32_t size = f - e;
       const int cls = bucket_class(a, size, sv[e], sv[f - 1]);
       const uint32_t pos = (uint32_t)(lo + e);
@@ -721,9 +742,9 @@ void radix_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32
                 uint32_t shift, uint32_t* hist, uint32_t* sums, hipStream_t s) {
   if (n == 0) return;
   const uint32_t nt = radix_tiles(n);
-  hipLaunchKernelGGL(k_hist, dim3(nt, S), dim3(kRThreads), 0, s, kin, n, shift, hist, nt);
+  hipLaunchKernelGGL((k_hist<>), dim3(nt, S), dim3(kRThreads), 0, s, kin, n, shift, hist, nt);
   seg_scan<uint32_t>(hist, (uint64_t)kRadix * nt, S, sums, nullptr, s);
-  hipLaunchKernelGGL(k_scatter, dim3(nt, S), dim3(kRThreads), 0, s, kin, vin, kout, vout, n, shift, hist, nt);
+  hipLaunchKernelGGL((k_scatter<>), dim3(nt, S), dim3(kRThreads), 0, s, kin, vin, kout, vout, n, shift, hist, nt);
 }
 
 void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s) {
