@@ -26,9 +26,8 @@ void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s);
 void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t nbins, uint64_t* tk, uint32_t* tv,
                    hipStream_t s);
 // pairs.hip
-size_t small_smem_bytes(const SmallCfg& c);
-void launch_pairs_small(const PairArgs& a, const uint2* desc, const uint64_t* prefix, uint32_t ndesc,
-                        uint64_t total_members, const SmallCfg& c, hipStream_t s);
+size_t chunk_smem_bytes(const ChunkCfg& c);
+void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, const ChunkCfg& c, hipStream_t s);
 void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, const uint64_t* cofs, uint32_t* ids,
                         uint32_t* cnt, hipStream_t s);
 void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits, const uint4* big,
@@ -38,7 +37,6 @@ void launch_split_out(const uint64_t* key, const uint32_t* val, uint64_t count, 
                       uint8_t* ov, hipStream_t s);
 void launch_pack_out(const uint32_t* oi, const uint32_t* oj, const uint8_t* ov, uint64_t count, uint64_t* key,
                      uint32_t* val, hipStream_t s);
-void launch_desc_sizes(const uint2* desc, uint32_t count, uint64_t* sizes, hipStream_t s);
 void launch_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out, hipStream_t s);
 void fill_u8(uint8_t* p, uint64_t count, uint8_t v, hipStream_t s);
 void fill_u32(uint32_t* p, uint64_t count, uint32_t v, hipStream_t s);
@@ -425,20 +423,27 @@ static Plan make_plan(uint32_t t, uint32_t v, bool distinct) {
   return p;
 }
 
-// Counters kept on the device during one search.
+// Counters kept on the device during one search.  Sums taken by many
+// workgroups live in kSpread slots each (see spread_slot) and are added up
+// on the host.
 struct DevCounters {
-  unsigned long long e_raw;
-  unsigned long long e_voted;
-  unsigned long long n_distinct;
+  unsigned long long e_raw[kSpread];
+  unsigned long long e_voted[kSpread];
+  unsigned long long n_distinct[kSpread];
+  unsigned int max_bucket[kSpread];
   unsigned long long n_flagged;
-  unsigned int max_bucket;
-  unsigned int small_count;
   unsigned int big_count;
   unsigned int bin_count;
   unsigned int out_count;
   int err;
-  unsigned long long pad;
 };
+
+template <typename T>
+static T spread_sum(const T* v) {
+  T s = 0;
+  for (uint32_t k = 0; k < kSpread; ++k) s += v[k];
+  return s;
+}
 
 static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps* f, const fast_lsh_filter* flt,
                        uint32_t flags, fast_lsh_stats* out_stats) {
@@ -516,28 +521,23 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   c->hstage.assign({0ull, n});
   RC(h2d(c, sbase, c->hstage.data(), 2));
 
-  // Pair-stage shapes: about 32 KB of LDS per workgroup so that several
-  // workgroups share a CU.
-  SmallCfg sc;
-  sc.rswl = pl.rsw | 1u;
-  const uint32_t lds_budget = 32768;
-  const uint32_t per_member = sc.rswl * 4 + 4 + 8;
-  sc.memb_max = std::max<uint32_t>(16, lds_budget / per_member);
-  const uint32_t smax = std::min<uint32_t>(64, sc.memb_max / 2);
-  sc.mb = sc.memb_max - smax + 1;
-  sc.nb_max = sc.mb / 2 + 2;
-  while (small_smem_bytes(sc) > lds_budget && sc.memb_max > 2 * smax) {
-    --sc.memb_max;
-    sc.mb = sc.memb_max - smax + 1;
-    sc.nb_max = sc.mb / 2 + 2;
+  // Pair stage: buckets of at most smax members are marked in place and
+  // handled by chunks of positions; larger ones go to the tiled kernel.
+  const uint32_t smax = 64;
+  ChunkCfg cc;
+  cc.rswl = pl.rsw | 1u;
+  cc.chunk = 512;
+  for (;;) {
+    cc.memb_max = cc.chunk + smax - 1;
+    if (chunk_smem_bytes(cc) <= 40960 || cc.chunk <= 32) break;
+    cc.chunk >>= 1;
   }
-
-  const uint64_t cap_small = tn / 2 + 1, cap_big = tn / (smax + 1) + 1, cap_bin = tn / 129 + t + 1;  // oversized bins and mixed bins above 128 elements
-  uint2* sdesc;
+  const uint64_t cap_big = tn / (smax + 1) + 1, cap_bin = tn / 129 + t + 1;  // oversized bins and mixed bins above 128 elements
   uint4 *bdesc, *bins;
-  RC(ws<uint2>(c, "sdesc", cap_small, &sdesc));
+  uint8_t* marks;
   RC(ws<uint4>(c, "bdesc", cap_big, &bdesc));
   RC(ws<uint4>(c, "bins", cap_bin, &bins));
+  RC(ws<uint8_t>(c, "marks", tn, &marks));
   BucketArgs ba;
   ba.keys = sorted_k;
   ba.vals = sorted_v;
@@ -551,14 +551,13 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   ba.min_lag = flt->min_lag;
   ba.flags = fl8;
   ba.small_max = smax;
-  ba.small_desc = sdesc;
-  ba.small_count = &dc->small_count;
+  ba.marks = marks;
   ba.big_desc = bdesc;
   ba.big_count = &dc->big_count;
   ba.bin_desc = bins;
   ba.bin_count = &dc->bin_count;
-  ba.e_raw = &dc->e_raw;
-  ba.max_bucket = &dc->max_bucket;
+  ba.e_raw = dc->e_raw;
+  ba.max_bucket = dc->max_bucket;
   prof_begin(c, FAST_LSH_STAGE_BUCKETS);
   launch_bucket(ba, t, s);
   prof_end(c);
@@ -592,14 +591,10 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   pa.need = pl.need;
   pa.want_distinct = distinct;
   pa.out_count = &dc->out_count;
-  pa.e_voted = &dc->e_voted;
-  pa.n_distinct = &dc->n_distinct;
+  pa.e_voted = dc->e_voted;
+  pa.n_distinct = dc->n_distinct;
 
   uint64_t out_cap = std::max<uint64_t>(1u << 20, n / 8);
-  uint64_t* prefix;
-  uint64_t* psums;
-  RC(ws<uint64_t>(c, "prefix", (uint64_t)hc.small_count + 1, &prefix));
-  RC(ws<uint64_t>(c, "psums", scan_sums_elems((uint64_t)hc.small_count + 1, 1) + 1, &psums));
   std::vector<uint4> hbig(hc.big_count);
   if (hc.big_count) {
     HIPCK(hipMemcpyAsync(hbig.data(), bdesc, hc.big_count * sizeof(uint4), hipMemcpyDeviceToHost, s));
@@ -615,21 +610,12 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
     pa.out_j = oj;
     pa.out_v = ov;
     pa.out_cap = (uint32_t)std::min<uint64_t>(out_cap, 0xFFFFFFFFull);
-    fill_u8(reinterpret_cast<uint8_t*>(&dc->e_voted), 16, 0, s);
+    fill_u8(reinterpret_cast<uint8_t*>(dc->e_voted), sizeof(dc->e_voted) + sizeof(dc->n_distinct), 0, s);
     fill_u32(&dc->out_count, 1, 0, s);
-    if (hc.small_count) {
-      launch_desc_sizes(sdesc, hc.small_count, prefix, s);
-      uint64_t* total;
-      RC(ws<uint64_t>(c, "ptotal", 1, &total));
-      scan_u64(prefix, hc.small_count, 1, psums, total, s);
-      LAUNCHCK();
-      uint64_t members = 0;
-      RC(d2h(c, &members, total));
-      prof_begin(c, FAST_LSH_STAGE_PAIRS);
-      launch_pairs_small(pa, sdesc, prefix, hc.small_count, members, sc, s);
-      prof_end(c);
-      LAUNCHCK();
-    }
+    prof_begin(c, FAST_LSH_STAGE_PAIRS);
+    launch_pairs_chunk(pa, marks, t, cc, s);
+    prof_end(c);
+    LAUNCHCK();
     if (hc.big_count) {
       std::vector<uint64_t> cofs(hc.big_count + 1, 0);
       for (uint32_t b = 0; b < hc.big_count; ++b) cofs[b + 1] = cofs[b] + hbig[b].z;
@@ -727,11 +713,11 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   prof_collect(c);
   fast_lsh_stats stv;
   stv.n_out = cnt;
-  stv.e_raw = hc.e_raw;
-  stv.e_voted = hc.e_voted;
-  stv.n_distinct = distinct ? hc.n_distinct : ~0ull;
+  stv.e_raw = spread_sum(hc.e_raw);
+  stv.e_voted = spread_sum(hc.e_voted);
+  stv.n_distinct = distinct ? spread_sum(hc.n_distinct) : ~0ull;
   stv.n_flagged = hc.n_flagged;
-  stv.max_bucket = hc.max_bucket;
+  stv.max_bucket = *std::max_element(hc.max_bucket, hc.max_bucket + kSpread);
   *out_stats = stv;
   return FAST_LSH_OK;
 }

@@ -8,6 +8,14 @@ namespace fl {
 
 constexpr uint32_t kP = 0x7FFFFFFFu;  // Mersenne prime 2^31 - 1 of the hash family
 
+// Counters updated by many workgroups are spread over kSpread slots (summed
+// on the host): atomics of every workgroup on one address serialise.
+constexpr uint32_t kSpread = 1024;
+
+__device__ __forceinline__ uint32_t spread_slot() {
+  return (blockIdx.x + blockIdx.y * 977u + blockIdx.z * 7919u) % kSpread;
+}
+
 // --------------------------------------------------------------------------
 // Universal hash h(x) = (a x + b) mod p evaluated from pre-doubled
 // parameters a2 = 2a, b2 = 2b (both < 2^32).  With y = a x + b < 2^48,
@@ -84,15 +92,14 @@ struct BucketArgs {
   uint32_t occ_num, occ_den;
   uint32_t min_lag;      // buckets whose id span is below this yield no pair
   uint8_t* flags;        // per fingerprint
-  uint32_t small_max;    // buckets of size <= small_max go to the small list
-  uint2* small_desc;     // {pos, seg<<16 | size}
-  uint32_t* small_count;
+  uint32_t small_max;    // buckets of size <= small_max are marked in place
+  uint8_t* marks;        // [S][n]: size of the small pair-capable bucket starting here, else 0
   uint4* big_desc;       // {pos, seg, size, 0}
   uint32_t* big_count;
   uint4* bin_desc;       // oversized bins {lo, hi, seg, 0}
   uint32_t* bin_count;
-  unsigned long long* e_raw;
-  unsigned int* max_bucket;
+  unsigned long long* e_raw;    // [kSpread]
+  unsigned int* max_bucket;     // [kSpread]
 };
 
 struct PairArgs {
@@ -109,15 +116,14 @@ struct PairArgs {
   uint8_t* out_v;
   unsigned int* out_count;
   uint32_t out_cap;
-  unsigned long long* e_voted;
-  unsigned long long* n_distinct;
+  unsigned long long* e_voted;     // [kSpread]
+  unsigned long long* n_distinct;  // [kSpread]
 };
 
-struct SmallCfg {
-  uint32_t memb_max;  // members staged per workgroup
-  uint32_t nb_max;    // buckets per workgroup
+struct ChunkCfg {
+  uint32_t chunk;     // positions per workgroup (buckets starting there)
+  uint32_t memb_max;  // chunk + small_max - 1: most members staged
   uint32_t rswl;      // LDS row stride in dwords (odd)
-  uint32_t mb;        // member budget that partitions the descriptor list
 };
 
 struct TileUnit {

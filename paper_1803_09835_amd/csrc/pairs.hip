@@ -160,8 +160,9 @@ __device__ void flush_tally(const PairArgs& a, PairTally tl) {
     nd += __shfl_xor(nd, o, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    if (ev) atomicAdd(a.e_voted, ev);
-    if (nd) atomicAdd(a.n_distinct, nd);
+    const uint32_t slot = spread_slot();
+    if (ev) atomicAdd(a.e_voted + slot, ev);
+    if (nd) atomicAdd(a.n_distinct + slot, nd);
   }
 }
 
@@ -202,72 +203,61 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
   return 2 * rsw - valid;
 }
 
-// Buckets of at most small_max members, partitioned by a prefix sum of their
-// sizes so that every workgroup stages about `mb` members.  Members and rows
-// are staged in LDS in parallel; then every thread walks a contiguous range
-// of the workgroup's pairs (row-major within each bucket), keeping the left
-// row in registers.
+// Small buckets of one table, found from the marks of a chunk of positions:
+// every bucket that starts in [p0, p0 + chunk) is handled by this
+// workgroup.  Members and rows are staged in LDS in parallel; then every
+// thread walks a contiguous range of the workgroup's pairs (row-major within
+// each bucket), keeping the left row in registers.
 template <int RSW>
-__global__ __launch_bounds__(kPT) void k_pairs_small(PairArgs a, const uint2* desc, const uint64_t* prefix,
-                                                     uint32_t ndesc, SmallCfg cfg) {
+__global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* marks_all, ChunkCfg cfg) {
   extern __shared__ uint32_t smem[];
-  uint32_t* lrows = smem;
-  uint32_t* lids = lrows + cfg.memb_max * cfg.rswl;
-  uint32_t* lpre = lids + cfg.memb_max;
-  uint32_t* bpof = lpre + cfg.nb_max + 1;
-  uint32_t* bpos = bpof + cfg.nb_max + 1;
-  uint32_t* bseg = bpos + cfg.nb_max;
+  uint32_t* lrows = smem;                             // memb_max * rswl
+  uint32_t* lids = lrows + cfg.memb_max * cfg.rswl;   // memb_max
+  uint32_t* hpos = lids + cfg.memb_max;               // chunk: head position offset
+  uint32_t* lpre = hpos + cfg.chunk;                  // chunk + 1: member prefix
+  uint32_t* bpof = lpre + cfg.chunk + 1;              // chunk + 1: pair prefix
   __shared__ uint32_t ws[8];
-  __shared__ uint32_t s_range[2];
   const uint32_t tid = threadIdx.x;
   const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_hw / 2;
+  const uint32_t seg = blockIdx.y;
+  const uint64_t p0 = (uint64_t)blockIdx.x * cfg.chunk;
+  const uint32_t cnt = (uint32_t)min((uint64_t)cfg.chunk, a.n - p0);
+  const uint8_t* marks = marks_all + (uint64_t)seg * a.n + p0;
+  const uint32_t* order = a.order + (uint64_t)seg * a.n + p0;
 
-  if (tid < 2) {
-    const uint64_t target = (uint64_t)(blockIdx.x + tid) * cfg.mb;
-    uint32_t L = 0, R = ndesc;
-    while (L < R) {
-      const uint32_t M = (L + R) / 2;
-      if (prefix[M] >= target) R = M; else L = M + 1;
-    }
-    s_range[tid] = L;
-  }
-  __syncthreads();
-  const uint32_t k_lo = s_range[0], nb = s_range[1] - s_range[0];
-  uint32_t mcarry = 0, pcarry = 0;
-  for (uint32_t b0 = 0; b0 < nb; b0 += kPT) {
-    const uint32_t b = b0 + tid;
-    uint32_t size = 0;
-    if (b < nb) {
-      const uint2 d = desc[k_lo + b];
-      size = d.y & 0xFFFFu;
-      bpos[b] = d.x;
-      bseg[b] = d.y >> 16;
-    }
-    uint32_t tm, tp;
+  // Heads of the chunk, compacted in position order.
+  uint32_t nh = 0, mcarry = 0, pcarry = 0;
+  for (uint32_t c0 = 0; c0 < cnt; c0 += kPT) {
+    const uint32_t q = c0 + tid;
+    const uint32_t size = q < cnt ? marks[q] : 0u;
+    uint32_t th, tm, tp;
+    const uint32_t xh = block_scan_excl<uint32_t>(size ? 1u : 0u, ws, &th);
     const uint32_t xm = block_scan_excl<uint32_t>(size, ws, &tm);
     const uint32_t xp = block_scan_excl<uint32_t>(size * (size - (size > 0)) / 2, ws, &tp);
-    if (b < nb) {
-      lpre[b] = mcarry + xm;
-      bpof[b] = pcarry + xp;
+    if (size) {
+      hpos[nh + xh] = q;
+      lpre[nh + xh] = mcarry + xm;
+      bpof[nh + xh] = pcarry + xp;
     }
+    nh += th;
     mcarry += tm;
     pcarry += tp;
   }
   if (tid == 0) {
-    lpre[nb] = mcarry;
-    bpof[nb] = pcarry;
+    lpre[nh] = mcarry;
+    bpof[nh] = pcarry;
   }
   __syncthreads();
+  if (nh == 0) return;
   // Stage member ids (excluded members marked dead) and their rows.
   const uint32_t M = mcarry;
-  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
+  const uint32_t g = seg / a.tables_per_group;
+  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows) + (uint64_t)g * a.n * rsw;
   for (uint32_t m = tid; m < M; m += kPT) {
-    const uint32_t b = last_le(lpre, nb, m);
-    const uint32_t seg = bseg[b];
-    const uint32_t id = a.order[(uint64_t)seg * a.n + bpos[b] + (m - lpre[b])];
-    const bool dead = a.flags[id] != 0;
-    lids[m] = dead ? kDead : id;
-    const uint32_t* src = R + ((uint64_t)(seg / a.tables_per_group) * a.n + id) * rsw;
+    const uint32_t b = last_le(lpre, nh, m);
+    const uint32_t id = order[hpos[b] + (m - lpre[b])];
+    lids[m] = a.flags[id] != 0 ? kDead : id;
+    const uint32_t* src = R + (uint64_t)id * rsw;
     uint32_t* dst = lrows + m * cfg.rswl;
     for (uint32_t w = 0; w < rsw; ++w) dst[w] = src[w];
   }
@@ -275,26 +265,25 @@ __global__ __launch_bounds__(kPT) void k_pairs_small(PairArgs a, const uint2* de
   // Pairs: thread tid walks [p, pend).
   PairTally tl{0ull, 0ull};
   const uint32_t P = pcarry;
+  const uint32_t pad = group_pad(a, seg, rsw);
   const uint32_t per = (P + kPT - 1) / kPT;
   uint32_t p = tid * per;
   const uint32_t pend = min(P, p + per);
   if (p < pend) {
-    uint32_t b = last_le(bpof, nb, p);
-    uint32_t base = lpre[b], m = lpre[b + 1] - base, u = bseg[b], pad = group_pad(a, u, rsw);
+    uint32_t b = last_le(bpof, nh, p);
+    uint32_t base = lpre[b], m = lpre[b + 1] - base;
     uint32_t x, y;
     tri_decode(m, p - bpof[b], x, y);
     uint32_t idx = lids[base + x];
     RowReg<RSW> rx;
     rx.load(lrows + (base + x) * cfg.rswl, rsw);
     for (; p < pend; ++p) {
-      visit_pair<RSW>(a, u, idx, lids[base + y], rx, lrows + (base + y) * cfg.rswl, rsw, pad, tl);
+      visit_pair<RSW>(a, seg, idx, lids[base + y], rx, lrows + (base + y) * cfg.rswl, rsw, pad, tl);
       if (++y == m) {
         if (++x == m - 1) {
-          if (++b >= nb) break;
+          if (++b >= nh) break;
           base = lpre[b];
           m = lpre[b + 1] - base;
-          u = bseg[b];
-          pad = group_pad(a, u, rsw);
           x = 0;
         }
         y = x + 1;
@@ -415,10 +404,6 @@ __global__ __launch_bounds__(kPT) void k_pack_out(const uint32_t* oi, const uint
   }
 }
 
-__global__ __launch_bounds__(kPT) void k_desc_sizes(const uint2* desc, uint32_t count, uint64_t* sizes) {
-  for (uint32_t e = blockIdx.x * kPT + threadIdx.x; e < count; e += gridDim.x * kPT) sizes[e] = desc[e].y & 0xFFFFu;
-}
-
 __global__ __launch_bounds__(kPT) void k_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out) {
   unsigned long long c = 0;
   for (uint64_t e = (uint64_t)blockIdx.x * kPT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * kPT) c += flags[e] != 0;
@@ -439,20 +424,18 @@ static unsigned grid_for(uint64_t count) {
   return (unsigned)(b == 0 ? 1 : (b < 65535 ? b : 65535));
 }
 
-size_t small_smem_bytes(const SmallCfg& c) {
-  return (size_t)c.memb_max * c.rswl * 4 + (size_t)c.memb_max * 4 + (size_t)(c.nb_max + 1) * 8 +
-         (size_t)c.nb_max * 8 + 16;
+size_t chunk_smem_bytes(const ChunkCfg& c) {
+  return (size_t)c.memb_max * c.rswl * 4 + (size_t)c.memb_max * 4 + (size_t)c.chunk * 4 + (size_t)(c.chunk + 1) * 8;
 }
 
-void launch_pairs_small(const PairArgs& a, const uint2* desc, const uint64_t* prefix, uint32_t ndesc,
-                        uint64_t total_members, const SmallCfg& c, hipStream_t s) {
-  if (ndesc == 0) return;
-  const uint64_t nwg = (total_members + c.mb - 1) / c.mb;
-  const size_t smem = small_smem_bytes(c);
+void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, const ChunkCfg& c, hipStream_t s) {
+  if (a.n == 0) return;
+  const dim3 grid((unsigned)((a.n + c.chunk - 1) / c.chunk), S);
+  const size_t smem = chunk_smem_bytes(c);
   switch (a.row_hw / 2) {
-    case 10: hipLaunchKernelGGL((k_pairs_small<10>), dim3((unsigned)nwg), dim3(kPT), smem, s, a, desc, prefix, ndesc, c); break;
-    case 17: hipLaunchKernelGGL((k_pairs_small<17>), dim3((unsigned)nwg), dim3(kPT), smem, s, a, desc, prefix, ndesc, c); break;
-    default: hipLaunchKernelGGL((k_pairs_small<0>), dim3((unsigned)nwg), dim3(kPT), smem, s, a, desc, prefix, ndesc, c); break;
+    case 10: hipLaunchKernelGGL((k_pairs_chunk<10>), grid, dim3(kPT), smem, s, a, marks, c); break;
+    case 17: hipLaunchKernelGGL((k_pairs_chunk<17>), grid, dim3(kPT), smem, s, a, marks, c); break;
+    default: hipLaunchKernelGGL((k_pairs_chunk<0>), grid, dim3(kPT), smem, s, a, marks, c); break;
   }
 }
 
@@ -484,11 +467,6 @@ void launch_pack_out(const uint32_t* oi, const uint32_t* oj, const uint8_t* ov, 
                      uint32_t* val, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(k_pack_out, dim3(grid_for(count)), dim3(kPT), 0, s, oi, oj, ov, count, key, val);
-}
-
-void launch_desc_sizes(const uint2* desc, uint32_t count, uint64_t* sizes, hipStream_t s) {
-  if (count == 0) return;
-  hipLaunchKernelGGL(k_desc_sizes, dim3(grid_for(count)), dim3(kPT), 0, s, desc, count, sizes);
 }
 
 void launch_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out, hipStream_t s) {

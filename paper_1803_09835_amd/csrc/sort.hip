@@ -21,8 +21,6 @@
 namespace fl {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kTile = kThreads * kItems;  // 4096
 constexpr int kRadix = 256;
 constexpr int kScanBlock = 4096;
 
@@ -44,8 +42,12 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d) {
 // Radix pass kernels.  Segment s occupies [s*n, (s+1)*n) of every array.
 // vin == nullptr means the value of element e is e (its id).
 // ---------------------------------------------------------------------------
-constexpr int kRThreads = 512;                 // radix-pass workgroup
-constexpr int kRItems = kTile / kRThreads;      // 8 elements per thread
+// Radix-pass tile: 16,384 elements (1024 threads x 16).  Large tiles make
+// each digit's run of output addresses long (64 elements on average), which
+// is what lets the scatter write at a large fraction of HBM bandwidth.
+constexpr int kRThreads = 1024;
+constexpr int kRItems = 16;
+constexpr int kTile = kRThreads * kRItems;
 
 template <int THREADS = kRThreads, int ITEMS = kRItems>
 __global__ __launch_bounds__(THREADS) void k_hist(const uint64_t* keys, uint64_t n, uint32_t shift,
@@ -340,8 +342,9 @@ __device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
     m = om > m ? om : m;
   }
   if ((threadIdx.x & 63) == 0) {
-    if (e) atomicAdd(a.e_raw, e);
-    atomicMax(a.max_bucket, m);
+    const uint32_t slot = spread_slot();
+    if (e) atomicAdd(a.e_raw + slot, e);
+    atomicMax(a.max_bucket + slot, m);
   }
 }
 
@@ -471,42 +474,39 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
   __syncthreads();
   for (uint32_t e = threadIdx.x; e < m; e += blockDim.x)
     if (mixed[bs[e]] != 2) V[lo + e] = sv[e];
-  // Buckets: pass 1 counts descriptors per thread, pass 2 writes them.
-  // (Positions inside a bin stay inside it, so bs[] still names the bin.)
-  uint32_t nsmall = 0, nbig = 0;
+  // Buckets: every position gets its mark (the size of a small pair-capable
+  // bucket starting there, else 0); large buckets go to a list.
+  uint8_t* marks = a.marks + (uint64_t)seg * a.n + lo;
+  uint32_t nbig = 0;
   for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
     const uint32_t b0 = bs[e];
     if (mixed[b0] == 2) continue;
-    if (e > 0 && sk[e] == sk[e - 1]) continue;
-    const uint32_t f = run_end(sk, e, b0, be, mixed);
-    const int cls = bucket_account(a, f - e, [&](uint64_t q) { return sv[e + q]; }, sv[e], tot);
-    nsmall += cls == 1;
-    nbig += cls == 2;
-  }
-  uint32_t* ws = sh;       // 4 entries
-  uint32_t* base = sh + 4; // 2 entries
-  uint32_t tsmall, tbig;
-  const uint32_t xs = block_excl_scan<uint32_t>(nsmall, ws, &tsmall);
-  const uint32_t xb = block_excl_scan<uint32_t>(nbig, ws, &tbig);
-  if (threadIdx.x == 0) {
-    base[0] = tsmall ? atomicAdd(a.small_count, tsmall) : 0;
-    base[1] = tbig ? atomicAdd(a.big_count, tbig) : 0;
-  }
-  __syncthreads();
-  uint32_t ps = base[0] + xs, pb = base[1] + xb;
-  if (nsmall | nbig) {
-    for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
-      const uint32_t b0 = bs[e];
-      if (mixed[b0] == 2) continue;
-      if (e > 0 && sk[e] == sk[e - 1]) continue;
+    uint8_t mk = 0;
+    if (e == 0 || sk[e] != sk[e - 1]) {
       const uint32_t f = run_end(sk, e, b0, be, mixed);
-      const uint32_t size = f - e;
-      const int cls = bucket_class(a, size, sv[e], sv[f - 1]);
-      const uint32_t pos = (uint32_t)(lo + e);
-      if (cls == 1)
-        a.small_desc[ps++] = make_uint2(pos, (seg << 16) | size);
-      else if (cls == 2)
-        a.big_desc[pb++] = make_uint4(pos, seg, size, 0);
+      const int cls = bucket_account(a, f - e, [&](uint64_t q) { return sv[e + q]; }, sv[e], tot);
+      if (cls == 1) mk = (uint8_t)(f - e);
+      nbig += cls == 2;
+    }
+    marks[e] = mk;
+  }
+  uint32_t* ws = sh;        // 4 entries
+  uint32_t* base = sh + 4;  // 1 entry
+  uint32_t tbig;
+  const uint32_t xb = block_excl_scan<uint32_t>(nbig, ws, &tbig);
+  if (tbig) {
+    if (threadIdx.x == 0) base[0] = atomicAdd(a.big_count, tbig);
+    __syncthreads();
+    uint32_t pb = base[0] + xb;
+    if (nbig) {
+      for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
+        const uint32_t b0 = bs[e];
+        if (mixed[b0] == 2) continue;
+        if (e > 0 && sk[e] == sk[e - 1]) continue;
+        const uint32_t f = run_end(sk, e, b0, be, mixed);
+        if (bucket_class(a, f - e, sv[e], sv[f - 1]) == 2)
+          a.big_desc[pb++] = make_uint4((uint32_t)(lo + e), seg, f - e, 0);
+      }
     }
   }
   __syncthreads();
@@ -684,11 +684,13 @@ __global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* 
   BucketTotals tot{0ull, 0u};
   if (tid == 0) s_carry = 0;
   __syncthreads();
+  uint8_t* marks = a.marks + off;
+  for (uint64_t p = lo + tid; p < hi; p += kThreads) marks[p] = 0;
+  __syncthreads();
   auto emit = [&](uint64_t s, uint64_t e) {
     const int cls = bucket_account(a, e - s, [&](uint64_t q) { return V[s + q]; }, V[s], tot);
     if (cls == 1) {
-      const uint32_t q = atomicAdd(a.small_count, 1u);
-      a.small_desc[q] = make_uint2((uint32_t)s, (seg << 16) | (uint32_t)(e - s));
+      marks[s] = (uint8_t)(e - s);
     } else if (cls == 2) {
       const uint32_t q = atomicAdd(a.big_count, 1u);
       a.big_desc[q] = make_uint4((uint32_t)s, seg, (uint32_t)(e - s), 0);
