@@ -303,7 +303,7 @@ static SigArgs sig_args(const fast_lsh_hash* h, const fast_lsh_fps* f, const uin
   a.b = dhash + 3 * F;
   a.err = err;
   a.tables_per_group = 1;
-  a.row_hw = 2;
+  a.row_dw = 4;
   return a;
 }
 
@@ -399,7 +399,7 @@ int fast_lsh_search(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps*
 // Search
 // ---------------------------------------------------------------------------
 struct Plan {
-  uint32_t t, G, TG, row_hw, rsw, need;
+  uint32_t t, G, TG, row_dw, rsw, need;
 };
 
 // Bits of the mixed key the radix passes bin on: a multiple of 8 large enough
@@ -418,8 +418,8 @@ static Plan make_plan(uint32_t t, uint32_t v, bool distinct) {
   p.TG = (t + G - 1) / G;
   p.G = (t + p.TG - 1) / p.TG;
   p.need = (v + p.G - 1) / p.G;
-  p.row_hw = (p.TG + 1) & ~1u;
-  p.rsw = p.row_hw / 2;
+  p.row_dw = row_dwords(p.TG);
+  p.rsw = p.row_dw;
   return p;
 }
 
@@ -466,14 +466,13 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
 
   uint64_t *mkeys, *ak, *bk;
   uint32_t *av, *bv;
-  uint16_t* rows;
+  uint32_t* rows;
   RC(ws<uint64_t>(c, "mkeys", tn, &mkeys));
-  RC(ws<uint16_t>(c, "rows", (uint64_t)pl.G * n * pl.row_hw, &rows));
+  RC(ws<uint32_t>(c, "rows", (uint64_t)pl.G * n * pl.row_dw, &rows));
   RC(ws<uint64_t>(c, "ak", tn, &ak));
   RC(ws<uint32_t>(c, "av", tn, &av));
   RC(ws<uint64_t>(c, "bk", tn, &bk));
   RC(ws<uint32_t>(c, "bv", tn, &bv));
-  fill_u32(reinterpret_cast<uint32_t*>(rows), (uint64_t)pl.G * n * pl.row_hw / 2, 0, s);
 
   // 1. signatures -> mixed keys (table-major) and sub-key rows
   SigArgs sa = sig_args(h, f, dh, &dc->err);
@@ -483,7 +482,7 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   sa.mkeys = mkeys;
   sa.rows = rows;
   sa.tables_per_group = pl.TG;
-  sa.row_hw = pl.row_hw;
+  sa.row_dw = pl.row_dw;
   prof_begin(c, FAST_LSH_STAGE_SIGNATURES);
   launch_sig(cap, h->scheme == FAST_LSH_MINMAX, sa, s);
   prof_end(c);
@@ -585,7 +584,7 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   pa.t = t;
   pa.G = pl.G;
   pa.tables_per_group = pl.TG;
-  pa.row_hw = pl.row_hw;
+  pa.row_dw = pl.row_dw;
   pa.min_lag = flt->min_lag;
   pa.min_votes = flt->min_votes;
   pa.need = pl.need;

@@ -52,6 +52,29 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
 }
 
 // --------------------------------------------------------------------------
+// Sub-key rows.  Each fingerprint carries, per group of tables, a row of
+// 15-bit sub-keys (the low bits of its mixed band key in each table of the
+// group) packed LSB-first, field k at bit 15k, in a row of row_dw dwords
+// (row_dw a multiple of 4, so a row is read with 16-byte loads; 34 tables
+// fit a 64-byte row).  Equal band keys give equal sub-keys.
+// --------------------------------------------------------------------------
+constexpr uint32_t kSubBits = 15;
+constexpr uint32_t kSubMask = (1u << kSubBits) - 1;
+
+__host__ __device__ constexpr uint32_t row_dwords(uint32_t tables) {
+  return 4 * ((kSubBits * tables + 127) / 128);
+}
+__host__ __device__ constexpr uint32_t row_fields(uint32_t dwords) { return 32 * dwords / kSubBits; }
+
+// Field k of the (XOR-combined or plain) row r.
+__device__ __forceinline__ uint32_t row_field(const uint32_t* r, uint32_t k) {
+  const uint32_t bit = kSubBits * k, w = bit >> 5, sh = bit & 31;
+  uint32_t v = r[w] >> sh;
+  if (sh > 32 - kSubBits) v |= r[w + 1] << (32 - sh);
+  return v & kSubMask;
+}
+
+// --------------------------------------------------------------------------
 // Launch arguments
 // --------------------------------------------------------------------------
 struct SigArgs {
@@ -74,9 +97,9 @@ struct SigArgs {
   uint64_t* keys;        // [table_count][n] band keys, or nullptr
   uint32_t* sigs;        // [n][table_count][r] values, or nullptr
   uint64_t* mkeys;       // [table_count][n] fmix64(band key), or nullptr
-  uint16_t* rows;        // sub-key rows [G][n][row_hw] (low 16 bits of fmix64), or nullptr
+  uint32_t* rows;        // sub-key rows [G][n][row_dw], or nullptr
   uint32_t tables_per_group;
-  uint32_t row_hw;       // halfwords per row (even)
+  uint32_t row_dw;       // dwords per row (a multiple of 4)
   int* err;              // set to 1 on an empty row or an index >= dim
 };
 
@@ -105,10 +128,10 @@ struct BucketArgs {
 struct PairArgs {
   const uint32_t* order;      // bucket members by position [S][n]
   const uint8_t* flags;
-  const uint16_t* rows;       // sub-key rows [G][n][row_hw]
+  const uint32_t* rows;       // sub-key rows [G][n][row_dw]
   const uint64_t* mkeys;      // exact keys [t][n]
   uint64_t n;
-  uint32_t t, G, tables_per_group, row_hw;
+  uint32_t t, G, tables_per_group, row_dw;
   uint32_t min_lag, min_votes, need;
   uint32_t want_distinct;
   uint32_t* out_i;

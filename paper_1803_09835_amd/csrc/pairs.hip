@@ -33,32 +33,21 @@ __device__ __forceinline__ void tri_decode(uint32_t m, uint32_t q, uint32_t& x, 
   y = q - S(xx) + (uint32_t)xx + 1;
 }
 
-__device__ __forceinline__ uint32_t eq_halves(uint32_t a, uint32_t b) {
-  const uint32_t x = a ^ b;
-  return (uint32_t)((x & 0xFFFFu) == 0) + (uint32_t)((x >> 16) == 0);
-}
-
 // Exact shared tables of (i, j) from global rows and mixed keys; reports the
-// pair if table u is its owner.  Returns nothing; writes the output.
+// pair if table u is its owner.
 __device__ __forceinline__ void exact_and_report(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
-  const uint32_t rsw = a.row_hw / 2;
-  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
   uint32_t votes = 0, owner = 0xFFFFFFFFu;
   for (uint32_t g = 0; g < a.G; ++g) {
-    const uint32_t* ri = R + ((uint64_t)g * a.n + i) * rsw;
-    const uint32_t* rj = R + ((uint64_t)g * a.n + j) * rsw;
+    const uint32_t* ri = a.rows + ((uint64_t)g * a.n + i) * a.row_dw;
+    const uint32_t* rj = a.rows + ((uint64_t)g * a.n + j) * a.row_dw;
+    const uint32_t valid = min(a.tables_per_group, a.t - g * a.tables_per_group);
     uint32_t cnt = 0, minu = 0xFFFFFFFFu;
-    for (uint32_t w = 0; w < rsw; ++w) {
-      const uint32_t x = ri[w] ^ rj[w];
-      for (uint32_t h = 0; h < 2; ++h) {
-        const uint32_t slot = 2 * w + h;
-        const uint32_t tab = g * a.tables_per_group + slot;
-        if (slot >= a.tables_per_group || tab >= a.t) continue;
-        if (((x >> (16 * h)) & 0xFFFFu) != 0) continue;
-        if (a.mkeys[(uint64_t)tab * a.n + i] == a.mkeys[(uint64_t)tab * a.n + j]) {
-          ++cnt;
-          minu = tab < minu ? tab : minu;
-        }
+    for (uint32_t k = 0; k < valid; ++k) {
+      if (row_field(ri, k) != row_field(rj, k)) continue;
+      const uint32_t tab = g * a.tables_per_group + k;
+      if (a.mkeys[(uint64_t)tab * a.n + i] == a.mkeys[(uint64_t)tab * a.n + j]) {
+        ++cnt;
+        minu = tab < minu ? tab : minu;
       }
     }
     votes += cnt;
@@ -75,15 +64,12 @@ __device__ __forceinline__ void exact_and_report(const PairArgs& a, uint32_t u, 
 }
 
 // True when no table below u exactly shares a bucket with (i, j) (G == 1:
-// one group, slot == table).
+// one group, field == table).
 __device__ __forceinline__ bool first_shared_is(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
-  const uint32_t rsw = a.row_hw / 2;
-  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
-  const uint32_t* ri = R + (uint64_t)i * rsw;
-  const uint32_t* rj = R + (uint64_t)j * rsw;
+  const uint32_t* ri = a.rows + (uint64_t)i * a.row_dw;
+  const uint32_t* rj = a.rows + (uint64_t)j * a.row_dw;
   for (uint32_t tab = 0; tab < u; ++tab) {
-    const uint32_t x = ri[tab >> 1] ^ rj[tab >> 1];
-    if (((x >> (16 * (tab & 1))) & 0xFFFFu) != 0) continue;
+    if (row_field(ri, tab) != row_field(rj, tab)) continue;
     if (a.mkeys[(uint64_t)tab * a.n + i] == a.mkeys[(uint64_t)tab * a.n + j]) return false;
   }
   return true;
@@ -100,42 +86,49 @@ constexpr uint32_t kDead = 0xFFFFFFFFu;  // member excluded by the occurrence fi
 // RSW == 0: runtime length, both rows read from LDS.
 template <int RSW>
 struct RowReg {
-  uint32_t w[RSW > 0 ? RSW : 1];
+  static constexpr int kW = RSW > 0 ? RSW : 1;
+  uint32_t w[kW];
   const uint32_t* lds;
   __device__ __forceinline__ void load(const uint32_t* src, uint32_t rsw) {
     if (RSW > 0) {
 #pragma unroll
-      for (int k = 0; k < (RSW > 0 ? RSW : 1); ++k) w[k] = src[k];
+      for (int k = 0; k < kW; ++k) w[k] = src[k];
     } else {
       lds = src;
     }
     (void)rsw;
   }
-  // Number of equal 16-bit sub-keys against another row.
+  // Number of equal sub-keys (15-bit fields) against another row.
   __device__ __forceinline__ uint32_t eq(const uint32_t* other, uint32_t rsw) const {
     uint32_t e = 0;
     if (RSW > 0) {
+      uint32_t x[kW + 1];
 #pragma unroll
-      for (int k = 0; k < (RSW > 0 ? RSW : 1); ++k) e += eq_halves(w[k], other[k]);
+      for (int k = 0; k < kW; ++k) x[k] = w[k] ^ other[k];
+      x[kW] = 0;
+#pragma unroll
+      for (uint32_t f = 0; f < row_fields(kW); ++f) e += row_field(x, f) == 0;
     } else {
-#pragma unroll 4
-      for (uint32_t k = 0; k < rsw; ++k) e += eq_halves(lds[k], other[k]);
+      const uint32_t nf = row_fields(rsw);
+      for (uint32_t f = 0; f < nf; ++f) e += row_field(lds, f) == row_field(other, f);
     }
     return e;
   }
-  // Equal sub-keys in slots below `u` (one group holding every table).
+  // Equal sub-keys in fields below `u` (one group holding every table).
   __device__ __forceinline__ uint32_t eq_below(const uint32_t* other, uint32_t rsw, uint32_t u) const {
     uint32_t e = 0;
     if (RSW > 0) {
+      uint32_t x[kW + 1];
 #pragma unroll
-      for (int k = 0; k < (RSW > 0 ? RSW : 1); ++k) e += below2(w[k] ^ other[k], (uint32_t)k, u);
+      for (int k = 0; k < kW; ++k) x[k] = w[k] ^ other[k];
+      x[kW] = 0;
+#pragma unroll
+      for (uint32_t f = 0; f < row_fields(kW); ++f) e += (f < u) && row_field(x, f) == 0;
     } else {
-      for (uint32_t k = 0; k < rsw; ++k) e += below2(lds[k] ^ other[k], k, u);
+      for (uint32_t f = 0; f < u; ++f) e += row_field(lds, f) == row_field(other, f);
     }
+    (void)rsw;
     return e;
-  }
-  __device__ __forceinline__ static uint32_t below2(uint32_t x, uint32_t k, uint32_t u) {
-    return (2 * k < u ? (uint32_t)((x & 0xFFFFu) == 0) : 0u) + (2 * k + 1 < u ? (uint32_t)((x >> 16) == 0) : 0u);
   }
 };
 
@@ -187,6 +180,18 @@ __device__ __forceinline__ T block_scan_excl(T v, T* ws, T* total) {
   return add + inc - v;
 }
 
+// Copy one row (rsw dwords, 16-byte aligned in HBM) into LDS.
+__device__ __forceinline__ void stage_row(const uint32_t* src, uint32_t* dst, uint32_t rsw) {
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  for (uint32_t q = 0; q < rsw / 4; ++q) {
+    const uint4 v = s4[q];
+    dst[4 * q] = v.x;
+    dst[4 * q + 1] = v.y;
+    dst[4 * q + 2] = v.z;
+    dst[4 * q + 3] = v.w;
+  }
+}
+
 // Last index b in [0, cnt) with arr[b] <= key (arr ascending, arr[0] <= key).
 __device__ __forceinline__ uint32_t last_le(const uint32_t* arr, uint32_t cnt, uint32_t key) {
   uint32_t L = 0, R = cnt;
@@ -197,10 +202,12 @@ __device__ __forceinline__ uint32_t last_le(const uint32_t* arr, uint32_t cnt, u
   return L;
 }
 
+// Fields of table u's group row that hold no table (zero in every row, so
+// always equal).
 __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uint32_t rsw) {
   const uint32_t g = u / a.tables_per_group;
   const uint32_t valid = min(a.tables_per_group, a.t - g * a.tables_per_group);
-  return 2 * rsw - valid;
+  return row_fields(rsw) - valid;
 }
 
 // Small buckets of one table, found from the marks of a chunk of positions:
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* 
   uint32_t* bpof = lpre + cfg.chunk + 1;              // chunk + 1: pair prefix
   __shared__ uint32_t ws[8];
   const uint32_t tid = threadIdx.x;
-  const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_hw / 2;
+  const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
   const uint32_t seg = blockIdx.y;
   const uint64_t p0 = (uint64_t)blockIdx.x * cfg.chunk;
   const uint32_t cnt = (uint32_t)min((uint64_t)cfg.chunk, a.n - p0);
@@ -252,14 +259,12 @@ __global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* 
   // Stage member ids (excluded members marked dead) and their rows.
   const uint32_t M = mcarry;
   const uint32_t g = seg / a.tables_per_group;
-  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows) + (uint64_t)g * a.n * rsw;
+  const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
   for (uint32_t m = tid; m < M; m += kPT) {
     const uint32_t b = last_le(lpre, nh, m);
     const uint32_t id = order[hpos[b] + (m - lpre[b])];
     lids[m] = a.flags[id] != 0 ? kDead : id;
-    const uint32_t* src = R + (uint64_t)id * rsw;
-    uint32_t* dst = lrows + m * cfg.rswl;
-    for (uint32_t w = 0; w < rsw; ++w) dst[w] = src[w];
+    stage_row(R + (uint64_t)id * rsw, lrows + m * cfg.rswl, rsw);
   }
   __syncthreads();
   // Pairs: thread tid walks [p, pend).
@@ -328,7 +333,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
                                                     uint32_t tb_size, uint32_t rswl) {
   extern __shared__ uint32_t smem[];
   const TileUnit un = units[blockIdx.x];
-  const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_hw / 2;
+  const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
   const uint32_t seg = big[un.bucket].y;
   const uint32_t* bid = ids + cofs[un.bucket];
   const uint32_t m = cnt[un.bucket];
@@ -341,19 +346,17 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
   uint32_t* idsA = smem + 2 * tb_size * rswl;
   uint32_t* idsB = diag ? idsA : idsA + tb_size;
   const uint32_t g = seg / a.tables_per_group;
-  const uint32_t* R = reinterpret_cast<const uint32_t*>(a.rows);
+  const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
   for (uint32_t q = threadIdx.x; q < na; q += kPT) {
     const uint32_t id = bid[a0 + q];
     idsA[q] = id;
-    const uint32_t* src = R + ((uint64_t)g * a.n + id) * rsw;
-    for (uint32_t w = 0; w < rsw; ++w) rowsA[q * rswl + w] = src[w];
+    stage_row(R + (uint64_t)id * rsw, rowsA + q * rswl, rsw);
   }
   if (!diag) {
     for (uint32_t q = threadIdx.x; q < nbm; q += kPT) {
       const uint32_t id = bid[b0 + q];
       idsB[q] = id;
-      const uint32_t* src = R + ((uint64_t)g * a.n + id) * rsw;
-      for (uint32_t w = 0; w < rsw; ++w) rowsB[q * rswl + w] = src[w];
+      stage_row(R + (uint64_t)id * rsw, rowsB + q * rswl, rsw);
     }
   }
   __syncthreads();
@@ -432,9 +435,9 @@ void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, con
   if (a.n == 0) return;
   const dim3 grid((unsigned)((a.n + c.chunk - 1) / c.chunk), S);
   const size_t smem = chunk_smem_bytes(c);
-  switch (a.row_hw / 2) {
-    case 10: hipLaunchKernelGGL((k_pairs_chunk<10>), grid, dim3(kPT), smem, s, a, marks, c); break;
-    case 17: hipLaunchKernelGGL((k_pairs_chunk<17>), grid, dim3(kPT), smem, s, a, marks, c); break;
+  switch (a.row_dw) {
+    case 12: hipLaunchKernelGGL((k_pairs_chunk<12>), grid, dim3(kPT), smem, s, a, marks, c); break;
+    case 16: hipLaunchKernelGGL((k_pairs_chunk<16>), grid, dim3(kPT), smem, s, a, marks, c); break;
     default: hipLaunchKernelGGL((k_pairs_chunk<0>), grid, dim3(kPT), smem, s, a, marks, c); break;
   }
 }
@@ -450,9 +453,9 @@ void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits
                        uint32_t rswl, hipStream_t s) {
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
-  switch (a.row_hw / 2) {
-    case 10: hipLaunchKernelGGL((k_pairs_tile<10>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
-    case 17: hipLaunchKernelGGL((k_pairs_tile<17>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
+  switch (a.row_dw) {
+    case 12: hipLaunchKernelGGL((k_pairs_tile<12>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
+    case 16: hipLaunchKernelGGL((k_pairs_tile<16>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
     default: hipLaunchKernelGGL((k_pairs_tile<0>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
   }
 }

@@ -58,15 +58,29 @@ struct KeyBuilder {
   }
 };
 
-__device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint64_t i, uint32_t u) {
+// Keys of table u for this lane's fingerprint; the sub-key goes into the
+// lane's row under construction in LDS (`my`, row_dw dwords), which is
+// written out with 16-byte stores when the last table of its group is done.
+__device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint64_t i, uint32_t u, bool live,
+                                            uint32_t* my) {
   const uint32_t tab = a.table_begin + u;
-  if (a.keys) a.keys[(uint64_t)u * a.n + i] = key;
+  if (live && a.keys) a.keys[(uint64_t)u * a.n + i] = key;
   if (a.mkeys || a.rows) {
     const uint64_t m = fmix64(key);
-    if (a.mkeys) a.mkeys[(uint64_t)u * a.n + i] = m;
+    if (live && a.mkeys) a.mkeys[(uint64_t)u * a.n + i] = m;
     if (a.rows) {
       const uint32_t g = tab / a.tables_per_group, slot = tab - g * a.tables_per_group;
-      a.rows[((uint64_t)g * a.n + i) * a.row_hw + slot] = (uint16_t)m;
+      if (slot == 0)
+        for (uint32_t w = 0; w < a.row_dw; ++w) my[w] = 0;
+      const uint32_t f = (uint32_t)m & kSubMask;
+      const uint32_t bit = kSubBits * slot, w = bit >> 5, sh = bit & 31;
+      my[w] |= f << sh;
+      if (sh > 32 - kSubBits) my[w + 1] |= f >> (32 - sh);
+      if (live && (slot + 1 == a.tables_per_group || u + 1 == a.table_count)) {
+        uint4* dst = reinterpret_cast<uint4*>(a.rows + ((uint64_t)g * a.n + i) * a.row_dw);
+        for (uint32_t q = 0; q < a.row_dw / 4; ++q)
+          dst[q] = make_uint4(my[4 * q], my[4 * q + 1], my[4 * q + 2], my[4 * q + 3]);
+      }
     }
   }
 }
@@ -76,7 +90,9 @@ __device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint
 // fixed-length with an even length and 4-byte aligned (other layouts take
 // k_sig_long).
 template <int CAP, bool MINMAX>
-__global__ __launch_bounds__(256) void k_sig(SigArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 ? 4 : 1))) void k_sig(SigArgs a) {
+  extern __shared__ uint32_t srow[];  // 256 rows of row_dw + 1 dwords (odd stride)
+  uint32_t* my = srow + threadIdx.x * (a.row_dw + 1);
   constexpr int W = CAP / 2;
   const uint64_t gi = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   const bool live = gi < a.n;
@@ -139,7 +155,7 @@ __global__ __launch_bounds__(256) void k_sig(SigArgs a) {
         if (MINMAX) kb.put(a, fB, acc.mxB, i, u, live);
       }
     }
-    if (live) store_table(a, kb.key, i, u);
+    store_table(a, kb.key, i, u, live, my);
   }
 }
 
@@ -147,6 +163,8 @@ __global__ __launch_bounds__(256) void k_sig(SigArgs a) {
 // from memory once per function pair.
 template <bool MINMAX>
 __global__ __launch_bounds__(256) void k_sig_long(SigArgs a) {
+  extern __shared__ uint32_t srow[];
+  uint32_t* my = srow + threadIdx.x * (a.row_dw + 1);
   const uint64_t gi = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   const bool live = gi < a.n;
   const uint64_t i = live ? gi : a.n - 1;
@@ -185,7 +203,7 @@ __global__ __launch_bounds__(256) void k_sig_long(SigArgs a) {
         if (MINMAX) kb.put(a, fB, acc.mxB, i, u, live);
       }
     }
-    if (live) store_table(a, kb.key, i, u);
+    store_table(a, kb.key, i, u, live, my);
   }
 }
 
@@ -222,14 +240,15 @@ int sig_capacity_for(uint64_t max_len) {
 
 template <bool MM>
 static void launch_cap(int cap, dim3 g, dim3 b, hipStream_t s, const SigArgs& a) {
+  const size_t sm = a.rows ? (size_t)256 * (a.row_dw + 1) * 4 : 0;
   switch (cap) {
-    case 16: hipLaunchKernelGGL((k_sig<16, MM>), g, b, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_sig<32, MM>), g, b, 0, s, a); break;
-    case 64: hipLaunchKernelGGL((k_sig<64, MM>), g, b, 0, s, a); break;
-    case 128: hipLaunchKernelGGL((k_sig<128, MM>), g, b, 0, s, a); break;
-    case 200: hipLaunchKernelGGL((k_sig<200, MM>), g, b, 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_sig<256, MM>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_sig_long<MM>), g, b, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_sig<16, MM>), g, b, sm, s, a); break;
+    case 32: hipLaunchKernelGGL((k_sig<32, MM>), g, b, sm, s, a); break;
+    case 64: hipLaunchKernelGGL((k_sig<64, MM>), g, b, sm, s, a); break;
+    case 128: hipLaunchKernelGGL((k_sig<128, MM>), g, b, sm, s, a); break;
+    case 200: hipLaunchKernelGGL((k_sig<200, MM>), g, b, sm, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sig<256, MM>), g, b, sm, s, a); break;
+    default: hipLaunchKernelGGL((k_sig_long<MM>), g, b, sm, s, a); break;
   }
 }
 
