@@ -525,9 +525,10 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   const uint32_t smax = 64;
   ChunkCfg cc;
   cc.rswl = pl.rsw | 1u;
+  cc.use_flags = 1;
   cc.chunk = 512;
   for (;;) {
-    cc.memb_max = cc.chunk + smax - 1;
+    cc.span = cc.chunk + smax - 1;
     if (chunk_smem_bytes(cc) <= 40960 || cc.chunk <= 32) break;
     cc.chunk >>= 1;
   }
@@ -611,6 +612,7 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
     pa.out_cap = (uint32_t)std::min<uint64_t>(out_cap, 0xFFFFFFFFull);
     fill_u8(reinterpret_cast<uint8_t*>(dc->e_voted), sizeof(dc->e_voted) + sizeof(dc->n_distinct), 0, s);
     fill_u32(&dc->out_count, 1, 0, s);
+    cc.use_flags = hc.n_flagged != 0;
     prof_begin(c, FAST_LSH_STAGE_PAIRS);
     launch_pairs_chunk(pa, marks, t, cc, s);
     prof_end(c);

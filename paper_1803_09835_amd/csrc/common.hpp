@@ -53,25 +53,19 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
 
 // --------------------------------------------------------------------------
 // Sub-key rows.  Each fingerprint carries, per group of tables, a row of
-// 15-bit sub-keys (the low bits of its mixed band key in each table of the
-// group) packed LSB-first, field k at bit 15k, in a row of row_dw dwords
-// (row_dw a multiple of 4, so a row is read with 16-byte loads; 34 tables
-// fit a 64-byte row).  Equal band keys give equal sub-keys.
+// 16-bit sub-keys (the low bits of its mixed band key in each table of the
+// group), field k in bits [16k, 16k+16) of the row, in row_dw dwords.
+// Equal band keys give equal sub-keys.
 // --------------------------------------------------------------------------
-constexpr uint32_t kSubBits = 15;
+constexpr uint32_t kSubBits = 16;
 constexpr uint32_t kSubMask = (1u << kSubBits) - 1;
 
-__host__ __device__ constexpr uint32_t row_dwords(uint32_t tables) {
-  return 4 * ((kSubBits * tables + 127) / 128);
-}
+__host__ __device__ constexpr uint32_t row_dwords(uint32_t tables) { return (kSubBits * tables + 31) / 32; }
 __host__ __device__ constexpr uint32_t row_fields(uint32_t dwords) { return 32 * dwords / kSubBits; }
 
-// Field k of the (XOR-combined or plain) row r.
+// Field k of the row r.
 __device__ __forceinline__ uint32_t row_field(const uint32_t* r, uint32_t k) {
-  const uint32_t bit = kSubBits * k, w = bit >> 5, sh = bit & 31;
-  uint32_t v = r[w] >> sh;
-  if (sh > 32 - kSubBits) v |= r[w + 1] << (32 - sh);
-  return v & kSubMask;
+  return (r[k >> 1] >> (16 * (k & 1))) & kSubMask;
 }
 
 // --------------------------------------------------------------------------
@@ -99,7 +93,7 @@ struct SigArgs {
   uint64_t* mkeys;       // [table_count][n] fmix64(band key), or nullptr
   uint32_t* rows;        // sub-key rows [G][n][row_dw], or nullptr
   uint32_t tables_per_group;
-  uint32_t row_dw;       // dwords per row (a multiple of 4)
+  uint32_t row_dw;       // dwords per row
   int* err;              // set to 1 on an empty row or an index >= dim
 };
 
@@ -145,8 +139,9 @@ struct PairArgs {
 
 struct ChunkCfg {
   uint32_t chunk;     // positions per workgroup (buckets starting there)
-  uint32_t memb_max;  // chunk + small_max - 1: most members staged
+  uint32_t span;      // chunk + small_max - 1: positions whose rows may be staged
   uint32_t rswl;      // LDS row stride in dwords (odd)
+  uint32_t use_flags; // 0 when no fingerprint is excluded
 };
 
 struct TileUnit {

@@ -98,32 +98,30 @@ struct RowReg {
     }
     (void)rsw;
   }
-  // Number of equal sub-keys (15-bit fields) against another row.
+  // Number of equal 16-bit sub-keys against another row.
   __device__ __forceinline__ uint32_t eq(const uint32_t* other, uint32_t rsw) const {
     uint32_t e = 0;
     if (RSW > 0) {
-      uint32_t x[kW + 1];
 #pragma unroll
-      for (int k = 0; k < kW; ++k) x[k] = w[k] ^ other[k];
-      x[kW] = 0;
-#pragma unroll
-      for (uint32_t f = 0; f < row_fields(kW); ++f) e += row_field(x, f) == 0;
+      for (int k = 0; k < kW; ++k) e += eq2(w[k], other[k]);
     } else {
-      const uint32_t nf = row_fields(rsw);
-      for (uint32_t f = 0; f < nf; ++f) e += row_field(lds, f) == row_field(other, f);
+#pragma unroll 4
+      for (uint32_t k = 0; k < rsw; ++k) e += eq2(lds[k], other[k]);
     }
     return e;
+  }
+  __device__ __forceinline__ static uint32_t eq2(uint32_t a, uint32_t b) {
+    return (uint32_t)((uint16_t)a == (uint16_t)b) + (uint32_t)((a >> 16) == (b >> 16));
   }
   // Equal sub-keys in fields below `u` (one group holding every table).
   __device__ __forceinline__ uint32_t eq_below(const uint32_t* other, uint32_t rsw, uint32_t u) const {
     uint32_t e = 0;
     if (RSW > 0) {
-      uint32_t x[kW + 1];
 #pragma unroll
-      for (int k = 0; k < kW; ++k) x[k] = w[k] ^ other[k];
-      x[kW] = 0;
-#pragma unroll
-      for (uint32_t f = 0; f < row_fields(kW); ++f) e += (f < u) && row_field(x, f) == 0;
+      for (int k = 0; k < kW; ++k) {
+        const uint32_t a = w[k], b = other[k];
+        e += (2u * k < u && (uint16_t)a == (uint16_t)b) + (2u * k + 1 < u && (a >> 16) == (b >> 16));
+      }
     } else {
       for (uint32_t f = 0; f < u; ++f) e += row_field(lds, f) == row_field(other, f);
     }
@@ -180,18 +178,6 @@ __device__ __forceinline__ T block_scan_excl(T v, T* ws, T* total) {
   return add + inc - v;
 }
 
-// Copy one row (rsw dwords, 16-byte aligned in HBM) into LDS.
-__device__ __forceinline__ void stage_row(const uint32_t* src, uint32_t* dst, uint32_t rsw) {
-  const uint4* s4 = reinterpret_cast<const uint4*>(src);
-  for (uint32_t q = 0; q < rsw / 4; ++q) {
-    const uint4 v = s4[q];
-    dst[4 * q] = v.x;
-    dst[4 * q + 1] = v.y;
-    dst[4 * q + 2] = v.z;
-    dst[4 * q + 3] = v.w;
-  }
-}
-
 // Last index b in [0, cnt) with arr[b] <= key (arr ascending, arr[0] <= key).
 __device__ __forceinline__ uint32_t last_le(const uint32_t* arr, uint32_t cnt, uint32_t key) {
   uint32_t L = 0, R = cnt;
@@ -212,59 +198,63 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
 
 // Small buckets of one table, found from the marks of a chunk of positions:
 // every bucket that starts in [p0, p0 + chunk) is handled by this
-// workgroup.  Members and rows are staged in LDS in parallel; then every
-// thread walks a contiguous range of the workgroup's pairs (row-major within
-// each bucket), keeping the left row in registers.
+// workgroup.  Ids of the positions [p0, p0 + span) and the marks are loaded
+// side by side; the rows of member positions are then staged with
+// consecutive lanes on consecutive dwords; finally every thread walks a
+// contiguous range of the workgroup's pairs (row-major within each bucket),
+// keeping the left row in registers.
 template <int RSW>
 __global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* marks_all, ChunkCfg cfg) {
   extern __shared__ uint32_t smem[];
-  uint32_t* lrows = smem;                             // memb_max * rswl
-  uint32_t* lids = lrows + cfg.memb_max * cfg.rswl;   // memb_max
-  uint32_t* hpos = lids + cfg.memb_max;               // chunk: head position offset
-  uint32_t* lpre = hpos + cfg.chunk;                  // chunk + 1: member prefix
-  uint32_t* bpof = lpre + cfg.chunk + 1;              // chunk + 1: pair prefix
+  uint32_t* lrows = smem;                          // span * rswl
+  uint32_t* lids = lrows + cfg.span * cfg.rswl;    // span: id per position (kDead if excluded)
+  uint32_t* hpos = lids + cfg.span;                // chunk: bucket start | size << 16
+  uint32_t* bpof = hpos + cfg.chunk;               // chunk + 1: pair prefix
+  uint8_t* memb = reinterpret_cast<uint8_t*>(bpof + cfg.chunk + 1);  // span: member of a bucket here
   __shared__ uint32_t ws[8];
   const uint32_t tid = threadIdx.x;
   const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
   const uint32_t seg = blockIdx.y;
   const uint64_t p0 = (uint64_t)blockIdx.x * cfg.chunk;
   const uint32_t cnt = (uint32_t)min((uint64_t)cfg.chunk, a.n - p0);
+  const uint32_t span = (uint32_t)min((uint64_t)cfg.span, a.n - p0);
   const uint8_t* marks = marks_all + (uint64_t)seg * a.n + p0;
   const uint32_t* order = a.order + (uint64_t)seg * a.n + p0;
 
-  // Heads of the chunk, compacted in position order.
-  uint32_t nh = 0, mcarry = 0, pcarry = 0;
+  for (uint32_t q = tid; q < span; q += kPT) {
+    lids[q] = order[q];
+    memb[q] = 0;
+  }
+  // Heads of the chunk in position order, with their pair offsets.
+  uint32_t nh = 0, pcarry = 0;
   for (uint32_t c0 = 0; c0 < cnt; c0 += kPT) {
     const uint32_t q = c0 + tid;
     const uint32_t size = q < cnt ? marks[q] : 0u;
-    uint32_t th, tm, tp;
+    uint32_t th, tp;
     const uint32_t xh = block_scan_excl<uint32_t>(size ? 1u : 0u, ws, &th);
-    const uint32_t xm = block_scan_excl<uint32_t>(size, ws, &tm);
     const uint32_t xp = block_scan_excl<uint32_t>(size * (size - (size > 0)) / 2, ws, &tp);
     if (size) {
-      hpos[nh + xh] = q;
-      lpre[nh + xh] = mcarry + xm;
+      hpos[nh + xh] = q | (size << 16);
       bpof[nh + xh] = pcarry + xp;
+      for (uint32_t m = 0; m < size; ++m) memb[q + m] = 1;
     }
     nh += th;
-    mcarry += tm;
     pcarry += tp;
   }
-  if (tid == 0) {
-    lpre[nh] = mcarry;
-    bpof[nh] = pcarry;
-  }
+  if (tid == 0) bpof[nh] = pcarry;
   __syncthreads();
   if (nh == 0) return;
-  // Stage member ids (excluded members marked dead) and their rows.
-  const uint32_t M = mcarry;
+  // Rows of member positions; excluded members marked dead.
   const uint32_t g = seg / a.tables_per_group;
   const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
-  for (uint32_t m = tid; m < M; m += kPT) {
-    const uint32_t b = last_le(lpre, nh, m);
-    const uint32_t id = order[hpos[b] + (m - lpre[b])];
-    lids[m] = a.flags[id] != 0 ? kDead : id;
-    stage_row(R + (uint64_t)id * rsw, lrows + m * cfg.rswl, rsw);
+  for (uint32_t idx = tid; idx < span * rsw; idx += kPT) {
+    const uint32_t q = idx / rsw, w = idx - q * rsw;
+    if (memb[q]) lrows[q * cfg.rswl + w] = R[(uint64_t)lids[q] * rsw + w];
+  }
+  if (cfg.use_flags) {
+    __syncthreads();
+    for (uint32_t q = tid; q < span; q += kPT)
+      if (memb[q] && a.flags[lids[q]]) lids[q] = kDead;
   }
   __syncthreads();
   // Pairs: thread tid walks [p, pend).
@@ -276,7 +266,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* 
   const uint32_t pend = min(P, p + per);
   if (p < pend) {
     uint32_t b = last_le(bpof, nh, p);
-    uint32_t base = lpre[b], m = lpre[b + 1] - base;
+    uint32_t base = hpos[b] & 0xFFFFu, m = hpos[b] >> 16;
     uint32_t x, y;
     tri_decode(m, p - bpof[b], x, y);
     uint32_t idx = lids[base + x];
@@ -287,8 +277,8 @@ __global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* 
       if (++y == m) {
         if (++x == m - 1) {
           if (++b >= nh) break;
-          base = lpre[b];
-          m = lpre[b + 1] - base;
+          base = hpos[b] & 0xFFFFu;
+          m = hpos[b] >> 16;
           x = 0;
         }
         y = x + 1;
@@ -347,16 +337,18 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
   uint32_t* idsB = diag ? idsA : idsA + tb_size;
   const uint32_t g = seg / a.tables_per_group;
   const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
-  for (uint32_t q = threadIdx.x; q < na; q += kPT) {
-    const uint32_t id = bid[a0 + q];
-    idsA[q] = id;
-    stage_row(R + (uint64_t)id * rsw, rowsA + q * rswl, rsw);
+  for (uint32_t q = threadIdx.x; q < na; q += kPT) idsA[q] = bid[a0 + q];
+  if (!diag)
+    for (uint32_t q = threadIdx.x; q < nbm; q += kPT) idsB[q] = bid[b0 + q];
+  __syncthreads();
+  for (uint32_t idx = threadIdx.x; idx < na * rsw; idx += kPT) {
+    const uint32_t q = idx / rsw, w = idx - q * rsw;
+    rowsA[q * rswl + w] = R[(uint64_t)idsA[q] * rsw + w];
   }
   if (!diag) {
-    for (uint32_t q = threadIdx.x; q < nbm; q += kPT) {
-      const uint32_t id = bid[b0 + q];
-      idsB[q] = id;
-      stage_row(R + (uint64_t)id * rsw, rowsB + q * rswl, rsw);
+    for (uint32_t idx = threadIdx.x; idx < nbm * rsw; idx += kPT) {
+      const uint32_t q = idx / rsw, w = idx - q * rsw;
+      rowsB[q * rswl + w] = R[(uint64_t)idsB[q] * rsw + w];
     }
   }
   __syncthreads();
@@ -428,7 +420,7 @@ static unsigned grid_for(uint64_t count) {
 }
 
 size_t chunk_smem_bytes(const ChunkCfg& c) {
-  return (size_t)c.memb_max * c.rswl * 4 + (size_t)c.memb_max * 4 + (size_t)c.chunk * 4 + (size_t)(c.chunk + 1) * 8;
+  return (size_t)c.span * c.rswl * 4 + (size_t)c.span * 4 + (size_t)(c.chunk + 1) * 8 + c.span + 16;
 }
 
 void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, const ChunkCfg& c, hipStream_t s) {
@@ -436,8 +428,8 @@ void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, con
   const dim3 grid((unsigned)((a.n + c.chunk - 1) / c.chunk), S);
   const size_t smem = chunk_smem_bytes(c);
   switch (a.row_dw) {
-    case 12: hipLaunchKernelGGL((k_pairs_chunk<12>), grid, dim3(kPT), smem, s, a, marks, c); break;
-    case 16: hipLaunchKernelGGL((k_pairs_chunk<16>), grid, dim3(kPT), smem, s, a, marks, c); break;
+    case 10: hipLaunchKernelGGL((k_pairs_chunk<10>), grid, dim3(kPT), smem, s, a, marks, c); break;
+    case 17: hipLaunchKernelGGL((k_pairs_chunk<17>), grid, dim3(kPT), smem, s, a, marks, c); break;
     default: hipLaunchKernelGGL((k_pairs_chunk<0>), grid, dim3(kPT), smem, s, a, marks, c); break;
   }
 }
@@ -454,8 +446,8 @@ void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
   switch (a.row_dw) {
-    case 12: hipLaunchKernelGGL((k_pairs_tile<12>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
-    case 16: hipLaunchKernelGGL((k_pairs_tile<16>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
+    case 10: hipLaunchKernelGGL((k_pairs_tile<10>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
+    case 17: hipLaunchKernelGGL((k_pairs_tile<17>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
     default: hipLaunchKernelGGL((k_pairs_tile<0>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
   }
 }

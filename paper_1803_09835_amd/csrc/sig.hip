@@ -59,8 +59,7 @@ struct KeyBuilder {
 };
 
 // Keys of table u for this lane's fingerprint; the sub-key goes into the
-// lane's row under construction in LDS (`my`, row_dw dwords), which is
-// written out with 16-byte stores when the last table of its group is done.
+// lane's row under construction in LDS (`my`, row_dw dwords).
 __device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint64_t i, uint32_t u, bool live,
                                             uint32_t* my) {
   const uint32_t tab = a.table_begin + u;
@@ -69,20 +68,31 @@ __device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint
     const uint64_t m = fmix64(key);
     if (live && a.mkeys) a.mkeys[(uint64_t)u * a.n + i] = m;
     if (a.rows) {
-      const uint32_t g = tab / a.tables_per_group, slot = tab - g * a.tables_per_group;
+      const uint32_t slot = tab % a.tables_per_group;
       if (slot == 0)
         for (uint32_t w = 0; w < a.row_dw; ++w) my[w] = 0;
-      const uint32_t f = (uint32_t)m & kSubMask;
-      const uint32_t bit = kSubBits * slot, w = bit >> 5, sh = bit & 31;
-      my[w] |= f << sh;
-      if (sh > 32 - kSubBits) my[w + 1] |= f >> (32 - sh);
-      if (live && (slot + 1 == a.tables_per_group || u + 1 == a.table_count)) {
-        uint4* dst = reinterpret_cast<uint4*>(a.rows + ((uint64_t)g * a.n + i) * a.row_dw);
-        for (uint32_t q = 0; q < a.row_dw / 4; ++q)
-          dst[q] = make_uint4(my[4 * q], my[4 * q + 1], my[4 * q + 2], my[4 * q + 3]);
-      }
+      my[slot >> 1] |= ((uint32_t)m & kSubMask) << (16 * (slot & 1));
     }
   }
+}
+
+// After the last table of a group: the workgroup's 256 rows of that group
+// are contiguous in HBM; copy them out with consecutive lanes on
+// consecutive dwords.
+__device__ __forceinline__ void flush_rows(const SigArgs& a, uint32_t u, const uint32_t* srow) {
+  const uint32_t tab = a.table_begin + u;
+  const uint32_t slot = tab % a.tables_per_group;
+  if (!a.rows || (slot + 1 != a.tables_per_group && u + 1 != a.table_count)) return;
+  __syncthreads();
+  const uint32_t g = tab / a.tables_per_group;
+  const uint64_t i0 = (uint64_t)blockIdx.x * 256;
+  const uint32_t live = (uint32_t)min((uint64_t)256, a.n - i0);
+  uint32_t* dst = a.rows + ((uint64_t)g * a.n + i0) * a.row_dw;
+  for (uint32_t idx = threadIdx.x; idx < live * a.row_dw; idx += 256) {
+    const uint32_t r = idx / a.row_dw, w = idx - r * a.row_dw;
+    dst[idx] = srow[r * (a.row_dw + 1) + w];
+  }
+  __syncthreads();
 }
 
 // CAP: most indices a row may hold (rows shorter than CAP are padded with
@@ -156,6 +166,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 
       }
     }
     store_table(a, kb.key, i, u, live, my);
+    flush_rows(a, u, srow);
   }
 }
 
@@ -204,6 +215,7 @@ __global__ __launch_bounds__(256) void k_sig_long(SigArgs a) {
       }
     }
     store_table(a, kb.key, i, u, live, my);
+    flush_rows(a, u, srow);
   }
 }
 
