@@ -178,6 +178,29 @@ __device__ __forceinline__ T block_scan_excl(T v, T* ws, T* total) {
   return add + inc - v;
 }
 
+// Copy one row of sub-keys from HBM into LDS; with a compile-time length all
+// its loads are issued before the first store.
+template <int RSW>
+__device__ __forceinline__ void stage_row(const uint32_t* src, uint32_t* dst, uint32_t rsw) {
+  if (RSW > 0) {
+    uint32_t v[RSW > 0 ? RSW : 1];
+#pragma unroll
+    for (int w = 0; w < (RSW > 0 ? RSW : 1); ++w) v[w] = src[w];
+#pragma unroll
+    for (int w = 0; w < (RSW > 0 ? RSW : 1); ++w) dst[w] = v[w];
+  } else {
+    uint32_t w = 0;
+    for (; w + 4 <= rsw; w += 4) {
+      const uint32_t v0 = src[w], v1 = src[w + 1], v2 = src[w + 2], v3 = src[w + 3];
+      dst[w] = v0;
+      dst[w + 1] = v1;
+      dst[w + 2] = v2;
+      dst[w + 3] = v3;
+    }
+    for (; w < rsw; ++w) dst[w] = src[w];
+  }
+}
+
 // Last index b in [0, cnt) with arr[b] <= key (arr ascending, arr[0] <= key).
 __device__ __forceinline__ uint32_t last_le(const uint32_t* arr, uint32_t cnt, uint32_t key) {
   uint32_t L = 0, R = cnt;
@@ -247,10 +270,8 @@ __global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* 
   // Rows of member positions; excluded members marked dead.
   const uint32_t g = seg / a.tables_per_group;
   const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
-  for (uint32_t idx = tid; idx < span * rsw; idx += kPT) {
-    const uint32_t q = idx / rsw, w = idx - q * rsw;
-    if (memb[q]) lrows[q * cfg.rswl + w] = R[(uint64_t)lids[q] * rsw + w];
-  }
+  for (uint32_t q = tid; q < span; q += kPT)
+    if (memb[q]) stage_row<RSW>(R + (uint64_t)lids[q] * rsw, lrows + q * cfg.rswl, rsw);
   if (cfg.use_flags) {
     __syncthreads();
     for (uint32_t q = tid; q < span; q += kPT)
@@ -341,16 +362,9 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
   if (!diag)
     for (uint32_t q = threadIdx.x; q < nbm; q += kPT) idsB[q] = bid[b0 + q];
   __syncthreads();
-  for (uint32_t idx = threadIdx.x; idx < na * rsw; idx += kPT) {
-    const uint32_t q = idx / rsw, w = idx - q * rsw;
-    rowsA[q * rswl + w] = R[(uint64_t)idsA[q] * rsw + w];
-  }
-  if (!diag) {
-    for (uint32_t idx = threadIdx.x; idx < nbm * rsw; idx += kPT) {
-      const uint32_t q = idx / rsw, w = idx - q * rsw;
-      rowsB[q * rswl + w] = R[(uint64_t)idsB[q] * rsw + w];
-    }
-  }
+  for (uint32_t q = threadIdx.x; q < na; q += kPT) stage_row<RSW>(R + (uint64_t)idsA[q] * rsw, rowsA + q * rswl, rsw);
+  if (!diag)
+    for (uint32_t q = threadIdx.x; q < nbm; q += kPT) stage_row<RSW>(R + (uint64_t)idsB[q] * rsw, rowsB + q * rswl, rsw);
   __syncthreads();
   const uint32_t pad = group_pad(a, seg, rsw);
   PairTally tl{0ull, 0ull};
