@@ -1,6 +1,7 @@
 // C-ABI entry points and host orchestration of the fast_lsh library.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -28,6 +29,8 @@ void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t nbins, uint6
 // pairs.hip
 size_t chunk_smem_bytes(const ChunkCfg& c);
 void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, const ChunkCfg& c, hipStream_t s);
+void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, uint32_t use_flags,
+                       hipStream_t s);
 void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, const uint64_t* cofs, uint32_t* ids,
                         uint32_t* cnt, hipStream_t s);
 void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits, const uint4* big,
@@ -614,7 +617,10 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
     fill_u32(&dc->out_count, 1, 0, s);
     cc.use_flags = hc.n_flagged != 0;
     prof_begin(c, FAST_LSH_STAGE_PAIRS);
-    launch_pairs_chunk(pa, marks, t, cc, s);
+    if (getenv("FAST_LSH_PAIRS_BLOCK"))
+      launch_pairs_chunk(pa, marks, t, cc, s);
+    else
+      launch_pairs_wave(pa, marks, t, cc.rswl, cc.use_flags, s);
     prof_end(c);
     LAUNCHCK();
     if (hc.big_count) {

@@ -311,6 +311,96 @@ __global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* 
   flush_tally(a, tl);
 }
 
+// Wave-per-chunk variant: one 64-lane workgroup handles the buckets that
+// start in 64 consecutive positions.  Heads and pair offsets come from
+// ballots and lane shuffles, so the only barriers are the LDS hand-offs of
+// a single wave; many such waves per CU overlap their loads.
+template <int RSW>
+__global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl,
+                                                   uint32_t use_flags) {
+  constexpr uint32_t kSpan = 64 + 63;  // small buckets hold at most 64 members
+  extern __shared__ uint32_t smem[];
+  uint32_t* lrows = smem;                   // kSpan * rswl
+  uint32_t* lids = lrows + kSpan * rswl;    // kSpan
+  uint32_t* hinfo = lids + kSpan;           // 64: head position | size << 16
+  uint32_t* bpof = hinfo + 64;              // 65: pair prefix
+  const uint32_t lane = threadIdx.x;
+  const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
+  const uint32_t seg = blockIdx.y;
+  const uint64_t p0 = (uint64_t)blockIdx.x * 64;
+  const uint64_t left = a.n - p0;
+  const uint8_t* marks = marks_all + (uint64_t)seg * a.n + p0;
+  const uint32_t* order = a.order + (uint64_t)seg * a.n + p0;
+
+  const uint32_t size = lane < left ? marks[lane] : 0u;
+  if (lane < left) lids[lane] = order[lane];
+  if (64 + lane < left && lane < kSpan - 64) lids[64 + lane] = order[64 + lane];
+  const uint64_t heads = __ballot(size != 0);
+  if (heads == 0) return;
+  const uint64_t lt = __lanemask_lt();
+  const uint32_t hidx = __popcll(heads & lt);
+  const uint32_t nh = __popcll(heads);
+  const uint32_t pc = size * (size - (size > 0)) / 2;
+  uint32_t inc = pc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += y;
+  }
+  const uint32_t P = __shfl(inc, 63, 64);
+  if (size) {
+    hinfo[hidx] = lane | (size << 16);
+    bpof[hidx] = inc - pc;
+  }
+  if (lane == 0) bpof[nh] = P;
+  // Member positions: q belongs to the last head h <= q when q < h + size(h).
+  const uint32_t g = seg / a.tables_per_group;
+  const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t r = 0; r < 2; ++r) {
+    const uint32_t q = lane + 64 * r;
+    const uint64_t upto = q >= 63 ? heads : (heads & ((2ull << q) - 1));
+    const uint32_t h = upto ? 63 - (uint32_t)__clzll(upto) : 0u;
+    const uint32_t hs = __shfl(size, h, 64);  // every lane active here
+    if (upto && q < kSpan && q < h + hs) {
+      const uint32_t id = lids[q];
+      stage_row<RSW>(R + (uint64_t)id * rsw, lrows + q * rswl, rsw);
+      if (use_flags && a.flags[id]) lids[q] = kDead;
+    }
+  }
+  __syncthreads();
+  PairTally tl{0ull, 0ull};
+  const uint32_t pad = group_pad(a, seg, rsw);
+  const uint32_t per = (P + 63) / 64;
+  uint32_t p = lane * per;
+  const uint32_t pend = min(P, p + per);
+  if (p < pend) {
+    uint32_t b = last_le(bpof, nh, p);
+    uint32_t base = hinfo[b] & 0xFFFFu, m = hinfo[b] >> 16;
+    uint32_t x, y;
+    tri_decode(m, p - bpof[b], x, y);
+    uint32_t idx = lids[base + x];
+    RowReg<RSW> rx;
+    rx.load(lrows + (base + x) * rswl, rsw);
+    for (; p < pend; ++p) {
+      visit_pair<RSW>(a, seg, idx, lids[base + y], rx, lrows + (base + y) * rswl, rsw, pad, tl);
+      if (++y == m) {
+        if (++x == m - 1) {
+          if (++b >= nh) break;
+          base = hinfo[b] & 0xFFFFu;
+          m = hinfo[b] >> 16;
+          x = 0;
+        }
+        y = x + 1;
+        idx = lids[base + x];
+        rx.load(lrows + (base + x) * rswl, rsw);
+      }
+    }
+  }
+  flush_tally(a, tl);
+}
+
 // Unflagged members of each large bucket, compacted in order.
 __global__ __launch_bounds__(kPT) void k_compact_big(PairArgs a, const uint4* big, const uint64_t* cofs,
                                                      uint32_t* ids, uint32_t* cnt) {
@@ -435,6 +525,18 @@ static unsigned grid_for(uint64_t count) {
 
 size_t chunk_smem_bytes(const ChunkCfg& c) {
   return (size_t)c.span * c.rswl * 4 + (size_t)c.span * 4 + (size_t)(c.chunk + 1) * 8 + c.span + 16;
+}
+
+void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, uint32_t use_flags,
+                       hipStream_t s) {
+  if (a.n == 0) return;
+  const dim3 grid((unsigned)((a.n + 63) / 64), S);
+  const size_t smem = (size_t)(127 * rswl + 127 + 64 + 65) * 4;
+  switch (a.row_dw) {
+    case 10: hipLaunchKernelGGL((k_pairs_wave<10>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
+    case 17: hipLaunchKernelGGL((k_pairs_wave<17>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
+    default: hipLaunchKernelGGL((k_pairs_wave<0>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
+  }
 }
 
 void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, const ChunkCfg& c, hipStream_t s) {
