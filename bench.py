@@ -31,10 +31,14 @@ HBM_PEAK_GBS = 8000.0
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 INT_PEAK_TOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0  # 39.32 T int32 lane-ops/s
 
-# Integer operations one hash evaluation needs on a 32-bit ALU: the 64-bit
-# multiply-add a*x + b, two for the Mersenne fold (shift, add), two for the
-# canonical residue (subtract, select), and one compare per tracked extreme.
-OPS_PER_EVAL = {0: 6, 1: 7}  # MinHash, Min-Max
+# Algorithmic int32 operations per hash evaluation h(x) = (a x + b) mod (2^31-1)
+# with its extreme updates: one 32x32->64-bit multiply-add, two for the
+# Mersenne fold (shift, add), two for the canonical residue (subtract,
+# unsigned min), and the extreme update with three-input min/max, which folds
+# two new values per instruction: 1/2 per tracked extreme.  (The kernel also
+# unpacks two 16-bit indices per register: half an operation per evaluation
+# that is not counted here.)
+OPS_PER_EVAL = {0: 5.5, 1: 6.0}  # MinHash, Min-Max
 
 
 def parse():

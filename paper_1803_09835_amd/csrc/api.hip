@@ -27,8 +27,6 @@ void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s);
 void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t nbins, uint64_t* tk, uint32_t* tv,
                    hipStream_t s);
 // pairs.hip
-size_t chunk_smem_bytes(const ChunkCfg& c);
-void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, const ChunkCfg& c, hipStream_t s);
 void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, uint32_t use_flags,
                        hipStream_t s);
 void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, const uint64_t* cofs, uint32_t* ids,
@@ -525,16 +523,10 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
 
   // Pair stage: buckets of at most smax members are marked in place and
   // handled by chunks of positions; larger ones go to the tiled kernel.
+  // Buckets of at most smax members are marked in place and handled by the
+  // wave-per-chunk kernel; larger ones go to the tiled kernel.
   const uint32_t smax = 64;
-  ChunkCfg cc;
-  cc.rswl = pl.rsw | 1u;
-  cc.use_flags = 1;
-  cc.chunk = 512;
-  for (;;) {
-    cc.span = cc.chunk + smax - 1;
-    if (chunk_smem_bytes(cc) <= 40960 || cc.chunk <= 32) break;
-    cc.chunk >>= 1;
-  }
+  const uint32_t rswl = pl.rsw | 1u;
   const uint64_t cap_big = tn / (smax + 1) + 1, cap_bin = tn / 129 + t + 1;  // oversized bins and mixed bins above 128 elements
   uint4 *bdesc, *bins;
   uint8_t* marks;
@@ -615,12 +607,8 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
     pa.out_cap = (uint32_t)std::min<uint64_t>(out_cap, 0xFFFFFFFFull);
     fill_u8(reinterpret_cast<uint8_t*>(dc->e_voted), sizeof(dc->e_voted) + sizeof(dc->n_distinct), 0, s);
     fill_u32(&dc->out_count, 1, 0, s);
-    cc.use_flags = hc.n_flagged != 0;
     prof_begin(c, FAST_LSH_STAGE_PAIRS);
-    if (getenv("FAST_LSH_PAIRS_BLOCK"))
-      launch_pairs_chunk(pa, marks, t, cc, s);
-    else
-      launch_pairs_wave(pa, marks, t, cc.rswl, cc.use_flags, s);
+    launch_pairs_wave(pa, marks, t, rswl, hc.n_flagged != 0, s);
     prof_end(c);
     LAUNCHCK();
     if (hc.big_count) {
@@ -636,7 +624,6 @@ static int search_impl(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
       LAUNCHCK();
       std::vector<uint32_t> hcnt(hc.big_count);
       RC(d2h(c, hcnt.data(), bcnt, hc.big_count));
-      const uint32_t rswl = pl.rsw | 1u;
       // tile edge: a power of two with two tiles of rows and ids within 64 KB of LDS
       const uint32_t fit = 65536 / (8 * rswl + 8);
       uint32_t tb = 256;

@@ -137,13 +137,6 @@ struct PairArgs {
   unsigned long long* n_distinct;  // [kSpread]
 };
 
-struct ChunkCfg {
-  uint32_t chunk;     // positions per workgroup (buckets starting there)
-  uint32_t span;      // chunk + small_max - 1: positions whose rows may be staged
-  uint32_t rswl;      // LDS row stride in dwords (odd)
-  uint32_t use_flags; // 0 when no fingerprint is excluded
-};
-
 struct TileUnit {
   uint32_t bucket, ta, tb, pad;
 };

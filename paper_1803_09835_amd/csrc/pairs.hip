@@ -219,100 +219,13 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
   return row_fields(rsw) - valid;
 }
 
-// Small buckets of one table, found from the marks of a chunk of positions:
-// every bucket that starts in [p0, p0 + chunk) is handled by this
-// workgroup.  Ids of the positions [p0, p0 + span) and the marks are loaded
-// side by side; the rows of member positions are then staged with
-// consecutive lanes on consecutive dwords; finally every thread walks a
-// contiguous range of the workgroup's pairs (row-major within each bucket),
-// keeping the left row in registers.
-template <int RSW>
-__global__ __launch_bounds__(kPT) void k_pairs_chunk(PairArgs a, const uint8_t* marks_all, ChunkCfg cfg) {
-  extern __shared__ uint32_t smem[];
-  uint32_t* lrows = smem;                          // span * rswl
-  uint32_t* lids = lrows + cfg.span * cfg.rswl;    // span: id per position (kDead if excluded)
-  uint32_t* hpos = lids + cfg.span;                // chunk: bucket start | size << 16
-  uint32_t* bpof = hpos + cfg.chunk;               // chunk + 1: pair prefix
-  uint8_t* memb = reinterpret_cast<uint8_t*>(bpof + cfg.chunk + 1);  // span: member of a bucket here
-  __shared__ uint32_t ws[8];
-  const uint32_t tid = threadIdx.x;
-  const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
-  const uint32_t seg = blockIdx.y;
-  const uint64_t p0 = (uint64_t)blockIdx.x * cfg.chunk;
-  const uint32_t cnt = (uint32_t)min((uint64_t)cfg.chunk, a.n - p0);
-  const uint32_t span = (uint32_t)min((uint64_t)cfg.span, a.n - p0);
-  const uint8_t* marks = marks_all + (uint64_t)seg * a.n + p0;
-  const uint32_t* order = a.order + (uint64_t)seg * a.n + p0;
-
-  for (uint32_t q = tid; q < span; q += kPT) {
-    lids[q] = order[q];
-    memb[q] = 0;
-  }
-  // Heads of the chunk in position order, with their pair offsets.
-  uint32_t nh = 0, pcarry = 0;
-  for (uint32_t c0 = 0; c0 < cnt; c0 += kPT) {
-    const uint32_t q = c0 + tid;
-    const uint32_t size = q < cnt ? marks[q] : 0u;
-    uint32_t th, tp;
-    const uint32_t xh = block_scan_excl<uint32_t>(size ? 1u : 0u, ws, &th);
-    const uint32_t xp = block_scan_excl<uint32_t>(size * (size - (size > 0)) / 2, ws, &tp);
-    if (size) {
-      hpos[nh + xh] = q | (size << 16);
-      bpof[nh + xh] = pcarry + xp;
-      for (uint32_t m = 0; m < size; ++m) memb[q + m] = 1;
-    }
-    nh += th;
-    pcarry += tp;
-  }
-  if (tid == 0) bpof[nh] = pcarry;
-  __syncthreads();
-  if (nh == 0) return;
-  // Rows of member positions; excluded members marked dead.
-  const uint32_t g = seg / a.tables_per_group;
-  const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
-  for (uint32_t q = tid; q < span; q += kPT)
-    if (memb[q]) stage_row<RSW>(R + (uint64_t)lids[q] * rsw, lrows + q * cfg.rswl, rsw);
-  if (cfg.use_flags) {
-    __syncthreads();
-    for (uint32_t q = tid; q < span; q += kPT)
-      if (memb[q] && a.flags[lids[q]]) lids[q] = kDead;
-  }
-  __syncthreads();
-  // Pairs: thread tid walks [p, pend).
-  PairTally tl{0ull, 0ull};
-  const uint32_t P = pcarry;
-  const uint32_t pad = group_pad(a, seg, rsw);
-  const uint32_t per = (P + kPT - 1) / kPT;
-  uint32_t p = tid * per;
-  const uint32_t pend = min(P, p + per);
-  if (p < pend) {
-    uint32_t b = last_le(bpof, nh, p);
-    uint32_t base = hpos[b] & 0xFFFFu, m = hpos[b] >> 16;
-    uint32_t x, y;
-    tri_decode(m, p - bpof[b], x, y);
-    uint32_t idx = lids[base + x];
-    RowReg<RSW> rx;
-    rx.load(lrows + (base + x) * cfg.rswl, rsw);
-    for (; p < pend; ++p) {
-      visit_pair<RSW>(a, seg, idx, lids[base + y], rx, lrows + (base + y) * cfg.rswl, rsw, pad, tl);
-      if (++y == m) {
-        if (++x == m - 1) {
-          if (++b >= nh) break;
-          base = hpos[b] & 0xFFFFu;
-          m = hpos[b] >> 16;
-          x = 0;
-        }
-        y = x + 1;
-        idx = lids[base + x];
-        rx.load(lrows + (base + x) * cfg.rswl, rsw);
-      }
-    }
-  }
-  flush_tally(a, tl);
-}
-
-// Wave-per-chunk variant: one 64-lane workgroup handles the buckets that
-// start in 64 consecutive positions.  Heads and pair offsets come from
+// Small buckets of one table: one 64-lane workgroup handles the buckets that
+// start in 64 consecutive positions (a bucket marked at position q holds the
+// ids at positions q .. q+size-1).  Ids and marks are loaded side by side,
+// the member rows are staged in LDS with each lane issuing a whole row's
+// loads at once, and every lane then walks a contiguous range of the
+// chunk's pairs (row-major within each bucket) with the left row in
+// registers.  Heads and pair offsets come from
 // ballots and lane shuffles, so the only barriers are the LDS hand-offs of
 // a single wave; many such waves per CU overlap their loads.
 template <int RSW>
@@ -523,10 +436,6 @@ static unsigned grid_for(uint64_t count) {
   return (unsigned)(b == 0 ? 1 : (b < 65535 ? b : 65535));
 }
 
-size_t chunk_smem_bytes(const ChunkCfg& c) {
-  return (size_t)c.span * c.rswl * 4 + (size_t)c.span * 4 + (size_t)(c.chunk + 1) * 8 + c.span + 16;
-}
-
 void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, uint32_t use_flags,
                        hipStream_t s) {
   if (a.n == 0) return;
@@ -536,17 +445,6 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
     case 10: hipLaunchKernelGGL((k_pairs_wave<10>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
     case 17: hipLaunchKernelGGL((k_pairs_wave<17>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
     default: hipLaunchKernelGGL((k_pairs_wave<0>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
-  }
-}
-
-void launch_pairs_chunk(const PairArgs& a, const uint8_t* marks, uint32_t S, const ChunkCfg& c, hipStream_t s) {
-  if (a.n == 0) return;
-  const dim3 grid((unsigned)((a.n + c.chunk - 1) / c.chunk), S);
-  const size_t smem = chunk_smem_bytes(c);
-  switch (a.row_dw) {
-    case 10: hipLaunchKernelGGL((k_pairs_chunk<10>), grid, dim3(kPT), smem, s, a, marks, c); break;
-    case 17: hipLaunchKernelGGL((k_pairs_chunk<17>), grid, dim3(kPT), smem, s, a, marks, c); break;
-    default: hipLaunchKernelGGL((k_pairs_chunk<0>), grid, dim3(kPT), smem, s, a, marks, c); break;
   }
 }
 
