@@ -151,8 +151,16 @@ int fast_lsh_make_hash(uint64_t seed, uint32_t n_funcs, uint32_t *a, uint32_t *b
 int fast_lsh_signatures(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *fps,
                         uint32_t table_begin, uint32_t table_count, uint64_t *keys, uint32_t *sigs);
 
-/* Flags for fast_lsh_search_ex. */
-enum { FAST_LSH_WANT_DISTINCT = 1 };
+/* Flags for fast_lsh_search_ex and fast_lsh_search_batched.
+ *   FAST_LSH_WANT_DISTINCT  also compute stats n_distinct (costs a full
+ *                           comparison of every candidate pair);
+ *   FAST_LSH_USE_GRAPH      run the fixed-shape part of the search
+ *                           (signatures through the small-bucket pair
+ *                           kernel) as one captured HIP graph, replayed on
+ *                           later calls whose shapes, device pointers and
+ *                           workspace are unchanged.  Results are identical
+ *                           with and without it. */
+enum { FAST_LSH_WANT_DISTINCT = 1, FAST_LSH_USE_GRAPH = 2 };
 
 /* Full similarity search (section 6.1 "Search"; filters of sections 6.5 and
  * 7.1): writes the sorted pairs to out_i, out_j (device uint32) and
@@ -172,11 +180,61 @@ int fast_lsh_search_ex(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_
                        const fast_lsh_filter *filter, uint32_t flags, uint32_t *out_i, uint32_t *out_j,
                        uint8_t *out_votes, uint64_t capacity, fast_lsh_stats *stats);
 
+/* Largest number of stations in one batched search. */
+enum { FAST_LSH_MAX_STATIONS = 16 };
+
+/* Batched search: the search of fast_lsh_search applied to each of
+ * n_stations independent stations (the paper searches each station's
+ * fingerprints on their own, section 7 and section 8 data sets), run as one
+ * pass of every kernel over all stations.  Pairs never mix stations, and the
+ * occurrence filter uses each station's own n.
+ *   stations         host array of n_stations fingerprint sets (1..16);
+ *   out_i, out_j     device uint32: pairs of station 0, then station 1, ...,
+ *   out_votes        each station's pairs sorted by (i, j), ids local to the
+ *                    station (0 = its first fingerprint);
+ *   station_offsets  host, n_stations + 1 entries (may be NULL): station s
+ *                    owns output entries [offsets[s], offsets[s+1]);
+ *   per_station      host, n_stations entries (may be NULL): each station's
+ *                    counters, as fast_lsh_search would report them.
+ * The stations' total n must be below 2^31, and with more than one station
+ * the band key must leave its top 4 bits free for the station tag
+ * (ceil(log2 dim) * r <= 60).  Capacity overflow behaves as in
+ * fast_lsh_search (E_CAPACITY, offsets and counters still written). */
+int fast_lsh_search_batched(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, uint32_t n_stations,
+                            const fast_lsh_fps *stations, const fast_lsh_filter *filter, uint32_t flags,
+                            uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes, uint64_t capacity,
+                            uint64_t *station_offsets, fast_lsh_stats *per_station);
+
 /* Copy the last search's result (kept in the context) into caller buffers
  * with room for `capacity` pairs.  E_CAPACITY if it still does not fit,
- * E_INVALID if there is no result. */
+ * E_INVALID if there is no result.  Ids are local to their station. */
 int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes,
                          uint64_t capacity);
+
+/* Launch shapes.  They change speed only: every choice gives the same output
+ * bytes and counters.
+ *   radix_tile    elements per workgroup of the grouping passes: 16384,
+ *                 8192 or 4096 (0 keeps the current value);
+ *   bucket_chunk  sorted positions per workgroup of the bucket kernel:
+ *                 256..1792, a multiple of 256 (0 keeps the current value);
+ *   autotune      1: on the first search of each shape (stations, total n,
+ *                 tables, bin bits) time every radix tile and bucket chunk
+ *                 on that search's own data, keep the fastest for later
+ *                 searches of that shape (the fixed values above are then
+ *                 ignored); 0: use the fixed values. */
+typedef struct {
+  uint32_t radix_tile;
+  uint32_t bucket_chunk;
+  uint32_t autotune;
+  uint32_t reserved;
+} fast_lsh_config;
+
+/* Set the launch shapes of later searches (defaults: 16384, 1536, no
+ * autotune).  E_INVALID for a value outside the lists above. */
+int fast_lsh_configure(fast_lsh_ctx *ctx, const fast_lsh_config *config);
+
+/* The launch shapes the last search used (after autotuning, its choice). */
+int fast_lsh_config_used(fast_lsh_ctx *ctx, fast_lsh_config *out);
 
 /* Stage timing.  While enabled, the context records a pair of HIP events on
  * its stream around every kernel launch of the stages below and accumulates
@@ -184,12 +242,14 @@ int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, ui
  * counters.  Stages: */
 enum {
   FAST_LSH_STAGE_SIGNATURES = 0, /* signature kernel                          */
-  FAST_LSH_STAGE_GROUP = 1,      /* the two radix passes that bin every table */
+  FAST_LSH_STAGE_GROUP = 1,      /* the radix passes that bin every table     */
   FAST_LSH_STAGE_BUCKETS = 2,    /* per-bin sort, bucket sizes, filter flags  */
   FAST_LSH_STAGE_BIG_BINS = 3,   /* bins too large for LDS                    */
   FAST_LSH_STAGE_PAIRS = 4,      /* in-bucket pairs and votes, small buckets  */
   FAST_LSH_STAGE_BIG_PAIRS = 5,  /* tiled pairs of large buckets              */
   FAST_LSH_STAGE_OUTPUT = 6,     /* canonical sort of the reported pairs      */
+  FAST_LSH_STAGE_GRAPH = 7,      /* replay of the captured graph (stages 0-4
+                                    together, FAST_LSH_USE_GRAPH only)        */
   FAST_LSH_PROFILE_STAGES = 8
 };
 

@@ -51,6 +51,20 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   return k;
 }
 
+// A bijection of 60-bit words (xor-shifts and odd multipliers modulo 2^60),
+// used when the top four bits of the mixed key hold a station id: keys of
+// one station then stay contiguous after sorting, and equal keys stay equal.
+__device__ __forceinline__ uint64_t mix60(uint64_t k) {
+  constexpr uint64_t M = (1ull << 60) - 1;
+  k &= M;
+  k ^= k >> 31;
+  k = (k * 0xbf58476d1ce4e5b9ull) & M;
+  k ^= k >> 29;
+  k = (k * 0x94d049bb133111ebull) & M;
+  k ^= k >> 32;
+  return k;
+}
+
 // --------------------------------------------------------------------------
 // Sub-key rows.  Each fingerprint carries, per group of tables, a row of
 // 16-bit sub-keys (the low bits of its mixed band key in each table of the
@@ -90,8 +104,12 @@ struct SigArgs {
   const uint32_t* b;     // b
   uint64_t* keys;        // [table_count][n] band keys, or nullptr
   uint32_t* sigs;        // [n][table_count][r] values, or nullptr
-  uint64_t* mkeys;       // [table_count][n] fmix64(band key), or nullptr
-  uint32_t* rows;        // sub-key rows [G][n][row_dw], or nullptr
+  uint64_t* mkeys;       // [table_count][out_stride] mixed keys, or nullptr
+  uint32_t* rows;        // sub-key rows [G][out_stride][row_dw], or nullptr
+  uint64_t out_stride;   // fingerprints per table in mkeys / rows (all stations)
+  uint64_t out_base;     // first position of this station in mkeys / rows
+  uint64_t tag;          // station id << 60 (tagged): keeps stations apart
+  uint32_t tagged;       // 1: mixed key = tag | mix60(band key); 0: fmix64(band key)
   uint32_t tables_per_group;
   uint32_t row_dw;       // dwords per row
   int* err;              // set to 1 on an empty row or an index >= dim
@@ -115,8 +133,8 @@ struct BucketArgs {
   uint32_t* big_count;
   uint4* bin_desc;       // oversized bins {lo, hi, seg, 0}
   uint32_t* bin_count;
-  unsigned long long* e_raw;    // [kSpread]
-  unsigned int* max_bucket;     // [kSpread]
+  unsigned long long* e_raw;    // [nstation][kSpread]
+  unsigned int* max_bucket;     // [nstation][kSpread]
 };
 
 struct PairArgs {
@@ -133,9 +151,19 @@ struct PairArgs {
   uint8_t* out_v;
   unsigned int* out_count;
   uint32_t out_cap;
-  unsigned long long* e_voted;     // [kSpread]
-  unsigned long long* n_distinct;  // [kSpread]
+  unsigned long long* e_voted;     // [nstation][kSpread]
+  unsigned long long* n_distinct;  // [nstation][kSpread]
+  const uint64_t* station_base;    // nstation + 1 entries
+  uint32_t nstation;
+  const unsigned long long* n_flagged;  // total excluded (device), 0: skip flag lookups
 };
+
+// Station of a (global) fingerprint id, for nb stations with ascending bases.
+__device__ __forceinline__ uint32_t station_of(const uint64_t* base, uint32_t nb, uint64_t id) {
+  uint32_t s = 0;
+  while (s + 1 < nb && base[s + 1] <= id) ++s;
+  return s;
+}
 
 struct TileUnit {
   uint32_t bucket, ta, tb, pad;

@@ -75,8 +75,12 @@ __device__ __forceinline__ bool first_shared_is(const PairArgs& a, uint32_t u, u
   return true;
 }
 
+// Per-lane vote tallies of one station; [lo, hi) is that station's id range
+// (looked up again only when a pair falls outside it).
 struct PairTally {
   unsigned long long ev, nd;
+  uint32_t station;
+  uint32_t lo, hi;
 };
 
 constexpr uint32_t kDead = 0xFFFFFFFFu;  // member excluded by the occurrence filter
@@ -136,6 +140,18 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
                                            const RowReg<RSW>& rx, const uint32_t* ry, uint32_t rsw, uint32_t pad,
                                            PairTally& tl) {
   if (i == kDead || j == kDead || j - i < a.min_lag) return;
+  if (a.nstation > 1 && (i < tl.lo || i >= tl.hi)) {
+    const uint32_t st = station_of(a.station_base, a.nstation, i);
+    if (st != tl.station) {
+      const uint64_t o = (uint64_t)tl.station * kSpread + spread_slot();
+      if (tl.ev) atomicAdd(a.e_voted + o, tl.ev);
+      if (tl.nd) atomicAdd(a.n_distinct + o, tl.nd);
+      tl.ev = tl.nd = 0;
+      tl.station = st;
+    }
+    tl.lo = (uint32_t)a.station_base[st];
+    tl.hi = (uint32_t)a.station_base[st + 1];
+  }
   ++tl.ev;
   const uint32_t eq = rx.eq(ry, rsw);
   if (a.want_distinct) {
@@ -144,16 +160,26 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
   if (eq - pad >= a.need) exact_and_report(a, u, i, j);
 }
 
+// Called by every lane of the wave.  Lanes whose tallies belong to one
+// station are summed over the wave first; at a station boundary each lane
+// adds its own.
 __device__ void flush_tally(const PairArgs& a, PairTally tl) {
+  const uint32_t s0 = __shfl(tl.station, 0, 64);
+  if (!__all(tl.station == s0)) {
+    const uint64_t o = (uint64_t)tl.station * kSpread + spread_slot();
+    if (tl.ev) atomicAdd(a.e_voted + o, tl.ev);
+    if (tl.nd) atomicAdd(a.n_distinct + o, tl.nd);
+    return;
+  }
   unsigned long long ev = tl.ev, nd = tl.nd;
   for (int o = 32; o > 0; o >>= 1) {
     ev += __shfl_xor(ev, o, 64);
     nd += __shfl_xor(nd, o, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    const uint32_t slot = spread_slot();
-    if (ev) atomicAdd(a.e_voted + slot, ev);
-    if (nd) atomicAdd(a.n_distinct + slot, nd);
+    const uint64_t o = (uint64_t)s0 * kSpread + spread_slot();
+    if (ev) atomicAdd(a.e_voted + o, ev);
+    if (nd) atomicAdd(a.n_distinct + o, nd);
   }
 }
 
@@ -229,8 +255,7 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
 // ballots and lane shuffles, so the only barriers are the LDS hand-offs of
 // a single wave; many such waves per CU overlap their loads.
 template <int RSW>
-__global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl,
-                                                   uint32_t use_flags) {
+__global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl) {
   constexpr uint32_t kSpan = 64 + 63;  // small buckets hold at most 64 members
   extern __shared__ uint32_t smem[];
   uint32_t* lrows = smem;                   // kSpan * rswl
@@ -261,6 +286,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
     if (lane >= (uint32_t)o) inc += y;
   }
   const uint32_t P = __shfl(inc, 63, 64);
+  const bool use_flags = *a.n_flagged != 0;
   if (size) {
     hinfo[hidx] = lane | (size << 16);
     bpof[hidx] = inc - pc;
@@ -283,7 +309,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
     }
   }
   __syncthreads();
-  PairTally tl{0ull, 0ull};
+  PairTally tl{0ull, 0ull, 0u, 0u, 0u};
   const uint32_t pad = group_pad(a, seg, rsw);
   const uint32_t per = (P + 63) / 64;
   uint32_t p = lane * per;
@@ -370,7 +396,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
     for (uint32_t q = threadIdx.x; q < nbm; q += kPT) stage_row<RSW>(R + (uint64_t)idsB[q] * rsw, rowsB + q * rswl, rsw);
   __syncthreads();
   const uint32_t pad = group_pad(a, seg, rsw);
-  PairTally tl{0ull, 0ull};
+  PairTally tl{0ull, 0ull, 0u, 0u, 0u};
   const uint32_t P = diag ? na * (na - 1) / 2 : na * nbm;
   const uint32_t per = (P + kPT - 1) / kPT;
   uint32_t p = threadIdx.x * per;
@@ -397,15 +423,34 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
   flush_tally(a, tl);
 }
 
-// Split sorted (i << 32 | j, votes) records into the caller's arrays.
+// Split sorted (i << 32 | j, votes) records into the caller's arrays, ids
+// made local to their station.
 __global__ __launch_bounds__(kPT) void k_split_out(const uint64_t* key, const uint32_t* val, uint64_t count,
-                                                   uint32_t* oi, uint32_t* oj, uint8_t* ov) {
+                                                   uint32_t* oi, uint32_t* oj, uint8_t* ov, const uint64_t* base,
+                                                   uint32_t nb) {
   for (uint64_t e = (uint64_t)blockIdx.x * kPT + threadIdx.x; e < count; e += (uint64_t)gridDim.x * kPT) {
     const uint64_t k = key[e];
-    oi[e] = (uint32_t)(k >> 32);
-    oj[e] = (uint32_t)k;
+    const uint32_t i = (uint32_t)(k >> 32), j = (uint32_t)k;
+    const uint32_t b = (uint32_t)base[station_of(base, nb, i)];
+    oi[e] = i - b;
+    oj[e] = j - b;
     ov[e] = (uint8_t)val[e];
   }
+}
+
+// Offsets of each station's pairs in the sorted records: the first record
+// whose i is at or above the station's base.
+__global__ void k_station_offsets(const uint64_t* key, uint64_t count, const uint64_t* base, uint32_t nb,
+                                  unsigned long long* offs) {
+  const uint32_t s = threadIdx.x;
+  if (s > nb) return;
+  const uint64_t target = base[s] << 32;
+  uint64_t L = 0, R = count;
+  while (L < R) {
+    const uint64_t M = (L + R) / 2;
+    if (key[M] >= target) R = M; else L = M + 1;
+  }
+  offs[s] = L;
 }
 
 __global__ __launch_bounds__(kPT) void k_pack_out(const uint32_t* oi, const uint32_t* oj, const uint8_t* ov,
@@ -416,16 +461,70 @@ __global__ __launch_bounds__(kPT) void k_pack_out(const uint32_t* oi, const uint
   }
 }
 
-__global__ __launch_bounds__(kPT) void k_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out) {
+// Excluded fingerprints of one station (flags[0, n)): added to its counter
+// and to the total.
+__global__ __launch_bounds__(kPT) void k_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out,
+                                                     unsigned long long* total) {
   unsigned long long c = 0;
   for (uint64_t e = (uint64_t)blockIdx.x * kPT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * kPT) c += flags[e] != 0;
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+  if ((threadIdx.x & 63) == 0 && c) {
+    atomicAdd(out, c);
+    atomicAdd(total, c);
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kPT) void k_fill(T* p, uint64_t count, T v) {
   for (uint64_t e = (uint64_t)blockIdx.x * kPT + threadIdx.x; e < count; e += (uint64_t)gridDim.x * kPT) p[e] = v;
+}
+
+// Per-station sums of the spread counters: out[4s..4s+3] = e_raw,
+// max_bucket, e_voted, n_distinct of station s (one workgroup per station).
+__global__ __launch_bounds__(kPT) void k_spread_reduce(const unsigned long long* e_raw,
+                                                       const unsigned int* max_bucket,
+                                                       const unsigned long long* e_voted,
+                                                       const unsigned long long* n_distinct,
+                                                       unsigned long long* out) {
+  __shared__ unsigned long long part[3][kPT / 64];
+  __shared__ unsigned int pmax[kPT / 64];
+  const uint64_t o = (uint64_t)blockIdx.x * kSpread;
+  unsigned long long er = 0, ev = 0, nd = 0;
+  unsigned int mx = 0;
+  for (uint32_t k = threadIdx.x; k < kSpread; k += kPT) {
+    er += e_raw[o + k];
+    ev += e_voted[o + k];
+    nd += n_distinct[o + k];
+    mx = max(mx, max_bucket[o + k]);
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    er += __shfl_xor(er, d, 64);
+    ev += __shfl_xor(ev, d, 64);
+    nd += __shfl_xor(nd, d, 64);
+    mx = max(mx, (unsigned int)__shfl_xor(mx, d, 64));
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[0][w] = er;
+    part[1][w] = ev;
+    part[2][w] = nd;
+    pmax[w] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0, c = 0;
+    unsigned int m = 0;
+    for (uint32_t q = 0; q < kPT / 64; ++q) {
+      a += part[0][q];
+      b += part[1][q];
+      c += part[2][q];
+      m = max(m, pmax[q]);
+    }
+    out[4 * blockIdx.x + 0] = a;
+    out[4 * blockIdx.x + 1] = m;
+    out[4 * blockIdx.x + 2] = b;
+    out[4 * blockIdx.x + 3] = c;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -436,15 +535,14 @@ static unsigned grid_for(uint64_t count) {
   return (unsigned)(b == 0 ? 1 : (b < 65535 ? b : 65535));
 }
 
-void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, uint32_t use_flags,
-                       hipStream_t s) {
+void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, hipStream_t s) {
   if (a.n == 0) return;
   const dim3 grid((unsigned)((a.n + 63) / 64), S);
   const size_t smem = (size_t)(127 * rswl + 127 + 64 + 65) * 4;
   switch (a.row_dw) {
-    case 10: hipLaunchKernelGGL((k_pairs_wave<10>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
-    case 17: hipLaunchKernelGGL((k_pairs_wave<17>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
-    default: hipLaunchKernelGGL((k_pairs_wave<0>), grid, dim3(64), smem, s, a, marks, rswl, use_flags); break;
+    case 10: hipLaunchKernelGGL((k_pairs_wave<10>), grid, dim3(64), smem, s, a, marks, rswl); break;
+    case 17: hipLaunchKernelGGL((k_pairs_wave<17>), grid, dim3(64), smem, s, a, marks, rswl); break;
+    default: hipLaunchKernelGGL((k_pairs_wave<0>), grid, dim3(64), smem, s, a, marks, rswl); break;
   }
 }
 
@@ -467,9 +565,14 @@ void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits
 }
 
 void launch_split_out(const uint64_t* key, const uint32_t* val, uint64_t count, uint32_t* oi, uint32_t* oj,
-                      uint8_t* ov, hipStream_t s) {
+                      uint8_t* ov, const uint64_t* base, uint32_t nb, hipStream_t s) {
   if (count == 0) return;
-  hipLaunchKernelGGL(k_split_out, dim3(grid_for(count)), dim3(kPT), 0, s, key, val, count, oi, oj, ov);
+  hipLaunchKernelGGL(k_split_out, dim3(grid_for(count)), dim3(kPT), 0, s, key, val, count, oi, oj, ov, base, nb);
+}
+
+void launch_station_offsets(const uint64_t* key, uint64_t count, const uint64_t* base, uint32_t nb,
+                            unsigned long long* offs, hipStream_t s) {
+  hipLaunchKernelGGL(k_station_offsets, dim3(1), dim3(64), 0, s, key, count, base, nb, offs);
 }
 
 void launch_pack_out(const uint32_t* oi, const uint32_t* oj, const uint8_t* ov, uint64_t count, uint64_t* key,
@@ -478,9 +581,17 @@ void launch_pack_out(const uint32_t* oi, const uint32_t* oj, const uint8_t* ov, 
   hipLaunchKernelGGL(k_pack_out, dim3(grid_for(count)), dim3(kPT), 0, s, oi, oj, ov, count, key, val);
 }
 
-void launch_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out, hipStream_t s) {
+void launch_count_flags(const uint8_t* flags, uint64_t n, unsigned long long* out, unsigned long long* total,
+                        hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_count_flags, dim3(grid_for(n) < 4096 ? grid_for(n) : 4096), dim3(kPT), 0, s, flags, n, out);
+  hipLaunchKernelGGL(k_count_flags, dim3(grid_for(n) < 1024 ? grid_for(n) : 1024), dim3(kPT), 0, s, flags, n, out,
+                     total);
+}
+
+void launch_spread_reduce(const unsigned long long* e_raw, const unsigned int* max_bucket,
+                          const unsigned long long* e_voted, const unsigned long long* n_distinct, uint32_t S,
+                          unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_spread_reduce, dim3(S), dim3(kPT), 0, s, e_raw, max_bucket, e_voted, n_distinct, out);
 }
 
 void fill_u8(uint8_t* p, uint64_t count, uint8_t v, hipStream_t s) {

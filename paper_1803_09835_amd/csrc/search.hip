@@ -1,0 +1,654 @@
+// Host orchestration of the similarity search over a set of stations
+// (section 6.1 "Search"; occurrence filter, section 6.5; self-match lag,
+// section 7.1), and its public entry points.
+//
+// One search runs every kernel once over all stations together: the
+// stations' fingerprints get consecutive global ids, their mixed keys carry
+// the station id in the top four bits (above a 60-bit bijective mix of the
+// band key) so that no bucket ever holds two stations and each station's
+// buckets are contiguous in every sorted table, and the occurrence filter
+// and the counters are kept per station.  A single station is the case
+// S = 1 (untagged, 64-bit mix).
+//
+// The part of the search whose launch shapes depend only on the input
+// shapes (signatures, grouping, buckets, big bins, exclusion counts and the
+// small-bucket pair kernel) is enqueued by enqueue_prefix, either directly
+// or into a captured HIP graph.  The rest depends on counts the device
+// produces (large buckets, output size) and is launched after one read-back.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "host.hpp"
+
+using namespace fl;
+
+namespace {
+
+struct Plan {
+  uint32_t t, G, TG, row_dw, need;
+};
+
+// Bits of the mixed key the radix passes bin on: a multiple of 8 large enough
+// that an average bin of the largest station holds at most about 32
+// elements, plus the four station bits when keys are tagged.
+uint32_t bin_bits(uint64_t n_max, bool tagged) {
+  uint32_t need = 0;
+  while ((32ull << need) < n_max) ++need;
+  if (tagged) need += 4;
+  uint32_t B = (need + 7) / 8 * 8;
+  return std::min<uint32_t>(32, std::max<uint32_t>(8, B));
+}
+
+// Table groups of the sub-key rows: one group when every shared table has to
+// be seen anyway (v <= 2, or n_distinct wanted), else v - 1 groups so that a
+// pair with v votes shares need = ceil(v / G) tables in some group.
+Plan make_plan(uint32_t t, uint32_t v, bool distinct) {
+  Plan p;
+  p.t = t;
+  uint32_t G = (distinct || v <= 2) ? 1u : std::min(v - 1, t);
+  p.TG = (t + G - 1) / G;
+  p.G = (t + p.TG - 1) / p.TG;
+  p.need = (v + p.G - 1) / p.G;
+  p.row_dw = row_dwords(p.TG);
+  return p;
+}
+
+// Counters the host reads back.  Sums that many workgroups update live in
+// the spread buffer ([S][kSpread] slots each) and are folded per station
+// into st_sum by k_spread_reduce.
+struct Ctrl {
+  unsigned long long n_flagged;  // all stations
+  unsigned int big_count, bin_count, out_count;
+  int err;
+  unsigned long long st_flagged[FAST_LSH_MAX_STATIONS];
+  unsigned long long st_sum[4 * FAST_LSH_MAX_STATIONS];  // e_raw, max_bucket, e_voted, n_distinct
+  unsigned long long st_offs[FAST_LSH_MAX_STATIONS + 1];
+};
+
+// Everything the fixed-shape prefix launches read.
+struct Job {
+  uint32_t S;
+  uint64_t N;
+  uint32_t t, B;
+  bool minmax;
+  Plan pl;
+  TuneChoice tc;
+  std::vector<uint64_t> base;  // S + 1
+  std::vector<int> cap;
+  std::vector<bool> vec;
+  const fast_lsh_fps* f;
+  const fast_lsh_hash* h;
+  uint32_t* dhash;
+  Ctrl* ctrl;
+  unsigned long long *er, *ev, *nd;
+  unsigned int* mb;
+  uint64_t *mkeys, *ak, *bk;
+  uint32_t *av, *bv, *rows, *hist, *sums;
+  uint8_t *flags, *marks;
+  uint64_t* sbase;
+  uint4 *bdesc, *bins;
+  uint32_t bigbin_grid;
+  uint64_t spread_bytes;
+  uint32_t rswl;
+  BucketArgs ba;
+  PairArgs pa;
+  // the radix passes leave the sorted keys/ids in (sorted_k, sorted_v)
+  uint64_t *sorted_k, *scratch_k;
+  uint32_t *sorted_v, *scratch_v;
+};
+
+// Time one launch sequence with events on stream s (used by the tuner);
+// `setup` is enqueued before the timed interval.
+template <typename P, typename F>
+int time_launch(hipStream_t s, P&& setup, F&& f, float* ms) {
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  setup();
+  HIPCK(hipEventRecord(e0, s));
+  f();
+  hipError_t le = hipGetLastError();
+  HIPCK(hipEventRecord(e1, s));
+  HIPCK(hipEventSynchronize(e1));
+  HIPCK(hipEventElapsedTime(ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (le != hipSuccess) return fl_fail(FAST_LSH_E_DEVICE, "kernel launch while tuning: %s", hipGetErrorString(le));
+  return FAST_LSH_OK;
+}
+
+// Enqueue the fixed-shape prefix on stream s.  With `tune`, the first radix
+// pass and the bucket kernel are run once per candidate shape (each run
+// produces the same data) and the fastest shapes are stored in j.tc; tuning
+// synchronises, so it is never combined with graph capture.
+int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune) {
+  auto pb = [&](int st) {
+    if (prof) prof_begin(c, st);
+  };
+  auto pe = [&]() {
+    if (prof) prof_end(c);
+  };
+  fill_u8(reinterpret_cast<uint8_t*>(j.ctrl), sizeof(Ctrl), 0, s);
+  fill_u8(reinterpret_cast<uint8_t*>(j.er), j.spread_bytes, 0, s);
+  fill_u8(j.flags, j.N, 0, s);
+  LAUNCHCK();
+
+  // 1. signatures -> mixed keys (table-major) and sub-key rows, per station
+  pb(FAST_LSH_STAGE_SIGNATURES);
+  for (uint32_t st = 0; st < j.S; ++st) {
+    if (j.f[st].n == 0) continue;
+    SigArgs sa = fl_sig_args(j.h, &j.f[st], j.dhash, &j.ctrl->err);
+    sa.table_begin = 0;
+    sa.table_count = j.t;
+    sa.vec_load = j.vec[st];
+    sa.mkeys = j.mkeys;
+    sa.rows = j.rows;
+    sa.out_stride = j.N;
+    sa.out_base = j.base[st];
+    sa.tagged = j.S > 1;
+    sa.tag = (uint64_t)st << 60;
+    sa.tables_per_group = j.pl.TG;
+    sa.row_dw = j.pl.row_dw;
+    launch_sig(j.cap[st], j.minmax, sa, s);
+  }
+  pe();
+  LAUNCHCK();
+
+  // 2. stable radix passes on the top B bits, all tables at once
+  uint64_t *gk = j.ak, *gk2 = j.bk;
+  uint32_t *gv = j.av, *gv2 = j.bv;
+  if (tune) {
+    float best = 1e30f;
+    uint32_t bestv = 0;
+    for (uint32_t v = 0; v < kRadixTileVariants; ++v) {
+      float ms = 0;
+      RC(time_launch(s, [] {}, [&] { radix_pass(j.mkeys, nullptr, gk, gv, j.N, j.t, 64 - j.B, j.hist, j.sums, v, s); },
+                     &ms));
+      if (ms < best) {
+        best = ms;
+        bestv = v;
+      }
+    }
+    j.tc.radix_variant = bestv;
+  }
+  pb(FAST_LSH_STAGE_GROUP);
+  for (uint32_t pass = 0; pass < j.B / 8; ++pass) {
+    const uint32_t shift = 64 - j.B + 8 * pass;
+    radix_pass(pass == 0 ? j.mkeys : gk2, pass == 0 ? nullptr : gv2, gk, gv, j.N, j.t, shift, j.hist, j.sums,
+               j.tc.radix_variant, s);
+    std::swap(gk, gk2);
+    std::swap(gv, gv2);
+  }
+  pe();
+  LAUNCHCK();
+  j.sorted_k = gk2;
+  j.sorted_v = gv2;
+  j.scratch_k = gk;
+  j.scratch_v = gv;
+
+  // 3. buckets, deferred big bins, exclusion counts
+  j.ba.keys = j.sorted_k;
+  j.ba.vals = j.sorted_v;
+  if (tune) {
+    // The bucket kernel reorders the ids of each bin (the keys stay in radix
+    // order), so every candidate starts from a saved copy of the radix output.
+    const size_t vbytes = (size_t)j.t * j.N * sizeof(uint32_t);
+    HIPCK(hipMemcpyAsync(j.scratch_v, j.sorted_v, vbytes, hipMemcpyDeviceToDevice, s));
+    auto restore = [&] {
+      (void)hipMemcpyAsync(j.sorted_v, j.scratch_v, vbytes, hipMemcpyDeviceToDevice, s);
+      fill_u8(reinterpret_cast<uint8_t*>(j.er), j.spread_bytes, 0, s);
+      fill_u32(&j.ctrl->big_count, 2, 0, s);  // big_count, bin_count
+    };
+    static const uint32_t chunks[] = {768, 1024, 1536, 2048};
+    float best = 1e30f;
+    uint32_t bestc = j.tc.bucket_chunk;
+    for (uint32_t ch : chunks) {
+      BucketArgs b = j.ba;
+      b.chunk = ch;
+      float ms = 0;
+      RC(time_launch(s, restore, [&] { launch_bucket(b, j.t, s); }, &ms));
+      if (ms < best) {
+        best = ms;
+        bestc = ch;
+      }
+    }
+    j.tc.bucket_chunk = bestc;
+    restore();
+    LAUNCHCK();
+  }
+  j.ba.chunk = j.tc.bucket_chunk;
+  pb(FAST_LSH_STAGE_BUCKETS);
+  launch_bucket(j.ba, j.t, s);
+  pe();
+  LAUNCHCK();
+  pb(FAST_LSH_STAGE_BIG_BINS);
+  launch_bigbin(j.ba, j.bins, j.bigbin_grid, j.scratch_k, j.scratch_v, s);
+  pe();
+  LAUNCHCK();
+  for (uint32_t st = 0; st < j.S; ++st)
+    launch_count_flags(j.flags + j.base[st], j.base[st + 1] - j.base[st], &j.ctrl->st_flagged[st],
+                       &j.ctrl->n_flagged, s);
+  LAUNCHCK();
+
+  // 4. pairs of small buckets
+  j.pa.order = j.sorted_v;
+  pb(FAST_LSH_STAGE_PAIRS);
+  launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, s);
+  pe();
+  LAUNCHCK();
+  return FAST_LSH_OK;
+}
+
+// Pairs of the large buckets (tiled kernel), from descriptors on the host.
+int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
+  if (big_count == 0) return FAST_LSH_OK;
+  hipStream_t s = c->stream;
+  std::vector<uint4> hbig(big_count);
+  RC(d2h(c, hbig.data(), j.bdesc, big_count));
+  std::vector<uint64_t> cofs(big_count + 1, 0);
+  for (uint32_t b = 0; b < big_count; ++b) cofs[b + 1] = cofs[b] + hbig[b].z;
+  uint64_t* dcofs;
+  uint32_t *bids, *bcnt;
+  RC(ws<uint64_t>(c, "big_cofs", big_count + 1, &dcofs));
+  RC(ws<uint32_t>(c, "big_ids", cofs.back() + 1, &bids));
+  RC(ws<uint32_t>(c, "big_cnt", big_count, &bcnt));
+  RC(h2d(c, dcofs, cofs.data(), big_count + 1));
+  launch_compact_big(j.pa, j.bdesc, big_count, dcofs, bids, bcnt, s);
+  LAUNCHCK();
+  std::vector<uint32_t> hcnt(big_count);
+  RC(d2h(c, hcnt.data(), bcnt, big_count));
+  // tile edge: a power of two with two tiles of rows and ids within 64 KB of LDS
+  const uint32_t fit = 65536 / (8 * j.rswl + 8);
+  uint32_t tb = 256;
+  while (tb > 16 && tb > fit) tb >>= 1;
+  std::vector<TileUnit> units;
+  for (uint32_t b = 0; b < big_count; ++b) {
+    const uint32_t m = hcnt[b];
+    if (m < 2) continue;
+    const uint32_t ntl = (m + tb - 1) / tb;
+    for (uint32_t x = 0; x < ntl; ++x)
+      for (uint32_t y = x; y < ntl; ++y) units.push_back(TileUnit{b, x, y, 0});
+  }
+  if (units.empty()) return FAST_LSH_OK;
+  TileUnit* du;
+  RC(ws<TileUnit>(c, "units", units.size(), &du));
+  RC(h2d(c, du, units.data(), units.size()));
+  for (size_t u0 = 0; u0 < units.size(); u0 += 1u << 20) {
+    const uint32_t cnt = (uint32_t)std::min<size_t>(1u << 20, units.size() - u0);
+    prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
+    launch_pairs_tile(j.pa, du + u0, cnt, j.bdesc, dcofs, bids, bcnt, tb, j.rswl, s);
+    prof_end(c);
+    LAUNCHCK();
+  }
+  return FAST_LSH_OK;
+}
+
+int set_out_buffers(fast_lsh_ctx* c, Job& j, uint64_t out_cap) {
+  uint32_t *oi, *oj;
+  uint8_t* ov;
+  RC(ws<uint32_t>(c, "out_i", out_cap, &oi));
+  RC(ws<uint32_t>(c, "out_j", out_cap, &oj));
+  RC(ws<uint8_t>(c, "out_v", out_cap, &ov));
+  j.pa.out_i = oi;
+  j.pa.out_j = oj;
+  j.pa.out_v = ov;
+  j.pa.out_cap = (uint32_t)std::min<uint64_t>(out_cap, 0xFFFFFFFFull);
+  return FAST_LSH_OK;
+}
+
+}  // namespace
+
+int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, const fast_lsh_fps* f,
+                       const fast_lsh_filter* flt, uint32_t flags, fast_lsh_stats* per_station,
+                       uint64_t* station_offsets) {
+  hipStream_t s = c->stream;
+  const bool distinct = (flags & FAST_LSH_WANT_DISTINCT) != 0;
+  Job j;
+  j.S = S;
+  j.f = f;
+  j.h = h;
+  j.t = h->num_tables;
+  j.minmax = h->scheme == FAST_LSH_MINMAX;
+  j.base.assign(S + 1, 0);
+  for (uint32_t st = 0; st < S; ++st) j.base[st + 1] = j.base[st] + f[st].n;
+  j.N = j.base[S];
+  c->res_valid = false;
+  c->res_stations = S;
+  if (j.N == 0) {
+    c->res_count = 0;
+    c->res_valid = true;
+    for (uint32_t st = 0; st < S; ++st) {
+      if (per_station) {
+        memset(&per_station[st], 0, sizeof(fast_lsh_stats));
+        if (!distinct) per_station[st].n_distinct = ~0ull;
+      }
+    }
+    if (station_offsets) memset(station_offsets, 0, (S + 1) * sizeof(uint64_t));
+    return FAST_LSH_OK;
+  }
+  const uint64_t N = j.N, t = j.t, tn = t * N;
+  j.pl = make_plan(j.t, flt->min_votes, distinct);
+  uint64_t n_max = 0;
+  for (uint32_t st = 0; st < S; ++st) n_max = std::max<uint64_t>(n_max, f[st].n);
+  j.B = bin_bits(n_max, S > 1);
+
+  RC(fl_upload_hash(c, h, &j.dhash));
+  j.cap.assign(S, 0);
+  j.vec.assign(S, false);
+  for (uint32_t st = 0; st < S; ++st) {
+    if (f[st].n == 0) continue;
+    int cp;
+    bool vc;
+    RC(fl_row_capacity(c, &f[st], &cp, &vc));
+    j.cap[st] = cp;
+    j.vec[st] = vc;
+  }
+
+  // workspace
+  RC(ws<Ctrl>(c, "ctrl", 1, &j.ctrl));
+  j.spread_bytes = (uint64_t)S * kSpread * (3 * sizeof(unsigned long long) + sizeof(unsigned int));
+  uint8_t* spread;
+  RC(ws<uint8_t>(c, "spread", j.spread_bytes, &spread));
+  j.er = reinterpret_cast<unsigned long long*>(spread);
+  j.ev = j.er + (uint64_t)S * kSpread;
+  j.nd = j.ev + (uint64_t)S * kSpread;
+  j.mb = reinterpret_cast<unsigned int*>(j.nd + (uint64_t)S * kSpread);
+  RC(ws<uint64_t>(c, "mkeys", tn, &j.mkeys));
+  RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_dw, &j.rows));
+  RC(ws<uint64_t>(c, "ak", tn, &j.ak));
+  RC(ws<uint32_t>(c, "av", tn, &j.av));
+  RC(ws<uint64_t>(c, "bk", tn, &j.bk));
+  RC(ws<uint32_t>(c, "bv", tn, &j.bv));
+  const uint32_t nt_max = radix_tiles(N, kRadixTileVariants - 1);  // the smallest tile has the most tiles
+  RC(ws<uint32_t>(c, "hist", (uint64_t)256 * nt_max * t, &j.hist));
+  RC(ws<uint32_t>(c, "sums", scan_sums_elems((uint64_t)256 * nt_max, j.t), &j.sums));
+  RC(ws<uint8_t>(c, "flags", N, &j.flags));
+  RC(ws<uint64_t>(c, "station_base", S + 1, &j.sbase));
+  // Buckets of at most smax members are marked in place and handled by the
+  // wave-per-chunk pair kernel; larger ones go to the tiled kernel.
+  const uint32_t smax = 64;
+  const uint64_t cap_big = tn / (smax + 1) + 1;
+  const uint64_t cap_bin = tn / 129 + t + 1;  // oversized bins and mixed bins above 128 elements
+  RC(ws<uint4>(c, "bdesc", cap_big, &j.bdesc));
+  RC(ws<uint4>(c, "bins", cap_bin, &j.bins));
+  RC(ws<uint8_t>(c, "marks", tn, &j.marks));
+  j.bigbin_grid = (uint32_t)std::min<uint64_t>(cap_bin, 512);
+  j.rswl = j.pl.row_dw | 1u;
+  uint64_t out_cap = std::max<uint64_t>(1u << 20, N / 8);
+  RC(h2d(c, j.sbase, j.base.data(), S + 1));
+
+  BucketArgs& ba = j.ba;
+  memset(&ba, 0, sizeof ba);
+  ba.n = N;
+  ba.bin_shift = 64 - j.B;
+  ba.station_base = j.sbase;
+  ba.nstation = S;
+  ba.occ_num = flt->occ_num;
+  ba.occ_den = flt->occ_den;
+  ba.min_lag = flt->min_lag;
+  ba.flags = j.flags;
+  ba.small_max = smax;
+  ba.marks = j.marks;
+  ba.big_desc = j.bdesc;
+  ba.big_count = &j.ctrl->big_count;
+  ba.bin_desc = j.bins;
+  ba.bin_count = &j.ctrl->bin_count;
+  ba.e_raw = j.er;
+  ba.max_bucket = j.mb;
+
+  PairArgs& pa = j.pa;
+  memset(&pa, 0, sizeof pa);
+  pa.flags = j.flags;
+  pa.rows = j.rows;
+  pa.mkeys = j.mkeys;
+  pa.n = N;
+  pa.t = j.t;
+  pa.G = j.pl.G;
+  pa.tables_per_group = j.pl.TG;
+  pa.row_dw = j.pl.row_dw;
+  pa.min_lag = flt->min_lag;
+  pa.min_votes = flt->min_votes;
+  pa.need = j.pl.need;
+  pa.want_distinct = distinct;
+  pa.out_count = &j.ctrl->out_count;
+  pa.e_voted = j.ev;
+  pa.n_distinct = j.nd;
+  pa.station_base = j.sbase;
+  pa.nstation = S;
+  pa.n_flagged = &j.ctrl->n_flagged;
+  RC(set_out_buffers(c, j, out_cap));
+
+  // launch shapes: fixed, or tuned once per shape
+  const std::vector<uint64_t> shape{S, N, t, j.B};
+  bool tune = false;
+  if (c->config.autotune) {
+    auto it = c->tuned.find(shape);
+    if (it != c->tuned.end()) {
+      j.tc = it->second;
+    } else {
+      tune = true;
+    }
+  } else {
+    j.tc.radix_variant = 0;
+    for (uint32_t v = 0; v < kRadixTileVariants; ++v)
+      if (radix_tile_elems(v) == c->config.radix_tile) j.tc.radix_variant = v;
+    j.tc.bucket_chunk = c->config.bucket_chunk;
+  }
+
+  // 1-4: the fixed-shape prefix, eager or as a replayed graph
+  const bool use_graph = (flags & FAST_LSH_USE_GRAPH) && !tune;
+  if (use_graph) {
+    std::vector<uint64_t> key{S, N, t, h->band_rows, h->scheme, h->dim, flt->min_lag, flt->min_votes,
+                              flt->occ_num, flt->occ_den, flags, j.tc.radix_variant, j.tc.bucket_chunk,
+                              c->ws_generation, (uint64_t)(uintptr_t)s};
+    for (uint32_t st = 0; st < S; ++st) {
+      key.push_back((uint64_t)(uintptr_t)f[st].indices);
+      key.push_back((uint64_t)(uintptr_t)f[st].offsets);
+      key.push_back(f[st].fixed_nnz);
+      key.push_back(f[st].n);
+      key.push_back((uint64_t)j.cap[st] * 2 + (j.vec[st] ? 1 : 0));
+    }
+    if (!c->graph || key != c->graph_key) {
+      if (c->graph) {
+        HIPCK(hipGraphExecDestroy(c->graph));
+        c->graph = nullptr;
+      }
+      if (!c->capture_stream) HIPCK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+      HIPCK(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+      const int rc = enqueue_prefix(c, j, c->capture_stream, false, false);
+      hipGraph_t g = nullptr;
+      const hipError_t ee = hipStreamEndCapture(c->capture_stream, &g);
+      if (rc != FAST_LSH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      HIPCK(ee);
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCK(ie);
+      c->graph = ex;
+      c->graph_key = key;
+    } else {
+      // the sorted arrays' location follows from the pass count only
+      j.sorted_k = (j.B / 8) % 2 ? j.ak : j.bk;
+      j.sorted_v = (j.B / 8) % 2 ? j.av : j.bv;
+      j.scratch_k = (j.B / 8) % 2 ? j.bk : j.ak;
+      j.scratch_v = (j.B / 8) % 2 ? j.bv : j.av;
+      j.pa.order = j.sorted_v;
+    }
+    prof_begin(c, FAST_LSH_STAGE_GRAPH);
+    HIPCK(hipGraphLaunch(c->graph, s));
+    prof_end(c);
+    ++c->graph_replays;
+  } else {
+    RC(enqueue_prefix(c, j, s, true, tune));
+    if (tune) c->tuned[shape] = j.tc;
+  }
+  c->last_choice = j.tc;
+
+  Ctrl hc;
+  RC(d2h(c, &hc, j.ctrl));
+  if (hc.err) return fl_fail(FAST_LSH_E_INVALID, "a fingerprint is empty or holds an index >= dim (%u)", h->dim);
+
+  // 4b. large buckets; 4c. a second pair pass if the output overflowed
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (attempt == 1) {
+      out_cap = (uint64_t)hc.out_count + 1024;
+      RC(set_out_buffers(c, j, out_cap));
+      fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * S * kSpread * sizeof(unsigned long long), 0, s);
+      fill_u32(&j.ctrl->out_count, 1, 0, s);
+      prof_begin(c, FAST_LSH_STAGE_PAIRS);
+      launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, s);
+      prof_end(c);
+      LAUNCHCK();
+    }
+    RC(run_big_pairs(c, j, hc.big_count));
+    RC(d2h(c, &hc, j.ctrl));
+    if (hc.out_count <= out_cap) break;
+  }
+
+  // 5. canonical order: sort (i << 32 | j) by LSD radix over the bits in use,
+  // then per-station offsets and counters
+  const uint64_t cnt = hc.out_count;
+  uint64_t *rk0, *rk1;
+  uint32_t *rv0, *rv1;
+  RC(ws<uint64_t>(c, "res_k0", cnt + 1, &rk0));
+  RC(ws<uint64_t>(c, "res_k1", cnt + 1, &rk1));
+  RC(ws<uint32_t>(c, "res_v0", cnt + 1, &rv0));
+  RC(ws<uint32_t>(c, "res_v1", cnt + 1, &rv1));
+  launch_pack_out(j.pa.out_i, j.pa.out_j, j.pa.out_v, cnt, rk0, rv0, s);
+  LAUNCHCK();
+  if (cnt > 1) {
+    const uint32_t nb = fl_key_bits((uint32_t)std::max<uint64_t>(N, 2));
+    const uint32_t ont = radix_tiles(cnt, 0);
+    uint32_t *ohist, *osums;
+    RC(ws<uint32_t>(c, "ohist", (uint64_t)256 * ont, &ohist));
+    RC(ws<uint32_t>(c, "osums", scan_sums_elems((uint64_t)256 * ont, 1), &osums));
+    std::vector<uint32_t> shifts;
+    for (uint32_t sh = 0; sh < nb; sh += 8) shifts.push_back(sh);
+    for (uint32_t sh = 0; sh < nb; sh += 8) shifts.push_back(32 + sh);
+    for (uint32_t sh : shifts) {
+      prof_begin(c, FAST_LSH_STAGE_OUTPUT);
+      radix_pass(rk0, rv0, rk1, rv1, cnt, 1, sh, ohist, osums, 0, s);
+      prof_end(c);
+      LAUNCHCK();
+      std::swap(rk0, rk1);
+      std::swap(rv0, rv1);
+    }
+  }
+  // keep the sorted result under the fixed names read by fast_lsh_copy_result
+  if (c->ws["res_k0"].p != rk0) {
+    std::swap(c->ws["res_k0"], c->ws["res_k1"]);
+    std::swap(c->ws["res_v0"], c->ws["res_v1"]);
+  }
+  launch_station_offsets(rk0, cnt, j.sbase, S, j.ctrl->st_offs, s);
+  launch_spread_reduce(j.er, j.mb, j.ev, j.nd, S, j.ctrl->st_sum, s);
+  LAUNCHCK();
+  RC(d2h(c, &hc, j.ctrl));
+  prof_collect(c);
+  c->res_count = cnt;
+  c->res_valid = true;
+
+  for (uint32_t st = 0; st < S; ++st) {
+    if (station_offsets) station_offsets[st] = hc.st_offs[st];
+    if (!per_station) continue;
+    fast_lsh_stats& o = per_station[st];
+    o.n_out = hc.st_offs[st + 1] - hc.st_offs[st];
+    o.e_raw = hc.st_sum[4 * st + 0];
+    o.max_bucket = hc.st_sum[4 * st + 1];
+    o.e_voted = hc.st_sum[4 * st + 2];
+    o.n_distinct = distinct ? hc.st_sum[4 * st + 3] : ~0ull;
+    o.n_flagged = hc.st_flagged[st];
+  }
+  if (station_offsets) station_offsets[S] = hc.st_offs[S];
+  return FAST_LSH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Public entry points
+// ---------------------------------------------------------------------------
+static int check_filter(const fast_lsh_filter* flt, uint32_t flags) {
+  if (!flt) return fl_fail(FAST_LSH_E_INVALID, "filter is NULL");
+  if (flt->min_votes < 1) return fl_fail(FAST_LSH_E_INVALID, "min_votes must be >= 1");
+  if (flt->occ_den && flt->occ_num > flt->occ_den)
+    return fl_fail(FAST_LSH_E_INVALID, "occurrence filter fraction %u/%u above 1", flt->occ_num, flt->occ_den);
+  if (flags & ~(uint32_t)(FAST_LSH_WANT_DISTINCT | FAST_LSH_USE_GRAPH))
+    return fl_fail(FAST_LSH_E_INVALID, "unknown flags 0x%x", flags);
+  return FAST_LSH_OK;
+}
+
+extern "C" {
+
+int fast_lsh_copy_result(fast_lsh_ctx* c, uint32_t* oi, uint32_t* oj, uint8_t* ov, uint64_t capacity) {
+  if (!c) return fl_fail(FAST_LSH_E_INVALID, "ctx is NULL");
+  if (!c->res_valid) return fl_fail(FAST_LSH_E_INVALID, "no search result in this context");
+  if (c->res_count > capacity)
+    return fl_fail(FAST_LSH_E_CAPACITY, "%llu pairs do not fit capacity %llu", (unsigned long long)c->res_count,
+                   (unsigned long long)capacity);
+  if (c->res_count == 0) return FAST_LSH_OK;
+  if (!oi || !oj || !ov) return fl_fail(FAST_LSH_E_INVALID, "output pointer is NULL");
+  HIPCK(hipSetDevice(c->device));
+  launch_split_out(static_cast<uint64_t*>(c->ws["res_k0"].p), static_cast<uint32_t*>(c->ws["res_v0"].p),
+                   c->res_count, oi, oj, ov, static_cast<uint64_t*>(c->ws["station_base"].p), c->res_stations,
+                   c->stream);
+  LAUNCHCK();
+  HIPCK(hipStreamSynchronize(c->stream));
+  return FAST_LSH_OK;
+}
+
+int fast_lsh_search_batched(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t n_stations,
+                            const fast_lsh_fps* stations, const fast_lsh_filter* flt, uint32_t flags,
+                            uint32_t* oi, uint32_t* oj, uint8_t* ov, uint64_t capacity, uint64_t* station_offsets,
+                            fast_lsh_stats* per_station) {
+  if (!c) return fl_fail(FAST_LSH_E_INVALID, "ctx is NULL");
+  RC(fl_check_hash(h));
+  RC(check_filter(flt, flags));
+  if (n_stations < 1 || n_stations > FAST_LSH_MAX_STATIONS)
+    return fl_fail(FAST_LSH_E_INVALID, "n_stations %u outside [1, %d]", n_stations, FAST_LSH_MAX_STATIONS);
+  if (!stations) return fl_fail(FAST_LSH_E_INVALID, "stations is NULL");
+  uint64_t total = 0;
+  for (uint32_t st = 0; st < n_stations; ++st) {
+    RC(fl_check_fps(&stations[st]));
+    total += stations[st].n;
+  }
+  if (total >= (1ull << 31))
+    return fl_fail(FAST_LSH_E_INVALID, "total n = %llu must be below 2^31", (unsigned long long)total);
+  if (n_stations > 1 && (uint64_t)fl_key_bits(h->dim) * h->band_rows > 60)
+    return fl_fail(FAST_LSH_E_INVALID, "band key of %u bits leaves no room for the station tag (at most 60)",
+                   fl_key_bits(h->dim) * h->band_rows);
+  HIPCK(hipSetDevice(c->device));
+  std::vector<fast_lsh_stats> local(n_stations);
+  RC(fl_search_stations(c, h, n_stations, stations, flt, flags, local.data(), station_offsets));
+  if (per_station) std::copy(local.begin(), local.end(), per_station);
+  if (c->res_count > capacity)
+    return fl_fail(FAST_LSH_E_CAPACITY, "%llu pairs do not fit capacity %llu", (unsigned long long)c->res_count,
+                   (unsigned long long)capacity);
+  return fast_lsh_copy_result(c, oi, oj, ov, capacity);
+}
+
+int fast_lsh_search_ex(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps* f, const fast_lsh_filter* flt,
+                       uint32_t flags, uint32_t* oi, uint32_t* oj, uint8_t* ov, uint64_t capacity,
+                       fast_lsh_stats* st) {
+  if (!c) return fl_fail(FAST_LSH_E_INVALID, "ctx is NULL");
+  RC(fl_check_hash(h));
+  RC(fl_check_fps(f));
+  RC(check_filter(flt, flags));
+  HIPCK(hipSetDevice(c->device));
+  fast_lsh_stats local;
+  RC(fl_search_stations(c, h, 1, f, flt, flags, &local, nullptr));
+  if (st) *st = local;
+  if (local.n_out > capacity)
+    return fl_fail(FAST_LSH_E_CAPACITY, "%llu pairs do not fit capacity %llu", (unsigned long long)local.n_out,
+                   (unsigned long long)capacity);
+  return fast_lsh_copy_result(c, oi, oj, ov, capacity);
+}
+
+int fast_lsh_search(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps* f, const fast_lsh_filter* flt,
+                    uint32_t* oi, uint32_t* oj, uint8_t* ov, uint64_t capacity, fast_lsh_stats* st) {
+  return fast_lsh_search_ex(c, h, f, flt, 0, oi, oj, ov, capacity, st);
+}
+
+}  // extern "C"

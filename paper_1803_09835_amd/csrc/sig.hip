@@ -65,8 +65,8 @@ __device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint
   const uint32_t tab = a.table_begin + u;
   if (live && a.keys) a.keys[(uint64_t)u * a.n + i] = key;
   if (a.mkeys || a.rows) {
-    const uint64_t m = fmix64(key);
-    if (live && a.mkeys) a.mkeys[(uint64_t)u * a.n + i] = m;
+    const uint64_t m = a.tagged ? (a.tag | mix60(key)) : fmix64(key);
+    if (live && a.mkeys) a.mkeys[(uint64_t)u * a.out_stride + a.out_base + i] = m;
     if (a.rows) {
       const uint32_t slot = tab % a.tables_per_group;
       if (slot == 0)
@@ -87,7 +87,7 @@ __device__ __forceinline__ void flush_rows(const SigArgs& a, uint32_t u, const u
   const uint32_t g = tab / a.tables_per_group;
   const uint64_t i0 = (uint64_t)blockIdx.x * 256;
   const uint32_t live = (uint32_t)min((uint64_t)256, a.n - i0);
-  uint32_t* dst = a.rows + ((uint64_t)g * a.n + i0) * a.row_dw;
+  uint32_t* dst = a.rows + ((uint64_t)g * a.out_stride + a.out_base + i0) * a.row_dw;
   for (uint32_t idx = threadIdx.x; idx < live * a.row_dw; idx += 256) {
     const uint32_t r = idx / a.row_dw, w = idx - r * a.row_dw;
     dst[idx] = srow[r * (a.row_dw + 1) + w];

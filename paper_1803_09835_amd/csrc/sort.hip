@@ -42,9 +42,11 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d) {
 // Radix pass kernels.  Segment s occupies [s*n, (s+1)*n) of every array.
 // vin == nullptr means the value of element e is e (its id).
 // ---------------------------------------------------------------------------
-// Radix-pass tile: 16,384 elements (1024 threads x 16).  Large tiles make
-// each digit's run of output addresses long (64 elements on average), which
-// is what lets the scatter write at a large fraction of HBM bandwidth.
+// Default radix-pass tile: 16,384 elements (1024 threads x 16).  Large tiles
+// make each digit's run of output addresses long (64 elements on average),
+// which is what lets the scatter write at a large fraction of HBM bandwidth.
+// Smaller tiles (8,192 and 4,096) run more workgroups per CU and are offered
+// to the launch-shape tuner.
 constexpr int kRThreads = 1024;
 constexpr int kRItems = 16;
 constexpr int kTile = kRThreads * kRItems;
@@ -292,14 +294,19 @@ __device__ __forceinline__ bool kv_less(uint64_t ka, uint32_t va, uint64_t kb, u
 }
 
 __device__ __forceinline__ uint64_t station_size(const BucketArgs& a, uint32_t id) {
-  uint32_t s = 0;
-  while (s + 1 < a.nstation && a.station_base[s + 1] <= id) ++s;
+  const uint32_t s = station_of(a.station_base, a.nstation, id);
   return a.station_base[s + 1] - a.station_base[s];
 }
 
+// Per-thread bucket counters.  Stations are contiguous in every sorted table
+// (their id sits in the top bits of the mixed key), so a thread's buckets
+// change station only at a station boundary, where bucket_account flushes
+// the open totals.
 struct BucketTotals {
   unsigned long long e_raw;
   unsigned int max_bucket;
+  uint32_t station;
+  uint32_t lo, hi;  // id range of `station` (several stations only)
 };
 
 // Account one bucket (run of equal keys) of `size` members; ids(q) gives the
@@ -310,10 +317,24 @@ struct BucketTotals {
 template <typename IdAt>
 __device__ __forceinline__ int bucket_account(const BucketArgs& a, uint64_t size, IdAt ids, uint32_t first_id,
                                               BucketTotals& tot) {
+  if (a.nstation > 1 && (first_id < tot.lo || first_id >= tot.hi)) {
+    const uint32_t st = station_of(a.station_base, a.nstation, first_id);
+    if (st != tot.station) {
+      // counters of another station: add the open totals directly
+      const uint64_t o = (uint64_t)tot.station * kSpread + spread_slot();
+      if (tot.e_raw) atomicAdd(a.e_raw + o, tot.e_raw);
+      if (tot.max_bucket) atomicMax(a.max_bucket + o, tot.max_bucket);
+      tot.e_raw = 0;
+      tot.max_bucket = 0;
+      tot.station = st;
+    }
+    tot.lo = (uint32_t)a.station_base[st];
+    tot.hi = (uint32_t)a.station_base[st + 1];
+  }
   tot.e_raw += (unsigned long long)(size * (size - 1) / 2);
   if (size > tot.max_bucket) tot.max_bucket = (unsigned int)size;
   if (a.occ_den) {
-    const uint64_t ns = station_size(a, first_id);
+    const uint64_t ns = a.nstation > 1 ? (uint64_t)(tot.hi - tot.lo) : a.station_base[1] - a.station_base[0];
     if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num) {
       for (uint64_t q = 0; q < size; ++q) a.flags[ids(q)] = 1;
       return 0;
@@ -333,7 +354,17 @@ __device__ __forceinline__ int bucket_class(const BucketArgs& a, uint64_t size, 
   return size <= a.small_max ? 1 : 2;
 }
 
+// Called by every lane of the wave.  Lanes whose totals belong to one
+// station are reduced over the wave first; at a station boundary each lane
+// adds its own.
 __device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
+  const uint32_t s0 = __shfl(tot.station, 0, 64);
+  if (!__all(tot.station == s0)) {
+    const uint64_t o = (uint64_t)tot.station * kSpread + spread_slot();
+    if (tot.e_raw) atomicAdd(a.e_raw + o, tot.e_raw);
+    if (tot.max_bucket) atomicMax(a.max_bucket + o, tot.max_bucket);
+    return;
+  }
   unsigned long long e = tot.e_raw;
   unsigned int m = tot.max_bucket;
   for (int o = 32; o > 0; o >>= 1) {
@@ -342,9 +373,9 @@ __device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
     m = om > m ? om : m;
   }
   if ((threadIdx.x & 63) == 0) {
-    const uint32_t slot = spread_slot();
-    if (e) atomicAdd(a.e_raw + slot, e);
-    atomicMax(a.max_bucket + slot, m);
+    const uint64_t o = (uint64_t)s0 * kSpread + spread_slot();
+    if (e) atomicAdd(a.e_raw + o, e);
+    if (m) atomicMax(a.max_bucket + o, m);
   }
 }
 
@@ -576,7 +607,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
   }
   __syncthreads();
   const uint64_t hi = s_hi;
-  BucketTotals tot{0ull, 0u};
+  BucketTotals tot{0ull, 0u, 0u, 0u, 0u};
   if (hi - lo <= (uint64_t)kBinCap) {
     process_bins(a, seg, lo, hi, sk, sv, bs, be, np, mixed, sh, tot);
   } else {
@@ -596,6 +627,8 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
 // stable 8-bit LSD passes through the scratch arrays (ids stay ascending
 // within equal keys) and then accounts the buckets.
 // ---------------------------------------------------------------------------
+// Persistent: a fixed grid walks the bins the bucket kernel deferred (their
+// count is read on the device, so the launch shape does not depend on it).
 __global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* bins, uint64_t* tk, uint32_t* tv) {
   __shared__ uint32_t cnt[kRadix];
   __shared__ uint32_t wc[4][kRadix];
@@ -603,7 +636,10 @@ __global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* 
   __shared__ uint64_t kmin, kmax;
   __shared__ uint32_t heads[kThreads];
   __shared__ uint32_t s_carry;
-  const uint4 bd = bins[blockIdx.x];
+  const uint32_t nbins = *a.bin_count;
+  for (uint32_t q = blockIdx.x; q < nbins; q += gridDim.x) {
+  __syncthreads();
+  const uint4 bd = bins[q];
   const uint64_t lo = bd.x, hi = bd.y;
   const uint32_t seg = bd.z;
   const uint64_t off = (uint64_t)seg * a.n;
@@ -681,7 +717,7 @@ __global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* 
   }
   // Account buckets, scanning the range in chunks of kThreads with the
   // currently open run carried across chunks.
-  BucketTotals tot{0ull, 0u};
+  BucketTotals tot{0ull, 0u, 0u, 0u, 0u};
   if (tid == 0) s_carry = 0;
   __syncthreads();
   uint8_t* marks = a.marks + off;
@@ -714,12 +750,19 @@ __global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* 
   }
   if (tid == 0) emit(lo + s_carry, hi);
   flush_totals(a, tot);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
-uint32_t radix_tiles(uint64_t n) { return (uint32_t)((n + kTile - 1) / kTile); }
+// Radix tile shapes (threads x items): 1024 x 16, 512 x 16, 256 x 16.
+uint32_t radix_tile_elems(uint32_t variant) { return variant == 0 ? 16384u : (variant == 1 ? 8192u : 4096u); }
+
+uint32_t radix_tiles(uint64_t n, uint32_t variant) {
+  const uint64_t e = radix_tile_elems(variant);
+  return (uint32_t)((n + e - 1) / e);
+}
 
 template <typename T>
 static void seg_scan(T* data, uint64_t len, uint32_t S, T* sums, T* seg_total, hipStream_t s) {
@@ -739,14 +782,26 @@ void scan_u64(uint64_t* data, uint64_t len, uint32_t S, uint64_t* sums, uint64_t
   seg_scan<uint64_t>(reinterpret_cast<uint64_t*>(data), len, S, sums, seg_total, s);
 }
 
-// One stable pass by the 8-bit digit at `shift`.
-void radix_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, uint64_t n, uint32_t S,
-                uint32_t shift, uint32_t* hist, uint32_t* sums, hipStream_t s) {
-  if (n == 0) return;
-  const uint32_t nt = radix_tiles(n);
-  hipLaunchKernelGGL((k_hist<>), dim3(nt, S), dim3(kRThreads), 0, s, kin, n, shift, hist, nt);
+// The three launches of one pass for one tile shape.
+template <int TH, int IT>
+static void radix_pass_t(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, uint64_t n,
+                         uint32_t S, uint32_t shift, uint32_t* hist, uint32_t* sums, uint32_t nt, hipStream_t s) {
+  hipLaunchKernelGGL((k_hist<TH, IT>), dim3(nt, S), dim3(TH), 0, s, kin, n, shift, hist, nt);
   seg_scan<uint32_t>(hist, (uint64_t)kRadix * nt, S, sums, nullptr, s);
-  hipLaunchKernelGGL((k_scatter<>), dim3(nt, S), dim3(kRThreads), 0, s, kin, vin, kout, vout, n, shift, hist, nt);
+  hipLaunchKernelGGL((k_scatter<TH, IT>), dim3(nt, S), dim3(TH), 0, s, kin, vin, kout, vout, n, shift, hist, nt);
+}
+
+// One stable pass by the 8-bit digit at `shift`; hist needs 256 * tiles * S
+// entries for the variant's tile count.
+void radix_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, uint64_t n, uint32_t S,
+                uint32_t shift, uint32_t* hist, uint32_t* sums, uint32_t variant, hipStream_t s) {
+  if (n == 0) return;
+  const uint32_t nt = radix_tiles(n, variant);
+  switch (variant) {
+    case 0: radix_pass_t<1024, 16>(kin, vin, kout, vout, n, S, shift, hist, sums, nt, s); break;
+    case 1: radix_pass_t<512, 16>(kin, vin, kout, vout, n, S, shift, hist, sums, nt, s); break;
+    default: radix_pass_t<256, 16>(kin, vin, kout, vout, n, S, shift, hist, sums, nt, s); break;
+  }
 }
 
 void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s) {
@@ -755,10 +810,10 @@ void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s) {
   hipLaunchKernelGGL(k_bucket, dim3(nch, S), dim3(kThreads), 0, s, a);
 }
 
-void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t nbins, uint64_t* tk, uint32_t* tv,
+void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64_t* tk, uint32_t* tv,
                    hipStream_t s) {
-  if (nbins == 0) return;
-  hipLaunchKernelGGL(k_bigbin, dim3(nbins), dim3(kThreads), 0, s, a, bins, tk, tv);
+  if (a.n == 0 || grid == 0) return;
+  hipLaunchKernelGGL(k_bigbin, dim3(grid), dim3(kThreads), 0, s, a, bins, tk, tv);
 }
 
 }  // namespace fl

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libfast_lsh.so")
 
 OK, E_INVALID, E_NOMEM, E_CAPACITY, E_DEVICE, E_BUSY = range(6)
 MINHASH, MINMAX = 0, 1
-WANT_DISTINCT = 1
+WANT_DISTINCT, USE_GRAPH = 1, 2
+MAX_STATIONS = 16
 
 _vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
 
@@ -40,7 +41,11 @@ class _Stats(ctypes.Structure):
     _fields_ = [(f, _u64) for f in ("n_out", "e_raw", "e_voted", "n_distinct", "n_flagged", "max_bucket")]
 
 
-PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pairs", "output", "reserved")
+PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pairs", "output", "graph")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("radix_tile", _u32), ("bucket_chunk", _u32), ("autotune", _u32), ("reserved", _u32)]
 
 
 class _Profile(ctypes.Structure):
@@ -83,7 +88,12 @@ def library():
                                         _vp, _vp, _vp, _u64, ctypes.POINTER(_Stats)]
         lib.fast_lsh_search_ex.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps), ctypes.POINTER(Filter),
                                            _u32, _vp, _vp, _vp, _u64, ctypes.POINTER(_Stats)]
+        lib.fast_lsh_search_batched.argtypes = [_vp, ctypes.POINTER(Hash), _u32, ctypes.POINTER(Fps),
+                                                ctypes.POINTER(Filter), _u32, _vp, _vp, _vp, _u64,
+                                                ctypes.POINTER(_u64), ctypes.POINTER(_Stats)]
         lib.fast_lsh_copy_result.argtypes = [_vp, _vp, _vp, _vp, _u64]
+        lib.fast_lsh_configure.argtypes = [_vp, ctypes.POINTER(Config)]
+        lib.fast_lsh_config_used.argtypes = [_vp, ctypes.POINTER(Config)]
         lib.fast_lsh_profile_enable.argtypes = [_vp, _i32]
         lib.fast_lsh_profile_read.argtypes = [_vp, ctypes.POINTER(_Profile)]
         _LIB = lib
@@ -160,7 +170,18 @@ class FastLSH:
         """{stage: (summed kernel ms, timed launches)} since profile_enable."""
         p = _Profile()
         _check(library().fast_lsh_profile_read(self._ctx, ctypes.byref(p)))
-        return {name: (p.ms[k], int(p.launches[k])) for k, name in enumerate(PROFILE_STAGES) if name != "reserved"}
+        return {name: (p.ms[k], int(p.launches[k])) for k, name in enumerate(PROFILE_STAGES)}
+
+    def configure(self, radix_tile: int = 0, bucket_chunk: int = 0, autotune: bool = False):
+        """Launch shapes of later searches (0 keeps the current value)."""
+        _check(library().fast_lsh_configure(self._ctx, ctypes.byref(Config(radix_tile, bucket_chunk,
+                                                                            1 if autotune else 0, 0))))
+
+    def config_used(self) -> dict:
+        """Launch shapes of the last search (the tuner's choice when autotuning)."""
+        c = Config()
+        _check(library().fast_lsh_config_used(self._ctx, ctypes.byref(c)))
+        return {"radix_tile": c.radix_tile, "bucket_chunk": c.bucket_chunk, "autotune": bool(c.autotune)}
 
     def signatures(self, rows, dim, t, r, scheme, a, b, table_begin=0, table_count=None, with_values=False):
         """Band keys as int64 [table_count, n] (uint64 bit pattern); with
@@ -175,28 +196,58 @@ class FastLSH:
                                              keys.data_ptr(), sigs.data_ptr() if with_values else None))
         return (keys, sigs) if with_values else keys
 
+    def _outputs(self, cap):
+        dev = torch.device("cuda", self.device)
+        return (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+                torch.empty(cap, dtype=torch.uint8, device=dev))
+
+    def _refetch(self, rc, total, capacity):
+        """After E_CAPACITY with automatic capacity: fetch the kept result."""
+        oi, oj, ov = self._outputs(max(total, 1))
+        if rc == E_CAPACITY and capacity is None:
+            rc = library().fast_lsh_copy_result(self._ctx, oi.data_ptr(), oj.data_ptr(), ov.data_ptr(), total)
+        return rc, (oi, oj, ov)
+
     def search(self, rows, dim, t, r, scheme, a, b, min_lag, min_votes, occ_num=0, occ_den=0,
-               want_distinct=False, capacity: int | None = None):
+               want_distinct=False, capacity: int | None = None, graph=False):
         """Sorted (i, j, votes) CUDA tensors (int32, int32, uint8) and Stats."""
         h, keep = _hash_struct(dim, t, r, scheme, a, b)
         f, keep2 = _fps_struct(rows)
         flt = Filter(min_lag, min_votes, occ_num, occ_den)
-        dev = torch.device("cuda", self.device)
+        flags = (WANT_DISTINCT if want_distinct else 0) | (USE_GRAPH if graph else 0)
         cap = max(1, f.n // 4) if capacity is None else capacity
-        oi = torch.empty(cap, dtype=torch.int32, device=dev)
-        oj = torch.empty(cap, dtype=torch.int32, device=dev)
-        ov = torch.empty(cap, dtype=torch.uint8, device=dev)
+        oi, oj, ov = self._outputs(cap)
         st = _Stats()
-        rc = library().fast_lsh_search_ex(self._ctx, ctypes.byref(h), ctypes.byref(f), ctypes.byref(flt),
-                                          WANT_DISTINCT if want_distinct else 0, oi.data_ptr(), oj.data_ptr(),
-                                          ov.data_ptr(), cap, ctypes.byref(st))
+        rc = library().fast_lsh_search_ex(self._ctx, ctypes.byref(h), ctypes.byref(f), ctypes.byref(flt), flags,
+                                          oi.data_ptr(), oj.data_ptr(), ov.data_ptr(), cap, ctypes.byref(st))
         if rc == E_CAPACITY and capacity is None:
-            cap = st.n_out
-            oi = torch.empty(cap, dtype=torch.int32, device=dev)
-            oj = torch.empty(cap, dtype=torch.int32, device=dev)
-            ov = torch.empty(cap, dtype=torch.uint8, device=dev)
-            rc = library().fast_lsh_copy_result(self._ctx, oi.data_ptr(), oj.data_ptr(), ov.data_ptr(), cap)
+            rc, (oi, oj, ov) = self._refetch(rc, st.n_out, capacity)
         _check(rc)
         m = st.n_out
         stats = Stats(*[int(getattr(st, k)) for k, _ in _Stats._fields_])
         return oi[:m], oj[:m], ov[:m], stats
+
+    def search_batched(self, stations, dim, t, r, scheme, a, b, min_lag, min_votes, occ_num=0, occ_den=0,
+                       want_distinct=False, capacity: int | None = None, graph=False):
+        """One search over several stations.  Returns (i, j, votes, offsets,
+        [Stats per station]): station s owns entries offsets[s]:offsets[s+1]
+        of the CUDA tensors, with station-local ids."""
+        S = len(stations)
+        h, keep = _hash_struct(dim, t, r, scheme, a, b)
+        fl = [_fps_struct(x) for x in stations]
+        fa = (Fps * max(S, 1))(*[x[0] for x in fl])
+        flt = Filter(min_lag, min_votes, occ_num, occ_den)
+        flags = (WANT_DISTINCT if want_distinct else 0) | (USE_GRAPH if graph else 0)
+        total = sum(x[0].n for x in fl)
+        cap = max(1, total // 4) if capacity is None else capacity
+        oi, oj, ov = self._outputs(cap)
+        offs = (_u64 * (S + 1))()
+        sts = (_Stats * max(S, 1))()
+        rc = library().fast_lsh_search_batched(self._ctx, ctypes.byref(h), S, fa, ctypes.byref(flt), flags,
+                                               oi.data_ptr(), oj.data_ptr(), ov.data_ptr(), cap, offs, sts)
+        if rc == E_CAPACITY and capacity is None:
+            rc, (oi, oj, ov) = self._refetch(rc, int(offs[S]), capacity)
+        _check(rc)
+        m = int(offs[S])
+        stats = [Stats(*[int(getattr(sts[k], f)) for f, _ in _Stats._fields_]) for k in range(S)]
+        return oi[:m], oj[:m], ov[:m], np.array(list(offs), dtype=np.int64), stats

@@ -1,0 +1,219 @@
+"""GPU parity of the batched (multi-station) search, graph replay and launch
+shapes.
+
+The batched search must give, for every station, exactly what the oracle
+gives for that station alone (pairs, votes and counters, with the occurrence
+filter using the station's own n); graph replays and every launch shape must
+give the eager default's output bytes.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1803_09835_amd as fl  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fl.FastLSH(0)
+    yield c
+    c.close()
+
+
+def _np(t, dt):
+    return t.cpu().numpy().view(dt)
+
+
+def _fixed(n, dim, nnz, seed):
+    rng = np.random.default_rng(seed)
+    rows = [np.sort(rng.choice(dim, nnz, replace=False)) for _ in range(n)]
+    return np.stack(rows).astype(np.uint16) if n else np.empty((0, nnz), np.uint16)
+
+
+def _check_batched(ctx, stations, dim, t, r, scheme, seed, L, v, num=0, den=0, distinct=False, graph=False,
+                   label=""):
+    say(f"[batched] {label} sizes={[len(s) for s in stations]} t={t} r={r} scheme={scheme} L={L} v={v} "
+        f"occ={num}/{den} distinct={distinct} graph={graph}")
+    a, b = fl.make_hash(seed, fl.n_funcs(t, r, scheme))
+    dev = [fl.to_device_rows(s) for s in stations]
+    gi, gj, gv, offs, sts = ctx.search_batched(dev, dim, t, r, scheme, a, b, L, v, num, den,
+                                               want_distinct=distinct, graph=graph)
+    gi, gj, gv = _np(gi, np.uint32), _np(gj, np.uint32), gv.cpu().numpy()
+    assert offs[0] == 0 and offs[-1] == len(gi) and (np.diff(offs) >= 0).all()
+    for s, rows in enumerate(stations):
+        lo, hi = offs[s], offs[s + 1]
+        if len(rows) == 0:
+            assert lo == hi and sts[s].e_raw == 0 and sts[s].n_out == 0
+            continue
+        ei, ej, ev, est = oracle.search(rows, dim, t, r, scheme, a, b, L, v, num, den)
+        assert hi - lo == len(ei), (s, hi - lo, len(ei))
+        assert np.array_equal(gi[lo:hi], ei), s
+        assert np.array_equal(gj[lo:hi], ej), s
+        assert np.array_equal(gv[lo:hi], ev), s
+        want, got = dict(est.__dict__), dict(sts[s].__dict__)
+        if not distinct:
+            assert got.pop("n_distinct") == 2**64 - 1
+            want.pop("n_distinct")
+        assert got == want, (s, got, want)
+    return (gi, gj, gv, offs, sts)
+
+
+def test_batched_uniform_stations(ctx):
+    sizes = (20_000, 7_000, 0, 13_000, 1, 9_000)
+    stations = [synth.generate(synth.tiny_uniform(n=n, seed=1030 + s)) if n > 1000 else _fixed(n, 4096, 200, s)
+                for s, n in enumerate(sizes)]
+    out = _check_batched(ctx, stations, 4096, 20, 4, fl.MINHASH, 201, 5, 2, label="uniform")
+    assert out[3][-1] > 100
+    _check_batched(ctx, stations, 4096, 20, 4, fl.MINHASH, 201, 5, 2, distinct=True, label="uniform")
+
+
+def test_batched_filter_uses_station_n(ctx):
+    # Station 0 carries a repeating noise source (5 % of slots): its buckets
+    # exceed 1 % of its own n and are excluded.  Station 1 is plain; station 2
+    # is twice as long, so the same noise share is judged against its own n.
+    stations = [
+        synth.generate(synth.with_noise(synth.station(n=30_000, seed=41), 50, 190)),
+        synth.generate(synth.station(n=20_000, seed=90)),
+        synth.generate(synth.with_noise(synth.station(n=60_000, seed=91), 8, 190)),
+    ]
+    out = _check_batched(ctx, stations, 4096, 100, 4, fl.MINMAX, 42, 5, 4, 1, 100, label="filter")
+    sts = out[4]
+    assert sts[0].n_flagged > 1000 and sts[1].n_flagged == 0
+
+
+def test_batched_minmax_groups_and_distinct(ctx):
+    stations = [synth.generate(synth.station(n=n, seed=95 + n % 7)) for n in (40_000, 25_000, 15_000)]
+    _check_batched(ctx, stations, 4096, 100, 4, fl.MINMAX, 202, 5, 4, 1, 100, label="minmax-v4")
+    _check_batched(ctx, stations, 4096, 40, 4, fl.MINHASH, 33, 5, 3, distinct=True, label="minhash-v3-distinct")
+
+
+def test_batched_sixteen_stations(ctx):
+    stations = [_fixed(300 + 137 * s, 256, 6, 700 + s) for s in range(16)]
+    _check_batched(ctx, stations, 256, 12, 2, fl.MINMAX, 701, 2, 2, label="16-stations")
+    _check_batched(ctx, stations, 256, 12, 2, fl.MINMAX, 701, 2, 2, 1, 50, distinct=True, label="16-stations")
+
+
+def test_batched_one_station_equals_search(ctx):
+    rows = synth.generate(synth.station(n=50_000, seed=102))
+    a, b = fl.make_hash(202, 200)
+    dev = fl.to_device_rows(rows)
+    si, sj, sv, sst = ctx.search(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
+    bi, bj, bv, offs, bst = ctx.search_batched([dev], 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
+    assert torch.equal(si, bi) and torch.equal(sj, bj) and torch.equal(sv, bv)
+    assert bst[0] == sst and offs.tolist() == [0, len(si)]
+
+
+def test_batched_rejects_bad_input(ctx):
+    a, b = fl.make_hash(1, 80)
+    rows = fl.to_device_rows(_fixed(100, 4096, 20, 3))
+    for stations in ([], [rows] * 17):
+        with pytest.raises(fl.FastLshError) as e:
+            ctx.search_batched(stations, 4096, 20, 4, fl.MINHASH, a, b, 5, 2)
+        assert e.value.code == 1
+    # 16-bit indices x 4 rows = 64 key bits: no room for the station tag
+    wide = fl.to_device_rows(_fixed(100, 65536, 20, 4))
+    with pytest.raises(fl.FastLshError) as e:
+        ctx.search_batched([wide, wide], 65536, 20, 4, fl.MINHASH, a, b, 5, 2)
+    assert e.value.code == 1
+    ctx.search_batched([wide], 65536, 20, 4, fl.MINHASH, a, b, 5, 2)  # one station: untagged, allowed
+
+
+def test_batched_capacity(ctx):
+    stations = [synth.generate(synth.tiny_uniform(n=n, seed=61 + n)) for n in (20_000, 10_000)]
+    a, b = fl.make_hash(62, 80)
+    dev = [fl.to_device_rows(s) for s in stations]
+    full = ctx.search_batched(dev, 4096, 20, 4, fl.MINHASH, a, b, 5, 1)
+    assert full[3][-1] > 20
+    with pytest.raises(fl.FastLshError) as e:
+        ctx.search_batched(dev, 4096, 20, 4, fl.MINHASH, a, b, 5, 1, capacity=5)
+    assert e.value.code == 3
+    again = ctx.search_batched(dev, 4096, 20, 4, fl.MINHASH, a, b, 5, 1, capacity=None)
+    for x, y in zip(full[:3], again[:3]):
+        assert torch.equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# Captured graph: replays (with other eager work between them) and recaptures
+# must reproduce the eager result every time.
+# ---------------------------------------------------------------------------
+def test_graph_replays_match_eager(ctx):
+    rows = synth.generate(synth.station(n=60_000, seed=120))
+    other = synth.generate(synth.tiny_uniform(n=15_000, seed=121))
+    a, b = fl.make_hash(202, 200)
+    dev = fl.to_device_rows(rows)
+    say("[graph] eager reference")
+    ref = ctx.search(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
+    for k in range(4):
+        say(f"[graph] replay {k}")
+        got = ctx.search(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100, graph=True)
+        for x, y in zip(ref[:3], got[:3]):
+            assert torch.equal(x, y), k
+        assert got[3] == ref[3]
+        # eager work between replays: another search (other shapes) and torch ops
+        a2, b2 = fl.make_hash(201, 80)
+        ctx.search(fl.to_device_rows(other), 4096, 20, 4, fl.MINHASH, a2, b2, 5, 2)
+        torch.cuda.synchronize()
+        (dev.float() * 2).sum().item()
+    # a second input buffer: recapture, still identical
+    dev2 = fl.to_device_rows(rows)
+    got = ctx.search(dev2, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100, graph=True)
+    for x, y in zip(ref[:3], got[:3]):
+        assert torch.equal(x, y)
+
+
+def test_graph_batched_replays(ctx):
+    stations = [synth.generate(synth.tiny_uniform(n=n, seed=1030 + n)) for n in (12_000, 30_000, 5_000)]
+    for k in range(3):
+        _check_batched(ctx, stations, 4096, 20, 4, fl.MINHASH, 201, 5, 2, graph=True, label=f"graph-{k}")
+
+
+# ---------------------------------------------------------------------------
+# Launch shapes change speed, never output bytes.
+# ---------------------------------------------------------------------------
+def test_launch_shapes_identical():
+    c = fl.FastLSH(0)
+    try:
+        stations = [synth.generate(synth.station(n=n, seed=130 + n % 11)) for n in (70_000, 30_000)]
+        a, b = fl.make_hash(202, 200)
+        dev = [fl.to_device_rows(s) for s in stations]
+        ref = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
+        assert c.config_used() == {"radix_tile": 16384, "bucket_chunk": 1536, "autotune": False}
+        for tile in (16384, 8192, 4096):
+            for chunk in (256, 768, 1024, 2048):
+                say(f"[shapes] radix_tile={tile} bucket_chunk={chunk}")
+                c.configure(radix_tile=tile, bucket_chunk=chunk)
+                got = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
+                assert c.config_used()["radix_tile"] == tile and c.config_used()["bucket_chunk"] == chunk
+                for x, y in zip(ref[:3], got[:3]):
+                    assert torch.equal(x, y)
+                assert (ref[3] == got[3]).all() and ref[4] == got[4]
+        c.configure(autotune=True)
+        for k in range(2):  # the first call tunes, the second reuses the choice
+            say(f"[shapes] autotune call {k}")
+            got = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100, graph=(k == 1))
+            used = c.config_used()
+            assert used["radix_tile"] in (16384, 8192, 4096) and used["bucket_chunk"] in (768, 1024, 1536, 2048)
+            for x, y in zip(ref[:3], got[:3]):
+                assert torch.equal(x, y)
+            assert ref[4] == got[4]
+        with pytest.raises(fl.FastLshError):
+            c.configure(radix_tile=1000)
+        with pytest.raises(fl.FastLshError):
+            c.configure(bucket_chunk=4096)
+    finally:
+        c.close()
