@@ -43,6 +43,11 @@ OPS_PER_EVAL = {0: 5.5, 1: 6.0}  # MinHash, Min-Max
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--workload", choices=("station", "batched"), default="station",
+                    help="station: one 90-day station (default); batched: 12 stations of 1-16 M fingerprints "
+                         "in one search, against 12 sequential searches")
+    ap.add_argument("--graph", action="store_true", help="replay the captured graph of the search prefix")
+    ap.add_argument("--autotune", action="store_true", help="tune launch shapes on the first (warm-up) search")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -60,6 +65,14 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md, "
                                    "not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.workload == "batched":
+        # This mode's process ended with a host segmentation fault within its
+        # first seconds (while generating the 12 stations from 12 host threads),
+        # once in three runs; the cause is not known, so it stays switched off.
+        print(json.dumps({"error": "the batched workload mode is switched off: its process crashed on the host "
+                                   "during data generation and the cause is not yet known (see DESIGN.md)",
+                          "workload": "batched"}))
         sys.exit(2)
 
     import numpy as np
@@ -81,8 +94,11 @@ def main():
     print(f"# generated {N} fingerprints in {gen_s:.1f}s; warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
 
+    if args.autotune:
+        ctx.configure(autotune=True)
+
     def step():
-        return ctx.search(dev_rows, dim, t, r, scheme, a, b, L, v, occ_num, occ_den)
+        return ctx.search(dev_rows, dim, t, r, scheme, a, b, L, v, occ_num, occ_den, graph=args.graph)
 
     for _ in range(args.warmup):
         step()
@@ -111,7 +127,7 @@ def main():
     stage_ms = {k: ms / args.steps for k, (ms, n) in prof.items()}
     stage_launch = {k: n / args.steps for k, (ms, n) in prof.items()}
     dom = max(stage_ms, key=stage_ms.get)
-    if dom == "signatures":
+    if dom == "signatures" and stage_launch[dom]:
         evals = N * fl.n_funcs(t, r, scheme) * 200  # (fingerprint, function, set element)
         per_launch_ms = stage_ms[dom] / max(stage_launch[dom], 1)
         achieved = evals * OPS_PER_EVAL[scheme] / (per_launch_ms / 1000.0) / 1e12
@@ -144,6 +160,7 @@ def main():
         "candidate_pairs_per_s": round(st.e_raw / (ms_per_step / 1000.0), 1),
         "stats": st.__dict__,
         "stage_ms": {k: round(x, 3) for k, x in stage_ms.items()},
+        "launch_shapes": ctx.config_used(),
         "roofline": roof,
     }
 
@@ -160,6 +177,106 @@ def main():
             "sample": f"first {ns} fingerprints of the same workload, full search (signatures + votes), "
                       f"{cpu_s:.1f} s; the pair work grows with N so a slice under-states the full-size cost",
         }
+    print(json.dumps(line), flush=True)
+
+
+def main_batched(args):
+    """12 stations of the uniform generator (50 events x 5 copies each), one
+    batched search against 12 sequential single-station searches."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1803_09835_amd as fl
+
+    dim, t, r, scheme, L, v = 4096, 20, 4, fl.MINHASH, 5, 2
+    sizes = [m * 1_000_000 for m in synth.BATCH_LENGTHS_M]
+    specs = [synth.tiny_uniform(n=n, seed=1030 + s) for s, n in enumerate(sizes)]
+    tg = time.time()
+    with ThreadPoolExecutor(max_workers=12) as ex:
+        host = list(ex.map(synth.generate, specs))
+    dev = []
+    for h in host:
+        dev.append(fl.to_device_rows(h))
+    N = sum(sizes)
+    print(f"# generated and uploaded {N} fingerprints in {time.time() - tg:.1f}s", file=sys.stderr, flush=True)
+    a, b = fl.make_hash(201, fl.n_funcs(t, r, scheme))
+    ctx_b = fl.FastLSH(0)
+    ctx_s = fl.FastLSH(0)
+    if args.autotune:
+        ctx_b.configure(autotune=True)
+        ctx_s.configure(autotune=True)
+
+    def batched():
+        return ctx_b.search_batched(dev, dim, t, r, scheme, a, b, L, v, graph=args.graph)
+
+    def sequential():
+        return [ctx_s.search(d, dim, t, r, scheme, a, b, L, v, graph=args.graph) for d in dev]
+
+    def timed(fn, name, ctx):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            out = fn()
+            print(f"# {name} step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        prof = ctx.profile_read()
+        return out, ms, {k: round(x / args.steps, 3) for k, (x, n) in prof.items()}, prof
+
+    out_b, ms_b, stage_b, prof_b = timed(batched, "batched", ctx_b)
+    out_s, ms_s, stage_s, _ = timed(sequential, "sequential", ctx_s)
+    # the two must agree pair for pair
+    offs = out_b[3]
+    same = all(torch.equal(out_b[q][offs[s]:offs[s + 1]], out_s[s][q]) for s in range(len(dev)) for q in range(3))
+    same = same and all(out_b[4][s] == out_s[s][3] for s in range(len(dev)))
+
+    evals = N * fl.n_funcs(t, r, scheme) * 200
+    dom = max(stage_b, key=stage_b.get)
+    if prof_b["signatures"][1]:
+        sig_launch_ms = prof_b["signatures"][0] / prof_b["signatures"][1]
+        achieved = evals * OPS_PER_EVAL[scheme] / (sig_launch_ms / 1000.0) / 1e12
+        roof = {"kernel": "k_sig<200,minhash> (all stations)", "bound": "alu", "achieved": round(achieved, 2),
+                "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s (int32)",
+                "frac": round(achieved / INT_PEAK_TOPS, 4), "traffic": None, "launch_ms": round(sig_launch_ms, 3)}
+    else:  # kernels inside the replayed graph are not timed one by one
+        roof = None
+    line = {
+        "metric": "fingerprints/s through MinHash+LSH vote count",
+        "value": round(N / (ms_b / 1000.0), 1),
+        "unit": "fingerprints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "12 stations of 1-8, 10, 12, 14, 16 M fingerprints (88 M), uniform 200-of-4096 "
+                               "background with 50 events x 5 copies keeping 160 bits each; MinHash t=20 r=4, "
+                               "lag 5, v=2, no occurrence filter; one batched search",
+                   "n": N, "stations": len(sizes), "tables": t, "rows": r, "scheme": "minhash", "min_lag": L,
+                   "min_votes": v, "graph": args.graph, "autotune": args.autotune},
+        "sequential_ms_per_step": round(ms_s, 3),
+        "speedup_vs_sequential": round(ms_s / ms_b, 3),
+        "identical_to_sequential": bool(same),
+        "n_out": int(offs[-1]),
+        "e_raw": int(sum(st.e_raw for st in out_b[4])),
+        "stage_ms": stage_b,
+        "sequential_stage_ms": stage_s,
+        "launch_shapes": ctx_b.config_used(),
+        "dominant_stage": dom,
+        "roofline": roof,
+    }
+    if args.cpu_sample > 0:
+        import oracle
+        rows = host[0][: min(args.cpu_sample, len(host[0]))]
+        tc = time.perf_counter()
+        oracle.search(rows, dim, t, r, oracle.MINHASH, a, b, L, v)
+        cpu_s = time.perf_counter() - tc
+        line["cpu_baseline"] = {"value": round(len(rows) / cpu_s, 1), "unit": "fingerprints/s",
+                                "cores": oracle.max_threads(), "kind": "oracle",
+                                "sample": f"the 1 M-fingerprint station searched alone, {cpu_s:.1f} s"}
     print(json.dumps(line), flush=True)
 
 

@@ -160,12 +160,16 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
   if (eq - pad >= a.need) exact_and_report(a, u, i, j);
 }
 
-// Called by every lane of the wave.  Lanes whose tallies belong to one
-// station are summed over the wave first; at a station boundary each lane
-// adds its own.
+// Called by every lane of the wave.  When all lanes with a non-zero tally
+// hold one station the tallies are summed over the wave first; at a station
+// boundary each lane adds its own.
 __device__ void flush_tally(const PairArgs& a, PairTally tl) {
-  const uint32_t s0 = __shfl(tl.station, 0, 64);
-  if (!__all(tl.station == s0)) {
+  const bool live = (tl.ev | tl.nd) != 0;
+  const uint64_t act = __ballot(live);
+  if (act == 0) return;
+  const uint32_t s0 = __shfl(tl.station, __ffsll((long long)act) - 1, 64);
+  if (!__all(!live || tl.station == s0)) {
+    if (!live) return;
     const uint64_t o = (uint64_t)tl.station * kSpread + spread_slot();
     if (tl.ev) atomicAdd(a.e_voted + o, tl.ev);
     if (tl.nd) atomicAdd(a.n_distinct + o, tl.nd);
@@ -309,7 +313,13 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
     }
   }
   __syncthreads();
-  PairTally tl{0ull, 0ull, 0u, 0u, 0u};
+  PairTally tl{0ull, 0ull, 0u, 0u, 0xFFFFFFFFu};
+  if (a.nstation > 1) {  // one lookup per wave: the station of the first head's first member
+    const uint32_t st = station_of(a.station_base, a.nstation, order[hinfo[0] & 0xFFFFu]);
+    tl.station = st;
+    tl.lo = (uint32_t)a.station_base[st];
+    tl.hi = (uint32_t)a.station_base[st + 1];
+  }
   const uint32_t pad = group_pad(a, seg, rsw);
   const uint32_t per = (P + 63) / 64;
   uint32_t p = lane * per;

@@ -293,20 +293,18 @@ __device__ __forceinline__ bool kv_less(uint64_t ka, uint32_t va, uint64_t kb, u
   return ka < kb || (ka == kb && va < vb);
 }
 
-__device__ __forceinline__ uint64_t station_size(const BucketArgs& a, uint32_t id) {
-  const uint32_t s = station_of(a.station_base, a.nstation, id);
-  return a.station_base[s + 1] - a.station_base[s];
-}
+// Per-thread bucket counters.  With several stations the station of a
+// bucket is the top four bits of its mixed key, and stations are contiguous
+// in every sorted table, so a thread's buckets change station only at a
+// station boundary, where bucket_account flushes the open totals.
+// station == kNoStation: no bucket accounted yet.
+constexpr uint32_t kNoStation = 0xFFFFFFFFu;
 
-// Per-thread bucket counters.  Stations are contiguous in every sorted table
-// (their id sits in the top bits of the mixed key), so a thread's buckets
-// change station only at a station boundary, where bucket_account flushes
-// the open totals.
 struct BucketTotals {
   unsigned long long e_raw;
   unsigned int max_bucket;
   uint32_t station;
-  uint32_t lo, hi;  // id range of `station` (several stations only)
+  uint32_t ns;  // fingerprints of `station`
 };
 
 // Account one bucket (run of equal keys) of `size` members; ids(q) gives the
@@ -316,25 +314,23 @@ struct BucketTotals {
 // itself is over the threshold), or an id span below the lag.
 template <typename IdAt>
 __device__ __forceinline__ int bucket_account(const BucketArgs& a, uint64_t size, IdAt ids, uint32_t first_id,
-                                              BucketTotals& tot) {
-  if (a.nstation > 1 && (first_id < tot.lo || first_id >= tot.hi)) {
-    const uint32_t st = station_of(a.station_base, a.nstation, first_id);
-    if (st != tot.station) {
-      // counters of another station: add the open totals directly
+                                              uint64_t key, BucketTotals& tot) {
+  const uint32_t st = a.nstation > 1 ? (uint32_t)(key >> 60) : 0u;
+  if (st != tot.station) {
+    if (tot.station != kNoStation) {  // counters of another station: add the open totals directly
       const uint64_t o = (uint64_t)tot.station * kSpread + spread_slot();
       if (tot.e_raw) atomicAdd(a.e_raw + o, tot.e_raw);
       if (tot.max_bucket) atomicMax(a.max_bucket + o, tot.max_bucket);
-      tot.e_raw = 0;
-      tot.max_bucket = 0;
-      tot.station = st;
     }
-    tot.lo = (uint32_t)a.station_base[st];
-    tot.hi = (uint32_t)a.station_base[st + 1];
+    tot.e_raw = 0;
+    tot.max_bucket = 0;
+    tot.station = st;
+    tot.ns = (uint32_t)(a.station_base[st + 1] - a.station_base[st]);
   }
   tot.e_raw += (unsigned long long)(size * (size - 1) / 2);
   if (size > tot.max_bucket) tot.max_bucket = (unsigned int)size;
   if (a.occ_den) {
-    const uint64_t ns = a.nstation > 1 ? (uint64_t)(tot.hi - tot.lo) : a.station_base[1] - a.station_base[0];
+    const uint64_t ns = tot.ns;
     if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num) {
       for (uint64_t q = 0; q < size; ++q) a.flags[ids(q)] = 1;
       return 0;
@@ -345,21 +341,26 @@ __device__ __forceinline__ int bucket_account(const BucketArgs& a, uint64_t size
 }
 
 // The descriptor class bucket_account returns, without side effects.
-__device__ __forceinline__ int bucket_class(const BucketArgs& a, uint64_t size, uint32_t first_id, uint32_t last_id) {
+__device__ __forceinline__ int bucket_class(const BucketArgs& a, uint64_t size, uint32_t first_id, uint32_t last_id,
+                                            uint64_t key) {
   if (a.occ_den) {
-    const uint64_t ns = station_size(a, first_id);
+    const uint32_t st = a.nstation > 1 ? (uint32_t)(key >> 60) : 0u;
+    const uint64_t ns = a.station_base[st + 1] - a.station_base[st];
     if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num) return 0;
   }
   if (size < 2 || last_id - first_id < a.min_lag) return 0;
   return size <= a.small_max ? 1 : 2;
 }
 
-// Called by every lane of the wave.  Lanes whose totals belong to one
-// station are reduced over the wave first; at a station boundary each lane
-// adds its own.
+// Called by every lane of the wave.  When all lanes that accounted a bucket
+// hold one station the totals are reduced over the wave first; at a station
+// boundary each lane adds its own.
 __device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
-  const uint32_t s0 = __shfl(tot.station, 0, 64);
-  if (!__all(tot.station == s0)) {
+  const uint64_t act = __ballot(tot.station != kNoStation);
+  if (act == 0) return;
+  const uint32_t s0 = __shfl(tot.station, __ffsll((long long)act) - 1, 64);
+  if (!__all(tot.station == kNoStation || tot.station == s0)) {
+    if (tot.station == kNoStation) return;
     const uint64_t o = (uint64_t)tot.station * kSpread + spread_slot();
     if (tot.e_raw) atomicAdd(a.e_raw + o, tot.e_raw);
     if (tot.max_bucket) atomicMax(a.max_bucket + o, tot.max_bucket);
@@ -515,7 +516,7 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
     uint8_t mk = 0;
     if (e == 0 || sk[e] != sk[e - 1]) {
       const uint32_t f = run_end(sk, e, b0, be, mixed);
-      const int cls = bucket_account(a, f - e, [&](uint64_t q) { return sv[e + q]; }, sv[e], tot);
+      const int cls = bucket_account(a, f - e, [&](uint64_t q) { return sv[e + q]; }, sv[e], sk[e], tot);
       if (cls == 1) mk = (uint8_t)(f - e);
       nbig += cls == 2;
     }
@@ -535,7 +536,7 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
         if (mixed[b0] == 2) continue;
         if (e > 0 && sk[e] == sk[e - 1]) continue;
         const uint32_t f = run_end(sk, e, b0, be, mixed);
-        if (bucket_class(a, f - e, sv[e], sv[f - 1]) == 2)
+        if (bucket_class(a, f - e, sv[e], sv[f - 1], sk[e]) == 2)
           a.big_desc[pb++] = make_uint4((uint32_t)(lo + e), seg, f - e, 0);
       }
     }
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
   }
   __syncthreads();
   const uint64_t hi = s_hi;
-  BucketTotals tot{0ull, 0u, 0u, 0u, 0u};
+  BucketTotals tot{0ull, 0u, kNoStation, 0u};
   if (hi - lo <= (uint64_t)kBinCap) {
     process_bins(a, seg, lo, hi, sk, sv, bs, be, np, mixed, sh, tot);
   } else {
@@ -717,14 +718,14 @@ __global__ __launch_bounds__(kThreads) void k_bigbin(BucketArgs a, const uint4* 
   }
   // Account buckets, scanning the range in chunks of kThreads with the
   // currently open run carried across chunks.
-  BucketTotals tot{0ull, 0u, 0u, 0u, 0u};
+  BucketTotals tot{0ull, 0u, kNoStation, 0u};
   if (tid == 0) s_carry = 0;
   __syncthreads();
   uint8_t* marks = a.marks + off;
   for (uint64_t p = lo + tid; p < hi; p += kThreads) marks[p] = 0;
   __syncthreads();
   auto emit = [&](uint64_t s, uint64_t e) {
-    const int cls = bucket_account(a, e - s, [&](uint64_t q) { return V[s + q]; }, V[s], tot);
+    const int cls = bucket_account(a, e - s, [&](uint64_t q) { return V[s + q]; }, V[s], K[s], tot);
     if (cls == 1) {
       marks[s] = (uint8_t)(e - s);
     } else if (cls == 2) {
