@@ -41,6 +41,21 @@ INT_PEAK_TOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0  # 39.3
 OPS_PER_EVAL = {0: 5.5, 1: 6.0}  # MinHash, Min-Max
 
 
+def sig_traffic(n):
+    """HBM bytes per signature launch from the committed counter figures, or
+    None when they were taken for another size or on different kernel code."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sig_station90d_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    src = b"".join(open(os.path.join(ROOT, "paper_1803_09835_amd", "csrc", f), "rb").read()
+                   for f in ("sig.hip", "common.hpp"))
+    if int(kv.get("n", -1)) != n or kv.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--workload", choices=("station", "batched"), default="station",
@@ -131,9 +146,12 @@ def main():
         evals = N * fl.n_funcs(t, r, scheme) * 200  # (fingerprint, function, set element)
         per_launch_ms = stage_ms[dom] / max(stage_launch[dom], 1)
         achieved = evals * OPS_PER_EVAL[scheme] / (per_launch_ms / 1000.0) / 1e12
+        traffic = sig_traffic(N)
         roof = {"kernel": "k_sig<200,minmax>", "bound": "alu", "achieved": round(achieved, 2),
                 "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s (int32)",
-                "frac": round(achieved / INT_PEAK_TOPS, 4), "traffic": None,
+                "frac": round(achieved / INT_PEAK_TOPS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, counter runs in profiles/)",
+                "traffic_gbs": round(traffic / (per_launch_ms / 1000.0) / 1e9, 1) if traffic else None,
                 "evals_per_s": evals / (per_launch_ms / 1000.0), "launch_ms": round(per_launch_ms, 3)}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
