@@ -205,6 +205,24 @@ int fast_lsh_search_batched(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, uint32
                             uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes, uint64_t capacity,
                             uint64_t *station_offsets, fast_lsh_stats *per_station);
 
+/* Bounded-memory search: the result and counters of fast_lsh_search_ex
+ * (identical bytes), computed with the tables taken group_tables at a time,
+ * the way the paper bounds memory by partitioning the search (section 6.4).
+ * Sorting and bucket segmentation need room for one group of tables only;
+ * the signatures of each group are computed twice (once to find bucket
+ * sizes and exclusions over all tables, once to emit the pairs), and exact
+ * key comparisons use a 16-bit sub-key row plus a 32-bit word per table and
+ * fingerprint instead of full 64-bit keys.  Workspace, in bytes, is about
+ *   n * (4 t + 2 t' + 1) + group_tables * n * (24 + 1) + small tables,
+ * with t' = t rounded up to whole 32-bit words per group of the vote filter
+ * (the fast_lsh_search workspace is about n * (2 t' + 1) + 33 t n).
+ * Requires band keys of at most 48 bits (ceil(log2 dim) * r <= 48) and does
+ * not take FAST_LSH_USE_GRAPH. */
+int fast_lsh_search_bounded(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *fps,
+                            const fast_lsh_filter *filter, uint32_t flags, uint32_t group_tables,
+                            uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes, uint64_t capacity,
+                            fast_lsh_stats *stats);
+
 /* Copy the last search's result (kept in the context) into caller buffers
  * with room for `capacity` pairs.  E_CAPACITY if it still does not fit,
  * E_INVALID if there is no result.  Ids are local to their station. */

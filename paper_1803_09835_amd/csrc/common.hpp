@@ -65,6 +65,27 @@ __device__ __forceinline__ uint64_t mix60(uint64_t k) {
   return k;
 }
 
+// A bijection of 48-bit words, for band keys of at most 48 bits: with the
+// mixed key m = mix48(key) << 16, the sub-key (bits 16-31) and the high word
+// (bits 32-63) together determine the band key.
+__device__ __forceinline__ uint64_t mix48(uint64_t k) {
+  constexpr uint64_t M = (1ull << 48) - 1;
+  k &= M;
+  k ^= k >> 24;
+  k = (k * 0xff51afd7ed558ccdull) & M;
+  k ^= k >> 23;
+  k = (k * 0xc4ceb9fe1a85ec53ull) & M;
+  k ^= k >> 24;
+  return k;
+}
+
+// Mixed-key forms (SigArgs::mix).
+enum : uint32_t {
+  kMixFull = 0,    // fmix64(band key); sub-key = bits 0-15
+  kMixStation = 1, // station << 60 | mix60(band key); sub-key = bits 0-15
+  kMixSplit = 2    // mix48(band key) << 16; sub-key = bits 16-31, high word = bits 32-63
+};
+
 // --------------------------------------------------------------------------
 // Sub-key rows.  Each fingerprint carries, per group of tables, a row of
 // 16-bit sub-keys (the low bits of its mixed band key in each table of the
@@ -108,8 +129,9 @@ struct SigArgs {
   uint32_t* rows;        // sub-key rows [G][out_stride][row_dw], or nullptr
   uint64_t out_stride;   // fingerprints per table in mkeys / rows (all stations)
   uint64_t out_base;     // first position of this station in mkeys / rows
-  uint64_t tag;          // station id << 60 (tagged): keeps stations apart
-  uint32_t tagged;       // 1: mixed key = tag | mix60(band key); 0: fmix64(band key)
+  uint64_t tag;          // station id << 60 (kMixStation): keeps stations apart
+  uint32_t mix;          // kMixFull, kMixStation or kMixSplit
+  uint32_t* hi32;        // [num_tables][out_stride] high words of split keys (global table index), or nullptr
   uint32_t tables_per_group;
   uint32_t row_dw;       // dwords per row
   int* err;              // set to 1 on an empty row or an index >= dim
@@ -141,9 +163,11 @@ struct PairArgs {
   const uint32_t* order;      // bucket members by position [S][n]
   const uint8_t* flags;
   const uint32_t* rows;       // sub-key rows [G][n][row_dw]
-  const uint64_t* mkeys;      // exact keys [t][n]
+  const uint64_t* mkeys;      // exact mixed keys [t][n], or nullptr when hi32 is given
+  const uint32_t* hi32;       // high words of split keys [t][n] (with equal sub-keys: equal keys)
   uint64_t n;
   uint32_t t, G, tables_per_group, row_dw;
+  uint32_t table_offset;      // table of launch segment 0 (segment s is table table_offset + s)
   uint32_t min_lag, min_votes, need;
   uint32_t want_distinct;
   uint32_t* out_i;

@@ -33,6 +33,12 @@ __device__ __forceinline__ void tri_decode(uint32_t m, uint32_t q, uint32_t& x, 
   y = q - S(xx) + (uint32_t)xx + 1;
 }
 
+// Band keys of i and j in table tab are equal (their sub-keys are equal).
+__device__ __forceinline__ bool keys_equal(const PairArgs& a, uint32_t tab, uint32_t i, uint32_t j) {
+  const uint64_t o = (uint64_t)tab * a.n;
+  return a.hi32 ? a.hi32[o + i] == a.hi32[o + j] : a.mkeys[o + i] == a.mkeys[o + j];
+}
+
 // Exact shared tables of (i, j) from global rows and mixed keys; reports the
 // pair if table u is its owner.
 __device__ __forceinline__ void exact_and_report(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
@@ -45,7 +51,7 @@ __device__ __forceinline__ void exact_and_report(const PairArgs& a, uint32_t u, 
     for (uint32_t k = 0; k < valid; ++k) {
       if (row_field(ri, k) != row_field(rj, k)) continue;
       const uint32_t tab = g * a.tables_per_group + k;
-      if (a.mkeys[(uint64_t)tab * a.n + i] == a.mkeys[(uint64_t)tab * a.n + j]) {
+      if (keys_equal(a, tab, i, j)) {
         ++cnt;
         minu = tab < minu ? tab : minu;
       }
@@ -70,7 +76,7 @@ __device__ __forceinline__ bool first_shared_is(const PairArgs& a, uint32_t u, u
   const uint32_t* rj = a.rows + (uint64_t)j * a.row_dw;
   for (uint32_t tab = 0; tab < u; ++tab) {
     if (row_field(ri, tab) != row_field(rj, tab)) continue;
-    if (a.mkeys[(uint64_t)tab * a.n + i] == a.mkeys[(uint64_t)tab * a.n + j]) return false;
+    if (keys_equal(a, tab, i, j)) return false;
   }
   return true;
 }
@@ -268,7 +274,8 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
   uint32_t* bpof = hinfo + 64;              // 65: pair prefix
   const uint32_t lane = threadIdx.x;
   const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
-  const uint32_t seg = blockIdx.y;
+  const uint32_t seg = blockIdx.y;           // launch segment (positions in order/marks)
+  const uint32_t u = seg + a.table_offset;    // its table
   const uint64_t p0 = (uint64_t)blockIdx.x * 64;
   const uint64_t left = a.n - p0;
   const uint8_t* marks = marks_all + (uint64_t)seg * a.n + p0;
@@ -297,7 +304,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
   }
   if (lane == 0) bpof[nh] = P;
   // Member positions: q belongs to the last head h <= q when q < h + size(h).
-  const uint32_t g = seg / a.tables_per_group;
+  const uint32_t g = u / a.tables_per_group;
   const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
   __syncthreads();
 #pragma unroll
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
     tl.lo = (uint32_t)a.station_base[st];
     tl.hi = (uint32_t)a.station_base[st + 1];
   }
-  const uint32_t pad = group_pad(a, seg, rsw);
+  const uint32_t pad = group_pad(a, u, rsw);
   const uint32_t per = (P + 63) / 64;
   uint32_t p = lane * per;
   const uint32_t pend = min(P, p + per);
@@ -333,7 +340,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
     RowReg<RSW> rx;
     rx.load(lrows + (base + x) * rswl, rsw);
     for (; p < pend; ++p) {
-      visit_pair<RSW>(a, seg, idx, lids[base + y], rx, lrows + (base + y) * rswl, rsw, pad, tl);
+      visit_pair<RSW>(a, u, idx, lids[base + y], rx, lrows + (base + y) * rswl, rsw, pad, tl);
       if (++y == m) {
         if (++x == m - 1) {
           if (++b >= nh) break;
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
   extern __shared__ uint32_t smem[];
   const TileUnit un = units[blockIdx.x];
   const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
-  const uint32_t seg = big[un.bucket].y;
+  const uint32_t u = big[un.bucket].y + a.table_offset;  // table of the bucket
   const uint32_t* bid = ids + cofs[un.bucket];
   const uint32_t m = cnt[un.bucket];
   const uint32_t a0 = un.ta * tb_size, b0 = un.tb * tb_size;
@@ -395,7 +402,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
   uint32_t* rowsB = diag ? rowsA : rowsA + tb_size * rswl;
   uint32_t* idsA = smem + 2 * tb_size * rswl;
   uint32_t* idsB = diag ? idsA : idsA + tb_size;
-  const uint32_t g = seg / a.tables_per_group;
+  const uint32_t g = u / a.tables_per_group;
   const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
   for (uint32_t q = threadIdx.x; q < na; q += kPT) idsA[q] = bid[a0 + q];
   if (!diag)
@@ -405,7 +412,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
   if (!diag)
     for (uint32_t q = threadIdx.x; q < nbm; q += kPT) stage_row<RSW>(R + (uint64_t)idsB[q] * rsw, rowsB + q * rswl, rsw);
   __syncthreads();
-  const uint32_t pad = group_pad(a, seg, rsw);
+  const uint32_t pad = group_pad(a, u, rsw);
   PairTally tl{0ull, 0ull, 0u, 0u, 0u};
   const uint32_t P = diag ? na * (na - 1) / 2 : na * nbm;
   const uint32_t per = (P + kPT - 1) / kPT;
@@ -422,7 +429,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
     RowReg<RSW> rx;
     rx.load(rowsA + x * rswl, rsw);
     for (; p < pend; ++p) {
-      visit_pair<RSW>(a, seg, idsA[x], idsB[y], rx, rowsB + y * rswl, rsw, pad, tl);
+      visit_pair<RSW>(a, u, idsA[x], idsB[y], rx, rowsB + y * rswl, rsw, pad, tl);
       if (++y == nbm) {
         ++x;
         y = diag ? x + 1 : 0;

@@ -147,7 +147,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
     sa.rows = j.rows;
     sa.out_stride = j.N;
     sa.out_base = j.base[st];
-    sa.tagged = j.S > 1;
+    sa.mix = j.S > 1 ? kMixStation : kMixFull;
     sa.tag = (uint64_t)st << 60;
     sa.tables_per_group = j.pl.TG;
     sa.row_dw = j.pl.row_dw;
@@ -295,6 +295,67 @@ int set_out_buffers(fast_lsh_ctx* c, Job& j, uint64_t out_cap) {
   j.pa.out_j = oj;
   j.pa.out_v = ov;
   j.pa.out_cap = (uint32_t)std::min<uint64_t>(out_cap, 0xFFFFFFFFull);
+  return FAST_LSH_OK;
+}
+
+// 5. canonical order: sort the reported (i << 32 | j) by LSD radix over the
+// bits in use, then per-station offsets and counters.
+int finish_output(fast_lsh_ctx* c, Job& j, uint64_t cnt, bool distinct, fast_lsh_stats* per_station,
+                  uint64_t* station_offsets) {
+  hipStream_t s = c->stream;
+  const uint32_t S = j.S;
+  const uint64_t N = j.N;
+  uint64_t *rk0, *rk1;
+  uint32_t *rv0, *rv1;
+  RC(ws<uint64_t>(c, "res_k0", cnt + 1, &rk0));
+  RC(ws<uint64_t>(c, "res_k1", cnt + 1, &rk1));
+  RC(ws<uint32_t>(c, "res_v0", cnt + 1, &rv0));
+  RC(ws<uint32_t>(c, "res_v1", cnt + 1, &rv1));
+  launch_pack_out(j.pa.out_i, j.pa.out_j, j.pa.out_v, cnt, rk0, rv0, s);
+  LAUNCHCK();
+  if (cnt > 1) {
+    const uint32_t nb = fl_key_bits((uint32_t)std::max<uint64_t>(N, 2));
+    const uint32_t ont = radix_tiles(cnt, 0);
+    uint32_t *ohist, *osums;
+    RC(ws<uint32_t>(c, "ohist", (uint64_t)256 * ont, &ohist));
+    RC(ws<uint32_t>(c, "osums", scan_sums_elems((uint64_t)256 * ont, 1), &osums));
+    std::vector<uint32_t> shifts;
+    for (uint32_t sh = 0; sh < nb; sh += 8) shifts.push_back(sh);
+    for (uint32_t sh = 0; sh < nb; sh += 8) shifts.push_back(32 + sh);
+    for (uint32_t sh : shifts) {
+      prof_begin(c, FAST_LSH_STAGE_OUTPUT);
+      radix_pass(rk0, rv0, rk1, rv1, cnt, 1, sh, ohist, osums, 0, s);
+      prof_end(c);
+      LAUNCHCK();
+      std::swap(rk0, rk1);
+      std::swap(rv0, rv1);
+    }
+  }
+  // keep the sorted result under the fixed names read by fast_lsh_copy_result
+  if (c->ws["res_k0"].p != rk0) {
+    std::swap(c->ws["res_k0"], c->ws["res_k1"]);
+    std::swap(c->ws["res_v0"], c->ws["res_v1"]);
+  }
+  launch_station_offsets(rk0, cnt, j.sbase, S, j.ctrl->st_offs, s);
+  launch_spread_reduce(j.er, j.mb, j.ev, j.nd, S, j.ctrl->st_sum, s);
+  LAUNCHCK();
+  Ctrl hc;
+  RC(d2h(c, &hc, j.ctrl));
+  prof_collect(c);
+  c->res_count = cnt;
+  c->res_valid = true;
+  for (uint32_t st = 0; st < S; ++st) {
+    if (station_offsets) station_offsets[st] = hc.st_offs[st];
+    if (!per_station) continue;
+    fast_lsh_stats& o = per_station[st];
+    o.n_out = hc.st_offs[st + 1] - hc.st_offs[st];
+    o.e_raw = hc.st_sum[4 * st + 0];
+    o.max_bucket = hc.st_sum[4 * st + 1];
+    o.e_voted = hc.st_sum[4 * st + 2];
+    o.n_distinct = distinct ? hc.st_sum[4 * st + 3] : ~0ull;
+    o.n_flagged = hc.st_flagged[st];
+  }
+  if (station_offsets) station_offsets[S] = hc.st_offs[S];
   return FAST_LSH_OK;
 }
 
@@ -510,61 +571,216 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
     if (hc.out_count <= out_cap) break;
   }
 
-  // 5. canonical order: sort (i << 32 | j) by LSD radix over the bits in use,
-  // then per-station offsets and counters
-  const uint64_t cnt = hc.out_count;
-  uint64_t *rk0, *rk1;
-  uint32_t *rv0, *rv1;
-  RC(ws<uint64_t>(c, "res_k0", cnt + 1, &rk0));
-  RC(ws<uint64_t>(c, "res_k1", cnt + 1, &rk1));
-  RC(ws<uint32_t>(c, "res_v0", cnt + 1, &rv0));
-  RC(ws<uint32_t>(c, "res_v1", cnt + 1, &rv1));
-  launch_pack_out(j.pa.out_i, j.pa.out_j, j.pa.out_v, cnt, rk0, rv0, s);
+  return finish_output(c, j, hc.out_count, distinct, per_station, station_offsets);
+}
+
+// ---------------------------------------------------------------------------
+// Bounded-memory search: the same result, with the tables taken in groups of
+// group_tables so that sorting needs room for one group only.  Pass 1 sorts
+// every group and finds its buckets (sizes, counters, occurrence flags); it
+// also writes each fingerprint's sub-key rows and the high words of its split
+// mixed keys for every table.  Pass 2 recomputes each group's signatures,
+// sorts and segments it again, and runs the pair kernels on its tables with
+// the final flags.  Exact key comparisons use sub-key plus high word, so no
+// table's full keys stay resident.
+// ---------------------------------------------------------------------------
+int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps* f, const fast_lsh_filter* flt,
+                      uint32_t flags, uint32_t group_tables, fast_lsh_stats* stats) {
+  hipStream_t s = c->stream;
+  const bool distinct = (flags & FAST_LSH_WANT_DISTINCT) != 0;
+  Job j;
+  j.S = 1;
+  j.f = f;
+  j.h = h;
+  j.t = h->num_tables;
+  j.minmax = h->scheme == FAST_LSH_MINMAX;
+  j.base = {0, f->n};
+  j.N = f->n;
+  c->res_valid = false;
+  c->res_stations = 1;
+  if (j.N == 0) {
+    c->res_count = 0;
+    c->res_valid = true;
+    memset(stats, 0, sizeof *stats);
+    if (!distinct) stats->n_distinct = ~0ull;
+    return FAST_LSH_OK;
+  }
+  const uint64_t N = j.N;
+  const uint32_t t = j.t;
+  const uint32_t TGm = std::min(group_tables, t);
+  const uint32_t ngroups = (t + TGm - 1) / TGm;
+  const uint64_t gn = (uint64_t)TGm * N;
+  j.pl = make_plan(t, flt->min_votes, distinct);
+  j.B = bin_bits(N, false);
+  RC(fl_upload_hash(c, h, &j.dhash));
+  j.cap.assign(1, 0);
+  j.vec.assign(1, false);
+  {
+    int cp;
+    bool vc;
+    RC(fl_row_capacity(c, f, &cp, &vc));
+    j.cap[0] = cp;
+    j.vec[0] = vc;
+  }
+  // persistent: counters, rows, high words, flags; per group: sort buffers
+  RC(ws<Ctrl>(c, "ctrl", 1, &j.ctrl));
+  j.spread_bytes = (uint64_t)kSpread * (3 * sizeof(unsigned long long) + sizeof(unsigned int));
+  uint8_t *spread, *spread2;
+  RC(ws<uint8_t>(c, "spread", j.spread_bytes, &spread));
+  RC(ws<uint8_t>(c, "spread_pass2", j.spread_bytes, &spread2));
+  j.er = reinterpret_cast<unsigned long long*>(spread);
+  j.ev = j.er + kSpread;
+  j.nd = j.ev + kSpread;
+  j.mb = reinterpret_cast<unsigned int*>(j.nd + kSpread);
+  uint32_t* hi32;
+  RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_dw, &j.rows));
+  RC(ws<uint32_t>(c, "hi32", (uint64_t)t * N, &hi32));
+  RC(ws<uint8_t>(c, "flags", N, &j.flags));
+  RC(ws<uint64_t>(c, "station_base", 2, &j.sbase));
+  RC(ws<uint64_t>(c, "ak", gn, &j.ak));
+  RC(ws<uint32_t>(c, "av", gn, &j.av));
+  RC(ws<uint64_t>(c, "bk", gn, &j.bk));  // also receives each group's mixed keys
+  RC(ws<uint32_t>(c, "bv", gn, &j.bv));
+  j.mkeys = j.bk;
+  const uint32_t nt_max = radix_tiles(N, kRadixTileVariants - 1);
+  RC(ws<uint32_t>(c, "hist", (uint64_t)256 * nt_max * TGm, &j.hist));
+  RC(ws<uint32_t>(c, "sums", scan_sums_elems((uint64_t)256 * nt_max, TGm), &j.sums));
+  const uint32_t smax = 64;
+  const uint64_t cap_big = gn / (smax + 1) + 1;
+  const uint64_t cap_bin = gn / 129 + TGm + 1;
+  RC(ws<uint4>(c, "bdesc", cap_big, &j.bdesc));
+  RC(ws<uint4>(c, "bins", cap_bin, &j.bins));
+  RC(ws<uint8_t>(c, "marks", gn, &j.marks));
+  j.bigbin_grid = (uint32_t)std::min<uint64_t>(cap_bin, 512);
+  j.rswl = j.pl.row_dw | 1u;
+  uint64_t out_cap = std::max<uint64_t>(1u << 20, N / 8);
+  RC(h2d(c, j.sbase, j.base.data(), 2));
+
+  BucketArgs& ba = j.ba;
+  memset(&ba, 0, sizeof ba);
+  ba.n = N;
+  ba.bin_shift = 64 - j.B;
+  ba.station_base = j.sbase;
+  ba.nstation = 1;
+  ba.occ_num = flt->occ_num;
+  ba.occ_den = flt->occ_den;
+  ba.min_lag = flt->min_lag;
+  ba.flags = j.flags;
+  ba.small_max = smax;
+  ba.marks = j.marks;
+  ba.big_desc = j.bdesc;
+  ba.big_count = &j.ctrl->big_count;
+  ba.bin_desc = j.bins;
+  ba.bin_count = &j.ctrl->bin_count;
+  ba.chunk = c->config.bucket_chunk;
+  PairArgs& pa = j.pa;
+  memset(&pa, 0, sizeof pa);
+  pa.flags = j.flags;
+  pa.rows = j.rows;
+  pa.hi32 = hi32;
+  pa.n = N;
+  pa.t = t;
+  pa.G = j.pl.G;
+  pa.tables_per_group = j.pl.TG;
+  pa.row_dw = j.pl.row_dw;
+  pa.min_lag = flt->min_lag;
+  pa.min_votes = flt->min_votes;
+  pa.need = j.pl.need;
+  pa.want_distinct = distinct;
+  pa.out_count = &j.ctrl->out_count;
+  pa.e_voted = j.ev;
+  pa.n_distinct = j.nd;
+  pa.station_base = j.sbase;
+  pa.nstation = 1;
+  pa.n_flagged = &j.ctrl->n_flagged;
+  uint32_t variant = 0;
+  for (uint32_t v = 0; v < kRadixTileVariants; ++v)
+    if (radix_tile_elems(v) == c->config.radix_tile) variant = v;
+  c->last_choice.radix_variant = variant;
+  c->last_choice.bucket_chunk = ba.chunk;
+
+  // Signatures, grouping and buckets of tables [tb, tb + tc); pass 1 also
+  // writes rows and high words and accounts the buckets.
+  auto group = [&](uint32_t tb, uint32_t tc, bool first_pass) -> int {
+    SigArgs sa = fl_sig_args(h, f, j.dhash, &j.ctrl->err);
+    sa.table_begin = tb;
+    sa.table_count = tc;
+    sa.vec_load = j.vec[0];
+    sa.mkeys = j.bk;
+    sa.rows = first_pass ? j.rows : nullptr;
+    sa.hi32 = first_pass ? hi32 : nullptr;
+    sa.mix = kMixSplit;
+    sa.tables_per_group = j.pl.TG;
+    sa.row_dw = j.pl.row_dw;
+    prof_begin(c, FAST_LSH_STAGE_SIGNATURES);
+    launch_sig(j.cap[0], j.minmax, sa, s);
+    prof_end(c);
+    LAUNCHCK();
+    uint64_t *gk = j.ak, *gk2 = j.bk;
+    uint32_t *gv = j.av, *gv2 = j.bv;
+    prof_begin(c, FAST_LSH_STAGE_GROUP);
+    for (uint32_t pass = 0; pass < j.B / 8; ++pass) {
+      const uint32_t shift = 64 - j.B + 8 * pass;
+      radix_pass(gk2, pass == 0 ? nullptr : gv2, gk, gv, N, tc, shift, j.hist, j.sums, variant, s);
+      std::swap(gk, gk2);
+      std::swap(gv, gv2);
+    }
+    prof_end(c);
+    LAUNCHCK();
+    j.sorted_k = gk2;
+    j.sorted_v = gv2;
+    j.scratch_k = gk;
+    j.scratch_v = gv;
+    fill_u32(&j.ctrl->big_count, 2, 0, s);  // big_count, bin_count
+    BucketArgs b = ba;
+    b.keys = j.sorted_k;
+    b.vals = j.sorted_v;
+    // pass 2 repeats the bucket accounting into a scratch copy of the counters
+    uint8_t* sp = first_pass ? spread : spread2;
+    b.e_raw = reinterpret_cast<unsigned long long*>(sp);
+    b.max_bucket = reinterpret_cast<unsigned int*>(sp + (uint64_t)kSpread * 3 * sizeof(unsigned long long));
+    prof_begin(c, FAST_LSH_STAGE_BUCKETS);
+    launch_bucket(b, tc, s);
+    prof_end(c);
+    prof_begin(c, FAST_LSH_STAGE_BIG_BINS);
+    launch_bigbin(b, j.bins, j.bigbin_grid, j.scratch_k, j.scratch_v, s);
+    prof_end(c);
+    LAUNCHCK();
+    return FAST_LSH_OK;
+  };
+
+  fill_u8(reinterpret_cast<uint8_t*>(j.ctrl), sizeof(Ctrl), 0, s);
+  fill_u8(spread, j.spread_bytes, 0, s);
+  fill_u8(j.flags, N, 0, s);
+  for (uint32_t g = 0; g < ngroups; ++g) RC(group(g * TGm, std::min(TGm, t - g * TGm), true));
+  launch_count_flags(j.flags, N, &j.ctrl->st_flagged[0], &j.ctrl->n_flagged, s);
   LAUNCHCK();
-  if (cnt > 1) {
-    const uint32_t nb = fl_key_bits((uint32_t)std::max<uint64_t>(N, 2));
-    const uint32_t ont = radix_tiles(cnt, 0);
-    uint32_t *ohist, *osums;
-    RC(ws<uint32_t>(c, "ohist", (uint64_t)256 * ont, &ohist));
-    RC(ws<uint32_t>(c, "osums", scan_sums_elems((uint64_t)256 * ont, 1), &osums));
-    std::vector<uint32_t> shifts;
-    for (uint32_t sh = 0; sh < nb; sh += 8) shifts.push_back(sh);
-    for (uint32_t sh = 0; sh < nb; sh += 8) shifts.push_back(32 + sh);
-    for (uint32_t sh : shifts) {
-      prof_begin(c, FAST_LSH_STAGE_OUTPUT);
-      radix_pass(rk0, rv0, rk1, rv1, cnt, 1, sh, ohist, osums, 0, s);
+  Ctrl hc;
+  RC(d2h(c, &hc, j.ctrl));
+  if (hc.err) return fl_fail(FAST_LSH_E_INVALID, "a fingerprint is empty or holds an index >= dim (%u)", h->dim);
+
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    RC(set_out_buffers(c, j, out_cap));
+    fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * kSpread * sizeof(unsigned long long), 0, s);
+    fill_u32(&j.ctrl->out_count, 1, 0, s);
+    for (uint32_t g = 0; g < ngroups; ++g) {
+      const uint32_t tb = g * TGm, tc = std::min(TGm, t - tb);
+      fill_u8(spread2, j.spread_bytes, 0, s);
+      RC(group(tb, tc, false));
+      j.pa.order = j.sorted_v;
+      j.pa.table_offset = tb;
+      prof_begin(c, FAST_LSH_STAGE_PAIRS);
+      launch_pairs_wave(j.pa, j.marks, tc, j.rswl, s);
       prof_end(c);
       LAUNCHCK();
-      std::swap(rk0, rk1);
-      std::swap(rv0, rv1);
+      RC(d2h(c, &hc, j.ctrl));
+      RC(run_big_pairs(c, j, hc.big_count));
     }
+    RC(d2h(c, &hc, j.ctrl));
+    if (hc.out_count <= out_cap) break;
+    out_cap = (uint64_t)hc.out_count + 1024;
   }
-  // keep the sorted result under the fixed names read by fast_lsh_copy_result
-  if (c->ws["res_k0"].p != rk0) {
-    std::swap(c->ws["res_k0"], c->ws["res_k1"]);
-    std::swap(c->ws["res_v0"], c->ws["res_v1"]);
-  }
-  launch_station_offsets(rk0, cnt, j.sbase, S, j.ctrl->st_offs, s);
-  launch_spread_reduce(j.er, j.mb, j.ev, j.nd, S, j.ctrl->st_sum, s);
-  LAUNCHCK();
-  RC(d2h(c, &hc, j.ctrl));
-  prof_collect(c);
-  c->res_count = cnt;
-  c->res_valid = true;
-
-  for (uint32_t st = 0; st < S; ++st) {
-    if (station_offsets) station_offsets[st] = hc.st_offs[st];
-    if (!per_station) continue;
-    fast_lsh_stats& o = per_station[st];
-    o.n_out = hc.st_offs[st + 1] - hc.st_offs[st];
-    o.e_raw = hc.st_sum[4 * st + 0];
-    o.max_bucket = hc.st_sum[4 * st + 1];
-    o.e_voted = hc.st_sum[4 * st + 2];
-    o.n_distinct = distinct ? hc.st_sum[4 * st + 3] : ~0ull;
-    o.n_flagged = hc.st_flagged[st];
-  }
-  if (station_offsets) station_offsets[S] = hc.st_offs[S];
-  return FAST_LSH_OK;
+  return finish_output(c, j, hc.out_count, distinct, stats, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -639,6 +855,28 @@ int fast_lsh_search_ex(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_f
   HIPCK(hipSetDevice(c->device));
   fast_lsh_stats local;
   RC(fl_search_stations(c, h, 1, f, flt, flags, &local, nullptr));
+  if (st) *st = local;
+  if (local.n_out > capacity)
+    return fl_fail(FAST_LSH_E_CAPACITY, "%llu pairs do not fit capacity %llu", (unsigned long long)local.n_out,
+                   (unsigned long long)capacity);
+  return fast_lsh_copy_result(c, oi, oj, ov, capacity);
+}
+
+int fast_lsh_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps* f,
+                            const fast_lsh_filter* flt, uint32_t flags, uint32_t group_tables, uint32_t* oi,
+                            uint32_t* oj, uint8_t* ov, uint64_t capacity, fast_lsh_stats* st) {
+  if (!c) return fl_fail(FAST_LSH_E_INVALID, "ctx is NULL");
+  RC(fl_check_hash(h));
+  RC(fl_check_fps(f));
+  RC(check_filter(flt, flags));
+  if (flags & FAST_LSH_USE_GRAPH) return fl_fail(FAST_LSH_E_INVALID, "the bounded search is not captured as a graph");
+  if (group_tables < 1) return fl_fail(FAST_LSH_E_INVALID, "group_tables must be >= 1");
+  if ((uint64_t)fl_key_bits(h->dim) * h->band_rows > 48)
+    return fl_fail(FAST_LSH_E_INVALID, "the bounded search needs band keys of at most 48 bits (got %u)",
+                   fl_key_bits(h->dim) * h->band_rows);
+  HIPCK(hipSetDevice(c->device));
+  fast_lsh_stats local;
+  RC(fl_search_bounded(c, h, f, flt, flags, group_tables, &local));
   if (st) *st = local;
   if (local.n_out > capacity)
     return fl_fail(FAST_LSH_E_CAPACITY, "%llu pairs do not fit capacity %llu", (unsigned long long)local.n_out,

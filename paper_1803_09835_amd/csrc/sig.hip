@@ -64,16 +64,28 @@ __device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint
                                             uint32_t* my) {
   const uint32_t tab = a.table_begin + u;
   if (live && a.keys) a.keys[(uint64_t)u * a.n + i] = key;
-  if (a.mkeys || a.rows) {
-    const uint64_t m = a.tagged ? (a.tag | mix60(key)) : fmix64(key);
+  if (a.mkeys || a.rows || a.hi32) {
+    const uint64_t m = a.mix == kMixSplit ? mix48(key) << 16
+                                          : (a.mix == kMixStation ? (a.tag | mix60(key)) : fmix64(key));
     if (live && a.mkeys) a.mkeys[(uint64_t)u * a.out_stride + a.out_base + i] = m;
+    if (live && a.hi32) a.hi32[(uint64_t)tab * a.out_stride + a.out_base + i] = (uint32_t)(m >> 32);
     if (a.rows) {
       const uint32_t slot = tab % a.tables_per_group;
       if (slot == 0)
         for (uint32_t w = 0; w < a.row_dw; ++w) my[w] = 0;
-      my[slot >> 1] |= ((uint32_t)m & kSubMask) << (16 * (slot & 1));
+      const uint32_t sub = (uint32_t)(m >> (a.mix == kMixSplit ? 16 : 0)) & kSubMask;
+      my[slot >> 1] |= sub << (16 * (slot & 1));
     }
   }
+}
+
+// A launch that starts inside a group of tables continues the rows an
+// earlier launch began: the lane's row of that group is loaded first.
+__device__ __forceinline__ void resume_row(const SigArgs& a, uint64_t i, bool live, uint32_t* my) {
+  if (!a.rows || a.table_begin % a.tables_per_group == 0) return;
+  const uint32_t g = a.table_begin / a.tables_per_group;
+  const uint32_t* src = a.rows + ((uint64_t)g * a.out_stride + a.out_base + i) * a.row_dw;
+  for (uint32_t w = 0; w < a.row_dw; ++w) my[w] = live ? src[w] : 0u;
 }
 
 // After the last table of a group: the workgroup's 256 rows of that group
@@ -141,6 +153,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 
   for (int w = 0; w < W; ++w) top = max(top, max(xs[w] & 0xFFFFu, xs[w] >> 16));
   if (top >= a.dim) bad = true;
   if (live && bad) *a.err = 1;
+  resume_row(a, i, live, my);
 
   for (uint32_t u = 0; u < a.table_count; ++u) {
     const uint32_t f0 = (a.table_begin + u) * a.fpt;
@@ -191,6 +204,7 @@ __global__ __launch_bounds__(256) void k_sig_long(SigArgs a) {
   for (uint64_t k = 0; k < len; ++k)
     if (a.ind[lo + k] >= a.dim) bad = true;
   if (live && bad) *a.err = 1;  // (empty rows never reach this kernel: the host rejects them)
+  resume_row(a, i, live, my);
 
   for (uint32_t u = 0; u < a.table_count; ++u) {
     const uint32_t f0 = (a.table_begin + u) * a.fpt;

@@ -91,6 +91,9 @@ def library():
         lib.fast_lsh_search_batched.argtypes = [_vp, ctypes.POINTER(Hash), _u32, ctypes.POINTER(Fps),
                                                 ctypes.POINTER(Filter), _u32, _vp, _vp, _vp, _u64,
                                                 ctypes.POINTER(_u64), ctypes.POINTER(_Stats)]
+        lib.fast_lsh_search_bounded.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps),
+                                                ctypes.POINTER(Filter), _u32, _u32, _vp, _vp, _vp, _u64,
+                                                ctypes.POINTER(_Stats)]
         lib.fast_lsh_copy_result.argtypes = [_vp, _vp, _vp, _vp, _u64]
         lib.fast_lsh_configure.argtypes = [_vp, ctypes.POINTER(Config)]
         lib.fast_lsh_config_used.argtypes = [_vp, ctypes.POINTER(Config)]
@@ -220,6 +223,26 @@ class FastLSH:
         st = _Stats()
         rc = library().fast_lsh_search_ex(self._ctx, ctypes.byref(h), ctypes.byref(f), ctypes.byref(flt), flags,
                                           oi.data_ptr(), oj.data_ptr(), ov.data_ptr(), cap, ctypes.byref(st))
+        if rc == E_CAPACITY and capacity is None:
+            rc, (oi, oj, ov) = self._refetch(rc, st.n_out, capacity)
+        _check(rc)
+        m = st.n_out
+        stats = Stats(*[int(getattr(st, k)) for k, _ in _Stats._fields_])
+        return oi[:m], oj[:m], ov[:m], stats
+
+    def search_bounded(self, rows, dim, t, r, scheme, a, b, min_lag, min_votes, occ_num=0, occ_den=0,
+                       group_tables=10, want_distinct=False, capacity: int | None = None):
+        """The search with tables taken group_tables at a time (same output)."""
+        h, keep = _hash_struct(dim, t, r, scheme, a, b)
+        f, keep2 = _fps_struct(rows)
+        flt = Filter(min_lag, min_votes, occ_num, occ_den)
+        flags = WANT_DISTINCT if want_distinct else 0
+        cap = max(1, f.n // 4) if capacity is None else capacity
+        oi, oj, ov = self._outputs(cap)
+        st = _Stats()
+        rc = library().fast_lsh_search_bounded(self._ctx, ctypes.byref(h), ctypes.byref(f), ctypes.byref(flt),
+                                               flags, group_tables, oi.data_ptr(), oj.data_ptr(), ov.data_ptr(),
+                                               cap, ctypes.byref(st))
         if rc == E_CAPACITY and capacity is None:
             rc, (oi, oj, ov) = self._refetch(rc, st.n_out, capacity)
         _check(rc)

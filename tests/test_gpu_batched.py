@@ -217,3 +217,73 @@ def test_launch_shapes_identical():
             c.configure(bucket_chunk=4096)
     finally:
         c.close()
+
+
+# ---------------------------------------------------------------------------
+# Bounded-memory search: identical output and counters to the full search
+# (and to the oracle) for every table-group size.
+# ---------------------------------------------------------------------------
+BOUNDED = [
+    ("station-g10", lambda: synth.generate(synth.station(n=120_000, seed=150)), 4096, 100, 4, fl.MINMAX, 5, 4, 1, 100, 10),
+    ("station-g7", lambda: synth.generate(synth.station(n=60_000, seed=151)), 4096, 100, 4, fl.MINMAX, 5, 4, 1, 100, 7),
+    ("station-g1", lambda: synth.generate(synth.station(n=20_000, seed=152)), 4096, 30, 4, fl.MINMAX, 5, 3, 1, 100, 1),
+    ("noise-g13", lambda: synth.generate(synth.with_noise(synth.station(n=30_000, seed=41), 50, 190)), 4096, 100, 4,
+     fl.MINMAX, 5, 4, 1, 100, 13),
+    ("noise-nofilter-g34", lambda: synth.generate(synth.with_noise(synth.station(n=30_000, seed=42), 50, 190)), 4096,
+     100, 4, fl.MINMAX, 5, 4, 0, 0, 34),
+    ("uniform-minhash-g6", lambda: synth.generate(synth.tiny_uniform()), 4096, 20, 4, fl.MINHASH, 5, 2, 0, 0, 6),
+    ("ragged-g5", lambda: _ragged_rows(3000, 512, 1, 40, 56), 512, 12, 2, fl.MINMAX, 3, 2, 0, 0, 5),
+    ("identical-g2", lambda: np.repeat(_fixed(1, 4096, 200, 43), 3000, axis=0), 4096, 5, 4, fl.MINMAX, 100, 2, 0, 0, 2),
+]
+
+
+def _ragged_rows(n, dim, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(lo, hi + 1, n)
+    rows = [np.sort(rng.choice(dim, L, replace=False)).astype(np.uint16) for L in lens]
+    return np.concatenate(rows), np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+
+
+def _dev(rows):
+    if isinstance(rows, tuple):
+        ind, off = rows
+        return (torch.from_numpy(ind.view(np.int16)).cuda(), torch.from_numpy(off.view(np.int64)).cuda())
+    return fl.to_device_rows(rows)
+
+
+@pytest.mark.parametrize("name,make,dim,t,r,scheme,L,v,num,den,gt", BOUNDED, ids=[b[0] for b in BOUNDED])
+def test_bounded_matches_full_and_oracle(ctx, name, make, dim, t, r, scheme, L, v, num, den, gt):
+    rows = make()
+    a, b = fl.make_hash(205, fl.n_funcs(t, r, scheme))
+    dev = _dev(rows)
+    for distinct in (False, True):
+        say(f"[bounded] {name} group_tables={gt} distinct={distinct}")
+        full = ctx.search(dev, dim, t, r, scheme, a, b, L, v, num, den, want_distinct=distinct)
+        bnd = ctx.search_bounded(dev, dim, t, r, scheme, a, b, L, v, num, den, group_tables=gt,
+                                 want_distinct=distinct)
+        for x, y in zip(full[:3], bnd[:3]):
+            assert torch.equal(x, y)
+        assert full[3] == bnd[3]
+    ei, ej, ev, est = oracle.search(rows, dim, t, r, scheme, a, b, L, v, num, den)
+    assert np.array_equal(_np(bnd[0], np.uint32), ei) and np.array_equal(_np(bnd[1], np.uint32), ej)
+    assert np.array_equal(bnd[2].cpu().numpy(), ev)
+    want = dict(est.__dict__)
+    got = dict(bnd[3].__dict__)
+    want.pop("n_distinct")
+    got.pop("n_distinct")
+    assert got == want
+
+
+def test_bounded_rejects(ctx):
+    a, b = fl.make_hash(1, 80)
+    rows = fl.to_device_rows(_fixed(100, 65536, 20, 4))
+    with pytest.raises(fl.FastLshError) as e:  # 64-bit band keys
+        ctx.search_bounded(rows, 65536, 20, 4, fl.MINHASH, a, b, 5, 2)
+    assert e.value.code == 1
+    rows = fl.to_device_rows(_fixed(100, 4096, 20, 5))
+    with pytest.raises(fl.FastLshError) as e:
+        ctx.search_bounded(rows, 4096, 20, 4, fl.MINHASH, a, b, 5, 2, group_tables=0)
+    assert e.value.code == 1
+    empty = torch.empty((0, 200), dtype=torch.int16, device="cuda")
+    gi, gj, gv, st = ctx.search_bounded(empty, 4096, 20, 4, fl.MINHASH, a, b, 5, 2)
+    assert len(gi) == 0 and st.n_out == 0
