@@ -254,6 +254,10 @@ int fast_lsh_configure(fast_lsh_ctx *ctx, const fast_lsh_config *config);
 /* The launch shapes the last search used (after autotuning, its choice). */
 int fast_lsh_config_used(fast_lsh_ctx *ctx, fast_lsh_config *out);
 
+/* Device memory the context's workspace holds now, in bytes (it grows to
+ * the largest search run on the context and is freed by ctx_destroy). */
+int fast_lsh_workspace_bytes(fast_lsh_ctx *ctx, uint64_t *bytes);
+
 /* Stage timing.  While enabled, the context records a pair of HIP events on
  * its stream around every kernel launch of the stages below and accumulates
  * their elapsed times when each call completes.  Enabling resets the

@@ -296,6 +296,12 @@ int fast_lsh_signatures(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_
   return FAST_LSH_OK;
 }
 
+int fast_lsh_workspace_bytes(fast_lsh_ctx* c, uint64_t* bytes) {
+  if (!c || !bytes) return fl_fail(FAST_LSH_E_INVALID, "ctx or bytes is NULL");
+  *bytes = c->ws_total;
+  return FAST_LSH_OK;
+}
+
 int fast_lsh_profile_enable(fast_lsh_ctx* c, int enable) {
   if (!c) return fl_fail(FAST_LSH_E_INVALID, "ctx is NULL");
   c->prof = enable != 0;

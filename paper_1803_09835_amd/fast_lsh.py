@@ -97,6 +97,7 @@ def library():
         lib.fast_lsh_copy_result.argtypes = [_vp, _vp, _vp, _vp, _u64]
         lib.fast_lsh_configure.argtypes = [_vp, ctypes.POINTER(Config)]
         lib.fast_lsh_config_used.argtypes = [_vp, ctypes.POINTER(Config)]
+        lib.fast_lsh_workspace_bytes.argtypes = [_vp, ctypes.POINTER(_u64)]
         lib.fast_lsh_profile_enable.argtypes = [_vp, _i32]
         lib.fast_lsh_profile_read.argtypes = [_vp, ctypes.POINTER(_Profile)]
         _LIB = lib
@@ -164,6 +165,12 @@ class FastLSH:
             self.close()
         except Exception:
             pass
+
+    def workspace_bytes(self) -> int:
+        """Device memory the context's workspace holds now."""
+        v = _u64()
+        _check(library().fast_lsh_workspace_bytes(self._ctx, ctypes.byref(v)))
+        return int(v.value)
 
     def profile_enable(self, on: bool = True):
         """Start (and reset) per-stage kernel timing with HIP events on the context stream."""

@@ -52,6 +52,7 @@ class _Spec(ctypes.Structure):
         ("jac_hi_milli", ctypes.c_uint32),
         ("noise_permille", ctypes.c_uint32),
         ("noise_keep", ctypes.c_uint32),
+        ("chain_len", ctypes.c_uint64),
     ]
 
 
@@ -88,17 +89,23 @@ class Spec:
     jac_hi_milli: int = 0
     noise_permille: int = 0
     noise_keep: int = 0
+    chain_len: int = 0
 
     def _c(self) -> _Spec:
         return _Spec(*[getattr(self, f) for f, _ in _Spec._fields_])
 
 
-def generate(spec: Spec, lo: int = 0, hi: int | None = None, labels: bool = False):
+def generate(spec: Spec, lo: int = 0, hi: int | None = None, labels: bool = False, out: np.ndarray | None = None):
     """Rows [lo, hi) of ``spec`` as a C-ordered ``uint16[hi-lo, nnz]`` array
     (sorted indices per row); with ``labels`` also ``int32[hi-lo]`` holding -1
-    (background), the planted source id, or -2 (noise copy)."""
+    (background), the planted source id, or -2 (noise copy).  ``out``: an
+    existing C-ordered 2-byte array of that shape to fill instead."""
     hi = spec.n if hi is None else hi
-    rows = np.empty((hi - lo, spec.nnz), dtype=np.uint16)
+    if out is not None:
+        assert out.flags.c_contiguous and out.itemsize == 2 and out.shape == (hi - lo, spec.nnz)
+        rows = out
+    else:
+        rows = np.empty((hi - lo, spec.nnz), dtype=np.uint16)
     lab = np.empty(hi - lo, dtype=np.int32) if labels else None
     c = spec._c()
     rc = _lib().synth_generate_range(ctypes.byref(c), lo, hi, rows.ctypes.data,
@@ -135,6 +142,15 @@ def station(n: int = STATION_90D, seed: int = 102, sources_per_90d: int = 2000) 
     ns = max(1, round(sources_per_90d * n / STATION_90D))
     return Spec(n=n, seed=seed, markov_keep=140, n_sources=ns, rep_min=3, rep_max=40,
                 jac_lo_milli=400, jac_hi_milli=900)
+
+
+def long_station(n: int = STATION_5Y, seed: int = 105, n_sources: int = 20_000,
+                 chain_len: int = 1_000_000) -> Spec:
+    """Five years at a 1 s lag: Markov background (70 % kept) in independent
+    chains of ``chain_len`` rows (so that generation runs in parallel), with
+    ``n_sources`` repeating sources, J ~ U[0.4, 0.9]."""
+    return Spec(n=n, seed=seed, markov_keep=140, n_sources=n_sources, rep_min=3, rep_max=40,
+                jac_lo_milli=400, jac_hi_milli=900, chain_len=chain_len)
 
 
 def with_noise(spec: Spec, permille: int = 50, keep: int = 190) -> Spec:

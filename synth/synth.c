@@ -52,6 +52,8 @@ typedef struct {
   uint32_t jac_hi_milli;
   uint32_t noise_permille;/* test-only: rows replaced by near-copies of one noise template */
   uint32_t noise_keep;    /* template bits each noise copy keeps           */
+  uint64_t chain_len;     /* Markov only: 0 = one chain over all rows; else independent
+                             chains of chain_len rows, chain c drawn from stream c    */
 } synth_spec;
 
 typedef struct { uint64_t s; } rng_t;
@@ -191,26 +193,35 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
       uniform_row(&r, d, k, out + (uint64_t)q * k);
     }
   } else {
-    rng_t r = stream_for(sp->seed, TAG_CHAIN, 0);
-    uint16_t *prev = (uint16_t *)malloc(k * sizeof(uint16_t));
-    uint16_t *cur = (uint16_t *)malloc(k * sizeof(uint16_t));
-    uint16_t *scratch = (uint16_t *)malloc(k * sizeof(uint16_t));
-    uint64_t *excl = (uint64_t *)calloc(words, 8);
-    uint64_t *bm = (uint64_t *)calloc(words, 8);
-    uniform_row(&r, d, k, prev);
-    for (uint64_t i = 0; i < hi; ++i) {
-      if (i > 0) {
-        memset(excl, 0, words * 8);
-        memset(bm, 0, words * 8);
-        for (uint32_t q = 0; q < k; ++q) bm_set(excl, prev[q]);
-        keep_subset(&r, prev, k, sp->markov_keep, scratch, bm);
-        draw_outside(&r, d, k - sp->markov_keep, excl, bm);
-        bm_emit(bm, words, cur);
-        uint16_t *t = prev; prev = cur; cur = t;
+    /* chains: one over all rows, or independent chains of chain_len rows
+       (those that meet [lo, hi) are walked in parallel from their start) */
+    const uint64_t clen = sp->chain_len ? sp->chain_len : sp->n;
+    const int64_t c0 = (int64_t)(lo / clen), c1 = (int64_t)((hi - 1) / clen) + 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = c0; c < c1; ++c) {
+      rng_t r = stream_for(sp->seed, TAG_CHAIN, (uint64_t)c);
+      uint16_t *prev = (uint16_t *)malloc(k * sizeof(uint16_t));
+      uint16_t *cur = (uint16_t *)malloc(k * sizeof(uint16_t));
+      uint16_t *scratch = (uint16_t *)malloc(k * sizeof(uint16_t));
+      uint64_t *excl = (uint64_t *)calloc(words, 8);
+      uint64_t *bm = (uint64_t *)calloc(words, 8);
+      const uint64_t start = (uint64_t)c * clen;
+      const uint64_t stop = start + clen < hi ? start + clen : hi;
+      uniform_row(&r, d, k, prev);
+      for (uint64_t i = start; i < stop; ++i) {
+        if (i > start) {
+          memset(excl, 0, words * 8);
+          memset(bm, 0, words * 8);
+          for (uint32_t q = 0; q < k; ++q) bm_set(excl, prev[q]);
+          keep_subset(&r, prev, k, sp->markov_keep, scratch, bm);
+          draw_outside(&r, d, k - sp->markov_keep, excl, bm);
+          bm_emit(bm, words, cur);
+          uint16_t *t = prev; prev = cur; cur = t;
+        }
+        if (i >= lo) memcpy(out + (i - lo) * k, prev, k * sizeof(uint16_t));
       }
-      if (i >= lo) memcpy(out + (i - lo) * k, prev, k * sizeof(uint16_t));
+      free(prev); free(cur); free(scratch); free(excl); free(bm);
     }
-    free(prev); free(cur); free(scratch); free(excl); free(bm);
   }
   if (label)
     for (uint64_t q = 0; q < cnt; ++q) label[q] = -1;

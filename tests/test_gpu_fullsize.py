@@ -1,0 +1,132 @@
+"""GPU parity at the full workload sizes, on samples the oracle can check
+one by one.
+
+The 90-day station (7,776,000 fingerprints) with the search bench.py times,
+and the 5-year station (157,788,000 fingerprints) with the bounded-memory
+search, in the same launch configuration.  The oracle cannot search these
+sizes whole, so it checks, exactly:
+  - every reported pair is canonical (i < j, sorted, lag and threshold kept);
+  - sampled reported pairs carry exactly the oracle's vote count;
+  - completeness on samples: pairs of copies of one planted source, and
+    pairs at short lags, that reach the threshold in the oracle are reported;
+  - the occurrence filter cannot fire here (largest bucket below 1 % of n),
+    and no fingerprint is excluded.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1803_09835_amd as fl  # noqa: E402
+
+DIM, T, R, SCHEME, L, V, NUM, DEN = 4096, 100, 4, fl.MINMAX, 5, 4, 1, 100
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _upload(spec, chunk=16_000_000):
+    """Rows to the device chunk by chunk through a pinned buffer; labels on the host."""
+    dev = torch.empty((spec.n, spec.nnz), dtype=torch.int16, device="cuda")
+    labels = np.empty(spec.n, dtype=np.int32)
+    pinned = torch.empty((min(chunk, spec.n), spec.nnz), dtype=torch.int16, pin_memory=True)
+    for lo in range(0, spec.n, chunk):
+        hi = min(spec.n, lo + chunk)
+        _, lab = synth.generate(spec, lo, hi, labels=True, out=pinned[: hi - lo].numpy().view(np.uint16))
+        labels[lo:hi] = lab
+        dev[lo:hi].copy_(pinned[: hi - lo])
+        say(f"[upload] rows {lo}..{hi}")
+    return dev, labels
+
+
+def _oracle_votes(dev, a, b, pi, pj):
+    ids = np.unique(np.concatenate([pi, pj]))
+    rows = dev[torch.from_numpy(ids.astype(np.int64)).cuda()].cpu().numpy().view(np.uint16)
+    keys = oracle.signatures(rows, DIM, T, R, oracle.MINMAX, a, b)
+    x, y = np.searchsorted(ids, pi), np.searchsorted(ids, pj)
+    return (keys[:, x] == keys[:, y]).sum(axis=0)
+
+
+def _check_sampled(dev, labels, out, n, a, b, seed):
+    gi, gj = out[0].cpu().numpy().view(np.uint32), out[1].cpu().numpy().view(np.uint32)
+    gv, st = out[2].cpu().numpy(), out[3]
+    say(f"[check] n={n} pairs={len(gi)} stats={st}")
+    assert len(gi) == st.n_out > 0
+    assert (gi < gj).all() and (gj - gi >= L).all() and (gv >= V).all() and (gv <= T).all()
+    key = (gi.astype(np.uint64) << np.uint64(32)) | gj.astype(np.uint64)
+    assert (key[1:] > key[:-1]).all()
+    assert st.max_bucket * DEN <= n * NUM and st.n_flagged == 0
+    assert st.e_voted >= gv.astype(np.int64).sum() and st.e_raw >= st.n_out
+    rng = np.random.default_rng(seed)
+    # reported pairs: exact votes
+    k = rng.choice(len(gi), min(3000, len(gi)), replace=False)
+    votes = _oracle_votes(dev, a, b, gi[k].astype(np.int64), gj[k].astype(np.int64))
+    assert np.array_equal(votes, gv[k].astype(votes.dtype))
+    # completeness: copies of planted sources, and short-lag pairs
+    planted = np.flatnonzero(labels >= 0)
+    srcs = rng.choice(np.unique(labels[planted]), 300, replace=False)
+    pi, pj = [], []
+    order = planted[np.argsort(labels[planted], kind="stable")]
+    lab_sorted = labels[order]
+    for s in srcs:
+        members = np.sort(order[np.searchsorted(lab_sorted, s):np.searchsorted(lab_sorted, s, side="right")])
+        for x in range(len(members)):
+            for y in range(x + 1, len(members)):
+                pi.append(members[x])
+                pj.append(members[y])
+    base = rng.integers(0, n - 64, 2000)
+    lag = rng.integers(L, 64, 2000)
+    pi = np.concatenate([np.array(pi, dtype=np.int64), base])
+    pj = np.concatenate([np.array(pj, dtype=np.int64), base + lag])
+    keep = pj - pi >= L
+    pi, pj = pi[keep], pj[keep]
+    votes = _oracle_votes(dev, a, b, pi, pj)
+    want = votes >= V
+    q = (pi.astype(np.uint64) << np.uint64(32)) | pj.astype(np.uint64)
+    pos = np.searchsorted(key, q)
+    found = (pos < len(key)) & (key[np.minimum(pos, len(key) - 1)] == q)
+    say(f"[check] completeness sample {len(q)} pairs, {int(want.sum())} at or above the threshold")
+    assert want.sum() > 50
+    assert np.array_equal(found, want)
+    got_v = gv[np.minimum(pos, len(key) - 1)][found]
+    assert np.array_equal(got_v.astype(votes.dtype), votes[found])
+
+
+def test_station_90d_full_size():
+    spec = synth.station(n=synth.STATION_90D, seed=102)
+    say("[fullsize] station 90 days: generating")
+    dev, labels = _upload(spec)
+    a, b = fl.make_hash(202, fl.n_funcs(T, R, SCHEME))
+    ctx = fl.FastLSH(0)
+    t0 = time.time()
+    out = ctx.search(dev, DIM, T, R, SCHEME, a, b, L, V, NUM, DEN)
+    torch.cuda.synchronize()
+    say(f"[fullsize] search {time.time() - t0:.2f}s")
+    _check_sampled(dev, labels, out, spec.n, a, b, 1)
+    ctx.close()
+
+
+def test_station_5y_bounded_full_size():
+    spec = synth.long_station(n=synth.STATION_5Y, seed=105)
+    say("[fullsize] station 5 years: generating")
+    dev, labels = _upload(spec)
+    a, b = fl.make_hash(205, fl.n_funcs(T, R, SCHEME))
+    ctx = fl.FastLSH(0)
+    t0 = time.time()
+    out = ctx.search_bounded(dev, DIM, T, R, SCHEME, a, b, L, V, NUM, DEN, group_tables=10)
+    torch.cuda.synchronize()
+    say(f"[fullsize] bounded search {time.time() - t0:.2f}s")
+    _check_sampled(dev, labels, out, spec.n, a, b, 2)
+    ctx.close()
