@@ -254,6 +254,85 @@ int fast_lsh_configure(fast_lsh_ctx *ctx, const fast_lsh_config *config);
 /* The launch shapes the last search used (after autotuning, its choice). */
 int fast_lsh_config_used(fast_lsh_ctx *ctx, fast_lsh_config *out);
 
+/* ---------------------------------------------------------------------------
+ * Serving form: stations whose tables stay resident, searched chunk by chunk.
+ *
+ * A server owns a HIP stream and a worker thread.  Each station is admitted
+ * with its history (built into resident tables: per table, the mixed band
+ * keys and ids sorted by key, 12 bytes per row and table, plus room to grow);
+ * chunks of new rows are then submitted as they arrive.  Each chunk is
+ * searched against everything its station holds at that point (history,
+ * earlier chunks, and its own earlier rows) and then inserted, so chunk c's
+ * result is every pair (i, j) with j in chunk c, i < j, j - i >= min_lag and
+ * votes >= min_votes (section 6.1 "Search" applied as a query, section 6.4),
+ * with station ids (history rows 0..n-1, then the chunks' rows in order).
+ * The union of the chunk results is the fast_lsh_search result of the whole
+ * station minus the history's own pairs.  The occurrence filter depends on
+ * the whole station and is not offered here (filter occ_den must be 0).
+ *
+ * Continuous batching: while a batch runs, arriving chunks wait; the next
+ * batch takes the oldest waiting chunks, at most one per station (a
+ * station's chunk waits for the one before it) and at most max_batch.
+ * HBM admission: a station is admitted only if its tables, its share of the
+ * shared history-merge buffer and its build buffers fit the budget.
+ * Chunk rows are DEVICE memory that must stay valid until the chunk's ticket
+ * is done; results are returned in HOST arrays.  Entry points other than
+ * submit/poll/take/now/info must not run concurrently with each other.
+ * ------------------------------------------------------------------------- */
+typedef struct fast_lsh_server fast_lsh_server;
+
+typedef struct {
+  uint32_t max_batch;   /* chunks per batch, 1..16                                   */
+  uint32_t max_chunk;   /* rows per chunk, 1..4096                                   */
+  uint64_t delta_rows;  /* rows of recent chunks kept per station before they are
+                           merged into its history tables (>= max_chunk)            */
+  uint64_t slack_rows;  /* rows each station may grow by                             */
+  uint64_t hbm_budget;  /* bytes for all resident tables and workspace (0: no bound) */
+} fast_lsh_server_config;
+
+typedef struct {
+  uint32_t stations, waiting;  /* admitted stations, chunks waiting            */
+  uint64_t resident_bytes;     /* station tables and the shared merge buffer   */
+  uint64_t workspace_bytes;    /* batch workspace                              */
+  uint64_t batches, chunks;    /* batches run, chunks they held                */
+  uint64_t largest_batch;
+} fast_lsh_server_state;
+
+/* cfg may be NULL: {8, 3600, 262144, 2000000, 0}. */
+int fast_lsh_server_create(int device, const fast_lsh_hash *hash, const fast_lsh_filter *filter,
+                           const fast_lsh_server_config *cfg, fast_lsh_server **out);
+/* Stops the worker after the waiting chunks are done and frees everything. */
+void fast_lsh_server_destroy(fast_lsh_server *server);
+/* Admit a station with its history (device rows; may be empty); *station
+ * receives its index.  Stations are added before the first submit (E_BUSY
+ * after).  E_NOMEM when the budget cannot hold it. */
+int fast_lsh_server_add_station(fast_lsh_server *server, const fast_lsh_fps *history, uint32_t *station);
+/* Queue a chunk (device rows, 1..max_chunk of them) of `station`;
+ * arrival_ns is the caller's arrival time on the server clock
+ * (fast_lsh_server_now_ns) and is kept for latency accounting.  *ticket
+ * receives the chunk's ticket.  Thread-safe, does not block. */
+int fast_lsh_server_submit(fast_lsh_server *server, uint32_t station, const fast_lsh_fps *chunk,
+                           uint64_t arrival_ns, uint64_t *ticket);
+/* FAST_LSH_OK with the chunk's counters (as fast_lsh_search defines them, for
+ * the chunk's pairs; max_bucket: the largest bucket holding one of its rows)
+ * and its completion time on the server clock once it is done, E_BUSY
+ * before (wait != 0 blocks until done), or the chunk's own error (E_INVALID
+ * for a bad row: the station is left unchanged). */
+int fast_lsh_server_poll(fast_lsh_server *server, uint64_t ticket, int wait, fast_lsh_stats *stats,
+                         uint64_t *done_ns);
+/* Copy a done chunk's pairs, sorted by (i, j), into HOST arrays and release
+ * the ticket (E_CAPACITY keeps it). */
+int fast_lsh_server_take(fast_lsh_server *server, uint64_t ticket, uint32_t *out_i, uint32_t *out_j,
+                         uint8_t *out_votes, uint64_t capacity);
+/* Nanoseconds on the server clock (steady, from server creation). */
+uint64_t fast_lsh_server_now_ns(fast_lsh_server *server);
+int fast_lsh_server_info(fast_lsh_server *server, fast_lsh_server_state *out);
+/* The batching rule on its own (host only): stations[k] is the station of
+ * the k-th waiting chunk, oldest first; picked[0..*n_picked) receives the
+ * indices of the chunks the next batch takes. */
+int fast_lsh_plan_batch(const uint32_t *stations, uint32_t n_waiting, uint32_t max_batch, uint32_t *picked,
+                        uint32_t *n_picked);
+
 /* Device memory the context's workspace holds now, in bytes (it grows to
  * the largest search run on the context and is freed by ctx_destroy). */
 int fast_lsh_workspace_bytes(fast_lsh_ctx *ctx, uint64_t *bytes);

@@ -6,8 +6,8 @@ filter, self-match exclusion and per-pair votes, all in hand-written HIP
 kernels behind the C-ABI of include/fast_lsh.h.  This package is the thin
 Python binding over that library.
 """
-from .fast_lsh import (MINHASH, MINMAX, FastLSH, FastLshError, Stats, library, make_hash, n_funcs,
-                       to_device_rows)
+from .fast_lsh import (MINHASH, MINMAX, FastLSH, FastLshError, Server, Stats, library, make_hash, n_funcs,
+                       plan_batch, to_device_rows)
 
-__all__ = ["MINHASH", "MINMAX", "FastLSH", "FastLshError", "Stats", "library", "make_hash", "n_funcs",
-           "to_device_rows"]
+__all__ = ["MINHASH", "MINMAX", "FastLSH", "FastLshError", "Server", "Stats", "library", "make_hash", "n_funcs",
+           "plan_batch", "to_device_rows"]

@@ -281,3 +281,121 @@ class FastLSH:
         m = int(offs[S])
         stats = [Stats(*[int(getattr(sts[k], f)) for f, _ in _Stats._fields_]) for k in range(S)]
         return oi[:m], oj[:m], ov[:m], np.array(list(offs), dtype=np.int64), stats
+
+
+# ---------------------------------------------------------------------------
+# Serving form
+# ---------------------------------------------------------------------------
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", _u32), ("max_chunk", _u32), ("delta_rows", _u64), ("slack_rows", _u64),
+                ("hbm_budget", _u64)]
+
+
+class _ServerState(ctypes.Structure):
+    _fields_ = [("stations", _u32), ("waiting", _u32), ("resident_bytes", _u64), ("workspace_bytes", _u64),
+                ("batches", _u64), ("chunks", _u64), ("largest_batch", _u64)]
+
+
+def _server_lib():
+    lib = library()
+    if not getattr(lib, "_server_ready", False):
+        lib.fast_lsh_server_create.argtypes = [_i32, ctypes.POINTER(Hash), ctypes.POINTER(Filter),
+                                               ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
+        lib.fast_lsh_server_destroy.argtypes = [_vp]
+        lib.fast_lsh_server_add_station.argtypes = [_vp, ctypes.POINTER(Fps), ctypes.POINTER(_u32)]
+        lib.fast_lsh_server_submit.argtypes = [_vp, _u32, ctypes.POINTER(Fps), _u64, ctypes.POINTER(_u64)]
+        lib.fast_lsh_server_poll.argtypes = [_vp, _u64, _i32, ctypes.POINTER(_Stats), ctypes.POINTER(_u64)]
+        lib.fast_lsh_server_take.argtypes = [_vp, _u64, _vp, _vp, _vp, _u64]
+        lib.fast_lsh_server_now_ns.argtypes = [_vp]
+        lib.fast_lsh_server_now_ns.restype = _u64
+        lib.fast_lsh_server_info.argtypes = [_vp, ctypes.POINTER(_ServerState)]
+        lib.fast_lsh_plan_batch.argtypes = [_vp, _u32, _u32, _vp, ctypes.POINTER(_u32)]
+        lib._server_ready = True
+    return lib
+
+
+def plan_batch(stations, max_batch: int):
+    """Indices of the waiting chunks (stations[k] = station of the k-th,
+    oldest first) that the next batch takes (host-side rule)."""
+    st = np.ascontiguousarray(stations, dtype=np.uint32)
+    picked = np.empty(max(len(st), 1), dtype=np.uint32)
+    n = _u32()
+    _check(_server_lib().fast_lsh_plan_batch(st.ctypes.data, len(st), max_batch, picked.ctypes.data,
+                                             ctypes.byref(n)))
+    return picked[: n.value].tolist()
+
+
+class Server:
+    """Stations with resident tables, searched chunk by chunk (continuous
+    batching on a worker thread of the library)."""
+
+    def __init__(self, dim, t, r, scheme, a, b, min_lag, min_votes, device=0, max_batch=8, max_chunk=3600,
+                 delta_rows=262144, slack_rows=2_000_000, hbm_budget=0):
+        lib = _server_lib()
+        h, self._keep = _hash_struct(dim, t, r, scheme, a, b)
+        cfg = ServerConfig(max_batch, max_chunk, delta_rows, slack_rows, hbm_budget)
+        flt = Filter(min_lag, min_votes, 0, 0)
+        sv = _vp()
+        _check(lib.fast_lsh_server_create(device, ctypes.byref(h), ctypes.byref(flt), ctypes.byref(cfg),
+                                          ctypes.byref(sv)))
+        self._sv = sv
+        self._rows = {}  # ticket -> device rows kept alive until the chunk is done
+
+    def close(self):
+        if getattr(self, "_sv", None):
+            _server_lib().fast_lsh_server_destroy(self._sv)
+            self._sv = None
+            self._rows.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_station(self, rows) -> int:
+        f, keep = _fps_struct(rows)
+        st = _u32()
+        _check(_server_lib().fast_lsh_server_add_station(self._sv, ctypes.byref(f), ctypes.byref(st)))
+        return int(st.value)
+
+    def now_ns(self) -> int:
+        return int(_server_lib().fast_lsh_server_now_ns(self._sv))
+
+    def submit(self, station: int, rows, arrival_ns: int | None = None) -> int:
+        f, keep = _fps_struct(rows)
+        tk = _u64()
+        arr = self.now_ns() if arrival_ns is None else arrival_ns
+        _check(_server_lib().fast_lsh_server_submit(self._sv, station, ctypes.byref(f), arr, ctypes.byref(tk)))
+        self._rows[int(tk.value)] = keep
+        return int(tk.value)
+
+    def poll(self, ticket: int, wait: bool = False):
+        """None while the chunk waits or runs; else (Stats, done_ns)."""
+        st = _Stats()
+        done = _u64()
+        rc = _server_lib().fast_lsh_server_poll(self._sv, ticket, 1 if wait else 0, ctypes.byref(st),
+                                                ctypes.byref(done))
+        if rc == E_BUSY:
+            return None
+        if rc != OK:
+            self._rows.pop(ticket, None)
+        _check(rc)
+        return Stats(*[int(getattr(st, k)) for k, _ in _Stats._fields_]), int(done.value)
+
+    def take(self, ticket: int):
+        """(i, j, votes) numpy arrays of a done chunk; releases the ticket."""
+        st, _ = self.poll(ticket, wait=True)
+        m = st.n_out
+        oi = np.empty(max(m, 1), np.uint32)
+        oj = np.empty(max(m, 1), np.uint32)
+        ov = np.empty(max(m, 1), np.uint8)
+        _check(_server_lib().fast_lsh_server_take(self._sv, ticket, oi.ctypes.data, oj.ctypes.data, ov.ctypes.data,
+                                                  m))
+        self._rows.pop(ticket, None)
+        return oi[:m], oj[:m], ov[:m]
+
+    def info(self) -> dict:
+        s = _ServerState()
+        _check(_server_lib().fast_lsh_server_info(self._sv, ctypes.byref(s)))
+        return {k: int(getattr(s, k)) for k, _ in _ServerState._fields_}
