@@ -58,10 +58,14 @@ def sig_traffic(n):
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--workload", choices=("station", "batched", "bounded"), default="station",
+    ap.add_argument("--chunks", type=int, default=3000, help="serving workload: chunks at the offered load")
+    ap.add_argument("--rate", type=float, default=40.0, help="serving workload: offered chunks/s (all stations)")
+    ap.add_argument("--stations", type=int, default=8, help="serving workload: stations")
+    ap.add_argument("--workload", choices=("station", "batched", "bounded", "serving"), default="station",
                     help="station: one 90-day station (default); batched: 12 stations of 1-16 M fingerprints "
                          "in one search, against 12 sequential searches; bounded: one 5-year station "
-                         "(157,788,000 fingerprints) with tables taken 10 at a time")
+                         "(157,788,000 fingerprints) with tables taken 10 at a time; serving: 8 stations of "
+                         "180 days resident, 3,600-row chunks arriving as Poisson streams")
     ap.add_argument("--group-tables", type=int, default=10, help="bounded workload: tables per group")
     ap.add_argument("--graph", action="store_true", help="replay the captured graph of the search prefix")
     ap.add_argument("--autotune", action="store_true", help="tune launch shapes on the first (warm-up) search")
@@ -85,6 +89,8 @@ def main():
         sys.exit(2)
     if args.workload == "bounded":
         return main_bounded(args)
+    if args.workload == "serving":
+        return main_serving(args)
     if args.workload == "batched":
         # This mode's process ended with a host segmentation fault within its
         # first seconds (while generating the 12 stations from 12 host threads),
@@ -302,21 +308,22 @@ def main_batched(args):
     print(json.dumps(line), flush=True)
 
 
-def upload_generated(spec, chunk=16_000_000):
-    """Generate spec's rows chunk by chunk into a pinned host buffer and copy
-    each chunk into one device tensor (int16 [n, nnz])."""
+def upload_generated(spec, lo=0, hi=None, chunk=16_000_000):
+    """Generate rows [lo, hi) of spec chunk by chunk into a pinned host buffer
+    and copy each chunk into one device tensor (int16 [hi - lo, nnz])."""
     import numpy as np
     import torch
 
     import synth
 
-    dev = torch.empty((spec.n, spec.nnz), dtype=torch.int16, device="cuda")
-    pinned = torch.empty((min(chunk, spec.n), spec.nnz), dtype=torch.int16, pin_memory=True)
-    for lo in range(0, spec.n, chunk):
-        hi = min(spec.n, lo + chunk)
-        synth.generate(spec, lo, hi, out=pinned[: hi - lo].numpy().view(np.uint16))
-        dev[lo:hi].copy_(pinned[: hi - lo])
-        print(f"# generated rows {lo}..{hi}", file=sys.stderr, flush=True)
+    hi = spec.n if hi is None else hi
+    dev = torch.empty((hi - lo, spec.nnz), dtype=torch.int16, device="cuda")
+    pinned = torch.empty((min(chunk, hi - lo), spec.nnz), dtype=torch.int16, pin_memory=True)
+    for c0 in range(lo, hi, chunk):
+        c1 = min(hi, c0 + chunk)
+        synth.generate(spec, c0, c1, out=pinned[: c1 - c0].numpy().view(np.uint16))
+        dev[c0 - lo:c1 - lo].copy_(pinned[: c1 - c0])
+        print(f"# generated rows {c0}..{c1}", file=sys.stderr, flush=True)
     del pinned
     return dev
 
@@ -394,6 +401,111 @@ def main_bounded(args):
                                 "cores": oracle.max_threads(), "kind": "oracle",
                                 "sample": f"first {ns} fingerprints searched alone, {cpu_s:.1f} s; the pair work "
                                           f"grows with N, so a slice over-states the CPU rate at full size"}
+    print(json.dumps(line), flush=True)
+
+
+def main_serving(args):
+    """Stations of 180 days resident; 3,600-row chunks arrive as independent
+    Poisson streams and are searched and inserted as they come."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1803_09835_amd as fl
+
+    S, CH = args.stations, synth.CHUNK
+    dim, t, r, scheme, L, v = 4096, 100, 4, fl.MINMAX, 5, 4
+    n_hist = synth.STATION_180D if args.n == 7_776_000 else args.n
+    # arrivals: station s at rate/S per second (exponential gaps, seed 304)
+    rng = np.random.default_rng(304)
+    per = args.rate / S
+    need = args.chunks // S + 40
+    times = [np.cumsum(rng.exponential(1.0 / per, need)) for _ in range(S)]
+    ev = sorted((times[s][c], s, c) for s in range(S) for c in range(need))[: args.chunks]
+    ramp = 100  # further chunks per station, all offered at once
+    used = [1 + max([c for _, s2, c in ev if s2 == s], default=-1) for s in range(S)]
+    n_stream = [(u + ramp) * CH for u in used]
+    a, b = fl.make_hash(204, fl.n_funcs(t, r, scheme))
+    sv = fl.Server(dim, t, r, scheme, a, b, L, v, max_batch=8, max_chunk=CH, delta_rows=262144,
+                   slack_rows=max(n_stream) + CH)
+    streams = []
+    tg = time.time()
+    for s in range(S):
+        spec = synth.Spec(n=n_hist + n_stream[s], seed=1040 + s, markov_keep=140, n_sources=4000, rep_min=3,
+                          rep_max=40, jac_lo_milli=400, jac_hi_milli=900, chain_len=1_000_000)
+        hist = upload_generated(spec, 0, n_hist)
+        sv.add_station(hist)
+        del hist
+        torch.cuda.empty_cache()
+        rows = synth.generate(spec, n_hist, n_hist + n_stream[s])
+        streams.append(fl.to_device_rows(rows))
+        print(f"# station {s}: {n_hist} history rows resident, {n_stream[s]} stream rows ready "
+              f"({time.time() - tg:.1f}s)", file=sys.stderr, flush=True)
+    info0 = sv.info()
+
+    def run(events, label):
+        """Submit (offset_s, station, chunk) at their times; latencies in ms."""
+        t0 = sv.now_ns() + 50_000_000
+        tickets = []
+        last = time.perf_counter()
+        for k, (off, s, c) in enumerate(events):
+            at = t0 + int(off * 1e9)
+            while True:
+                now = sv.now_ns()
+                if now >= at:
+                    break
+                if at - now > 2_000_000:
+                    time.sleep((at - now - 1_000_000) / 1e9)
+            tickets.append((at, sv.submit(s, streams[s][c * CH:(c + 1) * CH], at)))
+            if time.perf_counter() - last > 10:
+                last = time.perf_counter()
+                print(f"# {label}: {k + 1}/{len(events)} submitted", file=sys.stderr, flush=True)
+        lat, done, pairs = [], [], 0
+        for at, tk in tickets:
+            st, dn = sv.poll(tk, wait=True)
+            sv.take(tk)
+            lat.append((dn - at) / 1e6)
+            done.append(dn)
+            pairs += st.n_out
+        span = (max(done) - min(at for at, _ in tickets)) / 1e9
+        return np.array(lat), len(tickets) / span, pairs
+
+    lat, thr, pairs = run([(off, s, c) for off, s, c in ev], f"offered {args.rate}/s")
+    print(f"# offered load done: p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms",
+          file=sys.stderr, flush=True)
+    info1 = sv.info()
+    sat_events = [(0.0, s, used[s] + c) for c in range(ramp) for s in range(S)]
+    slat, sthr, _ = run(sat_events, "saturation")
+    info2 = sv.info()
+    batches = info2["batches"] - info1["batches"]
+    line = {
+        "metric": "fingerprints/s through MinHash+LSH vote count",
+        "value": round(sthr * CH, 1),
+        "unit": "fingerprints/s",
+        "n_gpus": 1, "steps": len(sat_events), "warmup": 0,
+        "ms_per_step": round(1000.0 / sthr, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"serving: {S} stations of 180 days (15,552,000 fingerprints each, Markov 70 %, "
+                               "4,000 repeating sources) resident; 3,600-fingerprint chunks searched against "
+                               "everything before them and inserted; Min-Max t=100 r=4, lag 5, v=4, no occurrence "
+                               "filter; value = fingerprints/s with all chunks offered at once (saturation)",
+                   "stations": S, "history_rows": n_hist, "chunk_rows": CH, "tables": t, "rows": r,
+                   "scheme": "minmax", "min_lag": L, "min_votes": v},
+        "offered_load": {"chunks_per_s": args.rate, "chunks": len(ev), "sustained_chunks_per_s": round(thr, 2),
+                         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                        "p99": round(float(np.percentile(lat, 99)), 3),
+                                        "mean": round(float(lat.mean()), 3), "max": round(float(lat.max()), 3)},
+                         "pairs": int(pairs)},
+        "saturation": {"chunks": len(sat_events), "chunks_per_s": round(sthr, 2), "batches": batches,
+                       "mean_batch": round(len(sat_events) / max(batches, 1), 2),
+                       "latency_ms": {"p50": round(float(np.percentile(slat, 50)), 3),
+                                      "p99": round(float(np.percentile(slat, 99)), 3)}},
+        "hbm_gb": {"resident": round(info2["resident_bytes"] / 1e9, 1),
+                   "workspace": round(info2["workspace_bytes"] / 1e9, 2),
+                   "stream_rows": round(sum(x.numel() * 2 for x in streams) / 1e9, 1)},
+        "roofline": None,
+    }
+    sv.close()
     print(json.dumps(line), flush=True)
 
 
