@@ -31,11 +31,11 @@ struct Plan {
 };
 
 // Bits of the mixed key the radix passes bin on: a multiple of 8 large enough
-// that an average bin of the largest station holds at most about 32
+// that an average bin of the largest station holds at most about 4
 // elements, plus the four station bits when keys are tagged.
 uint32_t bin_bits(uint64_t n_max, bool tagged) {
   uint32_t need = 0;
-  while ((32ull << need) < n_max) ++need;
+  while ((4ull << need) < n_max) ++need;
   if (tagged) need += 4;
   uint32_t B = (need + 7) / 8 * 8;
   return std::min<uint32_t>(32, std::max<uint32_t>(8, B));

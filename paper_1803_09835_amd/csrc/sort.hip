@@ -406,14 +406,14 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
   const uint32_t bsh = a.bin_shift;
   constexpr uint32_t kPer = kBinCap / kThreads;  // elements per thread, consecutive
   const uint32_t e0 = threadIdx.x * kPer;
-  // Load, and each thread's running bin start over its consecutive elements.
+  // Load with consecutive lanes on consecutive elements; then each thread's
+  // running bin start over its own consecutive elements.
   uint32_t run = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t e = e0 + q;
+    const uint32_t e = q * kThreads + threadIdx.x;
     if (e < m) {
-      const uint64_t k = K[lo + e];
-      sk[e] = k;
+      sk[e] = K[lo + e];
       sv[e] = V[lo + e];
       mixed[e] = 0;
     }
@@ -504,8 +504,9 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
     }
   }
   __syncthreads();
+  // only bins that mixed keys changed order
   for (uint32_t e = threadIdx.x; e < m; e += blockDim.x)
-    if (mixed[bs[e]] != 2) V[lo + e] = sv[e];
+    if (mixed[bs[e]] == 1) V[lo + e] = sv[e];
   // Buckets: every position gets its mark (the size of a small pair-capable
   // bucket starting there, else 0); large buckets go to a list.
   uint8_t* marks = a.marks + (uint64_t)seg * a.n + lo;
