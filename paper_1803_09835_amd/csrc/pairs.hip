@@ -138,10 +138,38 @@ struct RowReg {
     (void)rsw;
     return e;
   }
+  // Left row for the "another table shares the bucket" test (RSW > 0): the
+  // field of the pair's own table (equal for every pair of its bucket) and
+  // the padding fields (zero in every row) are inverted, so they never
+  // compare equal.
+  __device__ __forceinline__ void load_masked(const uint32_t* src, uint32_t own, uint32_t valid) {
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+      const uint32_t f = 2u * k;
+      const uint32_t m = ((f == own || f >= valid) ? 0x0000FFFFu : 0u) |
+                         ((f + 1 == own || f + 1 >= valid) ? 0xFFFF0000u : 0u);
+      w[k] = src[k] ^ m;
+    }
+  }
+  // Some 16-bit field equal to the other row's (after load_masked): the
+  // zero-half test (x - 0x00010001) & ~x & 0x80008000 on x = a ^ b, which
+  // is non-zero exactly when a half of x is zero.
+  __device__ __forceinline__ bool any_equal(const uint32_t* other) const {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+      const uint32_t x = w[k] ^ other[k];
+      acc |= (x - 0x00010001u) & ~x;
+    }
+    return (acc & 0x80008000u) != 0;
+  }
 };
 
 // One in-bucket pair of table u: i < j, `rx` the row of i, `ry` the row of j.
-template <int RSW>
+// FAST (need == 2, no distinct count, rx from load_masked): the group test
+// is "some other table of the group shares a bucket", decided without
+// counting; otherwise the equal fields are counted.
+template <int RSW, bool FAST>
 __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
                                            const RowReg<RSW>& rx, const uint32_t* ry, uint32_t rsw, uint32_t pad,
                                            PairTally& tl) {
@@ -159,6 +187,10 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
     tl.hi = (uint32_t)a.station_base[st + 1];
   }
   ++tl.ev;
+  if (FAST) {
+    if (rx.any_equal(ry)) exact_and_report(a, u, i, j);
+    return;
+  }
   const uint32_t eq = rx.eq(ry, rsw);
   if (a.want_distinct) {
     if (rx.eq_below(ry, rsw, u) == 0 || first_shared_is(a, u, i, j)) ++tl.nd;
@@ -264,7 +296,7 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
 // registers.  Heads and pair offsets come from
 // ballots and lane shuffles, so the only barriers are the LDS hand-offs of
 // a single wave; many such waves per CU overlap their loads.
-template <int RSW>
+template <int RSW, bool FAST>
 __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl) {
   constexpr uint32_t kSpan = 64 + 63;  // small buckets hold at most 64 members
   extern __shared__ uint32_t smem[];
@@ -338,9 +370,10 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
     tri_decode(m, p - bpof[b], x, y);
     uint32_t idx = lids[base + x];
     RowReg<RSW> rx;
-    rx.load(lrows + (base + x) * rswl, rsw);
+    const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
+    if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
     for (; p < pend; ++p) {
-      visit_pair<RSW>(a, u, idx, lids[base + y], rx, lrows + (base + y) * rswl, rsw, pad, tl);
+      visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, lrows + (base + y) * rswl, rsw, pad, tl);
       if (++y == m) {
         if (++x == m - 1) {
           if (++b >= nh) break;
@@ -350,7 +383,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
         }
         y = x + 1;
         idx = lids[base + x];
-        rx.load(lrows + (base + x) * rswl, rsw);
+        if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
       }
     }
   }
@@ -384,7 +417,7 @@ __global__ __launch_bounds__(kPT) void k_compact_big(PairArgs a, const uint4* bi
 
 // One tile (ta, tb) of the upper triangle of a large bucket's pair matrix;
 // every thread walks a contiguous range of the tile's pairs.
-template <int RSW>
+template <int RSW, bool FAST>
 __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* units, const uint4* big,
                                                     const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
                                                     uint32_t tb_size, uint32_t rswl) {
@@ -427,13 +460,16 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* 
       y = p - x * nbm;
     }
     RowReg<RSW> rx;
-    rx.load(rowsA + x * rswl, rsw);
+    const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
+    if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
     for (; p < pend; ++p) {
-      visit_pair<RSW>(a, u, idsA[x], idsB[y], rx, rowsB + y * rswl, rsw, pad, tl);
+      visit_pair<RSW, FAST>(a, u, idsA[x], idsB[y], rx, rowsB + y * rswl, rsw, pad, tl);
       if (++y == nbm) {
         ++x;
         y = diag ? x + 1 : 0;
-        if (x < na) rx.load(rowsA + x * rswl, rsw);
+        if (x < na) {
+          if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
+        }
       }
     }
   }
@@ -552,14 +588,24 @@ static unsigned grid_for(uint64_t count) {
   return (unsigned)(b == 0 ? 1 : (b < 65535 ? b : 65535));
 }
 
+// The group test reduces to "another table shares a bucket" when a pair
+// needs two shared tables in its group and no distinct count is wanted.
+static bool fast_test(const PairArgs& a) { return a.need == 2 && !a.want_distinct; }
+
 void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, hipStream_t s) {
   if (a.n == 0) return;
   const dim3 grid((unsigned)((a.n + 63) / 64), S);
   const size_t smem = (size_t)(127 * rswl + 127 + 64 + 65) * 4;
   switch (a.row_dw) {
-    case 10: hipLaunchKernelGGL((k_pairs_wave<10>), grid, dim3(64), smem, s, a, marks, rswl); break;
-    case 17: hipLaunchKernelGGL((k_pairs_wave<17>), grid, dim3(64), smem, s, a, marks, rswl); break;
-    default: hipLaunchKernelGGL((k_pairs_wave<0>), grid, dim3(64), smem, s, a, marks, rswl); break;
+    case 10:
+      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<10, true>), grid, dim3(64), smem, s, a, marks, rswl);
+      else hipLaunchKernelGGL((k_pairs_wave<10, false>), grid, dim3(64), smem, s, a, marks, rswl);
+      break;
+    case 17:
+      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<17, true>), grid, dim3(64), smem, s, a, marks, rswl);
+      else hipLaunchKernelGGL((k_pairs_wave<17, false>), grid, dim3(64), smem, s, a, marks, rswl);
+      break;
+    default: hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl); break;
   }
 }
 
@@ -575,9 +621,12 @@ void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
   switch (a.row_dw) {
-    case 10: hipLaunchKernelGGL((k_pairs_tile<10>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
-    case 17: hipLaunchKernelGGL((k_pairs_tile<17>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
-    default: hipLaunchKernelGGL((k_pairs_tile<0>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl); break;
+#define FL_TILE(R, F) \
+  hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl)
+    case 10: if (fast_test(a)) FL_TILE(10, true); else FL_TILE(10, false); break;
+    case 17: if (fast_test(a)) FL_TILE(17, true); else FL_TILE(17, false); break;
+    default: FL_TILE(0, false); break;
+#undef FL_TILE
   }
 }
 
