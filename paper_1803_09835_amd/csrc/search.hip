@@ -259,9 +259,11 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   LAUNCHCK();
   std::vector<uint32_t> hcnt(big_count);
   RC(d2h(c, hcnt.data(), bcnt, big_count));
-  // tile edge: a power of two with two tiles of rows and ids within 64 KB of LDS
+  // tile edge: 128 (two tiles of rows and ids in about 18 KB of LDS, so that
+  // eight workgroups share a CU and hide the row reads), smaller when rows are
+  // long enough that two tiles would exceed 64 KB
   const uint32_t fit = 65536 / (8 * j.rswl + 8);
-  uint32_t tb = 256;
+  uint32_t tb = 128;
   while (tb > 16 && tb > fit) tb >>= 1;
   std::vector<TileUnit> units;
   for (uint32_t b = 0; b < big_count; ++b) {
