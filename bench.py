@@ -32,13 +32,14 @@ CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 INT_PEAK_TOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0  # 39.32 T int32 lane-ops/s
 
 # Algorithmic int32 operations per hash evaluation h(x) = (a x + b) mod (2^31-1)
-# with its extreme updates: one 32x32->64-bit multiply-add, two for the
-# Mersenne fold (shift, add), two for the canonical residue (subtract,
-# unsigned min), and the extreme update with three-input min/max, which folds
-# two new values per instruction: 1/2 per tracked extreme.  (The kernel also
-# unpacks two 16-bit indices per register: half an operation per evaluation
-# that is not counted here.)
-OPS_PER_EVAL = {0: 5.5, 1: 6.0}  # MinHash, Min-Max
+# with its extreme updates: one 32x32->64-bit multiply-add and two for the
+# Mersenne fold (shift, add), then the extreme updates with three-input
+# min/max, which fold two new values per instruction: 1/2 per tracked
+# extreme (min for MinHash; min and max for Min-Max).  The folded value is
+# the hash value whenever it is below p, which the kernel checks with the
+# running maximum (for MinHash an extra half operation that is not counted,
+# like the half operation that unpacks two 16-bit indices per register).
+OPS_PER_EVAL = {0: 3.5, 1: 4.0}  # MinHash, Min-Max
 
 
 def sig_traffic(n):

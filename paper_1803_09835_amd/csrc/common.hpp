@@ -30,6 +30,15 @@ __device__ __forceinline__ uint32_t hash_mod(uint32_t a2, uint32_t b2, uint32_t 
   return min(s, s - kP);
 }
 
+// The folded hash before its last correction: s = (y & p) + (y >> 31) with
+// y = a x + b, congruent to y mod p.  For x < 2^16, s < 2^31 + 2^16 + 1, and
+// s is the canonical residue exactly when s < p; otherwise the residue is
+// s - p (below 2^16 + 2).
+__device__ __forceinline__ uint32_t hash_fold(uint32_t a2, uint32_t b2, uint32_t x) {
+  uint64_t y2 = (uint64_t)a2 * x + b2;
+  return ((uint32_t)y2 >> 1) + (uint32_t)(y2 >> 32);
+}
+
 // (u * w) mod p for u, w < p, canonical.
 __device__ __forceinline__ uint32_t mul_mod(uint32_t u, uint32_t w) {
   uint64_t z = (uint64_t)u * w;  // < 2^62

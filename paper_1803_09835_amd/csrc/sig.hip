@@ -16,6 +16,14 @@
 
 namespace fl {
 
+// Running extremes of two functions over the set elements, kept on the
+// folded values s (hash_fold): one multiply-add, a shift and an add per
+// evaluation, then three-input min and max (two elements per instruction).
+// While every s is below p the folded values are the hash values, so the
+// extremes are exact; an element with s >= p shows up as a maximum >= p, and
+// only then (about 2e-4 of the functions at d = 4096) are that function's
+// extremes recomputed from the canonical values (exact()).  The maximum is
+// kept for MinHash too, as that check.
 template <bool MINMAX>
 struct PairAcc {
   uint32_t mnA, mxA, mnB, mxB;
@@ -25,20 +33,34 @@ struct PairAcc {
   }
   __device__ __forceinline__ void add(uint32_t a2A, uint32_t b2A, uint32_t a2B, uint32_t b2B, uint32_t v) {
     const uint32_t x0 = v & 0xFFFFu, x1 = v >> 16;
-    const uint32_t hA0 = hash_mod(a2A, b2A, x0), hA1 = hash_mod(a2A, b2A, x1);
-    const uint32_t hB0 = hash_mod(a2B, b2B, x0), hB1 = hash_mod(a2B, b2B, x1);
-    mnA = min(mnA, min(hA0, hA1));
-    mnB = min(mnB, min(hB0, hB1));
-    if (MINMAX) {
-      mxA = max(mxA, max(hA0, hA1));
-      mxB = max(mxB, max(hB0, hB1));
-      // Serialise the running extremes: otherwise the compiler regroups the
-      // min and max reductions into separate trees and keeps every hash
-      // value of the row alive in registers.
-      asm volatile("" : "+v"(mnA), "+v"(mxA), "+v"(mnB), "+v"(mxB));
-    } else {
-      asm volatile("" : "+v"(mnA), "+v"(mnB));
-    }
+    const uint32_t sA0 = hash_fold(a2A, b2A, x0), sA1 = hash_fold(a2A, b2A, x1);
+    const uint32_t sB0 = hash_fold(a2B, b2B, x0), sB1 = hash_fold(a2B, b2B, x1);
+    mnA = min(mnA, min(sA0, sA1));
+    mnB = min(mnB, min(sB0, sB1));
+    mxA = max(mxA, max(sA0, sA1));
+    mxB = max(mxB, max(sB0, sB1));
+    // Serialise the running extremes: otherwise the compiler regroups the
+    // min and max reductions into separate trees and keeps every hash value
+    // of the row alive in registers.
+    asm volatile("" : "+v"(mnA), "+v"(mxA), "+v"(mnB), "+v"(mxB));
+  }
+  // Canonical extremes of one function, from every packed element pair that
+  // `each` hands to the callback.
+  template <typename Each>
+  __device__ __forceinline__ static void exact(uint32_t a2, uint32_t b2, Each each, uint32_t& mn, uint32_t& mx) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    each([&](uint32_t v) {
+      const uint32_t h0 = hash_mod(a2, b2, v & 0xFFFFu), h1 = hash_mod(a2, b2, v >> 16);
+      lo = min(lo, min(h0, h1));
+      hi = max(hi, max(h0, h1));
+    });
+    mn = lo;
+    mx = hi;
+  }
+  template <typename Each>
+  __device__ __forceinline__ void finish(uint32_t a2A, uint32_t b2A, uint32_t a2B, uint32_t b2B, Each each) {
+    if (mxA >= kP) exact(a2A, b2A, each, mnA, mxA);
+    if (mxB >= kP) exact(a2B, b2B, each, mnB, mxB);
   }
 };
 
@@ -171,6 +193,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 
       for (int w = 0; w < W; ++w) asm volatile("" : "+v"(xs[w]));
 #pragma unroll
       for (int w = 0; w < W; ++w) acc.add(a2A, b2A, a2B, b2B, xs[w]);
+      // the rare exact recomputation reads the row from memory (indexing the
+      // registers would move them to scratch)
+      acc.finish(a2A, b2A, a2B, b2B, [&](auto&& f) {
+        for (uint64_t k = 0; k < len; k += 2) {
+          const uint32_t x0 = a.ind[lo + k];
+          const uint32_t x1 = k + 1 < len ? a.ind[lo + k + 1] : x0;
+          f(x0 | (x1 << 16));
+        }
+      });
       kb.put(a, fA, acc.mnA, i, u, live);
       if (MINMAX) kb.put(a, fA, acc.mxA, i, u, live);
       if (two) {
@@ -216,11 +247,15 @@ __global__ __launch_bounds__(256) void k_sig_long(SigArgs a) {
       const uint32_t a2A = a.a2[fA], b2A = a.b2[fA], a2B = a.a2[fB], b2B = a.b2[fB];
       PairAcc<MINMAX> acc;
       acc.init();
-      for (uint64_t k = 0; k < len; k += 2) {
-        const uint32_t x0 = a.ind[lo + k];
-        const uint32_t x1 = k + 1 < len ? a.ind[lo + k + 1] : x0;
-        acc.add(a2A, b2A, a2B, b2B, x0 | (x1 << 16));
-      }
+      auto each = [&](auto&& f) {
+        for (uint64_t k = 0; k < len; k += 2) {
+          const uint32_t x0 = a.ind[lo + k];
+          const uint32_t x1 = k + 1 < len ? a.ind[lo + k + 1] : x0;
+          f(x0 | (x1 << 16));
+        }
+      };
+      each([&](uint32_t v) { acc.add(a2A, b2A, a2B, b2B, v); });
+      acc.finish(a2A, b2A, a2B, b2B, each);
       kb.put(a, fA, acc.mnA, i, u, live);
       if (MINMAX) kb.put(a, fA, acc.mxA, i, u, live);
       if (two) {
