@@ -234,7 +234,7 @@ int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, ui
  *   radix_tile    elements per workgroup of the grouping passes: 16384,
  *                 8192 or 4096 (0 keeps the current value);
  *   bucket_chunk  sorted positions per workgroup of the bucket kernel:
- *                 256..1792, a multiple of 256 (0 keeps the current value);
+ *                 256..1536, a multiple of 256 (0 keeps the current value);
  *   autotune      1: on the first search of each shape (stations, total n,
  *                 tables, bin bits) time every radix tile and bucket chunk
  *                 on that search's own data, keep the fastest for later

@@ -329,8 +329,8 @@ int fast_lsh_configure(fast_lsh_ctx* c, const fast_lsh_config* cfg) {
   for (uint32_t v = 0; v < kRadixTileVariants; ++v) known |= radix_tile_elems(v) == tile;
   if (!known) return fl_fail(FAST_LSH_E_INVALID, "radix_tile %u is not 16384, 8192 or 4096", cfg->radix_tile);
   const uint32_t chunk = cfg->bucket_chunk ? cfg->bucket_chunk : c->config.bucket_chunk;
-  if (chunk < 256 || chunk > 2048 || chunk % 256)
-    return fl_fail(FAST_LSH_E_INVALID, "bucket_chunk %u is not a multiple of 256 in [256, 2048]", cfg->bucket_chunk);
+  if (chunk < 256 || chunk > 1536 || chunk % 256)
+    return fl_fail(FAST_LSH_E_INVALID, "bucket_chunk %u is not a multiple of 256 in [256, 1536]", cfg->bucket_chunk);
   if (cfg->autotune > 1) return fl_fail(FAST_LSH_E_INVALID, "autotune must be 0 or 1");
   c->config.radix_tile = tile;
   c->config.bucket_chunk = chunk;

@@ -201,7 +201,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
       fill_u8(reinterpret_cast<uint8_t*>(j.er), j.spread_bytes, 0, s);
       fill_u32(&j.ctrl->big_count, 2, 0, s);  // big_count, bin_count
     };
-    static const uint32_t chunks[] = {768, 1024, 1536, 2048};
+    static const uint32_t chunks[] = {768, 1024, 1280, 1536};
     float best = 1e30f;
     uint32_t bestc = j.tc.bucket_chunk;
     for (uint32_t ch : chunks) {

@@ -286,7 +286,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t len, 
 // ---------------------------------------------------------------------------
 // Buckets from the bin-sorted order.
 // ---------------------------------------------------------------------------
-constexpr int kBinCap = 2048;
+// Elements one bucket workgroup holds in LDS: 7 per thread, an odd count so
+// that threads walking their own consecutive elements start on different
+// LDS banks.  Chunks are at most 1536 positions, so the bins that start in a
+// chunk (all but its last) always fit.
+constexpr int kBinCap = 1792;
 constexpr uint32_t kRankMax = 128;  // largest mixed bin ranked in LDS
 
 __device__ __forceinline__ bool kv_less(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb) {

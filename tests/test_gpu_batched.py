@@ -194,7 +194,7 @@ def test_launch_shapes_identical():
         ref = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
         assert c.config_used() == {"radix_tile": 16384, "bucket_chunk": 1536, "autotune": False}
         for tile in (16384, 8192, 4096):
-            for chunk in (256, 768, 1024, 2048):
+            for chunk in (256, 768, 1024, 1536):
                 say(f"[shapes] radix_tile={tile} bucket_chunk={chunk}")
                 c.configure(radix_tile=tile, bucket_chunk=chunk)
                 got = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
@@ -207,14 +207,14 @@ def test_launch_shapes_identical():
             say(f"[shapes] autotune call {k}")
             got = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100, graph=(k == 1))
             used = c.config_used()
-            assert used["radix_tile"] in (16384, 8192, 4096) and used["bucket_chunk"] in (768, 1024, 1536, 2048)
+            assert used["radix_tile"] in (16384, 8192, 4096) and used["bucket_chunk"] in (768, 1024, 1280, 1536)
             for x, y in zip(ref[:3], got[:3]):
                 assert torch.equal(x, y)
             assert ref[4] == got[4]
         with pytest.raises(fl.FastLshError):
             c.configure(radix_tile=1000)
         with pytest.raises(fl.FastLshError):
-            c.configure(bucket_chunk=4096)
+            c.configure(bucket_chunk=2048)
     finally:
         c.close()
 
