@@ -198,8 +198,9 @@ __device__ __forceinline__ uint32_t station_of(const uint64_t* base, uint32_t nb
   return s;
 }
 
-struct TileUnit {
-  uint32_t bucket, ta, tb, pad;
-};
+// Buckets of at most kSmallBucket members are handled by the wave-per-chunk
+// pair kernel (their members staged in LDS); larger ones by the tile kernel.
+constexpr uint32_t kSmallBucket = 32;
+
 
 }  // namespace fl

@@ -154,6 +154,11 @@ struct RowReg {
   // Some 16-bit field equal to the other row's (after load_masked): the
   // zero-half test (x - 0x00010001) & ~x & 0x80008000 on x = a ^ b, which
   // is non-zero exactly when a half of x is zero.
+  // The other row in registers (all loads issued at once).
+  __device__ __forceinline__ static void fetch(const uint32_t* src, uint32_t (&v)[kW]) {
+#pragma unroll
+    for (int k = 0; k < kW; ++k) v[k] = src[k];
+  }
   __device__ __forceinline__ bool any_equal(const uint32_t* other) const {
     uint32_t acc = 0;
 #pragma unroll
@@ -173,6 +178,14 @@ template <int RSW, bool FAST>
 __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
                                            const RowReg<RSW>& rx, const uint32_t* ry, uint32_t rsw, uint32_t pad,
                                            PairTally& tl) {
+  // FAST: the right row is read before the id checks, so that its loads and
+  // the partner id's share one LDS round trip
+  uint32_t rv[RowReg<RSW>::kW];
+  if (FAST) {
+    RowReg<RSW>::fetch(ry, rv);
+#pragma unroll
+    for (int k = 0; k < RowReg<RSW>::kW; ++k) asm volatile("" : "+v"(rv[k]));  // keep the loads above the branch
+  }
   if (i == kDead || j == kDead || j - i < a.min_lag) return;
   if (a.nstation > 1 && (i < tl.lo || i >= tl.hi)) {
     const uint32_t st = station_of(a.station_base, a.nstation, i);
@@ -188,7 +201,7 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
   }
   ++tl.ev;
   if (FAST) {
-    if (rx.any_equal(ry)) exact_and_report(a, u, i, j);
+    if (rx.any_equal(rv)) exact_and_report(a, u, i, j);
     return;
   }
   const uint32_t eq = rx.eq(ry, rsw);
@@ -298,7 +311,7 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
 // a single wave; many such waves per CU overlap their loads.
 template <int RSW, bool FAST>
 __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl) {
-  constexpr uint32_t kSpan = 64 + 63;  // small buckets hold at most 64 members
+  constexpr uint32_t kSpan = 64 + kSmallBucket - 1;  // heads in 64 positions, members up to kSmallBucket
   extern __shared__ uint32_t smem[];
   uint32_t* lrows = smem;                   // kSpan * rswl
   uint32_t* lids = lrows + kSpan * rswl;    // kSpan
@@ -417,19 +430,53 @@ __global__ __launch_bounds__(kPT) void k_compact_big(PairArgs a, const uint4* bi
 
 // One tile (ta, tb) of the upper triangle of a large bucket's pair matrix;
 // every thread walks a contiguous range of the tile's pairs.
+// Sizes of the large buckets (their member offsets are the scan of these).
+__global__ __launch_bounds__(kPT) void k_big_sizes(const uint4* big, uint32_t nbig, uint64_t* sizes) {
+  const uint64_t b = (uint64_t)blockIdx.x * kPT + threadIdx.x;
+  if (b < nbig) sizes[b] = big[b].z;
+}
+
+// Tiles of each large bucket: the upper triangle, diagonal included, of its
+// ceil(cnt / tb) x ceil(cnt / tb) grid of tb x tb tiles.
+__global__ __launch_bounds__(kPT) void k_tile_counts(const uint32_t* cnt, uint32_t nbig, uint32_t tb,
+                                                     uint64_t* tiles) {
+  const uint64_t b = (uint64_t)blockIdx.x * kPT + threadIdx.x;
+  if (b >= nbig) return;
+  const uint64_t m = cnt[b], ntl = (m + tb - 1) / tb;
+  tiles[b] = m < 2 ? 0 : ntl * (ntl + 1) / 2;
+}
+
+// One tile (ta, tb) of the upper triangle of a large bucket's pair matrix;
+// every thread walks a contiguous range of the tile's pairs.  Workgroup
+// unit_base + blockIdx.x takes the bucket whose tile range [toff[b],
+// toff[b+1]) holds it, and within it the tile of that rank.
 template <int RSW, bool FAST>
-__global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const TileUnit* units, const uint4* big,
-                                                    const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
-                                                    uint32_t tb_size, uint32_t rswl) {
+__global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* toff, uint32_t nbig,
+                                                    uint64_t unit_base, const uint4* big, const uint64_t* cofs,
+                                                    const uint32_t* ids, const uint32_t* cnt, uint32_t tb_size,
+                                                    uint32_t rswl) {
   extern __shared__ uint32_t smem[];
-  const TileUnit un = units[blockIdx.x];
+  const uint64_t unit = unit_base + blockIdx.x;
+  uint32_t bk = 0;
+  {
+    uint32_t lo = 0, hi = nbig;  // last b with toff[b] <= unit
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (toff[mid] <= unit) lo = mid; else hi = mid;
+    }
+    bk = lo;
+  }
+  const uint32_t m = cnt[bk];
+  const uint32_t ntl = (m + tb_size - 1) / tb_size;
+  uint32_t tx, ty;
+  tri_decode(ntl + 1, (uint32_t)(unit - toff[bk]), tx, ty);  // pairs x < y of ntl + 1 items: tile (x, y - 1)
+  const uint32_t ta = tx, tbi = ty - 1;
   const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
-  const uint32_t u = big[un.bucket].y + a.table_offset;  // table of the bucket
-  const uint32_t* bid = ids + cofs[un.bucket];
-  const uint32_t m = cnt[un.bucket];
-  const uint32_t a0 = un.ta * tb_size, b0 = un.tb * tb_size;
+  const uint32_t u = big[bk].y + a.table_offset;  // table of the bucket
+  const uint32_t* bid = ids + cofs[bk];
+  const uint32_t a0 = ta * tb_size, b0 = tbi * tb_size;
   const uint32_t na = min(tb_size, m - a0);
-  const bool diag = un.ta == un.tb;
+  const bool diag = ta == tbi;
   const uint32_t nbm = diag ? na : min(tb_size, m - b0);
   uint32_t* rowsA = smem;
   uint32_t* rowsB = diag ? rowsA : rowsA + tb_size * rswl;
@@ -595,7 +642,8 @@ static bool fast_test(const PairArgs& a) { return a.need == 2 && !a.want_distinc
 void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, hipStream_t s) {
   if (a.n == 0) return;
   const dim3 grid((unsigned)((a.n + 63) / 64), S);
-  const size_t smem = (size_t)(127 * rswl + 127 + 64 + 65) * 4;
+  constexpr uint32_t kSpan = 64 + kSmallBucket - 1;
+  const size_t smem = (size_t)(kSpan * rswl + kSpan + 64 + 65) * 4;
   switch (a.row_dw) {
     case 10:
       if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<10, true>), grid, dim3(64), smem, s, a, marks, rswl);
@@ -615,14 +663,23 @@ void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, cons
   hipLaunchKernelGGL(k_compact_big, dim3(nbig), dim3(kPT), 0, s, a, big, cofs, ids, cnt);
 }
 
-void launch_pairs_tile(const PairArgs& a, const TileUnit* units, uint32_t nunits, const uint4* big,
-                       const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt, uint32_t tb_size,
-                       uint32_t rswl, hipStream_t s) {
+void launch_big_sizes(const uint4* big, uint32_t nbig, uint64_t* sizes, hipStream_t s) {
+  if (nbig) hipLaunchKernelGGL(k_big_sizes, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, big, nbig, sizes);
+}
+
+void launch_tile_counts(const uint32_t* cnt, uint32_t nbig, uint32_t tb, uint64_t* tiles, hipStream_t s) {
+  if (nbig) hipLaunchKernelGGL(k_tile_counts, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, cnt, nbig, tb, tiles);
+}
+
+void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, uint32_t nbig, uint64_t unit_base, uint32_t nunits,
+                       const uint4* big, const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
+                       uint32_t tb_size, uint32_t rswl, hipStream_t s) {
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
   switch (a.row_dw) {
 #define FL_TILE(R, F) \
-  hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, units, big, cofs, ids, cnt, tb_size, rswl)
+  hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, toff, nbig, unit_base, big, cofs, ids, \
+                     cnt, tb_size, rswl)
     case 10: if (fast_test(a)) FL_TILE(10, true); else FL_TILE(10, false); break;
     case 17: if (fast_test(a)) FL_TILE(17, true); else FL_TILE(17, false); break;
     default: FL_TILE(0, false); break;

@@ -241,46 +241,43 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
   return FAST_LSH_OK;
 }
 
-// Pairs of the large buckets (tiled kernel), from descriptors on the host.
+// Pairs of the large buckets (tiled kernel).  Member offsets, compaction
+// (excluded members dropped) and tile counts are computed on the device; the
+// host reads back two totals (members, tiles) to size the ids and the grid.
 int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   if (big_count == 0) return FAST_LSH_OK;
   hipStream_t s = c->stream;
-  std::vector<uint4> hbig(big_count);
-  RC(d2h(c, hbig.data(), j.bdesc, big_count));
-  std::vector<uint64_t> cofs(big_count + 1, 0);
-  for (uint32_t b = 0; b < big_count; ++b) cofs[b + 1] = cofs[b] + hbig[b].z;
-  uint64_t* dcofs;
+  uint64_t *cofs, *toff, *sums;
   uint32_t *bids, *bcnt;
-  RC(ws<uint64_t>(c, "big_cofs", big_count + 1, &dcofs));
-  RC(ws<uint32_t>(c, "big_ids", cofs.back() + 1, &bids));
+  RC(ws<uint64_t>(c, "big_cofs", big_count + 1, &cofs));
+  RC(ws<uint64_t>(c, "big_toff", big_count + 1, &toff));
+  RC(ws<uint64_t>(c, "big_sums", scan_sums_elems(big_count, 1), &sums));
   RC(ws<uint32_t>(c, "big_cnt", big_count, &bcnt));
-  RC(h2d(c, dcofs, cofs.data(), big_count + 1));
-  launch_compact_big(j.pa, j.bdesc, big_count, dcofs, bids, bcnt, s);
+  launch_big_sizes(j.bdesc, big_count, cofs, s);
+  scan_u64(cofs, big_count, 1, sums, cofs + big_count, s);
   LAUNCHCK();
-  std::vector<uint32_t> hcnt(big_count);
-  RC(d2h(c, hcnt.data(), bcnt, big_count));
+  uint64_t members = 0;
+  RC(d2h(c, &members, cofs + big_count));
+  RC(ws<uint32_t>(c, "big_ids", members + 1, &bids));
+  launch_compact_big(j.pa, j.bdesc, big_count, cofs, bids, bcnt, s);
+  LAUNCHCK();
   // tile edge: 128 (two tiles of rows and ids in about 18 KB of LDS, so that
   // eight workgroups share a CU and hide the row reads), smaller when rows are
   // long enough that two tiles would exceed 64 KB
   const uint32_t fit = 65536 / (8 * j.rswl + 8);
   uint32_t tb = 128;
   while (tb > 16 && tb > fit) tb >>= 1;
-  std::vector<TileUnit> units;
-  for (uint32_t b = 0; b < big_count; ++b) {
-    const uint32_t m = hcnt[b];
-    if (m < 2) continue;
-    const uint32_t ntl = (m + tb - 1) / tb;
-    for (uint32_t x = 0; x < ntl; ++x)
-      for (uint32_t y = x; y < ntl; ++y) units.push_back(TileUnit{b, x, y, 0});
-  }
-  if (units.empty()) return FAST_LSH_OK;
-  TileUnit* du;
-  RC(ws<TileUnit>(c, "units", units.size(), &du));
-  RC(h2d(c, du, units.data(), units.size()));
-  for (size_t u0 = 0; u0 < units.size(); u0 += 1u << 20) {
-    const uint32_t cnt = (uint32_t)std::min<size_t>(1u << 20, units.size() - u0);
+  launch_tile_counts(bcnt, big_count, tb, toff, s);
+  scan_u64(toff, big_count, 1, sums, toff + big_count, s);
+  LAUNCHCK();
+  uint64_t units = 0;
+  RC(d2h(c, &units, toff + big_count));
+  // at most 2^22 workgroups of 256 threads per launch (work-items per grid
+  // dimension stay below 2^32)
+  for (uint64_t u0 = 0; u0 < units; u0 += 1u << 22) {
+    const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 22, units - u0);
     prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
-    launch_pairs_tile(j.pa, du + u0, cnt, j.bdesc, dcofs, bids, bcnt, tb, j.rswl, s);
+    launch_pairs_tile(j.pa, toff, big_count, u0, cnt, j.bdesc, cofs, bids, bcnt, tb, j.rswl, s);
     prof_end(c);
     LAUNCHCK();
   }
@@ -431,7 +428,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   RC(ws<uint64_t>(c, "station_base", S + 1, &j.sbase));
   // Buckets of at most smax members are marked in place and handled by the
   // wave-per-chunk pair kernel; larger ones go to the tiled kernel.
-  const uint32_t smax = 64;
+  const uint32_t smax = kSmallBucket;
   const uint64_t cap_big = tn / (smax + 1) + 1;
   const uint64_t cap_bin = tn / 129 + t + 1;  // oversized bins and mixed bins above 128 elements
   RC(ws<uint4>(c, "bdesc", cap_big, &j.bdesc));
@@ -647,7 +644,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   const uint32_t nt_max = radix_tiles(N, kRadixTileVariants - 1);
   RC(ws<uint32_t>(c, "hist", (uint64_t)256 * nt_max * TGm, &j.hist));
   RC(ws<uint32_t>(c, "sums", scan_sums_elems((uint64_t)256 * nt_max, TGm), &j.sums));
-  const uint32_t smax = 64;
+  const uint32_t smax = kSmallBucket;
   const uint64_t cap_big = gn / (smax + 1) + 1;
   const uint64_t cap_bin = gn / 129 + TGm + 1;
   RC(ws<uint4>(c, "bdesc", cap_big, &j.bdesc));
