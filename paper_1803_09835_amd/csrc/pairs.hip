@@ -404,28 +404,33 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
 }
 
 // Unflagged members of each large bucket, compacted in order.
-__global__ __launch_bounds__(kPT) void k_compact_big(PairArgs a, const uint4* big, const uint64_t* cofs,
-                                                     uint32_t* ids, uint32_t* cnt) {
+// (a bounded grid walks the buckets: their number can exceed what one
+// workgroup per bucket could launch)
+__global__ __launch_bounds__(kPT) void k_compact_big(PairArgs a, const uint4* big, uint32_t nbig,
+                                                     const uint64_t* cofs, uint32_t* ids, uint32_t* cnt) {
   __shared__ uint32_t ws[8];
   __shared__ uint32_t s_carry;
-  const uint4 d = big[blockIdx.x];
-  const uint32_t* ord = a.order + (uint64_t)d.y * a.n + d.x;
-  uint32_t* out = ids + cofs[blockIdx.x];
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  for (uint32_t c = 0; c < d.z; c += kPT) {
-    const uint32_t q = c + threadIdx.x;
-    const uint32_t id = q < d.z ? ord[q] : 0u;
-    const uint32_t keep = (q < d.z && a.flags[id] == 0) ? 1u : 0u;
-    uint32_t tot;
-    const uint32_t x = block_scan_excl<uint32_t>(keep, ws, &tot);
-    const uint32_t carry = s_carry;
-    if (keep) out[carry + x] = id;
+  for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+    const uint4 d = big[b];
+    const uint32_t* ord = a.order + (uint64_t)d.y * a.n + d.x;
+    uint32_t* out = ids + cofs[b];
+    if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    if (threadIdx.x == 0) s_carry = carry + tot;
+    for (uint32_t c = 0; c < d.z; c += kPT) {
+      const uint32_t q = c + threadIdx.x;
+      const uint32_t id = q < d.z ? ord[q] : 0u;
+      const uint32_t keep = (q < d.z && a.flags[id] == 0) ? 1u : 0u;
+      uint32_t tot;
+      const uint32_t x = block_scan_excl<uint32_t>(keep, ws, &tot);
+      const uint32_t carry = s_carry;
+      if (keep) out[carry + x] = id;
+      __syncthreads();
+      if (threadIdx.x == 0) s_carry = carry + tot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[b] = s_carry;
     __syncthreads();
   }
-  if (threadIdx.x == 0) cnt[blockIdx.x] = s_carry;
 }
 
 // One tile (ta, tb) of the upper triangle of a large bucket's pair matrix;
@@ -660,7 +665,8 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
 void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, const uint64_t* cofs, uint32_t* ids,
                         uint32_t* cnt, hipStream_t s) {
   if (nbig == 0) return;
-  hipLaunchKernelGGL(k_compact_big, dim3(nbig), dim3(kPT), 0, s, a, big, cofs, ids, cnt);
+  hipLaunchKernelGGL(k_compact_big, dim3(nbig < 65536u ? nbig : 65536u), dim3(kPT), 0, s, a, big, nbig, cofs, ids,
+                     cnt);
 }
 
 void launch_big_sizes(const uint4* big, uint32_t nbig, uint64_t* sizes, hipStream_t s) {
