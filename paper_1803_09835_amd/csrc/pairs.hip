@@ -39,27 +39,75 @@ __device__ __forceinline__ bool keys_equal(const PairArgs& a, uint32_t tab, uint
   return a.hi32 ? a.hi32[o + i] == a.hi32[o + j] : a.mkeys[o + i] == a.mkeys[o + j];
 }
 
-// Exact shared tables of (i, j) from global rows and mixed keys; reports the
-// pair if table u is its owner.
-__device__ __forceinline__ void exact_and_report(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
-  uint32_t votes = 0, owner = 0xFFFFFFFFu;
+// Bit k: fields f0 + k of rows ri and rj (nd <= 16 dwords from dword f0 / 2)
+// hold equal sub-keys.
+__device__ __forceinline__ uint32_t field_eq_mask(const uint32_t* ri, const uint32_t* rj, uint32_t nd) {
+  uint32_t m = 0;
+#pragma unroll 4
+  for (uint32_t d = 0; d < nd; ++d) {
+    const uint32_t x = ri[d] ^ rj[d];
+    m |= ((x & 0xFFFFu) == 0 ? 1u : 0u) << (2 * d);
+    m |= ((x >> 16) == 0 ? 1u : 0u) << (2 * d + 1);
+  }
+  return m;
+}
+
+// Tables tb + k (bit k of m, lowest first) whose full keys of i and j are
+// equal, counted until `limit`; the keys of four candidates are read at once.
+__device__ __forceinline__ uint32_t count_shared(const PairArgs& a, uint32_t m, uint32_t tb, uint32_t i, uint32_t j,
+                                                 uint32_t limit) {
+  uint32_t cnt = 0;
+  while (m && cnt < limit) {
+    uint32_t tab[4];
+    bool live[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      live[q] = m != 0;
+      tab[q] = tb + (live[q] ? (uint32_t)__builtin_ctz(m) : 0u);  // a dead slot re-reads table tb
+      m &= m - 1;
+    }
+    bool eq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) eq[q] = keys_equal(a, tab[q], i, j);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cnt += (live[q] && eq[q] && cnt < limit) ? 1u : 0u;
+  }
+  return cnt;
+}
+
+// Shared tables among the first `fields` tables of rows ri / rj's group
+// (its first table tb), counted until `limit`: candidates are the fields
+// with equal sub-keys, the full keys decide.
+__device__ __forceinline__ uint32_t group_shared(const PairArgs& a, const uint32_t* ri, const uint32_t* rj, uint32_t tb,
+                                                 uint32_t i, uint32_t j, uint32_t fields, uint32_t limit) {
+  uint32_t cnt = 0;
+  for (uint32_t f0 = 0; f0 < fields && cnt < limit; f0 += 32) {
+    uint32_t m = field_eq_mask(ri + f0 / 2, rj + f0 / 2, min(16u, (fields - f0 + 1) / 2));
+    if (fields - f0 < 32) m &= (1u << (fields - f0)) - 1;
+    cnt += count_shared(a, m, tb + f0, i, j, limit - cnt);
+  }
+  return cnt;
+}
+
+// Owner rule: a pair is reported by the smallest shared table of the first
+// group holding at least `need` shared tables, with its exact vote count.
+// Called for table u after lower_in_group found no shared table below u in
+// u's group, so u owns the pair exactly when no earlier group holds `need`
+// shared tables and u's group does.  An earlier group stops being counted
+// (and the check ends) as soon as it reaches `need`.
+__device__ void exact_and_report(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
+  const uint32_t gu = u / a.tables_per_group;
+  uint32_t votes = 0;
   for (uint32_t g = 0; g < a.G; ++g) {
+    const uint32_t fields = min(a.tables_per_group, a.t - g * a.tables_per_group);
     const uint32_t* ri = a.rows + ((uint64_t)g * a.n + i) * a.row_dw;
     const uint32_t* rj = a.rows + ((uint64_t)g * a.n + j) * a.row_dw;
-    const uint32_t valid = min(a.tables_per_group, a.t - g * a.tables_per_group);
-    uint32_t cnt = 0, minu = 0xFFFFFFFFu;
-    for (uint32_t k = 0; k < valid; ++k) {
-      if (row_field(ri, k) != row_field(rj, k)) continue;
-      const uint32_t tab = g * a.tables_per_group + k;
-      if (keys_equal(a, tab, i, j)) {
-        ++cnt;
-        minu = tab < minu ? tab : minu;
-      }
-    }
+    const uint32_t cnt = group_shared(a, ri, rj, g * a.tables_per_group, i, j, fields, g < gu ? a.need : 0xFFFFFFFFu);
+    if (g < gu && cnt >= a.need) return;   // the owner lies in group g
+    if (g == gu && cnt < a.need) return;   // the owner, if any, lies in a later group
     votes += cnt;
-    if (owner == 0xFFFFFFFFu && cnt >= a.need) owner = minu;
   }
-  if (owner == u && votes >= a.min_votes) {
+  if (votes >= a.min_votes) {
     const uint32_t q = atomicAdd(a.out_count, 1u);
     if (q < a.out_cap) {
       a.out_i[q] = i;
@@ -69,16 +117,16 @@ __device__ __forceinline__ void exact_and_report(const PairArgs& a, uint32_t u, 
   }
 }
 
-// True when no table below u exactly shares a bucket with (i, j) (G == 1:
-// one group, field == table).
-__device__ __forceinline__ bool first_shared_is(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j) {
-  const uint32_t* ri = a.rows + (uint64_t)i * a.row_dw;
-  const uint32_t* rj = a.rows + (uint64_t)j * a.row_dw;
-  for (uint32_t tab = 0; tab < u; ++tab) {
-    if (row_field(ri, tab) != row_field(rj, tab)) continue;
-    if (keys_equal(a, tab, i, j)) return false;
-  }
-  return true;
+// Some table of u's group below u exactly shares a bucket with (i, j);
+// rl, rr: the two rows of that group (in LDS).  Such a table precedes u in
+// the pair's shared set within the group, so u cannot own the pair, and with
+// one group holding every table u is then not the pair's first shared table.
+// A pair sharing s tables thus gets its full check (reading every group)
+// only from the smallest shared table of each group, not from all s.
+__device__ __forceinline__ bool lower_in_group(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
+                                               const uint32_t* rl, const uint32_t* rr) {
+  const uint32_t g = u / a.tables_per_group, own = u - g * a.tables_per_group;
+  return group_shared(a, rl, rr, g * a.tables_per_group, i, j, own, 1) != 0;
 }
 
 // Per-lane vote tallies of one station; [lo, hi) is that station's id range
@@ -151,14 +199,14 @@ struct RowReg {
       w[k] = src[k] ^ m;
     }
   }
-  // Some 16-bit field equal to the other row's (after load_masked): the
-  // zero-half test (x - 0x00010001) & ~x & 0x80008000 on x = a ^ b, which
-  // is non-zero exactly when a half of x is zero.
   // The other row in registers (all loads issued at once).
   __device__ __forceinline__ static void fetch(const uint32_t* src, uint32_t (&v)[kW]) {
 #pragma unroll
     for (int k = 0; k < kW; ++k) v[k] = src[k];
   }
+  // Some field equal to the other row's (after load_masked): the zero-half
+  // test (x - 0x00010001) & ~x & 0x80008000 on x = a ^ b, non-zero exactly
+  // when a half of x is zero.
   __device__ __forceinline__ bool any_equal(const uint32_t* other) const {
     uint32_t acc = 0;
 #pragma unroll
@@ -170,14 +218,15 @@ struct RowReg {
   }
 };
 
-// One in-bucket pair of table u: i < j, `rx` the row of i, `ry` the row of j.
+// One in-bucket pair of table u: i < j, `rx` the row of i (`rl` in LDS),
+// `ry` the row of j (in LDS).
 // FAST (need == 2, no distinct count, rx from load_masked): the group test
 // is "some other table of the group shares a bucket", decided without
 // counting; otherwise the equal fields are counted.
 template <int RSW, bool FAST>
 __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
-                                           const RowReg<RSW>& rx, const uint32_t* ry, uint32_t rsw, uint32_t pad,
-                                           PairTally& tl) {
+                                           const RowReg<RSW>& rx, const uint32_t* rl, const uint32_t* ry,
+                                           uint32_t rsw, uint32_t pad, PairTally& tl) {
   // FAST: the right row is read before the id checks, so that its loads and
   // the partner id's share one LDS round trip
   uint32_t rv[RowReg<RSW>::kW];
@@ -201,14 +250,19 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
   }
   ++tl.ev;
   if (FAST) {
-    if (rx.any_equal(rv)) exact_and_report(a, u, i, j);
+    if (rx.any_equal(rv) && !lower_in_group(a, u, i, j, rl, ry)) exact_and_report(a, u, i, j);
     return;
   }
   const uint32_t eq = rx.eq(ry, rsw);
-  if (a.want_distinct) {
-    if (rx.eq_below(ry, rsw, u) == 0 || first_shared_is(a, u, i, j)) ++tl.nd;
+  if (a.want_distinct) {  // one group: "lower" is "a table below u shares"
+    const bool lower = rx.eq_below(ry, rsw, u) != 0 && lower_in_group(a, u, i, j, rl, ry);
+    if (!lower) {
+      ++tl.nd;
+      if (eq - pad >= a.need) exact_and_report(a, u, i, j);
+    }
+    return;
   }
-  if (eq - pad >= a.need) exact_and_report(a, u, i, j);
+  if (eq - pad >= a.need && !lower_in_group(a, u, i, j, rl, ry)) exact_and_report(a, u, i, j);
 }
 
 // Called by every lane of the wave.  When all lanes with a non-zero tally
@@ -386,7 +440,8 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
     const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
     if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
     for (; p < pend; ++p) {
-      visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, lrows + (base + y) * rswl, rsw, pad, tl);
+      visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, lrows + (base + x) * rswl, lrows + (base + y) * rswl,
+                                 rsw, pad, tl);
       if (++y == m) {
         if (++x == m - 1) {
           if (++b >= nh) break;
@@ -515,7 +570,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
     const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
     if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
     for (; p < pend; ++p) {
-      visit_pair<RSW, FAST>(a, u, idsA[x], idsB[y], rx, rowsB + y * rswl, rsw, pad, tl);
+      visit_pair<RSW, FAST>(a, u, idsA[x], idsB[y], rx, rowsA + x * rswl, rowsB + y * rswl, rsw, pad, tl);
       if (++y == nbm) {
         ++x;
         y = diag ? x + 1 : 0;
@@ -658,7 +713,9 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
       if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<17, true>), grid, dim3(64), smem, s, a, marks, rswl);
       else hipLaunchKernelGGL((k_pairs_wave<17, false>), grid, dim3(64), smem, s, a, marks, rswl);
       break;
-    default: hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl); break;
+    default:
+      hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl);
+      break;
   }
 }
 
@@ -682,15 +739,15 @@ void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, uint32_t nbig, u
                        uint32_t tb_size, uint32_t rswl, hipStream_t s) {
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
-  switch (a.row_dw) {
-#define FL_TILE(R, F) \
+#define FL_TILE(R, F)                                                                                        \
   hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, toff, nbig, unit_base, big, cofs, ids, \
                      cnt, tb_size, rswl)
+  switch (a.row_dw) {
     case 10: if (fast_test(a)) FL_TILE(10, true); else FL_TILE(10, false); break;
     case 17: if (fast_test(a)) FL_TILE(17, true); else FL_TILE(17, false); break;
     default: FL_TILE(0, false); break;
-#undef FL_TILE
   }
+#undef FL_TILE
 }
 
 void launch_split_out(const uint64_t* key, const uint32_t* val, uint64_t count, uint32_t* oi, uint32_t* oj,

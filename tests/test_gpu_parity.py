@@ -197,6 +197,36 @@ def test_search_mixed_huge_bins(ctx):
     _compare(ctx, rows, 256, 4, 2, fl.MINHASH, 46, 1, 2, label="mixed-identical")
 
 
+def _near_copies(n_base, copies, dim, nnz, lo, hi, seed):
+    """Each base row and `copies` variants with lo..hi of its indices
+    replaced (Jaccard about 0.3-0.5: pairs sharing a handful of tables),
+    in random order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_base):
+        base = rng.choice(dim, nnz, replace=False)
+        out.append(np.sort(base))
+        for _ in range(copies):
+            k = int(rng.integers(lo, hi + 1))
+            keep = rng.choice(base, nnz - k, replace=False)
+            pool = np.setdiff1d(np.arange(dim), base)
+            out.append(np.sort(np.concatenate([keep, rng.choice(pool, k, replace=False)])))
+    rows = np.stack(out).astype(np.uint16)
+    return rows[rng.permutation(len(rows))]
+
+
+@pytest.mark.parametrize("t", [99, 100, 101])
+def test_search_group_rows_near_threshold(ctx, t):
+    # v = 4 puts t = 99..101 tables into 3 groups of 33-34 (the last one
+    # shorter).  Copies of moderate similarity give many pairs just at the
+    # vote threshold, where the owner rule turns on one or two shared tables
+    # of a group, often in its last fields.
+    rows = _near_copies(1500, 3, 4096, 200, 60, 110, 300 + t)
+    st = _compare(ctx, rows, 4096, t, 4, fl.MINMAX, 61 + t, 2, 4, label=f"near-copies-t{t}")
+    assert st.n_out > 500
+    _compare(ctx, rows, 4096, t, 4, fl.MINMAX, 61 + t, 2, 4, distinct=True, label=f"near-copies-t{t}")
+
+
 EDGE = [
     ("n1", lambda: _fixed(1, 4096, 200, 50), 4096, 10, 4, fl.MINMAX, 5, 2),
     ("n2-identical", lambda: np.repeat(_fixed(1, 4096, 200, 51), 2, axis=0), 4096, 10, 4, fl.MINMAX, 1, 10),
