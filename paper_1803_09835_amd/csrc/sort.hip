@@ -16,6 +16,8 @@
 // ballots (no LDS atomics, so the ranking is deterministic and stable), then
 // stages the tile in LDS in digit order so that global writes are runs of
 // consecutive addresses.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace fl {
@@ -396,33 +398,38 @@ __device__ __forceinline__ uint32_t run_end(const uint64_t* sk, uint32_t e, uint
   return f;
 }
 
-// Order [lo, hi) of segment seg (hi - lo <= kBinCap, whole bins) by
-// (key, id) in LDS, write the ids back in that order, and account every
-// bucket.  Elements arrive grouped by bin with ids ascending inside a bin,
-// so a bin holding a single key is already in order; only bins that mix
-// keys are ranked, by counting the (key, position) pairs below each element.
-__device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uint64_t hi, uint64_t* sk,
-                             uint32_t* sv, uint16_t* bs, uint16_t* be, uint16_t* np, uint8_t* mixed, uint32_t* sh,
-                             BucketTotals& tot) {
+// Copy positions [lo, lo + m) of segment seg (m <= kBinCap) into sk / sv,
+// consecutive lanes on consecutive elements.
+__device__ void load_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uint32_t m, uint64_t* sk, uint32_t* sv) {
   const uint64_t* K = a.keys + (uint64_t)seg * a.n;
-  uint32_t* V = a.vals + (uint64_t)seg * a.n;
-  const uint32_t m = (uint32_t)(hi - lo);
-  const uint32_t bsh = a.bin_shift;
-  constexpr uint32_t kPer = kBinCap / kThreads;  // elements per thread, consecutive
-  const uint32_t e0 = threadIdx.x * kPer;
-  // Load with consecutive lanes on consecutive elements; then each thread's
-  // running bin start over its own consecutive elements.
-  uint32_t run = 0;
+  const uint32_t* V = a.vals + (uint64_t)seg * a.n;
 #pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
+  for (uint32_t q = 0; q < kBinCap / kThreads; ++q) {
     const uint32_t e = q * kThreads + threadIdx.x;
     if (e < m) {
       sk[e] = K[lo + e];
       sv[e] = V[lo + e];
-      mixed[e] = 0;
     }
   }
   __syncthreads();
+}
+
+// Order positions [lo, lo + m) of segment seg (whole bins, already in
+// sk / sv) by (key, id) in LDS, write the ids back in that order, and
+// account every bucket.  Elements arrive grouped by bin with ids ascending
+// inside a bin, so a bin holding a single key is already in order; only
+// bins that mix keys are ranked, by counting the (key, position) pairs
+// below each element.
+__device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uint32_t m, uint64_t* sk, uint32_t* sv,
+                             uint16_t* bs, uint16_t* be, uint16_t* np, uint8_t* mixed, uint32_t* sh,
+                             BucketTotals& tot) {
+  uint32_t* V = a.vals + (uint64_t)seg * a.n;
+  const uint32_t bsh = a.bin_shift;
+  constexpr uint32_t kPer = kBinCap / kThreads;  // elements per thread, consecutive
+  const uint32_t e0 = threadIdx.x * kPer;
+  for (uint32_t e = threadIdx.x; e < m; e += kThreads) mixed[e] = 0;  // read only after the barriers below
+  // Each thread's running bin start over its own consecutive elements.
+  uint32_t run = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kPer; ++q) {
     const uint32_t e = e0 + q;
@@ -549,81 +556,124 @@ __device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uin
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kThreads) void k_bucket(BucketArgs a) {
+// Persistent over the chunks of one segment (table): chunk c covers
+// positions [c * chunk, (c + 1) * chunk) and owns the bins that start in it.
+// Its window, one position before the chunk up to kBinCap positions, is
+// staged in LDS in one pass; bin boundaries, the end of its last bin (when
+// inside the window) and the buckets all come from there, while the next
+// chunk's window is already being read into registers.
+__global__ __launch_bounds__(kThreads, 4) void k_bucket(BucketArgs a, uint32_t nchunks) {
   __shared__ uint64_t sk[kBinCap];
   __shared__ uint32_t sv[kBinCap];
   __shared__ uint16_t bs[kBinCap], be[kBinCap], np[kBinCap];
   __shared__ uint8_t mixed[kBinCap];
   __shared__ uint32_t sh[16];
   __shared__ unsigned long long s_hi;
-  __shared__ int s_first, s_last;
+  __shared__ int s_first, s_last, s_end;
+  constexpr uint32_t kPer = kBinCap / kThreads;
   const uint32_t seg = blockIdx.y;
   const uint32_t bsh = a.bin_shift;
   const uint64_t n = a.n;
-  const uint64_t c0 = (uint64_t)blockIdx.x * a.chunk;
-  const uint64_t c1 = c0 + a.chunk < n ? c0 + a.chunk : n;
   const uint64_t* K = a.keys + (uint64_t)seg * n;
-  if (threadIdx.x == 0) {
-    s_first = 0x7FFFFFFF;
-    s_last = -1;
-    s_hi = ~0ull;
-  }
-  __syncthreads();
-  {
-    int first = 0x7FFFFFFF, lastp = -1;
-    for (uint64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
-      if (p == 0 || (K[p] >> bsh) != (K[p - 1] >> bsh)) {
-        first = min(first, (int)(p - c0));
-        lastp = max(lastp, (int)(p - c0));
+  const uint32_t* V = a.vals + (uint64_t)seg * n;
+  uint64_t pk[kPer];
+  uint32_t pv[kPer];
+  auto window = [&](uint32_t c) -> uint64_t { return c ? (uint64_t)c * a.chunk - 1 : 0ull; };
+  auto fetch = [&](uint32_t c) {
+    const uint64_t w0 = window(c);
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      const uint64_t p = w0 + q * kThreads + threadIdx.x;
+      pk[q] = p < n ? K[p] : 0ull;
+      pv[q] = p < n ? V[p] : 0u;
+    }
+  };
+  BucketTotals tot{0ull, 0u, kNoStation, 0u};
+  uint32_t c = blockIdx.x;
+  if (c < nchunks) fetch(c);
+  for (; c < nchunks; c += gridDim.x) {
+    const uint64_t c0 = (uint64_t)c * a.chunk;
+    const uint64_t c1 = c0 + a.chunk < n ? c0 + a.chunk : n;
+    const uint64_t w0 = window(c);
+    const uint32_t wn = (uint32_t)(n - w0 < (uint64_t)kBinCap ? n - w0 : (uint64_t)kBinCap);
+#pragma unroll
+    for (uint32_t q = 0; q < kPer; ++q) {
+      const uint32_t e = q * kThreads + threadIdx.x;
+      if (e < wn) {
+        sk[e] = pk[q];
+        sv[e] = pv[q];
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      first = min(first, __shfl_xor(first, o, 64));
-      lastp = max(lastp, __shfl_xor(lastp, o, 64));
+    if (threadIdx.x == 0) {
+      s_first = 0x7FFFFFFF;
+      s_last = -1;
+      s_end = 0x7FFFFFFF;
     }
-    if ((threadIdx.x & 63) == 0) {
-      if (first != 0x7FFFFFFF) atomicMin(&s_first, first);
-      if (lastp >= 0) atomicMax(&s_last, lastp);
-    }
-  }
-  __syncthreads();
-  if (s_first == 0x7FFFFFFF) return;  // no bin starts in this chunk
-  const uint64_t lo = c0 + (uint64_t)s_first, last = c0 + (uint64_t)s_last;
-  // End of the last bin that starts in this chunk.
-  if (c1 == n) {
-    if (threadIdx.x == 0) s_hi = n;
-  } else {
-    const uint64_t binlast = K[c1 - 1] >> bsh;
-    const uint64_t p = c1 + threadIdx.x;
-    unsigned long long cand = (p < n && (K[p] >> bsh) != binlast) ? (unsigned long long)p : ~0ull;
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long oc = __shfl_xor(cand, o, 64);
-      cand = oc < cand ? oc : cand;
-    }
-    if ((threadIdx.x & 63) == 0 && cand != ~0ull) atomicMin(&s_hi, cand);
     __syncthreads();
-    if (threadIdx.x == 0 && s_hi == ~0ull) {
-      uint64_t L = c1 + blockDim.x < n ? c1 + blockDim.x : n, R = n;  // first p in [L, R) with bin(p) > binlast
+    if (c + gridDim.x < nchunks) fetch(c + gridDim.x);
+    // Bin heads: the first and last inside the chunk, and the first at or
+    // after its end (the end of its last bin), as window offsets.
+    {
+      const uint32_t cb = (uint32_t)(c0 - w0), ce = (uint32_t)(c1 - w0);
+      int first = 0x7FFFFFFF, lastp = -1, endp = 0x7FFFFFFF;
+#pragma unroll
+      for (uint32_t q = 0; q < kPer; ++q) {
+        const uint32_t e = q * kThreads + threadIdx.x;
+        if (e >= cb && e < wn && (w0 + e == 0 || (sk[e] >> bsh) != (sk[e - 1] >> bsh))) {
+          if (e < ce) {
+            first = min(first, (int)e);
+            lastp = max(lastp, (int)e);
+          } else {
+            endp = min(endp, (int)e);
+          }
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        first = min(first, __shfl_xor(first, o, 64));
+        lastp = max(lastp, __shfl_xor(lastp, o, 64));
+        endp = min(endp, __shfl_xor(endp, o, 64));
+      }
+      if ((threadIdx.x & 63) == 0) {
+        if (first != 0x7FFFFFFF) atomicMin(&s_first, first);
+        if (lastp >= 0) atomicMax(&s_last, lastp);
+        if (endp != 0x7FFFFFFF) atomicMin(&s_end, endp);
+      }
+    }
+    __syncthreads();
+    const int first = s_first, lastp = s_last, endp = s_end;
+    __syncthreads();  // the next chunk's thread 0 resets these
+    if (first == 0x7FFFFFFF) continue;  // no bin starts in this chunk
+    const uint64_t lo = w0 + (uint64_t)first;
+    if (endp != 0x7FFFFFFF || w0 + wn == n) {  // the last bin ends inside the window
+      const uint64_t hi = endp != 0x7FFFFFFF ? w0 + (uint64_t)endp : n;
+      process_bins(a, seg, lo, (uint32_t)(hi - lo), sk + first, sv + first, bs, be, np, mixed, sh, tot);
+      continue;
+    }
+    // The last bin runs past the window: the bins before it from LDS, then
+    // its end from HBM, and the bin itself from HBM or the big-bin list.
+    const uint64_t last = w0 + (uint64_t)lastp;
+    if (lastp > first)
+      process_bins(a, seg, lo, (uint32_t)(last - lo), sk + first, sv + first, bs, be, np, mixed, sh, tot);
+    if (threadIdx.x == 0) {
+      const uint64_t binlast = sk[lastp] >> bsh;
+      uint64_t L = w0 + wn, R = n;  // first p in [L, R) with bin(p) > binlast
       while (L < R) {
         const uint64_t M = (L + R) / 2;
         if ((K[M] >> bsh) > binlast) R = M; else L = M + 1;
       }
       s_hi = L;
     }
-  }
-  __syncthreads();
-  const uint64_t hi = s_hi;
-  BucketTotals tot{0ull, 0u, kNoStation, 0u};
-  if (hi - lo <= (uint64_t)kBinCap) {
-    process_bins(a, seg, lo, hi, sk, sv, bs, be, np, mixed, sh, tot);
-  } else {
-    if (last > lo) process_bins(a, seg, lo, last, sk, sv, bs, be, np, mixed, sh, tot);
+    __syncthreads();
+    const uint64_t hi = s_hi;
+    __syncthreads();
     if (hi - last <= (uint64_t)kBinCap) {
-      process_bins(a, seg, last, hi, sk, sv, bs, be, np, mixed, sh, tot);
+      load_bins(a, seg, last, (uint32_t)(hi - last), sk, sv);
+      process_bins(a, seg, last, (uint32_t)(hi - last), sk, sv, bs, be, np, mixed, sh, tot);
     } else if (threadIdx.x == 0) {
       const uint32_t q = atomicAdd(a.bin_count, 1u);
       a.bin_desc[q] = make_uint4((uint32_t)last, (uint32_t)hi, seg, 0);
     }
+    __syncthreads();
   }
   flush_totals(a, tot);
 }
@@ -810,10 +860,26 @@ void radix_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32
   }
 }
 
+// Compute units of the current device (queried once).
+static uint32_t device_cus() {
+  static uint32_t cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cus = (uint32_t)v;
+  }
+  return cus;
+}
+
+// Persistent: one resident round of workgroups (the LDS of four fits a CU)
+// spread over the segments.
 void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s) {
   if (a.n == 0) return;
   const uint32_t nch = (uint32_t)((a.n + a.chunk - 1) / a.chunk);
-  hipLaunchKernelGGL(k_bucket, dim3(nch, S), dim3(kThreads), 0, s, a);
+  const uint32_t per_seg = std::max<uint32_t>(1u, std::min<uint32_t>(nch, 4 * device_cus() / S));
+  hipLaunchKernelGGL(k_bucket, dim3(per_seg, S), dim3(kThreads), 0, s, a, nch);
 }
 
 void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64_t* tk, uint32_t* tv,
