@@ -233,8 +233,9 @@ int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, ui
  * bytes and counters.
  *   radix_tile    elements per workgroup of the grouping passes: 16384,
  *                 8192 or 4096 (0 keeps the current value);
- *   bucket_chunk  sorted positions per workgroup of the bucket kernel:
- *                 256..1536, a multiple of 256 (0 keeps the current value);
+ *   bucket_chunk  sorted positions per wavefront of the bucket kernel (the
+ *                 span it stages in LDS): 256..1536, a multiple of 256
+ *                 (0 keeps the current value);
  *   autotune      1: on the first search of each shape (stations, total n,
  *                 tables, bin bits) time every radix tile and bucket chunk
  *                 on that search's own data, keep the fastest for later
@@ -247,7 +248,7 @@ typedef struct {
   uint32_t reserved;
 } fast_lsh_config;
 
-/* Set the launch shapes of later searches (defaults: 16384, 1536, no
+/* Set the launch shapes of later searches (defaults: 16384, 512, no
  * autotune).  E_INVALID for a value outside the lists above. */
 int fast_lsh_configure(fast_lsh_ctx *ctx, const fast_lsh_config *config);
 

@@ -230,7 +230,7 @@ int fast_lsh_ctx_create(int device, void* hip_stream, uint64_t hbm_budget, fast_
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->budget = hbm_budget;
   c->config.radix_tile = radix_tile_elems(0);
-  c->config.bucket_chunk = 1536;
+  c->config.bucket_chunk = 512;
   c->config.autotune = 0;
   c->config.reserved = 0;
   *out = c;

@@ -201,7 +201,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
       fill_u8(reinterpret_cast<uint8_t*>(j.er), j.spread_bytes, 0, s);
       fill_u32(&j.ctrl->big_count, 2, 0, s);  // big_count, bin_count
     };
-    static const uint32_t chunks[] = {768, 1024, 1280, 1536};
+    static const uint32_t chunks[] = {256, 512, 768, 1024};
     float best = 1e30f;
     uint32_t bestc = j.tc.bucket_chunk;
     for (uint32_t ch : chunks) {
@@ -429,7 +429,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   // Buckets of at most smax members are marked in place and handled by the
   // wave-per-chunk pair kernel; larger ones go to the tiled kernel.
   const uint32_t smax = kSmallBucket;
-  const uint64_t cap_big = tn / (smax + 1) + 1;
+  const uint64_t cap_big = tn / (smax + 1) + 1 + bucket_desc_slack(tn / (smax + 1) + 1, t);
   const uint64_t cap_bin = tn / 129 + t + 1;  // oversized bins and mixed bins above 128 elements
   RC(ws<uint4>(c, "bdesc", cap_big, &j.bdesc));
   RC(ws<uint4>(c, "bins", cap_bin, &j.bins));
@@ -645,7 +645,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   RC(ws<uint32_t>(c, "hist", (uint64_t)256 * nt_max * TGm, &j.hist));
   RC(ws<uint32_t>(c, "sums", scan_sums_elems((uint64_t)256 * nt_max, TGm), &j.sums));
   const uint32_t smax = kSmallBucket;
-  const uint64_t cap_big = gn / (smax + 1) + 1;
+  const uint64_t cap_big = gn / (smax + 1) + 1 + bucket_desc_slack(gn / (smax + 1) + 1, TGm);
   const uint64_t cap_bin = gn / 129 + TGm + 1;
   RC(ws<uint4>(c, "bdesc", cap_big, &j.bdesc));
   RC(ws<uint4>(c, "bins", cap_bin, &j.bins));

@@ -287,16 +287,31 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t len, 
 
 // ---------------------------------------------------------------------------
 // Buckets from the bin-sorted order.
+//
+// One wavefront per span of `chunk` consecutive positions of a table: it owns
+// the bins whose first position lies in the span.  The span (with the
+// position before it and kSpanExt positions after it) is staged in the
+// wave's own LDS slice, and the wave walks it kWin positions at a time from
+// one bin start (kWinQ positions per lane): ballots of bin starts give every
+// complete bin of the window, its size and its first and last member.  A
+// bin holding a single key is one bucket already in id order; a bin that
+// mixes keys is ranked from LDS (each member counts the (key, position)
+// pairs below it).  A bin that does not end inside the window is read from
+// HBM; mixed ones above kRankLong members and all above kLongDefer go to
+// the big-bin list.  No workgroup barriers: the waves are independent.
 // ---------------------------------------------------------------------------
-// Elements one bucket workgroup holds in LDS: 7 per thread, an odd count so
-// that threads walking their own consecutive elements start on different
-// LDS banks.  Chunks are at most 1536 positions, so the bins that start in a
-// chunk (all but its last) always fit.
-constexpr int kBinCap = 1792;
-constexpr uint32_t kRankMax = 128;  // largest mixed bin ranked in LDS
+constexpr uint32_t kWinQ = 1;         // window positions per lane
+constexpr uint32_t kWin = 64 * kWinQ; // positions per window
+constexpr uint32_t kSpanExt = kWin;   // positions staged past a span for its last bins
+constexpr uint32_t kStageB = 5;       // 64-position loads in flight per lane while staging
+constexpr uint32_t kBucketWaves = 4;  // independent wavefronts per workgroup
+constexpr uint32_t kRankLong = 128;   // largest mixed bin ranked by one wave from HBM
+constexpr uint32_t kLongDefer = 2048; // larger bins go to the big-bin kernel
 
-__device__ __forceinline__ bool kv_less(uint64_t ka, uint32_t va, uint64_t kb, uint32_t vb) {
-  return ka < kb || (ka == kb && va < vb);
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // Per-thread bucket counters.  With several stations the station of a
@@ -312,51 +327,6 @@ struct BucketTotals {
   uint32_t station;
   uint32_t ns;  // fingerprints of `station`
 };
-
-// Account one bucket (run of equal keys) of `size` members; ids(q) gives the
-// q-th member (ascending).  Returns the descriptor class: 0 none, 1 small,
-// 2 big.  Buckets that cannot hold a reportable pair get no descriptor: a
-// single member, every member excluded by the occurrence filter (the bucket
-// itself is over the threshold), or an id span below the lag.
-template <typename IdAt>
-__device__ __forceinline__ int bucket_account(const BucketArgs& a, uint64_t size, IdAt ids, uint32_t first_id,
-                                              uint64_t key, BucketTotals& tot) {
-  const uint32_t st = a.nstation > 1 ? (uint32_t)(key >> 60) : 0u;
-  if (st != tot.station) {
-    if (tot.station != kNoStation) {  // counters of another station: add the open totals directly
-      const uint64_t o = (uint64_t)tot.station * kSpread + spread_slot();
-      if (tot.e_raw) atomicAdd(a.e_raw + o, tot.e_raw);
-      if (tot.max_bucket) atomicMax(a.max_bucket + o, tot.max_bucket);
-    }
-    tot.e_raw = 0;
-    tot.max_bucket = 0;
-    tot.station = st;
-    tot.ns = (uint32_t)(a.station_base[st + 1] - a.station_base[st]);
-  }
-  tot.e_raw += (unsigned long long)(size * (size - 1) / 2);
-  if (size > tot.max_bucket) tot.max_bucket = (unsigned int)size;
-  if (a.occ_den) {
-    const uint64_t ns = tot.ns;
-    if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num) {
-      for (uint64_t q = 0; q < size; ++q) a.flags[ids(q)] = 1;
-      return 0;
-    }
-  }
-  if (size < 2 || ids(size - 1) - first_id < a.min_lag) return 0;
-  return size <= a.small_max ? 1 : 2;
-}
-
-// The descriptor class bucket_account returns, without side effects.
-__device__ __forceinline__ int bucket_class(const BucketArgs& a, uint64_t size, uint32_t first_id, uint32_t last_id,
-                                            uint64_t key) {
-  if (a.occ_den) {
-    const uint32_t st = a.nstation > 1 ? (uint32_t)(key >> 60) : 0u;
-    const uint64_t ns = a.station_base[st + 1] - a.station_base[st];
-    if ((unsigned __int128)size * a.occ_den > (unsigned __int128)ns * a.occ_num) return 0;
-  }
-  if (size < 2 || last_id - first_id < a.min_lag) return 0;
-  return size <= a.small_max ? 1 : 2;
-}
 
 // Called by every lane of the wave.  When all lanes that accounted a bucket
 // hold one station the totals are reduced over the wave first; at a station
@@ -386,295 +356,416 @@ __device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
   }
 }
 
-// End of the run of equal keys starting at e inside bin b0: the bin's end
-// for a single-key bin, else a short scan (mixed bins here hold at most
-// kRankMax elements).
-__device__ __forceinline__ uint32_t run_end(const uint64_t* sk, uint32_t e, uint32_t b0, const uint16_t* be,
-                                            const uint8_t* mixed) {
-  const uint32_t b1 = be[b0];
-  if (!mixed[b0]) return b1;
-  uint32_t f = e + 1;
-  while (f < b1 && sk[f] == sk[e]) ++f;
-  return f;
-}
-
-// Copy positions [lo, lo + m) of segment seg (m <= kBinCap) into sk / sv,
-// consecutive lanes on consecutive elements.
-__device__ void load_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uint32_t m, uint64_t* sk, uint32_t* sv) {
-  const uint64_t* K = a.keys + (uint64_t)seg * a.n;
-  const uint32_t* V = a.vals + (uint64_t)seg * a.n;
-#pragma unroll
-  for (uint32_t q = 0; q < kBinCap / kThreads; ++q) {
-    const uint32_t e = q * kThreads + threadIdx.x;
-    if (e < m) {
-      sk[e] = K[lo + e];
-      sv[e] = V[lo + e];
-    }
+// Occurrence filter (section 6.5): a bucket of `size` members is over the
+// threshold of its station (fingerprint count ns) when size / ns > num / den.
+// The station's count is looked up when the station changes (a lane's keys
+// change station only at station boundaries of the sorted order).
+struct OccCache {
+  uint32_t st = kNoStation;
+  uint64_t ns = 0;
+};
+__device__ __forceinline__ bool bucket_over(const BucketArgs& a, uint64_t size, uint64_t key, OccCache& oc) {
+  if (!a.occ_den) return false;
+  const uint32_t st = a.nstation > 1 ? (uint32_t)(key >> 60) : 0u;
+  if (st != oc.st) {
+    oc.st = st;
+    oc.ns = a.station_base[st + 1] - a.station_base[st];
   }
-  __syncthreads();
+  return (unsigned __int128)size * a.occ_den > (unsigned __int128)oc.ns * a.occ_num;
 }
 
-// Order positions [lo, lo + m) of segment seg (whole bins, already in
-// sk / sv) by (key, id) in LDS, write the ids back in that order, and
-// account every bucket.  Elements arrive grouped by bin with ids ascending
-// inside a bin, so a bin holding a single key is already in order; only
-// bins that mix keys are ranked, by counting the (key, position) pairs
-// below each element.
-__device__ void process_bins(const BucketArgs& a, uint32_t seg, uint64_t lo, uint32_t m, uint64_t* sk, uint32_t* sv,
-                             uint16_t* bs, uint16_t* be, uint16_t* np, uint8_t* mixed, uint32_t* sh,
-                             BucketTotals& tot) {
-  uint32_t* V = a.vals + (uint64_t)seg * a.n;
+// Counters of one bucket (this lane heads it) and its descriptor class:
+// 0 none (one member, over the occurrence threshold, or an id span below
+// the lag), 1 small, 2 big.  The members' flags are the caller's.
+__device__ __forceinline__ int head_account(const BucketArgs& a, uint64_t size, uint32_t first_id, uint32_t last_id,
+                                            uint64_t key, BucketTotals& tot) {
+  const uint32_t st = a.nstation > 1 ? (uint32_t)(key >> 60) : 0u;
+  if (st != tot.station) {
+    if (tot.station != kNoStation) {  // counters of another station: add the open totals directly
+      const uint64_t o = (uint64_t)tot.station * kSpread + spread_slot();
+      if (tot.e_raw) atomicAdd(a.e_raw + o, tot.e_raw);
+      if (tot.max_bucket) atomicMax(a.max_bucket + o, tot.max_bucket);
+    }
+    tot.e_raw = 0;
+    tot.max_bucket = 0;
+    tot.station = st;
+    tot.ns = (uint32_t)(a.station_base[st + 1] - a.station_base[st]);
+  }
+  tot.e_raw += (unsigned long long)(size * (size - 1) / 2);
+  if (size > tot.max_bucket) tot.max_bucket = (unsigned int)size;
+  if (a.occ_den && (unsigned __int128)size * a.occ_den > (unsigned __int128)tot.ns * a.occ_num) return 0;
+  if (size < 2 || last_id - first_id < a.min_lag) return 0;
+  return size <= a.small_max ? 1 : 2;
+}
+
+// Account one bucket (run of equal keys) of `size` members; ids(q) gives the
+// q-th member (ascending); flags the members of a bucket over the
+// occurrence threshold.  Returns the descriptor class (head_account).
+template <typename IdAt>
+__device__ __forceinline__ int bucket_account(const BucketArgs& a, uint64_t size, IdAt ids, uint32_t first_id,
+                                              uint64_t key, BucketTotals& tot) {
+  const int cls = head_account(a, size, first_id, ids(size - 1), key, tot);
+  OccCache oc;
+  if (cls == 0 && bucket_over(a, size, key, oc))
+    for (uint64_t q = 0; q < size; ++q) a.flags[ids(q)] = 1;
+  return cls;
+}
+
+// Big-bucket descriptors.  A wave reserves kSlab slots of the list at a time
+// (one atomic per reservation: a counter that every bucket bumped would
+// serialise all waves on one L2 channel) and fills the slots it leaves
+// unused with empty descriptors (size 0), which every reader skips.
+constexpr uint32_t kSlab = 64;
+struct DescSlab {
+  uint32_t pos = 0, end = 0;  // wave-uniform
+};
+
+// Descriptors of the big buckets that lanes with `want` head (called by
+// every lane of the wave), in consecutive slots.
+__device__ __forceinline__ void slab_put(const BucketArgs& a, DescSlab& sl, bool want, uint64_t pos, uint32_t seg,
+                                         uint64_t size) {
+  const uint64_t m = __ballot(want);
+  if (m == 0) return;
+  const uint32_t k = (uint32_t)__popcll(m), lane = threadIdx.x & 63;
+  if (sl.pos + k > sl.end) {
+    for (uint32_t q = sl.pos + lane; q < sl.end; q += 64) a.big_desc[q] = make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t take = k > kSlab ? k : kSlab;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(a.big_count, take);
+    base = __shfl(base, 0, 64);
+    sl.pos = base;
+    sl.end = base + take;
+  }
+  if (want) a.big_desc[sl.pos + __popcll(m & lanemask_lt())] = make_uint4((uint32_t)pos, seg, (uint32_t)size, 0);
+  sl.pos += k;
+}
+
+// The wave's last reservation: its unused slots become empty descriptors.
+__device__ __forceinline__ void slab_close(const BucketArgs& a, const DescSlab& sl) {
+  for (uint32_t q = sl.pos + (threadIdx.x & 63); q < sl.end; q += 64) a.big_desc[q] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// One element of a bucket after ranking: its new position in the bin, the
+// bucket it belongs to (size, first and last id) and whether it heads it;
+// writes its mark and id, flags it if the bucket is over the threshold, and
+// accounts the bucket at its head.  Returns the class at the head, else 0.
+__device__ __forceinline__ int place(const BucketArgs& a, uint8_t* M, uint32_t* V, uint64_t at, uint64_t key,
+                                     uint32_t id, bool head, uint64_t size, uint32_t first_id, uint32_t last_id,
+                                     bool write_id, BucketTotals& tot, OccCache& oc) {
+  if (bucket_over(a, size, key, oc)) a.flags[id] = 1;
+  const int cls = head ? head_account(a, size, first_id, last_id, key, tot) : 0;
+  M[at] = cls == 1 ? (uint8_t)size : (uint8_t)0;
+  if (write_id) V[at] = id;
+  return cls;
+}
+
+// A bin [b, end) that did not end inside the wave's window, from HBM (every
+// lane calls it): its end, whether it mixes keys, and then either one bucket
+// (one key), a ranking of up to kRankLong members, or the big-bin list (bins
+// above kLongDefer members, and mixed ones above kRankLong, go there, to the
+// kernel that spreads a bin over a whole workgroup).  Returns the bin's end.
+__device__ uint64_t long_bin(const BucketArgs& a, uint32_t seg, uint64_t b, const uint64_t* K, uint32_t* V,
+                             uint8_t* M, BucketTotals& tot, OccCache& oc, DescSlab& sl) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t n = a.n;
   const uint32_t bsh = a.bin_shift;
-  constexpr uint32_t kPer = kBinCap / kThreads;  // elements per thread, consecutive
-  const uint32_t e0 = threadIdx.x * kPer;
-  for (uint32_t e = threadIdx.x; e < m; e += kThreads) mixed[e] = 0;  // read only after the barriers below
-  // Each thread's running bin start over its own consecutive elements.
-  uint32_t run = 0;
+  const uint64_t k0 = K[b], bin0 = k0 >> bsh;
+  // The bin's end among the next kScan positions (one round trip of loads),
+  // else by galloping and then bisecting over the ascending bin bits.
+  constexpr uint32_t kScanQ = 4;  // 64-position blocks per round trip
+  uint64_t end = n;
+  bool mixed = false, found = false;
+  for (uint64_t c = b; c < n && !found; c += 64 * kScanQ) {
+    uint64_t kp[kScanQ];
 #pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t e = e0 + q;
-    if (e < m && (e == 0 || (sk[e] >> bsh) != (sk[e - 1] >> bsh))) run = e;
-  }
-  // Exclusive max-scan of the per-thread last head gives the open bin start.
-  uint32_t carry = run;
-  {
-    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t inc = carry;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(inc, o, 64);
-      if (lane >= (uint32_t)o) inc = max(inc, y);
+    for (uint32_t q = 0; q < kScanQ; ++q) {
+      const uint64_t p = c + 64 * q + lane;
+      kp[q] = p < n ? K[p] : k0;
     }
-    if (lane == 63) sh[8 + wave] = inc;
-    __syncthreads();
-    uint32_t before = 0;
-    for (uint32_t w = 0; w < wave; ++w) before = max(before, sh[8 + w]);
-    const uint32_t prev = __shfl_up(inc, 1, 64);
-    carry = max(before, lane ? prev : 0u);
-    __syncthreads();
-  }
-  uint32_t cur = carry;
 #pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t e = e0 + q;
-    if (e < m) {
-      if (e == 0 || (sk[e] >> bsh) != (sk[e - 1] >> bsh)) cur = e;
-      bs[e] = (uint16_t)cur;
-      if (e + 1 == m || (sk[e + 1] >> bsh) != (sk[e] >> bsh)) be[cur] = (uint16_t)(e + 1);
-      if (sk[e] != sk[cur]) mixed[cur] = 1;
-    }
-  }
-  __syncthreads();
-  // Mixed bins above kRankMax elements are left in id order and handed to
-  // the single-workgroup path (k_bigbin): ranking them here costs O(m^2).
-#pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t e = e0 + q;
-    if (e < m && bs[e] == e && mixed[e] && be[e] - e > kRankMax) {
-      mixed[e] = 2;
-      const uint32_t slot = atomicAdd(a.bin_count, 1u);
-      a.bin_desc[slot] = make_uint4((uint32_t)(lo + e), (uint32_t)(lo + be[e]), seg, 0);
-    }
-  }
-  __syncthreads();
-  // Rank inside mixed bins.
-#pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t e = e0 + q;
-    if (e < m) {
-      const uint32_t b0 = bs[e];
-      uint32_t pos = e;
-      if (mixed[b0] == 1) {
-        const uint32_t b1 = be[b0];
-        const uint64_t k = sk[e];
-        pos = b0;
-        for (uint32_t f = b0; f < b1; ++f) {
-          const uint64_t kf = sk[f];
-          pos += (kf < k) || (kf == k && f < e);
-        }
-      }
-      np[e] = (uint16_t)pos;
-    }
-  }
-  __syncthreads();
-  uint64_t rk[kPer];
-  uint32_t rv[kPer];
-#pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t e = e0 + q;
-    rk[q] = e < m ? sk[e] : 0ull;
-    rv[q] = e < m ? sv[e] : 0u;
-  }
-  __syncthreads();
-#pragma unroll
-  for (uint32_t q = 0; q < kPer; ++q) {
-    const uint32_t e = e0 + q;
-    if (e < m) {
-      sk[np[e]] = rk[q];
-      sv[np[e]] = rv[q];
-    }
-  }
-  __syncthreads();
-  // only bins that mixed keys changed order
-  for (uint32_t e = threadIdx.x; e < m; e += blockDim.x)
-    if (mixed[bs[e]] == 1) V[lo + e] = sv[e];
-  // Buckets: every position gets its mark (the size of a small pair-capable
-  // bucket starting there, else 0); large buckets go to a list.
-  uint8_t* marks = a.marks + (uint64_t)seg * a.n + lo;
-  uint32_t nbig = 0;
-  for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
-    const uint32_t b0 = bs[e];
-    if (mixed[b0] == 2) continue;
-    uint8_t mk = 0;
-    if (e == 0 || sk[e] != sk[e - 1]) {
-      const uint32_t f = run_end(sk, e, b0, be, mixed);
-      const int cls = bucket_account(a, f - e, [&](uint64_t q) { return sv[e + q]; }, sv[e], sk[e], tot);
-      if (cls == 1) mk = (uint8_t)(f - e);
-      nbig += cls == 2;
-    }
-    marks[e] = mk;
-  }
-  uint32_t* ws = sh;        // 4 entries
-  uint32_t* base = sh + 4;  // 1 entry
-  uint32_t tbig;
-  const uint32_t xb = block_excl_scan<uint32_t>(nbig, ws, &tbig);
-  if (tbig) {
-    if (threadIdx.x == 0) base[0] = atomicAdd(a.big_count, tbig);
-    __syncthreads();
-    uint32_t pb = base[0] + xb;
-    if (nbig) {
-      for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) {
-        const uint32_t b0 = bs[e];
-        if (mixed[b0] == 2) continue;
-        if (e > 0 && sk[e] == sk[e - 1]) continue;
-        const uint32_t f = run_end(sk, e, b0, be, mixed);
-        if (bucket_class(a, f - e, sv[e], sv[f - 1], sk[e]) == 2)
-          a.big_desc[pb++] = make_uint4((uint32_t)(lo + e), seg, f - e, 0);
+    for (uint32_t q = 0; q < kScanQ; ++q) {
+      if (found) continue;
+      const uint64_t p = c + 64 * q + lane;
+      const bool in = p < n;
+      const uint64_t stop = __ballot(in && (kp[q] >> bsh) != bin0);
+      const uint64_t before = stop ? ((1ull << (__ffsll((long long)stop) - 1)) - 1) : ~0ull;
+      if (__ballot(in && kp[q] != k0) & before) mixed = true;
+      if (stop) {
+        end = c + 64 * q + (uint64_t)__ffsll((long long)stop) - 1;
+        found = true;
+      } else if (!__ballot(in)) {
+        found = true;  // end of the table: end = n
       }
     }
+    if (!found && c + 64 * kScanQ - b >= kLongDefer) break;  // long: bisect below
   }
-  __syncthreads();
+  if (!found) {
+    uint64_t lo = b + 64 * kScanQ, step = 64 * kScanQ;  // bin(lo - 1) == bin0
+    uint64_t hi = n;
+    while (lo < n) {  // gallop: first probe past the bin bounds the search
+      const uint64_t pr = lo + step < n ? lo + step : n - 1;
+      if ((K[pr] >> bsh) != bin0) {
+        hi = pr;
+        break;
+      }
+      lo = pr + 1;
+      step *= 2;
+    }
+    while (lo < hi) {  // first position in [lo, hi) outside the bin
+      const uint64_t mid = (lo + hi) / 2;
+      if ((K[mid] >> bsh) != bin0) hi = mid; else lo = mid + 1;
+    }
+    end = lo;
+  }
+  const uint64_t s = end - b;
+  if (s > kLongDefer || (mixed && s > kRankLong) || (!found && s > 64 * kScanQ)) {
+    if (lane == 0) {
+      const uint32_t q = atomicAdd(a.bin_count, 1u);
+      a.bin_desc[q] = make_uint4((uint32_t)b, (uint32_t)end, seg, 0);
+    }
+    return end;
+  }
+  if (!mixed) {
+    const uint32_t first = V[b], last = V[end - 1];
+    int cls = 0;
+    if (lane == 0) cls = head_account(a, s, first, last, k0, tot);
+    cls = __shfl(cls, 0, 64);
+    const bool over = bucket_over(a, s, k0, oc);
+    for (uint64_t c = b; c < end; c += 64) {
+      const uint64_t p = c + lane;
+      if (p < end) {
+        M[p] = (p == b && cls == 1) ? (uint8_t)s : (uint8_t)0;
+        if (over) a.flags[V[p]] = 1;
+      }
+    }
+    slab_put(a, sl, lane == 0 && cls == 2, b, seg, s);
+    return end;
+  }
+  // Rank: element e = lane + 64 q counts the members below it in (key, position).
+  constexpr int kQ = kRankLong / 64;
+  uint64_t kk[kQ];
+  uint32_t vv[kQ], less[kQ], eqb[kQ], eqc[kQ], lastv[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const uint32_t e = lane + 64u * q;
+    kk[q] = e < s ? K[b + e] : ~0ull;
+    vv[q] = e < s ? V[b + e] : 0u;
+    less[q] = eqb[q] = eqc[q] = 0;
+    lastv[q] = vv[q];
+  }
+  for (uint32_t f = 0; f < (uint32_t)s; ++f) {
+    const uint64_t kf = K[b + f];
+    const uint32_t vf = V[b + f];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const uint32_t e = lane + 64u * q;
+      less[q] += kf < kk[q] ? 1u : 0u;
+      eqb[q] += (kf == kk[q] && f < e) ? 1u : 0u;
+      eqc[q] += kf == kk[q] ? 1u : 0u;
+      lastv[q] = kf == kk[q] ? vf : lastv[q];
+    }
+  }
+  // every read of the bin precedes the writes below
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const uint32_t e = lane + 64u * q;
+    int cls = 0;
+    if (e < s)
+      cls = place(a, M, V, b + less[q] + eqb[q], kk[q], vv[q], eqb[q] == 0, eqc[q], vv[q], lastv[q], true, tot, oc);
+    slab_put(a, sl, cls == 2, b + less[q], seg, eqc[q]);
+  }
+  return end;
 }
 
-// Persistent over the chunks of one segment (table): chunk c covers
-// positions [c * chunk, (c + 1) * chunk) and owns the bins that start in it.
-// Its window, one position before the chunk up to kBinCap positions, is
-// staged in LDS in one pass; bin boundaries, the end of its last bin (when
-// inside the window) and the buckets all come from there, while the next
-// chunk's window is already being read into registers.
-__global__ __launch_bounds__(kThreads, 4) void k_bucket(BucketArgs a, uint32_t nchunks) {
-  __shared__ uint64_t sk[kBinCap];
-  __shared__ uint32_t sv[kBinCap];
-  __shared__ uint16_t bs[kBinCap], be[kBinCap], np[kBinCap];
-  __shared__ uint8_t mixed[kBinCap];
-  __shared__ uint32_t sh[16];
-  __shared__ unsigned long long s_hi;
-  __shared__ int s_first, s_last, s_end;
-  constexpr uint32_t kPer = kBinCap / kThreads;
+// Bit masks over a window of kWin positions, kWinQ words (word w holds
+// positions 64w .. 64w + 63).  Indices into the arrays are compile-time
+// after unrolling, so they stay in registers.
+// Highest set position <= p (position 0 is always set).
+__device__ __forceinline__ uint32_t win_prev(const uint64_t (&H)[kWinQ], uint32_t p) {
+  const uint32_t q = p >> 6, l = p & 63;
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kWinQ; ++w) {
+    uint64_t m = w < q ? H[w] : (w == q ? H[w] & (l == 63 ? ~0ull : ((2ull << l) - 1)) : 0ull);
+    if (m) r = 64 * w + 63 - (uint32_t)__clzll(m);
+  }
+  return r;
+}
+// Lowest set position > p, or kWin.
+__device__ __forceinline__ uint32_t win_next(const uint64_t (&H)[kWinQ], uint32_t p) {
+  const uint32_t q = p >> 6, l = p & 63;
+  uint32_t r = kWin;
+#pragma unroll
+  for (int w = kWinQ - 1; w >= 0; --w) {
+    uint64_t m = (uint32_t)w > q ? H[w] : ((uint32_t)w == q ? H[w] & (l == 63 ? 0ull : ~((2ull << l) - 1)) : 0ull);
+    if (m) r = 64 * (uint32_t)w + (uint32_t)__ffsll((long long)m) - 1;
+  }
+  return r;
+}
+// Some set position in (lo, hi).
+__device__ __forceinline__ bool win_any(const uint64_t (&C)[kWinQ], uint32_t lo, uint32_t hi) {
+  bool any = false;
+#pragma unroll
+  for (uint32_t w = 0; w < kWinQ; ++w) {
+    const uint32_t a = lo + 1 > 64 * w ? lo + 1 : 64 * w, b = hi < 64 * w + 64 ? hi : 64 * w + 64;
+    if (a < b) {
+      const uint64_t m = ((b - 64 * w) == 64 ? ~0ull : ((1ull << (b - 64 * w)) - 1)) & ~((1ull << (a - 64 * w)) - 1);
+      any |= (C[w] & m) != 0;
+    }
+  }
+  return any;
+}
+
+__global__ __launch_bounds__(kBucketWaves * 64, 5) void k_bucket(BucketArgs a, uint32_t nspans) {
+  extern __shared__ uint64_t bucket_lds[];
+  const uint32_t span = a.chunk;
+  const uint32_t cap = span + kSpanExt + 1;  // staged positions per wave
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint64_t* sk = bucket_lds + (size_t)wave * cap;
+  uint32_t* sv = reinterpret_cast<uint32_t*>(bucket_lds + (size_t)kBucketWaves * cap) + (size_t)wave * cap;
   const uint32_t seg = blockIdx.y;
   const uint32_t bsh = a.bin_shift;
   const uint64_t n = a.n;
   const uint64_t* K = a.keys + (uint64_t)seg * n;
-  const uint32_t* V = a.vals + (uint64_t)seg * n;
-  uint64_t pk[kPer];
-  uint32_t pv[kPer];
-  auto window = [&](uint32_t c) -> uint64_t { return c ? (uint64_t)c * a.chunk - 1 : 0ull; };
-  auto fetch = [&](uint32_t c) {
-    const uint64_t w0 = window(c);
-#pragma unroll
-    for (uint32_t q = 0; q < kPer; ++q) {
-      const uint64_t p = w0 + q * kThreads + threadIdx.x;
-      pk[q] = p < n ? K[p] : 0ull;
-      pv[q] = p < n ? V[p] : 0u;
-    }
-  };
+  uint32_t* V = a.vals + (uint64_t)seg * n;
+  uint8_t* M = a.marks + (uint64_t)seg * n;
   BucketTotals tot{0ull, 0u, kNoStation, 0u};
-  uint32_t c = blockIdx.x;
-  if (c < nchunks) fetch(c);
-  for (; c < nchunks; c += gridDim.x) {
-    const uint64_t c0 = (uint64_t)c * a.chunk;
-    const uint64_t c1 = c0 + a.chunk < n ? c0 + a.chunk : n;
-    const uint64_t w0 = window(c);
-    const uint32_t wn = (uint32_t)(n - w0 < (uint64_t)kBinCap ? n - w0 : (uint64_t)kBinCap);
+  OccCache oc;
+  DescSlab sl;
+  // The waves sweep the table together: the spans in flight at any time are
+  // neighbours, so they share pages of the key, id and mark arrays.
+  for (uint32_t sp = blockIdx.x * kBucketWaves + wave; sp < nspans; sp += gridDim.x * kBucketWaves) {
+    const uint64_t s0 = (uint64_t)sp * span;
+    const uint64_t s1 = s0 + span < n ? s0 + span : n;
+    const uint64_t w0 = s0 ? s0 - 1 : 0;  // staged: [w0, w0 + wn)
+    const uint32_t wn = (uint32_t)(n - w0 < (uint64_t)cap ? n - w0 : (uint64_t)cap);
+    const bool tail = w0 + wn == n;       // the staged positions reach the table's end
+    wave_sync();                          // the previous span's reads are done
+    for (uint32_t e0 = 0; e0 < wn; e0 += 64 * kStageB) {  // kStageB loads in flight, then LDS
+      uint64_t kb[kStageB];
+      uint32_t vb[kStageB];
 #pragma unroll
-    for (uint32_t q = 0; q < kPer; ++q) {
-      const uint32_t e = q * kThreads + threadIdx.x;
-      if (e < wn) {
-        sk[e] = pk[q];
-        sv[e] = pv[q];
+      for (uint32_t q = 0; q < kStageB; ++q) {
+        const uint32_t e = e0 + 64 * q + lane;
+        kb[q] = e < wn ? K[w0 + e] : 0ull;
+        vb[q] = e < wn ? V[w0 + e] : 0u;
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < kStageB; ++q) {
+        const uint32_t e = e0 + 64 * q + lane;
+        if (e < wn) {
+          sk[e] = kb[q];
+          sv[e] = vb[q];
+        }
       }
     }
-    if (threadIdx.x == 0) {
-      s_first = 0x7FFFFFFF;
-      s_last = -1;
-      s_end = 0x7FFFFFFF;
+    wave_sync();
+    // The span's first bin start (earlier positions belong to an earlier span's bin).
+    uint64_t b = s1;
+    for (uint64_t c = s0; c < s1; c += 64) {
+      const uint64_t p = c + lane;
+      const uint32_t e = (uint32_t)(p - w0);
+      const bool h = p < s1 && (p == 0 || (sk[e] >> bsh) != (sk[e - 1] >> bsh));
+      const uint64_t hm = __ballot(h);
+      if (hm) {
+        b = c + (uint64_t)__ffsll((long long)hm) - 1;
+        break;
+      }
     }
-    __syncthreads();
-    if (c + gridDim.x < nchunks) fetch(c + gridDim.x);
-    // Bin heads: the first and last inside the chunk, and the first at or
-    // after its end (the end of its last bin), as window offsets.
-    {
-      const uint32_t cb = (uint32_t)(c0 - w0), ce = (uint32_t)(c1 - w0);
-      int first = 0x7FFFFFFF, lastp = -1, endp = 0x7FFFFFFF;
+    while (b < s1) {
+      const uint32_t o = (uint32_t)(b - w0);
+      const uint32_t avail = wn - o;  // staged positions from b, at least 1
+      uint64_t kq[kWinQ], H[kWinQ], C[kWinQ];
+      uint32_t vq[kWinQ];
 #pragma unroll
-      for (uint32_t q = 0; q < kPer; ++q) {
-        const uint32_t e = q * kThreads + threadIdx.x;
-        if (e >= cb && e < wn && (w0 + e == 0 || (sk[e] >> bsh) != (sk[e - 1] >> bsh))) {
-          if (e < ce) {
-            first = min(first, (int)e);
-            lastp = max(lastp, (int)e);
-          } else {
-            endp = min(endp, (int)e);
+      for (uint32_t q = 0; q < kWinQ; ++q) {
+        const uint32_t P = 64 * q + lane;
+        const bool valid = P < avail;
+        kq[q] = valid ? sk[o + P] : 0ull;
+        vq[q] = valid ? sv[o + P] : 0u;
+        const uint64_t kprev = (valid && P > 0) ? sk[o + P - 1] : kq[q];
+        const bool bh = valid && (P == 0 || (kq[q] >> bsh) != (kprev >> bsh));
+        H[q] = __ballot(bh);
+        C[q] = __ballot(valid && !bh && kq[q] != kprev);
+      }
+      if (avail < kWin && tail) {  // the table's end closes the last bin
+#pragma unroll
+        for (uint32_t q = 0; q < kWinQ; ++q)
+          if (avail >> 6 == q) H[q] |= 1ull << (avail & 63);
+      }
+      uint32_t hl = 0;  // last start: its bin may go on
+#pragma unroll
+      for (uint32_t q = 0; q < kWinQ; ++q)
+        if (H[q]) hl = 64 * q + 63 - (uint32_t)__clzll(H[q]);
+      if (hl == 0) {
+        b = long_bin(a, seg, b, K, V, M, tot, oc, sl);
+        continue;
+      }
+      // Complete bins: those starting below hl.
+      uint32_t hd[kWinQ], en[kWinQ], size[kWinQ], first[kWinQ], last[kWinQ], pos[kWinQ];
+      bool act[kWinQ], mixed[kWinQ], head[kWinQ];
+      uint32_t ms = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < kWinQ; ++q) {
+        const uint32_t P = 64 * q + lane;
+        hd[q] = win_prev(H, P);
+        en[q] = win_next(H, hd[q]);
+        act[q] = P < hl && b + hd[q] < s1;
+        mixed[q] = act[q] && win_any(C, hd[q], en[q]);
+        pos[q] = P;
+        size[q] = en[q] - hd[q];
+        head[q] = P == hd[q];
+        first[q] = act[q] ? sv[o + hd[q]] : 0u;
+        last[q] = act[q] ? sv[o + en[q] - 1] : 0u;
+        if (mixed[q]) ms = max(ms, size[q]);
+      }
+      if (__ballot(ms != 0)) {  // rank inside the bins that mix keys, from LDS
+        for (int d = 32; d > 0; d >>= 1) ms = max(ms, (uint32_t)__shfl_xor(ms, d, 64));
+        uint32_t less[kWinQ], eqb[kWinQ], eqc[kWinQ], lastv[kWinQ];
+#pragma unroll
+        for (uint32_t q = 0; q < kWinQ; ++q) {
+          less[q] = eqb[q] = eqc[q] = 0;
+          lastv[q] = vq[q];
+        }
+        for (uint32_t j = 0; j < ms; ++j) {
+#pragma unroll
+          for (uint32_t q = 0; q < kWinQ; ++q) {
+            const uint32_t f = hd[q] + j;
+            if (mixed[q] && f < en[q]) {
+              const uint64_t kf = sk[o + f];
+              const uint32_t vf = sv[o + f];
+              less[q] += kf < kq[q] ? 1u : 0u;
+              eqb[q] += (kf == kq[q] && f < 64 * q + lane) ? 1u : 0u;
+              eqc[q] += kf == kq[q] ? 1u : 0u;
+              lastv[q] = kf == kq[q] ? vf : lastv[q];
+            }
+          }
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kWinQ; ++q) {
+          if (mixed[q]) {
+            pos[q] = hd[q] + less[q] + eqb[q];
+            size[q] = eqc[q];
+            first[q] = vq[q];
+            last[q] = lastv[q];
+            head[q] = eqb[q] == 0;
           }
         }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        first = min(first, __shfl_xor(first, o, 64));
-        lastp = max(lastp, __shfl_xor(lastp, o, 64));
-        endp = min(endp, __shfl_xor(endp, o, 64));
+      // every LDS read of the window precedes these writes to HBM
+      bool big[kWinQ];
+#pragma unroll
+      for (uint32_t q = 0; q < kWinQ; ++q) {
+        int cls = 0;
+        if (act[q]) cls = place(a, M, V, b + pos[q], kq[q], vq[q], head[q], size[q], first[q], last[q], mixed[q], tot, oc);
+        big[q] = cls == 2;
       }
-      if ((threadIdx.x & 63) == 0) {
-        if (first != 0x7FFFFFFF) atomicMin(&s_first, first);
-        if (lastp >= 0) atomicMax(&s_last, lastp);
-        if (endp != 0x7FFFFFFF) atomicMin(&s_end, endp);
-      }
+#pragma unroll
+      for (uint32_t q = 0; q < kWinQ; ++q) slab_put(a, sl, big[q], b + pos[q], seg, size[q]);
+      b += hl;
     }
-    __syncthreads();
-    const int first = s_first, lastp = s_last, endp = s_end;
-    __syncthreads();  // the next chunk's thread 0 resets these
-    if (first == 0x7FFFFFFF) continue;  // no bin starts in this chunk
-    const uint64_t lo = w0 + (uint64_t)first;
-    if (endp != 0x7FFFFFFF || w0 + wn == n) {  // the last bin ends inside the window
-      const uint64_t hi = endp != 0x7FFFFFFF ? w0 + (uint64_t)endp : n;
-      process_bins(a, seg, lo, (uint32_t)(hi - lo), sk + first, sv + first, bs, be, np, mixed, sh, tot);
-      continue;
-    }
-    // The last bin runs past the window: the bins before it from LDS, then
-    // its end from HBM, and the bin itself from HBM or the big-bin list.
-    const uint64_t last = w0 + (uint64_t)lastp;
-    if (lastp > first)
-      process_bins(a, seg, lo, (uint32_t)(last - lo), sk + first, sv + first, bs, be, np, mixed, sh, tot);
-    if (threadIdx.x == 0) {
-      const uint64_t binlast = sk[lastp] >> bsh;
-      uint64_t L = w0 + wn, R = n;  // first p in [L, R) with bin(p) > binlast
-      while (L < R) {
-        const uint64_t M = (L + R) / 2;
-        if ((K[M] >> bsh) > binlast) R = M; else L = M + 1;
-      }
-      s_hi = L;
-    }
-    __syncthreads();
-    const uint64_t hi = s_hi;
-    __syncthreads();
-    if (hi - last <= (uint64_t)kBinCap) {
-      load_bins(a, seg, last, (uint32_t)(hi - last), sk, sv);
-      process_bins(a, seg, last, (uint32_t)(hi - last), sk, sv, bs, be, np, mixed, sh, tot);
-    } else if (threadIdx.x == 0) {
-      const uint32_t q = atomicAdd(a.bin_count, 1u);
-      a.bin_desc[q] = make_uint4((uint32_t)last, (uint32_t)hi, seg, 0);
-    }
-    __syncthreads();
   }
+  slab_close(a, sl);
   flush_totals(a, tot);
 }
 
@@ -873,13 +964,24 @@ static uint32_t device_cus() {
   return cus;
 }
 
-// Persistent: one resident round of workgroups (the LDS of four fits a CU)
-// spread over the segments.
+// Most descriptor slots the bucket kernel reserves beyond the big buckets it
+// finds, for S segments: every wave's last reservation, and at most two
+// slots lost per reservation (a request holds at most three descriptors).
+uint64_t bucket_desc_slack(uint64_t big_max, uint32_t S) {
+  const uint64_t waves = (uint64_t)kBucketWaves * std::max<uint64_t>(S, 8ull * device_cus());
+  return waves * kSlab + 2 * ((big_max + waves * kSlab) / (kSlab - 2) + 1);
+}
+
+// Persistent: one resident round of workgroups (as many as the LDS of the
+// staged spans lets a CU hold, at most 8) spread over the segments.
 void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s) {
   if (a.n == 0) return;
-  const uint32_t nch = (uint32_t)((a.n + a.chunk - 1) / a.chunk);
-  const uint32_t per_seg = std::max<uint32_t>(1u, std::min<uint32_t>(nch, 4 * device_cus() / S));
-  hipLaunchKernelGGL(k_bucket, dim3(per_seg, S), dim3(kThreads), 0, s, a, nch);
+  const uint32_t nspans = (uint32_t)((a.n + a.chunk - 1) / a.chunk);
+  const size_t lds = (size_t)kBucketWaves * (a.chunk + kSpanExt + 1) * 12;
+  const uint32_t per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(8, (160u << 10) / lds));
+  const uint32_t need = (nspans + kBucketWaves - 1) / kBucketWaves;
+  const uint32_t per_seg = std::max<uint32_t>(1u, std::min<uint32_t>(need, per_cu * device_cus() / S));
+  hipLaunchKernelGGL(k_bucket, dim3(per_seg, S), dim3(kBucketWaves * 64), lds, s, a, nspans);
 }
 
 void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64_t* tk, uint32_t* tv,

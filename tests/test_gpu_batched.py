@@ -192,7 +192,7 @@ def test_launch_shapes_identical():
         a, b = fl.make_hash(202, 200)
         dev = [fl.to_device_rows(s) for s in stations]
         ref = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
-        assert c.config_used() == {"radix_tile": 16384, "bucket_chunk": 1536, "autotune": False}
+        assert c.config_used() == {"radix_tile": 16384, "bucket_chunk": 512, "autotune": False}
         for tile in (16384, 8192, 4096):
             for chunk in (256, 768, 1024, 1536):
                 say(f"[shapes] radix_tile={tile} bucket_chunk={chunk}")
@@ -207,7 +207,7 @@ def test_launch_shapes_identical():
             say(f"[shapes] autotune call {k}")
             got = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100, graph=(k == 1))
             used = c.config_used()
-            assert used["radix_tile"] in (16384, 8192, 4096) and used["bucket_chunk"] in (768, 1024, 1280, 1536)
+            assert used["radix_tile"] in (16384, 8192, 4096) and used["bucket_chunk"] in (256, 512, 768, 1024)
             for x, y in zip(ref[:3], got[:3]):
                 assert torch.equal(x, y)
             assert ref[4] == got[4]
