@@ -204,17 +204,15 @@ struct RowReg {
 #pragma unroll
     for (int k = 0; k < kW; ++k) v[k] = src[k];
   }
-  // Some field equal to the other row's (after load_masked): the zero-half
-  // test (x - 0x00010001) & ~x & 0x80008000 on x = a ^ b, non-zero exactly
-  // when a half of x is zero.
+  // Some field equal to the other row's (after load_masked): the unsigned
+  // minimum of the 16-bit halves of a ^ b over the row (packed, two halves
+  // per instruction) is zero exactly when a half is zero.
   __device__ __forceinline__ bool any_equal(const uint32_t* other) const {
-    uint32_t acc = 0;
+    typedef unsigned short half2 __attribute__((ext_vector_type(2)));
+    half2 acc = {0xFFFF, 0xFFFF};
 #pragma unroll
-    for (int k = 0; k < kW; ++k) {
-      const uint32_t x = w[k] ^ other[k];
-      acc |= (x - 0x00010001u) & ~x;
-    }
-    return (acc & 0x80008000u) != 0;
+    for (int k = 0; k < kW; ++k) acc = __builtin_elementwise_min(acc, __builtin_bit_cast(half2, w[k] ^ other[k]));
+    return acc.x == 0 || acc.y == 0;
   }
 };
 
