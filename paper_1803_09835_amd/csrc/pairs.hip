@@ -552,28 +552,46 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
   __syncthreads();
   const uint32_t pad = group_pad(a, u, rsw);
   PairTally tl{0ull, 0ull, 0u, 0u, 0u};
-  const uint32_t P = diag ? na * (na - 1) / 2 : na * nbm;
-  const uint32_t per = (P + kPT - 1) / kPT;
-  uint32_t p = threadIdx.x * per;
-  const uint32_t pend = min(P, p + per);
-  if (p < pend) {
-    uint32_t x, y;
-    if (diag) {
-      tri_decode(na, p, x, y);
-    } else {
-      x = p / nbm;
-      y = p - x * nbm;
+  const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
+  if (!diag && tb_size == kPT / 2 && na > kPT / 4 && nbm >= 16) {
+    // Full tiles off the diagonal: thread t holds left row t mod tb_size in
+    // registers and takes the columns of parity t / tb_size; the lanes of a
+    // wave share every column, so its id and row are one LDS broadcast.
+    const uint32_t x = threadIdx.x % tb_size, y0 = threadIdx.x / tb_size;
+    if (__ballot(x < na)) {
+      const bool live = x < na;
+      const uint32_t xs = live ? x : 0u;
+      RowReg<RSW> rx;
+      if (FAST) rx.load_masked(rowsA + xs * rswl, own, valid); else rx.load(rowsA + xs * rswl, rsw);
+      const uint32_t idx = idsA[xs];
+      for (uint32_t y = y0; y < nbm; y += 2)
+        if (live) visit_pair<RSW, FAST>(a, u, idx, idsB[y], rx, rowsA + xs * rswl, rowsB + y * rswl, rsw, pad, tl);
     }
-    RowReg<RSW> rx;
-    const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
-    if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
-    for (; p < pend; ++p) {
-      visit_pair<RSW, FAST>(a, u, idsA[x], idsB[y], rx, rowsA + x * rswl, rowsB + y * rswl, rsw, pad, tl);
-      if (++y == nbm) {
-        ++x;
-        y = diag ? x + 1 : 0;
-        if (x < na) {
-          if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
+  } else {
+    // Diagonal and partial tiles: every thread walks a contiguous range of
+    // the tile's pairs.
+    const uint32_t P = diag ? na * (na - 1) / 2 : na * nbm;
+    const uint32_t per = (P + kPT - 1) / kPT;
+    uint32_t p = threadIdx.x * per;
+    const uint32_t pend = min(P, p + per);
+    if (p < pend) {
+      uint32_t x, y;
+      if (diag) {
+        tri_decode(na, p, x, y);
+      } else {
+        x = p / nbm;
+        y = p - x * nbm;
+      }
+      RowReg<RSW> rx;
+      if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
+      for (; p < pend; ++p) {
+        visit_pair<RSW, FAST>(a, u, idsA[x], idsB[y], rx, rowsA + x * rswl, rowsB + y * rswl, rsw, pad, tl);
+        if (++y == nbm) {
+          ++x;
+          y = diag ? x + 1 : 0;
+          if (x < na) {
+            if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
+          }
         }
       }
     }
