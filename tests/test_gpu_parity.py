@@ -227,6 +227,23 @@ def test_search_group_rows_near_threshold(ctx, t):
     _compare(ctx, rows, 4096, t, 4, fl.MINMAX, 61 + t, 2, 4, distinct=True, label=f"near-copies-t{t}")
 
 
+@pytest.mark.parametrize("v", [2, 4])
+def test_search_long_and_mixed_bins(ctx, v):
+    # 1,015 rows leave 8 bin bits, so the bins of groups of identical rows
+    # (40-140 copies each) also hold other groups and single rows: bins that
+    # mix keys below 64 members (ranked in the window), between 64 and 128
+    # (ranked from HBM), above 128 (handed to the big-bin kernel), and
+    # one-key bins longer than the 64-position window.
+    sizes = [40, 45, 50, 60, 70, 80, 100, 130, 140]
+    base = _fixed(len(sizes), 4096, 200, 90)
+    rows = np.concatenate([np.repeat(base[g:g + 1], z, axis=0) for g, z in enumerate(sizes)] +
+                          [_fixed(300, 4096, 200, 91)])
+    rows = rows[np.random.default_rng(92).permutation(len(rows))]
+    st = _compare(ctx, rows, 4096, 255, 4, fl.MINMAX, 93, 3, v, label=f"long-mixed-bins-v{v}")
+    assert st.max_bucket >= 140 and st.n_out > 30_000
+    _compare(ctx, rows, 4096, 255, 4, fl.MINMAX, 93, 3, v, distinct=True, label=f"long-mixed-bins-v{v}")
+
+
 EDGE = [
     ("n1", lambda: _fixed(1, 4096, 200, 50), 4096, 10, 4, fl.MINMAX, 5, 2),
     ("n2-identical", lambda: np.repeat(_fixed(1, 4096, 200, 51), 2, axis=0), 4096, 10, 4, fl.MINMAX, 1, 10),
