@@ -34,7 +34,8 @@ void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, cons
                         uint32_t* cnt, hipStream_t s);
 void launch_big_sizes(const uint4* big, uint32_t nbig, uint64_t* sizes, hipStream_t s);
 void launch_tile_counts(const uint32_t* cnt, uint32_t nbig, uint32_t tb, uint64_t* tiles, hipStream_t s);
-void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, uint32_t nbig, uint64_t unit_base, uint32_t nunits,
+void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hipStream_t s);
+void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* owner, uint64_t unit_base, uint32_t nunits,
                        const uint4* big, const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
                        uint32_t tb_size, uint32_t rswl, hipStream_t s);
 void launch_split_out(const uint64_t* key, const uint32_t* val, uint64_t count, uint32_t* oi, uint32_t* oj,

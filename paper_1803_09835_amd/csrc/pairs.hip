@@ -504,26 +504,25 @@ __global__ __launch_bounds__(kPT) void k_tile_counts(const uint32_t* cnt, uint32
   tiles[b] = m < 2 ? 0 : ntl * (ntl + 1) / 2;
 }
 
-// One tile (ta, tb) of the upper triangle of a large bucket's pair matrix;
-// every thread walks a contiguous range of the tile's pairs.  Workgroup
-// unit_base + blockIdx.x takes the bucket whose tile range [toff[b],
-// toff[b+1]) holds it, and within it the tile of that rank.
+// The bucket of every tile unit: owner[q] = b for q in [toff[b], toff[b+1])
+// (one thread per bucket).
+__global__ __launch_bounds__(kPT) void k_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner) {
+  const uint64_t b = (uint64_t)blockIdx.x * kPT + threadIdx.x;
+  if (b >= nbig) return;
+  for (uint64_t q = toff[b], e = toff[b + 1]; q < e; ++q) owner[q] = (uint32_t)b;
+}
+
+// One tile (ta, tb) of the upper triangle of a large bucket's pair matrix.
+// Workgroup unit_base + blockIdx.x takes bucket owner[unit] (whose tile range
+// [toff[b], toff[b+1]) holds the unit) and within it the tile of that rank.
 template <int RSW, bool FAST>
-__global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* toff, uint32_t nbig,
+__global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* toff, const uint32_t* owner,
                                                     uint64_t unit_base, const uint4* big, const uint64_t* cofs,
                                                     const uint32_t* ids, const uint32_t* cnt, uint32_t tb_size,
                                                     uint32_t rswl) {
   extern __shared__ uint32_t smem[];
   const uint64_t unit = unit_base + blockIdx.x;
-  uint32_t bk = 0;
-  {
-    uint32_t lo = 0, hi = nbig;  // last b with toff[b] <= unit
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (toff[mid] <= unit) lo = mid; else hi = mid;
-    }
-    bk = lo;
-  }
+  const uint32_t bk = owner[unit];
   const uint32_t m = cnt[bk];
   const uint32_t ntl = (m + tb_size - 1) / tb_size;
   uint32_t tx, ty;
@@ -750,13 +749,17 @@ void launch_tile_counts(const uint32_t* cnt, uint32_t nbig, uint32_t tb, uint64_
   if (nbig) hipLaunchKernelGGL(k_tile_counts, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, cnt, nbig, tb, tiles);
 }
 
-void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, uint32_t nbig, uint64_t unit_base, uint32_t nunits,
+void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hipStream_t s) {
+  if (nbig) hipLaunchKernelGGL(k_unit_owner, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, toff, nbig, owner);
+}
+
+void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* owner, uint64_t unit_base, uint32_t nunits,
                        const uint4* big, const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
                        uint32_t tb_size, uint32_t rswl, hipStream_t s) {
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
 #define FL_TILE(R, F)                                                                                        \
-  hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, toff, nbig, unit_base, big, cofs, ids, \
+  hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, toff, owner, unit_base, big, cofs, ids, \
                      cnt, tb_size, rswl)
   switch (a.row_dw) {
     case 10: if (fast_test(a)) FL_TILE(10, true); else FL_TILE(10, false); break;

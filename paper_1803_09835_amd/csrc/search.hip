@@ -272,12 +272,16 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   LAUNCHCK();
   uint64_t units = 0;
   RC(d2h(c, &units, toff + big_count));
+  uint32_t* owner;  // bucket of every tile unit
+  RC(ws<uint32_t>(c, "big_owner", units + 1, &owner));
+  launch_unit_owner(toff, big_count, owner, s);
+  LAUNCHCK();
   // at most 2^22 workgroups of 256 threads per launch (work-items per grid
   // dimension stay below 2^32)
   for (uint64_t u0 = 0; u0 < units; u0 += 1u << 22) {
     const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 22, units - u0);
     prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
-    launch_pairs_tile(j.pa, toff, big_count, u0, cnt, j.bdesc, cofs, bids, bcnt, tb, j.rswl, s);
+    launch_pairs_tile(j.pa, toff, owner, u0, cnt, j.bdesc, cofs, bids, bcnt, tb, j.rswl, s);
     prof_end(c);
     LAUNCHCK();
   }
