@@ -704,19 +704,25 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
 
   // Signatures, grouping and buckets of tables [tb, tb + tc); pass 1 also
   // writes rows and high words and accounts the buckets.
+  // Pass 2 rebuilds the group's mixed keys (mix48(key) << 16) from the high
+  // words and sub-key rows pass 1 stored, instead of recomputing signatures.
   auto group = [&](uint32_t tb, uint32_t tc, bool first_pass) -> int {
-    SigArgs sa = fl_sig_args(h, f, j.dhash, &j.ctrl->err);
-    sa.table_begin = tb;
-    sa.table_count = tc;
-    sa.vec_load = j.vec[0];
-    sa.mkeys = j.bk;
-    sa.rows = first_pass ? j.rows : nullptr;
-    sa.hi32 = first_pass ? hi32 : nullptr;
-    sa.mix = kMixSplit;
-    sa.tables_per_group = j.pl.TG;
-    sa.row_dw = j.pl.row_dw;
     prof_begin(c, FAST_LSH_STAGE_SIGNATURES);
-    launch_sig(j.cap[0], j.minmax, sa, s);
+    if (first_pass) {
+      SigArgs sa = fl_sig_args(h, f, j.dhash, &j.ctrl->err);
+      sa.table_begin = tb;
+      sa.table_count = tc;
+      sa.vec_load = j.vec[0];
+      sa.mkeys = j.bk;
+      sa.rows = j.rows;
+      sa.hi32 = hi32;
+      sa.mix = kMixSplit;
+      sa.tables_per_group = j.pl.TG;
+      sa.row_dw = j.pl.row_dw;
+      launch_sig(j.cap[0], j.minmax, sa, s);
+    } else {
+      launch_split_keys(hi32, j.rows, N, tb, tc, j.pl.TG, j.pl.row_dw, j.bk, s);
+    }
     prof_end(c);
     LAUNCHCK();
     uint64_t *gk = j.ak, *gk2 = j.bk;

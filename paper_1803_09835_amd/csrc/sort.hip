@@ -990,4 +990,30 @@ void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64
   hipLaunchKernelGGL(k_bigbin, dim3(grid), dim3(kThreads), 0, s, a, bins, tk, tv);
 }
 
+// Mixed keys of tables [tb, tb + tc) rebuilt from what an earlier signature
+// pass stored, for keys of the form mix48(band key) << 16: the high word
+// (bits 32-63, hi32[u][i]) and the sub-key (bits 16-31, field u mod TG of the
+// row of table u's group).  One thread per fingerprint; its row dwords are
+// read once for all the tables.
+__global__ __launch_bounds__(256) void k_split_keys(const uint32_t* hi32, const uint32_t* rows, uint64_t n,
+                                                    uint32_t tb, uint32_t tc, uint32_t tables_per_group,
+                                                    uint32_t row_dw, uint64_t* mkeys) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    for (uint32_t q = 0; q < tc; ++q) {
+      const uint32_t u = tb + q, g = u / tables_per_group, k = u - g * tables_per_group;
+      const uint32_t w = rows[((uint64_t)g * n + i) * row_dw + (k >> 1)];
+      const uint64_t field = (w >> (16 * (k & 1))) & 0xFFFFu;
+      mkeys[(uint64_t)q * n + i] = ((uint64_t)hi32[(uint64_t)u * n + i] << 32) | (field << 16);
+    }
+  }
+}
+
+void launch_split_keys(const uint32_t* hi32, const uint32_t* rows, uint64_t n, uint32_t tb, uint32_t tc,
+                       uint32_t tables_per_group, uint32_t row_dw, uint64_t* mkeys, hipStream_t s) {
+  if (n == 0 || tc == 0) return;
+  const uint64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_split_keys, dim3((unsigned)(blocks < 65535 ? blocks : 65535)), dim3(256), 0, s, hi32, rows, n,
+                     tb, tc, tables_per_group, row_dw, mkeys);
+}
+
 }  // namespace fl
