@@ -313,34 +313,80 @@ __global__ __launch_bounds__(kQT) void k_query(QueryArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// 4. Merge of two sorted (key, id) runs per table segment: every element
-// finds its place by counting the other run's smaller elements (ids are
-// unique, so no two elements compare equal).
+// 4. Merge of a long sorted (key, id) run A and a short one B per table
+// segment (ids are unique, so no two elements compare equal).  Each element
+// of B finds its rank in A (the elements of A below it) by bisection and goes
+// straight to its place.  The ranks are non-decreasing, so an element of A
+// moves up by the number of ranks at or below its index: a block of A reads
+// the slice of ranks that fall in its range into LDS once.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_merge(const uint64_t* ak, const uint32_t* av, uint64_t as, uint64_t nA,
-                                               const uint64_t* bk, const uint32_t* bv, uint64_t bs, uint64_t nB,
-                                               uint64_t* ok, uint32_t* ov, uint64_t os) {
+constexpr uint32_t kMergeBlock = 2048;  // elements of A per block
+constexpr uint32_t kMergeSlice = 2048;  // ranks a block holds in LDS
+
+__global__ __launch_bounds__(256) void k_merge_rank(const uint64_t* ak, const uint32_t* av, uint64_t as, uint64_t nA,
+                                                    const uint64_t* bk, const uint32_t* bv, uint64_t bs, uint64_t nB,
+                                                    uint64_t* ok, uint32_t* ov, uint64_t os, uint32_t* rk) {
   const uint64_t u = blockIdx.y;
   const uint64_t* A = ak + u * as;
   const uint32_t* AV = av + u * as;
   const uint64_t* B = bk + u * bs;
   const uint32_t* BV = bv + u * bs;
-  uint64_t* O = ok + u * os;
-  uint32_t* OV = ov + u * os;
-  for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < nA + nB; x += (uint64_t)gridDim.x * 256) {
-    const bool fromA = x < nA;
-    const uint64_t self = fromA ? x : x - nA;
-    const uint64_t key = fromA ? A[self] : B[self];
-    const uint32_t id = fromA ? AV[self] : BV[self];
-    const uint64_t* K = fromA ? B : A;
-    const uint32_t* V = fromA ? BV : AV;
-    uint64_t lo = 0, hi = fromA ? nB : nA;  // elements of the other run below (key, id)
+  for (uint64_t d = (uint64_t)blockIdx.x * 256 + threadIdx.x; d < nB; d += (uint64_t)gridDim.x * 256) {
+    const uint64_t key = B[d];
+    const uint32_t id = BV[d];
+    uint64_t lo = 0, hi = nA;
     while (lo < hi) {
       const uint64_t m = (lo + hi) >> 1;
-      if (kv_lt(K[m], V[m], key, id)) lo = m + 1; else hi = m;
+      if (kv_lt(A[m], AV[m], key, id)) lo = m + 1; else hi = m;
     }
-    O[self + lo] = key;
-    OV[self + lo] = id;
+    rk[u * nB + d] = (uint32_t)lo;
+    ok[u * os + lo + d] = key;
+    ov[u * os + lo + d] = id;
+  }
+}
+
+// clo[b] = the first rank index d with rk[d] >= b * kMergeBlock, for blocks
+// b in [0, nblk] (index d covers the blocks between rank d - 1 and rank d).
+__global__ __launch_bounds__(256) void k_merge_blocks(const uint32_t* rk, uint64_t nB, uint32_t nblk,
+                                                      uint32_t* clo) {
+  const uint64_t u = blockIdx.y;
+  const uint32_t* R = rk + u * nB;
+  uint32_t* C = clo + u * (uint64_t)(nblk + 1);
+  for (uint64_t d = (uint64_t)blockIdx.x * 256 + threadIdx.x; d <= nB; d += (uint64_t)gridDim.x * 256) {
+    const uint32_t b0 = d == 0 ? 0u : R[d - 1] / kMergeBlock + 1;
+    const uint32_t b1 = d == nB ? nblk : min(R[d] / kMergeBlock, nblk);
+    for (uint32_t b = b0; b <= b1; ++b) C[b] = (uint32_t)d;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_merge_shift(const uint64_t* ak, const uint32_t* av, uint64_t as, uint64_t nA,
+                                                     uint64_t nB, uint32_t nblk, const uint32_t* rk,
+                                                     const uint32_t* clo, uint64_t* ok, uint32_t* ov, uint64_t os) {
+  __shared__ uint32_t slice[kMergeSlice];
+  const uint64_t u = blockIdx.y;
+  const uint64_t* A = ak + u * as;
+  const uint32_t* AV = av + u * as;
+  const uint32_t* R = rk + u * nB;
+  const uint32_t* C = clo + u * (uint64_t)(nblk + 1);
+  for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const uint32_t lo = C[b], m = C[b + 1] - lo;
+    const bool in_lds = m <= kMergeSlice;
+    __syncthreads();  // the previous block's slice is no longer read
+    if (in_lds)
+      for (uint32_t e = threadIdx.x; e < m; e += 256) slice[e] = R[lo + e];
+    __syncthreads();
+    const uint64_t x0 = (uint64_t)b * kMergeBlock;
+    const uint64_t x1 = x0 + kMergeBlock < nA ? x0 + kMergeBlock : nA;
+    for (uint64_t x = x0 + threadIdx.x; x < x1; x += 256) {
+      uint32_t l = 0, h = m;  // ranks of the slice at or below x
+      while (l < h) {
+        const uint32_t mid = (l + h) >> 1;
+        if ((in_lds ? slice[mid] : R[lo + mid]) <= x) l = mid + 1; else h = mid;
+      }
+      const uint64_t dst = u * os + x + lo + l;
+      ok[dst] = A[x];
+      ov[dst] = AV[x];
+    }
   }
 }
 
@@ -353,14 +399,27 @@ void launch_query(const QueryArgs& a, hipStream_t s) {
   if (a.Qtot) hipLaunchKernelGGL(k_query, dim3(a.Qtot), dim3(kQT), 0, s, a);
 }
 
+// Scratch: rk holds t * nB ranks, clo t * (ceil(nA / kMergeBlock) + 1) block starts.
+uint64_t merge_scratch(uint64_t nA, uint64_t nB, uint32_t t) {
+  return (uint64_t)t * (nB + (nA + kMergeBlock - 1) / kMergeBlock + 1);
+}
+
 void launch_merge(const uint64_t* ak, const uint32_t* av, uint64_t as, uint64_t nA, const uint64_t* bk,
                   const uint32_t* bv, uint64_t bs, uint64_t nB, uint64_t* ok, uint32_t* ov, uint64_t os, uint32_t t,
-                  hipStream_t s) {
-  const uint64_t n = nA + nB;
-  if (n == 0) return;
-  const uint64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_merge, dim3((unsigned)std::min<uint64_t>(blocks, 8192), t), dim3(256), 0, s, ak, av, as, nA,
-                     bk, bv, bs, nB, ok, ov, os);
+                  uint32_t* scratch, hipStream_t s) {
+  if (nA + nB == 0) return;
+  uint32_t* rk = scratch;
+  uint32_t* clo = scratch + (uint64_t)t * nB;
+  const uint32_t nblk = (uint32_t)((nA + kMergeBlock - 1) / kMergeBlock);
+  const uint64_t gb = (nB + 256) / 256;
+  if (nB)
+    hipLaunchKernelGGL(k_merge_rank, dim3((unsigned)std::min<uint64_t>(gb, 4096), t), dim3(256), 0, s, ak, av, as, nA,
+                       bk, bv, bs, nB, ok, ov, os, rk);
+  hipLaunchKernelGGL(k_merge_blocks, dim3((unsigned)std::min<uint64_t>(gb, 4096), t), dim3(256), 0, s, rk, nB, nblk,
+                     clo);
+  if (nblk)
+    hipLaunchKernelGGL(k_merge_shift, dim3(std::min<uint32_t>(nblk, 8192u), t), dim3(256), 0, s, ak, av, as, nA, nB,
+                       nblk, rk, clo, ok, ov, os);
 }
 
 }  // namespace fl
@@ -471,8 +530,10 @@ static int merge_history(fast_lsh_server* sv, Station& S) {
     return fl_fail(FAST_LSH_E_NOMEM, "station history is full (%llu rows of %llu)",
                    (unsigned long long)(S.nh + S.nd), (unsigned long long)S.hcap);
   if (sv->mphys < S.hcap) return fl_fail(FAST_LSH_E_DEVICE, "history merge buffer smaller than the station");
+  uint32_t* scr;
+  RC(ws<uint32_t>(sv->ctx, "sv_merge", merge_scratch(S.nh, S.nd, t), &scr));
   launch_merge(S.hkey, S.hid, S.hcap, S.nh, S.dkey[S.dcur], S.did[S.dcur], S.dcap, S.nd, sv->mkey, sv->mid, S.hcap,
-               t, sv->stream);
+               t, scr, sv->stream);
   LAUNCHCK();
   std::swap(S.hkey, sv->mkey);
   std::swap(S.hid, sv->mid);
@@ -636,8 +697,10 @@ static int run_batch(fast_lsh_server* sv, std::vector<std::pair<uint64_t, Ticket
     if (S.nd + nq > S.dcap) RC(merge_history(sv, S));
     const int nx = 1 - S.dcur;
     prof_begin(c, FAST_LSH_STAGE_OUTPUT);
+    uint32_t* scr;
+    RC(ws<uint32_t>(c, "sv_merge", merge_scratch(S.nd, nq, t), &scr));
     launch_merge(S.dkey[S.dcur], S.did[S.dcur], S.dcap, S.nd, csk + ent[e].cbase, csid + ent[e].cbase, Qtot, nq,
-                 S.dkey[nx], S.did[nx], S.dcap, t, s);
+                 S.dkey[nx], S.did[nx], S.dcap, t, scr, s);
     prof_end(c);
     LAUNCHCK();
     S.dcur = nx;
