@@ -274,6 +274,11 @@ int fast_lsh_config_used(fast_lsh_ctx *ctx, fast_lsh_config *out);
  * Continuous batching: while a batch runs, arriving chunks wait; the next
  * batch takes the oldest waiting chunks, at most one per station (a
  * station's chunk waits for the one before it) and at most max_batch.
+ * A chunk's ticket is done as soon as its result is on the host; the batch's
+ * chunks are then inserted into their stations (merging a full delta into
+ * the history) before the next batch runs.  If an insertion fails (the
+ * station's history is full), that chunk's result stands and every later
+ * chunk of the station fails with the insertion's error.
  * HBM admission: a station is admitted only if its tables, its share of the
  * shared history-merge buffer and its build buffers fit the budget.
  * Chunk rows are DEVICE memory that must stay valid until the chunk's ticket

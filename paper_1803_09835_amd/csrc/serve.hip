@@ -441,6 +441,19 @@ struct Station {
   uint64_t* dkey[2] = {nullptr, nullptr};
   uint32_t* did[2] = {nullptr, nullptr};
   int dcur = 0;
+  int err = 0;       // an insertion failed: later chunks of the station fail with it
+  std::string msg;
+};
+
+// What the insertion step after a batch needs: each chunk's station, rows
+// and place among the batch's sorted rows (per table: [t][Qtot]).
+struct Insertion {
+  std::vector<uint32_t> station;
+  std::vector<uint32_t> cbase, nq;
+  std::vector<bool> valid;
+  const uint64_t* csk = nullptr;
+  const uint32_t* csid = nullptr;
+  uint32_t Qtot = 0;
 };
 
 enum { kPending = 0, kRunning = 1, kDone = 2, kFailed = 3 };
@@ -484,6 +497,9 @@ struct fast_lsh_server {
   bool started = false, stop = false;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   uint64_t batches = 0, chunks = 0, max_seen = 0;
+  // sizes as of the worker's last step (the worker changes the buffers
+  // without the lock; fast_lsh_server_info reads these under it)
+  uint64_t snap_resident = 0, snap_workspace = 0;
 };
 
 // Pick the chunks of the next batch from the waiting ones, oldest first, at
@@ -543,8 +559,10 @@ static int merge_history(fast_lsh_server* sv, Station& S) {
   return FAST_LSH_OK;
 }
 
-// Run one batch (worker thread; the server lock is not held).
-static int run_batch(fast_lsh_server* sv, std::vector<std::pair<uint64_t, Ticket*>>& batch) {
+// Search one batch (worker thread; the server lock is not held): every
+// ticket's result is on the host when this returns; `ins` receives what the
+// insertion step needs.
+static int run_batch(fast_lsh_server* sv, std::vector<std::pair<uint64_t, Ticket*>>& batch, Insertion& ins) {
   fast_lsh_ctx* c = sv->ctx;
   hipStream_t s = sv->stream;
   const uint32_t t = sv->h.num_tables;
@@ -688,28 +706,66 @@ static int run_batch(fast_lsh_server* sv, std::vector<std::pair<uint64_t, Ticket
     }
     o.n_out = v.size();
   }
-  // 4. insert every valid chunk into its station's delta (a rejected chunk
-  // leaves its station unchanged)
+  ins.station.resize(nent);
+  ins.cbase.resize(nent);
+  ins.nq.resize(nent);
+  ins.valid.resize(nent);
   for (uint32_t e = 0; e < nent; ++e) {
-    if (batch[e].second->err != FAST_LSH_OK) continue;
-    Station& S = sv->st[batch[e].second->station];
-    const uint64_t nq = ent[e].nq;
-    if (S.nd + nq > S.dcap) RC(merge_history(sv, S));
-    const int nx = 1 - S.dcur;
-    prof_begin(c, FAST_LSH_STAGE_OUTPUT);
-    uint32_t* scr;
-    RC(ws<uint32_t>(c, "sv_merge", merge_scratch(S.nd, nq, t), &scr));
-    launch_merge(S.dkey[S.dcur], S.did[S.dcur], S.dcap, S.nd, csk + ent[e].cbase, csid + ent[e].cbase, Qtot, nq,
-                 S.dkey[nx], S.did[nx], S.dcap, t, scr, s);
-    prof_end(c);
-    LAUNCHCK();
-    S.dcur = nx;
-    S.nd += nq;
-    S.n += nq;
+    ins.station[e] = batch[e].second->station;
+    ins.cbase[e] = ent[e].cbase;
+    ins.nq[e] = ent[e].nq;
+    ins.valid[e] = batch[e].second->err == FAST_LSH_OK;
   }
-  HIPCK(hipStreamSynchronize(s));
-  prof_collect(c);
+  ins.csk = csk;
+  ins.csid = csid;
+  ins.Qtot = Qtot;
   return FAST_LSH_OK;
+}
+
+// Insert every valid chunk of the last batch into its station's delta (a
+// rejected chunk leaves its station unchanged), merging a full delta into
+// the history first.  Runs after the batch's tickets are done, so a history
+// merge delays only later batches.  A failed insertion marks its station.
+static void insert_batch(fast_lsh_server* sv, const Insertion& ins) {
+  fast_lsh_ctx* c = sv->ctx;
+  hipStream_t s = sv->stream;
+  const uint32_t t = sv->h.num_tables;
+  for (size_t e = 0; e < ins.station.size(); ++e) {
+    Station& S = sv->st[ins.station[e]];
+    if (!ins.valid[e] || S.err) continue;
+    const uint64_t nq = ins.nq[e];
+    int rc = FAST_LSH_OK;
+    if (S.nd + nq > S.dcap) rc = merge_history(sv, S);
+    uint32_t* scr = nullptr;
+    if (rc == FAST_LSH_OK) rc = ws<uint32_t>(c, "sv_merge", merge_scratch(S.nd, nq, t), &scr);
+    if (rc == FAST_LSH_OK) {
+      const int nx = 1 - S.dcur;
+      prof_begin(c, FAST_LSH_STAGE_OUTPUT);
+      launch_merge(S.dkey[S.dcur], S.did[S.dcur], S.dcap, S.nd, ins.csk + ins.cbase[e], ins.csid + ins.cbase[e],
+                   ins.Qtot, nq, S.dkey[nx], S.did[nx], S.dcap, t, scr, s);
+      prof_end(c);
+      if (hipGetLastError() != hipSuccess) {
+        rc = fl_fail(FAST_LSH_E_DEVICE, "chunk insertion launch failed");
+      } else {
+        S.dcur = nx;
+        S.nd += nq;
+        S.n += nq;
+      }
+    }
+    if (rc != FAST_LSH_OK) {
+      S.err = rc;
+      S.msg = fast_lsh_last_error();
+    }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess)
+    for (size_t e = 0; e < ins.station.size(); ++e) {
+      Station& S = sv->st[ins.station[e]];
+      if (!S.err) {
+        S.err = FAST_LSH_E_DEVICE;
+        S.msg = "chunk insertion failed on the device";
+      }
+    }
+  prof_collect(c);
 }
 
 static void worker_main(fast_lsh_server* sv) {
@@ -733,23 +789,40 @@ static void worker_main(fast_lsh_server* sv) {
     }
     for (uint64_t id : ids) sv->pending.erase(std::find(sv->pending.begin(), sv->pending.end(), id));
     lk.unlock();
-    for (auto& b : batch) b.second->err = FAST_LSH_OK;
-    const int rc = run_batch(sv, batch);
+    // chunks of a station whose insertion failed earlier fail with that error
+    std::vector<std::pair<uint64_t, Ticket*>> run;
+    for (auto& b : batch) {
+      const Station& S = sv->st[b.second->station];
+      b.second->err = S.err;
+      if (S.err) b.second->msg = S.msg; else run.push_back(b);
+    }
+    Insertion ins;
+    const int rc = run.empty() ? FAST_LSH_OK : run_batch(sv, run, ins);
     const std::string msg = rc == FAST_LSH_OK ? std::string() : std::string(fast_lsh_last_error());
     lk.lock();
     const uint64_t done = now_ns(sv->t0);
-    for (auto& b : batch) {
+    for (auto& b : run) {
       if (rc != FAST_LSH_OK) {  // the batch as a whole failed
         b.second->err = rc;
         b.second->msg = msg;
       }
+    }
+    for (auto& b : batch) {
       b.second->state = b.second->err == FAST_LSH_OK ? kDone : kFailed;
       b.second->done_ns = done;
     }
     ++sv->batches;
     sv->chunks += batch.size();
     sv->max_seen = std::max<uint64_t>(sv->max_seen, batch.size());
+    sv->snap_workspace = sv->ctx->ws_total;
     sv->cv_done.notify_all();
+    if (rc == FAST_LSH_OK && !run.empty()) {  // tickets are done; now the insertion
+      lk.unlock();
+      insert_batch(sv, ins);
+      lk.lock();
+      sv->snap_resident = resident_bytes(sv);
+      sv->snap_workspace = sv->ctx->ws_total;
+    }
   }
 }
 
@@ -979,6 +1052,8 @@ int fast_lsh_server_submit(fast_lsh_server* sv, uint32_t station, const fast_lsh
   T.arrival_ns = arrival_ns;
   sv->pending.push_back(id);
   if (!sv->started) {
+    sv->snap_resident = resident_bytes(sv);
+    sv->snap_workspace = sv->ctx->ws_total;
     sv->started = true;
     sv->worker = std::thread(worker_main, sv);
   }
@@ -1036,8 +1111,8 @@ int fast_lsh_server_info(fast_lsh_server* sv, fast_lsh_server_state* out) {
   std::lock_guard<std::mutex> lk(sv->mu);
   out->stations = (uint32_t)sv->st.size();
   out->waiting = (uint32_t)sv->pending.size();
-  out->resident_bytes = resident_bytes(sv);
-  out->workspace_bytes = sv->ctx->ws_total;
+  out->resident_bytes = sv->started ? sv->snap_resident : resident_bytes(sv);
+  out->workspace_bytes = sv->started ? sv->snap_workspace : sv->ctx->ws_total;
   out->batches = sv->batches;
   out->chunks = sv->chunks;
   out->largest_batch = sv->max_seen;

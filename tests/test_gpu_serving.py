@@ -212,3 +212,35 @@ def test_serving_admission_and_arguments():
     with pytest.raises(fl.FastLshError):
         sv.submit(st + 1, fl.to_device_rows(_fixed(10, 4096, 200, 4)))
     sv.close()
+
+
+def test_serving_full_history_fails_later_chunks():
+    # history 6,000 rows with room for 4,000 more, delta 4,000, chunks of
+    # 2,000: the second history merge (before chunk 5's insertion) would
+    # exceed the room, so chunk 5 keeps its result and chunk 6 fails.
+    sizes = [2000] * 6
+    n_hist = 6000
+    rows = synth.generate(synth.station(n=n_hist + sum(sizes), seed=210))
+    hist, chunks = rows[:n_hist], _chunks(rows, n_hist, sizes)
+    a, b = fl.make_hash(211, 200)
+    sv = fl.Server(4096, 100, 4, fl.MINMAX, a, b, 5, 4, max_chunk=2000, delta_rows=4000, slack_rows=4000)
+    st = sv.add_station(fl.to_device_rows(hist))
+    dev = [fl.to_device_rows(x) for x in chunks]
+    got = []
+    for c in range(5):
+        tk = sv.submit(st, dev[c])
+        got.append(sv.take(tk))
+    t6 = sv.submit(st, dev[5])
+    with pytest.raises(fl.FastLshError) as e:
+        sv.poll(t6, wait=True)
+    assert e.value.code == 2
+    sv.close()
+    # chunks 1-5 are exact: the oracle's pairs of the first 16,000 rows whose
+    # later member is in a chunk
+    ei, ej, ev, _ = _expected(rows[:n_hist + 10_000], n_hist, 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
+    gi = np.concatenate([g[0] for g in got])
+    gj = np.concatenate([g[1] for g in got])
+    gv = np.concatenate([g[2] for g in got])
+    o = np.lexsort((gj, gi))
+    say(f"[serve] full history: {len(gi)} pairs (oracle {len(ei)})")
+    assert np.array_equal(gi[o], ei) and np.array_equal(gj[o], ej) and np.array_equal(gv[o], ev)
