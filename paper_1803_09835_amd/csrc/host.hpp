@@ -32,14 +32,10 @@ void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64
                    hipStream_t s);
 // pairs.hip
 void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, hipStream_t s);
-void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, const uint64_t* cofs, uint32_t* ids,
-                        uint32_t* cnt, hipStream_t s);
-void launch_big_sizes(const uint4* big, uint32_t nbig, uint64_t* sizes, hipStream_t s);
-void launch_tile_counts(const uint32_t* cnt, uint32_t nbig, uint32_t tb, uint64_t* tiles, hipStream_t s);
+void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, hipStream_t s);
 void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hipStream_t s);
 void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* owner, uint64_t unit_base, uint32_t nunits,
-                       const uint4* big, const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
-                       uint32_t tb_size, uint32_t rswl, hipStream_t s);
+                       const uint4* big, uint32_t tb_size, uint32_t rswl, hipStream_t s);
 void launch_split_out(const uint64_t* key, const uint32_t* val, uint64_t count, uint32_t* oi, uint32_t* oj,
                       uint8_t* ov, const uint64_t* base, uint32_t nb, hipStream_t s);
 void launch_station_offsets(const uint64_t* key, uint64_t count, const uint64_t* base, uint32_t nb,

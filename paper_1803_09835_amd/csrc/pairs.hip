@@ -456,51 +456,13 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
   flush_tally(a, tl);
 }
 
-// Unflagged members of each large bucket, compacted in order.
-// (a bounded grid walks the buckets: their number can exceed what one
-// workgroup per bucket could launch)
-__global__ __launch_bounds__(kPT) void k_compact_big(PairArgs a, const uint4* big, uint32_t nbig,
-                                                     const uint64_t* cofs, uint32_t* ids, uint32_t* cnt) {
-  __shared__ uint32_t ws[8];
-  __shared__ uint32_t s_carry;
-  for (uint32_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-    const uint4 d = big[b];
-    const uint32_t* ord = a.order + (uint64_t)d.y * a.n + d.x;
-    uint32_t* out = ids + cofs[b];
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (uint32_t c = 0; c < d.z; c += kPT) {
-      const uint32_t q = c + threadIdx.x;
-      const uint32_t id = q < d.z ? ord[q] : 0u;
-      const uint32_t keep = (q < d.z && a.flags[id] == 0) ? 1u : 0u;
-      uint32_t tot;
-      const uint32_t x = block_scan_excl<uint32_t>(keep, ws, &tot);
-      const uint32_t carry = s_carry;
-      if (keep) out[carry + x] = id;
-      __syncthreads();
-      if (threadIdx.x == 0) s_carry = carry + tot;
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) cnt[b] = s_carry;
-    __syncthreads();
-  }
-}
-
-// One tile (ta, tb) of the upper triangle of a large bucket's pair matrix;
-// every thread walks a contiguous range of the tile's pairs.
-// Sizes of the large buckets (their member offsets are the scan of these).
-__global__ __launch_bounds__(kPT) void k_big_sizes(const uint4* big, uint32_t nbig, uint64_t* sizes) {
-  const uint64_t b = (uint64_t)blockIdx.x * kPT + threadIdx.x;
-  if (b < nbig) sizes[b] = big[b].z;
-}
-
 // Tiles of each large bucket: the upper triangle, diagonal included, of its
-// ceil(cnt / tb) x ceil(cnt / tb) grid of tb x tb tiles.
-__global__ __launch_bounds__(kPT) void k_tile_counts(const uint32_t* cnt, uint32_t nbig, uint32_t tb,
-                                                     uint64_t* tiles) {
+// ceil(m / tb) x ceil(m / tb) grid of tb x tb tiles (m members; an empty
+// descriptor has none).
+__global__ __launch_bounds__(kPT) void k_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles) {
   const uint64_t b = (uint64_t)blockIdx.x * kPT + threadIdx.x;
   if (b >= nbig) return;
-  const uint64_t m = cnt[b], ntl = (m + tb - 1) / tb;
+  const uint64_t m = big[b].z, ntl = (m + tb - 1) / tb;
   tiles[b] = m < 2 ? 0 : ntl * (ntl + 1) / 2;
 }
 
@@ -517,20 +479,20 @@ __global__ __launch_bounds__(kPT) void k_unit_owner(const uint64_t* toff, uint32
 // [toff[b], toff[b+1]) holds the unit) and within it the tile of that rank.
 template <int RSW, bool FAST>
 __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* toff, const uint32_t* owner,
-                                                    uint64_t unit_base, const uint4* big, const uint64_t* cofs,
-                                                    const uint32_t* ids, const uint32_t* cnt, uint32_t tb_size,
+                                                    uint64_t unit_base, const uint4* big, uint32_t tb_size,
                                                     uint32_t rswl) {
   extern __shared__ uint32_t smem[];
   const uint64_t unit = unit_base + blockIdx.x;
   const uint32_t bk = owner[unit];
-  const uint32_t m = cnt[bk];
+  const uint4 d = big[bk];  // {position, segment, members}
+  const uint32_t m = d.z;
   const uint32_t ntl = (m + tb_size - 1) / tb_size;
   uint32_t tx, ty;
   tri_decode(ntl + 1, (uint32_t)(unit - toff[bk]), tx, ty);  // pairs x < y of ntl + 1 items: tile (x, y - 1)
   const uint32_t ta = tx, tbi = ty - 1;
   const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
-  const uint32_t u = big[bk].y + a.table_offset;  // table of the bucket
-  const uint32_t* bid = ids + cofs[bk];
+  const uint32_t u = d.y + a.table_offset;  // table of the bucket
+  const uint32_t* bid = a.order + (uint64_t)d.y * a.n + d.x;  // members, ids ascending
   const uint32_t a0 = ta * tb_size, b0 = tbi * tb_size;
   const uint32_t na = min(tb_size, m - a0);
   const bool diag = ta == tbi;
@@ -545,9 +507,19 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
   if (!diag)
     for (uint32_t q = threadIdx.x; q < nbm; q += kPT) idsB[q] = bid[b0 + q];
   __syncthreads();
-  for (uint32_t q = threadIdx.x; q < na; q += kPT) stage_row<RSW>(R + (uint64_t)idsA[q] * rsw, rowsA + q * rswl, rsw);
+  // members excluded by the occurrence filter stay in place, marked dead
+  const bool use_flags = *a.n_flagged != 0;
+  for (uint32_t q = threadIdx.x; q < na; q += kPT) {
+    const uint32_t id = idsA[q];
+    stage_row<RSW>(R + (uint64_t)id * rsw, rowsA + q * rswl, rsw);
+    if (use_flags && a.flags[id]) idsA[q] = kDead;
+  }
   if (!diag)
-    for (uint32_t q = threadIdx.x; q < nbm; q += kPT) stage_row<RSW>(R + (uint64_t)idsB[q] * rsw, rowsB + q * rswl, rsw);
+    for (uint32_t q = threadIdx.x; q < nbm; q += kPT) {
+      const uint32_t id = idsB[q];
+      stage_row<RSW>(R + (uint64_t)id * rsw, rowsB + q * rswl, rsw);
+      if (use_flags && a.flags[id]) idsB[q] = kDead;
+    }
   __syncthreads();
   const uint32_t pad = group_pad(a, u, rsw);
   PairTally tl{0ull, 0ull, 0u, 0u, 0u};
@@ -734,19 +706,8 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
   }
 }
 
-void launch_compact_big(const PairArgs& a, const uint4* big, uint32_t nbig, const uint64_t* cofs, uint32_t* ids,
-                        uint32_t* cnt, hipStream_t s) {
-  if (nbig == 0) return;
-  hipLaunchKernelGGL(k_compact_big, dim3(nbig < 65536u ? nbig : 65536u), dim3(kPT), 0, s, a, big, nbig, cofs, ids,
-                     cnt);
-}
-
-void launch_big_sizes(const uint4* big, uint32_t nbig, uint64_t* sizes, hipStream_t s) {
-  if (nbig) hipLaunchKernelGGL(k_big_sizes, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, big, nbig, sizes);
-}
-
-void launch_tile_counts(const uint32_t* cnt, uint32_t nbig, uint32_t tb, uint64_t* tiles, hipStream_t s) {
-  if (nbig) hipLaunchKernelGGL(k_tile_counts, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, cnt, nbig, tb, tiles);
+void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, hipStream_t s) {
+  if (nbig) hipLaunchKernelGGL(k_tile_counts, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, big, nbig, tb, tiles);
 }
 
 void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hipStream_t s) {
@@ -754,13 +715,12 @@ void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hip
 }
 
 void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* owner, uint64_t unit_base, uint32_t nunits,
-                       const uint4* big, const uint64_t* cofs, const uint32_t* ids, const uint32_t* cnt,
-                       uint32_t tb_size, uint32_t rswl, hipStream_t s) {
+                       const uint4* big, uint32_t tb_size, uint32_t rswl, hipStream_t s) {
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
 #define FL_TILE(R, F)                                                                                        \
-  hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, toff, owner, unit_base, big, cofs, ids, \
-                     cnt, tb_size, rswl)
+  hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, toff, owner, unit_base, big, tb_size, \
+                     rswl)
   switch (a.row_dw) {
     case 10: if (fast_test(a)) FL_TILE(10, true); else FL_TILE(10, false); break;
     case 17: if (fast_test(a)) FL_TILE(17, true); else FL_TILE(17, false); break;

@@ -241,33 +241,23 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
   return FAST_LSH_OK;
 }
 
-// Pairs of the large buckets (tiled kernel).  Member offsets, compaction
-// (excluded members dropped) and tile counts are computed on the device; the
-// host reads back two totals (members, tiles) to size the ids and the grid.
+// Pairs of the large buckets (tiled kernel).  Tile counts and their offsets
+// are computed on the device (members are read in place from the sorted
+// order, excluded ones marked dead); the host reads back the tile total to
+// size the grid.
 int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   if (big_count == 0) return FAST_LSH_OK;
   hipStream_t s = c->stream;
-  uint64_t *cofs, *toff, *sums;
-  uint32_t *bids, *bcnt;
-  RC(ws<uint64_t>(c, "big_cofs", big_count + 1, &cofs));
+  uint64_t *toff, *sums;
   RC(ws<uint64_t>(c, "big_toff", big_count + 1, &toff));
   RC(ws<uint64_t>(c, "big_sums", scan_sums_elems(big_count, 1), &sums));
-  RC(ws<uint32_t>(c, "big_cnt", big_count, &bcnt));
-  launch_big_sizes(j.bdesc, big_count, cofs, s);
-  scan_u64(cofs, big_count, 1, sums, cofs + big_count, s);
-  LAUNCHCK();
-  uint64_t members = 0;
-  RC(d2h(c, &members, cofs + big_count));
-  RC(ws<uint32_t>(c, "big_ids", members + 1, &bids));
-  launch_compact_big(j.pa, j.bdesc, big_count, cofs, bids, bcnt, s);
-  LAUNCHCK();
   // tile edge: 128 (two tiles of rows and ids in about 18 KB of LDS, so that
   // eight workgroups share a CU and hide the row reads), smaller when rows are
   // long enough that two tiles would exceed 64 KB
   const uint32_t fit = 65536 / (8 * j.rswl + 8);
   uint32_t tb = 128;
   while (tb > 16 && tb > fit) tb >>= 1;
-  launch_tile_counts(bcnt, big_count, tb, toff, s);
+  launch_tile_counts(j.bdesc, big_count, tb, toff, s);
   scan_u64(toff, big_count, 1, sums, toff + big_count, s);
   LAUNCHCK();
   uint64_t units = 0;
@@ -281,7 +271,7 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   for (uint64_t u0 = 0; u0 < units; u0 += 1u << 22) {
     const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 22, units - u0);
     prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
-    launch_pairs_tile(j.pa, toff, owner, u0, cnt, j.bdesc, cofs, bids, bcnt, tb, j.rswl, s);
+    launch_pairs_tile(j.pa, toff, owner, u0, cnt, j.bdesc, tb, j.rswl, s);
     prof_end(c);
     LAUNCHCK();
   }
