@@ -404,17 +404,37 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
   const uint32_t g = u / a.tables_per_group;
   const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
   __syncthreads();
+  bool mem[2];
+  uint32_t mid[2];
 #pragma unroll
   for (uint32_t r = 0; r < 2; ++r) {
     const uint32_t q = lane + 64 * r;
     const uint64_t upto = q >= 63 ? heads : (heads & ((2ull << q) - 1));
     const uint32_t h = upto ? 63 - (uint32_t)__clzll(upto) : 0u;
     const uint32_t hs = __shfl(size, h, 64);  // every lane active here
-    if (upto && q < kSpan && q < h + hs) {
-      const uint32_t id = lids[q];
-      stage_row<RSW>(R + (uint64_t)id * rsw, lrows + q * rswl, rsw);
-      if (use_flags && a.flags[id]) lids[q] = kDead;
-    }
+    mem[r] = upto && q < kSpan && q < h + hs;
+    mid[r] = mem[r] ? lids[q] : 0u;
+  }
+  if (RSW > 0) {  // both rows' loads (each only where that member exists) before either store
+    constexpr int kW = RSW > 0 ? RSW : 1;
+    uint32_t v0[kW], v1[kW];
+    if (mem[0]) RowReg<RSW>::fetch(R + (uint64_t)mid[0] * rsw, v0);
+    if (mem[1]) RowReg<RSW>::fetch(R + (uint64_t)mid[1] * rsw, v1);
+    if (mem[0])
+#pragma unroll
+      for (int w = 0; w < kW; ++w) lrows[lane * rswl + w] = v0[w];
+    if (mem[1])
+#pragma unroll
+      for (int w = 0; w < kW; ++w) lrows[(lane + 64) * rswl + w] = v1[w];
+  } else {
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r)
+      if (mem[r]) stage_row<RSW>(R + (uint64_t)mid[r] * rsw, lrows + (lane + 64 * r) * rswl, rsw);
+  }
+  if (use_flags) {
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r)
+      if (mem[r] && a.flags[mid[r]]) lids[lane + 64 * r] = kDead;
   }
   __syncthreads();
   PairTally tl{0ull, 0ull, 0u, 0u, 0xFFFFFFFFu};
