@@ -32,14 +32,16 @@ CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 INT_PEAK_TOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0  # 39.32 T int32 lane-ops/s
 
 # Algorithmic int32 operations per hash evaluation h(x) = (a x + b) mod (2^31-1)
-# with its extreme updates: one 32x32->64-bit multiply-add and two for the
-# Mersenne fold (shift, add), then the extreme updates with three-input
-# min/max, which fold two new values per instruction: 1/2 per tracked
-# extreme (min for MinHash; min and max for Min-Max).  The folded value is
-# the hash value whenever it is below p, which the kernel checks with the
-# running maximum (for MinHash an extra half operation that is not counted,
-# like the half operation that unpacks two 16-bit indices per register).
-OPS_PER_EVAL = {0: 3.5, 1: 4.0}  # MinHash, Min-Max
+# with its extreme updates: one 32x32->64-bit multiply-add and one shift-add
+# for the Mersenne fold (twice the folded value, 2 (y mod 2^31) + 2 (y >> 31)
+# wrapped to 32 bits, kept in order), then the extreme updates with
+# three-input min/max, which fold two new values per instruction: 1/2 per
+# tracked extreme (min for MinHash; min and max for Min-Max).  The folded value
+# is the hash value whenever it is below p, which the kernel checks with the
+# running extremes (for MinHash the maximum, an extra half operation that is
+# not counted, like the half operation that unpacks two 16-bit indices per
+# register).
+OPS_PER_EVAL = {0: 2.5, 1: 3.0}  # MinHash, Min-Max
 
 
 def sig_traffic(n):

@@ -39,6 +39,19 @@ __device__ __forceinline__ uint32_t hash_fold(uint32_t a2, uint32_t b2, uint32_t
   return ((uint32_t)y2 >> 1) + (uint32_t)(y2 >> 32);
 }
 
+// Twice the folded hash, wrapped: t = 2 s mod 2^32 = (Y mod 2^32) +
+// 2 (Y >> 32) for Y = a2 x + b2 = 2y (one multiply-add and one shift-add).
+// Doubling keeps the order of the values below 2^31; s = p gives t = 2p, and
+// s >= 2^31 (possible only when s >= p) wraps to t = 2 (s - 2^31) < 2 dim.
+// Written as the one shift-add instruction: from C the compiler, knowing the
+// high word is below 2^17, rewrites the shift as a funnel shift and a mask.
+__device__ __forceinline__ uint32_t hash_fold2(uint32_t a2, uint32_t b2, uint32_t x) {
+  const uint64_t y2 = (uint64_t)a2 * x + b2;
+  uint32_t t;
+  asm("v_lshl_add_u32 %0, %1, 1, %2" : "=v"(t) : "v"((uint32_t)(y2 >> 32)), "v"((uint32_t)y2));
+  return t;
+}
+
 // (u * w) mod p for u, w < p, canonical.
 __device__ __forceinline__ uint32_t mul_mod(uint32_t u, uint32_t w) {
   uint64_t z = (uint64_t)u * w;  // < 2^62

@@ -16,14 +16,16 @@
 
 namespace fl {
 
-// Running extremes of two functions over the set elements, kept on the
-// folded values s (hash_fold): one multiply-add, a shift and an add per
-// evaluation, then three-input min and max (two elements per instruction).
-// While every s is below p the folded values are the hash values, so the
-// extremes are exact; an element with s >= p shows up as a maximum >= p, and
-// only then (about 2e-4 of the functions at d = 4096) are that function's
-// extremes recomputed from the canonical values (exact()).  The maximum is
-// kept for MinHash too, as that check.
+// Running extremes of two functions over the set elements, kept on
+// t = hash_fold2 (twice the folded value s, wrapped): one multiply-add and
+// one shift-add per evaluation, then three-input min and max (two elements
+// per instruction).  While every s is below p, s is the hash value and the
+// extremes of t are twice the exact extremes.  An element with s >= p shows
+// up as a maximum of 2p (s = p) or as a minimum below 2 dim (s >= 2^31
+// wraps there); then (about 4e-4 of the functions at d = 4,096, counting the
+// genuine minima that small) the function's extremes are recomputed from the
+// canonical values (exact()).  The maximum is kept for MinHash too, as that
+// check.
 template <bool MINMAX>
 struct PairAcc {
   uint32_t mnA, mxA, mnB, mxB;
@@ -33,12 +35,12 @@ struct PairAcc {
   }
   __device__ __forceinline__ void add(uint32_t a2A, uint32_t b2A, uint32_t a2B, uint32_t b2B, uint32_t v) {
     const uint32_t x0 = v & 0xFFFFu, x1 = v >> 16;
-    const uint32_t sA0 = hash_fold(a2A, b2A, x0), sA1 = hash_fold(a2A, b2A, x1);
-    const uint32_t sB0 = hash_fold(a2B, b2B, x0), sB1 = hash_fold(a2B, b2B, x1);
-    mnA = min(mnA, min(sA0, sA1));
-    mnB = min(mnB, min(sB0, sB1));
-    mxA = max(mxA, max(sA0, sA1));
-    mxB = max(mxB, max(sB0, sB1));
+    const uint32_t tA0 = hash_fold2(a2A, b2A, x0), tA1 = hash_fold2(a2A, b2A, x1);
+    const uint32_t tB0 = hash_fold2(a2B, b2B, x0), tB1 = hash_fold2(a2B, b2B, x1);
+    mnA = min(mnA, min(tA0, tA1));
+    mnB = min(mnB, min(tB0, tB1));
+    mxA = max(mxA, max(tA0, tA1));
+    mxB = max(mxB, max(tB0, tB1));
     // Serialise the running extremes: otherwise the compiler regroups the
     // min and max reductions into separate trees and keeps every hash value
     // of the row alive in registers.
@@ -57,10 +59,13 @@ struct PairAcc {
     mn = lo;
     mx = hi;
   }
+  // Hash values of the extremes (canonical), with dim the index bound.
   template <typename Each>
-  __device__ __forceinline__ void finish(uint32_t a2A, uint32_t b2A, uint32_t a2B, uint32_t b2B, Each each) {
-    if (mxA >= kP) exact(a2A, b2A, each, mnA, mxA);
-    if (mxB >= kP) exact(a2B, b2B, each, mnB, mxB);
+  __device__ __forceinline__ void finish(uint32_t a2A, uint32_t b2A, uint32_t a2B, uint32_t b2B, uint32_t dim,
+                                         Each each) {
+    const uint32_t wrap = 2u * dim;
+    if (mxA >= 2u * kP || mnA < wrap) exact(a2A, b2A, each, mnA, mxA); else { mnA >>= 1; mxA >>= 1; }
+    if (mxB >= 2u * kP || mnB < wrap) exact(a2B, b2B, each, mnB, mxB); else { mnB >>= 1; mxB >>= 1; }
   }
 };
 
@@ -195,7 +200,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 
       for (int w = 0; w < W; ++w) acc.add(a2A, b2A, a2B, b2B, xs[w]);
       // the rare exact recomputation reads the row from memory (indexing the
       // registers would move them to scratch)
-      acc.finish(a2A, b2A, a2B, b2B, [&](auto&& f) {
+      acc.finish(a2A, b2A, a2B, b2B, a.dim, [&](auto&& f) {
         for (uint64_t k = 0; k < len; k += 2) {
           const uint32_t x0 = a.ind[lo + k];
           const uint32_t x1 = k + 1 < len ? a.ind[lo + k + 1] : x0;
@@ -255,7 +260,7 @@ __global__ __launch_bounds__(256) void k_sig_long(SigArgs a) {
         }
       };
       each([&](uint32_t v) { acc.add(a2A, b2A, a2B, b2B, v); });
-      acc.finish(a2A, b2A, a2B, b2B, each);
+      acc.finish(a2A, b2A, a2B, b2B, a.dim, each);
       kb.put(a, fA, acc.mnA, i, u, live);
       if (MINMAX) kb.put(a, fA, acc.mxA, i, u, live);
       if (two) {

@@ -93,6 +93,39 @@ def test_signatures_bit_exact(ctx, name, make, dim, t, r, scheme):
     assert np.array_equal(vals.cpu().numpy().view(np.uint32), ovals)
 
 
+FOLD_CASES = [(200, fl.MINMAX), (200, fl.MINHASH), (100, fl.MINMAX), (300, fl.MINMAX), (37, fl.MINHASH)]
+
+
+@pytest.mark.parametrize("nnz,scheme", FOLD_CASES, ids=[f"nnz{c[0]}-{'minmax' if c[1] == fl.MINMAX else 'minhash'}" for c in FOLD_CASES])
+def test_signatures_fold_edge_values(ctx, nnz, scheme):
+    """Hash parameters chosen so that every function reaches a residue k in
+    0..7 at the largest index of one fingerprint, from a y = a x + b of many
+    multiples of p.  Folding y to (y mod 2^31) + (y >> 31) then gives p itself
+    (k = 0) or a value of at least 2^31 (k > 0): the two forms whose
+    canonical residue needs the correction step."""
+    dim, t, r = 4096, 12, 4
+    P = 2**31 - 1
+    rows = _fixed(300, dim, nnz, 23 + nnz)
+    nf = fl.n_funcs(t, r, scheme)
+    a, _ = fl.make_hash(77 + nnz, nf)
+    b = np.empty(nf, np.uint32)
+    hit = 0
+    for f in range(nf):
+        x0 = int(rows[f % len(rows)].max())
+        k = f % 8
+        b[f] = (k - int(a[f]) * x0) % P
+        y = int(a[f]) * x0 + int(b[f])
+        s = (y & P) + (y >> 31)
+        hit += s >= P
+    assert hit == nf  # every function has its out-of-range fold
+    say(f"[sig-fold] nnz={nnz} scheme={scheme}")
+    keys, vals = ctx.signatures(fl.to_device_rows(rows), dim, t, r, scheme, a, b, with_values=True)
+    torch.cuda.synchronize()
+    okeys, ovals = oracle.signatures(rows, dim, t, r, scheme, a, b, with_values=True)
+    assert np.array_equal(_u64(keys), okeys)
+    assert np.array_equal(vals.cpu().numpy().view(np.uint32), ovals)
+
+
 def test_signatures_table_range(ctx):
     rows = synth.generate(synth.station(n=1000, seed=21))
     a, b = fl.make_hash(5, 100)
