@@ -205,6 +205,7 @@ SigArgs fl_sig_args(const fast_lsh_hash* h, const fast_lsh_fps* f, const uint32_
   a.err = err;
   a.tables_per_group = 1;
   a.row_dw = 4;
+  a.row_pitch = 4;
   a.out_stride = f->n;
   return a;
 }

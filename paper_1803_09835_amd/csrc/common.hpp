@@ -112,13 +112,23 @@ enum : uint32_t {
 // Sub-key rows.  Each fingerprint carries, per group of tables, a row of
 // 16-bit sub-keys (the low bits of its mixed band key in each table of the
 // group), field k in bits [16k, 16k+16) of the row, in row_dw dwords.
-// Equal band keys give equal sub-keys.
+// Equal band keys give equal sub-keys.  Consecutive fingerprints' rows lie
+// row_pitch dwords apart: row_dw itself (dense), or padded so that no row
+// crosses a 128-byte line, which halves the memory requests of a random row
+// read.
 // --------------------------------------------------------------------------
 constexpr uint32_t kSubBits = 16;
 constexpr uint32_t kSubMask = (1u << kSubBits) - 1;
 
 __host__ __device__ constexpr uint32_t row_dwords(uint32_t tables) { return (kSubBits * tables + 31) / 32; }
 __host__ __device__ constexpr uint32_t row_fields(uint32_t dwords) { return 32 * dwords / kSubBits; }
+// Line-aligned pitch: the next power of two up to 32 dwords (one 128-byte
+// line), whole lines above that (rows start at 128-byte aligned bases).
+__host__ __device__ constexpr uint32_t row_pitch_lines(uint32_t dwords) {
+  uint32_t p = 1;
+  while (p < dwords && p < 32) p *= 2;
+  return dwords <= 32 ? p : (dwords + 31) / 32 * 32;
+}
 
 // Field k of the row r.
 __device__ __forceinline__ uint32_t row_field(const uint32_t* r, uint32_t k) {
@@ -148,7 +158,7 @@ struct SigArgs {
   uint64_t* keys;        // [table_count][n] band keys, or nullptr
   uint32_t* sigs;        // [n][table_count][r] values, or nullptr
   uint64_t* mkeys;       // [table_count][out_stride] mixed keys, or nullptr
-  uint32_t* rows;        // sub-key rows [G][out_stride][row_dw], or nullptr
+  uint32_t* rows;        // sub-key rows [G][out_stride][row_pitch], or nullptr
   uint64_t out_stride;   // fingerprints per table in mkeys / rows (all stations)
   uint64_t out_base;     // first position of this station in mkeys / rows
   uint64_t tag;          // station id << 60 (kMixStation): keeps stations apart
@@ -156,6 +166,7 @@ struct SigArgs {
   uint32_t* hi32;        // [num_tables][out_stride] high words of split keys (global table index), or nullptr
   uint32_t tables_per_group;
   uint32_t row_dw;       // dwords per row
+  uint32_t row_pitch;    // dwords from one fingerprint's row to the next
   int* err;              // set to 1 on an empty row or an index >= dim
 };
 
@@ -184,11 +195,12 @@ struct BucketArgs {
 struct PairArgs {
   const uint32_t* order;      // bucket members by position [S][n]
   const uint8_t* flags;
-  const uint32_t* rows;       // sub-key rows [G][n][row_dw]
+  const uint32_t* rows;       // sub-key rows [G][n][row_pitch]
   const uint64_t* mkeys;      // exact mixed keys [t][n], or nullptr when hi32 is given
   const uint32_t* hi32;       // high words of split keys [t][n] (with equal sub-keys: equal keys)
   uint64_t n;
   uint32_t t, G, tables_per_group, row_dw;
+  uint32_t row_pitch;         // dwords from one fingerprint's row to the next
   uint32_t table_offset;      // table of launch segment 0 (segment s is table table_offset + s)
   uint32_t min_lag, min_votes, need;
   uint32_t want_distinct;

@@ -26,8 +26,9 @@ void radix_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32
                 uint32_t shift, uint32_t* hist, uint32_t* sums, uint32_t variant, hipStream_t s);
 void launch_bucket(const BucketArgs& a, uint32_t S, hipStream_t s);
 void launch_split_keys(const uint32_t* hi32, const uint32_t* rows, uint64_t n, uint32_t tb, uint32_t tc,
-                       uint32_t tables_per_group, uint32_t row_dw, uint64_t* mkeys, hipStream_t s);
+                       uint32_t tables_per_group, uint32_t row_pitch, uint64_t* mkeys, hipStream_t s);
 uint64_t bucket_desc_slack(uint64_t big_max, uint32_t S);  // extra big-descriptor slots launch_bucket may use
+uint32_t device_cus();  // compute units of the current device
 void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64_t* tk, uint32_t* tv,
                    hipStream_t s);
 // pairs.hip

@@ -13,7 +13,10 @@
 // by their owner: the smallest table of the first group holding at least
 // `need` tables of S.  Every qualifying pair is therefore reported once,
 // with its exact vote count |S|, and no atomics are spent on votes.
+#include <algorithm>
+
 #include "common.hpp"
+#include "host.hpp"
 
 namespace fl {
 
@@ -100,8 +103,8 @@ __device__ void exact_and_report(const PairArgs& a, uint32_t u, uint32_t i, uint
   uint32_t votes = 0;
   for (uint32_t g = 0; g < a.G; ++g) {
     const uint32_t fields = min(a.tables_per_group, a.t - g * a.tables_per_group);
-    const uint32_t* ri = a.rows + ((uint64_t)g * a.n + i) * a.row_dw;
-    const uint32_t* rj = a.rows + ((uint64_t)g * a.n + j) * a.row_dw;
+    const uint32_t* ri = a.rows + ((uint64_t)g * a.n + i) * a.row_pitch;
+    const uint32_t* rj = a.rows + ((uint64_t)g * a.n + j) * a.row_pitch;
     const uint32_t cnt = group_shared(a, ri, rj, g * a.tables_per_group, i, j, fields, g < gu ? a.need : 0xFFFFFFFFu);
     if (g < gu && cnt >= a.need) return;   // the owner lies in group g
     if (g == gu && cnt < a.need) return;   // the owner, if any, lies in a later group
@@ -138,6 +141,10 @@ struct PairTally {
 };
 
 constexpr uint32_t kDead = 0xFFFFFFFFu;  // member excluded by the occurrence filter
+
+// Resident one-wave workgroups per CU for the small-bucket kernel: its
+// register limit (four waves per SIMD at 113 VGPRs).
+constexpr uint32_t kPairWavesPerCU = 16;
 
 // Row of sub-keys of one member of table u's group.  RSW > 0: the row length
 // is a compile-time constant and the left row of a pair lives in registers;
@@ -352,17 +359,20 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
   return row_fields(rsw) - valid;
 }
 
-// Small buckets of one table: one 64-lane workgroup handles the buckets that
-// start in 64 consecutive positions (a bucket marked at position q holds the
-// ids at positions q .. q+size-1).  Ids and marks are loaded side by side,
-// the member rows are staged in LDS with each lane issuing a whole row's
-// loads at once, and every lane then walks a contiguous range of the
-// chunk's pairs (row-major within each bucket) with the left row in
-// registers.  Heads and pair offsets come from
-// ballots and lane shuffles, so the only barriers are the LDS hand-offs of
-// a single wave; many such waves per CU overlap their loads.
+// Small buckets of one table, in chunks of 64 positions: a chunk holds the
+// buckets that start in its positions (a bucket marked at position q holds
+// the ids at positions q .. q+size-1).  One-wave workgroups stay resident
+// and walk the chunks of their segment with a stride of the grid width; the
+// marks and ids of a wave's next chunk are loaded before the current one is
+// processed, so they arrive while its rows load and its pairs run.  The
+// member rows are staged in LDS with each lane issuing a whole row's loads at
+// once, and every lane then walks a contiguous range of the chunk's pairs
+// (row-major within each bucket) with the left row in registers.  Heads and
+// pair offsets come from ballots and lane shuffles, so the only barriers are
+// the LDS hand-offs of a single wave.
 template <int RSW, bool FAST>
-__global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl) {
+__global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl,
+                                                   uint32_t nchunk) {
   constexpr uint32_t kSpan = 64 + kSmallBucket - 1;  // heads in 64 positions, members up to kSmallBucket
   extern __shared__ uint32_t smem[];
   uint32_t* lrows = smem;                   // kSpan * rswl
@@ -373,103 +383,112 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
   const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
   const uint32_t seg = blockIdx.y;           // launch segment (positions in order/marks)
   const uint32_t u = seg + a.table_offset;    // its table
-  const uint64_t p0 = (uint64_t)blockIdx.x * 64;
-  const uint64_t left = a.n - p0;
-  const uint8_t* marks = marks_all + (uint64_t)seg * a.n + p0;
-  const uint32_t* order = a.order + (uint64_t)seg * a.n + p0;
-
-  const uint32_t size = lane < left ? marks[lane] : 0u;
-  if (lane < left) lids[lane] = order[lane];
-  if (64 + lane < left && lane < kSpan - 64) lids[64 + lane] = order[64 + lane];
-  const uint64_t heads = __ballot(size != 0);
-  if (heads == 0) return;
-  const uint64_t lt = __lanemask_lt();
-  const uint32_t hidx = __popcll(heads & lt);
-  const uint32_t nh = __popcll(heads);
-  const uint32_t pc = size * (size - (size > 0)) / 2;
-  uint32_t inc = pc;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(inc, o, 64);
-    if (lane >= (uint32_t)o) inc += y;
-  }
-  const uint32_t P = __shfl(inc, 63, 64);
+  const uint8_t* marks = marks_all + (uint64_t)seg * a.n;
+  const uint32_t* order = a.order + (uint64_t)seg * a.n;
   const bool use_flags = *a.n_flagged != 0;
-  if (size) {
-    hinfo[hidx] = lane | (size << 16);
-    bpof[hidx] = inc - pc;
-  }
-  if (lane == 0) bpof[nh] = P;
-  // Member positions: q belongs to the last head h <= q when q < h + size(h).
   const uint32_t g = u / a.tables_per_group;
-  const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
-  __syncthreads();
-  bool mem[2];
-  uint32_t mid[2];
-#pragma unroll
-  for (uint32_t r = 0; r < 2; ++r) {
-    const uint32_t q = lane + 64 * r;
-    const uint64_t upto = q >= 63 ? heads : (heads & ((2ull << q) - 1));
-    const uint32_t h = upto ? 63 - (uint32_t)__clzll(upto) : 0u;
-    const uint32_t hs = __shfl(size, h, 64);  // every lane active here
-    mem[r] = upto && q < kSpan && q < h + hs;
-    mid[r] = mem[r] ? lids[q] : 0u;
-  }
-  if (RSW > 0) {  // both rows' loads (each only where that member exists) before either store
-    constexpr int kW = RSW > 0 ? RSW : 1;
-    uint32_t v0[kW], v1[kW];
-    if (mem[0]) RowReg<RSW>::fetch(R + (uint64_t)mid[0] * rsw, v0);
-    if (mem[1]) RowReg<RSW>::fetch(R + (uint64_t)mid[1] * rsw, v1);
-    if (mem[0])
-#pragma unroll
-      for (int w = 0; w < kW; ++w) lrows[lane * rswl + w] = v0[w];
-    if (mem[1])
-#pragma unroll
-      for (int w = 0; w < kW; ++w) lrows[(lane + 64) * rswl + w] = v1[w];
-  } else {
-#pragma unroll
-    for (uint32_t r = 0; r < 2; ++r)
-      if (mem[r]) stage_row<RSW>(R + (uint64_t)mid[r] * rsw, lrows + (lane + 64 * r) * rswl, rsw);
-  }
-  if (use_flags) {
-#pragma unroll
-    for (uint32_t r = 0; r < 2; ++r)
-      if (mem[r] && a.flags[mid[r]]) lids[lane + 64 * r] = kDead;
-  }
-  __syncthreads();
-  PairTally tl{0ull, 0ull, 0u, 0u, 0xFFFFFFFFu};
-  if (a.nstation > 1) {  // one lookup per wave: the station of the first head's first member
-    const uint32_t st = station_of(a.station_base, a.nstation, order[hinfo[0] & 0xFFFFu]);
-    tl.station = st;
-    tl.lo = (uint32_t)a.station_base[st];
-    tl.hi = (uint32_t)a.station_base[st + 1];
-  }
+  const uint32_t* R = a.rows + (uint64_t)g * a.n * a.row_pitch;
   const uint32_t pad = group_pad(a, u, rsw);
-  const uint32_t per = (P + 63) / 64;
-  uint32_t p = lane * per;
-  const uint32_t pend = min(P, p + per);
-  if (p < pend) {
-    uint32_t b = last_le(bpof, nh, p);
-    uint32_t base = hinfo[b] & 0xFFFFu, m = hinfo[b] >> 16;
-    uint32_t x, y;
-    tri_decode(m, p - bpof[b], x, y);
-    uint32_t idx = lids[base + x];
-    RowReg<RSW> rx;
-    const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
-    if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
-    for (; p < pend; ++p) {
-      visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, lrows + (base + x) * rswl, lrows + (base + y) * rswl,
-                                 rsw, pad, tl);
-      if (++y == m) {
-        if (++x == m - 1) {
-          if (++b >= nh) break;
-          base = hinfo[b] & 0xFFFFu;
-          m = hinfo[b] >> 16;
-          x = 0;
+  const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
+  // Tallies of the wave's station; with several stations the empty range
+  // makes the first pair look its station up.
+  PairTally tl{0ull, 0ull, 0u, 0u, a.nstation > 1 ? 0u : 0xFFFFFFFFu};
+
+  // The chunk's marks and ids (64 + kSpan - 64 positions, clipped at n).
+  uint32_t nsize = 0, nid0 = 0, nid1 = 0;
+  auto fetch = [&](uint32_t c) {
+    const uint64_t p0 = (uint64_t)c * 64;
+    const uint64_t left = a.n - p0;
+    nsize = lane < left ? marks[p0 + lane] : 0u;
+    nid0 = lane < left ? order[p0 + lane] : 0u;
+    nid1 = (64 + lane < left && lane < kSpan - 64) ? order[p0 + 64 + lane] : 0u;
+  };
+  uint32_t c = blockIdx.x;
+  if (c < nchunk) fetch(c);
+  for (; c < nchunk; c += gridDim.x) {
+    const uint32_t size = nsize, id0 = nid0, id1 = nid1;
+    if (c + gridDim.x < nchunk) fetch(c + gridDim.x);
+    const uint64_t heads = __ballot(size != 0);
+    if (heads == 0) continue;
+    __syncthreads();  // the previous chunk's LDS reads are complete
+    lids[lane] = id0;
+    if (lane < kSpan - 64) lids[64 + lane] = id1;
+    const uint64_t lt = __lanemask_lt();
+    const uint32_t hidx = __popcll(heads & lt);
+    const uint32_t nh = __popcll(heads);
+    const uint32_t pc = size * (size - (size > 0)) / 2;
+    uint32_t inc = pc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, 64);
+      if (lane >= (uint32_t)o) inc += y;
+    }
+    const uint32_t P = __shfl(inc, 63, 64);
+    if (size) {
+      hinfo[hidx] = lane | (size << 16);
+      bpof[hidx] = inc - pc;
+    }
+    if (lane == 0) bpof[nh] = P;
+    __syncthreads();
+    // Member positions: q belongs to the last head h <= q when q < h + size(h).
+    bool mem[2];
+    uint32_t mid[2];
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+      const uint32_t q = lane + 64 * r;
+      const uint64_t upto = q >= 63 ? heads : (heads & ((2ull << q) - 1));
+      const uint32_t h = upto ? 63 - (uint32_t)__clzll(upto) : 0u;
+      const uint32_t hs = __shfl(size, h, 64);  // every lane active here
+      mem[r] = upto && q < kSpan && q < h + hs;
+      mid[r] = mem[r] ? lids[q] : 0u;
+    }
+    if (RSW > 0) {  // both rows' loads (each only where that member exists) before either store
+      constexpr int kW = RSW > 0 ? RSW : 1;
+      uint32_t v0[kW], v1[kW];
+      if (mem[0]) RowReg<RSW>::fetch(R + (uint64_t)mid[0] * a.row_pitch, v0);
+      if (mem[1]) RowReg<RSW>::fetch(R + (uint64_t)mid[1] * a.row_pitch, v1);
+      if (mem[0])
+#pragma unroll
+        for (int w = 0; w < kW; ++w) lrows[lane * rswl + w] = v0[w];
+      if (mem[1])
+#pragma unroll
+        for (int w = 0; w < kW; ++w) lrows[(lane + 64) * rswl + w] = v1[w];
+    } else {
+#pragma unroll
+      for (uint32_t r = 0; r < 2; ++r)
+        if (mem[r]) stage_row<RSW>(R + (uint64_t)mid[r] * a.row_pitch, lrows + (lane + 64 * r) * rswl, rsw);
+    }
+    if (use_flags) {
+#pragma unroll
+      for (uint32_t r = 0; r < 2; ++r)
+        if (mem[r] && a.flags[mid[r]]) lids[lane + 64 * r] = kDead;
+    }
+    __syncthreads();
+    const uint32_t per = (P + 63) / 64;
+    uint32_t p = lane * per;
+    const uint32_t pend = min(P, p + per);
+    if (p < pend) {
+      uint32_t b = last_le(bpof, nh, p);
+      uint32_t base = hinfo[b] & 0xFFFFu, m = hinfo[b] >> 16;
+      uint32_t x, y;
+      tri_decode(m, p - bpof[b], x, y);
+      uint32_t idx = lids[base + x];
+      RowReg<RSW> rx;
+      if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
+      for (; p < pend; ++p) {
+        visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, lrows + (base + x) * rswl, lrows + (base + y) * rswl,
+                                   rsw, pad, tl);
+        if (++y == m) {
+          if (++x == m - 1) {
+            if (++b >= nh) break;
+            base = hinfo[b] & 0xFFFFu;
+            m = hinfo[b] >> 16;
+            x = 0;
+          }
+          y = x + 1;
+          idx = lids[base + x];
+          if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
         }
-        y = x + 1;
-        idx = lids[base + x];
-        if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
       }
     }
   }
@@ -522,7 +541,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
   uint32_t* idsA = smem + 2 * tb_size * rswl;
   uint32_t* idsB = diag ? idsA : idsA + tb_size;
   const uint32_t g = u / a.tables_per_group;
-  const uint32_t* R = a.rows + (uint64_t)g * a.n * rsw;
+  const uint32_t* R = a.rows + (uint64_t)g * a.n * a.row_pitch;
   for (uint32_t q = threadIdx.x; q < na; q += kPT) idsA[q] = bid[a0 + q];
   if (!diag)
     for (uint32_t q = threadIdx.x; q < nbm; q += kPT) idsB[q] = bid[b0 + q];
@@ -531,13 +550,13 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
   const bool use_flags = *a.n_flagged != 0;
   for (uint32_t q = threadIdx.x; q < na; q += kPT) {
     const uint32_t id = idsA[q];
-    stage_row<RSW>(R + (uint64_t)id * rsw, rowsA + q * rswl, rsw);
+    stage_row<RSW>(R + (uint64_t)id * a.row_pitch, rowsA + q * rswl, rsw);
     if (use_flags && a.flags[id]) idsA[q] = kDead;
   }
   if (!diag)
     for (uint32_t q = threadIdx.x; q < nbm; q += kPT) {
       const uint32_t id = idsB[q];
-      stage_row<RSW>(R + (uint64_t)id * rsw, rowsB + q * rswl, rsw);
+      stage_row<RSW>(R + (uint64_t)id * a.row_pitch, rowsB + q * rswl, rsw);
       if (use_flags && a.flags[id]) idsB[q] = kDead;
     }
   __syncthreads();
@@ -706,22 +725,27 @@ static unsigned grid_for(uint64_t count) {
 // needs two shared tables in its group and no distinct count is wanted.
 static bool fast_test(const PairArgs& a) { return a.need == 2 && !a.want_distinct; }
 
+// Persistent: one resident round of one-wave workgroups (as many as a CU
+// holds by LDS, at most kPairWavesPerCU) spread over the segments.
 void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, hipStream_t s) {
-  if (a.n == 0) return;
-  const dim3 grid((unsigned)((a.n + 63) / 64), S);
+  if (a.n == 0 || S == 0) return;
   constexpr uint32_t kSpan = 64 + kSmallBucket - 1;
   const size_t smem = (size_t)(kSpan * rswl + kSpan + 64 + 65) * 4;
+  const uint32_t nchunk = (uint32_t)((a.n + 63) / 64);
+  const uint32_t per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(kPairWavesPerCU, (160u << 10) / smem));
+  const uint32_t per_seg = std::max<uint32_t>(1u, std::min<uint32_t>(nchunk, per_cu * device_cus() / S));
+  const dim3 grid(per_seg, S);
   switch (a.row_dw) {
     case 10:
-      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<10, true>), grid, dim3(64), smem, s, a, marks, rswl);
-      else hipLaunchKernelGGL((k_pairs_wave<10, false>), grid, dim3(64), smem, s, a, marks, rswl);
+      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<10, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
+      else hipLaunchKernelGGL((k_pairs_wave<10, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
       break;
     case 17:
-      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<17, true>), grid, dim3(64), smem, s, a, marks, rswl);
-      else hipLaunchKernelGGL((k_pairs_wave<17, false>), grid, dim3(64), smem, s, a, marks, rswl);
+      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<17, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
+      else hipLaunchKernelGGL((k_pairs_wave<17, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
       break;
     default:
-      hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl);
+      hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
       break;
   }
 }

@@ -27,7 +27,7 @@ using namespace fl;
 namespace {
 
 struct Plan {
-  uint32_t t, G, TG, row_dw, need;
+  uint32_t t, G, TG, row_dw, row_pitch, need;
 };
 
 // Bits of the mixed key the radix passes bin on: a multiple of 8 large enough
@@ -43,8 +43,10 @@ uint32_t bin_bits(uint64_t n_max, bool tagged) {
 
 // Table groups of the sub-key rows: one group when every shared table has to
 // be seen anyway (v <= 2, or n_distinct wanted), else v - 1 groups so that a
-// pair with v votes shares need = ceil(v / G) tables in some group.
-Plan make_plan(uint32_t t, uint32_t v, bool distinct) {
+// pair with v votes shares need = ceil(v / G) tables in some group.  `lines`:
+// rows padded to the line-aligned pitch (fewer memory requests per random
+// row read); otherwise packed (the bounded form, where memory is the limit).
+Plan make_plan(uint32_t t, uint32_t v, bool distinct, bool lines) {
   Plan p;
   p.t = t;
   uint32_t G = (distinct || v <= 2) ? 1u : std::min(v - 1, t);
@@ -52,6 +54,7 @@ Plan make_plan(uint32_t t, uint32_t v, bool distinct) {
   p.G = (t + p.TG - 1) / p.TG;
   p.need = (v + p.G - 1) / p.G;
   p.row_dw = row_dwords(p.TG);
+  p.row_pitch = lines ? row_pitch_lines(p.row_dw) : p.row_dw;
   return p;
 }
 
@@ -151,6 +154,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
     sa.tag = (uint64_t)st << 60;
     sa.tables_per_group = j.pl.TG;
     sa.row_dw = j.pl.row_dw;
+    sa.row_pitch = j.pl.row_pitch;
     launch_sig(j.cap[st], j.minmax, sa, s);
   }
   pe();
@@ -383,7 +387,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
     return FAST_LSH_OK;
   }
   const uint64_t N = j.N, t = j.t, tn = t * N;
-  j.pl = make_plan(j.t, flt->min_votes, distinct);
+  j.pl = make_plan(j.t, flt->min_votes, distinct, true);
   uint64_t n_max = 0;
   for (uint32_t st = 0; st < S; ++st) n_max = std::max<uint64_t>(n_max, f[st].n);
   j.B = bin_bits(n_max, S > 1);
@@ -410,7 +414,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   j.nd = j.ev + (uint64_t)S * kSpread;
   j.mb = reinterpret_cast<unsigned int*>(j.nd + (uint64_t)S * kSpread);
   RC(ws<uint64_t>(c, "mkeys", tn, &j.mkeys));
-  RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_dw, &j.rows));
+  RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_pitch, &j.rows));
   RC(ws<uint64_t>(c, "ak", tn, &j.ak));
   RC(ws<uint32_t>(c, "av", tn, &j.av));
   RC(ws<uint64_t>(c, "bk", tn, &j.bk));
@@ -462,6 +466,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   pa.G = j.pl.G;
   pa.tables_per_group = j.pl.TG;
   pa.row_dw = j.pl.row_dw;
+  pa.row_pitch = j.pl.row_pitch;
   pa.min_lag = flt->min_lag;
   pa.min_votes = flt->min_votes;
   pa.need = j.pl.need;
@@ -603,7 +608,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   const uint32_t TGm = std::min(group_tables, t);
   const uint32_t ngroups = (t + TGm - 1) / TGm;
   const uint64_t gn = (uint64_t)TGm * N;
-  j.pl = make_plan(t, flt->min_votes, distinct);
+  j.pl = make_plan(t, flt->min_votes, distinct, false);
   j.B = bin_bits(N, false);
   RC(fl_upload_hash(c, h, &j.dhash));
   j.cap.assign(1, 0);
@@ -626,7 +631,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   j.nd = j.ev + kSpread;
   j.mb = reinterpret_cast<unsigned int*>(j.nd + kSpread);
   uint32_t* hi32;
-  RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_dw, &j.rows));
+  RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_pitch, &j.rows));
   RC(ws<uint32_t>(c, "hi32", (uint64_t)t * N, &hi32));
   RC(ws<uint8_t>(c, "flags", N, &j.flags));
   RC(ws<uint64_t>(c, "station_base", 2, &j.sbase));
@@ -676,6 +681,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   pa.G = j.pl.G;
   pa.tables_per_group = j.pl.TG;
   pa.row_dw = j.pl.row_dw;
+  pa.row_pitch = j.pl.row_pitch;
   pa.min_lag = flt->min_lag;
   pa.min_votes = flt->min_votes;
   pa.need = j.pl.need;
@@ -709,9 +715,10 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
       sa.mix = kMixSplit;
       sa.tables_per_group = j.pl.TG;
       sa.row_dw = j.pl.row_dw;
+      sa.row_pitch = j.pl.row_pitch;
       launch_sig(j.cap[0], j.minmax, sa, s);
     } else {
-      launch_split_keys(hi32, j.rows, N, tb, tc, j.pl.TG, j.pl.row_dw, j.bk, s);
+      launch_split_keys(hi32, j.rows, N, tb, tc, j.pl.TG, j.pl.row_pitch, j.bk, s);
     }
     prof_end(c);
     LAUNCHCK();

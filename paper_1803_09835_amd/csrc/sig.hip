@@ -111,7 +111,7 @@ __device__ __forceinline__ void store_table(const SigArgs& a, uint64_t key, uint
 __device__ __forceinline__ void resume_row(const SigArgs& a, uint64_t i, bool live, uint32_t* my) {
   if (!a.rows || a.table_begin % a.tables_per_group == 0) return;
   const uint32_t g = a.table_begin / a.tables_per_group;
-  const uint32_t* src = a.rows + ((uint64_t)g * a.out_stride + a.out_base + i) * a.row_dw;
+  const uint32_t* src = a.rows + ((uint64_t)g * a.out_stride + a.out_base + i) * a.row_pitch;
   for (uint32_t w = 0; w < a.row_dw; ++w) my[w] = live ? src[w] : 0u;
 }
 
@@ -126,10 +126,10 @@ __device__ __forceinline__ void flush_rows(const SigArgs& a, uint32_t u, const u
   const uint32_t g = tab / a.tables_per_group;
   const uint64_t i0 = (uint64_t)blockIdx.x * 256;
   const uint32_t live = (uint32_t)min((uint64_t)256, a.n - i0);
-  uint32_t* dst = a.rows + ((uint64_t)g * a.out_stride + a.out_base + i0) * a.row_dw;
+  uint32_t* dst = a.rows + ((uint64_t)g * a.out_stride + a.out_base + i0) * a.row_pitch;
   for (uint32_t idx = threadIdx.x; idx < live * a.row_dw; idx += 256) {
     const uint32_t r = idx / a.row_dw, w = idx - r * a.row_dw;
-    dst[idx] = srow[r * (a.row_dw + 1) + w];
+    dst[r * a.row_pitch + w] = srow[r * (a.row_dw + 1) + w];
   }
   __syncthreads();
 }

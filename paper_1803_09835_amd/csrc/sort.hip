@@ -952,7 +952,7 @@ void radix_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32
 }
 
 // Compute units of the current device (queried once).
-static uint32_t device_cus() {
+uint32_t device_cus() {
   static uint32_t cus = 0;
   if (cus == 0) {
     int dev = 0, v = 0;
@@ -993,15 +993,15 @@ void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64
 // Mixed keys of tables [tb, tb + tc) rebuilt from what an earlier signature
 // pass stored, for keys of the form mix48(band key) << 16: the high word
 // (bits 32-63, hi32[u][i]) and the sub-key (bits 16-31, field u mod TG of the
-// row of table u's group).  One thread per fingerprint; its row dwords are
-// read once for all the tables.
+// row of table u's group, rows row_pitch dwords apart).  One thread per
+// fingerprint.
 __global__ __launch_bounds__(256) void k_split_keys(const uint32_t* hi32, const uint32_t* rows, uint64_t n,
                                                     uint32_t tb, uint32_t tc, uint32_t tables_per_group,
-                                                    uint32_t row_dw, uint64_t* mkeys) {
+                                                    uint32_t row_pitch, uint64_t* mkeys) {
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
     for (uint32_t q = 0; q < tc; ++q) {
       const uint32_t u = tb + q, g = u / tables_per_group, k = u - g * tables_per_group;
-      const uint32_t w = rows[((uint64_t)g * n + i) * row_dw + (k >> 1)];
+      const uint32_t w = rows[((uint64_t)g * n + i) * row_pitch + (k >> 1)];
       const uint64_t field = (w >> (16 * (k & 1))) & 0xFFFFu;
       mkeys[(uint64_t)q * n + i] = ((uint64_t)hi32[(uint64_t)u * n + i] << 32) | (field << 16);
     }
@@ -1009,11 +1009,11 @@ __global__ __launch_bounds__(256) void k_split_keys(const uint32_t* hi32, const 
 }
 
 void launch_split_keys(const uint32_t* hi32, const uint32_t* rows, uint64_t n, uint32_t tb, uint32_t tc,
-                       uint32_t tables_per_group, uint32_t row_dw, uint64_t* mkeys, hipStream_t s) {
+                       uint32_t tables_per_group, uint32_t row_pitch, uint64_t* mkeys, hipStream_t s) {
   if (n == 0 || tc == 0) return;
   const uint64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_split_keys, dim3((unsigned)(blocks < 65535 ? blocks : 65535)), dim3(256), 0, s, hi32, rows, n,
-                     tb, tc, tables_per_group, row_dw, mkeys);
+                     tb, tc, tables_per_group, row_pitch, mkeys);
 }
 
 }  // namespace fl
