@@ -137,12 +137,10 @@ __device__ __forceinline__ void flush_rows(const SigArgs& a, uint32_t u, const u
 // CAP: most indices a row may hold (rows shorter than CAP are padded with
 // their first index, which leaves every min and max unchanged).  Rows are
 // fixed-length with an even length and 4-byte aligned (other layouts take
-// k_sig_long).  QUAD (two functions per table): each pass over the
-// register-resident row evaluates the four functions of two tables, so the
-// 16-bit unpacking of an index pair is shared by four functions, not two.
-template <int CAP, bool MINMAX, bool QUAD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 ? (QUAD ? 3 : 4) : 1))) void k_sig(
-    SigArgs a) {
+// k_sig_long).  Each pass over the register-resident row evaluates four
+// functions, so the 16-bit unpacking of an index pair is shared by four.
+template <int CAP, bool MINMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 ? 3 : 1))) void k_sig(SigArgs a) {
   extern __shared__ uint32_t srow[];  // 256 rows of row_dw + 1 dwords (odd stride)
   uint32_t* my = srow + threadIdx.x * (a.row_dw + 1);
   constexpr int W = CAP / 2;
@@ -194,70 +192,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 
       f(x0 | (x1 << 16));
     }
   };
-  if (QUAD) {
-    for (uint32_t u = 0; u < a.table_count; u += 2) {
-      const bool second = u + 1 < a.table_count;
-      const uint32_t fA = (a.table_begin + u) * 2, fB = fA + 1;
-      const uint32_t fC = second ? fA + 2 : fA, fD = second ? fA + 3 : fB;
-      const uint32_t a2A = a.a2[fA], b2A = a.b2[fA], a2B = a.a2[fB], b2B = a.b2[fB];
-      const uint32_t a2C = a.a2[fC], b2C = a.b2[fC], a2D = a.a2[fD], b2D = a.b2[fD];
-      PairAcc<MINMAX> p, q;
-      p.init();
-      q.init();
+  // Functions of the launch's tables in order (table-major), four per pass:
+  // a table's key is complete after its last function's values are placed.
+  const uint32_t F0 = a.table_begin * a.fpt, Fn = F0 + a.table_count * a.fpt;
+  KeyBuilder kb{0ull, 0u};
+  for (uint32_t F = F0; F < Fn; F += 4) {
+    uint32_t f[4], a2[4], b2[4];
 #pragma unroll
-      for (int w = 0; w < W; ++w) asm volatile("" : "+v"(xs[w]));
+    for (int k = 0; k < 4; ++k) {
+      f[k] = min(F + k, Fn - 1);  // past the last function: a repeat, not placed
+      a2[k] = a.a2[f[k]];
+      b2[k] = a.b2[f[k]];
+    }
+    PairAcc<MINMAX> p, q;
+    p.init();
+    q.init();
+#pragma unroll
+    for (int w = 0; w < W; ++w) asm volatile("" : "+v"(xs[w]));
 #pragma clang loop unroll(full)
-      for (int w = 0; w < W; ++w) {
-        p.add(a2A, b2A, a2B, b2B, xs[w]);
-        q.add(a2C, b2C, a2D, b2D, xs[w]);
-      }
-      p.finish(a2A, b2A, a2B, b2B, a.dim, each_pair);
-      q.finish(a2C, b2C, a2D, b2D, a.dim, each_pair);
-      KeyBuilder kb{0ull, 0u};
-      kb.put(a, fA, p.mnA, i, u, live);
-      if (MINMAX) kb.put(a, fA, p.mxA, i, u, live);
-      kb.put(a, fB, p.mnB, i, u, live);
-      if (MINMAX) kb.put(a, fB, p.mxB, i, u, live);
-      store_table(a, kb.key, i, u, live, my);
-      flush_rows(a, u, srow);
-      if (second) {
-        KeyBuilder kc{0ull, 0u};
-        kc.put(a, fC, q.mnA, i, u + 1, live);
-        if (MINMAX) kc.put(a, fC, q.mxA, i, u + 1, live);
-        kc.put(a, fD, q.mnB, i, u + 1, live);
-        if (MINMAX) kc.put(a, fD, q.mxB, i, u + 1, live);
-        store_table(a, kc.key, i, u + 1, live, my);
-        flush_rows(a, u + 1, srow);
+    for (int w = 0; w < W; ++w) {
+      p.add(a2[0], b2[0], a2[1], b2[1], xs[w]);
+      q.add(a2[2], b2[2], a2[3], b2[3], xs[w]);
+    }
+    p.finish(a2[0], b2[0], a2[1], b2[1], a.dim, each_pair);
+    q.finish(a2[2], b2[2], a2[3], b2[3], a.dim, each_pair);
+    const uint32_t mn[4] = {p.mnA, p.mnB, q.mnA, q.mnB}, mx[4] = {p.mxA, p.mxB, q.mxA, q.mxB};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (F + k >= Fn) break;
+      const uint32_t u = (F + k - F0) / a.fpt;
+      kb.put(a, f[k], mn[k], i, u, live);
+      if (MINMAX) kb.put(a, f[k], mx[k], i, u, live);
+      if ((F + k + 1 - F0) % a.fpt == 0) {
+        store_table(a, kb.key, i, u, live, my);
+        flush_rows(a, u, srow);
+        kb = KeyBuilder{0ull, 0u};
       }
     }
-    return;
-  }
-  for (uint32_t u = 0; u < a.table_count; ++u) {
-    const uint32_t f0 = (a.table_begin + u) * a.fpt;
-    KeyBuilder kb{0ull, 0u};
-    for (uint32_t q = 0; q < a.fpt; q += 2) {
-      const uint32_t fA = f0 + q;
-      const bool two = q + 1 < a.fpt;
-      const uint32_t fB = two ? fA + 1 : fA;
-      const uint32_t a2A = a.a2[fA], b2A = a.b2[fA], a2B = a.a2[fB], b2B = a.b2[fB];
-      PairAcc<MINMAX> acc;
-      acc.init();
-      // Keep the indices packed: without this the compiler hoists the 16-bit
-      // unpacking out of the table loop and doubles the live registers.
-#pragma unroll
-      for (int w = 0; w < W; ++w) asm volatile("" : "+v"(xs[w]));
-#pragma unroll
-      for (int w = 0; w < W; ++w) acc.add(a2A, b2A, a2B, b2B, xs[w]);
-      acc.finish(a2A, b2A, a2B, b2B, a.dim, each_pair);
-      kb.put(a, fA, acc.mnA, i, u, live);
-      if (MINMAX) kb.put(a, fA, acc.mxA, i, u, live);
-      if (two) {
-        kb.put(a, fB, acc.mnB, i, u, live);
-        if (MINMAX) kb.put(a, fB, acc.mxB, i, u, live);
-      }
-    }
-    store_table(a, kb.key, i, u, live, my);
-    flush_rows(a, u, srow);
   }
 }
 
@@ -346,26 +317,18 @@ int sig_capacity_for(uint64_t max_len) {
   return 0;  // long-row kernel
 }
 
-template <bool MM, bool QUAD>
-static void launch_cap_q(int cap, dim3 g, dim3 b, size_t sm, hipStream_t s, const SigArgs& a) {
-  switch (cap) {
-    case 16: hipLaunchKernelGGL((k_sig<16, MM, QUAD>), g, b, sm, s, a); break;
-    case 32: hipLaunchKernelGGL((k_sig<32, MM, QUAD>), g, b, sm, s, a); break;
-    case 64: hipLaunchKernelGGL((k_sig<64, MM, QUAD>), g, b, sm, s, a); break;
-    case 128: hipLaunchKernelGGL((k_sig<128, MM, QUAD>), g, b, sm, s, a); break;
-    case 200: hipLaunchKernelGGL((k_sig<200, MM, QUAD>), g, b, sm, s, a); break;
-    case 256: hipLaunchKernelGGL((k_sig<256, MM, QUAD>), g, b, sm, s, a); break;
-    default: hipLaunchKernelGGL((k_sig_long<MM>), g, b, sm, s, a); break;
-  }
-}
-
 template <bool MM>
 static void launch_cap(int cap, dim3 g, dim3 b, hipStream_t s, const SigArgs& a) {
   const size_t sm = a.rows ? (size_t)256 * (a.row_dw + 1) * 4 : 0;
-  if (a.fpt == 2)
-    launch_cap_q<MM, true>(cap, g, b, sm, s, a);
-  else
-    launch_cap_q<MM, false>(cap, g, b, sm, s, a);
+  switch (cap) {
+    case 16: hipLaunchKernelGGL((k_sig<16, MM>), g, b, sm, s, a); break;
+    case 32: hipLaunchKernelGGL((k_sig<32, MM>), g, b, sm, s, a); break;
+    case 64: hipLaunchKernelGGL((k_sig<64, MM>), g, b, sm, s, a); break;
+    case 128: hipLaunchKernelGGL((k_sig<128, MM>), g, b, sm, s, a); break;
+    case 200: hipLaunchKernelGGL((k_sig<200, MM>), g, b, sm, s, a); break;
+    case 256: hipLaunchKernelGGL((k_sig<256, MM>), g, b, sm, s, a); break;
+    default: hipLaunchKernelGGL((k_sig_long<MM>), g, b, sm, s, a); break;
+  }
 }
 
 void launch_sig(int cap, bool minmax, const SigArgs& a, hipStream_t s) {
