@@ -137,8 +137,8 @@ __device__ __forceinline__ void flush_rows(const SigArgs& a, uint32_t u, const u
 // CAP: most indices a row may hold (rows shorter than CAP are padded with
 // their first index, which leaves every min and max unchanged).  Rows are
 // fixed-length with an even length and 4-byte aligned (other layouts take
-// k_sig_long).  Each pass over the register-resident row evaluates four
-// functions, so the 16-bit unpacking of an index pair is shared by four.
+// k_sig_long).  Each pass over the register-resident row evaluates eight
+// functions, so the 16-bit unpacking of an index pair is shared by eight.
 template <int CAP, bool MINMAX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 ? 3 : 1))) void k_sig(SigArgs a) {
   extern __shared__ uint32_t srow[];  // 256 rows of row_dw + 1 dwords (odd stride)
@@ -192,37 +192,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 
       f(x0 | (x1 << 16));
     }
   };
-  // Functions of the launch's tables in order (table-major), four per pass:
+  // Functions of the launch's tables in order (table-major), kPass per pass:
   // a table's key is complete after its last function's values are placed.
+  constexpr int kPass = 8;
   const uint32_t F0 = a.table_begin * a.fpt, Fn = F0 + a.table_count * a.fpt;
   KeyBuilder kb{0ull, 0u};
-  for (uint32_t F = F0; F < Fn; F += 4) {
-    uint32_t f[4], a2[4], b2[4];
+  for (uint32_t F = F0; F < Fn; F += kPass) {
+    uint32_t f[kPass], a2[kPass], b2[kPass];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kPass; ++k) {
       f[k] = min(F + k, Fn - 1);  // past the last function: a repeat, not placed
       a2[k] = a.a2[f[k]];
       b2[k] = a.b2[f[k]];
     }
-    PairAcc<MINMAX> p, q;
-    p.init();
-    q.init();
+    PairAcc<MINMAX> acc[kPass / 2];
+#pragma unroll
+    for (int k = 0; k < kPass / 2; ++k) acc[k].init();
 #pragma unroll
     for (int w = 0; w < W; ++w) asm volatile("" : "+v"(xs[w]));
 #pragma clang loop unroll(full)
     for (int w = 0; w < W; ++w) {
-      p.add(a2[0], b2[0], a2[1], b2[1], xs[w]);
-      q.add(a2[2], b2[2], a2[3], b2[3], xs[w]);
-    }
-    p.finish(a2[0], b2[0], a2[1], b2[1], a.dim, each_pair);
-    q.finish(a2[2], b2[2], a2[3], b2[3], a.dim, each_pair);
-    const uint32_t mn[4] = {p.mnA, p.mnB, q.mnA, q.mnB}, mx[4] = {p.mxA, p.mxB, q.mxA, q.mxB};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < kPass / 2; ++k) acc[k].add(a2[2 * k], b2[2 * k], a2[2 * k + 1], b2[2 * k + 1], xs[w]);
+    }
+#pragma unroll
+    for (int k = 0; k < kPass / 2; ++k)
+      acc[k].finish(a2[2 * k], b2[2 * k], a2[2 * k + 1], b2[2 * k + 1], a.dim, each_pair);
+#pragma unroll
+    for (int k = 0; k < kPass; ++k) {
       if (F + k >= Fn) break;
       const uint32_t u = (F + k - F0) / a.fpt;
-      kb.put(a, f[k], mn[k], i, u, live);
-      if (MINMAX) kb.put(a, f[k], mx[k], i, u, live);
+      const PairAcc<MINMAX>& c = acc[k / 2];
+      kb.put(a, f[k], (k & 1) ? c.mnB : c.mnA, i, u, live);
+      if (MINMAX) kb.put(a, f[k], (k & 1) ? c.mxB : c.mxA, i, u, live);
       if ((F + k + 1 - F0) % a.fpt == 0) {
         store_table(a, kb.key, i, u, live, my);
         flush_rows(a, u, srow);
