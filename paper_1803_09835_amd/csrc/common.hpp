@@ -178,6 +178,7 @@ struct BucketArgs {
   uint32_t bin_shift;    // bin = key >> bin_shift (64 - B)
   // occurrence filter: station of an id found from station_base (nstation+1 entries)
   const uint64_t* station_base;
+  const uint64_t* occ_max;  // per station: largest bucket within the threshold (all ones: no filter)
   uint32_t nstation;
   uint32_t occ_num, occ_den;
   uint32_t min_lag;      // buckets whose id span is below this yield no pair

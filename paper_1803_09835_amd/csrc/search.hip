@@ -30,6 +30,14 @@ struct Plan {
   uint32_t t, G, TG, row_dw, row_pitch, need;
 };
 
+// Occurrence filter (section 6.5): the largest bucket of a station of ns
+// fingerprints within the threshold, size * den <= ns * num, i.e.
+// floor(ns * num / den); all ones when no filter is set.
+uint64_t occ_bound(uint64_t ns, const fast_lsh_filter* flt) {
+  if (!flt->occ_den) return ~0ull;
+  return (uint64_t)(((unsigned __int128)ns * flt->occ_num) / flt->occ_den);
+}
+
 // Bits of the mixed key the radix passes bin on: a multiple of 8 large enough
 // that an average bin of the largest station holds at most about 4
 // elements, plus the four station bits when keys are tagged.
@@ -423,7 +431,8 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   RC(ws<uint32_t>(c, "hist", (uint64_t)256 * nt_max * t, &j.hist));
   RC(ws<uint32_t>(c, "sums", scan_sums_elems((uint64_t)256 * nt_max, j.t), &j.sums));
   RC(ws<uint8_t>(c, "flags", N, &j.flags));
-  RC(ws<uint64_t>(c, "station_base", S + 1, &j.sbase));
+  // station bases (S + 1) and each station's occurrence bound (S)
+  RC(ws<uint64_t>(c, "station_base", 2 * S + 1, &j.sbase));
   // Buckets of at most smax members are marked in place and handled by the
   // wave-per-chunk pair kernel; larger ones go to the tiled kernel.
   const uint32_t smax = kSmallBucket;
@@ -435,13 +444,18 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   j.bigbin_grid = (uint32_t)std::min<uint64_t>(cap_bin, 512);
   j.rswl = j.pl.row_dw | 1u;
   uint64_t out_cap = std::max<uint64_t>(1u << 20, N / 8);
-  RC(h2d(c, j.sbase, j.base.data(), S + 1));
+  {
+    std::vector<uint64_t> hb(j.base);
+    for (uint32_t st = 0; st < S; ++st) hb.push_back(occ_bound(j.base[st + 1] - j.base[st], flt));
+    RC(h2d(c, j.sbase, hb.data(), 2 * S + 1));
+  }
 
   BucketArgs& ba = j.ba;
   memset(&ba, 0, sizeof ba);
   ba.n = N;
   ba.bin_shift = 64 - j.B;
   ba.station_base = j.sbase;
+  ba.occ_max = j.sbase + S + 1;
   ba.nstation = S;
   ba.occ_num = flt->occ_num;
   ba.occ_den = flt->occ_den;
@@ -634,7 +648,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_pitch, &j.rows));
   RC(ws<uint32_t>(c, "hi32", (uint64_t)t * N, &hi32));
   RC(ws<uint8_t>(c, "flags", N, &j.flags));
-  RC(ws<uint64_t>(c, "station_base", 2, &j.sbase));
+  RC(ws<uint64_t>(c, "station_base", 3, &j.sbase));  // bases, occurrence bound
   RC(ws<uint64_t>(c, "ak", gn, &j.ak));
   RC(ws<uint32_t>(c, "av", gn, &j.av));
   RC(ws<uint64_t>(c, "bk", gn, &j.bk));  // also receives each group's mixed keys
@@ -652,13 +666,17 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   j.bigbin_grid = (uint32_t)std::min<uint64_t>(cap_bin, 512);
   j.rswl = j.pl.row_dw | 1u;
   uint64_t out_cap = std::max<uint64_t>(1u << 20, N / 8);
-  RC(h2d(c, j.sbase, j.base.data(), 2));
+  {
+    const uint64_t hb[3] = {j.base[0], j.base[1], occ_bound(j.base[1] - j.base[0], flt)};
+    RC(h2d(c, j.sbase, hb, 3));
+  }
 
   BucketArgs& ba = j.ba;
   memset(&ba, 0, sizeof ba);
   ba.n = N;
   ba.bin_shift = 64 - j.B;
   ba.station_base = j.sbase;
+  ba.occ_max = j.sbase + 2;
   ba.nstation = 1;
   ba.occ_num = flt->occ_num;
   ba.occ_den = flt->occ_den;

@@ -325,8 +325,13 @@ struct BucketTotals {
   unsigned long long e_raw;
   unsigned int max_bucket;
   uint32_t station;
-  uint32_t ns;  // fingerprints of `station`
+  uint64_t occ_max;  // largest bucket of `station` within the occurrence threshold
 };
+
+// Occurrence filter (section 6.5): a bucket of `size` members is over the
+// threshold of its station (fingerprint count ns) when size / ns > num / den,
+// that is size * den > ns * num, which for an integer size is
+// size > floor(ns * num / den) = occ_max[station] (computed on the host).
 
 // Called by every lane of the wave.  When all lanes that accounted a bucket
 // hold one station the totals are reduced over the wave first; at a station
@@ -356,22 +361,20 @@ __device__ void flush_totals(const BucketArgs& a, BucketTotals tot) {
   }
 }
 
-// Occurrence filter (section 6.5): a bucket of `size` members is over the
-// threshold of its station (fingerprint count ns) when size / ns > num / den.
-// The station's count is looked up when the station changes (a lane's keys
+// The station's bound is recomputed when the station changes (a lane's keys
 // change station only at station boundaries of the sorted order).
 struct OccCache {
   uint32_t st = kNoStation;
-  uint64_t ns = 0;
+  uint64_t occ_max = 0;
 };
 __device__ __forceinline__ bool bucket_over(const BucketArgs& a, uint64_t size, uint64_t key, OccCache& oc) {
   if (!a.occ_den) return false;
   const uint32_t st = a.nstation > 1 ? (uint32_t)(key >> 60) : 0u;
   if (st != oc.st) {
     oc.st = st;
-    oc.ns = a.station_base[st + 1] - a.station_base[st];
+    oc.occ_max = a.occ_max[st];
   }
-  return (unsigned __int128)size * a.occ_den > (unsigned __int128)oc.ns * a.occ_num;
+  return size > oc.occ_max;
 }
 
 // Counters of one bucket (this lane heads it) and its descriptor class:
@@ -389,11 +392,11 @@ __device__ __forceinline__ int head_account(const BucketArgs& a, uint64_t size, 
     tot.e_raw = 0;
     tot.max_bucket = 0;
     tot.station = st;
-    tot.ns = (uint32_t)(a.station_base[st + 1] - a.station_base[st]);
+    tot.occ_max = a.occ_max[st];
   }
   tot.e_raw += (unsigned long long)(size * (size - 1) / 2);
   if (size > tot.max_bucket) tot.max_bucket = (unsigned int)size;
-  if (a.occ_den && (unsigned __int128)size * a.occ_den > (unsigned __int128)tot.ns * a.occ_num) return 0;
+  if (size > tot.occ_max) return 0;
   if (size < 2 || last_id - first_id < a.min_lag) return 0;
   return size <= a.small_max ? 1 : 2;
 }
