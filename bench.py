@@ -87,8 +87,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md, "
-                                   "not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "fast_lsh searches on one GPU; sharding a search over several GPUs is not "
+                                   "implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "bounded":
         return main_bounded(args)
@@ -99,7 +99,7 @@ def main():
         # first seconds (while generating the 12 stations from 12 host threads),
         # once in three runs; the cause is not known, so it stays switched off.
         print(json.dumps({"error": "the batched workload mode is switched off: its process crashed on the host "
-                                   "during data generation and the cause is not yet known (see DESIGN.md)",
+                                   "during data generation and the cause is not yet known",
                           "workload": "batched"}))
         sys.exit(2)
 
