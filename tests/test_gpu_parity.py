@@ -77,6 +77,10 @@ SIG_CASES = [
     ("dim16-r3", lambda: _fixed(300, 16, 6, 18), 16, 9, 3, fl.MINHASH),
     ("dim65536-r4-full64", lambda: _fixed(300, 65536, 64, 19), 65536, 7, 4, fl.MINMAX),
     ("dim8192-r8-chained", lambda: _fixed(300, 8192, 128, 20), 8192, 6, 8, fl.MINMAX),
+    # eight functions per pass over a row: one function per table, and three
+    # (passes that end inside a table)
+    ("minhash-r1", lambda: _fixed(500, 4096, 200, 25), 4096, 13, 1, fl.MINHASH),
+    ("minmax-r6-chained", lambda: _fixed(400, 4096, 200, 26), 4096, 7, 6, fl.MINMAX),
 ]
 
 
@@ -180,6 +184,20 @@ def _compare(ctx, rows, dim, t, r, scheme, seed, L, v, num=0, den=0, distinct=Fa
         want.pop("n_distinct")
     assert got == want
     return gst
+
+
+@pytest.mark.parametrize("n,num,den,keep,drop", [(1000, 1, 100, 10, 11), (1050, 1, 100, 10, 11),
+                                                 (1000, 3, 1000, 3, 4)])
+def test_search_occurrence_bound(ctx, n, num, den, keep, drop):
+    """Section 6.5: a bucket is excluded when its members exceed num / den of
+    the fingerprints.  `keep` identical fingerprints (a bucket of that size in
+    every table, exactly floor(n num / den)) stay; `drop` identical ones go."""
+    rows = _fixed(n, 4096, 200, 27 + n + num)
+    rows[100:100 + keep] = rows[100]
+    rows[500:500 + drop] = rows[500]
+    st = _compare(ctx, rows, 4096, 20, 4, fl.MINMAX, 28, 1, 4, num, den, label=f"occ-bound-{n}-{num}/{den}")
+    assert st.n_flagged == drop
+    assert st.n_out >= keep * (keep - 1) // 2
 
 
 def test_search_tiny_uniform_full(ctx):
