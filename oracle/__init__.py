@@ -15,6 +15,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import threading
 from dataclasses import dataclass
 
 import numpy as np
@@ -40,14 +41,21 @@ class _Stats(ctypes.Structure):
 
 
 _LIB = None
+_LOCK = threading.Lock()
 _vp, _u32, _u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
 
 
 def _lib():
     global _LIB
-    if _LIB is None:
+    if _LIB is not None:
+        return _LIB
+    with _LOCK:
+        if _LIB is not None:
+            return _LIB
         if not os.path.exists(_SO):
-            build()
+            # Compiled only by build() (or __graft_entry__.build()), never
+            # here: a process may already hold the GPU when it first calls in.
+            raise RuntimeError(f"{_SO} is not built; run __graft_entry__.build() first")
         lib = ctypes.CDLL(_SO)
         lib.orc_splitmix64_stream.argtypes = [_u64, _u32, _vp]
         lib.orc_make_hash.argtypes = [_u64, _u32, _vp, _vp]
@@ -57,6 +65,7 @@ def _lib():
         lib.orc_key_bits.restype = _u32
         lib.orc_band_key.argtypes = [_vp, _u32, _u32]
         lib.orc_band_key.restype = _u64
+        lib.orc_band_keys.argtypes = [_u64, _vp, _u32, _u32, _vp]
         lib.orc_signatures.argtypes = [_u32, _u32, _u32, _u32, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp]
         lib.orc_signatures.restype = ctypes.c_int
         lib.orc_search_keys.argtypes = [_u32, _u64, _vp, _u32, _u32, _u32, _u32,
@@ -109,6 +118,15 @@ def key_bits(dim: int) -> int:
 def band_key(argx, dim: int) -> int:
     arr = np.ascontiguousarray(argx, dtype=np.uint32)
     return int(_lib().orc_band_key(arr.ctypes.data, len(arr), dim))
+
+
+def band_keys(argx, dim: int) -> np.ndarray:
+    """band_key of every row of a uint32[n, r] array of attaining indices."""
+    arr = np.ascontiguousarray(argx, dtype=np.uint32)
+    n, r = arr.shape
+    out = np.empty(n, dtype=np.uint64)
+    _lib().orc_band_keys(n, arr.ctypes.data, r, dim, out.ctypes.data)
+    return out
 
 
 def _rows(rows):

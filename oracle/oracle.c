@@ -107,6 +107,11 @@ uint64_t orc_band_key(const uint32_t *argx, uint32_t r, uint32_t dim) {
   return k;
 }
 
+/* orc_band_key applied to n tuples of r indices each (row-major argx[n][r]). */
+void orc_band_keys(uint64_t n, const uint32_t *argx, uint32_t r, uint32_t dim, uint64_t *keys) {
+  for (uint64_t i = 0; i < n; ++i) keys[i] = orc_band_key(argx + i * r, r, dim);
+}
+
 /* Signature of one fingerprint for one table: the r values (MinHash: the
  * min over the set of r functions; Min-Max: min and max of r/2 functions)
  * and the element index attaining each of them. */

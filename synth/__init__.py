@@ -20,6 +20,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import threading
 from dataclasses import dataclass, replace
 
 import numpy as np
@@ -57,13 +58,20 @@ class _Spec(ctypes.Structure):
 
 
 _LIB = None
+_LOCK = threading.Lock()
 
 
 def _lib():
     global _LIB
-    if _LIB is None:
+    if _LIB is not None:
+        return _LIB
+    with _LOCK:
+        if _LIB is not None:
+            return _LIB
         if not os.path.exists(_SO):
-            build()
+            # Compiled only by build() (or __graft_entry__.build()), never
+            # here: a process may already hold the GPU when it first calls in.
+            raise RuntimeError(f"{_SO} is not built; run __graft_entry__.build() first")
         lib = ctypes.CDLL(_SO)
         lib.synth_generate_range.argtypes = [ctypes.POINTER(_Spec), ctypes.c_uint64, ctypes.c_uint64,
                                              ctypes.c_void_p, ctypes.c_void_p]
@@ -110,6 +118,8 @@ def generate(spec: Spec, lo: int = 0, hi: int | None = None, labels: bool = Fals
     c = spec._c()
     rc = _lib().synth_generate_range(ctypes.byref(c), lo, hi, rows.ctypes.data,
                                      lab.ctypes.data if labels else None)
+    if rc == 3:
+        raise MemoryError(f"synth: a host allocation failed while generating rows [{lo}, {hi}) of {spec}")
     if rc != 0:
         raise ValueError(f"synth: invalid spec {spec} (code {rc})")
     return (rows, lab) if labels else rows

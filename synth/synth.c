@@ -133,24 +133,31 @@ static void keep_subset(rng_t *r, const uint16_t *src, uint32_t k, uint32_t keep
 
 /* Copy of a template keeping `keep` template bits; the rest are drawn from
  * outside the template, so |copy ∩ template| = keep exactly. */
-static void make_copy(rng_t *r, uint32_t d, uint32_t k, const uint16_t *tpl, uint32_t keep, uint16_t *out) {
+static int make_copy(rng_t *r, uint32_t d, uint32_t k, const uint16_t *tpl, uint32_t keep, uint16_t *out) {
   uint32_t words = (d + 63) / 64;
   uint64_t *excl = (uint64_t *)calloc(words, 8);
   uint64_t *cur = (uint64_t *)calloc(words, 8);
   uint16_t *scratch = (uint16_t *)malloc(k * sizeof(uint16_t));
+  if (!excl || !cur || !scratch) {
+    free(excl); free(cur); free(scratch);
+    return 1;
+  }
   for (uint32_t q = 0; q < k; ++q) bm_set(excl, tpl[q]);
   keep_subset(r, tpl, k, keep, scratch, cur);
   draw_outside(r, d, k - keep, excl, cur);
   bm_emit(cur, words, out);
   free(excl); free(cur); free(scratch);
+  return 0;
 }
 
-static void uniform_row(rng_t *r, uint32_t d, uint32_t k, uint16_t *out) {
+static int uniform_row(rng_t *r, uint32_t d, uint32_t k, uint16_t *out) {
   uint32_t words = (d + 63) / 64;
   uint64_t *bm = (uint64_t *)calloc(words, 8);
+  if (!bm) return 1;
   floyd(r, d, k, bm);
   bm_emit(bm, words, out);
   free(bm);
+  return 0;
 }
 
 int synth_check(const synth_spec *sp) {
@@ -179,18 +186,24 @@ uint64_t synth_planted_count(const synth_spec *sp) {
 
 /* Fill rows [lo, hi) of the data set described by `sp` into out[(hi-lo)][nnz]
  * and, when `label` is non-NULL, label[(hi-lo)] with -1 (background), the
- * source id (planted copy) or -2 (noise copy).  Returns 0 on success. */
+ * source id (planted copy) or -2 (noise copy).  Returns 0 on success, 1 for
+ * an invalid spec or range, 2 when the planted rows exceed half the slots,
+ * 3 when a host allocation fails. */
 int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_t *out, int32_t *label) {
-  if (synth_check(sp) || lo > hi || hi > sp->n) return 1;
+  if (synth_check(sp) || lo > hi || hi > sp->n || (!out && hi > lo)) return 1;
   const uint32_t d = sp->dim, k = sp->nnz, words = (d + 63) / 64;
   const uint64_t cnt = hi - lo;
+  int oom = 0; /* set by any thread whose allocation failed */
 
   /* 1. background */
   if (sp->markov_keep == 0) {
 #pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < (int64_t)cnt; ++q) {
       rng_t r = stream_for(sp->seed, TAG_BG, lo + (uint64_t)q);
-      uniform_row(&r, d, k, out + (uint64_t)q * k);
+      if (uniform_row(&r, d, k, out + (uint64_t)q * k)) {
+#pragma omp atomic write
+        oom = 1;
+      }
     }
   } else {
     /* chains: one over all rows, or independent chains of chain_len rows
@@ -207,7 +220,12 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
       uint64_t *bm = (uint64_t *)calloc(words, 8);
       const uint64_t start = (uint64_t)c * clen;
       const uint64_t stop = start + clen < hi ? start + clen : hi;
-      uniform_row(&r, d, k, prev);
+      if (!prev || !cur || !scratch || !excl || !bm || uniform_row(&r, d, k, prev)) {
+        free(prev); free(cur); free(scratch); free(excl); free(bm);
+#pragma omp atomic write
+        oom = 1;
+        continue;
+      }
       for (uint64_t i = start; i < stop; ++i) {
         if (i > start) {
           memset(excl, 0, words * 8);
@@ -223,6 +241,7 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
       free(prev); free(cur); free(scratch); free(excl); free(bm);
     }
   }
+  if (oom) return 3;
   if (label)
     for (uint64_t q = 0; q < cnt; ++q) label[q] = -1;
 
@@ -236,6 +255,11 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
   uint64_t *slot = (uint64_t *)malloc(total * 8);
   int32_t *who = (int32_t *)malloc(total * 4);
   uint32_t *keep = (uint32_t *)malloc(total * 4);
+  uint16_t *tpl = (uint16_t *)malloc(((uint64_t)sp->n_sources + 1) * k * sizeof(uint16_t));
+  if (!used || !slot || !who || !keep || !tpl) {
+    free(used); free(slot); free(who); free(keep); free(tpl);
+    return 3;
+  }
   rng_t rs = stream_for(sp->seed, TAG_SLOT, 0);
   uint64_t m = 0;
   for (uint32_t s = 0; s < sp->n_sources; ++s) {
@@ -266,14 +290,13 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
   }
 
   /* 3. copy content, keyed by slot */
-  uint16_t *tpl = (uint16_t *)malloc(((uint64_t)sp->n_sources + 1) * k * sizeof(uint16_t));
   for (uint32_t s = 0; s < sp->n_sources; ++s) {
     rng_t rt = stream_for(sp->seed, TAG_TPL, s);
-    uniform_row(&rt, d, k, tpl + (uint64_t)s * k);
+    oom |= uniform_row(&rt, d, k, tpl + (uint64_t)s * k);
   }
   {
     rng_t rt = stream_for(sp->seed, TAG_NOISE, 0);
-    uniform_row(&rt, d, k, tpl + (uint64_t)sp->n_sources * k);
+    oom |= uniform_row(&rt, d, k, tpl + (uint64_t)sp->n_sources * k);
   }
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t q = 0; q < (int64_t)m; ++q) {
@@ -281,11 +304,14 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
     if (x < lo || x >= hi) continue;
     rng_t rc = stream_for(sp->seed, TAG_COPY, x);
     const uint16_t *t = tpl + (uint64_t)(who[q] >= 0 ? (uint32_t)who[q] : sp->n_sources) * k;
-    make_copy(&rc, d, k, t, keep[q], out + (x - lo) * k);
+    if (make_copy(&rc, d, k, t, keep[q], out + (x - lo) * k)) {
+#pragma omp atomic write
+      oom = 1;
+    }
     if (label) label[x - lo] = who[q];
   }
   free(used); free(slot); free(who); free(keep); free(tpl);
-  return 0;
+  return oom ? 3 : 0;
 }
 
 int synth_generate(const synth_spec *sp, uint16_t *out, int32_t *label) {

@@ -27,6 +27,28 @@ def test_splitmix64_published_values():
     assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
 
 
+def test_make_hash_known_answer():
+    # Function f draws a from output 2f and b from output 2f+1 of splitmix64
+    # seeded with the seed.  Seed 0's outputs (the published reference
+    # generator): 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F,
+    # 0xF88BB8A8724C81EC.  Worked out by hand:
+    #   a[0] = 1 + 0xE220A8397B1DCDAF mod (2^31 - 2) = 60845732
+    #   b[0] =     0x6E789E6AA1B965F4 mod (2^31 - 1) = 2125112010
+    #   a[1] = 1 + 0x06C45D188009454F mod (2^31 - 2) = 454736306
+    #   b[1] =     0xF88BB8A8724C81EC mod (2^31 - 1) = 1667494720
+    # A swapped draw order, a wrong modulus or a missing "+1" changes them.
+    out = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    assert [1 + out[0] % (P - 1), out[1] % P, 1 + out[2] % (P - 1), out[3] % P] == \
+        [60845732, 2125112010, 454736306, 1667494720]
+    assert [int(x) for x in oracle.splitmix64_stream(0, 4)] == out
+    a, b = oracle.make_hash(0, 2)
+    assert [int(x) for x in a] == [60845732, 454736306]
+    assert [int(x) for x in b] == [2125112010, 1667494720]
+    # Prefix property: the first functions do not depend on how many are drawn.
+    a5, b5 = oracle.make_hash(0, 5)
+    assert (a5[:2] == a).all() and (b5[:2] == b).all()
+
+
 def test_make_hash_ranges_and_determinism():
     a, b = oracle.make_hash(202, 5000)
     assert a.min() >= 1 and a.max() <= P - 1
@@ -343,3 +365,90 @@ def test_votes_equal_definition_on_outputs():
     # Output is sorted by (i, j) and unique.
     code = oi.astype(np.uint64) << np.uint64(32) | oj.astype(np.uint64)
     assert (np.diff(code.astype(np.int64)) > 0).all()
+
+
+# ---------------------------------------------------------------------------
+# The chained band key (ceil(log2 d) * r > 64)
+# ---------------------------------------------------------------------------
+def _partition_equal(a_labels, b_labels):
+    """The two labellings induce the same partition of the items."""
+    na = len(np.unique(a_labels))
+    nb = len(np.unique(b_labels))
+    joint = len(np.unique(np.stack([a_labels, b_labels], axis=1), axis=0))
+    return na == nb == joint
+
+
+@pytest.mark.parametrize("dim,r", [(8192, 8), (4096, 6)])
+def test_chained_key_equality_is_tuple_equality(dim, r):
+    # Above 64 packed bits the key is a chain of 64-bit mixes of the indices.
+    # Equal index tuples must give equal keys and distinct tuples distinct
+    # keys (a 64-bit collision among 1.3e6 tuples has probability ~5e-8).
+    # Near neighbours differ in one coordinate by one (a chain that skipped a
+    # coordinate or ignored the last one would collide on them) and exact
+    # duplicates are included.
+    assert oracle.key_bits(dim) * r > 64
+    rng = np.random.default_rng(dim + r)
+    n = 1_000_000
+    tup = rng.integers(0, dim, (n, r), dtype=np.uint32)
+    k = 200_000
+    src = rng.integers(0, n, k)
+    pos = rng.integers(0, r, k)
+    near = tup[src].copy()
+    near[np.arange(k), pos] = (near[np.arange(k), pos] + 1) % dim
+    first = tup[rng.integers(0, n, 50_000)].copy()  # differ only in the first or last coordinate
+    first[:, 0] = (first[:, 0] + 7) % dim
+    last = tup[rng.integers(0, n, 50_000)].copy()
+    last[:, -1] = (last[:, -1] + 7) % dim
+    dup = tup[rng.integers(0, n, 50_000)]
+    allt = np.concatenate([tup, near, first, last, dup])
+    keys = oracle.band_keys(allt, dim)
+    _, tlab = np.unique(allt, axis=0, return_inverse=True)
+    _, klab = np.unique(keys, return_inverse=True)
+    assert _partition_equal(tlab.ravel(), klab.ravel())
+
+
+def test_chained_key_on_planted_pairs():
+    # Through the whole signature path with chained keys (d = 4096, r = 6,
+    # 72 packed bits): for every pair of copies of one planted source and for
+    # neighbouring fingerprints of a Markov slice, the keys of a table are
+    # equal exactly when the six hash values are (the hash is injective on
+    # [0, d), so equal values mean equal attaining indices).
+    t, r, dim = 12, 6, 4096
+    for scheme in (oracle.MINHASH, oracle.MINMAX):
+        a, b = oracle.make_hash(77, oracle.n_funcs(t, r, scheme))
+        rows, lab = synth.generate(synth.tiny_uniform(n=4000, seed=78), labels=True)
+        mk = synth.generate(synth.station(n=1500, seed=79))
+        for data, pairs in ((rows, None), (mk, None)):
+            keys, vals = oracle.signatures(data, dim, t, r, scheme, a, b, with_values=True)
+            if data is rows:
+                pairs = [(i, j) for src in np.unique(lab[lab >= 0])
+                         for q, i in enumerate(np.nonzero(lab == src)[0]) for j in np.nonzero(lab == src)[0][q + 1:]]
+            else:
+                pairs = [(i, i + d) for i in range(len(data) - 3) for d in (1, 2, 3)]
+            n_equal = 0
+            for i, j in pairs:
+                same_vals = (vals[i] == vals[j]).all(axis=1)
+                same_keys = keys[:, i] == keys[:, j]
+                assert (same_vals == same_keys).all()
+                n_equal += int(same_keys.sum())
+            assert n_equal > 0  # the planted and neighbouring pairs do share tables
+
+
+def test_packed_key_used_up_to_64_bits():
+    # ceil(log2 d) * r <= 64: the key is the packed indices, row s at bit b*s
+    # (64 bits exactly at d = 65536, r = 4; 60 bits at d = 4096, r = 5).
+    # One bit more (d = 4096, r = 6) switches to the chain.
+    rng = np.random.default_rng(5)
+    for dim, r in ((65536, 4), (4096, 5), (2, 64)):
+        b = oracle.key_bits(dim)
+        assert b * r <= 64
+        tup = rng.integers(0, dim, (1000, r), dtype=np.uint64)
+        want = np.zeros(1000, np.uint64)
+        for s_ in range(r):
+            want |= tup[:, s_] << np.uint64(b * s_)
+        assert (oracle.band_keys(tup.astype(np.uint32), dim) == want).all()
+    tup = rng.integers(0, 4096, (1000, 6), dtype=np.uint64)
+    packed_low = np.zeros(1000, np.uint64)
+    for s_ in range(5):
+        packed_low |= tup[:, s_] << np.uint64(12 * s_)
+    assert (oracle.band_keys(tup.astype(np.uint32), 4096) != packed_low).mean() > 0.99
