@@ -68,10 +68,16 @@ def _lib():
         lib.orc_band_keys.argtypes = [_u64, _vp, _u32, _u32, _vp]
         lib.orc_signatures.argtypes = [_u32, _u32, _u32, _u32, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp]
         lib.orc_signatures.restype = ctypes.c_int
-        lib.orc_search_keys.argtypes = [_u32, _u64, _vp, _u32, _u32, _u32, _u32,
+        lib.orc_search_keys.argtypes = [_u32, _u64, _vp, _u32, _u32, _u32, _u32, _u32,
                                         ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                         ctypes.POINTER(_Stats), _vp]
         lib.orc_search_keys.restype = ctypes.c_int
+        lib.orc_table_scan.argtypes = [_u64, _vp, _u32, _u32, _vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
+                                       _u32, _u32, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_u64)]
+        lib.orc_table_scan.restype = ctypes.c_int
+        lib.orc_count_votes.argtypes = [_vp, _u64, _vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                        ctypes.POINTER(_vp), ctypes.POINTER(_Stats)]
+        lib.orc_count_votes.restype = ctypes.c_int
         lib.orc_pair_votes.argtypes = [_u32, _u64, _vp, _u64, _u64]
         lib.orc_pair_votes.restype = _u32
         lib.orc_free.argtypes = [_vp]
@@ -155,27 +161,91 @@ def signatures(rows, dim: int, t: int, r: int, scheme: int, a, b, with_values: b
     return (keys, sigs) if with_values else keys
 
 
+def _take_triplets(pi, pj, pv, m):
+    cast = lambda p, ct: np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ct)), (m,)).copy()
+    oi = cast(pi, ctypes.c_uint32) if m else np.empty(0, np.uint32)
+    oj = cast(pj, ctypes.c_uint32) if m else np.empty(0, np.uint32)
+    ov = cast(pv, ctypes.c_uint8) if m else np.empty(0, np.uint8)
+    for p in (pi, pj, pv):
+        _lib().orc_free(p)
+    return oi, oj, ov
+
+
 def search_keys(keys: np.ndarray, min_lag: int, min_votes: int, occ_num: int = 0, occ_den: int = 0,
-                want_flags: bool = False):
-    """(i, j, votes, Stats[, flags]) from table-major band keys uint64[t, n]."""
+                want_flags: bool = False, parts: int = 1):
+    """(i, j, votes, Stats[, flags]) from table-major band keys uint64[t, n];
+    ``parts`` vote partitions (ranges of i) are counted one after another."""
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
     t, n = keys.shape
     pi, pj, pv = _vp(), _vp(), _vp()
     st = _Stats()
     flags = np.empty(n, dtype=np.uint8) if want_flags else None
-    rc = _lib().orc_search_keys(t, n, keys.ctypes.data, min_lag, min_votes, occ_num, occ_den,
+    rc = _lib().orc_search_keys(t, n, keys.ctypes.data, min_lag, min_votes, occ_num, occ_den, parts,
                                 ctypes.byref(pi), ctypes.byref(pj), ctypes.byref(pv), ctypes.byref(st),
                                 flags.ctypes.data if want_flags else None)
+    if rc == 2:
+        raise MemoryError("oracle: out of host memory")
     if rc != 0:
         raise ValueError("oracle: invalid search parameters")
-    m = st.n_out
-    oi = np.ctypeslib.as_array(ctypes.cast(pi, ctypes.POINTER(ctypes.c_uint32)), (m,)).copy() if m else np.empty(0, np.uint32)
-    oj = np.ctypeslib.as_array(ctypes.cast(pj, ctypes.POINTER(ctypes.c_uint32)), (m,)).copy() if m else np.empty(0, np.uint32)
-    ov = np.ctypeslib.as_array(ctypes.cast(pv, ctypes.POINTER(ctypes.c_uint8)), (m,)).copy() if m else np.empty(0, np.uint8)
-    for p in (pi, pj, pv):
-        _lib().orc_free(p)
+    oi, oj, ov = _take_triplets(pi, pj, pv, st.n_out)
     stats = Stats(*[int(getattr(st, f)) for f, _ in _Stats._fields_])
     return (oi, oj, ov, stats, flags) if want_flags else (oi, oj, ov, stats)
+
+
+class TableScan:
+    """A search taken one table at a time (keys of one table in memory at
+    once): ``add_table`` sorts a table, accumulates its bucket counters and
+    exclusions and collects its candidate pairs whose i lies in ``ranges``;
+    ``result`` counts the votes of the collected pairs."""
+
+    def __init__(self, n: int, occ_num: int, occ_den: int, min_lag: int, ranges):
+        self.n, self.occ_num, self.occ_den, self.min_lag = n, occ_num, occ_den, min_lag
+        self.ranges = np.ascontiguousarray(np.asarray(ranges, dtype=np.uint64).reshape(-1))
+        self.flags = np.zeros(max(n, 1), dtype=np.uint8)
+        self.e_raw = _u64(0)
+        self.max_bucket = _u64(0)
+        self._pairs = _vp()
+        self._cnt = _u64(0)
+        self.tables = 0
+
+    def add_table(self, keys_u: np.ndarray):
+        keys_u = np.ascontiguousarray(keys_u, dtype=np.uint64)
+        assert keys_u.shape == (self.n,)
+        rc = _lib().orc_table_scan(self.n, keys_u.ctypes.data, self.occ_num, self.occ_den, self.flags.ctypes.data,
+                                   ctypes.byref(self.e_raw), ctypes.byref(self.max_bucket), self.min_lag,
+                                   len(self.ranges) // 2, self.ranges.ctypes.data, ctypes.byref(self._pairs),
+                                   ctypes.byref(self._cnt))
+        if rc != 0:
+            raise MemoryError("oracle: out of host memory")
+        self.tables += 1
+
+    @property
+    def pairs_collected(self) -> int:
+        return int(self._cnt.value)
+
+    def result(self, min_votes: int):
+        """(i, j, votes, Stats) of the collected ranges; e_raw, max_bucket and
+        n_flagged are those of the whole search."""
+        pi, pj, pv = _vp(), _vp(), _vp()
+        st = _Stats()
+        rc = _lib().orc_count_votes(self._pairs, self._cnt.value, self.flags.ctypes.data, min_votes,
+                                    ctypes.byref(pi), ctypes.byref(pj), ctypes.byref(pv), ctypes.byref(st))
+        if rc != 0:
+            raise MemoryError("oracle: out of host memory")
+        oi, oj, ov = _take_triplets(pi, pj, pv, st.n_out)
+        stats = Stats(n_out=int(st.n_out), e_raw=int(self.e_raw.value), e_voted=int(st.e_voted),
+                      n_distinct=int(st.n_distinct), n_flagged=int(self.flags[:self.n].sum()),
+                      max_bucket=int(self.max_bucket.value))
+        return oi, oj, ov, stats
+
+    def close(self):
+        if self._pairs:
+            _lib().orc_free(self._pairs)
+            self._pairs = _vp()
+            self._cnt = _u64(0)
+
+    def __del__(self):
+        self.close()
 
 
 def search(rows, dim: int, t: int, r: int, scheme: int, a, b, min_lag: int, min_votes: int,

@@ -196,95 +196,211 @@ static int cmp_u64(const void *x, const void *y) {
   return p < q ? -1 : (p > q ? 1 : 0);
 }
 
-/* Search from precomputed band keys (table-major, keys[u*n + i]).
- * On success *out_pairs holds n_out triplets as (i, j, votes) packed into
- * three arrays allocated with malloc (caller frees with orc_free). */
-int orc_search_keys(uint32_t t, uint64_t n, const uint64_t *keys, uint32_t min_lag, uint32_t min_votes,
-                    uint32_t occ_num, uint32_t occ_den, uint32_t **out_i, uint32_t **out_j, uint8_t **out_v,
-                    orc_stats *st, uint8_t *flags_out) {
-  memset(st, 0, sizeof(*st));
-  *out_i = NULL; *out_j = NULL; *out_v = NULL;
-  if (t == 0 || t > 255 || min_votes == 0 || n >= (1ull << 31)) return 1;
+/* One hash table (section 6.1 "Hash table construction"): the n fingerprints
+ * as (band key, id) sorted by key, then id, so that each bucket's members
+ * are adjacent with ids ascending. */
+static void orc_table_sort(uint64_t n, const uint64_t *keys_u, orc_kv *tab) {
+  for (uint64_t i = 0; i < n; ++i) { tab[i].key = keys_u[i]; tab[i].id = i; }
+  qsort(tab, n, sizeof(orc_kv), cmp_kv);
+}
 
-  /* Hash tables: for each table, fingerprints grouped by band key.  Sorting
-   * (key, id) pairs places each bucket's members next to each other with
-   * ids ascending. */
-  orc_kv **tab = (orc_kv **)malloc(t * sizeof(orc_kv *));
-  for (uint32_t u = 0; u < t; ++u) {
-    tab[u] = (orc_kv *)malloc((n ? n : 1) * sizeof(orc_kv));
-    for (uint64_t i = 0; i < n; ++i) { tab[u][i].key = keys[(uint64_t)u * n + i]; tab[u][i].id = i; }
+/* Bucket sizes of one sorted table: adds C(size, 2) of every bucket to
+ * *e_raw, raises *max_bucket to the largest size, and (occurrence filter,
+ * section 6.5) sets flag[id] for every member of a bucket whose size
+ * exceeds occ_num/occ_den of the n fingerprints (occ_den == 0: no filter). */
+static void orc_table_buckets(uint64_t n, const orc_kv *tab, uint32_t occ_num, uint32_t occ_den, uint8_t *flag,
+                              uint64_t *e_raw, uint64_t *max_bucket) {
+  uint64_t s = 0;
+  while (s < n) {
+    uint64_t e = s + 1;
+    while (e < n && tab[e].key == tab[s].key) ++e;
+    uint64_t size = e - s;
+    *e_raw += size * (size - 1) / 2;
+    if (size > *max_bucket) *max_bucket = size;
+    if (occ_den && (unsigned __int128)size * occ_den > (unsigned __int128)n * occ_num)
+      for (uint64_t q = s; q < e; ++q) flag[tab[q].id] = 1;
+    s = e;
   }
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int u = 0; u < (int)t; ++u) qsort(tab[u], n, sizeof(orc_kv), cmp_kv);
+}
 
-  /* Bucket sizes, raw candidate count and the occurrence filter. */
-  uint8_t *flag = (uint8_t *)calloc(n ? n : 1, 1);
-  for (uint32_t u = 0; u < t; ++u) {
-    uint64_t s = 0;
-    while (s < n) {
-      uint64_t e = s + 1;
-      while (e < n && tab[u][e].key == tab[u][s].key) ++e;
-      uint64_t size = e - s;
-      st->e_raw += size * (size - 1) / 2;
-      if (size > st->max_bucket) st->max_bucket = size;
-      if (occ_den && (unsigned __int128)size * occ_den > (unsigned __int128)n * occ_num)
-        for (uint64_t q = s; q < e; ++q) flag[tab[u][q].id] = 1;
-      s = e;
+/* A growable list of pairs packed as i << 32 | j. */
+typedef struct { uint64_t *p; uint64_t cnt, cap; int oom; } orc_pairs;
+
+static void orc_pairs_push(orc_pairs *v, uint64_t x) {
+  if (v->oom) return;
+  if (v->cnt == v->cap) {
+    uint64_t nc = v->cap ? 2 * v->cap : 1024;
+    uint64_t *np = (uint64_t *)realloc(v->p, nc * sizeof(uint64_t));
+    if (!np) { v->oom = 1; return; }
+    v->p = np;
+    v->cap = nc;
+  }
+  v->p[v->cnt++] = x;
+}
+
+/* Candidate pairs of one sorted table (section 6.1 "Search"; self-matches,
+ * section 7.1): every pair of members i < j of a bucket with j - i >= min_lag,
+ * neither member flagged (flag may be NULL: no exclusion), and i in
+ * [i_lo, i_hi), appended to *out. */
+static void orc_table_pairs(uint64_t n, const orc_kv *tab, const uint8_t *flag, uint32_t min_lag, uint64_t i_lo,
+                            uint64_t i_hi, orc_pairs *out) {
+  uint64_t s = 0;
+  while (s < n) {
+    uint64_t e = s + 1;
+    while (e < n && tab[e].key == tab[s].key) ++e;
+    for (uint64_t x = s; x < e; ++x) {
+      uint64_t i = tab[x].id;
+      if (i < i_lo || i >= i_hi || (flag && flag[i])) continue;
+      for (uint64_t y = x + 1; y < e; ++y) {
+        uint64_t j = tab[y].id;
+        if (j - i < min_lag || (flag && flag[j])) continue;
+        orc_pairs_push(out, (i << 32) | j);
+      }
     }
+    s = e;
   }
-  for (uint64_t i = 0; i < n; ++i) st->n_flagged += flag[i];
+}
 
-  /* Candidate pairs: every pair of distinct, unflagged members of a bucket
-   * with j - i >= min_lag, once per table in which they share a bucket. */
-  uint64_t cap = 1024, cnt = 0;
-  uint64_t *pairs = (uint64_t *)malloc(cap * sizeof(uint64_t));
-  for (uint32_t u = 0; u < t; ++u) {
-    uint64_t s = 0;
-    while (s < n) {
-      uint64_t e = s + 1;
-      while (e < n && tab[u][e].key == tab[u][s].key) ++e;
-      for (uint64_t x = s; x < e; ++x)
-        for (uint64_t y = x + 1; y < e; ++y) {
-          uint64_t i = tab[u][x].id, j = tab[u][y].id;
-          if (j - i < min_lag || flag[i] || flag[j]) continue;
-          if (cnt == cap) { cap *= 2; pairs = (uint64_t *)realloc(pairs, cap * sizeof(uint64_t)); }
-          pairs[cnt++] = (i << 32) | j;
-        }
-      s = e;
-    }
+/* Output arrays that grow as pairs are appended. */
+typedef struct { uint32_t *i, *j; uint8_t *v; uint64_t cnt, cap; int oom; } orc_out;
+
+static void orc_out_push(orc_out *o, uint32_t i, uint32_t j, uint8_t v) {
+  if (o->oom) return;
+  if (o->cnt == o->cap) {
+    uint64_t nc = o->cap ? 2 * o->cap : 16;
+    uint32_t *ni = (uint32_t *)realloc(o->i, nc * 4);
+    if (ni) o->i = ni;
+    uint32_t *nj = (uint32_t *)realloc(o->j, nc * 4);
+    if (nj) o->j = nj;
+    uint8_t *nv = (uint8_t *)realloc(o->v, nc);
+    if (nv) o->v = nv;
+    if (!ni || !nj || !nv) { o->oom = 1; return; }
+    o->cap = nc;
   }
-  for (uint32_t u = 0; u < t; ++u) free(tab[u]);
-  free(tab);
+  o->i[o->cnt] = i; o->j[o->cnt] = j; o->v[o->cnt] = v;
+  ++o->cnt;
+}
 
-  /* Votes: the number of tables that emitted a pair is the number of
-   * tables in which its two fingerprints share a bucket. */
+/* Votes (section 6.1 "Search"; section 7.2 triplets): every table that
+ * found a pair emitted it once, so after sorting the emitted pairs a pair
+ * that appears k times shares a bucket in k tables.  Pairs with a flagged
+ * member (flag may be NULL) are dropped; every other pair adds k to e_voted
+ * and one to n_distinct, and is appended to the output when k >= min_votes
+ * ("at least m", section 6.3).  Sorts pairs[] in place. */
+static void orc_votes(uint64_t *pairs, uint64_t cnt, const uint8_t *flag, uint32_t min_votes, orc_out *out,
+                      orc_stats *st) {
   qsort(pairs, cnt, sizeof(uint64_t), cmp_u64);
-  st->e_voted = cnt;
-  uint64_t outcap = 16, nout = 0;
-  uint32_t *oi = (uint32_t *)malloc(outcap * 4), *oj = (uint32_t *)malloc(outcap * 4);
-  uint8_t *ov = (uint8_t *)malloc(outcap);
   uint64_t s = 0;
   while (s < cnt) {
     uint64_t e = s + 1;
     while (e < cnt && pairs[e] == pairs[s]) ++e;
-    st->n_distinct += 1;
-    uint64_t votes = e - s;
-    if (votes >= min_votes) {
-      if (nout == outcap) {
-        outcap *= 2;
-        oi = (uint32_t *)realloc(oi, outcap * 4); oj = (uint32_t *)realloc(oj, outcap * 4);
-        ov = (uint8_t *)realloc(ov, outcap);
-      }
-      oi[nout] = (uint32_t)(pairs[s] >> 32); oj[nout] = (uint32_t)pairs[s]; ov[nout] = (uint8_t)votes;
-      ++nout;
+    uint32_t i = (uint32_t)(pairs[s] >> 32), j = (uint32_t)pairs[s];
+    if (!flag || (!flag[i] && !flag[j])) {
+      uint64_t votes = e - s;
+      st->e_voted += votes;
+      st->n_distinct += 1;
+      if (votes >= min_votes) orc_out_push(out, i, j, (uint8_t)votes);
     }
     s = e;
   }
-  free(pairs);
-  st->n_out = nout;
+}
+
+/* Search from precomputed band keys (table-major, keys[u*n + i]).
+ * The pairs are counted in n_parts vote partitions, consecutive ranges of
+ * the smaller id i (a pair belongs to the partition of its i), one after
+ * another; each partition's output is sorted by (i, j), so their
+ * concatenation is the output of the whole search, and the counters add up
+ * (partitioning only bounds memory, as in section 6.4).
+ * On success the output triplets (i, j, votes) are in three arrays
+ * allocated with malloc (caller frees with orc_free). */
+int orc_search_keys(uint32_t t, uint64_t n, const uint64_t *keys, uint32_t min_lag, uint32_t min_votes,
+                    uint32_t occ_num, uint32_t occ_den, uint32_t n_parts, uint32_t **out_i, uint32_t **out_j,
+                    uint8_t **out_v, orc_stats *st, uint8_t *flags_out) {
+  memset(st, 0, sizeof(*st));
+  *out_i = NULL; *out_j = NULL; *out_v = NULL;
+  if (t == 0 || t > 255 || min_votes == 0 || n >= (1ull << 31) || n_parts == 0) return 1;
+
+  /* The t hash tables. */
+  orc_kv **tab = (orc_kv **)calloc(t, sizeof(orc_kv *));
+  uint8_t *flag = (uint8_t *)calloc(n ? n : 1, 1);
+  int oom = !tab || !flag;
+  for (uint32_t u = 0; u < t && !oom; ++u) oom = !(tab[u] = (orc_kv *)malloc((n ? n : 1) * sizeof(orc_kv)));
+  if (oom) {
+    if (tab) for (uint32_t u = 0; u < t; ++u) free(tab[u]);
+    free(tab); free(flag);
+    return 2;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int u = 0; u < (int)t; ++u) orc_table_sort(n, keys + (uint64_t)u * n, tab[u]);
+
+  /* Bucket sizes, raw candidate count and the occurrence filter (sizes
+   * before any exclusion, flags from every table before any pair). */
+  for (uint32_t u = 0; u < t; ++u) orc_table_buckets(n, tab[u], occ_num, occ_den, flag, &st->e_raw, &st->max_bucket);
+  for (uint64_t i = 0; i < n; ++i) st->n_flagged += flag[i];
+
+  /* Pairs and votes, one vote partition at a time. */
+  orc_out out = {0};
+  for (uint32_t p = 0; p < n_parts && !oom; ++p) {
+    const uint64_t lo = n * p / n_parts, hi = n * (p + 1) / n_parts;
+    orc_pairs pairs = {0};
+    for (uint32_t u = 0; u < t; ++u) orc_table_pairs(n, tab[u], flag, min_lag, lo, hi, &pairs);
+    oom = pairs.oom;
+    if (!oom) orc_votes(pairs.p, pairs.cnt, NULL, min_votes, &out, st);
+    oom |= out.oom;
+    free(pairs.p);
+  }
+  for (uint32_t u = 0; u < t; ++u) free(tab[u]);
+  free(tab);
   if (flags_out) memcpy(flags_out, flag, n);
   free(flag);
-  *out_i = oi; *out_j = oj; *out_v = ov;
+  if (oom) {
+    free(out.i); free(out.j); free(out.v);
+    return 2;
+  }
+  st->n_out = out.cnt;
+  *out_i = out.i; *out_j = out.j; *out_v = out.v;
+  return 0;
+}
+
+/* One table of a search whose tables are taken one at a time (for inputs
+ * whose keys do not fit in memory at once): sorts the table's keys
+ * keys_u[n], adds its buckets to *e_raw / *max_bucket and ORs its
+ * occurrence-filter exclusions into flag[n] (orc_table_buckets), and appends
+ * its candidate pairs with i in any of the n_ranges ranges
+ * [ranges[2k], ranges[2k+1]) to *pairs / *cnt (a malloc'ed array the caller
+ * passes back on the next call and frees with orc_free), without exclusion:
+ * the exclusions are final only after every table, and orc_count_votes drops
+ * the pairs they hit.  Returns 0, or 2 when memory runs out. */
+int orc_table_scan(uint64_t n, const uint64_t *keys_u, uint32_t occ_num, uint32_t occ_den, uint8_t *flag,
+                   uint64_t *e_raw, uint64_t *max_bucket, uint32_t min_lag, uint32_t n_ranges,
+                   const uint64_t *ranges, uint64_t **pairs, uint64_t *cnt) {
+  orc_kv *tab = (orc_kv *)malloc((n ? n : 1) * sizeof(orc_kv));
+  if (!tab) return 2;
+  orc_table_sort(n, keys_u, tab);
+  orc_table_buckets(n, tab, occ_num, occ_den, flag, e_raw, max_bucket);
+  orc_pairs v = {*pairs, *cnt, *cnt, 0};
+  for (uint32_t k = 0; k < n_ranges; ++k) orc_table_pairs(n, tab, NULL, min_lag, ranges[2 * k], ranges[2 * k + 1], &v);
+  free(tab);
+  *pairs = v.p;
+  *cnt = v.cnt;
+  return v.oom ? 2 : 0;
+}
+
+/* Votes of the pairs collected by orc_table_scan over every table: drops the
+ * pairs with an excluded member (flag[n], may be NULL), counts the rest
+ * (orc_votes) and returns the output triplets as orc_search_keys does, with
+ * st->e_voted and st->n_distinct of these pairs.  Sorts pairs[] in place. */
+int orc_count_votes(uint64_t *pairs, uint64_t cnt, const uint8_t *flag, uint32_t min_votes, uint32_t **out_i,
+                    uint32_t **out_j, uint8_t **out_v, orc_stats *st) {
+  memset(st, 0, sizeof(*st));
+  orc_out out = {0};
+  orc_votes(pairs, cnt, flag, min_votes, &out, st);
+  if (out.oom) {
+    free(out.i); free(out.j); free(out.v);
+    return 2;
+  }
+  st->n_out = out.cnt;
+  *out_i = out.i; *out_j = out.j; *out_v = out.v;
   return 0;
 }
 
@@ -294,9 +410,10 @@ int orc_search(uint32_t dim, uint32_t t, uint32_t r, uint32_t scheme, const uint
                uint32_t min_votes, uint32_t occ_num, uint32_t occ_den, uint32_t **out_i, uint32_t **out_j,
                uint8_t **out_v, orc_stats *st) {
   uint64_t *keys = (uint64_t *)malloc((n ? n : 1) * (uint64_t)t * sizeof(uint64_t));
+  if (!keys) return 2;
   int rc = orc_signatures(dim, t, r, scheme, a, b, n, offsets, nnz, ind, keys, NULL);
   if (rc == 0)
-    rc = orc_search_keys(t, n, keys, min_lag, min_votes, occ_num, occ_den, out_i, out_j, out_v, st, NULL);
+    rc = orc_search_keys(t, n, keys, min_lag, min_votes, occ_num, occ_den, 1, out_i, out_j, out_v, st, NULL);
   free(keys);
   return rc;
 }

@@ -452,3 +452,51 @@ def test_packed_key_used_up_to_64_bits():
     for s_ in range(5):
         packed_low |= tup[:, s_] << np.uint64(12 * s_)
     assert (oracle.band_keys(tup.astype(np.uint32), 4096) != packed_low).mean() > 0.99
+
+
+# ---------------------------------------------------------------------------
+# Vote partitions and the table-at-a-time form (used for full-size expected
+# values) against the whole search, which the brute force pins
+# ---------------------------------------------------------------------------
+def _noise_keys(seed):
+    rows = synth.generate(synth.with_noise(synth.station(n=6000, seed=seed), 40, 190))
+    a, b = oracle.make_hash(seed + 1, 200)
+    return oracle.signatures(rows, 4096, 100, 4, oracle.MINMAX, a, b)
+
+
+def test_vote_partitions_change_nothing():
+    # Counting the pairs one range of i at a time (section 6.4: partitioned
+    # search gives the same result) concatenates to the same output.
+    keys = _noise_keys(300)
+    for num, den in ((0, 0), (1, 100)):
+        whole = oracle.search_keys(keys, 5, 4, num, den)
+        if den:
+            assert whole[3].n_flagged > 0
+        for parts in (2, 3, 7):
+            got = oracle.search_keys(keys, 5, 4, num, den, parts=parts)
+            for x, y in zip(whole[:3], got[:3]):
+                assert np.array_equal(x, y)
+            assert whole[3] == got[3]
+
+
+def test_table_scan_matches_whole_search():
+    # One table at a time, exclusions applied when the votes are counted:
+    # identical to the whole search (every range of i), and restricted to the
+    # ranges asked for otherwise; e_raw, max_bucket and n_flagged are global.
+    keys = _noise_keys(310)
+    t, n = keys.shape
+    for num, den in ((0, 0), (1, 100)):
+        ei, ej, ev, est = oracle.search_keys(keys, 5, 4, num, den)
+        for ranges in ([(0, n)], [(0, 700), (2500, 2600), (5900, n)]):
+            sc = oracle.TableScan(n, num, den, 5, ranges)
+            for u in range(t):
+                sc.add_table(keys[u])
+            gi, gj, gv, gst = sc.result(4)
+            sc.close()
+            keep = np.zeros(len(ei), bool)
+            for lo, hi in ranges:
+                keep |= (ei >= lo) & (ei < hi)
+            assert np.array_equal(gi, ei[keep]) and np.array_equal(gj, ej[keep]) and np.array_equal(gv, ev[keep])
+            assert (gst.e_raw, gst.max_bucket, gst.n_flagged) == (est.e_raw, est.max_bucket, est.n_flagged)
+            if ranges == [(0, n)]:
+                assert gst == est
