@@ -486,6 +486,7 @@ struct fast_lsh_server {
   fast_lsh_server_config cfg{};
   std::vector<Station> st;
   uint64_t mphys = 0;          // rows per table of the shared history-merge buffer
+  uint64_t max_hcap = 0;       // largest history stride of any station (mphys never drops below it)
   uint64_t* mkey = nullptr;
   uint32_t* mid = nullptr;
   std::mutex mu;
@@ -537,9 +538,11 @@ static int alloc_dev(void** p, uint64_t bytes) {
 }
 
 // Merge a station's delta into its history: the merged run is written to
-// the shared buffer (at least hcap rows per table, reserved when the
-// station was admitted), which then becomes the station's history while the
-// old history buffers become the shared one.
+// the shared buffer (as large as the largest station's history, reserved
+// when that station was admitted).  When the station's own history buffers
+// are at least that large they swap roles with the shared one (no copy);
+// a smaller station's merged run is copied back instead, so that the shared
+// buffer never shrinks below the largest station.
 static int merge_history(fast_lsh_server* sv, Station& S) {
   const uint32_t t = sv->h.num_tables;
   if (S.nh + S.nd > S.hcap)
@@ -551,10 +554,18 @@ static int merge_history(fast_lsh_server* sv, Station& S) {
   launch_merge(S.hkey, S.hid, S.hcap, S.nh, S.dkey[S.dcur], S.did[S.dcur], S.dcap, S.nd, sv->mkey, sv->mid, S.hcap,
                t, scr, sv->stream);
   LAUNCHCK();
-  std::swap(S.hkey, sv->mkey);
-  std::swap(S.hid, sv->mid);
-  std::swap(S.hphys, sv->mphys);
-  S.nh += S.nd;
+  const uint64_t rows = S.nh + S.nd;
+  if (S.hphys >= sv->max_hcap) {
+    std::swap(S.hkey, sv->mkey);
+    std::swap(S.hid, sv->mid);
+    std::swap(S.hphys, sv->mphys);
+  } else if (rows) {
+    HIPCK(hipMemcpy2DAsync(S.hkey, S.hcap * 8, sv->mkey, S.hcap * 8, rows * 8, t, hipMemcpyDeviceToDevice,
+                           sv->stream));
+    HIPCK(hipMemcpy2DAsync(S.hid, S.hcap * 4, sv->mid, S.hcap * 4, rows * 4, t, hipMemcpyDeviceToDevice,
+                           sv->stream));
+  }
+  S.nh = rows;
   S.nd = 0;
   return FAST_LSH_OK;
 }
@@ -1032,6 +1043,7 @@ int fast_lsh_server_add_station(fast_lsh_server* sv, const fast_lsh_fps* hist, u
   }
   std::lock_guard<std::mutex> lk(sv->mu);
   *station = (uint32_t)sv->st.size();
+  sv->max_hcap = std::max(sv->max_hcap, S.hcap);
   sv->st.push_back(S);
   return FAST_LSH_OK;
 }

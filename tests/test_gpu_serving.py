@@ -131,6 +131,8 @@ def test_serving_alone_and_mixed_batches_agree():
                                     delta_rows=6000, slack_rows=20_000)
         if mb == 1:
             assert info["largest_batch"] == 1
+        else:  # chunks of different stations did share a batch
+            assert info["largest_batch"] > 1
         _check(runs[mb], hists, chunk_rows, 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
     for s in range(3):  # per-chunk results identical, not only their union
         for p1, p8 in zip(runs[1][s][4], runs[8][s][4]):
@@ -244,3 +246,46 @@ def test_serving_full_history_fails_later_chunks():
     o = np.lexsort((gj, gi))
     say(f"[serve] full history: {len(gi)} pairs (oracle {len(ei)})")
     assert np.array_equal(gi[o], ei) and np.array_equal(gj[o], ej) and np.array_equal(gv[o], ev)
+
+
+def test_serving_small_station_merges_before_large_one():
+    # Station 1 (4,000 history rows) fills its delta and merges into its
+    # history before station 0 (20,000 rows) does.  The shared merge buffer
+    # must still hold the larger station afterwards, and every chunk of both
+    # stations must match the oracle.
+    sizes = {0: [2000] * 5, 1: [2000] * 5}
+    hist_n = {0: 20_000, 1: 4_000}
+    rows = {s: synth.generate(synth.station(n=hist_n[s] + sum(sizes[s]), seed=220 + s)) for s in (0, 1)}
+    hists = [rows[s][:hist_n[s]] for s in (0, 1)]
+    chunk_rows = [_chunks(rows[s], hist_n[s], sizes[s]) for s in (0, 1)]
+    a, b = fl.make_hash(221, 200)
+    sv = fl.Server(4096, 100, 4, fl.MINMAX, a, b, 5, 4, max_batch=4, max_chunk=2000, delta_rows=4000,
+                   slack_rows=12_000)
+    ids = [sv.add_station(fl.to_device_rows(h)) for h in hists]
+    dev = {(s, c): fl.to_device_rows(x) for s in (0, 1) for c, x in enumerate(chunk_rows[s])}
+    got = {0: {}, 1: {}}
+
+    def run(order):
+        tks = [(s, c, sv.submit(ids[s], dev[(s, c)])) for s, c in order]
+        for s, c, tk in tks:
+            st, _ = sv.poll(tk, wait=True)
+            got[s][c] = (*sv.take(tk), st)
+
+    # the small station's third chunk finds its delta full: its merge runs
+    # (after that batch) before any chunk of the large station is submitted
+    run([(1, 0), (1, 1), (1, 2)])
+    say("[serve] small station merged")
+    run([(0, 0), (0, 1), (0, 2)])  # the large station's merge
+    say("[serve] large station merged")
+    run([(1, 3), (0, 3), (1, 4), (0, 4)])
+    sv.close()
+    out = []
+    for s in (0, 1):
+        parts = [got[s][c] for c in sorted(got[s])]
+        gi = np.concatenate([p[0] for p in parts])
+        gj = np.concatenate([p[1] for p in parts])
+        gv = np.concatenate([p[2] for p in parts])
+        o = np.lexsort((gj, gi))
+        sums = {k: sum(getattr(p[3], k) for p in parts) for k in ("e_raw", "e_voted", "n_distinct")}
+        out.append((gi[o], gj[o], gv[o], sums, parts))
+    _check(out, hists, chunk_rows, 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
