@@ -22,7 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "align.c")]
 
 P = 2**31 - 1
 MINHASH, MINMAX = 0, 1
@@ -30,7 +30,7 @@ MINHASH, MINMAX = 0, 1
 
 def build() -> str:
     tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", _SRC, "-o", tmp])
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", *_SRC, "-o", tmp])
     os.replace(tmp, _SO)
     return _SO
 
@@ -81,7 +81,14 @@ def _lib():
         lib.orc_pair_votes.argtypes = [_u32, _u64, _vp, _u64, _u64]
         lib.orc_pair_votes.restype = _u32
         lib.orc_free.argtypes = [_vp]
+        lib.orc_channel_merge.argtypes = [_u32, _vp, _vp, _vp, _vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                          ctypes.POINTER(_vp), ctypes.POINTER(_u64)]
+        lib.orc_channel_merge.restype = ctypes.c_int
+        lib.orc_station_clusters.argtypes = [_u64, _vp, _vp, _vp, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp),
+                                             ctypes.POINTER(_u64)]
+        lib.orc_station_clusters.restype = ctypes.c_int
         lib.orc_max_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
         _LIB = lib
     return _LIB
 
@@ -258,7 +265,68 @@ def max_threads() -> int:
     return int(_lib().orc_max_threads())
 
 
+def set_threads(n: int) -> None:
+    """Threads of later oracle calls (timing only; results do not change)."""
+    _lib().orc_set_threads(int(n))
+
+
 def pair_votes(keys: np.ndarray, i: int, j: int) -> int:
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
     t, n = keys.shape
     return int(_lib().orc_pair_votes(t, n, keys.ctypes.data, i, j))
+
+
+# --------------------------------------------------------------------------
+# Spatiotemporal alignment (section 7): channel merge and station clusters
+# --------------------------------------------------------------------------
+CLUSTER_DTYPE = np.dtype([("dt_min", "<u4"), ("dt_max", "<u4"), ("idx1_min", "<u4"), ("idx1_max", "<u4"),
+                          ("n_entries", "<u4"), ("peak_sim", "<u4"), ("peak_dt", "<u4"), ("peak_idx1", "<u4"),
+                          ("sim_sum", "<u8")])
+
+
+def channel_merge(channels, min_sim: int):
+    """Channel-level sort-merge-reduce of search outputs [(i, j, votes), ...]
+    of one station's channels: (dt, idx1, sim) uint32 arrays ordered by
+    (dt, idx1), sums of sim >= min_sim only."""
+    arrs = [(np.ascontiguousarray(i, dtype=np.uint32), np.ascontiguousarray(j, dtype=np.uint32),
+             np.ascontiguousarray(v, dtype=np.uint8)) for i, j, v in channels]
+    n = len(arrs)
+    counts = np.array([len(a[0]) for a in arrs] or [0], dtype=np.uint64)
+    ptr = lambda q: np.array([a[q].ctypes.data for a in arrs] or [0], dtype=np.uint64)
+    pi, pj, pv = ptr(0), ptr(1), ptr(2)
+    odt, oid, osm, m = _vp(), _vp(), _vp(), _u64()
+    rc = _lib().orc_channel_merge(n, counts.ctypes.data, pi.ctypes.data, pj.ctypes.data, pv.ctypes.data, min_sim,
+                                  ctypes.byref(odt), ctypes.byref(oid), ctypes.byref(osm), ctypes.byref(m))
+    if rc == 1:
+        raise ValueError("oracle: a pair with j <= i")
+    if rc != 0:
+        raise MemoryError("oracle: out of host memory")
+    k = int(m.value)
+    out = []
+    for p in (odt, oid, osm):
+        a = np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint32)), (k,)).copy() if k else \
+            np.empty(0, np.uint32)
+        _lib().orc_free(p)
+        out.append(a)
+    return tuple(out)
+
+
+def station_clusters(dt, idx1, sim, max_gap: int, max_width: int, min_entries: int = 1, min_sum: int = 0):
+    """Station-level diagonal clusters of (dt, idx1)-ordered entries: a
+    structured array (CLUSTER_DTYPE) in the order of each cluster's first entry."""
+    dt = np.ascontiguousarray(dt, dtype=np.uint32)
+    idx1 = np.ascontiguousarray(idx1, dtype=np.uint32)
+    sim = np.ascontiguousarray(sim, dtype=np.uint32)
+    p, m = _vp(), _u64()
+    rc = _lib().orc_station_clusters(len(dt), dt.ctypes.data, idx1.ctypes.data, sim.ctypes.data, max_gap, max_width,
+                                     min_entries, min_sum, ctypes.byref(p), ctypes.byref(m))
+    if rc == 1:
+        raise ValueError("oracle: entries not strictly ordered by (dt, idx1)")
+    if rc != 0:
+        raise MemoryError("oracle: out of host memory")
+    k = int(m.value)
+    out = np.empty(k, dtype=CLUSTER_DTYPE)
+    if k:
+        ctypes.memmove(out.ctypes.data, p, k * CLUSTER_DTYPE.itemsize)
+    _lib().orc_free(p)
+    return out

@@ -436,3 +436,13 @@ int orc_max_threads(void) {
   return 1;
 #endif
 }
+
+/* Sets the number of threads later OpenMP loops of the oracle use (timing
+ * only; results do not depend on it). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -54,6 +54,7 @@ class _Spec(ctypes.Structure):
         ("noise_permille", ctypes.c_uint32),
         ("noise_keep", ctypes.c_uint32),
         ("chain_len", ctypes.c_uint64),
+        ("channel", ctypes.c_uint32),
     ]
 
 
@@ -98,6 +99,7 @@ class Spec:
     noise_permille: int = 0
     noise_keep: int = 0
     chain_len: int = 0
+    channel: int = 0
 
     def _c(self) -> _Spec:
         return _Spec(*[getattr(self, f) for f, _ in _Spec._fields_])

@@ -54,6 +54,11 @@ typedef struct {
   uint32_t noise_keep;    /* template bits each noise copy keeps           */
   uint64_t chain_len;     /* Markov only: 0 = one chain over all rows; else independent
                              chains of chain_len rows, chain c drawn from stream c    */
+  uint32_t channel;       /* channel of a multi-channel station: the planted sources
+                             (slots, repeat counts, templates) are shared by every
+                             channel of a seed, while the background rows and the
+                             content of each planted copy are drawn per channel;
+                             channel 0 is the single-channel workload            */
 } synth_spec;
 
 typedef struct { uint64_t s; } rng_t;
@@ -72,6 +77,11 @@ static inline rng_t stream_for(uint64_t seed, uint64_t tag, uint64_t idx) {
   r.s = seed ^ (tag << 56) ^ (idx * 0xD6E8FEB86659FD93ull);
   r.s = sm64_next(&r);
   return r;
+}
+
+/* Seed of the per-channel streams (background rows, copy content). */
+static inline uint64_t channel_seed(const synth_spec *sp) {
+  return sp->channel ? sp->seed ^ ((uint64_t)sp->channel * 0xA24BAED4963EE407ull) : sp->seed;
 }
 
 /* Uniform integer in [0, n) by the multiply-shift map of a 32-bit draw. */
@@ -199,7 +209,7 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
   if (sp->markov_keep == 0) {
 #pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < (int64_t)cnt; ++q) {
-      rng_t r = stream_for(sp->seed, TAG_BG, lo + (uint64_t)q);
+      rng_t r = stream_for(channel_seed(sp), TAG_BG, lo + (uint64_t)q);
       if (uniform_row(&r, d, k, out + (uint64_t)q * k)) {
 #pragma omp atomic write
         oom = 1;
@@ -212,7 +222,7 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
     const int64_t c0 = (int64_t)(lo / clen), c1 = (int64_t)((hi - 1) / clen) + 1;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t c = c0; c < c1; ++c) {
-      rng_t r = stream_for(sp->seed, TAG_CHAIN, (uint64_t)c);
+      rng_t r = stream_for(channel_seed(sp), TAG_CHAIN, (uint64_t)c);
       uint16_t *prev = (uint16_t *)malloc(k * sizeof(uint16_t));
       uint16_t *cur = (uint16_t *)malloc(k * sizeof(uint16_t));
       uint16_t *scratch = (uint16_t *)malloc(k * sizeof(uint16_t));
@@ -302,7 +312,7 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
   for (int64_t q = 0; q < (int64_t)m; ++q) {
     uint64_t x = slot[q];
     if (x < lo || x >= hi) continue;
-    rng_t rc = stream_for(sp->seed, TAG_COPY, x);
+    rng_t rc = stream_for(channel_seed(sp), TAG_COPY, x);
     const uint16_t *t = tpl + (uint64_t)(who[q] >= 0 ? (uint32_t)who[q] : sp->n_sources) * k;
     if (make_copy(&rc, d, k, t, keep[q], out + (x - lo) * k)) {
 #pragma omp atomic write

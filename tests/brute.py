@@ -70,3 +70,51 @@ def search_brute(keys, min_lag, min_votes, occ_num=0, occ_den=0):
     stats = dict(n_out=len(out), e_raw=e_raw, e_voted=e_voted, n_distinct=n_distinct,
                  n_flagged=int(flags.sum()), max_bucket=max_bucket)
     return out, stats, flags
+
+
+def channel_merge_brute(channels, min_sim):
+    """Combined similarity by a hash map of (dt, idx1) -> summed sim (the
+    'naive' shared-map route section 7.2 describes), filtered and sorted."""
+    acc = {}
+    for i, j, v in channels:
+        for x, y, s in zip(i.tolist(), j.tolist(), v.tolist()):
+            assert y > x
+            acc[(y - x, x)] = acc.get((y - x, x), 0) + s
+    keys = sorted(k for k, s in acc.items() if s >= min_sim)
+    return (np.array([k[0] for k in keys], dtype=np.uint32), np.array([k[1] for k in keys], dtype=np.uint32),
+            np.array([acc[k] for k in keys], dtype=np.uint32))
+
+
+def station_clusters_brute(dt, idx1, sim, max_gap, max_width, min_entries=1, min_sum=0):
+    """Clusters as connected components of the entries themselves: two
+    entries are neighbours when their diagonals differ by at most one and
+    their start times by at most max_gap (O(E^2), no runs, no union-find).
+    Returns a list of tuples in the field order of oracle.CLUSTER_DTYPE, in
+    the order of each cluster's first entry."""
+    n = len(dt)
+    dt = [int(x) for x in dt]
+    idx1 = [int(x) for x in idx1]
+    sim = [int(x) for x in sim]
+    comp = [-1] * n
+    for s in range(n):
+        if comp[s] >= 0:
+            continue
+        comp[s] = s
+        stack = [s]
+        while stack:
+            a = stack.pop()
+            for b in range(n):
+                if comp[b] < 0 and abs(dt[a] - dt[b]) <= 1 and abs(idx1[a] - idx1[b]) <= max_gap:
+                    comp[b] = s
+                    stack.append(b)
+    out = []
+    for c in sorted(set(comp)):  # the first entry of each component, in input order
+        mem = [k for k in range(n) if comp[k] == c]
+        d = [dt[k] for k in mem]
+        x = [idx1[k] for k in mem]
+        peak = min(mem, key=lambda k: (-sim[k], dt[k], idx1[k]))
+        tot = sum(sim[k] for k in mem)
+        if max(d) - min(d) + 1 > max_width or len(mem) < min_entries or tot < min_sum:
+            continue
+        out.append((min(d), max(d), min(x), max(x), len(mem), sim[peak], dt[peak], idx1[peak], tot))
+    return out

@@ -23,6 +23,7 @@ typedef struct {
   uint32_t markov_keep, n_sources, rep_min, rep_max, plant_keep, jac_lo_milli, jac_hi_milli, noise_permille,
       noise_keep;
   uint64_t chain_len;
+  uint32_t channel;
 } synth_spec;
 
 int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_t *out, int32_t *label);
