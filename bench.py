@@ -1,23 +1,34 @@
 #!/usr/bin/env python3
-"""Throughput of the LSH similarity search on one MI355X.
+"""Throughput and streaming latency of the LSH similarity search on one MI355X.
 
-Workload: one station, 90 days of fingerprints at a 1 s lag (7,776,000
-fingerprints, 4096-dim, 200 set bits each; Markov background keeping 70 % of
-the previous fingerprint; 2,000 repeating sources with 3-40 copies whose
-Jaccard similarity to the template is U[0.4, 0.9]).  Min-Max hash, t = 100
-tables, r = 4 rows (2 functions per table), self-match lag 5, at least 4
-votes, occurrence filter at 1 % of N.
+Default workload (the largest one-GPU configuration): one station, 5 years of
+fingerprints at a 1 s lag (157,788,000 fingerprints, 4096-dim, 200 set bits
+each; Markov background keeping 70 % of the previous fingerprint; 20,000
+repeating sources with 3-40 copies whose Jaccard similarity to the template
+is U[0.4, 0.9]).  Min-Max hash, t = 100 tables, r = 4 rows (2 functions per
+table), self-match lag 5, at least 4 votes, occurrence filter at 1 % of N;
+the tables are taken 10 at a time so that the search fits in HBM.
 
 One step = one full search: signatures, grouping of all 100 tables, bucket
 segmentation and occurrence filter, in-bucket pair votes, threshold and
 canonical sort, from fingerprints resident in HBM to the sorted pairs in HBM
 and the pair count on the host.  value = fingerprints / second.
 
-Prints one JSON line.
+After the timed steps the same process runs the streaming workload (8
+stations of 180 days resident, 3,600-fingerprint chunks arriving as Poisson
+streams at 40 chunks/s) and adds its p50/p99 chunk latency and sustained
+chunk rate to the line, next to the time a plain search of one station's
+history plus one chunk takes on the same GPU.
+
+Other workloads: --workload station (90 days, 7,776,000 fingerprints, tables
+all at once), bounded (the 5-year search alone), serving (the streaming
+workload alone), batched (12 stations in one search against 12 sequential
+searches).  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -25,6 +36,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+METRIC = "fingerprints/s through MinHash+LSH vote count; p50/p99 streaming chunk latency"
 
 # MI355X published peaks and unit counts
 HBM_PEAK_GBS = 8000.0
@@ -42,6 +55,25 @@ INT_PEAK_TOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0  # 39.3
 # not counted, like the half operation that unpacks two 16-bit indices per
 # register).
 OPS_PER_EVAL = {0: 2.5, 1: 3.0}  # MinHash, Min-Max
+
+# Algorithmic bytes of the pair stages: one 8-byte vote update per valid
+# candidate pair (a pair passing the lag and the exclusion, counted in
+# e_voted) and one 4-byte id read per bucket member.
+BYTES_PER_VOTED_PAIR, BYTES_PER_MEMBER = 8, 4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def sig_traffic(n):
@@ -61,23 +93,27 @@ def sig_traffic(n):
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--chunks", type=int, default=3000, help="serving workload: chunks at the offered load")
-    ap.add_argument("--rate", type=float, default=40.0, help="serving workload: offered chunks/s (all stations)")
-    ap.add_argument("--stations", type=int, default=8, help="serving workload: stations")
-    ap.add_argument("--workload", choices=("station", "batched", "bounded", "serving"), default="station",
-                    help="station: one 90-day station (default); batched: 12 stations of 1-16 M fingerprints "
-                         "in one search, against 12 sequential searches; bounded: one 5-year station "
-                         "(157,788,000 fingerprints) with tables taken 10 at a time; serving: 8 stations of "
-                         "180 days resident, 3,600-row chunks arriving as Poisson streams")
-    ap.add_argument("--group-tables", type=int, default=10, help="bounded workload: tables per group")
+    ap.add_argument("--workload", choices=("headline", "station", "batched", "bounded", "serving"),
+                    default="headline",
+                    help="headline (default): the 5-year station (157,788,000 fingerprints, tables 10 at a "
+                         "time) timed over the steps, then the streaming workload's latency; station: one "
+                         "90-day station; bounded: the 5-year search alone; serving: 8 stations of 180 days "
+                         "resident, 3,600-row chunks arriving as Poisson streams; batched: 12 stations of "
+                         "1-16 M fingerprints in one search, against 12 sequential searches")
+    ap.add_argument("--chunks", type=int, default=3000, help="serving: chunks at the offered load")
+    ap.add_argument("--rate", type=float, default=40.0, help="serving: offered chunks/s (all stations)")
+    ap.add_argument("--stations", type=int, default=8, help="serving: stations")
+    ap.add_argument("--group-tables", type=int, default=10, help="bounded: tables per group")
     ap.add_argument("--graph", action="store_true", help="replay the captured graph of the search prefix")
     ap.add_argument("--autotune", action="store_true", help="tune launch shapes on the first (warm-up) search")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=7_776_000, help="fingerprints (default: 90 days at 1 s)")
+    ap.add_argument("--n", type=int, default=0, help="fingerprints (0: the workload's own size)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
-                    help="fingerprints of the same workload the CPU oracle is timed on (0: skip)")
+                    help="fingerprints of the same workload the CPU oracle is timed on, all threads (0: skip)")
+    ap.add_argument("--cpu-sample-1t", type=int, default=100_000,
+                    help="fingerprints the CPU oracle is timed on with one thread (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, copy this many MiB device-to-device with a plain copy kernel "
                          "(reference dispatch for HBM counter calibration)")
@@ -87,29 +123,116 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "fast_lsh searches on one GPU; sharding a search over several GPUs is not "
-                                   "implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU: no search, batch or server is sharded over "
+                                   "several GPUs", "n_gpus": args.gpus}))
         sys.exit(2)
-    if args.workload == "bounded":
-        return main_bounded(args)
-    if args.workload == "serving":
-        return main_serving(args)
-    if args.workload == "batched":
-        # This mode's process ended with a host segmentation fault within its
-        # first seconds (while generating the 12 stations from 12 host threads),
-        # once in three runs; the cause is not known, so it stays switched off.
-        print(json.dumps({"error": "the batched workload mode is switched off: its process crashed on the host "
-                                   "during data generation and the cause is not yet known",
-                          "workload": "batched"}))
-        sys.exit(2)
+    if args.workload == "headline":
+        line = run_bounded(args)
+        free_gpu()
+        srv, spec0 = run_serving(args)
+        free_gpu()
+        plain = run_plain_chunk(spec0)
+        free_gpu()
+        line["metric"] = METRIC
+        line["latency_ms"] = srv["offered_load"]["latency_ms"]
+        srv["plain_search_of_history_plus_chunk"] = plain
+        line["serving"] = srv
+    elif args.workload == "station":
+        line = run_station(args)
+    elif args.workload == "bounded":
+        line = run_bounded(args)
+    elif args.workload == "serving":
+        line, _ = run_serving(args)
+        line["metric"] = METRIC
+        line["latency_ms"] = line["offered_load"]["latency_ms"]
+    else:
+        line = run_batched(args)
+    print(json.dumps(line), flush=True)
 
-    import numpy as np
+
+def free_gpu():
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def time_oracle(rows, dim, t, r, scheme, a, b, L, v, occ_num, occ_den, threads=0):
+    import oracle
+    if threads:
+        oracle.set_threads(threads)
+    used = oracle.max_threads()
+    tc = time.perf_counter()
+    oracle.search(rows, dim, t, r, scheme, a, b, L, v, occ_num, occ_den)
+    return time.perf_counter() - tc, used
+
+
+def cpu_baseline(rows_of, dim, t, r, scheme, a, b, L, v, occ_num, occ_den, args, label):
+    """The oracle timed on the host on the first fingerprints of the workload:
+    all threads on --cpu-sample rows, one thread on --cpu-sample-1t rows."""
+    import oracle
+    out = None
+    all_threads = oracle.max_threads()
+    if args.cpu_sample > 0:
+        rows = rows_of(args.cpu_sample)
+        s, used = time_oracle(rows, dim, t, r, scheme, a, b, L, v, occ_num, occ_den)
+        out = {"value": round(len(rows) / s, 1), "unit": "fingerprints/s", "cores": used, "kind": "oracle",
+               "cpu": cpu_model(),
+               "sample": f"first {len(rows)} fingerprints of {label}, searched alone (signatures + votes) in "
+                         f"{s:.1f} s on {used} threads; the pair work grows faster than N, so a slice "
+                         f"over-states the CPU rate at full size"}
+        log(f"# cpu oracle: {len(rows)} rows in {s:.1f} s on {used} threads")
+    if args.cpu_sample_1t > 0:
+        rows = rows_of(args.cpu_sample_1t)
+        s, used = time_oracle(rows, dim, t, r, scheme, a, b, L, v, occ_num, occ_den, threads=1)
+        oracle.set_threads(all_threads)
+        one = {"value": round(len(rows) / s, 1), "unit": "fingerprints/s", "cores": used,
+               "sample": f"first {len(rows)} fingerprints, {s:.1f} s on one thread"}
+        log(f"# cpu oracle: {len(rows)} rows in {s:.1f} s on 1 thread")
+        if out is None:
+            out = dict(one, kind="oracle", cpu=cpu_model())
+        else:
+            out["single_thread"] = one
+    return out
+
+
+def stage_table(prof, steps):
+    return ({k: ms / steps for k, (ms, n) in prof.items()}, {k: n / steps for k, (ms, n) in prof.items()})
+
+
+def sig_roofline(N, nf, scheme, sig_ms, launches, kernel):
+    """k_sig against the int32 VALU peak: N x F x 200 evaluations per search."""
+    evals = N * nf * 200
+    achieved = evals * OPS_PER_EVAL[scheme] / (sig_ms / 1000.0) / 1e12
+    return {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 2), "peak": round(INT_PEAK_TOPS, 2),
+            "unit": "TOP/s (int32)", "frac": round(achieved / INT_PEAK_TOPS, 4),
+            "evals_per_s": round(evals / (sig_ms / 1000.0), 1),
+            "launch_ms": round(sig_ms / max(launches, 1), 3), "launches_per_search": launches}
+
+
+def tile_roofline(work, st, tile_ms, launches):
+    """k_pairs_tile against HBM: 8 B per valid candidate pair it counts and 4 B
+    per member of the buckets it takes, over its kernel time per search."""
+    algo = BYTES_PER_VOTED_PAIR * work["big_voted"] + BYTES_PER_MEMBER * work["big_members"]
+    gbs = algo / (tile_ms / 1000.0) / 1e9
+    return {"kernel": "k_pairs_tile<17,true>", "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_search": algo,
+            "units": {"voted_pairs": work["big_voted"], "members": work["big_members"],
+                      "candidate_pairs": work["big_candidates"]},
+            "candidate_pairs_per_s": round(work["big_candidates"] / (tile_ms / 1000.0), 1),
+            "launch_ms": round(tile_ms / max(launches, 1), 3), "launches_per_search": launches,
+            "kernel_ms_per_search": round(tile_ms, 3)}
+
+
+def run_station(args):
+    """One 90-day station, every table at once."""
     import torch
 
     import synth
     import paper_1803_09835_amd as fl
 
-    N = args.n
+    N = args.n or synth.STATION_90D
     dim, t, r, scheme = 4096, 100, 4, fl.MINMAX
     L, v, occ_num, occ_den = 5, 4, 1, 100
     spec = synth.station(n=N, seed=102)
@@ -119,9 +242,7 @@ def main():
     a, b = fl.make_hash(202, fl.n_funcs(t, r, scheme))
     dev_rows = fl.to_device_rows(rows)
     ctx = fl.FastLSH(0)
-    print(f"# generated {N} fingerprints in {gen_s:.1f}s; warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
-
+    log(f"# generated {N} fingerprints in {gen_s:.1f}s; warmup {args.warmup}, steps {args.steps}")
     if args.autotune:
         ctx.configure(autotune=True)
 
@@ -136,10 +257,11 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         out = step()
-        print(f"# step {k + 1}/{args.steps}: {out[3].n_out} pairs", file=sys.stderr, flush=True)
+        log(f"# step {k + 1}/{args.steps}: {out[3].n_out} pairs")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
+    work = ctx.last_work()
     if args.calib_copy_mib:
         src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -148,41 +270,24 @@ def main():
         del src, dst
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     st = out[3]
-    value = N / (ms_per_step / 1000.0)
-
-    # Dominant kernel and its roofline (kernel time from HIP events on the
-    # context stream over the timed steps).
-    stage_ms = {k: ms / args.steps for k, (ms, n) in prof.items()}
-    stage_launch = {k: n / args.steps for k, (ms, n) in prof.items()}
+    stage_ms, stage_launch = stage_table(prof, args.steps)
     dom = max(stage_ms, key=stage_ms.get)
-    if dom == "signatures" and stage_launch[dom]:
-        evals = N * fl.n_funcs(t, r, scheme) * 200  # (fingerprint, function, set element)
-        per_launch_ms = stage_ms[dom] / max(stage_launch[dom], 1)
-        achieved = evals * OPS_PER_EVAL[scheme] / (per_launch_ms / 1000.0) / 1e12
+    sig = sig_roofline(N, fl.n_funcs(t, r, scheme), scheme, stage_ms["signatures"], stage_launch["signatures"],
+                       "k_sig<200,minmax>")
+    if dom == "signatures":
+        roof = dict(sig)
         traffic = sig_traffic(N)
-        roof = {"kernel": "k_sig<200,minmax>", "bound": "alu", "achieved": round(achieved, 2),
-                "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s (int32)",
-                "frac": round(achieved / INT_PEAK_TOPS, 4), "traffic": traffic,
-                "traffic_unit": "bytes per launch (HBM, counter runs in profiles/)",
-                "traffic_gbs": round(traffic / (per_launch_ms / 1000.0) / 1e9, 1) if traffic else None,
-                "evals_per_s": evals / (per_launch_ms / 1000.0), "launch_ms": round(per_launch_ms, 3)}
+        roof["traffic"] = traffic
+        roof["traffic_unit"] = "bytes per launch (HBM, counter runs in profiles/)"
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": None, "launch_ms": round(stage_ms[dom], 3)}
-
     line = {
         "metric": "fingerprints/s through MinHash+LSH vote count",
-        "value": round(value, 1),
+        "value": round(N / (ms_per_step / 1000.0), 1),
         "unit": "fingerprints/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "one station, 90 days at 1 s lag: 7,776,000 fingerprints, 4096-dim, 200 bits, "
                                "Markov 70 %, 2,000 repeating sources; Min-Max t=100 r=4, lag 5, v=4, "
                                "occurrence filter 1 %",
@@ -193,122 +298,12 @@ def main():
         "stage_ms": {k: round(x, 3) for k, x in stage_ms.items()},
         "launch_shapes": ctx.config_used(),
         "roofline": roof,
+        "k_pairs_tile": tile_roofline(work, st, stage_ms["big_pairs"], stage_launch["big_pairs"]),
     }
-
-    if args.cpu_sample > 0:
-        import oracle
-        ns = min(args.cpu_sample, N)
-        sample = rows[:ns]
-        tc = time.perf_counter()
-        _, _, _, ost = oracle.search(sample, dim, t, r, oracle.MINMAX, a, b, L, v, occ_num, occ_den)
-        cpu_s = time.perf_counter() - tc
-        line["cpu_baseline"] = {
-            "value": round(ns / cpu_s, 1), "unit": "fingerprints/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"first {ns} fingerprints of the same workload, full search (signatures + votes), "
-                      f"{cpu_s:.1f} s; the pair work grows with N so a slice under-states the full-size cost",
-        }
-    print(json.dumps(line), flush=True)
-
-
-def main_batched(args):
-    """12 stations of the uniform generator (50 events x 5 copies each), one
-    batched search against 12 sequential single-station searches."""
-    from concurrent.futures import ThreadPoolExecutor
-
-    import numpy as np
-    import torch
-
-    import synth
-    import paper_1803_09835_amd as fl
-
-    dim, t, r, scheme, L, v = 4096, 20, 4, fl.MINHASH, 5, 2
-    sizes = [m * 1_000_000 for m in synth.BATCH_LENGTHS_M]
-    specs = [synth.tiny_uniform(n=n, seed=1030 + s) for s, n in enumerate(sizes)]
-    tg = time.time()
-    with ThreadPoolExecutor(max_workers=12) as ex:
-        host = list(ex.map(synth.generate, specs))
-    dev = []
-    for h in host:
-        dev.append(fl.to_device_rows(h))
-    N = sum(sizes)
-    print(f"# generated and uploaded {N} fingerprints in {time.time() - tg:.1f}s", file=sys.stderr, flush=True)
-    a, b = fl.make_hash(201, fl.n_funcs(t, r, scheme))
-    ctx_b = fl.FastLSH(0)
-    ctx_s = fl.FastLSH(0)
-    if args.autotune:
-        ctx_b.configure(autotune=True)
-        ctx_s.configure(autotune=True)
-
-    def batched():
-        return ctx_b.search_batched(dev, dim, t, r, scheme, a, b, L, v, graph=args.graph)
-
-    def sequential():
-        return [ctx_s.search(d, dim, t, r, scheme, a, b, L, v, graph=args.graph) for d in dev]
-
-    def timed(fn, name, ctx):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        ctx.profile_enable(True)
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            out = fn()
-            print(f"# {name} step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
-        prof = ctx.profile_read()
-        return out, ms, {k: round(x / args.steps, 3) for k, (x, n) in prof.items()}, prof
-
-    out_b, ms_b, stage_b, prof_b = timed(batched, "batched", ctx_b)
-    out_s, ms_s, stage_s, _ = timed(sequential, "sequential", ctx_s)
-    # the two must agree pair for pair
-    offs = out_b[3]
-    same = all(torch.equal(out_b[q][offs[s]:offs[s + 1]], out_s[s][q]) for s in range(len(dev)) for q in range(3))
-    same = same and all(out_b[4][s] == out_s[s][3] for s in range(len(dev)))
-
-    evals = N * fl.n_funcs(t, r, scheme) * 200
-    dom = max(stage_b, key=stage_b.get)
-    if prof_b["signatures"][1]:
-        sig_launch_ms = prof_b["signatures"][0] / prof_b["signatures"][1]
-        achieved = evals * OPS_PER_EVAL[scheme] / (sig_launch_ms / 1000.0) / 1e12
-        roof = {"kernel": "k_sig<200,minhash> (all stations)", "bound": "alu", "achieved": round(achieved, 2),
-                "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s (int32)",
-                "frac": round(achieved / INT_PEAK_TOPS, 4), "traffic": None, "launch_ms": round(sig_launch_ms, 3)}
-    else:  # kernels inside the replayed graph are not timed one by one
-        roof = None
-    line = {
-        "metric": "fingerprints/s through MinHash+LSH vote count",
-        "value": round(N / (ms_b / 1000.0), 1),
-        "unit": "fingerprints/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "12 stations of 1-8, 10, 12, 14, 16 M fingerprints (88 M), uniform 200-of-4096 "
-                               "background with 50 events x 5 copies keeping 160 bits each; MinHash t=20 r=4, "
-                               "lag 5, v=2, no occurrence filter; one batched search",
-                   "n": N, "stations": len(sizes), "tables": t, "rows": r, "scheme": "minhash", "min_lag": L,
-                   "min_votes": v, "graph": args.graph, "autotune": args.autotune},
-        "sequential_ms_per_step": round(ms_s, 3),
-        "speedup_vs_sequential": round(ms_s / ms_b, 3),
-        "identical_to_sequential": bool(same),
-        "n_out": int(offs[-1]),
-        "e_raw": int(sum(st.e_raw for st in out_b[4])),
-        "stage_ms": stage_b,
-        "sequential_stage_ms": stage_s,
-        "launch_shapes": ctx_b.config_used(),
-        "dominant_stage": dom,
-        "roofline": roof,
-    }
-    if args.cpu_sample > 0:
-        import oracle
-        rows = host[0][: min(args.cpu_sample, len(host[0]))]
-        tc = time.perf_counter()
-        oracle.search(rows, dim, t, r, oracle.MINHASH, a, b, L, v)
-        cpu_s = time.perf_counter() - tc
-        line["cpu_baseline"] = {"value": round(len(rows) / cpu_s, 1), "unit": "fingerprints/s",
-                                "cores": oracle.max_threads(), "kind": "oracle",
-                                "sample": f"the 1 M-fingerprint station searched alone, {cpu_s:.1f} s"}
-    print(json.dumps(line), flush=True)
+    line["cpu_baseline"] = cpu_baseline(lambda m: rows[:min(m, N)], dim, t, r, scheme, a, b, L, v, occ_num,
+                                        occ_den, args, "the same workload")
+    ctx.close()
+    return line
 
 
 def upload_generated(spec, lo=0, hi=None, chunk=16_000_000):
@@ -326,12 +321,12 @@ def upload_generated(spec, lo=0, hi=None, chunk=16_000_000):
         c1 = min(hi, c0 + chunk)
         synth.generate(spec, c0, c1, out=pinned[: c1 - c0].numpy().view(np.uint16))
         dev[c0 - lo:c1 - lo].copy_(pinned[: c1 - c0])
-        print(f"# generated rows {c0}..{c1}", file=sys.stderr, flush=True)
+        log(f"# generated rows {c0}..{c1}")
     del pinned
     return dev
 
 
-def main_bounded(args):
+def run_bounded(args):
     """One 5-year station with the bounded-memory search (tables in groups)."""
     import numpy as np
     import torch
@@ -339,12 +334,12 @@ def main_bounded(args):
     import synth
     import paper_1803_09835_amd as fl
 
-    N = synth.STATION_5Y if args.n == 7_776_000 else args.n
+    N = args.n or synth.STATION_5Y
     dim, t, r, scheme, L, v, occ_num, occ_den = 4096, 100, 4, fl.MINMAX, 5, 4, 1, 100
     spec = synth.long_station(n=N, seed=105)
     tg = time.time()
     dev = upload_generated(spec)
-    print(f"# generated and uploaded {N} fingerprints in {time.time() - tg:.1f}s", file=sys.stderr, flush=True)
+    log(f"# generated and uploaded {N} fingerprints in {time.time() - tg:.1f}s")
     a, b = fl.make_hash(205, fl.n_funcs(t, r, scheme))
     ctx = fl.FastLSH(0)
     gt = args.group_tables
@@ -354,23 +349,26 @@ def main_bounded(args):
 
     for k in range(args.warmup):
         out = step()
-        print(f"# warm-up {k + 1}/{args.warmup}: {out[3].n_out} pairs", file=sys.stderr, flush=True)
+        log(f"# warm-up {k + 1}/{args.warmup}: {out[3].n_out} pairs")
     torch.cuda.synchronize()
     ctx.profile_enable(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
         out = step()
-        print(f"# step {k + 1}/{args.steps}: {out[3].n_out} pairs", file=sys.stderr, flush=True)
+        log(f"# step {k + 1}/{args.steps}: {out[3].n_out} pairs")
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     prof = ctx.profile_read()
-    stage_ms = {k: round(x / args.steps, 3) for k, (x, n) in prof.items()}
+    work = ctx.last_work()
+    stage_ms, stage_launch = stage_table(prof, args.steps)
     st = out[3]
-    # signature kernel: 2 x t tables of work per search (both passes)
-    sig_ms = prof["signatures"][0] / args.steps
-    evals = 2 * N * fl.n_funcs(t, r, scheme) * 200
-    sig_tops = evals * OPS_PER_EVAL[scheme] / (sig_ms / 1000.0) / 1e12
     dom = max(stage_ms, key=stage_ms.get)
+    sig = sig_roofline(N, fl.n_funcs(t, r, scheme), scheme, stage_ms["signatures"], stage_launch["signatures"],
+                       "k_sig<200,minmax> (each table once)")
+    tile = tile_roofline(work, st, stage_ms["big_pairs"], stage_launch["big_pairs"])
+    roof = tile if dom == "big_pairs" else (sig if dom == "signatures" else
+                                             {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
+                                              "unit": "GB/s", "frac": None, "traffic": None})
     line = {
         "metric": "fingerprints/s through MinHash+LSH vote count",
         "value": round(N / (ms / 1000.0), 1),
@@ -384,30 +382,30 @@ def main_bounded(args):
                    "occ": f"{occ_num}/{occ_den}", "group_tables": gt},
         "candidate_pairs_per_s": round(st.e_raw / (ms / 1000.0), 1),
         "stats": st.__dict__,
-        "stage_ms": stage_ms,
+        "stage_ms": {k: round(x, 3) for k, x in stage_ms.items()},
         "dominant_stage": dom,
         "hbm_gb": {"fingerprints": round(dev.numel() * 2 / 1e9, 1),
                    "workspace": round(ctx.workspace_bytes() / 1e9, 1)},
-        "roofline": {"kernel": "k_sig<200,minmax> (both passes)", "bound": "alu", "achieved": round(sig_tops, 2),
-                     "peak": round(INT_PEAK_TOPS, 2), "unit": "TOP/s (int32)",
-                     "frac": round(sig_tops / INT_PEAK_TOPS, 4), "traffic": None,
-                     "launch_ms": round(sig_ms / max(prof["signatures"][1] / args.steps, 1), 3)},
+        "roofline": roof,
+        "k_sig": sig,
     }
-    if args.cpu_sample > 0:
-        import oracle
-        ns = min(args.cpu_sample, N)
-        rows = dev[:ns].cpu().numpy().view(np.uint16)
-        tc = time.perf_counter()
-        oracle.search(rows, dim, t, r, oracle.MINMAX, a, b, L, v, occ_num, occ_den)
-        cpu_s = time.perf_counter() - tc
-        line["cpu_baseline"] = {"value": round(ns / cpu_s, 1), "unit": "fingerprints/s",
-                                "cores": oracle.max_threads(), "kind": "oracle",
-                                "sample": f"first {ns} fingerprints searched alone, {cpu_s:.1f} s; the pair work "
-                                          f"grows with N, so a slice over-states the CPU rate at full size"}
-    print(json.dumps(line), flush=True)
+    if dom != "big_pairs":
+        line["k_pairs_tile"] = tile
+    ctx.close()
+    del ctx
+    line["cpu_baseline"] = cpu_baseline(lambda m: dev[:min(m, N)].cpu().numpy().view(np.uint16), dim, t, r,
+                                        scheme, a, b, L, v, occ_num, occ_den, args, "the 5-year station")
+    del dev
+    return line
 
 
-def main_serving(args):
+def serving_specs(S, n_hist, n_stream):
+    import synth
+    return [synth.Spec(n=n_hist + n_stream[s], seed=1040 + s, markov_keep=140, n_sources=4000, rep_min=3,
+                       rep_max=40, jac_lo_milli=400, jac_hi_milli=900, chain_len=1_000_000) for s in range(S)]
+
+
+def run_serving(args):
     """Stations of 180 days resident; 3,600-row chunks arrive as independent
     Poisson streams and are searched and inserted as they come."""
     import numpy as np
@@ -418,7 +416,7 @@ def main_serving(args):
 
     S, CH = args.stations, synth.CHUNK
     dim, t, r, scheme, L, v = 4096, 100, 4, fl.MINMAX, 5, 4
-    n_hist = synth.STATION_180D if args.n == 7_776_000 else args.n
+    n_hist = synth.STATION_180D if args.workload in ("headline",) or not args.n else args.n
     # arrivals: station s at rate/S per second (exponential gaps, seed 304)
     rng = np.random.default_rng(304)
     per = args.rate / S
@@ -433,18 +431,16 @@ def main_serving(args):
                    slack_rows=max(n_stream) + CH)
     streams = []
     tg = time.time()
-    for s in range(S):
-        spec = synth.Spec(n=n_hist + n_stream[s], seed=1040 + s, markov_keep=140, n_sources=4000, rep_min=3,
-                          rep_max=40, jac_lo_milli=400, jac_hi_milli=900, chain_len=1_000_000)
+    specs = serving_specs(S, n_hist, n_stream)
+    for s, spec in enumerate(specs):
         hist = upload_generated(spec, 0, n_hist)
         sv.add_station(hist)
         del hist
         torch.cuda.empty_cache()
         rows = synth.generate(spec, n_hist, n_hist + n_stream[s])
         streams.append(fl.to_device_rows(rows))
-        print(f"# station {s}: {n_hist} history rows resident, {n_stream[s]} stream rows ready "
-              f"({time.time() - tg:.1f}s)", file=sys.stderr, flush=True)
-    info0 = sv.info()
+        log(f"# station {s}: {n_hist} history rows resident, {n_stream[s]} stream rows ready "
+            f"({time.time() - tg:.1f}s)")
 
     def run(events, label):
         """Submit (offset_s, station, chunk) at their times; latencies in ms."""
@@ -462,7 +458,7 @@ def main_serving(args):
             tickets.append((at, sv.submit(s, streams[s][c * CH:(c + 1) * CH], at)))
             if time.perf_counter() - last > 10:
                 last = time.perf_counter()
-                print(f"# {label}: {k + 1}/{len(events)} submitted", file=sys.stderr, flush=True)
+                log(f"# {label}: {k + 1}/{len(events)} submitted")
         lat, done, pairs = [], [], 0
         for at, tk in tickets:
             st, dn = sv.poll(tk, wait=True)
@@ -474,8 +470,7 @@ def main_serving(args):
         return np.array(lat), len(tickets) / span, pairs
 
     lat, thr, pairs = run([(off, s, c) for off, s, c in ev], f"offered {args.rate}/s")
-    print(f"# offered load done: p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms",
-          file=sys.stderr, flush=True)
+    log(f"# offered load done: p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms")
     info1 = sv.info()
     sat_events = [(0.0, s, used[s] + c) for c in range(ramp) for s in range(S)]
     slat, sthr, _ = run(sat_events, "saturation")
@@ -501,6 +496,7 @@ def main_serving(args):
                          "pairs": int(pairs)},
         "saturation": {"chunks": len(sat_events), "chunks_per_s": round(sthr, 2), "batches": batches,
                        "mean_batch": round(len(sat_events) / max(batches, 1), 2),
+                       "fingerprints_per_s": round(sthr * CH, 1),
                        "latency_ms": {"p50": round(float(np.percentile(slat, 50)), 3),
                                       "p99": round(float(np.percentile(slat, 99)), 3)}},
         "hbm_gb": {"resident": round(info2["resident_bytes"] / 1e9, 1),
@@ -509,7 +505,131 @@ def main_serving(args):
         "roofline": None,
     }
     sv.close()
-    print(json.dumps(line), flush=True)
+    del sv, streams
+    return line, specs[0]
+
+
+def run_plain_chunk(spec, reps=3):
+    """The plain path for one chunk: a full search of a served station's
+    history plus its first chunk (15,555,600 fingerprints of that station's
+    rows), whose pairs with the later member in the chunk are that chunk's
+    result.  Returns its time."""
+    import torch
+
+    import synth
+    import paper_1803_09835_amd as fl
+
+    CH = synth.CHUNK
+    n_hist = synth.STATION_180D
+    dim, t, r, scheme, L, v = 4096, 100, 4, fl.MINMAX, 5, 4
+    dev = upload_generated(spec, 0, n_hist + CH)
+    a, b = fl.make_hash(204, fl.n_funcs(t, r, scheme))
+    ctx = fl.FastLSH(0)
+    ctx.search(dev, dim, t, r, scheme, a, b, L, v)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = ctx.search(dev, dim, t, r, scheme, a, b, L, v)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1000.0)
+    n_chunk = int((out[1] >= n_hist).sum().item())
+    log(f"# plain search of history + chunk: {min(ms):.1f} ms, {n_chunk} pairs end in the chunk")
+    ctx.close()
+    del dev, ctx
+    return {"n": n_hist + CH, "ms": round(sorted(ms)[len(ms) // 2], 3), "reps": reps,
+            "pairs_ending_in_chunk": n_chunk}
+
+
+def run_batched(args):
+    """12 stations of the uniform generator (50 events x 5 copies each), one
+    batched search against 12 sequential single-station searches."""
+    import torch
+
+    import synth
+    import paper_1803_09835_amd as fl
+
+    dim, t, r, scheme, L, v = 4096, 20, 4, fl.MINHASH, 5, 2
+    sizes = [m * 1_000_000 for m in synth.BATCH_LENGTHS_M]
+    specs = [synth.tiny_uniform(n=n, seed=1030 + s) for s, n in enumerate(sizes)]
+    # one station after another (each generation is OpenMP-parallel inside),
+    # before the GPU is touched
+    tg = time.time()
+    host = []
+    for s, sp in enumerate(specs):
+        host.append(synth.generate(sp))
+        log(f"# station {s}: {sp.n} rows generated ({time.time() - tg:.1f}s)")
+    dev = [fl.to_device_rows(h) for h in host]
+    N = sum(sizes)
+    log(f"# generated and uploaded {N} fingerprints in {time.time() - tg:.1f}s")
+    a, b = fl.make_hash(201, fl.n_funcs(t, r, scheme))
+    ctx_b = fl.FastLSH(0)
+    ctx_s = fl.FastLSH(0)
+    if args.autotune:
+        ctx_b.configure(autotune=True)
+        ctx_s.configure(autotune=True)
+
+    def batched():
+        return ctx_b.search_batched(dev, dim, t, r, scheme, a, b, L, v, graph=args.graph)
+
+    def sequential():
+        return [ctx_s.search(d, dim, t, r, scheme, a, b, L, v, graph=args.graph) for d in dev]
+
+    def timed(fn, name, ctx):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            out = fn()
+            log(f"# {name} step {k + 1}/{args.steps}")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        prof = ctx.profile_read()
+        return out, ms, {k: round(x / args.steps, 3) for k, (x, n) in prof.items()}, prof
+
+    out_b, ms_b, stage_b, prof_b = timed(batched, "batched", ctx_b)
+    out_s, ms_s, stage_s, _ = timed(sequential, "sequential", ctx_s)
+    # the two must agree pair for pair
+    offs = out_b[3]
+    same = all(torch.equal(out_b[q][offs[s]:offs[s + 1]], out_s[s][q]) for s in range(len(dev)) for q in range(3))
+    same = same and all(out_b[4][s] == out_s[s][3] for s in range(len(dev)))
+
+    dom = max(stage_b, key=stage_b.get)
+    if prof_b["signatures"][1]:
+        roof = sig_roofline(N, fl.n_funcs(t, r, scheme), scheme, prof_b["signatures"][0] / args.steps,
+                            prof_b["signatures"][1] / args.steps, "k_sig<200,minhash> (all stations)")
+        roof["traffic"] = None
+    else:  # kernels inside the replayed graph are not timed one by one
+        roof = None
+    line = {
+        "metric": "fingerprints/s through MinHash+LSH vote count",
+        "value": round(N / (ms_b / 1000.0), 1),
+        "unit": "fingerprints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "12 stations of 1-8, 10, 12, 14, 16 M fingerprints (88 M), uniform 200-of-4096 "
+                               "background with 50 events x 5 copies keeping 160 bits each; MinHash t=20 r=4, "
+                               "lag 5, v=2, no occurrence filter; one batched search",
+                   "n": N, "stations": len(sizes), "tables": t, "rows": r, "scheme": "minhash", "min_lag": L,
+                   "min_votes": v, "graph": args.graph, "autotune": args.autotune},
+        "sequential_ms_per_step": round(ms_s, 3),
+        "speedup_vs_sequential": round(ms_s / ms_b, 3),
+        "identical_to_sequential": bool(same),
+        "n_out": int(offs[-1]),
+        "e_raw": int(sum(st.e_raw for st in out_b[4])),
+        "stage_ms": stage_b,
+        "sequential_stage_ms": stage_s,
+        "launch_shapes": ctx_b.config_used(),
+        "dominant_stage": dom,
+        "roofline": roof,
+    }
+    line["cpu_baseline"] = cpu_baseline(lambda m: host[0][:min(m, len(host[0]))], dim, t, r, scheme, a, b, L, v,
+                                        0, 0, args, "the 1 M-fingerprint station")
+    ctx_b.close()
+    ctx_s.close()
+    return line
 
 
 if __name__ == "__main__":

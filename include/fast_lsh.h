@@ -345,8 +345,9 @@ int fast_lsh_workspace_bytes(fast_lsh_ctx *ctx, uint64_t *bytes);
 
 /* Stage timing.  While enabled, the context records a pair of HIP events on
  * its stream around every kernel launch of the stages below and accumulates
- * their elapsed times when each call completes.  Enabling resets the
- * counters.  Stages: */
+ * their elapsed times when each call completes (there is no limit on the
+ * number of launches a call records).  Enabling resets the counters.
+ * Stages: */
 enum {
   FAST_LSH_STAGE_SIGNATURES = 0, /* signature kernel                          */
   FAST_LSH_STAGE_GROUP = 1,      /* the radix passes that bin every table     */
@@ -357,7 +358,11 @@ enum {
   FAST_LSH_STAGE_OUTPUT = 6,     /* canonical sort of the reported pairs      */
   FAST_LSH_STAGE_GRAPH = 7,      /* replay of the captured graph (stages 0-4
                                     together, FAST_LSH_USE_GRAPH only)        */
-  FAST_LSH_PROFILE_STAGES = 8
+  FAST_LSH_STAGE_SPLIT_KEYS = 8, /* bounded search, second pass: a group's
+                                    mixed keys rebuilt from stored words      */
+  FAST_LSH_STAGE_CHANNEL_MERGE = 9, /* fast_lsh_channel_merge                 */
+  FAST_LSH_STAGE_CLUSTERS = 10,  /* fast_lsh_station_clusters                 */
+  FAST_LSH_PROFILE_STAGES = 11
 };
 
 typedef struct {
@@ -367,6 +372,87 @@ typedef struct {
 
 int fast_lsh_profile_enable(fast_lsh_ctx *ctx, int enable);
 int fast_lsh_profile_read(fast_lsh_ctx *ctx, fast_lsh_profile *out);
+
+/* Work counters of the last search on the context (fast_lsh_search,
+ * _search_ex, _search_batched, _search_bounded), for rooflines: the buckets
+ * above 32 members, whose pairs the tiled kernel checks.  big_members sums
+ * their sizes m and big_candidates their in-bucket pairs C(m, 2) (over every
+ * table; part of e_raw); big_voted counts those pairs that pass the lag and
+ * the exclusion (part of e_voted).  search_calls counts the searches
+ * completed on the context.  Zero before the first search. */
+typedef struct {
+  uint64_t big_voted, big_members, big_candidates, search_calls;
+} fast_lsh_work;
+
+int fast_lsh_last_work(fast_lsh_ctx *ctx, fast_lsh_work *out);
+
+/* ------------------------------------------------------------------------
+ * Spatiotemporal alignment of search outputs (section 7)
+ * ------------------------------------------------------------------------ */
+
+/* One channel's search output: count pairs (i[k], j[k], votes[k]) with
+ * i < j, all DEVICE pointers (the arrays a search returns).  As a triplet of
+ * section 7.2 a pair is (dt, idx1, sim) = (j - i, i, votes). */
+typedef struct {
+  const uint32_t *i, *j;
+  const uint8_t *votes;
+  uint64_t count;
+} fast_lsh_pairs;
+
+/* Channel-level merge (section 7.1 "Channel Level"; section 7.2 "Channel",
+ * sort-merge-reduce): the similarity matrices of the n_channels channels of
+ * one station (same time base) are summed, and entries whose summed
+ * similarity is below min_sim are dropped.
+ *
+ * channels: HOST array of n_channels descriptors (device arrays; any order
+ * of pairs within a channel; a channel should not repeat a pair, repeats
+ * are summed like entries of different channels).  n_fingerprints: the
+ * station's fingerprint count, every id must be below it (at most 2^32 - 1).
+ * Output: DEVICE arrays out_dt, out_idx1, out_sim (uint32, caller-owned) of
+ * the combined entries with sim >= min_sim, ordered by (dt, idx1); *n_out
+ * (HOST) is their number.  E_CAPACITY when *n_out > capacity (nothing
+ * written; call again with room for *n_out); E_INVALID for NULL pointers or
+ * a pair with j <= i or j >= n_fingerprints.  Workspace: about 40 bytes per
+ * input pair.  Blocking (returns when the outputs are written). */
+int fast_lsh_channel_merge(fast_lsh_ctx *ctx, uint32_t n_channels, const fast_lsh_pairs *channels,
+                           uint64_t n_fingerprints, uint32_t min_sim, uint32_t *out_dt, uint32_t *out_idx1,
+                           uint32_t *out_sim, uint64_t capacity, uint64_t *n_out);
+
+/* Station-level clustering parameters (section 7.2 "Station"; the paper
+ * gives no values).  A run along one diagonal continues while consecutive
+ * entries' idx1 differ by at most max_gap; runs of diagonals dt and dt + 1
+ * join when their idx1 spans [lo, hi] come within max_gap of each other
+ * (equivalently: the clusters are the connected components of the entries,
+ * two entries being neighbours when their dt differ by at most one and their
+ * idx1 by at most max_gap).  A cluster is kept when its width
+ * dt_max - dt_min + 1 is at most max_width ("relatively narrow"), it holds
+ * at least min_entries entries and its summed similarity is at least
+ * min_sum (small clusters and isolated matches are pruned). */
+typedef struct {
+  uint32_t max_gap, max_width, min_entries, reserved; /* reserved: set to 0 */
+  uint64_t min_sum;
+} fast_lsh_cluster_params;
+
+/* One kept cluster: its bounding box, entry count, summed similarity and
+ * strongest entry (largest sim; among equal sims the first in (dt, idx1)
+ * order).  40 bytes. */
+typedef struct {
+  uint32_t dt_min, dt_max, idx1_min, idx1_max;
+  uint32_t n_entries, peak_sim, peak_dt, peak_idx1;
+  uint64_t sim_sum;
+} fast_lsh_cluster;
+
+/* Station-level clustering (section 7.1 "Station Level"; section 7.2
+ * "Station") of n combined entries (dt[k], idx1[k], sim[k]), DEVICE arrays
+ * strictly ordered by (dt, idx1) (the channel merge's output), n < 2^32,
+ * every sim below 2^24.  Output: the kept clusters in the order of their
+ * first entry, written to the DEVICE array out (caller-owned); *n_out
+ * (HOST) is their number.  E_CAPACITY when *n_out > capacity (nothing
+ * written); E_INVALID for NULL pointers, entries out of order or repeated,
+ * or a sim of 2^24 or more.  Workspace: about 50 bytes per entry.  Blocking. */
+int fast_lsh_station_clusters(fast_lsh_ctx *ctx, const uint32_t *dt, const uint32_t *idx1, const uint32_t *sim,
+                              uint64_t n, const fast_lsh_cluster_params *params, fast_lsh_cluster *out,
+                              uint64_t capacity, uint64_t *n_out);
 
 #ifdef __cplusplus
 }

@@ -32,19 +32,31 @@ int fl_fail(int code, const char* fmt, ...) {
 // Context and workspace
 // ---------------------------------------------------------------------------
 void prof_begin(fast_lsh_ctx* c, int stage) {
-  if (!c->prof || c->nrec >= fast_lsh_ctx::kMaxRec) return;
-  if (c->ev.empty()) {
-    c->ev.resize(2 * fast_lsh_ctx::kMaxRec);
-    for (auto& e : c->ev) (void)hipEventCreate(&e);
+  if (!c->prof) return;
+  if ((size_t)c->nrec >= c->rec_stage.size()) {
+    // grow the pool by 256 intervals; when an event cannot be created the
+    // launch goes untimed and fast_lsh_profile_read reports E_DEVICE
+    const size_t old = c->ev.size();
+    c->ev.resize(old + 512, nullptr);
+    for (size_t k = old; k < c->ev.size(); ++k)
+      if (hipEventCreate(&c->ev[k]) != hipSuccess) {
+        (void)hipGetLastError();
+        c->ev.resize(k & ~(size_t)1);
+        c->prof_lost = true;
+        return;
+      }
+    c->rec_stage.resize(c->ev.size() / 2);
   }
   c->rec_stage[c->nrec] = stage;
   (void)hipEventRecord(c->ev[2 * c->nrec], c->stream);
+  c->rec_open = true;
 }
 
 void prof_end(fast_lsh_ctx* c) {
-  if (!c->prof || c->nrec >= fast_lsh_ctx::kMaxRec) return;
+  if (!c->prof || !c->rec_open) return;
   (void)hipEventRecord(c->ev[2 * c->nrec + 1], c->stream);
   ++c->nrec;
+  c->rec_open = false;
 }
 
 // Accumulate recorded intervals (the caller has synchronised the stream).
@@ -307,6 +319,8 @@ int fast_lsh_profile_enable(fast_lsh_ctx* c, int enable) {
   if (!c) return fl_fail(FAST_LSH_E_INVALID, "ctx is NULL");
   c->prof = enable != 0;
   c->nrec = 0;
+  c->rec_open = false;
+  c->prof_lost = false;
   for (int k = 0; k < FAST_LSH_PROFILE_STAGES; ++k) {
     c->prof_ms[k] = 0;
     c->prof_launches[k] = 0;
@@ -316,10 +330,17 @@ int fast_lsh_profile_enable(fast_lsh_ctx* c, int enable) {
 
 int fast_lsh_profile_read(fast_lsh_ctx* c, fast_lsh_profile* out) {
   if (!c || !out) return fl_fail(FAST_LSH_E_INVALID, "ctx or out is NULL");
+  if (c->prof_lost) return fl_fail(FAST_LSH_E_DEVICE, "stage timing lost launches: a HIP event could not be created");
   for (int k = 0; k < FAST_LSH_PROFILE_STAGES; ++k) {
     out->ms[k] = c->prof_ms[k];
     out->launches[k] = c->prof_launches[k];
   }
+  return FAST_LSH_OK;
+}
+
+int fast_lsh_last_work(fast_lsh_ctx* c, fast_lsh_work* out) {
+  if (!c || !out) return fl_fail(FAST_LSH_E_INVALID, "ctx or out is NULL");
+  *out = c->last_work;
   return FAST_LSH_OK;
 }
 

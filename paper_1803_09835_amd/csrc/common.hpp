@@ -215,6 +215,7 @@ struct PairArgs {
   const uint64_t* station_base;    // nstation + 1 entries
   uint32_t nstation;
   const unsigned long long* n_flagged;  // total excluded (device), 0: skip flag lookups
+  unsigned long long* big_voted;   // [kSpread] pairs counted in e_voted by the tiled kernel (or nullptr)
 };
 
 // Station of a (global) fingerprint id, for nb stations with ascending bases.

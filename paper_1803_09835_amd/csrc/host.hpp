@@ -33,7 +33,9 @@ void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64
                    hipStream_t s);
 // pairs.hip
 void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, hipStream_t s);
-void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, hipStream_t s);
+void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, unsigned long long* work,
+                        hipStream_t s);
+void launch_work_reduce(const unsigned long long* work, unsigned long long* out, hipStream_t s);
 void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hipStream_t s);
 void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* owner, uint64_t unit_base, uint32_t nunits,
                        const uint4* big, uint32_t tb_size, uint32_t rswl, hipStream_t s);
@@ -105,6 +107,7 @@ struct fast_lsh_ctx {
   uint64_t res_count = 0;
   uint32_t res_stations = 0;
   bool res_valid = false;
+  fast_lsh_work last_work = {0, 0, 0, 0};  // work counters of the last search
   // launch-shape tuning
   fast_lsh_config config;
   std::map<std::vector<uint64_t>, TuneChoice> tuned;  // shape key -> choice
@@ -113,12 +116,14 @@ struct fast_lsh_ctx {
   hipGraphExec_t graph = nullptr;
   std::vector<uint64_t> graph_key;
   uint64_t graph_replays = 0;
-  // stage timing (HIP events on the context stream around each launch)
-  static constexpr int kMaxRec = 256;
+  // stage timing (HIP events on the context stream around each launch; the
+  // event pool grows with the launches of one call)
   bool prof = false;
-  std::vector<hipEvent_t> ev;
-  int rec_stage[kMaxRec];
+  std::vector<hipEvent_t> ev;  // two per recorded interval
+  std::vector<int> rec_stage;
   int nrec = 0;
+  bool rec_open = false;   // an interval's start is recorded, its end not yet
+  bool prof_lost = false;  // an event could not be created: some launches went untimed
   double prof_ms[FAST_LSH_PROFILE_STAGES] = {0};
   uint64_t prof_launches[FAST_LSH_PROFILE_STAGES] = {0};
 };

@@ -283,6 +283,7 @@ __device__ void flush_tally(const PairArgs& a, PairTally tl) {
     const uint64_t o = (uint64_t)tl.station * kSpread + spread_slot();
     if (tl.ev) atomicAdd(a.e_voted + o, tl.ev);
     if (tl.nd) atomicAdd(a.n_distinct + o, tl.nd);
+    if (tl.ev && a.big_voted) atomicAdd(a.big_voted + spread_slot(), tl.ev);
     return;
   }
   unsigned long long ev = tl.ev, nd = tl.nd;
@@ -294,6 +295,7 @@ __device__ void flush_tally(const PairArgs& a, PairTally tl) {
     const uint64_t o = (uint64_t)s0 * kSpread + spread_slot();
     if (ev) atomicAdd(a.e_voted + o, ev);
     if (nd) atomicAdd(a.n_distinct + o, nd);
+    if (ev && a.big_voted) atomicAdd(a.big_voted + spread_slot(), ev);
   }
 }
 
@@ -497,12 +499,44 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
 
 // Tiles of each large bucket: the upper triangle, diagonal included, of its
 // ceil(m / tb) x ceil(m / tb) grid of tb x tb tiles (m members; an empty
-// descriptor has none).
-__global__ __launch_bounds__(kPT) void k_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles) {
+// descriptor has none).  Also adds the buckets' members and in-bucket pairs
+// C(m, 2) to work[kSpread..2 kSpread) and work[2 kSpread..3 kSpread)
+// (measurement counters, summed by k_work_reduce).
+__global__ __launch_bounds__(kPT) void k_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles,
+                                                     unsigned long long* work) {
   const uint64_t b = (uint64_t)blockIdx.x * kPT + threadIdx.x;
-  if (b >= nbig) return;
-  const uint64_t m = big[b].z, ntl = (m + tb - 1) / tb;
-  tiles[b] = m < 2 ? 0 : ntl * (ntl + 1) / 2;
+  const uint64_t m = b < nbig ? big[b].z : 0;
+  if (b < nbig) {
+    const uint64_t ntl = (m + tb - 1) / tb;
+    tiles[b] = m < 2 ? 0 : ntl * (ntl + 1) / 2;
+  }
+  unsigned long long mem = m < 2 ? 0 : m, cand = m < 2 ? 0 : m * (m - 1) / 2;
+  for (int o = 32; o > 0; o >>= 1) {
+    mem += __shfl_xor(mem, o, 64);
+    cand += __shfl_xor(cand, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && mem) {
+    const uint32_t slot = spread_slot();
+    atomicAdd(work + kSpread + slot, mem);
+    atomicAdd(work + 2 * kSpread + slot, cand);
+  }
+}
+
+// work[3][kSpread] summed into out[3] (one workgroup).
+__global__ __launch_bounds__(kPT) void k_work_reduce(const unsigned long long* work, unsigned long long* out) {
+  __shared__ unsigned long long part[3][kPT / 64];
+  for (int f = 0; f < 3; ++f) {
+    unsigned long long x = 0;
+    for (uint32_t k = threadIdx.x; k < kSpread; k += kPT) x += work[f * kSpread + k];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) part[f][threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long x = 0;
+    for (uint32_t w = 0; w < kPT / 64; ++w) x += part[threadIdx.x][w];
+    out[threadIdx.x] = x;
+  }
 }
 
 // The bucket of every tile unit: owner[q] = b for q in [toff[b], toff[b+1])
@@ -750,8 +784,14 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
   }
 }
 
-void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, hipStream_t s) {
-  if (nbig) hipLaunchKernelGGL(k_tile_counts, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, big, nbig, tb, tiles);
+void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, unsigned long long* work,
+                        hipStream_t s) {
+  if (nbig)
+    hipLaunchKernelGGL(k_tile_counts, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, big, nbig, tb, tiles, work);
+}
+
+void launch_work_reduce(const unsigned long long* work, unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_work_reduce, dim3(1), dim3(kPT), 0, s, work, out);
 }
 
 void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hipStream_t s) {

@@ -76,6 +76,7 @@ struct Ctrl {
   unsigned long long st_flagged[FAST_LSH_MAX_STATIONS];
   unsigned long long st_sum[4 * FAST_LSH_MAX_STATIONS];  // e_raw, max_bucket, e_voted, n_distinct
   unsigned long long st_offs[FAST_LSH_MAX_STATIONS + 1];
+  unsigned long long work[3];  // tiled buckets: voted pairs, members, in-bucket pairs
 };
 
 // Everything the fixed-shape prefix launches read.
@@ -102,6 +103,7 @@ struct Job {
   uint4 *bdesc, *bins;
   uint32_t bigbin_grid;
   uint64_t spread_bytes;
+  unsigned long long* work;  // [3][kSpread]: tiled buckets' voted pairs, members, in-bucket pairs
   uint32_t rswl;
   BucketArgs ba;
   PairArgs pa;
@@ -269,7 +271,7 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   const uint32_t fit = 65536 / (8 * j.rswl + 8);
   uint32_t tb = 128;
   while (tb > 16 && tb > fit) tb >>= 1;
-  launch_tile_counts(j.bdesc, big_count, tb, toff, s);
+  launch_tile_counts(j.bdesc, big_count, tb, toff, j.work, s);
   scan_u64(toff, big_count, 1, sums, toff + big_count, s);
   LAUNCHCK();
   uint64_t units = 0;
@@ -280,10 +282,12 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   LAUNCHCK();
   // at most 2^22 workgroups of 256 threads per launch (work-items per grid
   // dimension stay below 2^32)
+  PairArgs pa = j.pa;
+  pa.big_voted = j.work;
   for (uint64_t u0 = 0; u0 < units; u0 += 1u << 22) {
     const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 22, units - u0);
     prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
-    launch_pairs_tile(j.pa, toff, owner, u0, cnt, j.bdesc, tb, j.rswl, s);
+    launch_pairs_tile(pa, toff, owner, u0, cnt, j.bdesc, tb, j.rswl, s);
     prof_end(c);
     LAUNCHCK();
   }
@@ -343,10 +347,15 @@ int finish_output(fast_lsh_ctx* c, Job& j, uint64_t cnt, bool distinct, fast_lsh
   }
   launch_station_offsets(rk0, cnt, j.sbase, S, j.ctrl->st_offs, s);
   launch_spread_reduce(j.er, j.mb, j.ev, j.nd, S, j.ctrl->st_sum, s);
+  launch_work_reduce(j.work, j.ctrl->work, s);
   LAUNCHCK();
   Ctrl hc;
   RC(d2h(c, &hc, j.ctrl));
   prof_collect(c);
+  c->last_work.big_voted = hc.work[0];
+  c->last_work.big_members = hc.work[1];
+  c->last_work.big_candidates = hc.work[2];
+  c->last_work.search_calls += 1;
   c->res_count = cnt;
   c->res_valid = true;
   for (uint32_t st = 0; st < S; ++st) {
@@ -421,6 +430,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   j.ev = j.er + (uint64_t)S * kSpread;
   j.nd = j.ev + (uint64_t)S * kSpread;
   j.mb = reinterpret_cast<unsigned int*>(j.nd + (uint64_t)S * kSpread);
+  RC(ws<unsigned long long>(c, "work", 3 * kSpread, &j.work));
   RC(ws<uint64_t>(c, "mkeys", tn, &j.mkeys));
   RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_pitch, &j.rows));
   RC(ws<uint64_t>(c, "ak", tn, &j.ak));
@@ -568,6 +578,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
 
   // 4b. large buckets; 4c. a second pair pass if the output overflowed
   for (int attempt = 0; attempt < 2; ++attempt) {
+    fill_u64(reinterpret_cast<uint64_t*>(j.work), 3 * kSpread, 0, s);
     if (attempt == 1) {
       out_cap = (uint64_t)hc.out_count + 1024;
       RC(set_out_buffers(c, j, out_cap));
@@ -644,6 +655,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   j.ev = j.er + kSpread;
   j.nd = j.ev + kSpread;
   j.mb = reinterpret_cast<unsigned int*>(j.nd + kSpread);
+  RC(ws<unsigned long long>(c, "work", 3 * kSpread, &j.work));
   uint32_t* hi32;
   RC(ws<uint32_t>(c, "rows", (uint64_t)j.pl.G * N * j.pl.row_pitch, &j.rows));
   RC(ws<uint32_t>(c, "hi32", (uint64_t)t * N, &hi32));
@@ -721,7 +733,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   // Pass 2 rebuilds the group's mixed keys (mix48(key) << 16) from the high
   // words and sub-key rows pass 1 stored, instead of recomputing signatures.
   auto group = [&](uint32_t tb, uint32_t tc, bool first_pass) -> int {
-    prof_begin(c, FAST_LSH_STAGE_SIGNATURES);
+    prof_begin(c, first_pass ? FAST_LSH_STAGE_SIGNATURES : FAST_LSH_STAGE_SPLIT_KEYS);
     if (first_pass) {
       SigArgs sa = fl_sig_args(h, f, j.dhash, &j.ctrl->err);
       sa.table_begin = tb;
@@ -786,6 +798,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   for (int attempt = 0; attempt < 2; ++attempt) {
     RC(set_out_buffers(c, j, out_cap));
     fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * kSpread * sizeof(unsigned long long), 0, s);
+    fill_u64(reinterpret_cast<uint64_t*>(j.work), 3 * kSpread, 0, s);
     fill_u32(&j.ctrl->out_count, 1, 0, s);
     for (uint32_t g = 0; g < ngroups; ++g) {
       const uint32_t tb = g * TGm, tc = std::min(TGm, t - tb);

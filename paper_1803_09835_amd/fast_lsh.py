@@ -41,7 +41,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [(f, _u64) for f in ("n_out", "e_raw", "e_voted", "n_distinct", "n_flagged", "max_bucket")]
 
 
-PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pairs", "output", "graph")
+PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pairs", "output", "graph", "split_keys",
+                  "channel_merge", "clusters")
 
 
 class Config(ctypes.Structure):
@@ -49,7 +50,26 @@ class Config(ctypes.Structure):
 
 
 class _Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * len(PROFILE_STAGES)), ("launches", ctypes.c_uint64 * len(PROFILE_STAGES))]
+
+
+class Pairs(ctypes.Structure):
+    _fields_ = [("i", _vp), ("j", _vp), ("votes", _vp), ("count", _u64)]
+
+
+class ClusterParams(ctypes.Structure):
+    _fields_ = [("max_gap", _u32), ("max_width", _u32), ("min_entries", _u32), ("reserved", _u32),
+                ("min_sum", _u64)]
+
+
+# fast_lsh_cluster as a numpy record (40 bytes)
+CLUSTER_DTYPE = np.dtype([("dt_min", "<u4"), ("dt_max", "<u4"), ("idx1_min", "<u4"), ("idx1_max", "<u4"),
+                          ("n_entries", "<u4"), ("peak_sim", "<u4"), ("peak_dt", "<u4"), ("peak_idx1", "<u4"),
+                          ("sim_sum", "<u8")])
+
+
+class _Work(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("big_voted", "big_members", "big_candidates", "search_calls")]
 
 
 @dataclass
@@ -100,6 +120,11 @@ def library():
         lib.fast_lsh_workspace_bytes.argtypes = [_vp, ctypes.POINTER(_u64)]
         lib.fast_lsh_profile_enable.argtypes = [_vp, _i32]
         lib.fast_lsh_profile_read.argtypes = [_vp, ctypes.POINTER(_Profile)]
+        lib.fast_lsh_last_work.argtypes = [_vp, ctypes.POINTER(_Work)]
+        lib.fast_lsh_channel_merge.argtypes = [_vp, _u32, ctypes.POINTER(Pairs), _u64, _u32, _vp, _vp, _vp, _u64,
+                                               ctypes.POINTER(_u64)]
+        lib.fast_lsh_station_clusters.argtypes = [_vp, _vp, _vp, _vp, _u64, ctypes.POINTER(ClusterParams), _vp,
+                                                  _u64, ctypes.POINTER(_u64)]
         _LIB = lib
     return _LIB
 
@@ -181,6 +206,48 @@ class FastLSH:
         p = _Profile()
         _check(library().fast_lsh_profile_read(self._ctx, ctypes.byref(p)))
         return {name: (p.ms[k], int(p.launches[k])) for k, name in enumerate(PROFILE_STAGES)}
+
+    def channel_merge(self, channels, n_fingerprints: int, min_sim: int, capacity: int | None = None):
+        """Combined similarity of one station's channels (section 7.2): channels
+        is a list of (i, j, votes) CUDA tensors (search outputs); returns
+        (dt, idx1, sim) int32 CUDA tensors ordered by (dt, idx1)."""
+        keep = [(i.contiguous(), j.contiguous(), v.contiguous()) for i, j, v in channels]
+        arr = (Pairs * max(1, len(keep)))()
+        for q, (i, j, v) in enumerate(keep):
+            assert i.is_cuda and i.element_size() == 4 and j.element_size() == 4 and v.element_size() == 1
+            arr[q] = Pairs(i.data_ptr(), j.data_ptr(), v.data_ptr(), i.numel())
+        total = sum(i.numel() for i, _, _ in keep)
+        cap = max(1, total) if capacity is None else capacity
+        out = [torch.empty(max(cap, 1), dtype=torch.int32, device=f"cuda:{self.device}") for _ in range(3)]
+        m = _u64()
+        rc = library().fast_lsh_channel_merge(self._ctx, len(keep), arr, n_fingerprints, min_sim, out[0].data_ptr(),
+                                              out[1].data_ptr(), out[2].data_ptr(), cap, ctypes.byref(m))
+        _check(rc)
+        k = int(m.value)
+        return out[0][:k], out[1][:k], out[2][:k]
+
+    def station_clusters(self, dt, idx1, sim, max_gap: int, max_width: int, min_entries: int = 1, min_sum: int = 0,
+                         capacity: int | None = None):
+        """Diagonal clusters of (dt, idx1)-ordered entries (section 7.2): a
+        uint8 CUDA tensor of CLUSTER_DTYPE records ([k, 40] bytes)."""
+        dt, idx1, sim = dt.contiguous(), idx1.contiguous(), sim.contiguous()
+        n = dt.numel()
+        assert idx1.numel() == n and sim.numel() == n
+        assert all(x.is_cuda and x.element_size() == 4 for x in (dt, idx1, sim))
+        cap = max(1, n) if capacity is None else capacity
+        out = torch.empty((max(cap, 1), CLUSTER_DTYPE.itemsize), dtype=torch.uint8, device=f"cuda:{self.device}")
+        prm = ClusterParams(max_gap, max_width, min_entries, 0, min_sum)
+        m = _u64()
+        _check(library().fast_lsh_station_clusters(self._ctx, dt.data_ptr(), idx1.data_ptr(), sim.data_ptr(), n,
+                                                   ctypes.byref(prm), out.data_ptr(), cap, ctypes.byref(m)))
+        return out[: int(m.value)]
+
+    def last_work(self) -> dict:
+        """Work counters of the last search (tiled buckets: voted pairs,
+        members, in-bucket pairs; searches completed)."""
+        w = _Work()
+        _check(library().fast_lsh_last_work(self._ctx, ctypes.byref(w)))
+        return {f: int(getattr(w, f)) for f, _ in _Work._fields_}
 
     def configure(self, radix_tile: int = 0, bucket_chunk: int = 0, autotune: bool = False):
         """Launch shapes of later searches (0 keeps the current value)."""
