@@ -163,16 +163,24 @@ int orc_station_clusters(uint64_t n, const uint32_t *dt, const uint32_t *idx1, c
     }
   }
 
-  /* 2. merge runs of adjacent diagonals whose spans come within the gap */
+  /* 2. merge runs of adjacent diagonals whose spans come within the gap:
+   *    run a against every run b of diagonal dt(a) + 1, those runs taken in
+   *    order of their start until a start lies beyond hi(a) + gap */
   uint64_t *parent = (uint64_t *)malloc((nr ? nr : 1) * sizeof(uint64_t));
-  if (!parent) { free(run); return 2; }
+  uint64_t *next = (uint64_t *)malloc((nr ? nr : 1) * sizeof(uint64_t)); /* first run of a later diagonal */
+  if (!parent || !next) { free(run); free(parent); free(next); return 2; }
   for (uint64_t r = 0; r < nr; ++r) parent[r] = r;
+  for (uint64_t r = nr, ns = nr; r-- > 0;) {
+    if (r + 1 < nr && run[r + 1].dt != run[r].dt) ns = r + 1;
+    next[r] = ns;
+  }
   for (uint64_t a = 0; a < nr; ++a)
-    for (uint64_t b = a + 1; b < nr && run[b].dt <= run[a].dt + 1; ++b) {
-      if (run[b].dt != run[a].dt + 1) continue;
+    for (uint64_t b = next[a]; b < nr && run[b].dt == (uint64_t)run[a].dt + 1; ++b) {
       const uint64_t alo = run[a].lo, ahi = run[a].hi, blo = run[b].lo, bhi = run[b].hi;
-      if (blo <= ahi + max_gap && alo <= bhi + max_gap) uf_union(parent, a, b);
+      if (blo > ahi + max_gap) break;
+      if (alo <= bhi + max_gap) uf_union(parent, a, b);
     }
+  free(next);
 
   /* 3. one summary per cluster, kept at its root (its first run) */
   orc_cluster *sum = (orc_cluster *)calloc(nr ? nr : 1, sizeof(orc_cluster));

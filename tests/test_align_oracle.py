@@ -6,29 +6,8 @@ import numpy as np
 import pytest
 
 import oracle
+from align_inputs import channels as _channels, entries as _entries
 from brute import channel_merge_brute, station_clusters_brute
-
-
-def _channels(seed, n_ch=3, n=400, pairs=300, shared=0.4, vmax=12):
-    """Random search outputs of n_ch channels over n fingerprints: a share of
-    the pairs appears in every channel (with its own votes per channel)."""
-    rng = np.random.default_rng(seed)
-    common = set()
-    while len(common) < int(pairs * shared):
-        i = int(rng.integers(0, n - 1))
-        common.add((i, int(rng.integers(i + 1, n))))
-    out = []
-    for c in range(n_ch):
-        ps = set(common)
-        while len(ps) < pairs:
-            i = int(rng.integers(0, n - 1))
-            ps.add((i, int(rng.integers(i + 1, n))))
-        ps = sorted(ps)
-        i = np.array([p[0] for p in ps], dtype=np.uint32)
-        j = np.array([p[1] for p in ps], dtype=np.uint32)
-        v = rng.integers(1, vmax + 1, len(ps)).astype(np.uint8)
-        out.append((i, j, v))
-    return out
 
 
 @pytest.mark.parametrize("seed,min_sim", [(1, 0), (2, 1), (3, 8), (4, 20), (5, 40)])
@@ -67,24 +46,6 @@ def test_channel_merge_invariants():
     assert [len(x) for x in oracle.channel_merge([], 0)] == [0, 0, 0]
     with pytest.raises(ValueError):
         oracle.channel_merge([(np.array([3], np.uint32), np.array([3], np.uint32), np.array([1], np.uint8))], 0)
-
-
-def _entries(seed, n_diag=12, streaks=6, noise=120, span=400):
-    """(dt, idx1)-ordered entries: thin diagonal streaks (runs with small gaps,
-    spilling onto neighbouring diagonals) among isolated points."""
-    rng = np.random.default_rng(seed)
-    pts = {}
-    for _ in range(streaks):
-        d0, x0 = int(rng.integers(5, 5 + n_diag)), int(rng.integers(0, span))
-        for k in range(int(rng.integers(3, 25))):
-            d = d0 + int(rng.integers(-1, 2)) if rng.random() < 0.3 else d0
-            x = x0 + k * int(rng.integers(1, 4))
-            pts[(d, x)] = int(rng.integers(1, 20))
-    for _ in range(noise):
-        pts[(int(rng.integers(5, 5 + n_diag)), int(rng.integers(0, span)))] = int(rng.integers(1, 20))
-    keys = sorted(pts)
-    return (np.array([k[0] for k in keys], np.uint32), np.array([k[1] for k in keys], np.uint32),
-            np.array([pts[k] for k in keys], np.uint32))
 
 
 @pytest.mark.parametrize("seed,gap,width,me,ms", [(1, 1, 1, 1, 0), (2, 3, 2, 2, 0), (3, 5, 3, 3, 20),
