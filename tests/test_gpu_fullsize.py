@@ -12,6 +12,9 @@ sizes whole, so it checks, exactly:
   - the occurrence filter cannot fire here (largest bucket below 1 % of n),
     and no fingerprint is excluded.
 """
+import hashlib
+import json
+import os
 import sys
 import time
 
@@ -104,16 +107,45 @@ def _check_sampled(dev, labels, out, n, a, b, seed):
     assert np.array_equal(got_v.astype(votes.dtype), votes[found])
 
 
+GOLDEN_90D = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "station90d.json")
+PAIR = np.dtype([("i", "<u4"), ("j", "<u4"), ("v", "u1")])
+
+
+def _digest(out):
+    rec = np.empty(len(out[0]), dtype=PAIR)
+    rec["i"] = out[0].cpu().numpy().view(np.uint32)
+    rec["j"] = out[1].cpu().numpy().view(np.uint32)
+    rec["v"] = out[2].cpu().numpy()
+    return hashlib.sha256(rec.tobytes()).hexdigest(), np.bincount(rec["v"], minlength=T + 1)
+
+
 def test_station_90d_full_size():
+    """The 90-day station searched as bench.py's station workload searches it,
+    against the oracle's complete result (tests/golden/station90d.json, written
+    by make_station90d.py from the oracle alone): the SHA-256 of the sorted
+    output and every counter, with and without the distinct-pair count (the
+    two take different row layouts), plus the sampled checks."""
     spec = synth.station(n=synth.STATION_90D, seed=102)
     say("[fullsize] station 90 days: generating")
     dev, labels = _upload(spec)
     a, b = fl.make_hash(202, fl.n_funcs(T, R, SCHEME))
     ctx = fl.FastLSH(0)
-    t0 = time.time()
-    out = ctx.search(dev, DIM, T, R, SCHEME, a, b, L, V, NUM, DEN)
-    torch.cuda.synchronize()
-    say(f"[fullsize] search {time.time() - t0:.2f}s")
+    gold = json.load(open(GOLDEN_90D))
+    assert gold["n"] == spec.n and gold["data_seed"] == 102 and gold["hash_seed"] == 202
+    for distinct in (False, True):
+        t0 = time.time()
+        out = ctx.search(dev, DIM, T, R, SCHEME, a, b, L, V, NUM, DEN, want_distinct=distinct)
+        torch.cuda.synchronize()
+        say(f"[fullsize] search (distinct={distinct}) {time.time() - t0:.2f}s: {out[3]}")
+        dig, hist = _digest(out)
+        got = dict(out[3].__dict__)
+        want = dict(gold["stats"])
+        if not distinct:
+            assert got.pop("n_distinct") == 2**64 - 1
+            want.pop("n_distinct")
+        assert got == want
+        assert {str(k): int(c) for k, c in enumerate(hist) if c} == gold["pairs_by_votes"]
+        assert dig == gold["sha256_pairs"]
     _check_sampled(dev, labels, out, spec.n, a, b, 1)
     ctx.close()
 
