@@ -93,13 +93,15 @@ def sig_traffic(n):
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--workload", choices=("headline", "station", "batched", "bounded", "serving"),
+    ap.add_argument("--workload", choices=("headline", "station", "batched", "bounded", "serving", "alignment"),
                     default="headline",
                     help="headline (default): the 5-year station (157,788,000 fingerprints, tables 10 at a "
                          "time) timed over the steps, then the streaming workload's latency; station: one "
                          "90-day station; bounded: the 5-year search alone; serving: 8 stations of 180 days "
                          "resident, 3,600-row chunks arriving as Poisson streams; batched: 12 stations of "
-                         "1-16 M fingerprints in one search, against 12 sequential searches")
+                         "1-16 M fingerprints in one search, against 12 sequential searches; alignment: three "
+                         "channels of the 90-day station searched with a lenient threshold, then their channel "
+                         "merge and station clusters timed")
     ap.add_argument("--chunks", type=int, default=3000, help="serving: chunks at the offered load")
     ap.add_argument("--rate", type=float, default=40.0, help="serving: offered chunks/s (all stations)")
     ap.add_argument("--stations", type=int, default=8, help="serving: stations")
@@ -145,6 +147,8 @@ def main():
         line, _ = run_serving(args)
         line["metric"] = METRIC
         line["latency_ms"] = line["offered_load"]["latency_ms"]
+    elif args.workload == "alignment":
+        line = run_alignment(args)
     else:
         line = run_batched(args)
     print(json.dumps(line), flush=True)
@@ -629,6 +633,94 @@ def run_batched(args):
                                         0, 0, args, "the 1 M-fingerprint station")
     ctx_b.close()
     ctx_s.close()
+    return line
+
+
+def run_alignment(args):
+    """Three channels of one 90-day station (shared repeating sources,
+    per-channel background), each searched with a lenient threshold (v = 2);
+    one step = the channel merge of the three outputs (combined similarity
+    at least 6) plus the station clusters of the merged entries."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1803_09835_amd as fl
+
+    N = args.n or synth.STATION_90D
+    dim, t, r, scheme, L, v = 4096, 100, 4, fl.MINMAX, 5, 2
+    min_sim, gap, width, min_entries = 6, 10, 3, 2
+    a, b = fl.make_hash(202, fl.n_funcs(t, r, scheme))
+    ctx = fl.FastLSH(0)
+    chans = []
+    for ch in range(3):
+        spec = synth.Spec(n=N, seed=102, markov_keep=140, n_sources=max(1, round(2000 * N / synth.STATION_90D)),
+                          rep_min=3, rep_max=40, jac_lo_milli=400, jac_hi_milli=900, channel=ch)
+        dev = fl.to_device_rows(synth.generate(spec))
+        oi, oj, ov, st = ctx.search(dev, dim, t, r, scheme, a, b, L, v, 1, 100)
+        chans.append((oi.clone(), oj.clone(), ov.clone()))
+        del dev, oi, oj, ov
+        log(f"# channel {ch}: {st.n_out} pairs at v >= {v}")
+    torch.cuda.empty_cache()
+    total = sum(c[0].numel() for c in chans)
+
+    def step():
+        dt, x, sm = ctx.channel_merge(chans, N, min_sim)
+        cl = ctx.station_clusters(dt, x, sm, gap, width, min_entries, 0)
+        return dt, x, sm, cl
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+        log(f"# step {k + 1}/{args.steps}: {out[0].numel()} merged entries, {out[3].shape[0]} clusters")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    prof = ctx.profile_read()
+    stage_ms, _ = stage_table(prof, args.steps)
+    merged, n_cl = out[0].numel(), out[3].shape[0]
+    # algorithmic bytes of the merge: the 9-byte pairs read, one LSD sort of
+    # 12-byte records (8-byte key, 4-byte sim: read and written once per
+    # 8-bit digit of the two ids, plus a 8-byte key read per histogram), the
+    # merged 12-byte entries written
+    nb = max(1, (N - 1).bit_length())
+    passes = 2 * ((nb + 7) // 8)
+    algo = total * 9 + total * passes * (24 + 8) + merged * 12
+    mgbs = algo / (stage_ms["channel_merge"] / 1000.0) / 1e9
+    line = {
+        "metric": "fingerprint pairs/s through the channel merge and station clustering",
+        "value": round(total / (ms / 1000.0), 1),
+        "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "three channels of one station, 90 days at 1 s lag (7,776,000 fingerprints each, "
+                               "shared repeating sources, per-channel Markov background); each searched with "
+                               "Min-Max t=100 r=4, lag 5, v=2, filter 1 %; channel merge at combined similarity "
+                               f">= {min_sim}, clusters with gap {gap}, width {width}, at least {min_entries} entries",
+                   "n": N, "channels": 3, "pairs_in": total, "min_sim": min_sim, "max_gap": gap,
+                   "max_width": width, "min_entries": min_entries},
+        "merged_entries": merged, "clusters": n_cl,
+        "stage_ms": {k: round(x, 3) for k, x in stage_ms.items() if x},
+        "roofline": {"kernel": "channel merge (pack, radix passes, run sums, compaction)", "bound": "hbm",
+                     "achieved": round(mgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(mgbs / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": algo,
+                     "radix_passes": passes},
+    }
+    import oracle
+    host = [(c[0].cpu().numpy().view(np.uint32), c[1].cpu().numpy().view(np.uint32), c[2].cpu().numpy())
+            for c in chans]
+    tc = time.perf_counter()
+    wdt, wx, ws = oracle.channel_merge(host, min_sim)
+    oracle.station_clusters(wdt, wx, ws, gap, width, min_entries, 0)
+    cpu_s = time.perf_counter() - tc
+    line["cpu_baseline"] = {"value": round(total / cpu_s, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                            "cpu": cpu_model(),
+                            "sample": f"the whole input ({total} pairs), merge and clusters in {cpu_s:.1f} s "
+                                      "(single-threaded code)"}
+    ctx.close()
     return line
 
 
