@@ -418,6 +418,24 @@ int fast_lsh_channel_merge(fast_lsh_ctx *ctx, uint32_t n_channels, const fast_ls
                            uint64_t n_fingerprints, uint32_t min_sim, uint32_t *out_dt, uint32_t *out_idx1,
                            uint32_t *out_sim, uint64_t capacity, uint64_t *n_out);
 
+/* Allocation-free channel merge, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, semantics and errors as
+ * fast_lsh_channel_merge, but every intermediate buffer lives in one
+ * fixed scratch array of FAST_LSH_NOALLOC_SCRATCH_BYTES per device, which
+ * the library's code object holds from its first use on that device until
+ * the process ends; the call allocates nothing (no hipMalloc, no workspace
+ * growth, no stage timing).  Inputs whose buffers exceed the array (about
+ * 36 bytes per input pair plus small scan and histogram arrays: at most
+ * 1,860,736 pairs) are rejected with FAST_LSH_E_NOMEM.  The array is shared
+ * by every call on the device: calls that overlap on one device (several
+ * contexts or threads at once) race and must be serialised by the caller;
+ * each call clears the parts it needs, so earlier contents never matter. */
+#define FAST_LSH_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int fast_lsh_channel_merge_noalloc(fast_lsh_ctx *ctx, uint32_t n_channels, const fast_lsh_pairs *channels,
+                                   uint64_t n_fingerprints, uint32_t min_sim, uint32_t *out_dt,
+                                   uint32_t *out_idx1, uint32_t *out_sim, uint64_t capacity, uint64_t *n_out);
+
 /* Station-level clustering parameters (section 7.2 "Station"; the paper
  * gives no values).  A run along one diagonal continues while consecutive
  * entries' idx1 differ by at most max_gap; runs of diagonals dt and dt + 1

@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "host.hpp"
 
@@ -286,83 +287,195 @@ unsigned grid_of(uint64_t n) {
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, 8u * device_cus()));
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// Channel merge host side: buffers, checks, the launch sequence
+// ---------------------------------------------------------------------------
+struct MergeBufs {
+  uint64_t *k0, *k1, *keep, *sums64;
+  uint32_t *v0, *v1, *hist, *sums, *tot;
+  AlignCtrl* ctl;
+};
 
-extern "C" {
+// The merge's buffers for `total` pairs laid out one after another from
+// base (256-byte aligned pieces); returns the bytes they span.  base ==
+// nullptr only measures.
+uint64_t merge_layout(uint64_t total, uint8_t* base, MergeBufs* b) {
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += (std::max<uint64_t>(bytes, 1) + 255) & ~255ull;
+    return p;
+  };
+  const uint32_t nt = radix_tiles(total, 0);
+  b->k0 = static_cast<uint64_t*>(take(8 * total));
+  b->k1 = static_cast<uint64_t*>(take(8 * total));
+  b->v0 = static_cast<uint32_t*>(take(4 * total));
+  b->v1 = static_cast<uint32_t*>(take(4 * total));
+  b->hist = static_cast<uint32_t*>(take(4ull * 256 * nt));
+  b->sums = static_cast<uint32_t*>(take(4 * scan_sums_elems((uint64_t)256 * nt, 1)));
+  b->keep = static_cast<uint64_t*>(take(8 * total));
+  b->sums64 = static_cast<uint64_t*>(take(8 * (scan_sums_elems(total, 1) + 1)));
+  b->tot = static_cast<uint32_t*>(take(4 * total));
+  b->ctl = static_cast<AlignCtrl*>(take(sizeof(AlignCtrl)));
+  return off;
+}
 
-int fast_lsh_channel_merge(fast_lsh_ctx* c, uint32_t n_channels, const fast_lsh_pairs* ch, uint64_t n_fps,
-                           uint32_t min_sim, uint32_t* odt, uint32_t* oidx, uint32_t* osim, uint64_t capacity,
-                           uint64_t* n_out) {
+int merge_check(fast_lsh_ctx* c, uint32_t n_channels, const fast_lsh_pairs* ch, uint64_t n_fps, uint64_t* n_out,
+                uint64_t* total) {
   if (!c) return fl_fail(FAST_LSH_E_INVALID, "ctx is NULL");
   if (!n_out) return fl_fail(FAST_LSH_E_INVALID, "n_out is NULL");
   *n_out = 0;
   if (n_channels > 0 && !ch) return fl_fail(FAST_LSH_E_INVALID, "channels is NULL");
-  if (n_fps >= (1ull << 32)) return fl_fail(FAST_LSH_E_INVALID, "n_fingerprints %llu must be below 2^32",
-                                            (unsigned long long)n_fps);
-  uint64_t total = 0;
+  if (n_fps >= (1ull << 32))
+    return fl_fail(FAST_LSH_E_INVALID, "n_fingerprints %llu must be below 2^32", (unsigned long long)n_fps);
+  *total = 0;
   for (uint32_t q = 0; q < n_channels; ++q) {
     if (ch[q].count && (!ch[q].i || !ch[q].j || !ch[q].votes))
       return fl_fail(FAST_LSH_E_INVALID, "channel %u has a NULL array", q);
-    total += ch[q].count;
+    *total += ch[q].count;
   }
-  HIPCK(hipSetDevice(c->device));
-  if (total == 0) return FAST_LSH_OK;
+  return FAST_LSH_OK;
+}
+
+// Pack, sort, sum and compact (total > 0 pairs) with the buffers in b.
+int merge_run(fast_lsh_ctx* c, uint32_t n_channels, const fast_lsh_pairs* ch, uint64_t n_fps, uint32_t min_sim,
+              uint64_t total, const MergeBufs& b, bool prof, uint32_t* odt, uint32_t* oidx, uint32_t* osim,
+              uint64_t capacity, uint64_t* n_out) {
   hipStream_t s = c->stream;
-  uint64_t *k0, *k1, *keep, *sums64;
-  uint32_t *v0, *v1, *hist, *sums, *tot;
-  AlignCtrl* ctl;
-  RC(ws<uint64_t>(c, "cm_k0", total, &k0));
-  RC(ws<uint64_t>(c, "cm_k1", total, &k1));
-  RC(ws<uint32_t>(c, "cm_v0", total, &v0));
-  RC(ws<uint32_t>(c, "cm_v1", total, &v1));
-  const uint32_t nt = radix_tiles(total, 0);
-  RC(ws<uint32_t>(c, "cm_hist", (uint64_t)256 * nt, &hist));
-  RC(ws<uint32_t>(c, "cm_sums", scan_sums_elems((uint64_t)256 * nt, 1), &sums));
-  RC(ws<uint64_t>(c, "cm_keep", total, &keep));
-  RC(ws<uint64_t>(c, "cm_sums64", scan_sums_elems(total, 1) + 1, &sums64));
-  RC(ws<uint32_t>(c, "cm_tot", total, &tot));
-  RC(ws<AlignCtrl>(c, "al_ctrl", 1, &ctl));
-  fill_u8(reinterpret_cast<uint8_t*>(ctl), sizeof(AlignCtrl), 0, s);
-  prof_begin(c, FAST_LSH_STAGE_CHANNEL_MERGE);
+  uint64_t *k0 = b.k0, *k1 = b.k1;
+  uint32_t *v0 = b.v0, *v1 = b.v1;
+  fill_u8(reinterpret_cast<uint8_t*>(b.ctl), sizeof(AlignCtrl), 0, s);
+  if (prof) prof_begin(c, FAST_LSH_STAGE_CHANNEL_MERGE);
   uint64_t off = 0;
   for (uint32_t q = 0; q < n_channels; ++q) {
     if (ch[q].count == 0) continue;
     hipLaunchKernelGGL(k_pack_pairs, dim3(grid_of(ch[q].count)), dim3(kAT), 0, s, ch[q].i, ch[q].j, ch[q].votes,
-                       ch[q].count, n_fps, k0 + off, v0 + off, &ctl->err);
+                       ch[q].count, n_fps, k0 + off, v0 + off, &b.ctl->err);
     off += ch[q].count;
   }
   // LSD passes: the idx1 bits, then the dt bits (both below n_fps)
   const uint32_t nb = fl_key_bits((uint32_t)std::max<uint64_t>(n_fps, 2));
   for (uint32_t base : {0u, 32u})
     for (uint32_t sh = 0; sh < nb; sh += 8) {
-      radix_pass(k0, v0, k1, v1, total, 1, base + sh, hist, sums, 0, s);
+      radix_pass(k0, v0, k1, v1, total, 1, base + sh, b.hist, b.sums, 0, s);
       std::swap(k0, k1);
       std::swap(v0, v1);
     }
-  hipLaunchKernelGGL(k_merge_heads, dim3(grid_of(total)), dim3(kAT), 0, s, k0, v0, total, min_sim, keep, tot);
-  scan_u64(keep, total, 1, sums64, sums64 + scan_sums_elems(total, 1), s);
-  prof_end(c);
+  hipLaunchKernelGGL(k_merge_heads, dim3(grid_of(total)), dim3(kAT), 0, s, k0, v0, total, min_sim, b.keep, b.tot);
+  uint64_t* count = b.sums64 + scan_sums_elems(total, 1);
+  scan_u64(b.keep, total, 1, b.sums64, count, s);
+  if (prof) prof_end(c);
   LAUNCHCK();
   uint64_t m = 0;
-  RC(d2h(c, &m, sums64 + scan_sums_elems(total, 1)));
+  RC(d2h(c, &m, count));
   AlignCtrl hc;
-  RC(d2h(c, &hc, ctl));
-  if (hc.err) return fl_fail(FAST_LSH_E_INVALID, "a channel holds a pair with j <= i or an id >= %llu",
-                             (unsigned long long)n_fps);
+  RC(d2h(c, &hc, b.ctl));
+  if (hc.err) {
+    if (prof) prof_collect(c);
+    return fl_fail(FAST_LSH_E_INVALID, "a channel holds a pair with j <= i or an id >= %llu",
+                   (unsigned long long)n_fps);
+  }
   *n_out = m;
   if (m > capacity) {
-    prof_collect(c);
+    if (prof) prof_collect(c);
     return fl_fail(FAST_LSH_E_CAPACITY, "%llu merged entries do not fit capacity %llu", (unsigned long long)m,
                    (unsigned long long)capacity);
   }
   if (m && (!odt || !oidx || !osim)) return fl_fail(FAST_LSH_E_INVALID, "output pointer is NULL");
-  prof_begin(c, FAST_LSH_STAGE_CHANNEL_MERGE);
-  if (m) hipLaunchKernelGGL(k_merge_emit, dim3(grid_of(total)), dim3(kAT), 0, s, k0, tot, keep, total, m, odt, oidx, osim);
-  prof_end(c);
+  if (prof) prof_begin(c, FAST_LSH_STAGE_CHANNEL_MERGE);
+  if (m)
+    hipLaunchKernelGGL(k_merge_emit, dim3(grid_of(total)), dim3(kAT), 0, s, k0, b.tot, b.keep, total, m, odt, oidx,
+                       osim);
+  if (prof) prof_end(c);
   LAUNCHCK();
   HIPCK(hipStreamSynchronize(s));
-  prof_collect(c);
+  if (prof) prof_collect(c);
   return FAST_LSH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free merge: one array per device, held by the
+// code object until the process ends.  Host code never passes the array's
+// name to a kernel: it passes the device address hipGetSymbolAddress gives
+// for the current device, taken once per device.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kScratchBytes = FAST_LSH_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxScratchDevices = 64;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+void* g_scratch_ptr[kMaxScratchDevices];
+std::mutex g_scratch_mu;
+
+int scratch_ptr(int device, uint8_t** out) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return fl_fail(FAST_LSH_E_INVALID, "device %d: the allocation-free calls serve devices 0-%d", device,
+                   kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the current device's copy
+    if (e != hipSuccess || !p)
+      return fl_fail(FAST_LSH_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                     hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = static_cast<uint8_t*>(g_scratch_ptr[device]);
+  return FAST_LSH_OK;
+}
+
+// Largest pair count whose merge layout fits the scratch array.
+uint64_t noalloc_max_pairs() {
+  // largest total whose layout fits the scratch array (the layout grows with total)
+  uint64_t lo = 0, hi = kScratchBytes / 36 + 1;
+  MergeBufs b;
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (merge_layout(mid, nullptr, &b) <= kScratchBytes) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace
+
+// Taken at context creation, with the context's device current.
+int fl_scratch_init(int device) {
+  uint8_t* p = nullptr;
+  return scratch_ptr(device, &p);
+}
+
+extern "C" {
+
+int fast_lsh_channel_merge(fast_lsh_ctx* c, uint32_t n_channels, const fast_lsh_pairs* ch, uint64_t n_fps,
+                           uint32_t min_sim, uint32_t* odt, uint32_t* oidx, uint32_t* osim, uint64_t capacity,
+                           uint64_t* n_out) {
+  uint64_t total = 0;
+  RC(merge_check(c, n_channels, ch, n_fps, n_out, &total));
+  HIPCK(hipSetDevice(c->device));
+  if (total == 0) return FAST_LSH_OK;
+  MergeBufs b;
+  const uint64_t bytes = merge_layout(total, nullptr, &b);
+  uint8_t* base;
+  RC(ws<uint8_t>(c, "cm_arena", bytes, &base));
+  merge_layout(total, base, &b);
+  return merge_run(c, n_channels, ch, n_fps, min_sim, total, b, true, odt, oidx, osim, capacity, n_out);
+}
+
+int fast_lsh_channel_merge_noalloc(fast_lsh_ctx* c, uint32_t n_channels, const fast_lsh_pairs* ch, uint64_t n_fps,
+                                   uint32_t min_sim, uint32_t* odt, uint32_t* oidx, uint32_t* osim,
+                                   uint64_t capacity, uint64_t* n_out) {
+  uint64_t total = 0;
+  RC(merge_check(c, n_channels, ch, n_fps, n_out, &total));
+  HIPCK(hipSetDevice(c->device));
+  if (total == 0) return FAST_LSH_OK;
+  MergeBufs b;
+  const uint64_t bytes = merge_layout(total, nullptr, &b);
+  if (bytes > kScratchBytes)
+    return fl_fail(FAST_LSH_E_NOMEM, "%llu pairs need %llu bytes of scratch; the allocation-free merge holds %llu "
+                   "(at most %llu pairs)", (unsigned long long)total, (unsigned long long)bytes,
+                   (unsigned long long)kScratchBytes, (unsigned long long)noalloc_max_pairs());
+  uint8_t* base = nullptr;
+  RC(scratch_ptr(c->device, &base));
+  merge_layout(total, base, &b);
+  return merge_run(c, n_channels, ch, n_fps, min_sim, total, b, false, odt, oidx, osim, capacity, n_out);
 }
 
 int fast_lsh_station_clusters(fast_lsh_ctx* c, const uint32_t* dt, const uint32_t* idx1, const uint32_t* sim,

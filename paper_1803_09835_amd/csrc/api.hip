@@ -238,6 +238,7 @@ int fast_lsh_ctx_create(int device, void* hip_stream, uint64_t hbm_budget, fast_
   HIPCK(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fl_fail(FAST_LSH_E_INVALID, "device %d not present (%d devices)", device, ndev);
   HIPCK(hipSetDevice(device));
+  RC(fl_scratch_init(device));
   fast_lsh_ctx* c = new fast_lsh_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);

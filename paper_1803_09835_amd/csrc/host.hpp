@@ -170,5 +170,8 @@ fl::SigArgs fl_sig_args(const fast_lsh_hash* h, const fast_lsh_fps* f, const uin
 int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, const fast_lsh_fps* f,
                        const fast_lsh_filter* flt, uint32_t flags, fast_lsh_stats* per_station,
                        uint64_t* station_offsets);
+// Device address of the allocation-free calls' scratch array, taken once per
+// device (align.hip).
+int fl_scratch_init(int device);
 int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps* f, const fast_lsh_filter* flt,
                       uint32_t flags, uint32_t group_tables, fast_lsh_stats* stats);

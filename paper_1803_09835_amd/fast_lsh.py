@@ -123,6 +123,7 @@ def library():
         lib.fast_lsh_last_work.argtypes = [_vp, ctypes.POINTER(_Work)]
         lib.fast_lsh_channel_merge.argtypes = [_vp, _u32, ctypes.POINTER(Pairs), _u64, _u32, _vp, _vp, _vp, _u64,
                                                ctypes.POINTER(_u64)]
+        lib.fast_lsh_channel_merge_noalloc.argtypes = lib.fast_lsh_channel_merge.argtypes
         lib.fast_lsh_station_clusters.argtypes = [_vp, _vp, _vp, _vp, _u64, ctypes.POINTER(ClusterParams), _vp,
                                                   _u64, ctypes.POINTER(_u64)]
         _LIB = lib
@@ -207,10 +208,12 @@ class FastLSH:
         _check(library().fast_lsh_profile_read(self._ctx, ctypes.byref(p)))
         return {name: (p.ms[k], int(p.launches[k])) for k, name in enumerate(PROFILE_STAGES)}
 
-    def channel_merge(self, channels, n_fingerprints: int, min_sim: int, capacity: int | None = None):
+    def channel_merge(self, channels, n_fingerprints: int, min_sim: int, capacity: int | None = None,
+                      noalloc: bool = False):
         """Combined similarity of one station's channels (section 7.2): channels
         is a list of (i, j, votes) CUDA tensors (search outputs); returns
-        (dt, idx1, sim) int32 CUDA tensors ordered by (dt, idx1)."""
+        (dt, idx1, sim) int32 CUDA tensors ordered by (dt, idx1).  noalloc:
+        the library call that allocates no device memory (fixed scratch)."""
         keep = [(i.contiguous(), j.contiguous(), v.contiguous()) for i, j, v in channels]
         arr = (Pairs * max(1, len(keep)))()
         for q, (i, j, v) in enumerate(keep):
@@ -220,8 +223,9 @@ class FastLSH:
         cap = max(1, total) if capacity is None else capacity
         out = [torch.empty(max(cap, 1), dtype=torch.int32, device=f"cuda:{self.device}") for _ in range(3)]
         m = _u64()
-        rc = library().fast_lsh_channel_merge(self._ctx, len(keep), arr, n_fingerprints, min_sim, out[0].data_ptr(),
-                                              out[1].data_ptr(), out[2].data_ptr(), cap, ctypes.byref(m))
+        fn = library().fast_lsh_channel_merge_noalloc if noalloc else library().fast_lsh_channel_merge
+        rc = fn(self._ctx, len(keep), arr, n_fingerprints, min_sim, out[0].data_ptr(), out[1].data_ptr(),
+                out[2].data_ptr(), cap, ctypes.byref(m))
         _check(rc)
         k = int(m.value)
         return out[0][:k], out[1][:k], out[2][:k]
