@@ -108,6 +108,8 @@ def parse():
     ap.add_argument("--group-tables", type=int, default=10, help="bounded: tables per group")
     ap.add_argument("--graph", action="store_true", help="replay the captured graph of the search prefix")
     ap.add_argument("--autotune", action="store_true", help="tune launch shapes on the first (warm-up) search")
+    ap.add_argument("--bin-bits", type=int, default=0,
+                    help="key bits the grouping passes sort on (8/16/24/32; 0: automatic)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -246,6 +248,8 @@ def run_station(args):
     a, b = fl.make_hash(202, fl.n_funcs(t, r, scheme))
     dev_rows = fl.to_device_rows(rows)
     ctx = fl.FastLSH(0)
+    if args.bin_bits:
+        ctx.configure(bin_bits=args.bin_bits)
     log(f"# generated {N} fingerprints in {gen_s:.1f}s; warmup {args.warmup}, steps {args.steps}")
     if args.autotune:
         ctx.configure(autotune=True)
@@ -346,6 +350,8 @@ def run_bounded(args):
     log(f"# generated and uploaded {N} fingerprints in {time.time() - tg:.1f}s")
     a, b = fl.make_hash(205, fl.n_funcs(t, r, scheme))
     ctx = fl.FastLSH(0)
+    if args.bin_bits:
+        ctx.configure(bin_bits=args.bin_bits)
     gt = args.group_tables
 
     def step():
@@ -392,6 +398,7 @@ def run_bounded(args):
                    "workspace": round(ctx.workspace_bytes() / 1e9, 1)},
         "roofline": roof,
         "k_sig": sig,
+        "launch_shapes": ctx.config_used(),
     }
     if dom != "big_pairs":
         line["k_pairs_tile"] = tile
@@ -569,6 +576,9 @@ def run_batched(args):
     a, b = fl.make_hash(201, fl.n_funcs(t, r, scheme))
     ctx_b = fl.FastLSH(0)
     ctx_s = fl.FastLSH(0)
+    if args.bin_bits:
+        ctx_b.configure(bin_bits=args.bin_bits)
+        ctx_s.configure(bin_bits=args.bin_bits)
     if args.autotune:
         ctx_b.configure(autotune=True)
         ctx_s.configure(autotune=True)
@@ -652,6 +662,8 @@ def run_alignment(args):
     min_sim, gap, width, min_entries = 6, 10, 3, 2
     a, b = fl.make_hash(202, fl.n_funcs(t, r, scheme))
     ctx = fl.FastLSH(0)
+    if args.bin_bits:
+        ctx.configure(bin_bits=args.bin_bits)
     chans = []
     for ch in range(3):
         spec = synth.Spec(n=N, seed=102, markov_keep=140, n_sources=max(1, round(2000 * N / synth.STATION_90D)),

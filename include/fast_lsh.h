@@ -240,12 +240,18 @@ int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, ui
  *                 tables, bin bits) time every radix tile and bucket chunk
  *                 on that search's own data, keep the fastest for later
  *                 searches of that shape (the fixed values above are then
- *                 ignored); 0: use the fixed values. */
+ *                 ignored); 0: use the fixed values;
+ *   bin_bits      top bits of the mixed key the grouping passes sort on
+ *                 (8, 16, 24 or 32: one radix pass per 8 bits; equal keys
+ *                 share every bit, so any choice gives the same buckets,
+ *                 coarser bins leave more keys for the bucket kernel to
+ *                 separate); 0: the automatic rule (bins of the largest
+ *                 station averaging at most about 4 fingerprints). */
 typedef struct {
   uint32_t radix_tile;
   uint32_t bucket_chunk;
   uint32_t autotune;
-  uint32_t reserved;
+  uint32_t bin_bits;
 } fast_lsh_config;
 
 /* Set the launch shapes of later searches (defaults: 16384, 512, no

@@ -246,7 +246,7 @@ int fast_lsh_ctx_create(int device, void* hip_stream, uint64_t hbm_budget, fast_
   c->config.radix_tile = radix_tile_elems(0);
   c->config.bucket_chunk = 512;
   c->config.autotune = 0;
-  c->config.reserved = 0;
+  c->config.bin_bits = 0;
   *out = c;
   g_err.clear();
   return FAST_LSH_OK;
@@ -355,9 +355,12 @@ int fast_lsh_configure(fast_lsh_ctx* c, const fast_lsh_config* cfg) {
   if (chunk < 256 || chunk > 1536 || chunk % 256)
     return fl_fail(FAST_LSH_E_INVALID, "bucket_chunk %u is not a multiple of 256 in [256, 1536]", cfg->bucket_chunk);
   if (cfg->autotune > 1) return fl_fail(FAST_LSH_E_INVALID, "autotune must be 0 or 1");
+  if (cfg->bin_bits % 8 || cfg->bin_bits > 32)
+    return fl_fail(FAST_LSH_E_INVALID, "bin_bits %u is not 0, 8, 16, 24 or 32", cfg->bin_bits);
   c->config.radix_tile = tile;
   c->config.bucket_chunk = chunk;
   c->config.autotune = cfg->autotune;
+  c->config.bin_bits = cfg->bin_bits;
   return FAST_LSH_OK;
 }
 
@@ -366,7 +369,7 @@ int fast_lsh_config_used(fast_lsh_ctx* c, fast_lsh_config* out) {
   out->radix_tile = radix_tile_elems(c->last_choice.radix_variant);
   out->bucket_chunk = c->last_choice.bucket_chunk;
   out->autotune = c->config.autotune;
-  out->reserved = 0;
+  out->bin_bits = c->last_bin_bits;
   return FAST_LSH_OK;
 }
 

@@ -112,6 +112,7 @@ struct fast_lsh_ctx {
   fast_lsh_config config;
   std::map<std::vector<uint64_t>, TuneChoice> tuned;  // shape key -> choice
   TuneChoice last_choice;
+  uint32_t last_bin_bits = 0;  // bin bits of the last search
   // captured search prefix
   hipGraphExec_t graph = nullptr;
   std::vector<uint64_t> graph_key;

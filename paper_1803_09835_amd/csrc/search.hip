@@ -407,7 +407,8 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   j.pl = make_plan(j.t, flt->min_votes, distinct, true);
   uint64_t n_max = 0;
   for (uint32_t st = 0; st < S; ++st) n_max = std::max<uint64_t>(n_max, f[st].n);
-  j.B = bin_bits(n_max, S > 1);
+  j.B = c->config.bin_bits ? c->config.bin_bits : bin_bits(n_max, S > 1);
+  c->last_bin_bits = j.B;
 
   RC(fl_upload_hash(c, h, &j.dhash));
   j.cap.assign(S, 0);
@@ -634,7 +635,8 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   const uint32_t ngroups = (t + TGm - 1) / TGm;
   const uint64_t gn = (uint64_t)TGm * N;
   j.pl = make_plan(t, flt->min_votes, distinct, false);
-  j.B = bin_bits(N, false);
+  j.B = c->config.bin_bits ? c->config.bin_bits : bin_bits(N, false);
+  c->last_bin_bits = j.B;
   RC(fl_upload_hash(c, h, &j.dhash));
   j.cap.assign(1, 0);
   j.vec.assign(1, false);

@@ -500,6 +500,9 @@ __device__ uint64_t long_bin(const BucketArgs& a, uint32_t seg, uint64_t b, cons
         found = true;  // end of the table: end = n
       }
     }
+    // the round reached the table's end without leaving the bin: the bin
+    // ends with the table (end = n)
+    if (!found && c + 64 * kScanQ >= n) found = true;
     if (!found && c + 64 * kScanQ - b >= kLongDefer) break;  // long: bisect below
   }
   if (!found) {

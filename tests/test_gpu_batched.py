@@ -102,6 +102,22 @@ def test_batched_minmax_groups_and_distinct(ctx):
     _check_batched(ctx, stations, 4096, 40, 4, fl.MINHASH, 33, 5, 3, distinct=True, label="minhash-v3-distinct")
 
 
+@pytest.mark.parametrize("bits", [8, 16, 24, 32])
+def test_batched_bin_bits(bits):
+    """Bin bits of the tagged keys (station in the top four bits) change speed
+    only: every choice gives each station's oracle output."""
+    c = fl.FastLSH(0)
+    c.configure(bin_bits=bits)
+    stations = [synth.generate(synth.with_noise(synth.station(n=30_000, seed=41), 50, 190)),
+                synth.generate(synth.station(n=50_000, seed=90)), _fixed(5, 4096, 200, 3)]
+    _check_batched(c, stations, 4096, 100, 4, fl.MINMAX, 42, 5, 4, 1, 100, label=f"bin-bits-{bits}")
+    bounded = c.search_bounded(fl.to_device_rows(stations[1]), 4096, 100, 4, fl.MINMAX, *fl.make_hash(42, 200), 5, 4,
+                               1, 100, group_tables=10)
+    full = c.search(fl.to_device_rows(stations[1]), 4096, 100, 4, fl.MINMAX, *fl.make_hash(42, 200), 5, 4, 1, 100)
+    assert all(torch.equal(x, y) for x, y in zip(bounded[:3], full[:3])) and bounded[3] == full[3]
+    c.close()
+
+
 def test_batched_sixteen_stations(ctx):
     stations = [_fixed(300 + 137 * s, 256, 6, 700 + s) for s in range(16)]
     _check_batched(ctx, stations, 256, 12, 2, fl.MINMAX, 701, 2, 2, label="16-stations")

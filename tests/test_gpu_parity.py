@@ -218,6 +218,24 @@ def test_search_station(ctx, n):
         _compare(ctx, rows, 4096, 100, 4, fl.MINMAX, 202, 5, 4, 1, 100, distinct=True, label="station")
 
 
+@pytest.mark.parametrize("bits,n,t,seed", [(8, 120_000, 100, 61), (24, 120_000, 100, 61), (32, 120_000, 100, 61),
+                                          (8, 50_000, 2, 90), (8, 50_000, 100, 90)])
+def test_search_bin_bits(bits, n, t, seed):
+    """The grouping passes' bin bits change speed only: coarser or finer bins
+    give the oracle's output and counters (the automatic choice here is 16).
+    With 8 bits and 50,000 fingerprints some table's last bin holds 193-256
+    members and runs to the table's end, the case where the bucket kernel
+    once took the bin's end past the table (into the next one)."""
+    c = fl.FastLSH(0)
+    c.configure(bin_bits=bits)
+    spec = synth.station(n=n, seed=seed)
+    rows = synth.generate(synth.with_noise(spec, 20, 190) if seed == 61 else spec)
+    _compare(c, rows, 4096, t, 4, fl.MINMAX, 62 if seed == 61 else 42, 5, 4 if t > 2 else 1, 1, 100,
+             label=f"bin-bits-{bits}")
+    assert c.config_used()["bin_bits"] == bits
+    c.close()
+
+
 def test_search_station_minhash_v3(ctx):
     rows = synth.generate(synth.station(n=60_000, seed=31))
     _compare(ctx, rows, 4096, 40, 4, fl.MINHASH, 33, 5, 3, label="station-minhash")
