@@ -22,7 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "align.c")]
+_SRC = [os.path.join(_HERE, f) for f in ("oracle.c", "align.c", "partition.c")]
 
 P = 2**31 - 1
 MINHASH, MINMAX = 0, 1
@@ -87,6 +87,13 @@ def _lib():
         lib.orc_station_clusters.argtypes = [_u64, _vp, _vp, _vp, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp),
                                              ctypes.POINTER(_u64)]
         lib.orc_station_clusters.restype = ctypes.c_int
+        lib.orc_query_keys.argtypes = [_u32, _u64, _vp, _u64, _vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                       ctypes.POINTER(_vp), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]
+        lib.orc_query_keys.restype = ctypes.c_int
+        lib.orc_search_partitioned_keys.argtypes = [_u32, _u64, _vp, _u32, _u32, _u32, _u32, _u32,
+                                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                                    ctypes.POINTER(_Stats), _vp]
+        lib.orc_search_partitioned_keys.restype = ctypes.c_int
         lib.orc_max_threads.restype = ctypes.c_int
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         _LIB = lib
@@ -330,3 +337,53 @@ def station_clusters(dt, idx1, sim, max_gap: int, max_width: int, min_entries: i
         ctypes.memmove(out.ctypes.data, p, k * CLUSTER_DTYPE.itemsize)
     _lib().orc_free(p)
     return out
+
+
+# --------------------------------------------------------------------------
+# Section 6.4 / 6.5 forms: query-only hashing, partitioned search with the
+# dynamic occurrence filter
+# --------------------------------------------------------------------------
+def query_keys(qkeys: np.ndarray, dkeys: np.ndarray, min_votes: int):
+    """(q, x, votes, n_matches): query-only hashing from band keys uint64[t, nq]
+    and uint64[t, nd]; pairs with at least min_votes votes, ordered by (q, x)."""
+    qkeys = np.ascontiguousarray(qkeys, dtype=np.uint64)
+    dkeys = np.ascontiguousarray(dkeys, dtype=np.uint64)
+    t, nq = qkeys.shape
+    t2, nd = dkeys.shape
+    assert t == t2
+    pq, px, pv, m, nc = _vp(), _vp(), _vp(), _u64(), _u64()
+    rc = _lib().orc_query_keys(t, nq, qkeys.ctypes.data, nd, dkeys.ctypes.data, min_votes, ctypes.byref(pq),
+                               ctypes.byref(px), ctypes.byref(pv), ctypes.byref(m), ctypes.byref(nc))
+    if rc == 1:
+        raise ValueError("oracle: invalid query arguments")
+    if rc != 0:
+        raise MemoryError("oracle: out of host memory")
+    q, x, v = _take_triplets(pq, px, pv, int(m.value))
+    return q, x, v, int(nc.value)
+
+
+def query(queries, dataset, dim: int, t: int, r: int, scheme: int, a, b, min_votes: int):
+    """Query-only hashing from fingerprints (signatures, then query_keys)."""
+    return query_keys(signatures(queries, dim, t, r, scheme, a, b), signatures(dataset, dim, t, r, scheme, a, b),
+                      min_votes)
+
+
+def search_partitioned_keys(keys: np.ndarray, min_lag: int, min_votes: int, occ_num: int, occ_den: int,
+                            n_parts: int, want_excluded: bool = False):
+    """(i, j, votes, Stats[, excluded]): partitioned search with the dynamic
+    occurrence filter from band keys uint64[t, n]."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    t, n = keys.shape
+    pi, pj, pv = _vp(), _vp(), _vp()
+    st = _Stats()
+    ex = np.empty(max(n, 1), dtype=np.uint8)
+    rc = _lib().orc_search_partitioned_keys(t, n, keys.ctypes.data, min_lag, min_votes, occ_num, occ_den, n_parts,
+                                            ctypes.byref(pi), ctypes.byref(pj), ctypes.byref(pv), ctypes.byref(st),
+                                            ex.ctypes.data)
+    if rc == 1:
+        raise ValueError("oracle: invalid partitioned-search arguments")
+    if rc != 0:
+        raise MemoryError("oracle: out of host memory")
+    oi, oj, ov = _take_triplets(pi, pj, pv, st.n_out)
+    stats = Stats(*[int(getattr(st, f)) for f, _ in _Stats._fields_])
+    return (oi, oj, ov, stats, ex[:n]) if want_excluded else (oi, oj, ov, stats)

@@ -118,3 +118,64 @@ def station_clusters_brute(dt, idx1, sim, max_gap, max_width, min_entries=1, min
             continue
         out.append((min(d), max(d), min(x), max(x), len(mem), sim[peak], dt[peak], idx1[peak], tot))
     return out
+
+
+def vote_matrix(keys):
+    """votes[i, j] = number of tables whose keys of i and j are equal (dense)."""
+    t, n = keys.shape
+    v = np.zeros((n, n), dtype=np.int64)
+    for u in range(t):
+        v += keys[u][:, None] == keys[u][None, :]
+    return v
+
+
+def query_brute(qkeys, dkeys, min_votes):
+    """Query-only result straight from the definition: votes[q, x] counted by
+    comparing every query's keys with every item's keys."""
+    v = np.zeros((qkeys.shape[1], dkeys.shape[1]), dtype=np.int64)
+    for u in range(qkeys.shape[0]):
+        v += qkeys[u][:, None] == dkeys[u][None, :]
+    q, x = np.nonzero(v >= min_votes)
+    return q.astype(np.uint32), x.astype(np.uint32), v[q, x].astype(np.uint8)
+
+
+def partitioned_brute(keys, min_lag, min_votes, occ_num, occ_den, n_parts):
+    """The partitioned search with the dynamic occurrence filter, step by step
+    on a dense vote matrix (no buckets).  Returns (i, j, votes, counters)."""
+    t, n = keys.shape
+    v = vote_matrix(keys)
+    ex = np.zeros(n, dtype=bool)
+    idx = np.arange(n)
+    out, e_voted, n_distinct = [], 0, 0
+    for p in range(n_parts):
+        lo, hi = n * p // n_parts, n * (p + 1) // n_parts
+        cands = {}
+        for i in range(lo, hi):
+            if ex[i]:
+                continue
+            ok = (v[i] >= 1) & (idx != i) & (np.abs(idx - i) >= min_lag) & ~ex
+            cands[i] = np.flatnonzero(ok)
+        if occ_den:
+            newly = set()
+            for i, c in cands.items():
+                if len(c) * occ_den > (hi - lo) * occ_num:
+                    newly.add(i)
+                    newly.update(int(j) for j in c)
+            ex[list(newly)] = True
+        for i in range(lo, hi):
+            if ex[i]:
+                continue
+            for j in range(i + min_lag if min_lag > 0 else i + 1, n):
+                if j <= i or ex[j] or v[i, j] == 0:
+                    continue
+                e_voted += int(v[i, j])
+                n_distinct += 1
+                if v[i, j] >= min_votes:
+                    out.append((i, j, int(v[i, j])))
+    iu = np.triu_indices(n, 1)
+    e_raw = int(v[iu].sum())
+    max_bucket = max(int(np.unique(keys[u], return_counts=True)[1].max()) for u in range(t)) if n else 0
+    st = dict(n_out=len(out), e_raw=e_raw, e_voted=e_voted, n_distinct=n_distinct, n_flagged=int(ex.sum()),
+              max_bucket=max_bucket)
+    return (np.array([o[0] for o in out], np.uint32), np.array([o[1] for o in out], np.uint32),
+            np.array([o[2] for o in out], np.uint8), st)
