@@ -392,6 +392,25 @@ typedef struct {
 
 int fast_lsh_last_work(fast_lsh_ctx *ctx, fast_lsh_work *out);
 
+/* Query-only hashing (section 6.4, "Partition"): only the queries are
+ * hashed into the t tables; every dataset item is looked up in each table,
+ * and (query q, item x) gets one vote per table in which x falls in q's
+ * bucket.  Output: every pair with votes >= min_votes, ordered by (q, x),
+ * in DEVICE arrays out_q, out_x (query and item indices), out_votes
+ * (caller-owned); the same pairs a search over tables holding the whole
+ * dataset reports for the queries.  No lag and no occurrence filter apply
+ * (queries and items are separate sets).  stats (HOST, optional): n_out;
+ * e_raw = e_voted = the (table, query, item) matches; n_distinct is not
+ * computed (all ones); the rest 0.  Queries and dataset hold fewer than
+ * 2^32 fingerprints each.  E_CAPACITY when n_out > capacity (nothing
+ * written, stats set); E_INVALID for bad hash parameters or fingerprints.
+ * Workspace: the queries' tables (24 bytes per query and table), the
+ * dataset's keys for a group of tables (at most 8 GB), 24 bytes per
+ * match.  Blocking. */
+int fast_lsh_query(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *queries,
+                   const fast_lsh_fps *dataset, uint32_t min_votes, uint32_t *out_q, uint32_t *out_x,
+                   uint8_t *out_votes, uint64_t capacity, fast_lsh_stats *stats);
+
 /* ------------------------------------------------------------------------
  * Spatiotemporal alignment of search outputs (section 7)
  * ------------------------------------------------------------------------ */

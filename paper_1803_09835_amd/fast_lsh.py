@@ -124,6 +124,8 @@ def library():
         lib.fast_lsh_channel_merge.argtypes = [_vp, _u32, ctypes.POINTER(Pairs), _u64, _u32, _vp, _vp, _vp, _u64,
                                                ctypes.POINTER(_u64)]
         lib.fast_lsh_channel_merge_noalloc.argtypes = lib.fast_lsh_channel_merge.argtypes
+        lib.fast_lsh_query.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps), ctypes.POINTER(Fps), _u32,
+                                       _vp, _vp, _vp, _u64, ctypes.POINTER(_Stats)]
         lib.fast_lsh_station_clusters.argtypes = [_vp, _vp, _vp, _vp, _u64, ctypes.POINTER(ClusterParams), _vp,
                                                   _u64, ctypes.POINTER(_u64)]
         _LIB = lib
@@ -207,6 +209,26 @@ class FastLSH:
         p = _Profile()
         _check(library().fast_lsh_profile_read(self._ctx, ctypes.byref(p)))
         return {name: (p.ms[k], int(p.launches[k])) for k, name in enumerate(PROFILE_STAGES)}
+
+    def query(self, queries, dataset, dim, t, r, scheme, a, b, min_votes, capacity: int | None = None):
+        """Query-only hashing (section 6.4): (q, x, votes) CUDA tensors of the
+        (query, item) pairs with at least min_votes votes, and Stats."""
+        h, keep = _hash_struct(dim, t, r, scheme, a, b)
+        fq, kq = _fps_struct(queries)
+        fd, kd = _fps_struct(dataset)
+        cap = max(1, 4 * fq.n) if capacity is None else capacity
+        st = _Stats()
+        while True:
+            oq, ox, ov = self._outputs(cap)
+            rc = library().fast_lsh_query(self._ctx, ctypes.byref(h), ctypes.byref(fq), ctypes.byref(fd), min_votes,
+                                          oq.data_ptr(), ox.data_ptr(), ov.data_ptr(), cap, ctypes.byref(st))
+            if rc == E_CAPACITY and capacity is None:
+                cap = st.n_out
+                continue
+            break
+        _check(rc)
+        m = st.n_out
+        return oq[:m], ox[:m], ov[:m], Stats(*[int(getattr(st, k)) for k, _ in _Stats._fields_])
 
     def channel_merge(self, channels, n_fingerprints: int, min_sim: int, capacity: int | None = None,
                       noalloc: bool = False):
