@@ -392,6 +392,30 @@ typedef struct {
 
 int fast_lsh_last_work(fast_lsh_ctx *ctx, fast_lsh_work *out);
 
+/* Partitioned search with the dynamic occurrence filter (section 6.4
+ * "Partition", section 6.5 "Removing correlated noise").  The n
+ * fingerprints are split into n_partitions consecutive id ranges
+ * [n p / P, n (p + 1) / P) (P = min(n_partitions, n)), taken in order.  For
+ * partition p: (1) every fingerprint of p not excluded yet counts its
+ * near-neighbour candidates: the distinct other fingerprints at least
+ * min_lag away, not excluded, that share a bucket with it in some table;
+ * (2) when occ_den != 0, the fingerprints of p whose count c satisfies
+ * c * occ_den > |p| * occ_num are excluded together with all their
+ * candidates (counts taken before any exclusion of p); (3) the pairs (i, j)
+ * with i in p, i < j, j - i >= min_lag, neither excluded, votes >= min_votes
+ * are reported.  Exclusions only affect later output.  With occ_den == 0
+ * the output equals fast_lsh_search's without filter, for every partition
+ * count.  Output and capacity as fast_lsh_search (one table group: pass
+ * FAST_LSH_WANT_DISTINCT for n_distinct); stats: e_raw and max_bucket of
+ * all tables (no static filter), e_voted / n_distinct over the pairs the
+ * partitions could report, n_flagged the fingerprints excluded at the end.
+ * E_INVALID for n_partitions == 0, FAST_LSH_USE_GRAPH or bad inputs.
+ * Cost: up to three pair passes over all buckets per partition. */
+int fast_lsh_search_partitioned(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *fps,
+                                const fast_lsh_filter *filter, uint32_t flags, uint32_t n_partitions,
+                                uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes, uint64_t capacity,
+                                fast_lsh_stats *stats);
+
 /* Query-only hashing (section 6.4, "Partition"): only the queries are
  * hashed into the t tables; every dataset item is looked up in each table,
  * and (query q, item x) gets one vote per table in which x falls in q's

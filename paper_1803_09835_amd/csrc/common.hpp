@@ -216,6 +216,18 @@ struct PairArgs {
   uint32_t nstation;
   const unsigned long long* n_flagged;  // total excluded (device), 0: skip flag lookups
   unsigned long long* big_voted;   // [kSpread] pairs counted in e_voted by the tiled kernel (or nullptr)
+  // Partitioned search with the dynamic occurrence filter (one table group,
+  // first shared table found exactly as for the distinct count).  part_mode
+  // 0: plain search; 1: every candidate pair, at its first shared table,
+  // adds one to cand[] of its members in [plo, phi); 2: at its first shared
+  // table, a pair with exactly one member in fp[] (the partition's
+  // over-threshold fingerprints) sets ex_next[] of the other; 3: the plain
+  // search restricted to pairs whose smaller id lies in [plo, phi).
+  uint32_t part_mode;
+  uint32_t plo, phi;
+  uint32_t* cand;
+  const uint8_t* fp;
+  uint8_t* ex_next;
 };
 
 // Station of a (global) fingerprint id, for nb stations with ascending bases.

@@ -36,6 +36,9 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
 void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, unsigned long long* work,
                         hipStream_t s);
 void launch_work_reduce(const unsigned long long* work, unsigned long long* out, hipStream_t s);
+void launch_part_flag(const uint8_t* ex, const uint32_t* cand, uint64_t lo, uint64_t hi, uint32_t num, uint32_t den,
+                      uint8_t* fp, unsigned int* nfp, hipStream_t s);
+void launch_part_merge(uint8_t* ex, uint8_t* fp, uint8_t* ex_next, uint64_t n, hipStream_t s);
 void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hipStream_t s);
 void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* owner, uint64_t unit_base, uint32_t nunits,
                        const uint4* big, uint32_t tb_size, uint32_t rswl, hipStream_t s);
@@ -170,7 +173,7 @@ fl::SigArgs fl_sig_args(const fast_lsh_hash* h, const fast_lsh_fps* f, const uin
 // Search over a set of stations (search.hip)
 int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, const fast_lsh_fps* f,
                        const fast_lsh_filter* flt, uint32_t flags, fast_lsh_stats* per_station,
-                       uint64_t* station_offsets);
+                       uint64_t* station_offsets, uint32_t parts = 0);
 // Device address of the allocation-free calls' scratch array, taken once per
 // device (align.hip).
 int fl_scratch_init(int device);

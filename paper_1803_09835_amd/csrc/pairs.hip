@@ -241,6 +241,26 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
     for (int k = 0; k < RowReg<RSW>::kW; ++k) asm volatile("" : "+v"(rv[k]));  // keep the loads above the branch
   }
   if (i == kDead || j == kDead || j - i < a.min_lag) return;
+  if (!FAST && a.part_mode) {
+    // partitioned search: every mode needs the pair's first shared table
+    const bool lower = rx.eq_below(ry, rsw, u) != 0 && lower_in_group(a, u, i, j, rl, ry);
+    if (a.part_mode == 1) {
+      if (!lower) {
+        if (i >= a.plo && i < a.phi) atomicAdd(a.cand + i, 1u);
+        if (j >= a.plo && j < a.phi) atomicAdd(a.cand + j, 1u);
+      }
+      return;
+    }
+    if (a.part_mode == 2) {
+      if (!lower) {
+        const bool fi = a.fp[i] != 0, fj = a.fp[j] != 0;
+        if (fi && !fj) a.ex_next[j] = 1;
+        if (fj && !fi) a.ex_next[i] = 1;
+      }
+      return;
+    }
+    if (i < a.plo || i >= a.phi) return;  // mode 3: pairs of this partition only
+  }
   if (a.nstation > 1 && (i < tl.lo || i >= tl.hi)) {
     const uint32_t st = station_of(a.station_base, a.nstation, i);
     if (st != tl.station) {
@@ -747,6 +767,31 @@ __global__ __launch_bounds__(kPT) void k_spread_reduce(const unsigned long long*
   }
 }
 
+// Partitioned search, one partition [lo, hi) of size psize: fp[i] = 1 for
+// every fingerprint of it not excluded whose candidate count exceeds the
+// threshold (cand * den > psize * num); *nfp counts them.
+__global__ __launch_bounds__(kPT) void k_part_flag(const uint8_t* ex, const uint32_t* cand, uint64_t lo, uint64_t hi,
+                                                   uint32_t num, uint32_t den, uint8_t* fp, unsigned int* nfp) {
+  const uint64_t psize = hi - lo;
+  unsigned int c = 0;
+  for (uint64_t i = lo + (uint64_t)blockIdx.x * kPT + threadIdx.x; i < hi; i += (uint64_t)gridDim.x * kPT) {
+    const bool f = !ex[i] && (unsigned __int128)cand[i] * den > (unsigned __int128)psize * num;
+    fp[i] = f ? 1 : 0;
+    c += f ? 1u : 0u;
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(nfp, c);
+}
+
+// ex[i] |= fp[i] | ex_next[i] over [0, n); fp and ex_next cleared.
+__global__ __launch_bounds__(kPT) void k_part_merge(uint8_t* ex, uint8_t* fp, uint8_t* ex_next, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kPT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kPT) {
+    if (fp[i] | ex_next[i]) ex[i] = 1;
+    fp[i] = 0;
+    ex_next[i] = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
@@ -756,8 +801,9 @@ static unsigned grid_for(uint64_t count) {
 }
 
 // The group test reduces to "another table shares a bucket" when a pair
-// needs two shared tables in its group and no distinct count is wanted.
-static bool fast_test(const PairArgs& a) { return a.need == 2 && !a.want_distinct; }
+// needs two shared tables in its group and no distinct count is wanted (the
+// partitioned passes always take the counting form).
+static bool fast_test(const PairArgs& a) { return a.need == 2 && !a.want_distinct && a.part_mode == 0; }
 
 // Persistent: one resident round of one-wave workgroups (as many as a CU
 // holds by LDS, at most kPairWavesPerCU) spread over the segments.
@@ -788,6 +834,15 @@ void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* 
                         hipStream_t s) {
   if (nbig)
     hipLaunchKernelGGL(k_tile_counts, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, big, nbig, tb, tiles, work);
+}
+
+void launch_part_flag(const uint8_t* ex, const uint32_t* cand, uint64_t lo, uint64_t hi, uint32_t num, uint32_t den,
+                      uint8_t* fp, unsigned int* nfp, hipStream_t s) {
+  if (hi > lo) hipLaunchKernelGGL(k_part_flag, dim3(grid_for(hi - lo)), dim3(kPT), 0, s, ex, cand, lo, hi, num, den, fp, nfp);
+}
+
+void launch_part_merge(uint8_t* ex, uint8_t* fp, uint8_t* ex_next, uint64_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_part_merge, dim3(grid_for(n)), dim3(kPT), 0, s, ex, fp, ex_next, n);
 }
 
 void launch_work_reduce(const unsigned long long* work, unsigned long long* out, hipStream_t s) {

@@ -105,6 +105,7 @@ struct Job {
   uint64_t spread_bytes;
   unsigned long long* work;  // [3][kSpread]: tiled buckets' voted pairs, members, in-bucket pairs
   uint32_t rswl;
+  uint32_t parts = 0;  // > 0: partitioned search with the dynamic occurrence filter (no pair launch in the prefix)
   BucketArgs ba;
   PairArgs pa;
   // the radix passes leave the sorted keys/ids in (sorted_k, sorted_v)
@@ -248,6 +249,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
 
   // 4. pairs of small buckets
   j.pa.order = j.sorted_v;
+  if (j.parts) return FAST_LSH_OK;  // the partitioned search launches its own pair passes
   pb(FAST_LSH_STAGE_PAIRS);
   launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, s);
   pe();
@@ -259,7 +261,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
 // are computed on the device (members are read in place from the sorted
 // order, excluded ones marked dead); the host reads back the tile total to
 // size the grid.
-int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
+int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count, const PairArgs& args, unsigned long long* work) {
   if (big_count == 0) return FAST_LSH_OK;
   hipStream_t s = c->stream;
   uint64_t *toff, *sums;
@@ -271,7 +273,7 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   const uint32_t fit = 65536 / (8 * j.rswl + 8);
   uint32_t tb = 128;
   while (tb > 16 && tb > fit) tb >>= 1;
-  launch_tile_counts(j.bdesc, big_count, tb, toff, j.work, s);
+  launch_tile_counts(j.bdesc, big_count, tb, toff, work, s);
   scan_u64(toff, big_count, 1, sums, toff + big_count, s);
   LAUNCHCK();
   uint64_t units = 0;
@@ -282,8 +284,8 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count) {
   LAUNCHCK();
   // at most 2^22 workgroups of 256 threads per launch (work-items per grid
   // dimension stay below 2^32)
-  PairArgs pa = j.pa;
-  pa.big_voted = j.work;
+  PairArgs pa = args;
+  pa.big_voted = work;
   for (uint64_t u0 = 0; u0 < units; u0 += 1u << 22) {
     const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 22, units - u0);
     prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
@@ -373,14 +375,107 @@ int finish_output(fast_lsh_ctx* c, Job& j, uint64_t cnt, bool distinct, fast_lsh
   return FAST_LSH_OK;
 }
 
+// Partitioned search with the dynamic occurrence filter (sections 6.4,
+// 6.5), after the prefix has grouped and segmented every table without the
+// static filter.  Partitions are consecutive id ranges taken in order; for
+// partition p: (1) each of its fingerprints counts its candidates (distinct
+// other fingerprints at least min_lag away, not excluded, sharing a bucket);
+// (2) those over occ_num/occ_den of the partition's size are excluded with
+// all their candidates; (3) the pairs whose smaller id lies in p are
+// reported.  The exclusion bytes j.flags start at zero and only grow.
+int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t big_count, uint64_t out_cap,
+                   Ctrl* hc_out) {
+  hipStream_t s = c->stream;
+  const uint64_t N = j.N;
+  uint32_t* cand;
+  uint8_t *fp, *exn;
+  unsigned long long *always, *dummy;
+  unsigned int* nfp;
+  RC(ws<uint32_t>(c, "part_cand", N, &cand));
+  RC(ws<uint8_t>(c, "part_fp", N, &fp));
+  RC(ws<uint8_t>(c, "part_exnext", N, &exn));
+  RC(ws<unsigned long long>(c, "part_one", 1, &always));
+  RC(ws<unsigned long long>(c, "part_work", 3 * kSpread, &dummy));
+  RC(ws<unsigned int>(c, "part_nfp", 1, &nfp));
+  fill_u64(reinterpret_cast<uint64_t*>(always), 1, 1, s);  // the pair kernels always consult the exclusions
+  Ctrl hc;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    RC(set_out_buffers(c, j, out_cap));
+    fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * kSpread * sizeof(unsigned long long), 0, s);
+    fill_u64(reinterpret_cast<uint64_t*>(j.work), 3 * kSpread, 0, s);
+    fill_u32(&j.ctrl->out_count, 1, 0, s);
+    fill_u8(j.flags, N, 0, s);
+    fill_u8(fp, N, 0, s);
+    fill_u8(exn, N, 0, s);
+    PairArgs pa = j.pa;
+    pa.n_flagged = always;
+    pa.cand = cand;
+    pa.fp = fp;
+    pa.ex_next = exn;
+    for (uint32_t p = 0; p < j.parts; ++p) {
+      pa.plo = (uint32_t)(N * p / j.parts);
+      pa.phi = (uint32_t)(N * (p + 1) / j.parts);
+      if (flt.occ_den && pa.phi > pa.plo) {
+        fill_u32(cand + pa.plo, pa.phi - pa.plo, 0, s);
+        fill_u32(nfp, 1, 0, s);
+        PairArgs m1 = pa;
+        m1.part_mode = 1;
+        prof_begin(c, FAST_LSH_STAGE_PAIRS);
+        launch_pairs_wave(m1, j.marks, j.t, j.rswl, s);
+        prof_end(c);
+        LAUNCHCK();
+        RC(run_big_pairs(c, j, big_count, m1, dummy));
+        launch_part_flag(j.flags, cand, pa.plo, pa.phi, flt.occ_num, flt.occ_den, fp, nfp, s);
+        LAUNCHCK();
+        unsigned int hn = 0;
+        RC(d2h(c, &hn, nfp));
+        if (hn) {
+          PairArgs m2 = pa;
+          m2.part_mode = 2;
+          prof_begin(c, FAST_LSH_STAGE_PAIRS);
+          launch_pairs_wave(m2, j.marks, j.t, j.rswl, s);
+          prof_end(c);
+          LAUNCHCK();
+          RC(run_big_pairs(c, j, big_count, m2, dummy));
+          launch_part_merge(j.flags, fp, exn, N, s);
+          LAUNCHCK();
+        }
+      }
+      PairArgs m3 = pa;
+      m3.part_mode = 3;
+      prof_begin(c, FAST_LSH_STAGE_PAIRS);
+      launch_pairs_wave(m3, j.marks, j.t, j.rswl, s);
+      prof_end(c);
+      LAUNCHCK();
+      RC(run_big_pairs(c, j, big_count, m3, j.work));
+    }
+    RC(d2h(c, &hc, j.ctrl));
+    if (hc.out_count <= out_cap) break;
+    out_cap = (uint64_t)hc.out_count + 1024;
+  }
+  // final exclusions
+  fill_u64(reinterpret_cast<uint64_t*>(&j.ctrl->n_flagged), 1, 0, s);
+  fill_u64(reinterpret_cast<uint64_t*>(&j.ctrl->st_flagged[0]), 1, 0, s);
+  launch_count_flags(j.flags, N, &j.ctrl->st_flagged[0], &j.ctrl->n_flagged, s);
+  LAUNCHCK();
+  *hc_out = hc;
+  return FAST_LSH_OK;
+}
+
 }  // namespace
 
 int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, const fast_lsh_fps* f,
-                       const fast_lsh_filter* flt, uint32_t flags, fast_lsh_stats* per_station,
-                       uint64_t* station_offsets) {
+                       const fast_lsh_filter* flt_in, uint32_t flags, fast_lsh_stats* per_station,
+                       uint64_t* station_offsets, uint32_t parts) {
   hipStream_t s = c->stream;
   const bool distinct = (flags & FAST_LSH_WANT_DISTINCT) != 0;
+  // The partitioned search applies the occurrence filter dynamically per
+  // partition; the bucket stage then runs without its static form.
+  fast_lsh_filter flt_buckets = *flt_in;
+  if (parts) flt_buckets.occ_num = flt_buckets.occ_den = 0;
+  const fast_lsh_filter* flt = &flt_buckets;
   Job j;
+  j.parts = parts;
   j.S = S;
   j.f = f;
   j.h = h;
@@ -404,7 +499,8 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
     return FAST_LSH_OK;
   }
   const uint64_t N = j.N, t = j.t, tn = t * N;
-  j.pl = make_plan(j.t, flt->min_votes, distinct, true);
+  // the partitioned passes find each pair's first shared table: one table group
+  j.pl = make_plan(j.t, flt->min_votes, distinct || parts > 0, true);
   uint64_t n_max = 0;
   for (uint32_t st = 0; st < S; ++st) n_max = std::max<uint64_t>(n_max, f[st].n);
   j.B = c->config.bin_bits ? c->config.bin_bits : bin_bits(n_max, S > 1);
@@ -522,7 +618,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   }
 
   // 1-4: the fixed-shape prefix, eager or as a replayed graph
-  const bool use_graph = (flags & FAST_LSH_USE_GRAPH) && !tune;
+  const bool use_graph = (flags & FAST_LSH_USE_GRAPH) && !tune && !parts;
   if (use_graph) {
     std::vector<uint64_t> key{S, N, t, h->band_rows, h->scheme, h->dim, flt->min_lag, flt->min_votes,
                               flt->occ_num, flt->occ_den, flags, j.tc.radix_variant, j.tc.bucket_chunk,
@@ -576,6 +672,10 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   Ctrl hc;
   RC(d2h(c, &hc, j.ctrl));
   if (hc.err) return fl_fail(FAST_LSH_E_INVALID, "a fingerprint is empty or holds an index >= dim (%u)", h->dim);
+  if (parts) {
+    RC(run_partitions(c, j, *flt_in, hc.big_count, out_cap, &hc));
+    return finish_output(c, j, hc.out_count, distinct, per_station, station_offsets);
+  }
 
   // 4b. large buckets; 4c. a second pair pass if the output overflowed
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -590,7 +690,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
       prof_end(c);
       LAUNCHCK();
     }
-    RC(run_big_pairs(c, j, hc.big_count));
+    RC(run_big_pairs(c, j, hc.big_count, j.pa, j.work));
     RC(d2h(c, &hc, j.ctrl));
     if (hc.out_count <= out_cap) break;
   }
@@ -813,7 +913,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
       prof_end(c);
       LAUNCHCK();
       RC(d2h(c, &hc, j.ctrl));
-      RC(run_big_pairs(c, j, hc.big_count));
+      RC(run_big_pairs(c, j, hc.big_count, j.pa, j.work));
     }
     RC(d2h(c, &hc, j.ctrl));
     if (hc.out_count <= out_cap) break;
@@ -916,6 +1016,26 @@ int fast_lsh_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_
   HIPCK(hipSetDevice(c->device));
   fast_lsh_stats local;
   RC(fl_search_bounded(c, h, f, flt, flags, group_tables, &local));
+  if (st) *st = local;
+  if (local.n_out > capacity)
+    return fl_fail(FAST_LSH_E_CAPACITY, "%llu pairs do not fit capacity %llu", (unsigned long long)local.n_out,
+                   (unsigned long long)capacity);
+  return fast_lsh_copy_result(c, oi, oj, ov, capacity);
+}
+
+int fast_lsh_search_partitioned(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps* f,
+                                const fast_lsh_filter* flt, uint32_t flags, uint32_t n_partitions, uint32_t* oi,
+                                uint32_t* oj, uint8_t* ov, uint64_t capacity, fast_lsh_stats* st) {
+  if (!c) return fl_fail(FAST_LSH_E_INVALID, "ctx is NULL");
+  RC(fl_check_hash(h));
+  RC(fl_check_fps(f));
+  RC(check_filter(flt, flags));
+  if (flags & FAST_LSH_USE_GRAPH) return fl_fail(FAST_LSH_E_INVALID, "the partitioned search is not captured as a graph");
+  if (n_partitions < 1) return fl_fail(FAST_LSH_E_INVALID, "n_partitions must be >= 1");
+  HIPCK(hipSetDevice(c->device));
+  fast_lsh_stats local;
+  RC(fl_search_stations(c, h, 1, f, flt, flags, &local, nullptr, (uint32_t)std::min<uint64_t>(n_partitions,
+                                                                                               std::max<uint64_t>(f->n, 1))));
   if (st) *st = local;
   if (local.n_out > capacity)
     return fl_fail(FAST_LSH_E_CAPACITY, "%llu pairs do not fit capacity %llu", (unsigned long long)local.n_out,

@@ -124,6 +124,9 @@ def library():
         lib.fast_lsh_channel_merge.argtypes = [_vp, _u32, ctypes.POINTER(Pairs), _u64, _u32, _vp, _vp, _vp, _u64,
                                                ctypes.POINTER(_u64)]
         lib.fast_lsh_channel_merge_noalloc.argtypes = lib.fast_lsh_channel_merge.argtypes
+        lib.fast_lsh_search_partitioned.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps),
+                                                    ctypes.POINTER(Filter), _u32, _u32, _vp, _vp, _vp, _u64,
+                                                    ctypes.POINTER(_Stats)]
         lib.fast_lsh_query.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps), ctypes.POINTER(Fps), _u32,
                                        _vp, _vp, _vp, _u64, ctypes.POINTER(_Stats)]
         lib.fast_lsh_station_clusters.argtypes = [_vp, _vp, _vp, _vp, _u64, ctypes.POINTER(ClusterParams), _vp,
@@ -209,6 +212,26 @@ class FastLSH:
         p = _Profile()
         _check(library().fast_lsh_profile_read(self._ctx, ctypes.byref(p)))
         return {name: (p.ms[k], int(p.launches[k])) for k, name in enumerate(PROFILE_STAGES)}
+
+    def search_partitioned(self, rows, dim, t, r, scheme, a, b, min_lag, min_votes, occ_num=0, occ_den=0,
+                           n_partitions=1, want_distinct=False, capacity: int | None = None):
+        """Partitioned search with the dynamic occurrence filter (sections 6.4,
+        6.5): sorted (i, j, votes) CUDA tensors and Stats."""
+        h, keep = _hash_struct(dim, t, r, scheme, a, b)
+        f, keep2 = _fps_struct(rows)
+        flt = Filter(min_lag, min_votes, occ_num, occ_den)
+        flags = WANT_DISTINCT if want_distinct else 0
+        cap = max(1, f.n // 4) if capacity is None else capacity
+        oi, oj, ov = self._outputs(cap)
+        st = _Stats()
+        rc = library().fast_lsh_search_partitioned(self._ctx, ctypes.byref(h), ctypes.byref(f), ctypes.byref(flt),
+                                                   flags, n_partitions, oi.data_ptr(), oj.data_ptr(), ov.data_ptr(),
+                                                   cap, ctypes.byref(st))
+        if rc == E_CAPACITY and capacity is None:
+            rc, (oi, oj, ov) = self._refetch(rc, st.n_out, capacity)
+        _check(rc)
+        m = st.n_out
+        return oi[:m], oj[:m], ov[:m], Stats(*[int(getattr(st, k)) for k, _ in _Stats._fields_])
 
     def query(self, queries, dataset, dim, t, r, scheme, a, b, min_votes, capacity: int | None = None):
         """Query-only hashing (section 6.4): (q, x, votes) CUDA tensors of the
