@@ -93,7 +93,8 @@ def sig_traffic(n):
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--workload", choices=("headline", "station", "batched", "bounded", "serving", "alignment"),
+    ap.add_argument("--workload", choices=("headline", "station", "batched", "bounded", "serving", "alignment",
+                                           "query", "partitioned"),
                     default="headline",
                     help="headline (default): the 5-year station (157,788,000 fingerprints, tables 10 at a "
                          "time) timed over the steps, then the streaming workload's latency; station: one "
@@ -101,7 +102,9 @@ def parse():
                          "resident, 3,600-row chunks arriving as Poisson streams; batched: 12 stations of "
                          "1-16 M fingerprints in one search, against 12 sequential searches; alignment: three "
                          "channels of the 90-day station searched with a lenient threshold, then their channel "
-                         "merge and station clusters timed")
+                         "merge and station clusters timed; query: 1,000 queries against the 90-day station "
+                         "with only the queries hashed, beside the plain search of both; partitioned: the "
+                         "90-day station in three partitions with the dynamic occurrence filter")
     ap.add_argument("--chunks", type=int, default=3000, help="serving: chunks at the offered load")
     ap.add_argument("--rate", type=float, default=40.0, help="serving: offered chunks/s (all stations)")
     ap.add_argument("--stations", type=int, default=8, help="serving: stations")
@@ -151,6 +154,10 @@ def main():
         line["latency_ms"] = line["offered_load"]["latency_ms"]
     elif args.workload == "alignment":
         line = run_alignment(args)
+    elif args.workload == "query":
+        line = run_query(args)
+    elif args.workload == "partitioned":
+        line = run_partitioned(args)
     else:
         line = run_batched(args)
     print(json.dumps(line), flush=True)
@@ -732,6 +739,135 @@ def run_alignment(args):
                             "cpu": cpu_model(),
                             "sample": f"the whole input ({total} pairs), merge and clusters in {cpu_s:.1f} s "
                                       "(single-threaded code)"}
+    ctx.close()
+    return line
+
+
+def run_query(args, nq=1000):
+    """Query-only hashing: nq queries (half of them rows of the station,
+    half independent fingerprints) against the 90-day station; one step =
+    one query-only search.  The plain search of station plus queries (tables
+    over everything) is timed beside it."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1803_09835_amd as fl
+
+    N = args.n or synth.STATION_90D
+    dim, t, r, scheme, v = 4096, 100, 4, fl.MINMAX, 4
+    rows = synth.generate(synth.station(n=N, seed=102))
+    rng = np.random.default_rng(306)
+    qrows = np.concatenate([rows[rng.choice(N, nq // 2, replace=False)],
+                            synth.generate(synth.Spec(n=nq - nq // 2, seed=307))])
+    a, b = fl.make_hash(202, fl.n_funcs(t, r, scheme))
+    d, q = fl.to_device_rows(rows), fl.to_device_rows(qrows)
+    ctx = fl.FastLSH(0)
+
+    def step():
+        return ctx.query(q, d, dim, t, r, scheme, a, b, v)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+        log(f"# step {k + 1}/{args.steps}: {out[3].n_out} pairs, {out[3].e_raw} matches")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    prof = ctx.profile_read()
+    stage_ms, stage_launch = stage_table(prof, args.steps)
+    both = torch.cat([d, q])
+    ctx.search(both, dim, t, r, scheme, a, b, 1, v)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    ctx.search(both, dim, t, r, scheme, a, b, 1, v)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - tp) * 1000.0
+    sig = sig_roofline(N, fl.n_funcs(t, r, scheme), scheme, stage_ms["signatures"], stage_launch["signatures"],
+                       "k_sig<200,minmax> (dataset and queries)")
+    line = {
+        "metric": "dataset fingerprints/s through query-only hashing",
+        "value": round(N / (ms / 1000.0), 1),
+        "unit": "fingerprints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{nq} queries (half of them rows of the station, half independent) against one "
+                               "station, 90 days at 1 s lag (7,776,000 fingerprints); Min-Max t=100 r=4, v=4; only "
+                               "the queries hashed into tables",
+                   "n": N, "queries": nq, "tables": t, "rows": r, "min_votes": v},
+        "pairs": out[3].n_out, "matches": out[3].e_raw,
+        "stage_ms": {k: round(x, 3) for k, x in stage_ms.items() if x},
+        "plain_search_of_dataset_and_queries_ms": round(plain_ms, 3),
+        "speedup_vs_plain_search": round(plain_ms / ms, 2),
+        "roofline": sig,
+    }
+    import oracle
+    ns = min(200_000, N)
+    tc = time.perf_counter()
+    oracle.query(qrows, rows[:ns], dim, t, r, oracle.MINMAX, a, b, v)
+    cpu_s = time.perf_counter() - tc
+    line["cpu_baseline"] = {"value": round(ns / cpu_s, 1), "unit": "fingerprints/s", "cores": oracle.max_threads(),
+                            "kind": "oracle", "cpu": cpu_model(),
+                            "sample": f"the {nq} queries against the first {ns} fingerprints, {cpu_s:.1f} s"}
+    ctx.close()
+    return line
+
+
+def run_partitioned(args, parts=3):
+    """The 90-day station searched in three partitions (months) with the
+    dynamic occurrence filter at 1 % of each partition; one step = one
+    partitioned search.  The plain search (static filter) is timed beside it."""
+    import torch
+
+    import synth
+    import paper_1803_09835_amd as fl
+
+    N = args.n or synth.STATION_90D
+    dim, t, r, scheme, L, v = 4096, 100, 4, fl.MINMAX, 5, 4
+    rows = synth.generate(synth.station(n=N, seed=102))
+    a, b = fl.make_hash(202, fl.n_funcs(t, r, scheme))
+    d = fl.to_device_rows(rows)
+    ctx = fl.FastLSH(0)
+
+    def step():
+        return ctx.search_partitioned(d, dim, t, r, scheme, a, b, L, v, 1, 100, n_partitions=parts)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out = step()
+        log(f"# step {k + 1}/{args.steps}: {out[3].n_out} pairs, {out[3].n_flagged} excluded")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    prof = ctx.profile_read()
+    stage_ms, _ = stage_table(prof, args.steps)
+    ctx.search(d, dim, t, r, scheme, a, b, L, v, 1, 100)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    plain = ctx.search(d, dim, t, r, scheme, a, b, L, v, 1, 100)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - tp) * 1000.0
+    line = {
+        "metric": "fingerprints/s through the partitioned search with the dynamic occurrence filter",
+        "value": round(N / (ms / 1000.0), 1),
+        "unit": "fingerprints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "one station, 90 days at 1 s lag (7,776,000 fingerprints) in three partitions of 30 "
+                               "days; Min-Max t=100 r=4, lag 5, v=4; dynamic occurrence filter at 1 % of each "
+                               "partition", "n": N, "partitions": parts, "tables": t, "min_votes": v},
+        "stats": out[3].__dict__,
+        "same_pairs_as_plain_search": bool(all(torch.equal(x, y) for x, y in zip(out[:3], plain[:3]))),
+        "stage_ms": {k: round(x, 3) for k, x in stage_ms.items() if x},
+        "plain_search_ms": round(plain_ms, 3),
+        "roofline": None,
+    }
     ctx.close()
     return line
 

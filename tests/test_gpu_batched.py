@@ -208,7 +208,10 @@ def test_launch_shapes_identical():
         a, b = fl.make_hash(202, 200)
         dev = [fl.to_device_rows(s) for s in stations]
         ref = c.search_batched(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
-        assert c.config_used() == {"radix_tile": 16384, "bucket_chunk": 512, "autotune": False}
+        used = c.config_used()
+        assert {k: used[k] for k in ("radix_tile", "bucket_chunk", "autotune")} == \
+            {"radix_tile": 16384, "bucket_chunk": 512, "autotune": False}
+        assert used["bin_bits"] == 24  # 70,000 fingerprints: 15 bits plus the four station bits, two passes
         for tile in (16384, 8192, 4096):
             for chunk in (256, 768, 1024, 1536):
                 say(f"[shapes] radix_tile={tile} bucket_chunk={chunk}")
