@@ -33,7 +33,7 @@ _SRC = os.path.join(_HERE, "synth.c")
 def build() -> str:
     """Compile ``libsynth.so`` in place (always recompiles)."""
     tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", _SRC, "-o", tmp])
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", _SRC, "-o", tmp, "-lm"])
     os.replace(tmp, _SO)
     return _SO
 
@@ -58,6 +58,13 @@ class _Spec(ctypes.Structure):
     ]
 
 
+class _WaveSpec(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("n_sources", ctypes.c_uint32),
+                ("rep_min", ctypes.c_uint32), ("rep_max", ctypes.c_uint32), ("event_len", ctypes.c_uint32),
+                ("noise_std", ctypes.c_float), ("amp_lo", ctypes.c_float), ("amp_hi", ctypes.c_float),
+                ("reserved", ctypes.c_uint32)]
+
+
 _LIB = None
 _LOCK = threading.Lock()
 
@@ -78,6 +85,11 @@ def _lib():
                                              ctypes.c_void_p, ctypes.c_void_p]
         lib.synth_generate_range.restype = ctypes.c_int
         lib.synth_planted_count.argtypes = [ctypes.POINTER(_Spec)]
+        lib.synth_waveform_range.argtypes = [ctypes.POINTER(_WaveSpec), ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.synth_waveform_range.restype = ctypes.c_int
+        lib.synth_wave_events.argtypes = [ctypes.POINTER(_WaveSpec)]
+        lib.synth_wave_events.restype = ctypes.c_uint64
         lib.synth_planted_count.restype = ctypes.c_uint64
         _LIB = lib
     return _LIB
@@ -169,3 +181,53 @@ def with_noise(spec: Spec, permille: int = 50, keep: int = 190) -> Spec:
     """Test-only variant: a repeating-noise source fills `permille` of all
     slots with copies keeping `keep` of its bits (drives the occurrence filter)."""
     return replace(spec, noise_permille=permille, noise_keep=keep)
+
+
+# --------------------------------------------------------------------------
+# Continuous waveforms (input of the fingerprint extraction)
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class WaveSpec:
+    """One channel sampled at 100 Hz: Gaussian noise of noise_std plus
+    n_sources repeating sources (rep_min..rep_max events each, event_len
+    samples, a P and an S wave packet, amplitude ~ U[amp_lo, amp_hi])."""
+    n: int
+    seed: int = 0
+    n_sources: int = 0
+    rep_min: int = 1
+    rep_max: int = 1
+    event_len: int = 1500
+    noise_std: float = 1.0
+    amp_lo: float = 2.0
+    amp_hi: float = 8.0
+
+    def _c(self) -> _WaveSpec:
+        return _WaveSpec(self.n, self.seed, self.n_sources, self.rep_min, self.rep_max, self.event_len,
+                         self.noise_std, self.amp_lo, self.amp_hi, 0)
+
+
+def waveform(spec: WaveSpec, lo: int = 0, hi: int | None = None, events: bool = False, out: np.ndarray | None = None):
+    """Samples [lo, hi) as float32 (and, with ``events``, every event's
+    (start sample, source) arrays)."""
+    hi = spec.n if hi is None else hi
+    x = out if out is not None else np.empty(hi - lo, dtype=np.float32)
+    assert x.dtype == np.float32 and x.flags.c_contiguous and len(x) == hi - lo
+    c = spec._c()
+    ne = int(_lib().synth_wave_events(ctypes.byref(c)))
+    st = np.empty(max(ne, 1), dtype=np.uint64) if events else None
+    so = np.empty(max(ne, 1), dtype=np.uint32) if events else None
+    rc = _lib().synth_waveform_range(ctypes.byref(c), lo, hi, x.ctypes.data, st.ctypes.data if events else None,
+                                     so.ctypes.data if events else None)
+    if rc == 3:
+        raise MemoryError("synth: a host allocation failed")
+    if rc != 0:
+        raise ValueError(f"synth: invalid waveform spec {spec} (code {rc})")
+    return (x, st[:ne], so[:ne]) if events else x
+
+
+def station_waveform(days: float = 90, seed: int = 402, sources_per_90d: int = 2000) -> WaveSpec:
+    """A station's continuous record at 100 Hz with repeating sources (3-40
+    events each), the waveform counterpart of ``station``."""
+    n = int(round(days * DAY * 100))
+    ns = max(1, round(sources_per_90d * days / 90))
+    return WaveSpec(n=n, seed=seed, n_sources=ns, rep_min=3, rep_max=40)

@@ -29,6 +29,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 #define TAG_BG 1ull      /* independent background row, indexed by row */
 #define TAG_CHAIN 2ull   /* the Markov chain (one sequential stream)    */
@@ -326,4 +327,119 @@ int synth_generate_range(const synth_spec *sp, uint64_t lo, uint64_t hi, uint16_
 
 int synth_generate(const synth_spec *sp, uint16_t *out, int32_t *label) {
   return synth_generate_range(sp, 0, sp ? sp->n : 0, out, label);
+}
+
+/* ---------------------------------------------------------------------------
+ * Synthetic continuous waveforms (input of the fingerprint extraction).
+ *
+ * One channel of ground motion sampled at a fixed rate: Gaussian background
+ * noise, plus repeating sources whose waveform (a template: a P wave packet
+ * followed by a larger, slower S wave packet, each a decaying sinusoid) is
+ * added at random times with random amplitudes.  Sample k of the noise is
+ * drawn from a stream keyed by (seed, k), so any range of samples can be
+ * generated on its own; the events are drawn from streams keyed by the seed
+ * and the source index.  Events never overlap one another.
+ * ------------------------------------------------------------------------- */
+#define TAG_WNOISE 8ull  /* background sample k                        */
+#define TAG_WSRC 9ull    /* source s: repeat count and template shape    */
+#define TAG_WSLOT 10ull  /* event start times (one sequential stream)    */
+#define TAG_WAMP 11ull   /* event e: amplitude                           */
+
+typedef struct {
+  uint64_t n;            /* samples                                    */
+  uint64_t seed;
+  uint32_t n_sources;    /* repeating sources                          */
+  uint32_t rep_min, rep_max;
+  uint32_t event_len;    /* samples per event                          */
+  float noise_std;       /* background standard deviation              */
+  float amp_lo, amp_hi;  /* event amplitude ~ U[amp_lo, amp_hi]        */
+  uint32_t reserved;
+} synth_wave_spec;
+
+typedef struct {
+  float p_at, s_at, p_f, s_f, p_tau, s_tau, p_amp, s_amp;  /* samples, cycles per sample, samples */
+} wave_tpl;
+
+static void wave_template(uint64_t seed, uint32_t s, wave_tpl *t, uint32_t len) {
+  rng_t r = stream_for(seed, TAG_WSRC, s);
+  (void)sm64_next(&r); /* the repeat count's draw */
+  t->p_at = (float)(0.10 + 0.05 * unit(&r)) * (float)len;
+  t->s_at = t->p_at + (float)(0.20 + 0.15 * unit(&r)) * (float)len;
+  t->p_f = (float)((5.0 + 7.0 * unit(&r)) / 100.0);  /* 5-12 Hz at 100 Hz */
+  t->s_f = (float)((2.0 + 6.0 * unit(&r)) / 100.0);  /* 2-8 Hz */
+  t->p_tau = (float)(0.03 + 0.05 * unit(&r)) * (float)len;
+  t->s_tau = (float)(0.06 + 0.10 * unit(&r)) * (float)len;
+  t->p_amp = (float)(0.5 + 0.5 * unit(&r));
+  t->s_amp = (float)(1.0 + 1.0 * unit(&r));
+}
+
+static float wave_template_at(const wave_tpl *t, uint32_t q) {
+  double v = 0.0;
+  const double x = (double)q;
+  if (x >= t->p_at) v += t->p_amp * exp(-(x - t->p_at) / t->p_tau) * sin(6.283185307179586 * t->p_f * (x - t->p_at));
+  if (x >= t->s_at) v += t->s_amp * exp(-(x - t->s_at) / t->s_tau) * sin(6.283185307179586 * t->s_f * (x - t->s_at));
+  return (float)v;
+}
+
+static uint32_t wave_repeats(const synth_wave_spec *sp, uint32_t s) {
+  rng_t r = stream_for(sp->seed, TAG_WSRC, s);
+  return sp->rep_min + below(&r, sp->rep_max - sp->rep_min + 1);
+}
+
+/* Number of events the spec places (sum of the sources' repeat counts). */
+uint64_t synth_wave_events(const synth_wave_spec *sp) {
+  uint64_t e = 0;
+  for (uint32_t s = 0; s < sp->n_sources; ++s) e += wave_repeats(sp, s);
+  return e;
+}
+
+/* Samples [lo, hi) into out[hi - lo]; when start/source are non-NULL they
+ * receive every event's first sample and source (synth_wave_events entries,
+ * ordered by source then repeat).  Returns 0, 1 for an invalid spec or range,
+ * 2 when the events do not fit without overlap, 3 when an allocation fails. */
+int synth_waveform_range(const synth_wave_spec *sp, uint64_t lo, uint64_t hi, float *out, uint64_t *start,
+                         uint32_t *source) {
+  if (!sp || lo > hi || hi > sp->n || (!out && hi > lo) || sp->event_len == 0 || sp->rep_min == 0 ||
+      sp->rep_max < sp->rep_min || sp->amp_hi < sp->amp_lo)
+    return 1;
+  const uint64_t ne = synth_wave_events(sp);
+  const uint64_t slots = sp->n / sp->event_len; /* events start on distinct multiples of event_len */
+  if (ne > slots / 2) return 2;
+  /* 1. background */
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < (int64_t)(hi - lo); ++q) {
+    rng_t r = stream_for(sp->seed, TAG_WNOISE, lo + (uint64_t)q);
+    const double u1 = (double)((sm64_next(&r) >> 11) + 1) * (1.0 / 9007199254740993.0);
+    const double u2 = unit(&r);
+    out[q] = (float)(sp->noise_std * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+  }
+  /* 2. events: distinct slots drawn in order, one per event */
+  uint64_t *slot = (uint64_t *)malloc((ne ? ne : 1) * sizeof(uint64_t));
+  uint8_t *used = (uint8_t *)calloc(slots ? slots : 1, 1);
+  wave_tpl *tpl = (wave_tpl *)malloc((sp->n_sources ? sp->n_sources : 1) * sizeof(wave_tpl));
+  if (!slot || !used || !tpl) { free(slot); free(used); free(tpl); return 3; }
+  rng_t rs = stream_for(sp->seed, TAG_WSLOT, 0);
+  for (uint64_t e = 0; e < ne; ++e) {
+    uint64_t x;
+    do { x = ((sm64_next(&rs) >> 11) % slots); } while (used[x]);
+    used[x] = 1;
+    slot[e] = x * sp->event_len;
+  }
+  for (uint32_t s = 0; s < sp->n_sources; ++s) wave_template(sp->seed, s, &tpl[s], sp->event_len);
+  uint64_t e = 0;
+  for (uint32_t s = 0; s < sp->n_sources; ++s) {
+    const uint32_t reps = wave_repeats(sp, s);
+    for (uint32_t c = 0; c < reps; ++c, ++e) {
+      const uint64_t t0 = slot[e];
+      if (start) start[e] = t0;
+      if (source) source[e] = s;
+      if (t0 + sp->event_len <= lo || t0 >= hi) continue;
+      rng_t ra = stream_for(sp->seed, TAG_WAMP, e);
+      const float amp = (float)(sp->amp_lo + (sp->amp_hi - sp->amp_lo) * unit(&ra));
+      const uint64_t a = t0 > lo ? t0 : lo, b = t0 + sp->event_len < hi ? t0 + sp->event_len : hi;
+      for (uint64_t k = a; k < b; ++k) out[k - lo] += amp * wave_template_at(&tpl[s], (uint32_t)(k - t0));
+    }
+  }
+  free(slot); free(used); free(tpl);
+  return 0;
 }
