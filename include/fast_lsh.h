@@ -368,7 +368,8 @@ enum {
                                     mixed keys rebuilt from stored words      */
   FAST_LSH_STAGE_CHANNEL_MERGE = 9, /* fast_lsh_channel_merge                 */
   FAST_LSH_STAGE_CLUSTERS = 10,  /* fast_lsh_station_clusters                 */
-  FAST_LSH_PROFILE_STAGES = 11
+  FAST_LSH_STAGE_FINGERPRINTS = 11, /* fast_lsh_fingerprints                  */
+  FAST_LSH_PROFILE_STAGES = 12
 };
 
 typedef struct {
@@ -415,6 +416,42 @@ int fast_lsh_search_partitioned(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, co
                                 const fast_lsh_filter *filter, uint32_t flags, uint32_t n_partitions,
                                 uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes, uint64_t capacity,
                                 fast_lsh_stats *stats);
+
+/* Fingerprint extraction parameters (section 5.1; the paper gives no
+ * values).  window: samples per STFT frame (periodic Hann), at most 256;
+ * hop: samples between frames (1-64; window * 65 + 256 * hop <= 16384);
+ * [band_lo, band_hi): the frequency bins kept (bin k = k / window cycles
+ * per sample), 8, 16, 32 or 64 of them = the image rows; fp_frames frames
+ * per fingerprint, averaged time_ds at a time into fp_frames / time_ds
+ * image columns (a power of two); rows * cols in [64, 2048]; fp_lag: frames
+ * between consecutive fingerprints; top_k: set bits per fingerprint
+ * (<= rows * cols).  The fingerprint dimension is 2 * rows * cols. */
+typedef struct {
+  uint32_t window, hop, band_lo, band_hi, fp_frames, time_ds, fp_lag, top_k;
+} fast_lsh_fp_params;
+
+/* Fingerprint extraction (section 5.1; section 5.2 normalization statistics
+ * from a sample) of one channel: samples[n_samples] (DEVICE float32) ->
+ * n_fp = (n_frames - fp_frames) / fp_lag + 1 fingerprints, n_frames =
+ * (n_samples - window) / hop + 1.  Steps: STFT power in the band; per
+ * fingerprint the spectral image (rows = bins, columns = averaged frames);
+ * the 2-D orthonormal Haar transform (rows, then columns; per axis the
+ * final average, then details coarsest to finest; coefficient c = row *
+ * cols + column); z = (w - median) / MAD per coefficient (z = 0 where
+ * MAD = 0), median and MAD the lower middle values over the fingerprints
+ * sample_ids[n_sample] (DEVICE, each < n_fp; the caller draws the sample);
+ * the top_k coefficients of largest |z| (ties: smaller c; z != 0 only);
+ * bit 2c for z > 0, 2c + 1 for z < 0.  Output: out[n_fp][top_k] (DEVICE
+ * uint16, ascending bit indices; a fingerprint with fewer than top_k
+ * non-zero z fills the rest with 0xFFFF), out_count[n_fp] (DEVICE, optional:
+ * bits per fingerprint), med_mad (DEVICE, optional: 2 * rows * cols floats,
+ * the medians then the MADs).  *n_fp (HOST) is set even on E_CAPACITY
+ * (n_fp > capacity: nothing written).  Arithmetic in float32.  Workspace:
+ * the spectrogram (4 * rows bytes per frame) and 24 bytes per (sampled
+ * fingerprint, coefficient).  Blocking. */
+int fast_lsh_fingerprints(fast_lsh_ctx *ctx, const float *samples, uint64_t n_samples,
+                          const fast_lsh_fp_params *params, const uint64_t *sample_ids, uint64_t n_sample,
+                          uint16_t *out, uint32_t *out_count, uint64_t capacity, uint64_t *n_fp, float *med_mad);
 
 /* Query-only hashing (section 6.4, "Partition"): only the queries are
  * hashed into the t tables; every dataset item is looked up in each table,

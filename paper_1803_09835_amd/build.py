@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfast_lsh.so")
-SOURCES = ["sig.hip", "sort.hip", "pairs.hip", "api.hip", "search.hip", "serve.hip", "align.hip", "query.hip"]
+SOURCES = ["sig.hip", "sort.hip", "pairs.hip", "api.hip", "search.hip", "serve.hip", "align.hip", "query.hip", "fingerprint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -42,7 +42,7 @@ class _Stats(ctypes.Structure):
 
 
 PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pairs", "output", "graph", "split_keys",
-                  "channel_merge", "clusters")
+                  "channel_merge", "clusters", "fingerprints")
 
 
 class Config(ctypes.Structure):
@@ -66,6 +66,10 @@ class ClusterParams(ctypes.Structure):
 CLUSTER_DTYPE = np.dtype([("dt_min", "<u4"), ("dt_max", "<u4"), ("idx1_min", "<u4"), ("idx1_max", "<u4"),
                           ("n_entries", "<u4"), ("peak_sim", "<u4"), ("peak_dt", "<u4"), ("peak_idx1", "<u4"),
                           ("sim_sum", "<u8")])
+
+
+class FpParams(ctypes.Structure):
+    _fields_ = [(f, _u32) for f in ("window", "hop", "band_lo", "band_hi", "fp_frames", "time_ds", "fp_lag", "top_k")]
 
 
 class _Work(ctypes.Structure):
@@ -127,6 +131,8 @@ def library():
         lib.fast_lsh_search_partitioned.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps),
                                                     ctypes.POINTER(Filter), _u32, _u32, _vp, _vp, _vp, _u64,
                                                     ctypes.POINTER(_Stats)]
+        lib.fast_lsh_fingerprints.argtypes = [_vp, _vp, _u64, ctypes.POINTER(FpParams), _vp, _u64, _vp, _vp, _u64,
+                                              ctypes.POINTER(_u64), _vp]
         lib.fast_lsh_query.argtypes = [_vp, ctypes.POINTER(Hash), ctypes.POINTER(Fps), ctypes.POINTER(Fps), _u32,
                                        _vp, _vp, _vp, _u64, ctypes.POINTER(_Stats)]
         lib.fast_lsh_station_clusters.argtypes = [_vp, _vp, _vp, _vp, _u64, ctypes.POINTER(ClusterParams), _vp,
@@ -232,6 +238,31 @@ class FastLSH:
         _check(rc)
         m = st.n_out
         return oi[:m], oj[:m], ov[:m], Stats(*[int(getattr(st, k)) for k, _ in _Stats._fields_])
+
+    def fingerprints(self, samples, sample_ids, window=200, hop=10, band_lo=4, band_hi=36, fp_frames=128, time_ds=2,
+                     fp_lag=10, top_k=200, want_stats=False):
+        """Fingerprints (section 5) of a float32 CUDA tensor of samples: an
+        int16 CUDA tensor [n_fp, top_k] of bit indices (uint16 bits), the
+        per-fingerprint counts, and (want_stats) the medians and MADs."""
+        prm = FpParams(window, hop, band_lo, band_hi, fp_frames, time_ds, fp_lag, top_k)
+        assert samples.is_cuda and samples.dtype == torch.float32 and samples.is_contiguous()
+        ids = torch.as_tensor(sample_ids, dtype=torch.int64, device=f"cuda:{self.device}").contiguous()
+        nfp = _u64()
+        rc = library().fast_lsh_fingerprints(self._ctx, samples.data_ptr(), samples.numel(), ctypes.byref(prm),
+                                             ids.data_ptr(), ids.numel(), None, None, 0, ctypes.byref(nfp), None)
+        if rc not in (OK, E_CAPACITY):
+            _check(rc)
+        n = int(nfp.value)
+        dev = f"cuda:{self.device}"
+        out = torch.empty((max(n, 1), top_k), dtype=torch.int16, device=dev)
+        cnt = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        nc = (band_hi - band_lo) * (fp_frames // time_ds)
+        stats = torch.empty(2 * nc, dtype=torch.float32, device=dev) if want_stats else None
+        _check(library().fast_lsh_fingerprints(self._ctx, samples.data_ptr(), samples.numel(), ctypes.byref(prm),
+                                               ids.data_ptr(), ids.numel(), out.data_ptr(), cnt.data_ptr(), n,
+                                               ctypes.byref(nfp), stats.data_ptr() if want_stats else None))
+        res = (out[:n], cnt[:n])
+        return res + ((stats[:nc], stats[nc:]),) if want_stats else res
 
     def query(self, queries, dataset, dim, t, r, scheme, a, b, min_votes, capacity: int | None = None):
         """Query-only hashing (section 6.4): (q, x, votes) CUDA tensors of the

@@ -1,0 +1,127 @@
+"""GPU parity of the fingerprint extraction (section 5) through the C-ABI
+against the float64 oracle.  The kernels compute in float32, so values are
+compared within a tolerance and the integer decisions (which K coefficients,
+their signs) must agree except where the oracle's |z| lies within a relative
+1e-3 of its K-th largest value (the decision band fp32 rounding can move)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fingerprint as ofp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1803_09835_amd as fl  # noqa: E402
+
+BAND = 1e-3  # relative decision band around the K-th largest |z|
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fl.FastLSH(0)
+    yield c
+    c.close()
+
+
+def _check(ctx, x, p, sample, label, ids=None):
+    say(f"[fingerprints] {label}: {len(x)} samples, params {p}, sample {len(sample)}")
+    kw = dict(window=p.window, hop=p.hop, band_lo=p.band_lo, band_hi=p.band_hi, fp_frames=p.fp_frames,
+              time_ds=p.time_ds, fp_lag=p.fp_lag, top_k=p.top_k)
+    out, cnt, (med, mad) = ctx.fingerprints(torch.from_numpy(x).cuda(), sample, want_stats=True, **kw)
+    nf = ofp.n_fingerprints(len(x), p)
+    assert out.shape[0] == nf
+    ids = np.arange(nf) if ids is None else ids
+    wfp, z, wmed, wmad = ofp.fingerprints(x.astype(np.float64), p, sample, ids)
+    scale = np.abs(wmed).max() + wmad.max()
+    assert np.allclose(med.cpu().numpy(), wmed, rtol=1e-4, atol=1e-5 * scale)
+    assert np.allclose(mad.cpu().numpy(), wmad, rtol=1e-4, atol=1e-5 * scale)
+    got = out.cpu().numpy().view(np.uint16)
+    cnt = cnt.cpu().numpy()
+    moved = 0
+    for k, i in enumerate(ids):
+        g = got[i][: cnt[i]]
+        w = wfp[k]
+        assert (got[i][cnt[i]:] == 0xFFFF).all() and (np.diff(g.astype(np.int64)) > 0).all()
+        if np.array_equal(g, w):
+            continue
+        az = np.abs(z[k])
+        zk = np.sort(az)[-p.top_k]
+        # coefficients chosen by one side only must sit in the decision band,
+        # and a coefficient both choose must carry the same sign bit
+        gc, wc = set((g // 2).tolist()), set((w // 2).tolist())
+        for c in gc ^ wc:
+            assert abs(az[c] - zk) <= BAND * zk, (i, c, az[c], zk)
+            moved += 1
+        gs = {int(b) // 2: int(b) & 1 for b in g}
+        ws = {int(b) // 2: int(b) & 1 for b in w}
+        assert all(gs[c] == ws[c] for c in gc & wc)
+    total = sum(len(w) for w in wfp)
+    say(f"[fingerprints] {label}: {moved} of {total} bits in the decision band moved")
+    assert moved <= max(2, total // 1000)
+    return got, cnt
+
+
+def test_fingerprints_match_oracle(ctx):
+    spec = synth.WaveSpec(n=100 * 1800, seed=11, n_sources=6, rep_min=3, rep_max=5, noise_std=1.0)
+    x = synth.waveform(spec)
+    p = ofp.FpParams()
+    nf = ofp.n_fingerprints(len(x), p)
+    got, cnt = _check(ctx, x, p, np.arange(0, nf, 5), "30 min default")
+    assert (cnt == p.top_k).all()
+
+
+@pytest.mark.parametrize("prm", [dict(window=128, hop=8, band_lo=2, band_hi=18, fp_frames=64, time_ds=1, fp_lag=5,
+                                      top_k=50),
+                                 dict(window=64, hop=4, band_lo=0, band_hi=8, fp_frames=32, time_ds=4, fp_lag=3,
+                                      top_k=20),
+                                 dict(window=200, hop=10, band_lo=4, band_hi=68, fp_frames=128, time_ds=4, fp_lag=10,
+                                      top_k=300)])
+def test_fingerprints_other_shapes(ctx, prm):
+    # 16 x 64, 8 x 8 (one wave's 64 coefficients) and 64 x 32 images
+    spec = synth.WaveSpec(n=100 * 900, seed=12, n_sources=4, rep_min=3, rep_max=3, noise_std=1.0)
+    x = synth.waveform(spec)
+    p = ofp.FpParams(**prm)
+    nf = ofp.n_fingerprints(len(x), p)
+    _check(ctx, x, p, np.arange(0, nf, 3), f"shape {prm}")
+
+
+def test_fingerprints_ragged_tail_and_ties(ctx):
+    # a record whose last frames do not fill a fingerprint, a sample of one,
+    # and a silent stretch (many equal |z| and z = 0 coefficients)
+    rng = np.random.default_rng(13)
+    x = rng.normal(size=100 * 300 + 77).astype(np.float32)
+    x[5000:9000] = 0.0
+    p = ofp.FpParams()
+    nf = ofp.n_fingerprints(len(x), p)
+    _check(ctx, x, p, np.array([7]), "one-sample statistics", ids=None)
+    _check(ctx, x, p, np.arange(nf), "every fingerprint sampled")
+
+
+def test_fingerprints_identical_windows_and_errors(ctx):
+    rng = np.random.default_rng(14)
+    x = np.tile(rng.normal(size=1500).astype(np.float32), 20)
+    p = ofp.FpParams()
+    nf = ofp.n_fingerprints(len(x), p)
+    out, cnt = ctx.fingerprints(torch.from_numpy(x).cuda(), np.arange(0, nf, 2))
+    g = out.cpu().numpy()
+    assert all(np.array_equal(g[i], g[i + 15]) for i in range(nf - 15))
+    short = torch.zeros(100, dtype=torch.float32, device="cuda")
+    o, c = ctx.fingerprints(short, [0])
+    assert o.shape[0] == 0
+    with pytest.raises(fl.FastLshError) as e:
+        ctx.fingerprints(torch.from_numpy(x).cuda(), [nf])  # sample id out of range
+    assert e.value.code == fl.E_INVALID
+    with pytest.raises(fl.FastLshError) as e:
+        ctx.fingerprints(torch.from_numpy(x).cuda(), [0], band_lo=4, band_hi=30)  # 26 rows
+    assert e.value.code == fl.E_INVALID
