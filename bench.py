@@ -94,7 +94,7 @@ def sig_traffic(n):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--workload", choices=("headline", "station", "batched", "bounded", "serving", "alignment",
-                                           "query", "partitioned"),
+                                           "query", "partitioned", "fingerprints"),
                     default="headline",
                     help="headline (default): the 5-year station (157,788,000 fingerprints, tables 10 at a "
                          "time) timed over the steps, then the streaming workload's latency; station: one "
@@ -104,7 +104,8 @@ def parse():
                          "channels of the 90-day station searched with a lenient threshold, then their channel "
                          "merge and station clusters timed; query: 1,000 queries against the 90-day station "
                          "with only the queries hashed, beside the plain search of both; partitioned: the "
-                         "90-day station in three partitions with the dynamic occurrence filter")
+                         "90-day station in three partitions with the dynamic occurrence filter; fingerprints: "
+                         "fingerprint extraction of 90 days of 100 Hz waveform (7,776,000 fingerprints)")
     ap.add_argument("--chunks", type=int, default=3000, help="serving: chunks at the offered load")
     ap.add_argument("--rate", type=float, default=40.0, help="serving: offered chunks/s (all stations)")
     ap.add_argument("--stations", type=int, default=8, help="serving: stations")
@@ -158,6 +159,8 @@ def main():
         line = run_query(args)
     elif args.workload == "partitioned":
         line = run_partitioned(args)
+    elif args.workload == "fingerprints":
+        line = run_fingerprints(args)
     else:
         line = run_batched(args)
     print(json.dumps(line), flush=True)
@@ -868,6 +871,88 @@ def run_partitioned(args, parts=3):
         "plain_search_ms": round(plain_ms, 3),
         "roofline": None,
     }
+    ctx.close()
+    return line
+
+
+def run_fingerprints(args):
+    """Fingerprint extraction of one channel, 90 days at 100 Hz (777,600,000
+    samples: Gaussian noise with 2,000 repeating sources of 3-40 events),
+    window 200, hop 10, band bins 4-35, 128 frames per fingerprint averaged
+    in pairs, 1 s lag, K = 200: 7,776,000 fingerprints of 4,096 bits.  The
+    normalization statistics use a seeded 1 % sample of the fingerprints.
+    One step = one extraction from samples in HBM to fingerprints in HBM."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1803_09835_amd as fl
+
+    spec = synth.station_waveform(days=(args.n / 86_400 / 100) if args.n else 90)
+    window, hop, rows, fp_frames, fp_lag, top_k = 200, 10, 32, 128, 10, 200
+    n = spec.n
+    dev = torch.empty(n, dtype=torch.float32, device="cuda")
+    pinned = torch.empty(min(n, 100_000_000), dtype=torch.float32, pin_memory=True)
+    tg = time.time()
+    for lo in range(0, n, pinned.numel()):
+        hi = min(n, lo + pinned.numel())
+        synth.waveform(spec, lo, hi, out=pinned[: hi - lo].numpy())
+        dev[lo:hi].copy_(pinned[: hi - lo])
+    del pinned
+    frames = (n - window) // hop + 1
+    nf = (frames - fp_frames) // fp_lag + 1
+    rng = np.random.default_rng(405)
+    sample = np.sort(rng.choice(nf, max(1, nf // 100), replace=False))
+    log(f"# waveform of {n} samples in {time.time() - tg:.1f}s; {nf} fingerprints, sample {len(sample)}")
+    ctx = fl.FastLSH(0)
+
+    def step():
+        return ctx.fingerprints(dev, sample)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        out, cnt = step()
+        log(f"# step {k + 1}/{args.steps}: {out.shape[0]} fingerprints")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    prof = ctx.profile_read()
+    stage_ms, _ = stage_table(prof, args.steps)
+    flop = frames * rows * 2 * window * 2  # cosine and sine rows of every kept bin: one FMA per sample each
+    tf = flop / (stage_ms["spectrogram"] / 1000.0) / 1e12
+    full = int((cnt == top_k).sum().item())
+    line = {
+        "metric": "fingerprints/s through fingerprint extraction",
+        "value": round(nf / (ms / 1000.0), 1),
+        "unit": "fingerprints/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "one channel, 90 days at 100 Hz (777,600,000 samples, Gaussian noise, 2,000 repeating "
+                               "sources of 3-40 P/S events); STFT window 200 hop 10, bins 4-35, 128 frames averaged "
+                               "in pairs, 1 s lag, 2-D Haar, MAD over a 1 % sample, K = 200",
+                   "samples": n, "fingerprints": nf, "sample": len(sample), "dim": 2 * rows * fp_frames // 2,
+                   "top_k": top_k},
+        "fingerprints_with_k_bits": full,
+        "stage_ms": {k: round(x, 3) for k, x in stage_ms.items() if x},
+        "roofline": {"kernel": "k_stft", "bound": "fp32", "achieved": round(tf, 2), "peak": 157.3,
+                     "unit": "TFLOP/s (fp32 vector FMA)", "frac": round(tf / 157.3, 4), "traffic": None,
+                     "flop_per_frame": rows * 4 * window, "frames": frames},
+    }
+    from oracle import fingerprint as ofp
+    p = ofp.FpParams()
+    sl = 100 * 3600  # one hour of samples
+    xs = dev[:sl].cpu().numpy()
+    nfs = ofp.n_fingerprints(sl, p)
+    tc = time.perf_counter()
+    ofp.fingerprints(xs.astype(np.float64), p, np.arange(0, nfs, 100), np.arange(nfs))
+    cpu_s = time.perf_counter() - tc
+    line["cpu_baseline"] = {"value": round(nfs / cpu_s, 1), "unit": "fingerprints/s", "cores": 1, "kind": "oracle",
+                            "cpu": cpu_model(),
+                            "sample": f"the first hour ({nfs} fingerprints, statistics of every 100th), {cpu_s:.1f} s "
+                                      "in float64 numpy (one thread)"}
     ctx.close()
     return line
 

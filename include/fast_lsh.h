@@ -368,8 +368,10 @@ enum {
                                     mixed keys rebuilt from stored words      */
   FAST_LSH_STAGE_CHANNEL_MERGE = 9, /* fast_lsh_channel_merge                 */
   FAST_LSH_STAGE_CLUSTERS = 10,  /* fast_lsh_station_clusters                 */
-  FAST_LSH_STAGE_FINGERPRINTS = 11, /* fast_lsh_fingerprints                  */
-  FAST_LSH_PROFILE_STAGES = 12
+  FAST_LSH_STAGE_FINGERPRINTS = 11, /* fast_lsh_fingerprints: images, Haar,
+                                       statistics, top-K                      */
+  FAST_LSH_STAGE_SPECTROGRAM = 12,  /* fast_lsh_fingerprints: STFT power      */
+  FAST_LSH_PROFILE_STAGES = 13
 };
 
 typedef struct {

@@ -388,7 +388,7 @@ extern "C" int fast_lsh_fingerprints(fast_lsh_ctx* c, const float* samples, uint
   float* spec;
   RC(ws<float>(c, "fp_spec", a.n_frames * rows, &spec));
   // 1. spectrogram
-  prof_begin(c, FAST_LSH_STAGE_FINGERPRINTS);
+  prof_begin(c, FAST_LSH_STAGE_SPECTROGRAM);
   {
     const size_t lds = stft_lds_bytes(W, a.hop);
     const dim3 grid((unsigned)((a.n_frames + kFramesPerBlock - 1) / kFramesPerBlock), (rows + 31) / 32);
