@@ -384,7 +384,7 @@ int fast_lsh_profile_read(fast_lsh_ctx *ctx, fast_lsh_profile *out);
 
 /* Work counters of the last search on the context (fast_lsh_search,
  * _search_ex, _search_batched, _search_bounded), for rooflines: the buckets
- * above 32 members, whose pairs the tiled kernel checks.  big_members sums
+ * above 64 members, whose pairs the tiled kernel checks.  big_members sums
  * their sizes m and big_candidates their in-bucket pairs C(m, 2) (over every
  * table; part of e_raw); big_voted counts those pairs that pass the lag and
  * the exclusion (part of e_voted).  search_calls counts the searches

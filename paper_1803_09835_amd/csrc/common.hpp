@@ -239,7 +239,7 @@ __device__ __forceinline__ uint32_t station_of(const uint64_t* base, uint32_t nb
 
 // Buckets of at most kSmallBucket members are handled by the wave-per-chunk
 // pair kernel (their members staged in LDS); larger ones by the tile kernel.
-constexpr uint32_t kSmallBucket = 32;
+constexpr uint32_t kSmallBucket = 64;
 
 
 }  // namespace fl
