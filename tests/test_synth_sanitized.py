@@ -22,7 +22,7 @@ def test_generator_twelve_stations_concurrently_under_asan_ubsan(tmp_path):
     cmd = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-fno-omit-frame-pointer",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
            os.path.join(ROOT, "synth", "synth.c"), os.path.join(HERE, "synth_driver.c"),
-           "-lpthread", "-o", exe]
+           "-lpthread", "-lm", "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     env = dict(os.environ, ASAN_OPTIONS="halt_on_error=1:detect_leaks=1", OMP_NUM_THREADS="4",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
