@@ -134,11 +134,54 @@ __device__ __forceinline__ void flush_rows(const SigArgs& a, uint32_t u, const u
   __syncthreads();
 }
 
+// One pass over the register-resident row: functions [F, F + KP) of the
+// launch (those past Fn are repeats of its last function and are not
+// placed), their values placed into the key under construction, and each
+// table stored when its last function is placed.
+template <int KP, int W, bool MINMAX, typename Each>
+__device__ __forceinline__ void sig_pass(const SigArgs& a, uint32_t F, uint32_t F0, uint32_t Fn, uint32_t (&xs)[W],
+                                         Each each_pair, KeyBuilder& kb, uint64_t i, bool live, uint32_t* my,
+                                         uint32_t* srow) {
+  uint32_t f[KP], a2[KP], b2[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    f[k] = min(F + k, Fn - 1);
+    a2[k] = a.a2[f[k]];
+    b2[k] = a.b2[f[k]];
+  }
+  PairAcc<MINMAX> acc[KP / 2];
+#pragma unroll
+  for (int k = 0; k < KP / 2; ++k) acc[k].init();
+#pragma unroll
+  for (int w = 0; w < W; ++w) asm volatile("" : "+v"(xs[w]));
+#pragma clang loop unroll(full)
+  for (int w = 0; w < W; ++w) {
+#pragma unroll
+    for (int k = 0; k < KP / 2; ++k) acc[k].add(a2[2 * k], b2[2 * k], a2[2 * k + 1], b2[2 * k + 1], xs[w]);
+  }
+#pragma unroll
+  for (int k = 0; k < KP / 2; ++k) acc[k].finish(a2[2 * k], b2[2 * k], a2[2 * k + 1], b2[2 * k + 1], a.dim, each_pair);
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    if (F + k >= Fn) break;
+    const uint32_t u = (F + k - F0) / a.fpt;
+    const PairAcc<MINMAX>& c = acc[k / 2];
+    kb.put(a, f[k], (k & 1) ? c.mnB : c.mnA, i, u, live);
+    if (MINMAX) kb.put(a, f[k], (k & 1) ? c.mxB : c.mxA, i, u, live);
+    if ((F + k + 1 - F0) % a.fpt == 0) {
+      store_table(a, kb.key, i, u, live, my);
+      flush_rows(a, u, srow);
+      kb = KeyBuilder{0ull, 0u};
+    }
+  }
+}
+
 // CAP: most indices a row may hold (rows shorter than CAP are padded with
 // their first index, which leaves every min and max unchanged).  Rows are
 // fixed-length with an even length and 4-byte aligned (other layouts take
 // k_sig_long).  Each pass over the register-resident row evaluates eight
-// functions, so the 16-bit unpacking of an index pair is shared by eight.
+// functions (four in a short last pass), so the 16-bit unpacking of an index
+// pair is shared by eight.
 template <int CAP, bool MINMAX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 ? 3 : 1))) void k_sig(SigArgs a) {
   extern __shared__ uint32_t srow[];  // 256 rows of row_dw + 1 dwords (odd stride)
@@ -192,46 +235,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CAP <= 200 
       f(x0 | (x1 << 16));
     }
   };
-  // Functions of the launch's tables in order (table-major), kPass per pass:
-  // a table's key is complete after its last function's values are placed.
-  constexpr int kPass = 8;
+  // Functions of the launch's tables in order (table-major), eight per pass;
+  // a remainder of at most four takes a four-function pass, so a launch of
+  // 4 (mod 8) functions evaluates no repeats.  A table's key is complete
+  // after its last function's values are placed.
   const uint32_t F0 = a.table_begin * a.fpt, Fn = F0 + a.table_count * a.fpt;
   KeyBuilder kb{0ull, 0u};
-  for (uint32_t F = F0; F < Fn; F += kPass) {
-    uint32_t f[kPass], a2[kPass], b2[kPass];
-#pragma unroll
-    for (int k = 0; k < kPass; ++k) {
-      f[k] = min(F + k, Fn - 1);  // past the last function: a repeat, not placed
-      a2[k] = a.a2[f[k]];
-      b2[k] = a.b2[f[k]];
-    }
-    PairAcc<MINMAX> acc[kPass / 2];
-#pragma unroll
-    for (int k = 0; k < kPass / 2; ++k) acc[k].init();
-#pragma unroll
-    for (int w = 0; w < W; ++w) asm volatile("" : "+v"(xs[w]));
-#pragma clang loop unroll(full)
-    for (int w = 0; w < W; ++w) {
-#pragma unroll
-      for (int k = 0; k < kPass / 2; ++k) acc[k].add(a2[2 * k], b2[2 * k], a2[2 * k + 1], b2[2 * k + 1], xs[w]);
-    }
-#pragma unroll
-    for (int k = 0; k < kPass / 2; ++k)
-      acc[k].finish(a2[2 * k], b2[2 * k], a2[2 * k + 1], b2[2 * k + 1], a.dim, each_pair);
-#pragma unroll
-    for (int k = 0; k < kPass; ++k) {
-      if (F + k >= Fn) break;
-      const uint32_t u = (F + k - F0) / a.fpt;
-      const PairAcc<MINMAX>& c = acc[k / 2];
-      kb.put(a, f[k], (k & 1) ? c.mnB : c.mnA, i, u, live);
-      if (MINMAX) kb.put(a, f[k], (k & 1) ? c.mxB : c.mxA, i, u, live);
-      if ((F + k + 1 - F0) % a.fpt == 0) {
-        store_table(a, kb.key, i, u, live, my);
-        flush_rows(a, u, srow);
-        kb = KeyBuilder{0ull, 0u};
-      }
-    }
-  }
+  // (F + 4 < Fn, not Fn - F > 4: a pass over a remainder of five to seven
+  // functions leaves F past Fn)
+  uint32_t F = F0;
+  for (; F + 4 < Fn; F += 8) sig_pass<8, W, MINMAX>(a, F, F0, Fn, xs, each_pair, kb, i, live, my, srow);
+  if (F < Fn) sig_pass<4, W, MINMAX>(a, F, F0, Fn, xs, each_pair, kb, i, live, my, srow);
 }
 
 // Rows longer than the largest register-resident capacity: indices are read
