@@ -282,11 +282,17 @@ int fast_lsh_config_used(fast_lsh_ctx *ctx, fast_lsh_config *out);
  * station's chunk waits for the one before it) and at most max_batch.
  * A chunk's ticket is done as soon as its result is on the host; the batch's
  * chunks are then inserted into their stations (merging a full delta into
- * the history) before the next batch runs.  If an insertion fails (the
- * station's history is full), that chunk's result stands and every later
- * chunk of the station fails with the insertion's error.
+ * the history) before the next batch runs.  If an insertion fails (a device
+ * or allocation error), that chunk's result stands and every later chunk of
+ * the station fails with the insertion's error.
  * HBM admission: a station is admitted only if its tables, its share of the
- * shared history-merge buffer and its build buffers fit the budget.
+ * shared history-merge buffer and its build buffers fit the budget.  A chunk
+ * is admitted only if its rows fit the station's tables (history rows plus
+ * slack_rows, less the rows of the chunks already queued for the station):
+ * otherwise submit returns E_NOMEM and the station is unchanged, so no
+ * admitted chunk can fail its insertion.  With a budget, the first submit
+ * also checks that a full batch's workspace (max_batch chunks of max_chunk
+ * rows) fits beside the resident tables.
  * Chunk rows are DEVICE memory that must stay valid until the chunk's ticket
  * is done; results are returned in HOST arrays.  Entry points other than
  * submit/poll/take/now/info must not run concurrently with each other.
@@ -322,7 +328,8 @@ int fast_lsh_server_add_station(fast_lsh_server *server, const fast_lsh_fps *his
 /* Queue a chunk (device rows, 1..max_chunk of them) of `station`;
  * arrival_ns is the caller's arrival time on the server clock
  * (fast_lsh_server_now_ns) and is kept for latency accounting.  *ticket
- * receives the chunk's ticket.  Thread-safe, does not block. */
+ * receives the chunk's ticket.  Thread-safe, does not block.  E_NOMEM when
+ * the chunk's rows do not fit its station (see HBM admission above). */
 int fast_lsh_server_submit(fast_lsh_server *server, uint32_t station, const fast_lsh_fps *chunk,
                            uint64_t arrival_ns, uint64_t *ticket);
 /* FAST_LSH_OK with the chunk's counters (as fast_lsh_search defines them, for

@@ -485,6 +485,9 @@ struct fast_lsh_server {
   fast_lsh_filter flt{};
   fast_lsh_server_config cfg{};
   std::vector<Station> st;
+  // per station: rows held plus the rows of its chunks waiting or running
+  // (under mu); a chunk is admitted only while this stays within hcap
+  std::vector<uint64_t> reserved;
   uint64_t mphys = 0;          // rows per table of the shared history-merge buffer
   uint64_t max_hcap = 0;       // largest history stride of any station (mphys never drops below it)
   uint64_t* mkey = nullptr;
@@ -526,6 +529,18 @@ static uint64_t resident_bytes(const fast_lsh_server* sv) {
   uint64_t r = t * sv->mphys * 12;
   for (const Station& S : sv->st) r += t * (S.hphys + 2 * S.dcap) * 12;
   return r;
+}
+
+// Workspace of a full batch (max_batch chunks of max_chunk rows): the
+// chunks' keys, sorted keys and ids per table, the output records at their
+// initial size (16 per row; a batch with more matches grows them), and the
+// scratch of the largest history merge.
+static uint64_t batch_bytes(const fast_lsh_server* sv) {
+  const uint64_t t = sv->h.num_tables;
+  const uint64_t Q = (uint64_t)sv->cfg.max_batch * sv->cfg.max_chunk;
+  uint64_t merge = 0;
+  for (const Station& S : sv->st) merge = std::max(merge, merge_scratch(S.hcap, S.dcap, (uint32_t)t) * 4);
+  return 20 * t * Q + 10 * std::max<uint64_t>(1u << 16, 16 * Q) + merge;
 }
 
 static int alloc_dev(void** p, uint64_t bytes) {
@@ -821,6 +836,8 @@ static void worker_main(fast_lsh_server* sv) {
     for (auto& b : batch) {
       b.second->state = b.second->err == FAST_LSH_OK ? kDone : kFailed;
       b.second->done_ns = done;
+      // a failed chunk is not inserted: its rows leave the reservation
+      if (b.second->err != FAST_LSH_OK) sv->reserved[b.second->station] -= b.second->chunk.n;
     }
     ++sv->batches;
     sv->chunks += batch.size();
@@ -1045,6 +1062,7 @@ int fast_lsh_server_add_station(fast_lsh_server* sv, const fast_lsh_fps* hist, u
   *station = (uint32_t)sv->st.size();
   sv->max_hcap = std::max(sv->max_hcap, S.hcap);
   sv->st.push_back(S);
+  sv->reserved.push_back(S.n);
   return FAST_LSH_OK;
 }
 
@@ -1057,6 +1075,20 @@ int fast_lsh_server_submit(fast_lsh_server* sv, uint32_t station, const fast_lsh
                    sv->cfg.max_chunk);
   std::lock_guard<std::mutex> lk(sv->mu);
   if (station >= sv->st.size()) return fl_fail(FAST_LSH_E_INVALID, "no station %u", station);
+  // admission by footprint: the chunk's rows must fit the tables its station
+  // holds once every chunk already queued for it is inserted, and (with a
+  // budget) a full batch's workspace must fit beside the resident tables
+  if (sv->reserved[station] + chunk->n > sv->st[station].hcap)
+    return fl_fail(FAST_LSH_E_NOMEM, "station %u has room for %llu more rows, the chunk has %llu", station,
+                   (unsigned long long)(sv->st[station].hcap - sv->reserved[station]),
+                   (unsigned long long)chunk->n);
+  if (!sv->started && sv->cfg.hbm_budget) {
+    const uint64_t need = resident_bytes(sv) + batch_bytes(sv);
+    if (need > sv->cfg.hbm_budget)
+      return fl_fail(FAST_LSH_E_NOMEM, "resident tables and a full batch need %llu bytes of the %llu-byte budget",
+                     (unsigned long long)need, (unsigned long long)sv->cfg.hbm_budget);
+  }
+  sv->reserved[station] += chunk->n;
   const uint64_t id = sv->next_ticket++;
   Ticket& T = sv->tickets[id];
   T.station = station;

@@ -162,3 +162,99 @@ def test_station_5y_bounded_full_size():
     say(f"[fullsize] bounded search {time.time() - t0:.2f}s")
     _check_sampled(dev, labels, out, spec.n, a, b, 2)
     ctx.close()
+
+
+def test_serving_180d_full_size():
+    """The serving workload at its full size: 8 stations with 180-day
+    histories (15,552,000 fingerprints each, the recipe bench.py serves)
+    resident, and 12 chunks of 3,600 fingerprints per station offered at
+    once, so that batches mix stations.  Every chunk's pairs have their later
+    member in the chunk, lie at or above the lag and the threshold and come
+    sorted; sampled reported pairs carry exactly the oracle's votes; and
+    every pair of copies of a planted source, and sampled short-lag pairs,
+    whose later member lies in a chunk is reported exactly when the oracle's
+    votes reach the threshold."""
+    S, CH, NCH = 8, synth.CHUNK, 12
+    n_hist = synth.STATION_180D
+    n = n_hist + NCH * CH
+    a, b = fl.make_hash(204, fl.n_funcs(T, R, SCHEME))
+    sv = fl.Server(DIM, T, R, SCHEME, a, b, L, V, max_batch=8, max_chunk=CH, delta_rows=262144,
+                   slack_rows=NCH * CH)
+    host, labs, streams = [], [], []
+    for s in range(S):
+        spec = synth.Spec(n=n, seed=1040 + s, markov_keep=140, n_sources=4000, rep_min=3, rep_max=40,
+                          jac_lo_milli=400, jac_hi_milli=900, chain_len=1_000_000)
+        rows = np.empty((n, spec.nnz), dtype=np.uint16)
+        _, lab = synth.generate(spec, 0, n, labels=True, out=rows)
+        hist = torch.from_numpy(rows[:n_hist].view(np.int16)).cuda()
+        assert sv.add_station(hist) == s
+        del hist
+        torch.cuda.empty_cache()
+        streams.append(torch.from_numpy(rows[n_hist:].view(np.int16)).cuda())
+        host.append(rows)
+        labs.append(lab)
+        say(f"[serve-full] station {s}: {n_hist} rows resident")
+    tickets = {(s, c): sv.submit(s, streams[s][c * CH:(c + 1) * CH]) for c in range(NCH) for s in range(S)}
+    got = {k: sv.take(tk) for k, tk in tickets.items()}
+    info = sv.info()
+    sv.close()
+    say(f"[serve-full] {len(got)} chunks done, server {info}")
+    assert info["largest_batch"] > 1
+    rng = np.random.default_rng(7)
+    total_want = 0
+    for s in range(S):
+        parts = []
+        for c in range(NCH):
+            oi, oj, ov = (x.astype(np.int64) for x in got[(s, c)])
+            lo = n_hist + c * CH
+            assert ((oj >= lo) & (oj < lo + CH)).all() and (oi < oj).all() and (oj - oi >= L).all()
+            assert (ov >= V).all() and (ov <= T).all()
+            key = (oi << 32) | oj
+            assert (key[1:] > key[:-1]).all()
+            parts.append((oi, oj, ov))
+        gi = np.concatenate([p[0] for p in parts])
+        gj = np.concatenate([p[1] for p in parts])
+        gv = np.concatenate([p[2] for p in parts])
+        key = (gi << 32) | gj
+        o = np.argsort(key)
+        key, gv = key[o], gv[o]
+        rows, lab = host[s], labs[s]
+        # reported pairs: exact votes
+        k = rng.choice(len(key), min(400, len(key)), replace=False)
+        votes = _host_votes(rows, a, b, key[k] >> 32, key[k] & 0xFFFFFFFF)
+        assert np.array_equal(votes, gv[k])
+        # completeness: every copy pair with its later copy in a chunk, and
+        # short-lag pairs ending in the chunks
+        planted = np.flatnonzero(lab >= 0)
+        order = planted[np.argsort(lab[planted], kind="stable")]
+        lab_sorted = lab[order]
+        pi, pj = [], []
+        for j in planted[planted >= n_hist]:
+            members = order[np.searchsorted(lab_sorted, lab[j]):np.searchsorted(lab_sorted, lab[j], side="right")]
+            for i in members[(members < j) & (j - members >= L)]:
+                pi.append(i)
+                pj.append(j)
+        jj = rng.integers(n_hist, n, 500)
+        ll = rng.integers(L, 64, 500)
+        pi = np.concatenate([np.array(pi, dtype=np.int64), jj - ll])
+        pj = np.concatenate([np.array(pj, dtype=np.int64), jj])
+        votes = _host_votes(rows, a, b, pi, pj)
+        want = votes >= V
+        q = (pi << 32) | pj
+        pos = np.minimum(np.searchsorted(key, q), len(key) - 1)
+        found = key[pos] == q
+        say(f"[serve-full] station {s}: {len(key)} pairs in its chunks; completeness sample {len(q)} pairs, "
+            f"{int(want.sum())} at or above the threshold")
+        assert np.array_equal(found, want)
+        assert np.array_equal(gv[pos][found], votes[found])
+        total_want += int(want.sum())
+    assert total_want > 100
+
+
+def _host_votes(rows, a, b, pi, pj):
+    """Oracle votes of pairs (pi, pj) of host rows."""
+    pi, pj = np.asarray(pi, dtype=np.int64), np.asarray(pj, dtype=np.int64)
+    ids = np.unique(np.concatenate([pi, pj]))
+    keys = oracle.signatures(np.ascontiguousarray(rows[ids]), DIM, T, R, oracle.MINMAX, a, b)
+    x, y = np.searchsorted(ids, pi), np.searchsorted(ids, pj)
+    return (keys[:, x] == keys[:, y]).sum(axis=0).astype(np.int64)

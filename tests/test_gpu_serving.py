@@ -216,35 +216,45 @@ def test_serving_admission_and_arguments():
     sv.close()
 
 
-def test_serving_full_history_fails_later_chunks():
-    # history 6,000 rows with room for 4,000 more, delta 4,000, chunks of
-    # 2,000: the second history merge (before chunk 5's insertion) would
-    # exceed the room, so chunk 5 keeps its result and chunk 6 fails.
-    sizes = [2000] * 6
+def test_serving_admits_chunks_by_station_room():
+    # history 6,000 rows with room for 5,000 more, delta 4,000: chunks
+    # already queued count against the room, a chunk that does not fit is
+    # refused at submit (E_NOMEM) and leaves the station as it was, a chunk
+    # that fails (a bad row) gives its rows back, and the admitted chunks'
+    # results are exact (the third one's insertion merges the full delta
+    # into the history)
     n_hist = 6000
-    rows = synth.generate(synth.station(n=n_hist + sum(sizes), seed=210))
-    hist, chunks = rows[:n_hist], _chunks(rows, n_hist, sizes)
+    rows = synth.generate(synth.station(n=n_hist + 7000, seed=210))
     a, b = fl.make_hash(211, 200)
-    sv = fl.Server(4096, 100, 4, fl.MINMAX, a, b, 5, 4, max_chunk=2000, delta_rows=4000, slack_rows=4000)
-    st = sv.add_station(fl.to_device_rows(hist))
-    dev = [fl.to_device_rows(x) for x in chunks]
-    got = []
-    for c in range(5):
-        tk = sv.submit(st, dev[c])
-        got.append(sv.take(tk))
-    t6 = sv.submit(st, dev[5])
+    sv = fl.Server(4096, 100, 4, fl.MINMAX, a, b, 5, 4, max_chunk=2000, delta_rows=4000, slack_rows=5000)
+    st = sv.add_station(fl.to_device_rows(rows[:n_hist]))
+    dev = lambda x: fl.to_device_rows(np.ascontiguousarray(x))  # noqa: E731
+    t0 = sv.submit(st, dev(rows[6000:8000]))
+    t1 = sv.submit(st, dev(rows[8000:10000]))
+    with pytest.raises(fl.FastLshError) as e:  # 10,000 + 2,000 rows > 11,000
+        sv.submit(st, dev(rows[10000:12000]))
+    assert e.value.code == 2
+    bad = rows[10000:11000].copy()
+    bad[17, -1] = 5000  # an index >= dim: the chunk fails on the device
+    tb = sv.submit(st, dev(bad))
+    with pytest.raises(fl.FastLshError) as e:  # the bad chunk still holds its rows
+        sv.submit(st, dev(rows[11000:11001]))
+    assert e.value.code == 2
     with pytest.raises(fl.FastLshError) as e:
-        sv.poll(t6, wait=True)
+        sv.poll(tb, wait=True)
+    assert e.value.code == 1
+    t2 = sv.submit(st, dev(rows[10000:11000]))
+    got = [sv.take(tk) for tk in (t0, t1, t2)]
+    with pytest.raises(fl.FastLshError) as e:  # the station is full now
+        sv.submit(st, dev(rows[11000:11001]))
     assert e.value.code == 2
     sv.close()
-    # chunks 1-5 are exact: the oracle's pairs of the first 16,000 rows whose
-    # later member is in a chunk
-    ei, ej, ev, _ = _expected(rows[:n_hist + 10_000], n_hist, 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
+    ei, ej, ev, _ = _expected(rows[:11000], n_hist, 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
     gi = np.concatenate([g[0] for g in got])
     gj = np.concatenate([g[1] for g in got])
     gv = np.concatenate([g[2] for g in got])
     o = np.lexsort((gj, gi))
-    say(f"[serve] full history: {len(gi)} pairs (oracle {len(ei)})")
+    say(f"[serve] admission by room: {len(gi)} pairs (oracle {len(ei)})")
     assert np.array_equal(gi[o], ei) and np.array_equal(gj[o], ej) and np.array_equal(gv[o], ev)
 
 
