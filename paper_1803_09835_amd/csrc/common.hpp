@@ -239,7 +239,12 @@ __device__ __forceinline__ uint32_t station_of(const uint64_t* base, uint32_t nb
 
 // Buckets of at most kSmallBucket members are handled by the wave-per-chunk
 // pair kernel (their members staged in LDS); larger ones by the tile kernel.
+// The pair forms that compare each pair against a row held in registers
+// (the FAST test on 10- or 17-dword rows) take buckets of up to 64 members
+// there; the forms with longer rows or full counts take up to 32, since the
+// wave kernel's LDS span, and with it its residency, grows with the limit.
 constexpr uint32_t kSmallBucket = 64;
+constexpr uint32_t kSmallBucketGeneral = 32;
 
 
 }  // namespace fl

@@ -223,43 +223,42 @@ struct RowReg {
   }
 };
 
-// One in-bucket pair of table u: i < j, `rx` the row of i (`rl` in LDS),
-// `ry` the row of j (in LDS).
+// One in-bucket pair of table u: i < j, `rl` and `ry` the rows of i and j
+// in LDS; `rx` holds one of the two rows in registers and `ro` is the other
+// one (in LDS).
 // FAST (need == 2, no distinct count, rx from load_masked): the group test
 // is "some other table of the group shares a bucket", decided without
 // counting; otherwise the equal fields are counted.
 template <int RSW, bool FAST>
 __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
                                            const RowReg<RSW>& rx, const uint32_t* rl, const uint32_t* ry,
-                                           uint32_t rsw, uint32_t pad, PairTally& tl) {
+                                           const uint32_t* ro, uint32_t rsw, uint32_t pad, PairTally& tl) {
   // FAST: the right row is read before the id checks, so that its loads and
   // the partner id's share one LDS round trip
   uint32_t rv[RowReg<RSW>::kW];
   if (FAST) {
-    RowReg<RSW>::fetch(ry, rv);
+    RowReg<RSW>::fetch(ro, rv);
 #pragma unroll
     for (int k = 0; k < RowReg<RSW>::kW; ++k) asm volatile("" : "+v"(rv[k]));  // keep the loads above the branch
   }
   if (i == kDead || j == kDead || j - i < a.min_lag) return;
-  if (!FAST && a.part_mode) {
-    // partitioned search: every mode needs the pair's first shared table
-    const bool lower = rx.eq_below(ry, rsw, u) != 0 && lower_in_group(a, u, i, j, rl, ry);
+  if (a.part_mode == 3 && (i < a.plo || i >= a.phi)) return;  // pairs of this partition only
+  if (!FAST && (a.part_mode == 1 || a.part_mode == 2)) {
+    // partitioned search: counts and exclusions at the pair's first shared
+    // table only, tested after the cheaper checks that can skip the pair
     if (a.part_mode == 1) {
-      if (!lower) {
-        if (i >= a.plo && i < a.phi) atomicAdd(a.cand + i, 1u);
-        if (j >= a.plo && j < a.phi) atomicAdd(a.cand + j, 1u);
-      }
+      const bool ii = i >= a.plo && i < a.phi, jj = j >= a.plo && j < a.phi;
+      if (!(ii || jj)) return;
+      if (rx.eq_below(ro, rsw, u) != 0 && lower_in_group(a, u, i, j, rl, ry)) return;
+      if (ii) atomicAdd(a.cand + i, 1u);
+      if (jj) atomicAdd(a.cand + j, 1u);
       return;
     }
-    if (a.part_mode == 2) {
-      if (!lower) {
-        const bool fi = a.fp[i] != 0, fj = a.fp[j] != 0;
-        if (fi && !fj) a.ex_next[j] = 1;
-        if (fj && !fi) a.ex_next[i] = 1;
-      }
-      return;
-    }
-    if (i < a.plo || i >= a.phi) return;  // mode 3: pairs of this partition only
+    const bool fi = a.fp[i] != 0, fj = a.fp[j] != 0;
+    if (fi == fj) return;
+    if (rx.eq_below(ro, rsw, u) != 0 && lower_in_group(a, u, i, j, rl, ry)) return;
+    a.ex_next[fi ? j : i] = 1;
+    return;
   }
   if (a.nstation > 1 && (i < tl.lo || i >= tl.hi)) {
     const uint32_t st = station_of(a.station_base, a.nstation, i);
@@ -278,9 +277,9 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
     if (rx.any_equal(rv) && !lower_in_group(a, u, i, j, rl, ry)) exact_and_report(a, u, i, j);
     return;
   }
-  const uint32_t eq = rx.eq(ry, rsw);
+  const uint32_t eq = rx.eq(ro, rsw);
   if (a.want_distinct) {  // one group: "lower" is "a table below u shares"
-    const bool lower = rx.eq_below(ry, rsw, u) != 0 && lower_in_group(a, u, i, j, rl, ry);
+    const bool lower = rx.eq_below(ro, rsw, u) != 0 && lower_in_group(a, u, i, j, rl, ry);
     if (!lower) {
       ++tl.nd;
       if (eq - pad >= a.need) exact_and_report(a, u, i, j);
@@ -394,12 +393,13 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
 // the LDS hand-offs of a single wave.
 template <int RSW, bool FAST>
 __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl,
-                                                   uint32_t nchunk) {
-  constexpr uint32_t kSpan = 64 + kSmallBucket - 1;  // heads in 64 positions, members up to kSmallBucket
+                                                   uint32_t nchunk, uint32_t span) {
+  // span = 64 + small_max - 1: heads in 64 positions, members up to small_max
+  // (at most kSmallBucket) after them
   extern __shared__ uint32_t smem[];
-  uint32_t* lrows = smem;                   // kSpan * rswl
-  uint32_t* lids = lrows + kSpan * rswl;    // kSpan
-  uint32_t* hinfo = lids + kSpan;           // 64: head position | size << 16
+  uint32_t* lrows = smem;                   // span * rswl
+  uint32_t* lids = lrows + span * rswl;     // span
+  uint32_t* hinfo = lids + span;            // 64: head position | size << 16
   uint32_t* bpof = hinfo + 64;              // 65: pair prefix
   const uint32_t lane = threadIdx.x;
   const uint32_t rsw = RSW > 0 ? (uint32_t)RSW : a.row_dw;
@@ -416,14 +416,14 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
   // makes the first pair look its station up.
   PairTally tl{0ull, 0ull, 0u, 0u, a.nstation > 1 ? 0u : 0xFFFFFFFFu};
 
-  // The chunk's marks and ids (64 + kSpan - 64 positions, clipped at n).
+  // The chunk's marks and ids (span positions, clipped at n).
   uint32_t nsize = 0, nid0 = 0, nid1 = 0;
   auto fetch = [&](uint32_t c) {
     const uint64_t p0 = (uint64_t)c * 64;
     const uint64_t left = a.n - p0;
     nsize = lane < left ? marks[p0 + lane] : 0u;
     nid0 = lane < left ? order[p0 + lane] : 0u;
-    nid1 = (64 + lane < left && lane < kSpan - 64) ? order[p0 + 64 + lane] : 0u;
+    nid1 = (64 + lane < left && lane < span - 64) ? order[p0 + 64 + lane] : 0u;
   };
   uint32_t c = blockIdx.x;
   if (c < nchunk) fetch(c);
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
     if (heads == 0) continue;
     __syncthreads();  // the previous chunk's LDS reads are complete
     lids[lane] = id0;
-    if (lane < kSpan - 64) lids[64 + lane] = id1;
+    if (lane < span - 64) lids[64 + lane] = id1;
     const uint64_t lt = __lanemask_lt();
     const uint32_t hidx = __popcll(heads & lt);
     const uint32_t nh = __popcll(heads);
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
       const uint64_t upto = q >= 63 ? heads : (heads & ((2ull << q) - 1));
       const uint32_t h = upto ? 63 - (uint32_t)__clzll(upto) : 0u;
       const uint32_t hs = __shfl(size, h, 64);  // every lane active here
-      mem[r] = upto && q < kSpan && q < h + hs;
+      mem[r] = upto && q < span && q < h + hs;
       mid[r] = mem[r] ? lids[q] : 0u;
     }
     if (RSW > 0) {  // both rows' loads (each only where that member exists) before either store
@@ -498,8 +498,8 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
       RowReg<RSW> rx;
       if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
       for (; p < pend; ++p) {
-        visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, lrows + (base + x) * rswl, lrows + (base + y) * rswl,
-                                   rsw, pad, tl);
+        const uint32_t* ry = lrows + (base + y) * rswl;
+        visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, lrows + (base + x) * rswl, ry, ry, rsw, pad, tl);
         if (++y == m) {
           if (++x == m - 1) {
             if (++b >= nh) break;
@@ -629,11 +629,38 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       if (FAST) rx.load_masked(rowsA + xs * rswl, own, valid); else rx.load(rowsA + xs * rswl, rsw);
       const uint32_t idx = idsA[xs];
       for (uint32_t y = y0; y < nbm; y += 2)
-        if (live) visit_pair<RSW, FAST>(a, u, idx, idsB[y], rx, rowsA + xs * rswl, rowsB + y * rswl, rsw, pad, tl);
+        if (live)
+          visit_pair<RSW, FAST>(a, u, idx, idsB[y], rx, rowsA + xs * rswl, rowsB + y * rswl, rowsB + y * rswl, rsw,
+                                pad, tl);
+    }
+  } else if (diag && tb_size == kPT / 2) {
+    // Diagonal tiles: the pairs {x, (x + k) mod na} for k = 1 .. na / 2 are
+    // each unordered pair once (for even na the round k = na / 2 meets
+    // every pair twice and is taken from its smaller position only).
+    // Thread t holds row x = t mod tb_size in registers and takes the rounds
+    // of parity t / tb_size; in a round the wave's lanes read consecutive
+    // rows (conflict-free at the odd row stride).
+    const uint32_t x = threadIdx.x % tb_size, k0 = 1 + threadIdx.x / tb_size;
+    if (__ballot(x < na)) {
+      const bool live = x < na;
+      const uint32_t xs = live ? x : 0u;
+      RowReg<RSW> rx;
+      if (FAST) rx.load_masked(rowsA + xs * rswl, own, valid); else rx.load(rowsA + xs * rswl, rsw);
+      const uint32_t idx = idsA[xs];
+      const uint32_t* rowx = rowsA + xs * rswl;
+      for (uint32_t k = k0; 2 * k <= na; k += 2) {
+        if (!live || (2 * k == na && x >= k)) continue;
+        const uint32_t y = x + k < na ? x + k : x + k - na;
+        const uint32_t* rowy = rowsA + y * rswl;
+        const uint32_t idy = idsA[y];
+        const bool fw = y > x;  // selects, not branches: one inlined visit per lane
+        visit_pair<RSW, FAST>(a, u, fw ? idx : idy, fw ? idy : idx, rx, fw ? rowx : rowy, fw ? rowy : rowx, rowy,
+                              rsw, pad, tl);
+      }
     }
   } else {
-    // Diagonal and partial tiles: every thread walks a contiguous range of
-    // the tile's pairs.
+    // Partial tiles: every thread walks a contiguous range of the tile's
+    // pairs.
     const uint32_t P = diag ? na * (na - 1) / 2 : na * nbm;
     const uint32_t per = (P + kPT - 1) / kPT;
     uint32_t p = threadIdx.x * per;
@@ -649,7 +676,8 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       RowReg<RSW> rx;
       if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
       for (; p < pend; ++p) {
-        visit_pair<RSW, FAST>(a, u, idsA[x], idsB[y], rx, rowsA + x * rswl, rowsB + y * rswl, rsw, pad, tl);
+        visit_pair<RSW, FAST>(a, u, idsA[x], idsB[y], rx, rowsA + x * rswl, rowsB + y * rswl, rowsB + y * rswl, rsw,
+                              pad, tl);
         if (++y == nbm) {
           ++x;
           y = diag ? x + 1 : 0;
@@ -803,29 +831,39 @@ static unsigned grid_for(uint64_t count) {
 // The group test reduces to "another table shares a bucket" when a pair
 // needs two shared tables in its group and no distinct count is wanted (the
 // partitioned passes always take the counting form).
-static bool fast_test(const PairArgs& a) { return a.need == 2 && !a.want_distinct && a.part_mode == 0; }
+// The reporting pass of a partition (mode 3) is the plain search restricted
+// to a range of i, so it takes the same form.
+static bool fast_test(const PairArgs& a) {
+  return a.need == 2 && !a.want_distinct && (a.part_mode == 0 || a.part_mode == 3);
+}
 
 // Persistent: one resident round of one-wave workgroups (as many as a CU
 // holds by LDS, at most kPairWavesPerCU) spread over the segments.
-void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, hipStream_t s) {
+uint32_t pair_small_max(uint32_t need, bool distinct, uint32_t parts, uint32_t row_dw) {
+  return (need == 2 && !distinct && parts == 0 && (row_dw == 10 || row_dw == 17)) ? kSmallBucket
+                                                                                  : kSmallBucketGeneral;
+}
+
+void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, uint32_t small_max,
+                       hipStream_t s) {
   if (a.n == 0 || S == 0) return;
-  constexpr uint32_t kSpan = 64 + kSmallBucket - 1;
-  const size_t smem = (size_t)(kSpan * rswl + kSpan + 64 + 65) * 4;
+  const uint32_t span = 64 + small_max - 1;
+  const size_t smem = (size_t)(span * rswl + span + 64 + 65) * 4;
   const uint32_t nchunk = (uint32_t)((a.n + 63) / 64);
   const uint32_t per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(kPairWavesPerCU, (160u << 10) / smem));
   const uint32_t per_seg = std::max<uint32_t>(1u, std::min<uint32_t>(nchunk, per_cu * device_cus() / S));
   const dim3 grid(per_seg, S);
   switch (a.row_dw) {
     case 10:
-      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<10, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
-      else hipLaunchKernelGGL((k_pairs_wave<10, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
+      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<10, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
+      else hipLaunchKernelGGL((k_pairs_wave<10, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
       break;
     case 17:
-      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<17, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
-      else hipLaunchKernelGGL((k_pairs_wave<17, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
+      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<17, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
+      else hipLaunchKernelGGL((k_pairs_wave<17, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
       break;
     default:
-      hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk);
+      hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
       break;
   }
 }

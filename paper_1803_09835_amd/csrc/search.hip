@@ -251,7 +251,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
   j.pa.order = j.sorted_v;
   if (j.parts) return FAST_LSH_OK;  // the partitioned search launches its own pair passes
   pb(FAST_LSH_STAGE_PAIRS);
-  launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, s);
+  launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, j.ba.small_max, s);
   pe();
   LAUNCHCK();
   return FAST_LSH_OK;
@@ -421,7 +421,7 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
         PairArgs m1 = pa;
         m1.part_mode = 1;
         prof_begin(c, FAST_LSH_STAGE_PAIRS);
-        launch_pairs_wave(m1, j.marks, j.t, j.rswl, s);
+        launch_pairs_wave(m1, j.marks, j.t, j.rswl, j.ba.small_max, s);
         prof_end(c);
         LAUNCHCK();
         RC(run_big_pairs(c, j, big_count, m1, dummy));
@@ -433,7 +433,7 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
           PairArgs m2 = pa;
           m2.part_mode = 2;
           prof_begin(c, FAST_LSH_STAGE_PAIRS);
-          launch_pairs_wave(m2, j.marks, j.t, j.rswl, s);
+          launch_pairs_wave(m2, j.marks, j.t, j.rswl, j.ba.small_max, s);
           prof_end(c);
           LAUNCHCK();
           RC(run_big_pairs(c, j, big_count, m2, dummy));
@@ -444,7 +444,7 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
       PairArgs m3 = pa;
       m3.part_mode = 3;
       prof_begin(c, FAST_LSH_STAGE_PAIRS);
-      launch_pairs_wave(m3, j.marks, j.t, j.rswl, s);
+      launch_pairs_wave(m3, j.marks, j.t, j.rswl, j.ba.small_max, s);
       prof_end(c);
       LAUNCHCK();
       RC(run_big_pairs(c, j, big_count, m3, j.work));
@@ -542,7 +542,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   RC(ws<uint64_t>(c, "station_base", 2 * S + 1, &j.sbase));
   // Buckets of at most smax members are marked in place and handled by the
   // wave-per-chunk pair kernel; larger ones go to the tiled kernel.
-  const uint32_t smax = kSmallBucket;
+  const uint32_t smax = pair_small_max(j.pl.need, distinct, parts, j.pl.row_dw);
   const uint64_t cap_big = tn / (smax + 1) + 1 + bucket_desc_slack(tn / (smax + 1) + 1, t);
   const uint64_t cap_bin = tn / 129 + t + 1;  // oversized bins and mixed bins above 128 elements
   RC(ws<uint4>(c, "bdesc", cap_big, &j.bdesc));
@@ -686,7 +686,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
       fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * S * kSpread * sizeof(unsigned long long), 0, s);
       fill_u32(&j.ctrl->out_count, 1, 0, s);
       prof_begin(c, FAST_LSH_STAGE_PAIRS);
-      launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, s);
+      launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, j.ba.small_max, s);
       prof_end(c);
       LAUNCHCK();
     }
@@ -771,7 +771,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   const uint32_t nt_max = radix_tiles(N, kRadixTileVariants - 1);
   RC(ws<uint32_t>(c, "hist", (uint64_t)256 * nt_max * TGm, &j.hist));
   RC(ws<uint32_t>(c, "sums", scan_sums_elems((uint64_t)256 * nt_max, TGm), &j.sums));
-  const uint32_t smax = kSmallBucket;
+  const uint32_t smax = pair_small_max(j.pl.need, distinct, 0, j.pl.row_dw);
   const uint64_t cap_big = gn / (smax + 1) + 1 + bucket_desc_slack(gn / (smax + 1) + 1, TGm);
   const uint64_t cap_bin = gn / 129 + TGm + 1;
   RC(ws<uint4>(c, "bdesc", cap_big, &j.bdesc));
@@ -909,7 +909,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
       j.pa.order = j.sorted_v;
       j.pa.table_offset = tb;
       prof_begin(c, FAST_LSH_STAGE_PAIRS);
-      launch_pairs_wave(j.pa, j.marks, tc, j.rswl, s);
+      launch_pairs_wave(j.pa, j.marks, tc, j.rswl, j.ba.small_max, s);
       prof_end(c);
       LAUNCHCK();
       RC(d2h(c, &hc, j.ctrl));
