@@ -20,10 +20,19 @@ streams at 40 chunks/s) and adds its p50/p99 chunk latency and sustained
 chunk rate to the line, next to the time a plain search of one station's
 history plus one chunk takes on the same GPU.
 
-Other workloads: --workload station (90 days, 7,776,000 fingerprints, tables
-all at once), bounded (the 5-year search alone), serving (the streaming
-workload alone), batched (12 stations in one search against 12 sequential
-searches).  Prints one JSON line.
+Other workloads (--workload):
+  station       90 days, 7,776,000 fingerprints, tables all at once;
+  bounded       the 5-year search alone;
+  serving       the streaming workload alone;
+  batched       12 stations in one search against 12 sequential searches;
+  alignment     three channels of the 90-day station searched, then the
+                channel merge and the station clusters;
+  query         1,000 queries hashed against the 90-day station (query-only
+                hashing) against the plain search of both;
+  partitioned   the 90-day station in three 30-day partitions with the
+                dynamic, per-partition occurrence filter;
+  fingerprints  fingerprint extraction from 90 days of 100 Hz waveform.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -76,16 +85,18 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def sig_traffic(n):
-    """HBM bytes per signature launch from the committed counter figures, or
-    None when they were taken for another size or on different kernel code."""
+def kernel_traffic(name, n):
+    """HBM bytes per launch of a kernel from the committed counter figures
+    (profiles/<name>_traffic.txt), or None when they were taken for another
+    size or on different kernel code (the file holds the SHA-256 of the
+    sources it lists)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_sig_station90d_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
-    src = b"".join(open(os.path.join(ROOT, "paper_1803_09835_amd", "csrc", f), "rb").read()
-                   for f in ("sig.hip", "common.hpp"))
+    files = kv.get("sources", "sig.hip,common.hpp").split(",")
+    src = b"".join(open(os.path.join(ROOT, "paper_1803_09835_amd", "csrc", f), "rb").read() for f in files)
     if int(kv.get("n", -1)) != n or kv.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return int(kv["fetch_bytes"]) + int(kv["write_bytes"])
@@ -280,12 +291,7 @@ def run_station(args):
     t1 = time.perf_counter()
     prof = ctx.profile_read()
     work = ctx.last_work()
-    if args.calib_copy_mib:
-        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calib_copy(args)
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     st = out[3]
     stage_ms, stage_launch = stage_table(prof, args.steps)
@@ -294,7 +300,7 @@ def run_station(args):
                        "k_sig<200,minmax>")
     if dom == "signatures":
         roof = dict(sig)
-        traffic = sig_traffic(N)
+        traffic = kernel_traffic("k_sig_station90d", N)
         roof["traffic"] = traffic
         roof["traffic_unit"] = "bytes per launch (HBM, counter runs in profiles/)"
     else:
@@ -322,6 +328,20 @@ def run_station(args):
                                         occ_den, args, "the same workload")
     ctx.close()
     return line
+
+
+def calib_copy(args):
+    """A device-to-device copy of --calib-copy-mib MiB after the timed steps:
+    the reference dispatch whose HBM counters calibrate FETCH_SIZE and
+    WRITE_SIZE."""
+    if not args.calib_copy_mib:
+        return
+    import torch
+    src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def upload_generated(spec, lo=0, hi=None, chunk=16_000_000):
@@ -380,12 +400,15 @@ def run_bounded(args):
     ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     prof = ctx.profile_read()
     work = ctx.last_work()
+    calib_copy(args)
     stage_ms, stage_launch = stage_table(prof, args.steps)
     st = out[3]
     dom = max(stage_ms, key=stage_ms.get)
     sig = sig_roofline(N, fl.n_funcs(t, r, scheme), scheme, stage_ms["signatures"], stage_launch["signatures"],
                        "k_sig<200,minmax> (each table once)")
     tile = tile_roofline(work, st, stage_ms["big_pairs"], stage_launch["big_pairs"])
+    tile["traffic"] = kernel_traffic("k_pairs_tile_station5y", N)
+    tile["traffic_unit"] = "bytes per launch (HBM, counter runs in profiles/)"
     roof = tile if dom == "big_pairs" else (sig if dom == "signatures" else
                                              {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
                                               "unit": "GB/s", "frac": None, "traffic": None})
