@@ -246,16 +246,28 @@ int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, ui
  *                 share every bit, so any choice gives the same buckets,
  *                 coarser bins leave more keys for the bucket kernel to
  *                 separate); 0: the automatic rule (bins of the largest
- *                 station averaging at most about 4 fingerprints). */
+ *                 station averaging at most about 4 fingerprints);
+ *   keep_groups   bounded search: the most table groups whose grouping
+ *                 (bucket-ordered ids, small-bucket marks, large-bucket
+ *                 descriptors: 5 bytes per fingerprint and table, plus the
+ *                 descriptors) pass 1 keeps for pass 2, which then runs the
+ *                 pair kernels on them instead of sorting and segmenting
+ *                 those groups again.  FAST_LSH_KEEP_AUTO: as many as the
+ *                 free HBM (less a margin of 4 GiB and 2 %) and the
+ *                 context's budget hold; 0: none.  fast_lsh_config_used
+ *                 reports the number the last bounded search kept. */
+#define FAST_LSH_KEEP_AUTO 0xFFFFFFFFu
 typedef struct {
   uint32_t radix_tile;
   uint32_t bucket_chunk;
   uint32_t autotune;
   uint32_t bin_bits;
+  uint32_t keep_groups;
 } fast_lsh_config;
 
 /* Set the launch shapes of later searches (defaults: 16384, 512, no
- * autotune).  E_INVALID for a value outside the lists above. */
+ * autotune, automatic bin bits, FAST_LSH_KEEP_AUTO).  E_INVALID for a value
+ * outside the lists above. */
 int fast_lsh_configure(fast_lsh_ctx *ctx, const fast_lsh_config *config);
 
 /* The launch shapes the last search used (after autotuning, its choice). */

@@ -247,6 +247,7 @@ int fast_lsh_ctx_create(int device, void* hip_stream, uint64_t hbm_budget, fast_
   c->config.bucket_chunk = 512;
   c->config.autotune = 0;
   c->config.bin_bits = 0;
+  c->config.keep_groups = FAST_LSH_KEEP_AUTO;
   *out = c;
   g_err.clear();
   return FAST_LSH_OK;
@@ -361,6 +362,7 @@ int fast_lsh_configure(fast_lsh_ctx* c, const fast_lsh_config* cfg) {
   c->config.bucket_chunk = chunk;
   c->config.autotune = cfg->autotune;
   c->config.bin_bits = cfg->bin_bits;
+  c->config.keep_groups = cfg->keep_groups;
   return FAST_LSH_OK;
 }
 
@@ -370,6 +372,7 @@ int fast_lsh_config_used(fast_lsh_ctx* c, fast_lsh_config* out) {
   out->bucket_chunk = c->last_choice.bucket_chunk;
   out->autotune = c->config.autotune;
   out->bin_bits = c->last_bin_bits;
+  out->keep_groups = c->last_kept;
   return FAST_LSH_OK;
 }
 

@@ -119,6 +119,7 @@ struct fast_lsh_ctx {
   std::map<std::vector<uint64_t>, TuneChoice> tuned;  // shape key -> choice
   TuneChoice last_choice;
   uint32_t last_bin_bits = 0;  // bin bits of the last search
+  uint32_t last_kept = 0;      // table groups the last bounded search kept for its pass 2
   // captured search prefix
   hipGraphExec_t graph = nullptr;
   std::vector<uint64_t> graph_key;

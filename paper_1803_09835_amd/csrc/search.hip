@@ -703,10 +703,12 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
 // group_tables so that sorting needs room for one group only.  Pass 1 sorts
 // every group and finds its buckets (sizes, counters, occurrence flags); it
 // also writes each fingerprint's sub-key rows and the high words of its split
-// mixed keys for every table.  Pass 2 recomputes each group's signatures,
-// sorts and segments it again, and runs the pair kernels on its tables with
-// the final flags.  Exact key comparisons use sub-key plus high word, so no
-// table's full keys stay resident.
+// mixed keys for every table.  Pass 2 runs the pair kernels on every group's
+// tables with the final flags: for the groups pass 1 kept (bucket-ordered
+// ids, marks and large-bucket descriptors, as many groups as HBM holds)
+// directly, for the others after rebuilding the group's keys from the stored
+// words and sorting and segmenting it again.  Exact key comparisons use
+// sub-key plus high word, so no table's full keys stay resident.
 // ---------------------------------------------------------------------------
 int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fps* f, const fast_lsh_filter* flt,
                       uint32_t flags, uint32_t group_tables, fast_lsh_stats* stats) {
@@ -779,6 +781,37 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   RC(ws<uint8_t>(c, "marks", gn, &j.marks));
   j.bigbin_grid = (uint32_t)std::min<uint64_t>(cap_bin, 512);
   j.rswl = j.pl.row_dw | 1u;
+  // Groups whose grouping pass 1 keeps for pass 2: at most keep_groups, as
+  // many as the free HBM (less a margin) and the budget hold, counting what
+  // earlier calls left allocated under these names.
+  uint32_t kept = 0;
+  uint32_t* keep_ids = nullptr;
+  uint8_t* keep_marks = nullptr;
+  uint4* keep_desc = nullptr;
+  {
+    const uint64_t per = gn * 4 + gn + cap_big * sizeof(uint4);
+    uint64_t held = 0;
+    for (const char* nm : {"keep_ids", "keep_marks", "keep_desc"}) {
+      auto it = c->ws.find(nm);
+      if (it != c->ws.end()) held += it->second.cap;
+    }
+    size_t fr = 0, tot = 0;
+    HIPCK(hipMemGetInfo(&fr, &tot));
+    const uint64_t margin = (4ull << 30) + tot / 50;
+    uint64_t avail = (uint64_t)fr + held > margin ? (uint64_t)fr + held - margin : 0;
+    if (c->budget) {
+      const uint64_t other = c->ws_total - held;
+      avail = std::min<uint64_t>(avail, c->budget > other ? c->budget - other : 0);
+    }
+    kept = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(ngroups, avail / per), c->config.keep_groups);
+    if (kept) {
+      RC(ws<uint32_t>(c, "keep_ids", (uint64_t)kept * gn, &keep_ids));
+      RC(ws<uint8_t>(c, "keep_marks", (uint64_t)kept * gn, &keep_marks));
+      RC(ws<uint4>(c, "keep_desc", (uint64_t)kept * cap_big, &keep_desc));
+    }
+  }
+  c->last_kept = kept;
+  std::vector<uint32_t> kept_big(kept, 0);
   uint64_t out_cap = std::max<uint64_t>(1u << 20, N / 8);
   {
     const uint64_t hb[3] = {j.base[0], j.base[1], occ_bound(j.base[1] - j.base[0], flt)};
@@ -890,10 +923,24 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   fill_u8(reinterpret_cast<uint8_t*>(j.ctrl), sizeof(Ctrl), 0, s);
   fill_u8(spread, j.spread_bytes, 0, s);
   fill_u8(j.flags, N, 0, s);
-  for (uint32_t g = 0; g < ngroups; ++g) RC(group(g * TGm, std::min(TGm, t - g * TGm), true));
+  Ctrl hc;
+  for (uint32_t g = 0; g < ngroups; ++g) {
+    const uint32_t tb = g * TGm, tc = std::min(TGm, t - tb);
+    // a kept group's marks and descriptors go straight to its own slices
+    ba.marks = g < kept ? keep_marks + (uint64_t)g * gn : j.marks;
+    ba.big_desc = g < kept ? keep_desc + (uint64_t)g * cap_big : j.bdesc;
+    RC(group(tb, tc, true));
+    if (g < kept) {
+      HIPCK(hipMemcpyAsync(keep_ids + (uint64_t)g * gn, j.sorted_v, (uint64_t)tc * N * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, s));
+      RC(d2h(c, &hc, j.ctrl));
+      kept_big[g] = hc.big_count;
+    }
+  }
+  ba.marks = j.marks;
+  ba.big_desc = j.bdesc;
   launch_count_flags(j.flags, N, &j.ctrl->st_flagged[0], &j.ctrl->n_flagged, s);
   LAUNCHCK();
-  Ctrl hc;
   RC(d2h(c, &hc, j.ctrl));
   if (hc.err) return fl_fail(FAST_LSH_E_INVALID, "a fingerprint is empty or holds an index >= dim (%u)", h->dim);
 
@@ -904,6 +951,20 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
     fill_u32(&j.ctrl->out_count, 1, 0, s);
     for (uint32_t g = 0; g < ngroups; ++g) {
       const uint32_t tb = g * TGm, tc = std::min(TGm, t - tb);
+      if (g < kept) {  // pass 1's grouping of this group, with the final flags
+        j.pa.order = keep_ids + (uint64_t)g * gn;
+        j.pa.table_offset = tb;
+        prof_begin(c, FAST_LSH_STAGE_PAIRS);
+        launch_pairs_wave(j.pa, keep_marks + (uint64_t)g * gn, tc, j.rswl, ba.small_max, s);
+        prof_end(c);
+        LAUNCHCK();
+        uint4* shared_desc = j.bdesc;
+        j.bdesc = keep_desc + (uint64_t)g * cap_big;
+        const int rc = run_big_pairs(c, j, kept_big[g], j.pa, j.work);
+        j.bdesc = shared_desc;
+        RC(rc);
+        continue;
+      }
       fill_u8(spread2, j.spread_bytes, 0, s);
       RC(group(tb, tc, false));
       j.pa.order = j.sorted_v;

@@ -46,7 +46,11 @@ PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pa
 
 
 class Config(ctypes.Structure):
-    _fields_ = [("radix_tile", _u32), ("bucket_chunk", _u32), ("autotune", _u32), ("bin_bits", _u32)]
+    _fields_ = [("radix_tile", _u32), ("bucket_chunk", _u32), ("autotune", _u32), ("bin_bits", _u32),
+                ("keep_groups", _u32)]
+
+
+KEEP_AUTO = 0xFFFFFFFF
 
 
 class _Profile(ctypes.Structure):
@@ -329,18 +333,22 @@ class FastLSH:
         _check(library().fast_lsh_last_work(self._ctx, ctypes.byref(w)))
         return {f: int(getattr(w, f)) for f, _ in _Work._fields_}
 
-    def configure(self, radix_tile: int = 0, bucket_chunk: int = 0, autotune: bool = False, bin_bits: int = 0):
+    def configure(self, radix_tile: int = 0, bucket_chunk: int = 0, autotune: bool = False, bin_bits: int = 0,
+                  keep_groups: int = KEEP_AUTO):
         """Launch shapes of later searches (0 keeps the current tile and chunk;
-        bin_bits 0 is the automatic rule)."""
+        bin_bits 0 is the automatic rule; keep_groups caps the table groups
+        the bounded search keeps between its passes, KEEP_AUTO: as many as
+        HBM holds)."""
         _check(library().fast_lsh_configure(self._ctx, ctypes.byref(Config(radix_tile, bucket_chunk,
-                                                                            1 if autotune else 0, bin_bits))))
+                                                                            1 if autotune else 0, bin_bits,
+                                                                            keep_groups))))
 
     def config_used(self) -> dict:
         """Launch shapes of the last search (the tuner's choice when autotuning)."""
         c = Config()
         _check(library().fast_lsh_config_used(self._ctx, ctypes.byref(c)))
         return {"radix_tile": c.radix_tile, "bucket_chunk": c.bucket_chunk, "autotune": bool(c.autotune),
-                "bin_bits": c.bin_bits}
+                "bin_bits": c.bin_bits, "keep_groups": c.keep_groups}
 
     def signatures(self, rows, dim, t, r, scheme, a, b, table_begin=0, table_count=None, with_values=False):
         """Band keys as int64 [table_count, n] (uint64 bit pattern); with

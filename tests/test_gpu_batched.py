@@ -275,14 +275,21 @@ def test_bounded_matches_full_and_oracle(ctx, name, make, dim, t, r, scheme, L, 
     rows = make()
     a, b = fl.make_hash(205, fl.n_funcs(t, r, scheme))
     dev = _dev(rows)
+    ngroups = -(-t // gt)
     for distinct in (False, True):
-        say(f"[bounded] {name} group_tables={gt} distinct={distinct}")
         full = ctx.search(dev, dim, t, r, scheme, a, b, L, v, num, den, want_distinct=distinct)
-        bnd = ctx.search_bounded(dev, dim, t, r, scheme, a, b, L, v, num, den, group_tables=gt,
-                                 want_distinct=distinct)
-        for x, y in zip(full[:3], bnd[:3]):
-            assert torch.equal(x, y)
-        assert full[3] == bnd[3]
+        # pass 2 on pass 1's kept groupings (all of them: HBM holds these
+        # sizes), on none (every group sorted again), and on the first only
+        for keep in (fl.KEEP_AUTO, 0, 1):
+            say(f"[bounded] {name} group_tables={gt} distinct={distinct} keep_groups={keep:#x}")
+            ctx.configure(keep_groups=keep)
+            bnd = ctx.search_bounded(dev, dim, t, r, scheme, a, b, L, v, num, den, group_tables=gt,
+                                     want_distinct=distinct)
+            assert ctx.config_used()["keep_groups"] == (ngroups if keep == fl.KEEP_AUTO else min(keep, ngroups))
+            for x, y in zip(full[:3], bnd[:3]):
+                assert torch.equal(x, y)
+            assert full[3] == bnd[3]
+    ctx.configure()
     ei, ej, ev, est = oracle.search(rows, dim, t, r, scheme, a, b, L, v, num, den)
     assert np.array_equal(_np(bnd[0], np.uint32), ei) and np.array_equal(_np(bnd[1], np.uint32), ej)
     assert np.array_equal(bnd[2].cpu().numpy(), ev)
