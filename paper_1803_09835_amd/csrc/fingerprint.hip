@@ -20,7 +20,8 @@
 // GPU form.  k_stft: a workgroup takes 256 consecutive frames and 32 bins;
 // the samples the frames cover and each wavefront's Hann-weighted cosine /
 // sine rows for its 8 bins are staged in LDS; each lane accumulates 4
-// frames x 8 bins (real and imaginary parts) over the window with fp32 FMA.
+// frames (64 apart) x 8 bins (real and imaginary parts) over the window with
+// fp32 FMA.
 // k_fp: one wavefront per fingerprint: the image is assembled in LDS, the
 // Haar levels run in place (every lane reads its pairs, then writes), the
 // normalized |z| of the lane's 32 consecutive coefficients are kept in
@@ -49,6 +50,7 @@ struct FpArgs {
   const float* x;
   uint64_t n;          // samples
   uint32_t window, hop, band_lo, rows, fp_frames, time_ds, cols, fp_lag, top_k;
+  uint32_t lrows, lcols;  // log2 of rows and cols (both powers of two)
   uint64_t n_frames, n_fp;
 };
 
@@ -97,7 +99,10 @@ __global__ __launch_bounds__(kFT) void k_stft(FpArgs a, float* spec) {
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[q][j] = 0.0f;
-  const float* xl = xs + (size_t)lane * 4 * a.hop;
+  // lane l takes frames l, l + 64, l + 128, l + 192 of the block, so that in
+  // every sample step the wave reads samples hop apart (a few banks each)
+  const float* xl = xs + (size_t)lane * a.hop;
+  const uint32_t qs = 64 * a.hop;
   for (uint32_t nn = 0; nn < W; ++nn) {
     float b[16];
     const float4* bp = reinterpret_cast<const float4*>(B + nn * 16);
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(kFT) void k_stft(FpArgs a, float* spec) {
     }
     float xv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) xv[q] = xl[q * a.hop + nn];
+    for (int q = 0; q < 4; ++q) xv[q] = xl[q * qs + nn];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -119,7 +124,7 @@ __global__ __launch_bounds__(kFT) void k_stft(FpArgs a, float* spec) {
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const uint64_t f = f0 + lane * 4 + q;
+    const uint64_t f = f0 + lane + 64 * q;
     if (f >= a.n_frames) continue;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -132,15 +137,15 @@ __global__ __launch_bounds__(kFT) void k_stft(FpArgs a, float* spec) {
 // In-place Haar levels along one axis of the image v (pitch P): `lines`
 // lines of length `len`, element (line, i) at v[line * ls + i * es].  All
 // waves of the workgroup run the same levels (barriers).
-__device__ __forceinline__ void haar_axis(float* v, uint32_t lines, uint32_t len, uint32_t ls, uint32_t es,
+__device__ __forceinline__ void haar_axis(float* v, uint32_t lines, uint32_t llen, uint32_t ls, uint32_t es,
                                           uint32_t lane) {
   const float s = 0.70710678118654752f;
-  for (uint32_t n = len; n > 1; n >>= 1) {
-    const uint32_t half = n >> 1, items = lines * half;
+  for (uint32_t lh = llen; lh > 0; --lh) {  // level with 2^lh elements per line
+    const uint32_t half = 1u << (lh - 1), items = lines * half;
     float av[kMaxCoef / 2 / 64], dv[kMaxCoef / 2 / 64];
     uint32_t k = 0;
     for (uint32_t e = lane; e < items; e += 64, ++k) {
-      const uint32_t line = e / half, j = e - line * half;
+      const uint32_t line = e >> (lh - 1), j = e & (half - 1);
       const float x0 = v[line * ls + (2 * j) * es], x1 = v[line * ls + (2 * j + 1) * es];
       av[k] = (x0 + x1) * s;
       dv[k] = (x0 - x1) * s;
@@ -148,7 +153,7 @@ __device__ __forceinline__ void haar_axis(float* v, uint32_t lines, uint32_t len
     __syncthreads();
     k = 0;
     for (uint32_t e = lane; e < items; e += 64, ++k) {
-      const uint32_t line = e / half, j = e - line * half;
+      const uint32_t line = e >> (lh - 1), j = e & (half - 1);
       v[line * ls + j * es] = av[k];
       v[line * ls + (half + j) * es] = dv[k];
     }
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(kFT) void k_fp(FpArgs a, const float* spec, int mod
   const uint64_t F0 = fi * a.fp_lag;
   const float inv = 1.0f / (float)a.time_ds;
   for (uint32_t e = lane; e < NC; e += 64) {
-    const uint32_t c = e / R, r = e - c * R;  // consecutive lanes: consecutive bins of one frame
+    const uint32_t c = e >> a.lrows, r = e & (R - 1);  // consecutive lanes: consecutive bins of one frame
     float sum = 0.0f;
     if (live)
       for (uint32_t d = 0; d < a.time_ds; ++d) sum += spec[(F0 + (uint64_t)c * a.time_ds + d) * R + r];
@@ -184,12 +189,12 @@ __global__ __launch_bounds__(kFT) void k_fp(FpArgs a, const float* spec, int mod
   }
   __syncthreads();
   // 2. Haar: rows (length C), then columns (length R)
-  haar_axis(v, R, C, P, 1, lane);
-  haar_axis(v, C, R, 1, P, lane);
+  haar_axis(v, R, a.lcols, P, 1, lane);
+  haar_axis(v, C, a.lrows, 1, P, lane);
   if (mode == 0) {
     if (live)
       for (uint32_t e = lane; e < NC; e += 64) {
-        const uint32_t r = e / C, c = e - r * C;
+        const uint32_t r = e >> a.lcols, c = e & (C - 1);
         keys_t[(uint64_t)e * n_items + item] = f2o(v[r * P + c]);
       }
     return;
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(kFT) void k_fp(FpArgs a, const float* spec, int mod
   uint32_t nz = 0;
   for (uint32_t q = 0; q < per; ++q) {
     const uint32_t e = lane * per + q;
-    const uint32_t r = e / C, c = e - r * C;
+    const uint32_t r = e >> a.lcols, c = e & (C - 1);
     const float w = v[r * P + c];
     const float m = mad[e];
     const float z = m > 0.0f ? (w - med[e]) / m : 0.0f;
@@ -210,14 +215,38 @@ __global__ __launch_bounds__(kFT) void k_fp(FpArgs a, const float* spec, int mod
     nz += key[q] != 0u;
   }
   for (int o = 32; o > 0; o >>= 1) nz += __shfl_xor(nz, o, 64);
-  // 4. the K-th largest key T (radix select over four 8-bit digits), and how
-  // many keys equal to T are taken (the smallest indices first); each
-  // wavefront works on its own histogram, so only wavefront-level syncs
+  // 4. the K-th largest key T (radix select over four 8-bit digits: the top
+  // one by wavefront counts, the others by LDS histograms), and how many
+  // keys equal to T are taken (the smallest indices first); each wavefront
+  // works on its own histogram, so only wavefront-level syncs
   uint32_t T = 0, take_eq = 0;
   const bool all_nonzero = nz <= a.top_k;
   if (!all_nonzero) {
-    uint32_t prefix = 0, mask = 0, remaining = a.top_k;
-    for (int shift = 24; shift >= 0; shift -= 8) {
+    uint32_t remaining = a.top_k;
+    // top digit: the keys' top bytes (sign and exponent) take few values, so
+    // instead of a histogram (whose atomics would all meet in those few
+    // bins) the occupied values are visited from the largest down with
+    // wavefront counts until the K-th key's value is reached
+    uint32_t d = 0;
+    for (uint32_t q = 0; q < per; ++q) d = max(d, key[q] >> 24);
+    for (int o = 32; o > 0; o >>= 1) d = max(d, (uint32_t)__shfl_xor(d, o, 64));
+    for (;;) {
+      uint32_t c = 0, below = 0;
+      for (uint32_t q = 0; q < per; ++q) {
+        const uint32_t t = key[q] >> 24;
+        c += key[q] != 0u && t == d;
+        if (key[q] != 0u && t < d) below = max(below, t);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, 64);
+        below = max(below, (uint32_t)__shfl_xor(below, o, 64));
+      }
+      if (c >= remaining) break;  // more than top_k keys are non-zero, so this ends
+      remaining -= c;
+      d = below;
+    }
+    uint32_t prefix = d << 24, mask = 0xFF000000u;
+    for (int shift = 16; shift >= 0; shift -= 8) {
       for (uint32_t b = lane; b < 256; b += 64) hist[b] = 0;
       wave_lds_sync();
       for (uint32_t q = 0; q < per; ++q)
@@ -363,6 +392,8 @@ extern "C" int fast_lsh_fingerprints(fast_lsh_ctx* c, const float* samples, uint
   a.fp_frames = prm->fp_frames;
   a.time_ds = prm->time_ds;
   a.cols = cols;
+  a.lrows = (uint32_t)__builtin_ctz(rows);
+  a.lcols = (uint32_t)__builtin_ctz(cols);
   a.fp_lag = prm->fp_lag;
   a.top_k = prm->top_k;
   a.n_frames = n_samples < W ? 0 : (n_samples - W) / prm->hop + 1;
