@@ -318,7 +318,7 @@ def run_station(args):
                    "n": N, "tables": t, "rows": r, "scheme": "minmax", "min_lag": L, "min_votes": v,
                    "occ": f"{occ_num}/{occ_den}"},
         "candidate_pairs_per_s": round(st.e_raw / (ms_per_step / 1000.0), 1),
-        "stats": st.__dict__,
+        "stats": stats_json(st),
         "stage_ms": {k: round(x, 3) for k, x in stage_ms.items()},
         "launch_shapes": ctx.config_used(),
         "roofline": roof,
@@ -328,6 +328,15 @@ def run_station(args):
                                         occ_den, args, "the same workload")
     ctx.close()
     return line
+
+
+def stats_json(st):
+    """Search counters for the JSON line; n_distinct is null when the search
+    was not asked to count distinct pairs (the library's all-ones marker)."""
+    d = dict(st.__dict__)
+    if d.get("n_distinct") == 2**64 - 1:
+        d["n_distinct"] = None
+    return d
 
 
 def calib_copy(args):
@@ -424,7 +433,7 @@ def run_bounded(args):
                    "n": N, "tables": t, "rows": r, "scheme": "minmax", "min_lag": L, "min_votes": v,
                    "occ": f"{occ_num}/{occ_den}", "group_tables": gt},
         "candidate_pairs_per_s": round(st.e_raw / (ms / 1000.0), 1),
-        "stats": st.__dict__,
+        "stats": stats_json(st),
         "stage_ms": {k: round(x, 3) for k, x in stage_ms.items()},
         "dominant_stage": dom,
         "hbm_gb": {"fingerprints": round(dev.numel() * 2 / 1e9, 1),
@@ -888,7 +897,7 @@ def run_partitioned(args, parts=3):
         "config": {"workload": "one station, 90 days at 1 s lag (7,776,000 fingerprints) in three partitions of 30 "
                                "days; Min-Max t=100 r=4, lag 5, v=4; dynamic occurrence filter at 1 % of each "
                                "partition", "n": N, "partitions": parts, "tables": t, "min_votes": v},
-        "stats": out[3].__dict__,
+        "stats": stats_json(out[3]),
         "same_pairs_as_plain_search": bool(all(torch.equal(x, y) for x, y in zip(out[:3], plain[:3]))),
         "stage_ms": {k: round(x, 3) for k, x in stage_ms.items() if x},
         "plain_search_ms": round(plain_ms, 3),
