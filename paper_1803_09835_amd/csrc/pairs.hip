@@ -496,10 +496,12 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
       tri_decode(m, p - bpof[b], x, y);
       uint32_t idx = lids[base + x];
       RowReg<RSW> rx;
-      if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
+      const uint32_t* rl = lrows + (base + x) * rswl;
+      const uint32_t* ry = lrows + (base + y) * rswl;  // stepped with y (no multiply per pair)
+      if (FAST) rx.load_masked(rl, own, valid); else rx.load(rl, rsw);
       for (; p < pend; ++p) {
-        const uint32_t* ry = lrows + (base + y) * rswl;
-        visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, lrows + (base + x) * rswl, ry, ry, rsw, pad, tl);
+        visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, rl, ry, ry, rsw, pad, tl);
+        ry += rswl;
         if (++y == m) {
           if (++x == m - 1) {
             if (++b >= nh) break;
@@ -509,7 +511,9 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
           }
           y = x + 1;
           idx = lids[base + x];
-          if (FAST) rx.load_masked(lrows + (base + x) * rswl, own, valid); else rx.load(lrows + (base + x) * rswl, rsw);
+          rl = lrows + (base + x) * rswl;
+          ry = rl + rswl;
+          if (FAST) rx.load_masked(rl, own, valid); else rx.load(rl, rsw);
         }
       }
     }
@@ -640,7 +644,10 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
     // Thread t holds row x = t mod tb_size in registers and takes the rounds
     // of parity t / tb_size; in a round the wave's lanes read consecutive
     // rows (conflict-free at the odd row stride).
-    const uint32_t x = threadIdx.x % tb_size, k0 = 1 + threadIdx.x / tb_size;
+    // (the round parity is uniform over a wave: a scalar, so the loop
+    // control stays off the vector unit)
+    const uint32_t x = threadIdx.x % tb_size;
+    const uint32_t k0 = 1 + __builtin_amdgcn_readfirstlane(threadIdx.x / tb_size);
     if (__ballot(x < na)) {
       const bool live = x < na;
       const uint32_t xs = live ? x : 0u;
@@ -648,14 +655,22 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       if (FAST) rx.load_masked(rowsA + xs * rswl, own, valid); else rx.load(rowsA + xs * rswl, rsw);
       const uint32_t idx = idsA[xs];
       const uint32_t* rowx = rowsA + xs * rswl;
+      // y = (x + k) mod na and its row, stepped by two rows per round
+      uint32_t y = xs + k0 < na ? xs + k0 : xs + k0 - na;
+      const uint32_t* rowy = rowsA + y * rswl;
       for (uint32_t k = k0; 2 * k <= na; k += 2) {
-        if (!live || (2 * k == na && x >= k)) continue;
-        const uint32_t y = x + k < na ? x + k : x + k - na;
-        const uint32_t* rowy = rowsA + y * rswl;
-        const uint32_t idy = idsA[y];
-        const bool fw = y > x;  // selects, not branches: one inlined visit per lane
-        visit_pair<RSW, FAST>(a, u, fw ? idx : idy, fw ? idy : idx, rx, fw ? rowx : rowy, fw ? rowy : rowx, rowy,
-                              rsw, pad, tl);
+        if (live && !(2 * k == na && x >= k)) {
+          const uint32_t idy = idsA[y];
+          const bool fw = y > x;  // selects, not branches: one inlined visit per lane
+          visit_pair<RSW, FAST>(a, u, fw ? idx : idy, fw ? idy : idx, rx, fw ? rowx : rowy, fw ? rowy : rowx, rowy,
+                                rsw, pad, tl);
+        }
+        // next round: two rows on, wrapping past na (selects, no branch)
+        y += 2;
+        rowy += 2 * rswl;
+        const bool wrap = y >= na;
+        y = wrap ? y - na : y;
+        rowy = wrap ? rowy - na * rswl : rowy;
       }
     }
   } else {
