@@ -208,14 +208,21 @@ int fast_lsh_search_batched(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, uint32
 /* Bounded-memory search: the result and counters of fast_lsh_search_ex
  * (identical bytes), computed with the tables taken group_tables at a time,
  * the way the paper bounds memory by partitioning the search (section 6.4).
- * Sorting and bucket segmentation need room for one group of tables only;
- * the signatures of each group are computed twice (once to find bucket
- * sizes and exclusions over all tables, once to emit the pairs), and exact
- * key comparisons use a 16-bit sub-key row plus a 32-bit word per table and
- * fingerprint instead of full 64-bit keys.  Workspace, in bytes, is about
- *   n * (4 t + 2 t' + 1) + group_tables * n * (24 + 1) + small tables,
+ * Sorting and bucket segmentation need room for one group of tables only.
+ * Pass 1 computes each group's signatures once, groups and segments it
+ * (bucket sizes and exclusions over all tables) and stores a 16-bit
+ * sub-key row and a 32-bit key word per table and fingerprint, which exact
+ * key comparisons use instead of full 64-bit keys.  Pass 2 emits the pairs
+ * group by group: from pass 1's kept grouping (ids in bucket order, marks,
+ * large-bucket descriptors) for as many groups as fast_lsh_config's
+ * keep_groups and the free HBM allow, otherwise after rebuilding, sorting
+ * and segmenting the group's keys again.  Workspace, in bytes, is about
+ *   n * (4 t + 2 t' + 1) + group_tables * n * (24 + 1) + small tables
+ *   + kept groups * group_tables * n * 5,
  * with t' = t rounded up to whole 32-bit words per group of the vote filter
- * (the fast_lsh_search workspace is about n * (2 t' + 1) + 33 t n).
+ * (the fast_lsh_search workspace is about n * (2 t' + 1) + 33 t n); like
+ * every workspace buffer it stays allocated in the context (reported by
+ * fast_lsh_workspace_bytes) until the context is destroyed.
  * Requires band keys of at most 48 bits (ceil(log2 dim) * r <= 48) and does
  * not take FAST_LSH_USE_GRAPH. */
 int fast_lsh_search_bounded(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *fps,
