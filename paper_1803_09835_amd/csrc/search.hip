@@ -800,14 +800,31 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
     const uint64_t margin = (4ull << 30) + tot / 50;
     uint64_t avail = (uint64_t)fr + held > margin ? (uint64_t)fr + held - margin : 0;
     if (c->budget) {
+      // within a budget, leave room for what the search allocates later (the
+      // output records and their sort, the large-bucket tile offsets)
       const uint64_t other = c->ws_total - held;
-      avail = std::min<uint64_t>(avail, c->budget > other ? c->budget - other : 0);
+      const uint64_t later = (64ull << 20) + std::max<uint64_t>(1u << 20, N / 8) * 32 +
+                             (gn / (smax + 1) + 2) * 24;
+      avail = std::min<uint64_t>(avail, c->budget > other + later ? c->budget - other - later : 0);
     }
     kept = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(ngroups, avail / per), c->config.keep_groups);
-    if (kept) {
-      RC(ws<uint32_t>(c, "keep_ids", (uint64_t)kept * gn, &keep_ids));
-      RC(ws<uint8_t>(c, "keep_marks", (uint64_t)kept * gn, &keep_marks));
-      RC(ws<uint4>(c, "keep_desc", (uint64_t)kept * cap_big, &keep_desc));
+    if (kept && (ws<uint32_t>(c, "keep_ids", (uint64_t)kept * gn, &keep_ids) != FAST_LSH_OK ||
+                 ws<uint8_t>(c, "keep_marks", (uint64_t)kept * gn, &keep_marks) != FAST_LSH_OK ||
+                 ws<uint4>(c, "keep_desc", (uint64_t)kept * cap_big, &keep_desc) != FAST_LSH_OK)) {
+      // the memory was not there after all: release what was taken and sort
+      // every group again in pass 2
+      HIPCK(hipStreamSynchronize(s));
+      for (const char* nm : {"keep_ids", "keep_marks", "keep_desc"}) {
+        auto it = c->ws.find(nm);
+        if (it == c->ws.end()) continue;
+        if (it->second.p) {
+          HIPCK(hipFree(it->second.p));
+          c->ws_total -= it->second.cap;
+        }
+        c->ws.erase(it);
+      }
+      ++c->ws_generation;
+      kept = 0;
     }
   }
   c->last_kept = kept;

@@ -313,3 +313,39 @@ def test_bounded_rejects(ctx):
     empty = torch.empty((0, 200), dtype=torch.int16, device="cuda")
     gi, gj, gv, st = ctx.search_bounded(empty, 4096, 20, 4, fl.MINHASH, a, b, 5, 2)
     assert len(gi) == 0 and st.n_out == 0
+
+
+def test_bounded_keeps_what_the_budget_holds():
+    # A context whose HBM budget holds the bounded search's workspace plus
+    # about two and a half groups' kept groupings keeps one or two of the ten
+    # and sorts the others again; the result is the full search's either way.
+    rows = synth.generate(synth.station(n=3_000_000, seed=48))
+    a, b = fl.make_hash(205, 200)
+    dev = fl.to_device_rows(rows)
+    args = (dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100)
+    c0 = fl.FastLSH(0)
+    full = c0.search(*args)
+    c0.close()
+    sizes = {}
+    for keep in (0, fl.KEEP_AUTO):
+        c = fl.FastLSH(0)
+        c.configure(keep_groups=keep)
+        out = c.search_bounded(*args, group_tables=10)
+        sizes[keep] = (c.workspace_bytes(), c.config_used()["keep_groups"])
+        c.close()
+        for x, y in zip(full[:3], out[:3]):
+            assert torch.equal(x, y)
+        assert full[3] == out[3]
+    assert sizes[0][1] == 0 and sizes[fl.KEEP_AUTO][1] == 10
+    per_group = (sizes[fl.KEEP_AUTO][0] - sizes[0][0]) / 10
+    budget = int(sizes[0][0] + 2.5 * per_group)
+    say(f"[bounded] workspace {sizes[0][0]} without kept groupings, {per_group:.0f} per kept group; budget {budget}")
+    c = fl.FastLSH(0, hbm_budget=budget)
+    out = c.search_bounded(*args, group_tables=10)
+    kept = c.config_used()["keep_groups"]
+    assert 1 <= kept <= 2 and c.workspace_bytes() <= budget
+    c.close()
+    say(f"[bounded] budget keeps {kept} groupings")
+    for x, y in zip(full[:3], out[:3]):
+        assert torch.equal(x, y)
+    assert full[3] == out[3]
