@@ -258,3 +258,71 @@ def _host_votes(rows, a, b, pi, pj):
     keys = oracle.signatures(np.ascontiguousarray(rows[ids]), DIM, T, R, oracle.MINMAX, a, b)
     x, y = np.searchsorted(ids, pi), np.searchsorted(ids, pj)
     return (keys[:, x] == keys[:, y]).sum(axis=0).astype(np.int64)
+
+
+def test_batched_12_stations_full_size():
+    """The batched workload at its full size (12 stations of 1-8, 10, 12, 14
+    and 16 M uniform fingerprints with 50 x 5 planted copies each, 88 M in
+    all; MinHash t=20 r=4, lag 5, v=2): the one batched search equals every
+    station searched alone, element by element and counter by counter;
+    sampled reported pairs carry the oracle's votes, and every pair of
+    copies of a planted source is reported exactly when the oracle's votes
+    reach the threshold."""
+    t, r, scheme, lag, v = 20, 4, fl.MINHASH, 5, 2
+    a, b = fl.make_hash(201, fl.n_funcs(t, r, scheme))
+    hosts, labs, devs = [], [], []
+    for s, m in enumerate(synth.BATCH_LENGTHS_M):
+        spec = synth.tiny_uniform(n=m * 1_000_000, seed=1030 + s)
+        rows = np.empty((spec.n, spec.nnz), dtype=np.uint16)
+        _, lab = synth.generate(spec, 0, spec.n, labels=True, out=rows)
+        hosts.append(rows)
+        labs.append(lab)
+        devs.append(torch.from_numpy(rows.view(np.int16)).cuda())
+    say(f"[batched-full] {sum(len(x) for x in hosts)} fingerprints in {len(hosts)} stations")
+    ctx = fl.FastLSH(0)
+    bi, bj, bv, offs, bst = ctx.search_batched(devs, DIM, t, r, scheme, a, b, lag, v)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    total_want = 0
+    for s, rows in enumerate(hosts):
+        oi, oj, ov, st = ctx.search(devs[s], DIM, t, r, scheme, a, b, lag, v)
+        lo, hi = int(offs[s]), int(offs[s + 1])
+        assert torch.equal(bi[lo:hi], oi) and torch.equal(bj[lo:hi], oj) and torch.equal(bv[lo:hi], ov)
+        assert bst[s] == st
+        gi = oi.cpu().numpy().view(np.uint32).astype(np.int64)
+        gj = oj.cpu().numpy().view(np.uint32).astype(np.int64)
+        gv = ov.cpu().numpy().astype(np.int64)
+        key = (gi << 32) | gj
+        k = rng.choice(len(key), min(300, len(key)), replace=False)
+        assert np.array_equal(_minhash_votes(rows, a, b, t, r, gi[k], gj[k]), gv[k])
+        lab = labs[s]
+        planted = np.flatnonzero(lab >= 0)
+        pi, pj = [], []
+        for src in np.unique(lab[planted]):
+            members = np.sort(planted[lab[planted] == src])
+            for x in range(len(members)):
+                for y in range(x + 1, len(members)):
+                    if members[y] - members[x] >= lag:
+                        pi.append(members[x])
+                        pj.append(members[y])
+        pi, pj = np.array(pi, dtype=np.int64), np.array(pj, dtype=np.int64)
+        votes = _minhash_votes(rows, a, b, t, r, pi, pj)
+        want = votes >= v
+        q = (pi << 32) | pj
+        pos = np.minimum(np.searchsorted(key, q), len(key) - 1)
+        found = key[pos] == q
+        say(f"[batched-full] station {s}: {hi - lo} pairs, {st}; planted pairs {len(q)}, {int(want.sum())} at or "
+            f"above the threshold")
+        assert np.array_equal(found, want)
+        assert np.array_equal(gv[pos][found], votes[found])
+        total_want += int(want.sum())
+    assert total_want > 100
+    ctx.close()
+
+
+def _minhash_votes(rows, a, b, t, r, pi, pj):
+    """Oracle votes (MinHash) of pairs (pi, pj) of host rows."""
+    ids = np.unique(np.concatenate([pi, pj]))
+    keys = oracle.signatures(np.ascontiguousarray(rows[ids]), DIM, t, r, oracle.MINHASH, a, b)
+    x, y = np.searchsorted(ids, pi), np.searchsorted(ids, pj)
+    return (keys[:, x] == keys[:, y]).sum(axis=0).astype(np.int64)
