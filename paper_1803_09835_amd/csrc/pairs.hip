@@ -564,11 +564,14 @@ __global__ __launch_bounds__(kPT) void k_work_reduce(const unsigned long long* w
 }
 
 // The bucket of every tile unit: owner[q] = b for q in [toff[b], toff[b+1])
-// (one thread per bucket).
+// (one wavefront per bucket, its lanes on consecutive units, the waves
+// striding over the buckets: the largest bucket's million tiles take
+// sixteen thousand stores of a wave instead of a million of one thread).
 __global__ __launch_bounds__(kPT) void k_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner) {
-  const uint64_t b = (uint64_t)blockIdx.x * kPT + threadIdx.x;
-  if (b >= nbig) return;
-  for (uint64_t q = toff[b], e = toff[b + 1]; q < e; ++q) owner[q] = (uint32_t)b;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * (kPT / 64);
+  for (uint32_t b = blockIdx.x * (kPT / 64) + threadIdx.x / 64; b < nbig; b += waves)
+    for (uint64_t q = toff[b] + lane, e = toff[b + 1]; q < e; q += 64) owner[q] = b;
 }
 
 // One tile (ta, tb) of the upper triangle of a large bucket's pair matrix.
@@ -903,7 +906,10 @@ void launch_work_reduce(const unsigned long long* work, unsigned long long* out,
 }
 
 void launch_unit_owner(const uint64_t* toff, uint32_t nbig, uint32_t* owner, hipStream_t s) {
-  if (nbig) hipLaunchKernelGGL(k_unit_owner, dim3((nbig + kPT - 1) / kPT), dim3(kPT), 0, s, toff, nbig, owner);
+  if (nbig) {
+    const uint32_t blocks = std::min<uint32_t>((nbig + kPT / 64 - 1) / (kPT / 64), 16 * device_cus());
+    hipLaunchKernelGGL(k_unit_owner, dim3(blocks), dim3(kPT), 0, s, toff, nbig, owner);
+  }
 }
 
 void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* owner, uint64_t unit_base, uint32_t nunits,

@@ -884,7 +884,9 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   // writes rows and high words and accounts the buckets.
   // Pass 2 rebuilds the group's mixed keys (mix48(key) << 16) from the high
   // words and sub-key rows pass 1 stored, instead of recomputing signatures.
-  auto group = [&](uint32_t tb, uint32_t tc, bool first_pass) -> int {
+  // keep_vals: where the last radix pass leaves the group's ids (a kept
+  // grouping's slice, sorted in place there by the bucket kernels), or null.
+  auto group = [&](uint32_t tb, uint32_t tc, bool first_pass, uint32_t* keep_vals) -> int {
     prof_begin(c, first_pass ? FAST_LSH_STAGE_SIGNATURES : FAST_LSH_STAGE_SPLIT_KEYS);
     if (first_pass) {
       SigArgs sa = fl_sig_args(h, f, j.dhash, &j.ctrl->err);
@@ -909,9 +911,13 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
     prof_begin(c, FAST_LSH_STAGE_GROUP);
     for (uint32_t pass = 0; pass < j.B / 8; ++pass) {
       const uint32_t shift = 64 - j.B + 8 * pass;
-      radix_pass(gk2, pass == 0 ? nullptr : gv2, gk, gv, N, tc, shift, j.hist, j.sums, variant, s);
+      uint32_t* vout = (keep_vals && pass + 1 == j.B / 8) ? keep_vals : gv;
+      radix_pass(gk2, pass == 0 ? nullptr : gv2, gk, vout, N, tc, shift, j.hist, j.sums, variant, s);
       std::swap(gk, gk2);
-      std::swap(gv, gv2);
+      if (vout == gv)
+        std::swap(gv, gv2);
+      else
+        gv2 = vout;  // gv stays free for the big-bin kernel
     }
     prof_end(c);
     LAUNCHCK();
@@ -946,10 +952,8 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
     // a kept group's marks and descriptors go straight to its own slices
     ba.marks = g < kept ? keep_marks + (uint64_t)g * gn : j.marks;
     ba.big_desc = g < kept ? keep_desc + (uint64_t)g * cap_big : j.bdesc;
-    RC(group(tb, tc, true));
+    RC(group(tb, tc, true, g < kept ? keep_ids + (uint64_t)g * gn : nullptr));
     if (g < kept) {
-      HIPCK(hipMemcpyAsync(keep_ids + (uint64_t)g * gn, j.sorted_v, (uint64_t)tc * N * sizeof(uint32_t),
-                           hipMemcpyDeviceToDevice, s));
       RC(d2h(c, &hc, j.ctrl));
       kept_big[g] = hc.big_count;
     }
@@ -983,7 +987,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
         continue;
       }
       fill_u8(spread2, j.spread_bytes, 0, s);
-      RC(group(tb, tc, false));
+      RC(group(tb, tc, false, nullptr));
       j.pa.order = j.sorted_v;
       j.pa.table_offset = tb;
       prof_begin(c, FAST_LSH_STAGE_PAIRS);
