@@ -237,6 +237,18 @@ __device__ __forceinline__ uint32_t station_of(const uint64_t* base, uint32_t nb
   return s;
 }
 
+// Workgroups of a launch are handed to the eight XCDs in turn (workgroup b
+// to XCD b mod 8), each XCD with its own L2.  Kernels whose neighbouring
+// workgroups share data take their work item from xcd_block: a bijection of
+// [0, nb) that gives each XCD a contiguous range of items (b goes to the
+// (b / 8)-th item of XCD (b mod 8)'s range; the first nb mod 8 XCDs hold
+// q + 1 items, the others q, q = nb / 8).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t q = nb / kXcd, r = nb % kXcd, x = b % kXcd, idx = b / kXcd;
+  return x < r ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
+}
+
 // Buckets of at most kSmallBucket members are handled by the wave-per-chunk
 // pair kernel (their members staged in LDS); larger ones by the tile kernel.
 // The pair forms that compare each pair against a row held in registers

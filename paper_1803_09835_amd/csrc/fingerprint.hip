@@ -173,7 +173,9 @@ __global__ __launch_bounds__(kFT) void k_fp(FpArgs a, const float* spec, int mod
   const uint32_t R = a.rows, C = a.cols, NC = R * C, P = C + kPitchPad;
   float* v = lds2 + (size_t)wave * (R * P + 256);  // image, then 256 histogram words
   uint32_t* hist = reinterpret_cast<uint32_t*>(v + R * P);
-  const uint64_t item = (uint64_t)blockIdx.x * 4 + wave;
+  // consecutive fingerprints share most of their frames: keep them on one
+  // XCD's L2
+  const uint64_t item = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
   const bool live = item < n_items;
   const uint64_t fi = !live ? 0 : (mode == 0 ? sample_ids[item] : item);
   // 1. spectral image: column c averages frames c*ds .. c*ds+ds-1 of the

@@ -582,6 +582,8 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
                                                     uint64_t unit_base, const uint4* big, uint32_t tb_size,
                                                     uint32_t rswl) {
   extern __shared__ uint32_t smem[];
+  // (units stay in launch order across the XCDs: contiguous unit ranges per
+  // XCD balance badly, tiles of a range differing widely in cost)
   const uint64_t unit = unit_base + blockIdx.x;
   const uint32_t bk = owner[unit];
   const uint4 d = big[bk];  // {position, segment, members}
