@@ -150,8 +150,20 @@ def test_station_90d_full_size():
     ctx.close()
 
 
+GOLDEN_5Y = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "station5y_counters.json")
+
+
 def test_station_5y_bounded_full_size():
+    """The 5-year station searched as bench.py's default workload searches it
+    (bounded search, tables 10 at a time): its exact global counters e_raw,
+    max_bucket and n_flagged against the oracle's (tests/golden/
+    station5y_counters.json, written by make_station5y_counters.py from the
+    oracle alone, a few tables at a time), plus the sampled checks of the
+    pairs."""
+    gold = json.load(open(GOLDEN_5Y))
     spec = synth.long_station(n=synth.STATION_5Y, seed=105)
+    assert gold["n"] == spec.n and gold["data_seed"] == 105 and gold["hash_seed"] == 205
+    assert (gold["tables"], gold["rows"], gold["occ_num"], gold["occ_den"]) == (T, R, NUM, DEN)
     say("[fullsize] station 5 years: generating")
     dev, labels = _upload(spec)
     a, b = fl.make_hash(205, fl.n_funcs(T, R, SCHEME))
@@ -159,7 +171,9 @@ def test_station_5y_bounded_full_size():
     t0 = time.time()
     out = ctx.search_bounded(dev, DIM, T, R, SCHEME, a, b, L, V, NUM, DEN, group_tables=10)
     torch.cuda.synchronize()
-    say(f"[fullsize] bounded search {time.time() - t0:.2f}s")
+    st = out[3]
+    say(f"[fullsize] bounded search {time.time() - t0:.2f}s: {st}, groupings kept {ctx.config_used()['keep_groups']}")
+    assert {"e_raw": st.e_raw, "max_bucket": st.max_bucket, "n_flagged": st.n_flagged} == gold["counters"]
     _check_sampled(dev, labels, out, spec.n, a, b, 2)
     ctx.close()
 
