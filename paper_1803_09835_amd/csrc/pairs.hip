@@ -163,34 +163,44 @@ struct RowReg {
     }
     (void)rsw;
   }
-  // Number of equal 16-bit sub-keys against another row.
+  // Number of equal 16-bit sub-keys against another row.  RSW > 0: the
+  // unequal ones are counted in packed halves (min(a ^ b, 1) is 0 for an
+  // equal field, 1 otherwise), two fields per instruction.
   __device__ __forceinline__ uint32_t eq(const uint32_t* other, uint32_t rsw) const {
-    uint32_t e = 0;
     if (RSW > 0) {
+      typedef unsigned short half2 __attribute__((ext_vector_type(2)));
+      const half2 one = {1, 1};
+      half2 ne = {0, 0};
 #pragma unroll
-      for (int k = 0; k < kW; ++k) e += eq2(w[k], other[k]);
-    } else {
-#pragma unroll 4
-      for (uint32_t k = 0; k < rsw; ++k) e += eq2(lds[k], other[k]);
+      for (int k = 0; k < kW; ++k) ne += __builtin_elementwise_min(__builtin_bit_cast(half2, w[k] ^ other[k]), one);
+      return 2u * kW - ((uint32_t)ne.x + (uint32_t)ne.y);
     }
+    uint32_t e = 0;
+#pragma unroll 4
+    for (uint32_t k = 0; k < rsw; ++k) e += eq2(lds[k], other[k]);
     return e;
   }
   __device__ __forceinline__ static uint32_t eq2(uint32_t a, uint32_t b) {
     return (uint32_t)((uint16_t)a == (uint16_t)b) + (uint32_t)((a >> 16) == (b >> 16));
   }
-  // Equal sub-keys in fields below `u` (one group holding every table).
+  // Non-zero when some sub-key in a field below `u` is equal (one group
+  // holding every table).  RSW > 0: the fields at or above u are forced
+  // unequal by a mask (u is uniform over the wave, so the masks are scalar)
+  // and the packed minimum of a ^ b over the row finds a zero half.
   __device__ __forceinline__ uint32_t eq_below(const uint32_t* other, uint32_t rsw, uint32_t u) const {
-    uint32_t e = 0;
+    (void)rsw;
     if (RSW > 0) {
+      typedef unsigned short half2 __attribute__((ext_vector_type(2)));
+      half2 acc = {0xFFFF, 0xFFFF};
 #pragma unroll
       for (int k = 0; k < kW; ++k) {
-        const uint32_t a = w[k], b = other[k];
-        e += (2u * k < u && (uint16_t)a == (uint16_t)b) + (2u * k + 1 < u && (a >> 16) == (b >> 16));
+        const uint32_t m = (2u * k >= u ? 0x0000FFFFu : 0u) | (2u * k + 1 >= u ? 0xFFFF0000u : 0u);
+        acc = __builtin_elementwise_min(acc, __builtin_bit_cast(half2, (w[k] ^ other[k]) | m));
       }
-    } else {
-      for (uint32_t f = 0; f < u; ++f) e += row_field(lds, f) == row_field(other, f);
+      return (uint32_t)(acc.x == 0) + (uint32_t)(acc.y == 0);
     }
-    (void)rsw;
+    uint32_t e = 0;
+    for (uint32_t f = 0; f < u; ++f) e += row_field(lds, f) == row_field(other, f);
     return e;
   }
   // Left row for the "another table shares the bucket" test (RSW > 0): the
@@ -242,7 +252,7 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
     for (int k = 0; k < RowReg<RSW>::kW; ++k) asm volatile("" : "+v"(rv[k]));  // keep the loads above the branch
   }
   if (i == kDead || j == kDead || j - i < a.min_lag) return;
-  if (a.part_mode == 3 && (i < a.plo || i >= a.phi)) return;  // pairs of this partition only
+  if (a.part_mode == 3 && (i < a.plo || i >= a.phi)) return;  // pairs of the partitions reported
   if (!FAST && (a.part_mode == 1 || a.part_mode == 2)) {
     // partitioned search: counts and exclusions at the pair's first shared
     // table only, tested after the cheaper checks that can skip the pair
@@ -464,7 +474,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
       mem[r] = upto && q < span && q < h + hs;
       mid[r] = mem[r] ? lids[q] : 0u;
     }
-    if (RSW > 0) {  // both rows' loads (each only where that member exists) before either store
+    if (RSW > 0 && RSW <= 32) {  // both rows' loads (each only where that member exists) before either store
       constexpr int kW = RSW > 0 ? RSW : 1;
       uint32_t v0[kW], v1[kW];
       if (mem[0]) RowReg<RSW>::fetch(R + (uint64_t)mid[0] * a.row_pitch, v0);
@@ -882,6 +892,10 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
       if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<17, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
       else hipLaunchKernelGGL((k_pairs_wave<17, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
       break;
+    case 50:  // one group of 100 tables
+      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<50, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
+      else hipLaunchKernelGGL((k_pairs_wave<50, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
+      break;
     default:
       hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
       break;
@@ -924,6 +938,7 @@ void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* 
   switch (a.row_dw) {
     case 10: if (fast_test(a)) FL_TILE(10, true); else FL_TILE(10, false); break;
     case 17: if (fast_test(a)) FL_TILE(17, true); else FL_TILE(17, false); break;
+    case 50: if (fast_test(a)) FL_TILE(50, true); else FL_TILE(50, false); break;
     default: FL_TILE(0, false); break;
   }
 #undef FL_TILE

@@ -383,10 +383,23 @@ int finish_output(fast_lsh_ctx* c, Job& j, uint64_t cnt, bool distinct, fast_lsh
 // (2) those over occ_num/occ_den of the partition's size are excluded with
 // all their candidates; (3) the pairs whose smaller id lies in p are
 // reported.  The exclusion bytes j.flags start at zero and only grow.
+//
+// The passes are merged across partitions where the exclusions allow it.
+// A fingerprint's count depends only on the exclusions made before its
+// partition, so one counting pass serves every partition from the current
+// one to the last, until some partition excludes: then the partitions after
+// it are counted again.  Partition p's pairs are reported with the
+// exclusions as they stand after p, and those change only at a partition
+// that excludes, so one reporting pass covers each run of partitions up to
+// the next one that excludes.  Without exclusions this is one counting and
+// one reporting pass whatever the partition count; each partition that
+// excludes adds an exclusion pass and at most one counting and one
+// reporting pass.
 int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t big_count, uint64_t out_cap,
                    Ctrl* hc_out) {
   hipStream_t s = c->stream;
   const uint64_t N = j.N;
+  const uint32_t P = j.parts;
   uint32_t* cand;
   uint8_t *fp, *exn;
   unsigned long long *always, *dummy;
@@ -398,6 +411,23 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
   RC(ws<unsigned long long>(c, "part_work", 3 * kSpread, &dummy));
   RC(ws<unsigned int>(c, "part_nfp", 1, &nfp));
   fill_u64(reinterpret_cast<uint64_t*>(always), 1, 1, s);  // the pair kernels always consult the exclusions
+  auto lo_of = [&](uint32_t p) { return (uint32_t)(N * p / P); };
+  // one pass of mode m over the pairs whose ids the mode restricts to [lo, hi)
+  auto pass = [&](const PairArgs& base, int mode, uint32_t lo, uint32_t hi, unsigned long long* work) -> int {
+    PairArgs m = base;
+    m.part_mode = mode;
+    m.plo = lo;
+    m.phi = hi;
+    prof_begin(c, FAST_LSH_STAGE_PAIRS);
+    launch_pairs_wave(m, j.marks, j.t, j.rswl, j.ba.small_max, s);
+    prof_end(c);
+    LAUNCHCK();
+    return run_big_pairs(c, j, big_count, m, work);
+  };
+  auto count_from = [&](const PairArgs& base, uint32_t p) -> int {
+    fill_u32(cand + lo_of(p), N - lo_of(p), 0, s);
+    return pass(base, 1, lo_of(p), (uint32_t)N, dummy);
+  };
   Ctrl hc;
   for (int attempt = 0; attempt < 2; ++attempt) {
     RC(set_out_buffers(c, j, out_cap));
@@ -412,43 +442,28 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
     pa.cand = cand;
     pa.fp = fp;
     pa.ex_next = exn;
-    for (uint32_t p = 0; p < j.parts; ++p) {
-      pa.plo = (uint32_t)(N * p / j.parts);
-      pa.phi = (uint32_t)(N * (p + 1) / j.parts);
-      if (flt.occ_den && pa.phi > pa.plo) {
-        fill_u32(cand + pa.plo, pa.phi - pa.plo, 0, s);
+    uint32_t unreported = 0;  // first partition whose pairs are not reported yet
+    if (flt.occ_den) {
+      RC(count_from(pa, 0));
+      for (uint32_t p = 0; p < P; ++p) {
+        const uint32_t lo = lo_of(p), hi = lo_of(p + 1);
+        if (hi == lo) continue;
         fill_u32(nfp, 1, 0, s);
-        PairArgs m1 = pa;
-        m1.part_mode = 1;
-        prof_begin(c, FAST_LSH_STAGE_PAIRS);
-        launch_pairs_wave(m1, j.marks, j.t, j.rswl, j.ba.small_max, s);
-        prof_end(c);
-        LAUNCHCK();
-        RC(run_big_pairs(c, j, big_count, m1, dummy));
-        launch_part_flag(j.flags, cand, pa.plo, pa.phi, flt.occ_num, flt.occ_den, fp, nfp, s);
+        launch_part_flag(j.flags, cand, lo, hi, flt.occ_num, flt.occ_den, fp, nfp, s);
         LAUNCHCK();
         unsigned int hn = 0;
         RC(d2h(c, &hn, nfp));
-        if (hn) {
-          PairArgs m2 = pa;
-          m2.part_mode = 2;
-          prof_begin(c, FAST_LSH_STAGE_PAIRS);
-          launch_pairs_wave(m2, j.marks, j.t, j.rswl, j.ba.small_max, s);
-          prof_end(c);
-          LAUNCHCK();
-          RC(run_big_pairs(c, j, big_count, m2, dummy));
-          launch_part_merge(j.flags, fp, exn, N, s);
-          LAUNCHCK();
-        }
+        if (!hn) continue;
+        // the partitions before p see the exclusions as they stand now
+        if (unreported < p) RC(pass(pa, 3, lo_of(unreported), lo, j.work));
+        unreported = p;
+        RC(pass(pa, 2, lo, hi, dummy));
+        launch_part_merge(j.flags, fp, exn, N, s);
+        LAUNCHCK();
+        if (p + 1 < P) RC(count_from(pa, p + 1));
       }
-      PairArgs m3 = pa;
-      m3.part_mode = 3;
-      prof_begin(c, FAST_LSH_STAGE_PAIRS);
-      launch_pairs_wave(m3, j.marks, j.t, j.rswl, j.ba.small_max, s);
-      prof_end(c);
-      LAUNCHCK();
-      RC(run_big_pairs(c, j, big_count, m3, j.work));
     }
+    RC(pass(pa, 3, lo_of(unreported), (uint32_t)N, j.work));
     RC(d2h(c, &hc, j.ctrl));
     if (hc.out_count <= out_cap) break;
     out_cap = (uint64_t)hc.out_count + 1024;
