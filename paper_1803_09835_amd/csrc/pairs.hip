@@ -132,6 +132,25 @@ __device__ __forceinline__ bool lower_in_group(const PairArgs& a, uint32_t u, ui
   return group_shared(a, rl, rr, g * a.tables_per_group, i, j, own, 1) != 0;
 }
 
+// Some table of u's group above u exactly shares a bucket with (i, j); rl,
+// rr: the pair's rows of that group (in LDS).  With need == 2 and no lower
+// table of the group sharing, u can own the pair only if one does: a pair
+// whose sub-keys agree by chance is then turned away after one key check,
+// without the owner check's reads of the other groups' rows.
+__device__ __forceinline__ bool upper_in_group(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
+                                               const uint32_t* rl, const uint32_t* rr) {
+  const uint32_t g = u / a.tables_per_group, own = u - g * a.tables_per_group;
+  const uint32_t tb = g * a.tables_per_group;
+  const uint32_t fields = min(a.tables_per_group, a.t - tb);
+  for (uint32_t f0 = (own + 1) & ~31u; f0 < fields; f0 += 32) {
+    uint32_t m = field_eq_mask(rl + f0 / 2, rr + f0 / 2, min(16u, (fields - f0 + 1) / 2));
+    if (fields - f0 < 32) m &= (1u << (fields - f0)) - 1;
+    if (f0 <= own) m &= ~((2u << (own - f0)) - 1u);  // fields f0 .. own dropped
+    if (count_shared(a, m, tb + f0, i, j, 1) != 0) return true;
+  }
+  return false;
+}
+
 // Per-lane vote tallies of one station; [lo, hi) is that station's id range
 // (looked up again only when a pair falls outside it).
 struct PairTally {
@@ -284,7 +303,8 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
   }
   ++tl.ev;
   if (FAST) {
-    if (rx.any_equal(rv) && !lower_in_group(a, u, i, j, rl, ry)) exact_and_report(a, u, i, j);
+    if (rx.any_equal(rv) && !lower_in_group(a, u, i, j, rl, ry) && upper_in_group(a, u, i, j, rl, ry))
+      exact_and_report(a, u, i, j);
     return;
   }
   const uint32_t eq = rx.eq(ro, rsw);
@@ -647,10 +667,10 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       RowReg<RSW> rx;
       if (FAST) rx.load_masked(rowsA + xs * rswl, own, valid); else rx.load(rowsA + xs * rswl, rsw);
       const uint32_t idx = idsA[xs];
-      for (uint32_t y = y0; y < nbm; y += 2)
-        if (live)
-          visit_pair<RSW, FAST>(a, u, idx, idsB[y], rx, rowsA + xs * rswl, rowsB + y * rswl, rowsB + y * rswl, rsw,
-                                pad, tl);
+      const uint32_t* rowx = rowsA + xs * rswl;
+      const uint32_t* rowy = rowsB + y0 * rswl;  // stepped with y (no multiply per pair)
+      for (uint32_t y = y0; y < nbm; y += 2, rowy += 2 * rswl)
+        if (live) visit_pair<RSW, FAST>(a, u, idx, idsB[y], rx, rowx, rowy, rowy, rsw, pad, tl);
     }
   } else if (diag && tb_size == kPT / 2) {
     // Diagonal tiles: the pairs {x, (x + k) mod na} for k = 1 .. na / 2 are
@@ -703,16 +723,23 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
         x = p / nbm;
         y = p - x * nbm;
       }
+      // rows and the left id follow x and y (no multiply per pair)
+      const uint32_t* rl = rowsA + x * rswl;
+      const uint32_t* ry = rowsB + y * rswl;
+      uint32_t idx = idsA[x];
       RowReg<RSW> rx;
-      if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
+      if (FAST) rx.load_masked(rl, own, valid); else rx.load(rl, rsw);
       for (; p < pend; ++p) {
-        visit_pair<RSW, FAST>(a, u, idsA[x], idsB[y], rx, rowsA + x * rswl, rowsB + y * rswl, rowsB + y * rswl, rsw,
-                              pad, tl);
+        visit_pair<RSW, FAST>(a, u, idx, idsB[y], rx, rl, ry, ry, rsw, pad, tl);
+        ry += rswl;
         if (++y == nbm) {
           ++x;
           y = diag ? x + 1 : 0;
           if (x < na) {
-            if (FAST) rx.load_masked(rowsA + x * rswl, own, valid); else rx.load(rowsA + x * rswl, rsw);
+            rl = rowsA + x * rswl;
+            ry = rowsB + y * rswl;
+            idx = idsA[x];
+            if (FAST) rx.load_masked(rl, own, valid); else rx.load(rl, rsw);
           }
         }
       }
