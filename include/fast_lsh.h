@@ -397,7 +397,9 @@ enum {
   FAST_LSH_STAGE_FINGERPRINTS = 11, /* fast_lsh_fingerprints: images, Haar,
                                        statistics, top-K                      */
   FAST_LSH_STAGE_SPECTROGRAM = 12,  /* fast_lsh_fingerprints: STFT power      */
-  FAST_LSH_PROFILE_STAGES = 13
+  FAST_LSH_STAGE_PAIR_CHECKS = 13,  /* exact checks of the pairs the pair
+                                       kernels queued (need == 2 form)        */
+  FAST_LSH_PROFILE_STAGES = 14
 };
 
 typedef struct {

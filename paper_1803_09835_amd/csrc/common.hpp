@@ -228,6 +228,14 @@ struct PairArgs {
   uint32_t* cand;
   const uint8_t* fp;
   uint8_t* ex_next;
+  // Candidate queue of the need == 2 form: a pair that passes the sub-key
+  // group test is appended as (i, j, table) to its workgroup's spread slot,
+  // q[slot][0, qcap), and given its exact checks by a later launch with one
+  // lane per pair, instead of stalling its wavefront on them; a pair that
+  // finds the slot full is checked in place.  qcap == 0: all in place.
+  uint4* q;
+  unsigned int* q_count;  // [kSpread] appends per slot (may pass qcap)
+  uint32_t qcap;
 };
 
 // Station of a (global) fingerprint id, for nb stations with ascending bases.

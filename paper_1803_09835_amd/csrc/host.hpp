@@ -36,6 +36,10 @@ void launch_bigbin(const BucketArgs& a, const uint4* bins, uint32_t grid, uint64
 uint32_t pair_small_max(uint32_t need, bool distinct, uint32_t parts, uint32_t row_dw);
 void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t rswl, uint32_t small_max,
                        hipStream_t s);
+// Whether a pair launch with these arguments queues its candidates, and the
+// launch that checks (and empties) the queue after it.
+bool pair_launch_queues(const PairArgs& a);
+void launch_check_queue(const PairArgs& a, hipStream_t s);
 void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, unsigned long long* work,
                         hipStream_t s);
 void launch_work_reduce(const unsigned long long* work, unsigned long long* out, hipStream_t s);

@@ -151,6 +151,34 @@ __device__ __forceinline__ bool upper_in_group(const PairArgs& a, uint32_t u, ui
   return false;
 }
 
+// The exact checks of a pair (i < j) of table u's bucket whose sub-keys
+// passed the group test (need == 2): u owns it only if no lower table of
+// u's group shares a bucket with it and some higher one does; the owner
+// check then settles the earlier groups and the votes.  rl, rr: the pair's
+// rows of u's group (in LDS or in memory).
+__device__ __forceinline__ void check_candidate(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
+                                                const uint32_t* rl, const uint32_t* rr) {
+  if (!lower_in_group(a, u, i, j, rl, rr) && upper_in_group(a, u, i, j, rl, rr)) exact_and_report(a, u, i, j);
+}
+
+// Appends the calling lane's candidate (want) to the queue of the
+// workgroup's spread slot: one atomic per wavefront for all its active
+// lanes that want to.  False when the slot is full (check it in place).
+__device__ __forceinline__ bool enqueue_candidate(const PairArgs& a, bool want, uint32_t u, uint32_t i, uint32_t j) {
+  const uint64_t m = __ballot(want);
+  if (m == 0) return true;
+  const uint32_t lane = threadIdx.x & 63, lead = (uint32_t)__ffsll((long long)m) - 1;
+  const uint32_t slot = spread_slot();
+  uint32_t base = 0;
+  if (lane == lead) base = atomicAdd(a.q_count + slot, (unsigned int)__popcll(m));
+  base = __shfl(base, lead, 64);
+  if (!want) return true;
+  const uint32_t q = base + (uint32_t)__popcll(m & __lanemask_lt());
+  if (q >= a.qcap) return false;
+  a.q[(uint64_t)slot * a.qcap + q] = make_uint4(i, j, u, 0u);
+  return true;
+}
+
 // Per-lane vote tallies of one station; [lo, hi) is that station's id range
 // (looked up again only when a pair falls outside it).
 struct PairTally {
@@ -303,8 +331,8 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
   }
   ++tl.ev;
   if (FAST) {
-    if (rx.any_equal(rv) && !lower_in_group(a, u, i, j, rl, ry) && upper_in_group(a, u, i, j, rl, ry))
-      exact_and_report(a, u, i, j);
+    const bool cand = rx.any_equal(rv);
+    if (a.qcap ? !enqueue_candidate(a, cand, u, i, j) : cand) check_candidate(a, u, i, j, rl, ry);
     return;
   }
   const uint32_t eq = rx.eq(ro, rsw);
@@ -877,6 +905,73 @@ __global__ __launch_bounds__(kPT) void k_part_merge(uint8_t* ex, uint8_t* fp, ui
   }
 }
 
+// check_candidate for rows held in registers (RSW dwords each, read from
+// memory once): the fields with equal sub-keys are found in one pass, then
+// those below u's field and those above it are settled by exact key checks.
+template <int RSW>
+__device__ __forceinline__ void check_candidate_regs(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
+                                                     const uint32_t (&ri)[RSW], const uint32_t (&rj)[RSW]) {
+  constexpr int kC = (RSW + 15) / 16;  // chunks of 32 fields
+  const uint32_t g = u / a.tables_per_group, own = u - g * a.tables_per_group;
+  const uint32_t tb = g * a.tables_per_group;
+  const uint32_t fields = min(a.tables_per_group, a.t - tb);
+  uint32_t lo[kC], hi[kC];
+#pragma unroll
+  for (int c = 0; c < kC; ++c) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int d = 0; d < 16; ++d) {
+      const int k = c * 16 + d;
+      if (k < RSW) {
+        const uint32_t x = ri[k] ^ rj[k];
+        m |= ((x & 0xFFFFu) == 0 ? 1u : 0u) << (2 * d);
+        m |= ((x >> 16) == 0 ? 1u : 0u) << (2 * d + 1);
+      }
+    }
+    const uint32_t f0 = 32u * c;
+    const uint32_t nf = fields > f0 ? min(32u, fields - f0) : 0u;  // fields of the group in this chunk
+    m &= nf == 32 ? 0xFFFFFFFFu : (1u << nf) - 1u;
+    const uint32_t below = own <= f0 ? 0u : (own - f0 >= 32 ? 0xFFFFFFFFu : (1u << (own - f0)) - 1u);
+    const uint32_t upto = own < f0 ? 0u : (own - f0 >= 31 ? 0xFFFFFFFFu : (2u << (own - f0)) - 1u);
+    lo[c] = m & below;
+    hi[c] = m & ~upto;
+  }
+#pragma unroll
+  for (int c = 0; c < kC; ++c)
+    if (lo[c] && count_shared(a, lo[c], tb + 32u * c, i, j, 1) != 0) return;  // a lower table shares
+#pragma unroll
+  for (int c = 0; c < kC; ++c)
+    if (hi[c] && count_shared(a, hi[c], tb + 32u * c, i, j, 1) != 0) {
+      exact_and_report(a, u, i, j);
+      return;
+    }
+}
+
+// The queued candidates of spread slot blockIdx.x, one lane per pair (the
+// slot's entries split over kCheckSplit workgroups), each pair's two rows
+// read from memory once.
+constexpr uint32_t kCheckSplit = 4;
+template <int RSW>
+__global__ __launch_bounds__(kPT) void k_check_queue(PairArgs a) {
+  const uint32_t slot = blockIdx.x;
+  const uint32_t cnt = min(a.q_count[slot], a.qcap);
+  const uint4* q = a.q + (uint64_t)slot * a.qcap;
+  for (uint32_t e = blockIdx.y * kPT + threadIdx.x; e < cnt; e += kCheckSplit * kPT) {
+    const uint4 c = q[e];
+    const uint32_t g = c.z / a.tables_per_group;
+    const uint32_t* R = a.rows + (uint64_t)g * a.n * a.row_pitch;
+    const uint32_t* pi = R + (uint64_t)c.x * a.row_pitch;
+    const uint32_t* pj = R + (uint64_t)c.y * a.row_pitch;
+    uint32_t ri[RSW], rj[RSW];
+#pragma unroll
+    for (int k = 0; k < RSW; ++k) {
+      ri[k] = pi[k];
+      rj[k] = pj[k];
+    }
+    check_candidate_regs<RSW>(a, c.z, c.x, c.y, ri, rj);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
@@ -927,6 +1022,21 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
       hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
       break;
   }
+}
+
+bool pair_launch_queues(const PairArgs& a) {
+  return a.qcap != 0 && fast_test(a) && (a.row_dw == 10 || a.row_dw == 17 || a.row_dw == 50);
+}
+
+void launch_check_queue(const PairArgs& a, hipStream_t s) {
+  if (!pair_launch_queues(a)) return;
+  const dim3 grid(kSpread, kCheckSplit);
+  switch (a.row_dw) {
+    case 10: hipLaunchKernelGGL(k_check_queue<10>, grid, dim3(kPT), 0, s, a); break;
+    case 17: hipLaunchKernelGGL(k_check_queue<17>, grid, dim3(kPT), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_check_queue<50>, grid, dim3(kPT), 0, s, a); break;  // 50 (pair_launch_queues)
+  }
+  fill_u32(a.q_count, kSpread, 0, s);  // the queue is empty again
 }
 
 void launch_tile_counts(const uint4* big, uint32_t nbig, uint32_t tb, uint64_t* tiles, unsigned long long* work,

@@ -147,6 +147,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
   fill_u8(reinterpret_cast<uint8_t*>(j.ctrl), sizeof(Ctrl), 0, s);
   fill_u8(reinterpret_cast<uint8_t*>(j.er), j.spread_bytes, 0, s);
   fill_u8(j.flags, j.N, 0, s);
+  if (j.pa.qcap) fill_u32(j.pa.q_count, kSpread, 0, s);
   LAUNCHCK();
 
   // 1. signatures -> mixed keys (table-major) and sub-key rows, per station
@@ -254,6 +255,40 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
   launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, j.ba.small_max, s);
   pe();
   LAUNCHCK();
+  if (pair_launch_queues(j.pa)) {
+    pb(FAST_LSH_STAGE_PAIR_CHECKS);
+    launch_check_queue(j.pa, s);
+    pe();
+    LAUNCHCK();
+  }
+  return FAST_LSH_OK;
+}
+
+// The candidate queue of the pair kernels' need == 2 form: N / 64 entries
+// per spread slot, between 64 and 16,384 (about twice what one launch of a
+// 5-year station queues per slot; a pair that finds its slot full is checked
+// in place).
+int alloc_queue(fast_lsh_ctx* c, uint64_t N, PairArgs* pa) {
+  const uint32_t qcap = (uint32_t)std::min<uint64_t>(16384, std::max<uint64_t>(64, N / 64));
+  uint4* q;
+  unsigned int* cnt;
+  RC(ws<uint4>(c, "cand_queue", (uint64_t)kSpread * qcap, &q));
+  RC(ws<unsigned int>(c, "cand_count", kSpread, &cnt));
+  if (pa) {
+    pa->q = q;
+    pa->q_count = cnt;
+    pa->qcap = qcap;
+  }
+  return FAST_LSH_OK;
+}
+
+// The exact checks of what a pair launch queued (they also empty the queue).
+int pair_checks(fast_lsh_ctx* c, const PairArgs& a) {
+  if (!pair_launch_queues(a)) return FAST_LSH_OK;
+  prof_begin(c, FAST_LSH_STAGE_PAIR_CHECKS);
+  launch_check_queue(a, c->stream);
+  prof_end(c);
+  LAUNCHCK();
   return FAST_LSH_OK;
 }
 
@@ -282,16 +317,18 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count, const PairArgs& a
   RC(ws<uint32_t>(c, "big_owner", units + 1, &owner));
   launch_unit_owner(toff, big_count, owner, s);
   LAUNCHCK();
-  // at most 2^22 workgroups of 256 threads per launch (work-items per grid
-  // dimension stay below 2^32)
+  // at most 2^21 workgroups of 256 threads per launch (work-items per grid
+  // dimension stay below 2^32, and one launch's queued candidates mostly fit
+  // the queue)
   PairArgs pa = args;
   pa.big_voted = work;
-  for (uint64_t u0 = 0; u0 < units; u0 += 1u << 22) {
-    const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 22, units - u0);
+  for (uint64_t u0 = 0; u0 < units; u0 += 1u << 21) {
+    const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 21, units - u0);
     prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
     launch_pairs_tile(pa, toff, owner, u0, cnt, j.bdesc, tb, j.rswl, s);
     prof_end(c);
     LAUNCHCK();
+    RC(pair_checks(c, pa));
   }
   return FAST_LSH_OK;
 }
@@ -422,6 +459,7 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
     launch_pairs_wave(m, j.marks, j.t, j.rswl, j.ba.small_max, s);
     prof_end(c);
     LAUNCHCK();
+    RC(pair_checks(c, m));
     return run_big_pairs(c, j, big_count, m, work);
   };
   auto count_from = [&](const PairArgs& base, uint32_t p) -> int {
@@ -613,6 +651,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   pa.station_base = j.sbase;
   pa.nstation = S;
   pa.n_flagged = &j.ctrl->n_flagged;
+  RC(alloc_queue(c, N, &pa));
   RC(set_out_buffers(c, j, out_cap));
 
   // launch shapes: fixed, or tuned once per shape
@@ -704,6 +743,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
       launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, j.ba.small_max, s);
       prof_end(c);
       LAUNCHCK();
+      RC(pair_checks(c, j.pa));
     }
     RC(run_big_pairs(c, j, hc.big_count, j.pa, j.work));
     RC(d2h(c, &hc, j.ctrl));
@@ -796,6 +836,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   RC(ws<uint8_t>(c, "marks", gn, &j.marks));
   j.bigbin_grid = (uint32_t)std::min<uint64_t>(cap_bin, 512);
   j.rswl = j.pl.row_dw | 1u;
+  RC(alloc_queue(c, N, nullptr));  // before the keep budget counts free memory
   // Groups whose grouping pass 1 keeps for pass 2: at most keep_groups, as
   // many as the free HBM (less a margin) and the budget hold, counting what
   // earlier calls left allocated under these names.
@@ -889,6 +930,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   pa.station_base = j.sbase;
   pa.nstation = 1;
   pa.n_flagged = &j.ctrl->n_flagged;
+  RC(alloc_queue(c, N, &pa));
   uint32_t variant = 0;
   for (uint32_t v = 0; v < kRadixTileVariants; ++v)
     if (radix_tile_elems(v) == c->config.radix_tile) variant = v;
@@ -985,6 +1027,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
     fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * kSpread * sizeof(unsigned long long), 0, s);
     fill_u64(reinterpret_cast<uint64_t*>(j.work), 3 * kSpread, 0, s);
     fill_u32(&j.ctrl->out_count, 1, 0, s);
+    fill_u32(j.pa.q_count, kSpread, 0, s);
     for (uint32_t g = 0; g < ngroups; ++g) {
       const uint32_t tb = g * TGm, tc = std::min(TGm, t - tb);
       if (g < kept) {  // pass 1's grouping of this group, with the final flags
@@ -994,6 +1037,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
         launch_pairs_wave(j.pa, keep_marks + (uint64_t)g * gn, tc, j.rswl, ba.small_max, s);
         prof_end(c);
         LAUNCHCK();
+        RC(pair_checks(c, j.pa));
         uint4* shared_desc = j.bdesc;
         j.bdesc = keep_desc + (uint64_t)g * cap_big;
         const int rc = run_big_pairs(c, j, kept_big[g], j.pa, j.work);
@@ -1009,6 +1053,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
       launch_pairs_wave(j.pa, j.marks, tc, j.rswl, j.ba.small_max, s);
       prof_end(c);
       LAUNCHCK();
+      RC(pair_checks(c, j.pa));
       RC(d2h(c, &hc, j.ctrl));
       RC(run_big_pairs(c, j, hc.big_count, j.pa, j.work));
     }

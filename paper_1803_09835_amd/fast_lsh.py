@@ -42,7 +42,7 @@ class _Stats(ctypes.Structure):
 
 
 PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pairs", "output", "graph", "split_keys",
-                  "channel_merge", "clusters", "fingerprints", "spectrogram")
+                  "channel_merge", "clusters", "fingerprints", "spectrogram", "pair_checks")
 
 
 class Config(ctypes.Structure):
