@@ -262,18 +262,31 @@ int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, ui
  *                 those groups again.  FAST_LSH_KEEP_AUTO: as many as the
  *                 free HBM (less a margin of 4 GiB and 2 %) and the
  *                 context's budget hold; 0: none.  fast_lsh_config_used
- *                 reports the number the last bounded search kept. */
+ *                 reports the number the last bounded search kept;
+ *   queue_slot    pair kernels of the need == 2 form (min_votes v split
+ *                 over v - 1 table groups, need = 2): a pair whose sub-keys
+ *                 pass the group test is queued, up to queue_slot entries
+ *                 per spread slot (16 bytes each, 1024 slots), and a later
+ *                 launch gives the queued pairs their exact key checks one
+ *                 lane per pair; a workgroup whose slot fills up runs again
+ *                 with the checks in place (fast_lsh_work.pair_redos).
+ *                 0: automatic (n / 64, between 64 and 16384);
+ *                 FAST_LSH_QUEUE_OFF: no queue, checks in place; at most
+ *                 2^20.  Any value gives the same result.
+ *                 fast_lsh_config_used reports the last search's size. */
 #define FAST_LSH_KEEP_AUTO 0xFFFFFFFFu
+#define FAST_LSH_QUEUE_OFF 0xFFFFFFFFu
 typedef struct {
   uint32_t radix_tile;
   uint32_t bucket_chunk;
   uint32_t autotune;
   uint32_t bin_bits;
   uint32_t keep_groups;
+  uint32_t queue_slot;
 } fast_lsh_config;
 
 /* Set the launch shapes of later searches (defaults: 16384, 512, no
- * autotune, automatic bin bits, FAST_LSH_KEEP_AUTO).  E_INVALID for a value
+ * autotune, automatic bin bits, FAST_LSH_KEEP_AUTO, automatic queue).  E_INVALID for a value
  * outside the lists above. */
 int fast_lsh_configure(fast_lsh_ctx *ctx, const fast_lsh_config *config);
 
@@ -416,9 +429,11 @@ int fast_lsh_profile_read(fast_lsh_ctx *ctx, fast_lsh_profile *out);
  * their sizes m and big_candidates their in-bucket pairs C(m, 2) (over every
  * table; part of e_raw); big_voted counts those pairs that pass the lag and
  * the exclusion (part of e_voted).  search_calls counts the searches
- * completed on the context.  Zero before the first search. */
+ * completed on the context; pair_redos the second runs of pair launches
+ * (workgroups whose candidate queue slot filled up) in the last search.
+ * Zero before the first search. */
 typedef struct {
-  uint64_t big_voted, big_members, big_candidates, search_calls;
+  uint64_t big_voted, big_members, big_candidates, search_calls, pair_redos;
 } fast_lsh_work;
 
 int fast_lsh_last_work(fast_lsh_ctx *ctx, fast_lsh_work *out);

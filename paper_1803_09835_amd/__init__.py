@@ -10,10 +10,10 @@ of include/fast_lsh.h.  This package is the thin
 Python binding over that library.
 """
 from .fast_lsh import (CLUSTER_DTYPE, E_BUSY, E_CAPACITY, E_DEVICE, E_INVALID, E_NOMEM, KEEP_AUTO, MINHASH, MINMAX,
-                       OK, FastLSH, FastLshError, Server, Stats, library, make_hash, n_funcs, plan_batch,
+                       OK, QUEUE_OFF, FastLSH, FastLshError, Server, Stats, library, make_hash, n_funcs, plan_batch,
                        to_device_rows)
 
 __all__ = ["CLUSTER_DTYPE", "E_BUSY", "E_CAPACITY", "E_DEVICE", "E_INVALID", "E_NOMEM", "KEEP_AUTO", "MINHASH",
-           "MINMAX", "OK",
+           "MINMAX", "OK", "QUEUE_OFF",
            "FastLSH", "FastLshError", "Server", "Stats", "library", "make_hash", "n_funcs", "plan_batch",
            "to_device_rows"]

@@ -248,6 +248,7 @@ int fast_lsh_ctx_create(int device, void* hip_stream, uint64_t hbm_budget, fast_
   c->config.autotune = 0;
   c->config.bin_bits = 0;
   c->config.keep_groups = FAST_LSH_KEEP_AUTO;
+  c->config.queue_slot = 0;
   *out = c;
   g_err.clear();
   return FAST_LSH_OK;
@@ -358,11 +359,14 @@ int fast_lsh_configure(fast_lsh_ctx* c, const fast_lsh_config* cfg) {
   if (cfg->autotune > 1) return fl_fail(FAST_LSH_E_INVALID, "autotune must be 0 or 1");
   if (cfg->bin_bits % 8 || cfg->bin_bits > 32)
     return fl_fail(FAST_LSH_E_INVALID, "bin_bits %u is not 0, 8, 16, 24 or 32", cfg->bin_bits);
+  if (cfg->queue_slot != FAST_LSH_QUEUE_OFF && cfg->queue_slot > (1u << 20))
+    return fl_fail(FAST_LSH_E_INVALID, "queue_slot %u is above 2^20", cfg->queue_slot);
   c->config.radix_tile = tile;
   c->config.bucket_chunk = chunk;
   c->config.autotune = cfg->autotune;
   c->config.bin_bits = cfg->bin_bits;
   c->config.keep_groups = cfg->keep_groups;
+  c->config.queue_slot = cfg->queue_slot;
   return FAST_LSH_OK;
 }
 
@@ -373,6 +377,7 @@ int fast_lsh_config_used(fast_lsh_ctx* c, fast_lsh_config* out) {
   out->autotune = c->config.autotune;
   out->bin_bits = c->last_bin_bits;
   out->keep_groups = c->last_kept;
+  out->queue_slot = c->last_qcap;
   return FAST_LSH_OK;
 }
 

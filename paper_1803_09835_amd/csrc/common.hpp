@@ -229,13 +229,21 @@ struct PairArgs {
   const uint8_t* fp;
   uint8_t* ex_next;
   // Candidate queue of the need == 2 form: a pair that passes the sub-key
-  // group test is appended as (i, j, table) to its workgroup's spread slot,
-  // q[slot][0, qcap), and given its exact checks by a later launch with one
-  // lane per pair, instead of stalling its wavefront on them; a pair that
-  // finds the slot full is checked in place.  qcap == 0: all in place.
+  // group test is appended as (i, j, table, chunk) to its workgroup's
+  // spread slot, q[slot][0, qcap), and given its exact checks by a later
+  // launch with one lane per pair, instead of stalling its wavefront on
+  // them.  The chunk is the small-bucket kernel's 64 positions of a table
+  // (segment * nchunk + chunk) or the tiled kernel's unit.  A pair that
+  // finds its slot full sets q_ovf[chunk] and *q_any; the checks skip the
+  // chunk's entries and the host runs the launch again with redo set (only
+  // the marked chunks work, checks in place, no vote tallies).  qcap == 0:
+  // checks in place.
   uint4* q;
   unsigned int* q_count;  // [kSpread] appends per slot (may pass qcap)
   uint32_t qcap;
+  uint8_t* q_ovf;         // per chunk of the launch
+  unsigned int* q_any;
+  uint32_t redo;
 };
 
 // Station of a (global) fingerprint id, for nb stations with ascending bases.

@@ -124,6 +124,8 @@ struct fast_lsh_ctx {
   TuneChoice last_choice;
   uint32_t last_bin_bits = 0;  // bin bits of the last search
   uint32_t last_kept = 0;      // table groups the last bounded search kept for its pass 2
+  uint32_t last_qcap = 0;      // candidate queue entries per slot of the last search (FAST_LSH_QUEUE_OFF: none)
+  uint64_t pair_redos = 0;     // second pair runs of the current search
   // captured search prefix
   hipGraphExec_t graph = nullptr;
   std::vector<uint64_t> graph_key;

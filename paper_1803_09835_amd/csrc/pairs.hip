@@ -161,10 +161,11 @@ __device__ __forceinline__ void check_candidate(const PairArgs& a, uint32_t u, u
   if (!lower_in_group(a, u, i, j, rl, rr) && upper_in_group(a, u, i, j, rl, rr)) exact_and_report(a, u, i, j);
 }
 
-// Appends the calling lane's candidate (want) to the queue of the
-// workgroup's spread slot: one atomic per wavefront for all its active
-// lanes that want to.  False when the slot is full (check it in place).
-__device__ __forceinline__ bool enqueue_candidate(const PairArgs& a, bool want, uint32_t u, uint32_t i, uint32_t j) {
+// Appends the calling lane's candidate (want) of workgroup blk to the queue
+// of the workgroup's spread slot: one atomic per wavefront for all its
+// active lanes that want to.  False when the slot is full.
+__device__ __forceinline__ bool enqueue_candidate(const PairArgs& a, bool want, uint32_t u, uint32_t i, uint32_t j,
+                                                  uint32_t blk) {
   const uint64_t m = __ballot(want);
   if (m == 0) return true;
   const uint32_t lane = threadIdx.x & 63, lead = (uint32_t)__ffsll((long long)m) - 1;
@@ -175,7 +176,7 @@ __device__ __forceinline__ bool enqueue_candidate(const PairArgs& a, bool want, 
   if (!want) return true;
   const uint32_t q = base + (uint32_t)__popcll(m & __lanemask_lt());
   if (q >= a.qcap) return false;
-  a.q[(uint64_t)slot * a.qcap + q] = make_uint4(i, j, u, 0u);
+  a.q[(uint64_t)slot * a.qcap + q] = make_uint4(i, j, u, blk);
   return true;
 }
 
@@ -185,6 +186,7 @@ struct PairTally {
   unsigned long long ev, nd;
   uint32_t station;
   uint32_t lo, hi;
+  uint32_t blk = 0;  // the lane's chunk (tiled: unit), for the candidate queue
 };
 
 constexpr uint32_t kDead = 0xFFFFFFFFu;  // member excluded by the occurrence filter
@@ -285,8 +287,9 @@ struct RowReg {
 // one (in LDS).
 // FAST (need == 2, no distinct count, rx from load_masked): the group test
 // is "some other table of the group shares a bucket", decided without
-// counting; otherwise the equal fields are counted.
-template <int RSW, bool FAST>
+// counting; otherwise the equal fields are counted.  QUEUE (FAST only): a
+// pair that passes the group test goes to the candidate queue.
+template <int RSW, bool FAST, bool QUEUE>
 __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32_t i, uint32_t j,
                                            const RowReg<RSW>& rx, const uint32_t* rl, const uint32_t* ry,
                                            const uint32_t* ro, uint32_t rsw, uint32_t pad, PairTally& tl) {
@@ -332,7 +335,15 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
   ++tl.ev;
   if (FAST) {
     const bool cand = rx.any_equal(rv);
-    if (a.qcap ? !enqueue_candidate(a, cand, u, i, j) : cand) check_candidate(a, u, i, j, rl, ry);
+    if (QUEUE) {
+      // (no checks in place here: they would cost the loop registers)
+      if (!enqueue_candidate(a, cand, u, i, j, tl.blk)) {
+        a.q_ovf[tl.blk] = 1;
+        *a.q_any = 1;
+      }
+    } else if (cand) {
+      check_candidate(a, u, i, j, rl, ry);
+    }
     return;
   }
   const uint32_t eq = rx.eq(ro, rsw);
@@ -449,7 +460,7 @@ __device__ __forceinline__ uint32_t group_pad(const PairArgs& a, uint32_t u, uin
 // (row-major within each bucket) with the left row in registers.  Heads and
 // pair offsets come from ballots and lane shuffles, so the only barriers are
 // the LDS hand-offs of a single wave.
-template <int RSW, bool FAST>
+template <int RSW, bool FAST, bool QUEUE>
 __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* marks_all, uint32_t rswl,
                                                    uint32_t nchunk, uint32_t span) {
   // span = 64 + small_max - 1: heads in 64 positions, members up to small_max
@@ -488,6 +499,8 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
   for (; c < nchunk; c += gridDim.x) {
     const uint32_t size = nsize, id0 = nid0, id1 = nid1;
     if (c + gridDim.x < nchunk) fetch(c + gridDim.x);
+    tl.blk = seg * nchunk + c;  // (the host keeps S * nchunk below 2^32 when queueing)
+    if (a.redo && !a.q_ovf[tl.blk]) continue;  // a second run takes the marked chunks only
     const uint64_t heads = __ballot(size != 0);
     if (heads == 0) continue;
     __syncthreads();  // the previous chunk's LDS reads are complete
@@ -558,7 +571,7 @@ __global__ __launch_bounds__(64) void k_pairs_wave(PairArgs a, const uint8_t* ma
       const uint32_t* ry = lrows + (base + y) * rswl;  // stepped with y (no multiply per pair)
       if (FAST) rx.load_masked(rl, own, valid); else rx.load(rl, rsw);
       for (; p < pend; ++p) {
-        visit_pair<RSW, FAST>(a, u, idx, lids[base + y], rx, rl, ry, ry, rsw, pad, tl);
+        visit_pair<RSW, FAST, QUEUE>(a, u, idx, lids[base + y], rx, rl, ry, ry, rsw, pad, tl);
         ry += rswl;
         if (++y == m) {
           if (++x == m - 1) {
@@ -635,7 +648,7 @@ __global__ __launch_bounds__(kPT) void k_unit_owner(const uint64_t* toff, uint32
 // One tile (ta, tb) of the upper triangle of a large bucket's pair matrix.
 // Workgroup unit_base + blockIdx.x takes bucket owner[unit] (whose tile range
 // [toff[b], toff[b+1]) holds the unit) and within it the tile of that rank.
-template <int RSW, bool FAST>
+template <int RSW, bool FAST, bool QUEUE>
 __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* toff, const uint32_t* owner,
                                                     uint64_t unit_base, const uint4* big, uint32_t tb_size,
                                                     uint32_t rswl) {
@@ -643,6 +656,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
   // (units stay in launch order across the XCDs: contiguous unit ranges per
   // XCD balance badly, tiles of a range differing widely in cost)
   const uint64_t unit = unit_base + blockIdx.x;
+  if (a.redo && !a.q_ovf[unit]) return;  // a second run takes the marked units only
   const uint32_t bk = owner[unit];
   const uint4 d = big[bk];  // {position, segment, members}
   const uint32_t m = d.z;
@@ -683,6 +697,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
   __syncthreads();
   const uint32_t pad = group_pad(a, u, rsw);
   PairTally tl{0ull, 0ull, 0u, 0u, 0u};
+  tl.blk = (uint32_t)unit;
   const uint32_t own = u % a.tables_per_group, valid = row_fields(rsw) - pad;
   if (!diag && tb_size == kPT / 2 && na > kPT / 4 && nbm >= 16) {
     // Full tiles off the diagonal: thread t holds left row t mod tb_size in
@@ -698,7 +713,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       const uint32_t* rowx = rowsA + xs * rswl;
       const uint32_t* rowy = rowsB + y0 * rswl;  // stepped with y (no multiply per pair)
       for (uint32_t y = y0; y < nbm; y += 2, rowy += 2 * rswl)
-        if (live) visit_pair<RSW, FAST>(a, u, idx, idsB[y], rx, rowx, rowy, rowy, rsw, pad, tl);
+        if (live) visit_pair<RSW, FAST, QUEUE>(a, u, idx, idsB[y], rx, rowx, rowy, rowy, rsw, pad, tl);
     }
   } else if (diag && tb_size == kPT / 2) {
     // Diagonal tiles: the pairs {x, (x + k) mod na} for k = 1 .. na / 2 are
@@ -725,7 +740,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
         if (live && !(2 * k == na && x >= k)) {
           const uint32_t idy = idsA[y];
           const bool fw = y > x;  // selects, not branches: one inlined visit per lane
-          visit_pair<RSW, FAST>(a, u, fw ? idx : idy, fw ? idy : idx, rx, fw ? rowx : rowy, fw ? rowy : rowx, rowy,
+          visit_pair<RSW, FAST, QUEUE>(a, u, fw ? idx : idy, fw ? idy : idx, rx, fw ? rowx : rowy, fw ? rowy : rowx, rowy,
                                 rsw, pad, tl);
         }
         // next round: two rows on, wrapping past na (selects, no branch)
@@ -758,7 +773,7 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       RowReg<RSW> rx;
       if (FAST) rx.load_masked(rl, own, valid); else rx.load(rl, rsw);
       for (; p < pend; ++p) {
-        visit_pair<RSW, FAST>(a, u, idx, idsB[y], rx, rl, ry, ry, rsw, pad, tl);
+        visit_pair<RSW, FAST, QUEUE>(a, u, idx, idsB[y], rx, rl, ry, ry, rsw, pad, tl);
         ry += rswl;
         if (++y == nbm) {
           ++x;
@@ -958,6 +973,7 @@ __global__ __launch_bounds__(kPT) void k_check_queue(PairArgs a) {
   const uint4* q = a.q + (uint64_t)slot * a.qcap;
   for (uint32_t e = blockIdx.y * kPT + threadIdx.x; e < cnt; e += kCheckSplit * kPT) {
     const uint4 c = q[e];
+    if (a.q_ovf[c.w]) continue;  // its workgroup runs again with the checks in place
     const uint32_t g = c.z / a.tables_per_group;
     const uint32_t* R = a.rows + (uint64_t)g * a.n * a.row_pitch;
     const uint32_t* pi = R + (uint64_t)c.x * a.row_pitch;
@@ -1005,23 +1021,18 @@ void launch_pairs_wave(const PairArgs& a, const uint8_t* marks, uint32_t S, uint
   const uint32_t per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(kPairWavesPerCU, (160u << 10) / smem));
   const uint32_t per_seg = std::max<uint32_t>(1u, std::min<uint32_t>(nchunk, per_cu * device_cus() / S));
   const dim3 grid(per_seg, S);
+  const bool fast = fast_test(a), queue = fast && a.qcap != 0;
+#define FL_WAVE(R, F, Q) \
+  hipLaunchKernelGGL((k_pairs_wave<R, F, Q>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span)
   switch (a.row_dw) {
-    case 10:
-      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<10, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
-      else hipLaunchKernelGGL((k_pairs_wave<10, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
-      break;
-    case 17:
-      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<17, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
-      else hipLaunchKernelGGL((k_pairs_wave<17, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
-      break;
+    case 10: if (queue) FL_WAVE(10, true, true); else if (fast) FL_WAVE(10, true, false); else FL_WAVE(10, false, false); break;
+    case 17: if (queue) FL_WAVE(17, true, true); else if (fast) FL_WAVE(17, true, false); else FL_WAVE(17, false, false); break;
     case 50:  // one group of 100 tables
-      if (fast_test(a)) hipLaunchKernelGGL((k_pairs_wave<50, true>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
-      else hipLaunchKernelGGL((k_pairs_wave<50, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
+      if (queue) FL_WAVE(50, true, true); else if (fast) FL_WAVE(50, true, false); else FL_WAVE(50, false, false);
       break;
-    default:
-      hipLaunchKernelGGL((k_pairs_wave<0, false>), grid, dim3(64), smem, s, a, marks, rswl, nchunk, span);
-      break;
+    default: FL_WAVE(0, false, false); break;
   }
+#undef FL_WAVE
 }
 
 bool pair_launch_queues(const PairArgs& a) {
@@ -1069,14 +1080,15 @@ void launch_pairs_tile(const PairArgs& a, const uint64_t* toff, const uint32_t* 
                        const uint4* big, uint32_t tb_size, uint32_t rswl, hipStream_t s) {
   if (nunits == 0) return;
   const size_t smem = (size_t)tb_size * rswl * 8 + (size_t)tb_size * 8;
-#define FL_TILE(R, F)                                                                                        \
-  hipLaunchKernelGGL((k_pairs_tile<R, F>), dim3(nunits), dim3(kPT), smem, s, a, toff, owner, unit_base, big, tb_size, \
-                     rswl)
+  const bool fast = fast_test(a), queue = fast && a.qcap != 0;
+#define FL_TILE(R, F, Q)                                                                                        \
+  hipLaunchKernelGGL((k_pairs_tile<R, F, Q>), dim3(nunits), dim3(kPT), smem, s, a, toff, owner, unit_base, big, \
+                     tb_size, rswl)
   switch (a.row_dw) {
-    case 10: if (fast_test(a)) FL_TILE(10, true); else FL_TILE(10, false); break;
-    case 17: if (fast_test(a)) FL_TILE(17, true); else FL_TILE(17, false); break;
-    case 50: if (fast_test(a)) FL_TILE(50, true); else FL_TILE(50, false); break;
-    default: FL_TILE(0, false); break;
+    case 10: if (queue) FL_TILE(10, true, true); else if (fast) FL_TILE(10, true, false); else FL_TILE(10, false, false); break;
+    case 17: if (queue) FL_TILE(17, true, true); else if (fast) FL_TILE(17, true, false); else FL_TILE(17, false, false); break;
+    case 50: if (queue) FL_TILE(50, true, true); else if (fast) FL_TILE(50, true, false); else FL_TILE(50, false, false); break;
+    default: FL_TILE(0, false, false); break;
   }
 #undef FL_TILE
 }

@@ -105,6 +105,7 @@ struct Job {
   uint64_t spread_bytes;
   unsigned long long* work;  // [3][kSpread]: tiled buckets' voted pairs, members, in-bucket pairs
   uint32_t rswl;
+  unsigned long long* redo_tally = nullptr;  // votes of second pair runs, discarded
   uint32_t parts = 0;  // > 0: partitioned search with the dynamic occurrence filter (no pair launch in the prefix)
   BucketArgs ba;
   PairArgs pa;
@@ -132,6 +133,8 @@ int time_launch(hipStream_t s, P&& setup, F&& f, float* ms) {
   if (le != hipSuccess) return fl_fail(FAST_LSH_E_DEVICE, "kernel launch while tuning: %s", hipGetErrorString(le));
   return FAST_LSH_OK;
 }
+
+void wave_marks_clear(const PairArgs& a, uint32_t S, hipStream_t s);
 
 // Enqueue the fixed-shape prefix on stream s.  With `tune`, the first radix
 // pass and the bucket kernel are run once per candidate shape (each run
@@ -251,6 +254,7 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
   // 4. pairs of small buckets
   j.pa.order = j.sorted_v;
   if (j.parts) return FAST_LSH_OK;  // the partitioned search launches its own pair passes
+  wave_marks_clear(j.pa, j.t, s);
   pb(FAST_LSH_STAGE_PAIRS);
   launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, j.ba.small_max, s);
   pe();
@@ -268,17 +272,67 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
 // per spread slot, between 64 and 16,384 (about twice what one launch of a
 // 5-year station queues per slot; a pair that finds its slot full is checked
 // in place).
-int alloc_queue(fast_lsh_ctx* c, uint64_t N, PairArgs* pa) {
-  const uint32_t qcap = (uint32_t)std::min<uint64_t>(16384, std::max<uint64_t>(64, N / 64));
+int alloc_queue(fast_lsh_ctx* c, uint64_t N, uint32_t S, uint32_t T, Job* j) {
+  const uint32_t cfg = c->config.queue_slot;
+  uint32_t qcap = cfg == FAST_LSH_QUEUE_OFF ? 0u
+                  : cfg ? cfg : (uint32_t)std::min<uint64_t>(16384, std::max<uint64_t>(64, N / 64));
+  if ((uint64_t)T * ((N + 63) / 64) >= (1ull << 32)) qcap = 0;  // queue entries name their chunk in 32 bits
+  c->last_qcap = qcap ? qcap : FAST_LSH_QUEUE_OFF;
+  c->pair_redos = 0;
   uint4* q;
-  unsigned int* cnt;
-  RC(ws<uint4>(c, "cand_queue", (uint64_t)kSpread * qcap, &q));
-  RC(ws<unsigned int>(c, "cand_count", kSpread, &cnt));
-  if (pa) {
-    pa->q = q;
-    pa->q_count = cnt;
-    pa->qcap = qcap;
+  unsigned int *cnt, *any;
+  uint8_t* ovf;
+  unsigned long long* tally;
+  RC(ws<uint4>(c, "cand_queue", (uint64_t)kSpread * std::max(qcap, 1u), &q));
+  RC(ws<unsigned int>(c, "cand_count", kSpread + 1, &cnt));
+  any = cnt + kSpread;
+  // overflow marks of a small-bucket launch: one per 64 positions of a table
+  const uint64_t marks = (uint64_t)T * ((N + 63) / 64);
+  RC(ws<uint8_t>(c, "cand_ovf_wave", std::max<uint64_t>(marks, 1), &ovf));
+  RC(ws<unsigned long long>(c, "redo_tally", 2ull * S * kSpread, &tally));
+  if (j) {
+    j->pa.q = q;
+    j->pa.q_count = cnt;
+    j->pa.qcap = qcap;
+    j->pa.q_any = any;
+    j->pa.q_ovf = ovf;  // small-bucket launches; the tiled ones bring their own marks
+    j->redo_tally = tally;
   }
+  return FAST_LSH_OK;
+}
+
+// A second run of a pair launch's marked workgroups (checks in place, the
+// votes already counted by the first run).
+PairArgs redo_args(const Job& j, const PairArgs& a) {
+  PairArgs r = a;
+  r.redo = 1;
+  r.qcap = 0;
+  r.e_voted = j.redo_tally;
+  r.n_distinct = j.redo_tally + (uint64_t)a.nstation * kSpread;
+  r.big_voted = nullptr;
+  return r;
+}
+
+// Before a small-bucket pair launch of S tables that queues: no chunk marked.
+void wave_marks_clear(const PairArgs& a, uint32_t S, hipStream_t s) {
+  if (!pair_launch_queues(a)) return;
+  fill_u8(a.q_ovf, (uint64_t)S * ((a.n + 63) / 64), 0, s);
+  fill_u32(a.q_any, 1, 0, s);
+}
+
+// After a small-bucket pair launch and its checks: the chunks that found
+// their queue slot full run again (synchronises when the launch queued).
+int wave_settle(fast_lsh_ctx* c, const Job& j, const PairArgs& a, const uint8_t* marks, uint32_t S,
+                uint32_t small_max) {
+  if (!pair_launch_queues(a)) return FAST_LSH_OK;
+  unsigned int any = 0;
+  RC(d2h(c, &any, a.q_any));
+  if (!any) return FAST_LSH_OK;
+  ++c->pair_redos;
+  prof_begin(c, FAST_LSH_STAGE_PAIRS);
+  launch_pairs_wave(redo_args(j, a), marks, S, j.rswl, small_max, c->stream);
+  prof_end(c);
+  LAUNCHCK();
   return FAST_LSH_OK;
 }
 
@@ -290,6 +344,18 @@ int pair_checks(fast_lsh_ctx* c, const PairArgs& a) {
   prof_end(c);
   LAUNCHCK();
   return FAST_LSH_OK;
+}
+
+// One small-bucket pair pass: the launch, its queued checks and the second
+// run of chunks that found their queue slot full.
+int wave_pass(fast_lsh_ctx* c, const Job& j, const PairArgs& a, const uint8_t* marks, uint32_t S, uint32_t small_max) {
+  wave_marks_clear(a, S, c->stream);
+  prof_begin(c, FAST_LSH_STAGE_PAIRS);
+  launch_pairs_wave(a, marks, S, j.rswl, small_max, c->stream);
+  prof_end(c);
+  LAUNCHCK();
+  RC(pair_checks(c, a));
+  return wave_settle(c, j, a, marks, S, small_max);
 }
 
 // Pairs of the large buckets (tiled kernel).  Tile counts and their offsets
@@ -322,6 +388,15 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count, const PairArgs& a
   // the queue)
   PairArgs pa = args;
   pa.big_voted = work;
+  if (pair_launch_queues(pa)) {
+    if (units >= (1ull << 32)) {
+      pa.qcap = 0;  // (queue entries name their unit in 32 bits)
+    } else {  // overflow marks per unit
+      RC(ws<uint8_t>(c, "cand_ovf_tiles", std::max<uint64_t>(units, 1), &pa.q_ovf));
+      fill_u8(pa.q_ovf, units, 0, s);
+      fill_u32(pa.q_any, 1, 0, s);
+    }
+  }
   for (uint64_t u0 = 0; u0 < units; u0 += 1u << 21) {
     const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 21, units - u0);
     prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
@@ -329,6 +404,21 @@ int run_big_pairs(fast_lsh_ctx* c, Job& j, uint32_t big_count, const PairArgs& a
     prof_end(c);
     LAUNCHCK();
     RC(pair_checks(c, pa));
+  }
+  if (pair_launch_queues(pa)) {  // units whose queue slot filled up run again
+    unsigned int any = 0;
+    RC(d2h(c, &any, pa.q_any));
+    if (any) {
+      ++c->pair_redos;
+      const PairArgs r = redo_args(j, pa);
+      for (uint64_t u0 = 0; u0 < units; u0 += 1u << 21) {
+        const uint32_t cnt = (uint32_t)std::min<uint64_t>(1u << 21, units - u0);
+        prof_begin(c, FAST_LSH_STAGE_BIG_PAIRS);
+        launch_pairs_tile(r, toff, owner, u0, cnt, j.bdesc, tb, j.rswl, s);
+        prof_end(c);
+        LAUNCHCK();
+      }
+    }
   }
   return FAST_LSH_OK;
 }
@@ -395,6 +485,7 @@ int finish_output(fast_lsh_ctx* c, Job& j, uint64_t cnt, bool distinct, fast_lsh
   c->last_work.big_members = hc.work[1];
   c->last_work.big_candidates = hc.work[2];
   c->last_work.search_calls += 1;
+  c->last_work.pair_redos = c->pair_redos;
   c->res_count = cnt;
   c->res_valid = true;
   for (uint32_t st = 0; st < S; ++st) {
@@ -455,11 +546,7 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
     m.part_mode = mode;
     m.plo = lo;
     m.phi = hi;
-    prof_begin(c, FAST_LSH_STAGE_PAIRS);
-    launch_pairs_wave(m, j.marks, j.t, j.rswl, j.ba.small_max, s);
-    prof_end(c);
-    LAUNCHCK();
-    RC(pair_checks(c, m));
+    RC(wave_pass(c, j, m, j.marks, j.t, j.ba.small_max));
     return run_big_pairs(c, j, big_count, m, work);
   };
   auto count_from = [&](const PairArgs& base, uint32_t p) -> int {
@@ -651,7 +738,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   pa.station_base = j.sbase;
   pa.nstation = S;
   pa.n_flagged = &j.ctrl->n_flagged;
-  RC(alloc_queue(c, N, &pa));
+  RC(alloc_queue(c, N, S, j.t, &j));
   RC(set_out_buffers(c, j, out_cap));
 
   // launch shapes: fixed, or tuned once per shape
@@ -726,6 +813,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   Ctrl hc;
   RC(d2h(c, &hc, j.ctrl));
   if (hc.err) return fl_fail(FAST_LSH_E_INVALID, "a fingerprint is empty or holds an index >= dim (%u)", h->dim);
+  if (!parts) RC(wave_settle(c, j, j.pa, j.marks, j.t, j.ba.small_max));  // the prefix's small-bucket pairs
   if (parts) {
     RC(run_partitions(c, j, *flt_in, hc.big_count, out_cap, &hc));
     return finish_output(c, j, hc.out_count, distinct, per_station, station_offsets);
@@ -739,11 +827,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
       RC(set_out_buffers(c, j, out_cap));
       fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * S * kSpread * sizeof(unsigned long long), 0, s);
       fill_u32(&j.ctrl->out_count, 1, 0, s);
-      prof_begin(c, FAST_LSH_STAGE_PAIRS);
-      launch_pairs_wave(j.pa, j.marks, j.t, j.rswl, j.ba.small_max, s);
-      prof_end(c);
-      LAUNCHCK();
-      RC(pair_checks(c, j.pa));
+      RC(wave_pass(c, j, j.pa, j.marks, j.t, j.ba.small_max));
     }
     RC(run_big_pairs(c, j, hc.big_count, j.pa, j.work));
     RC(d2h(c, &hc, j.ctrl));
@@ -836,7 +920,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   RC(ws<uint8_t>(c, "marks", gn, &j.marks));
   j.bigbin_grid = (uint32_t)std::min<uint64_t>(cap_bin, 512);
   j.rswl = j.pl.row_dw | 1u;
-  RC(alloc_queue(c, N, nullptr));  // before the keep budget counts free memory
+  RC(alloc_queue(c, N, 1, TGm, nullptr));  // before the keep budget counts free memory
   // Groups whose grouping pass 1 keeps for pass 2: at most keep_groups, as
   // many as the free HBM (less a margin) and the budget hold, counting what
   // earlier calls left allocated under these names.
@@ -930,7 +1014,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
   pa.station_base = j.sbase;
   pa.nstation = 1;
   pa.n_flagged = &j.ctrl->n_flagged;
-  RC(alloc_queue(c, N, &pa));
+  RC(alloc_queue(c, N, 1, TGm, &j));
   uint32_t variant = 0;
   for (uint32_t v = 0; v < kRadixTileVariants; ++v)
     if (radix_tile_elems(v) == c->config.radix_tile) variant = v;
@@ -1033,11 +1117,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
       if (g < kept) {  // pass 1's grouping of this group, with the final flags
         j.pa.order = keep_ids + (uint64_t)g * gn;
         j.pa.table_offset = tb;
-        prof_begin(c, FAST_LSH_STAGE_PAIRS);
-        launch_pairs_wave(j.pa, keep_marks + (uint64_t)g * gn, tc, j.rswl, ba.small_max, s);
-        prof_end(c);
-        LAUNCHCK();
-        RC(pair_checks(c, j.pa));
+        RC(wave_pass(c, j, j.pa, keep_marks + (uint64_t)g * gn, tc, ba.small_max));
         uint4* shared_desc = j.bdesc;
         j.bdesc = keep_desc + (uint64_t)g * cap_big;
         const int rc = run_big_pairs(c, j, kept_big[g], j.pa, j.work);
@@ -1049,11 +1129,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
       RC(group(tb, tc, false, nullptr));
       j.pa.order = j.sorted_v;
       j.pa.table_offset = tb;
-      prof_begin(c, FAST_LSH_STAGE_PAIRS);
-      launch_pairs_wave(j.pa, j.marks, tc, j.rswl, j.ba.small_max, s);
-      prof_end(c);
-      LAUNCHCK();
-      RC(pair_checks(c, j.pa));
+      RC(wave_pass(c, j, j.pa, j.marks, tc, j.ba.small_max));
       RC(d2h(c, &hc, j.ctrl));
       RC(run_big_pairs(c, j, hc.big_count, j.pa, j.work));
     }

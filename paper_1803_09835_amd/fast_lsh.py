@@ -47,10 +47,11 @@ PROFILE_STAGES = ("signatures", "group", "buckets", "big_bins", "pairs", "big_pa
 
 class Config(ctypes.Structure):
     _fields_ = [("radix_tile", _u32), ("bucket_chunk", _u32), ("autotune", _u32), ("bin_bits", _u32),
-                ("keep_groups", _u32)]
+                ("keep_groups", _u32), ("queue_slot", _u32)]
 
 
 KEEP_AUTO = 0xFFFFFFFF
+QUEUE_OFF = 0xFFFFFFFF
 
 
 class _Profile(ctypes.Structure):
@@ -77,7 +78,8 @@ class FpParams(ctypes.Structure):
 
 
 class _Work(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_uint64) for f in ("big_voted", "big_members", "big_candidates", "search_calls")]
+    _fields_ = [(f, ctypes.c_uint64) for f in ("big_voted", "big_members", "big_candidates", "search_calls",
+                                               "pair_redos")]
 
 
 @dataclass
@@ -334,21 +336,22 @@ class FastLSH:
         return {f: int(getattr(w, f)) for f, _ in _Work._fields_}
 
     def configure(self, radix_tile: int = 0, bucket_chunk: int = 0, autotune: bool = False, bin_bits: int = 0,
-                  keep_groups: int = KEEP_AUTO):
+                  keep_groups: int = KEEP_AUTO, queue_slot: int = 0):
         """Launch shapes of later searches (0 keeps the current tile and chunk;
         bin_bits 0 is the automatic rule; keep_groups caps the table groups
         the bounded search keeps between its passes, KEEP_AUTO: as many as
-        HBM holds)."""
+        HBM holds; queue_slot: candidate queue entries per spread slot, 0
+        automatic, QUEUE_OFF checks in place)."""
         _check(library().fast_lsh_configure(self._ctx, ctypes.byref(Config(radix_tile, bucket_chunk,
                                                                             1 if autotune else 0, bin_bits,
-                                                                            keep_groups))))
+                                                                            keep_groups, queue_slot))))
 
     def config_used(self) -> dict:
         """Launch shapes of the last search (the tuner's choice when autotuning)."""
         c = Config()
         _check(library().fast_lsh_config_used(self._ctx, ctypes.byref(c)))
         return {"radix_tile": c.radix_tile, "bucket_chunk": c.bucket_chunk, "autotune": bool(c.autotune),
-                "bin_bits": c.bin_bits, "keep_groups": c.keep_groups}
+                "bin_bits": c.bin_bits, "keep_groups": c.keep_groups, "queue_slot": c.queue_slot}
 
     def signatures(self, rows, dim, t, r, scheme, a, b, table_begin=0, table_count=None, with_values=False):
         """Band keys as int64 [table_count, n] (uint64 bit pattern); with

@@ -252,6 +252,52 @@ def test_search_repeating_noise(ctx, num, den):
         assert st.n_flagged > 1000
 
 
+@pytest.mark.parametrize("qslot,v", [(0, 4), (1, 4), (3, 4), (fl.QUEUE_OFF, 4), (1, 2), (0, 2)])
+def test_search_candidate_queue(qslot, v):
+    """The pair kernels queue the pairs that pass the sub-key group test and
+    check them in a later launch; a workgroup whose queue slot fills up runs
+    again with the checks in place.  Any queue size gives the oracle's
+    output and counters: one entry per slot forces the second runs (tiled
+    and small-bucket launches), QUEUE_OFF checks everything in place.  v=4
+    splits 100 tables into 3 groups (17-dword rows, the checks take the
+    rows' field masks), v=2 keeps one group (50-dword rows)."""
+    c = fl.FastLSH(0)
+    c.configure(queue_slot=qslot)
+    rows = synth.generate(synth.with_noise(synth.station(n=30_000, seed=47), 50, 190))
+    st = _compare(c, rows, 4096, 100, 4, fl.MINMAX, 48, 5, v, label=f"queue-{qslot}")
+    assert st.max_bucket > 300
+    used = c.config_used()["queue_slot"]
+    assert used == (qslot if qslot else 30_000 // 64 if 30_000 // 64 > 64 else 64)
+    redos = c.last_work()["pair_redos"]
+    assert redos == 0 if qslot == fl.QUEUE_OFF else (redos > 0 if qslot == 1 else True)
+    c.close()
+
+
+def test_bounded_candidate_queue_overflow():
+    """The bounded search with one queue entry per slot (second runs in
+    every pair launch of both passes' groups) against the oracle."""
+    c = fl.FastLSH(0)
+    c.configure(queue_slot=1)
+    rows = synth.generate(synth.with_noise(synth.station(n=30_000, seed=49), 50, 190))
+    a, b = fl.make_hash(50, fl.n_funcs(100, 4, fl.MINMAX))
+    say("[search] bounded queue_slot=1 n=30000 t=100 v=4 groups of 10")
+    gi, gj, gv, gst = c.search_bounded(fl.to_device_rows(rows), 4096, 100, 4, fl.MINMAX, a, b, 5, 4, 1, 100,
+                                       group_tables=10)
+    assert c.last_work()["pair_redos"] > 0
+    keys = oracle.signatures(rows, 4096, 100, 4, fl.MINMAX, a, b)
+    ei, ej, ev, est = oracle.search_keys(keys, 5, 4, 1, 100)
+    assert np.array_equal(gi.cpu().numpy().view(np.uint32), ei)
+    assert np.array_equal(gj.cpu().numpy().view(np.uint32), ej)
+    assert np.array_equal(gv.cpu().numpy(), ev)
+    got, want = dict(gst.__dict__), dict(est.__dict__)
+    assert got.pop("n_distinct") == 2**64 - 1
+    want.pop("n_distinct")
+    assert got == want
+    with pytest.raises(fl.FastLshError):
+        c.configure(queue_slot=(1 << 20) + 1)
+    c.close()
+
+
 def test_search_huge_bins(ctx):
     # Every fingerprint identical: one bucket of n in every table (oversized
     # bins, the single-workgroup sort path and tiled pairs).
