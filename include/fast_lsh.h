@@ -270,7 +270,7 @@ int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, ui
  *                 launch gives the queued pairs their exact key checks one
  *                 lane per pair; a workgroup whose slot fills up runs again
  *                 with the checks in place (fast_lsh_work.pair_redos).
- *                 0: automatic (n / 64, between 64 and 16384);
+ *                 0: automatic (n / 64, between 64 and 32768);
  *                 FAST_LSH_QUEUE_OFF: no queue, checks in place; at most
  *                 2^20.  Any value gives the same result.
  *                 fast_lsh_config_used reports the last search's size. */

@@ -965,7 +965,7 @@ __device__ __forceinline__ void check_candidate_regs(const PairArgs& a, uint32_t
 // The queued candidates of spread slot blockIdx.x, one lane per pair (the
 // slot's entries split over kCheckSplit workgroups), each pair's two rows
 // read from memory once.
-constexpr uint32_t kCheckSplit = 4;
+constexpr uint32_t kCheckSplit = 16;
 template <int RSW>
 __global__ __launch_bounds__(kPT) void k_check_queue(PairArgs a) {
   const uint32_t slot = blockIdx.x;

@@ -269,13 +269,13 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
 }
 
 // The candidate queue of the pair kernels' need == 2 form: N / 64 entries
-// per spread slot, between 64 and 16,384 (about twice what one launch of a
-// 5-year station queues per slot; a pair that finds its slot full is checked
-// in place).
+// per spread slot, between 64 and 32,768 (one launch of a 5-year station
+// queues about 8,000 per slot on average, unevenly: at 16,384 a few chunks
+// per search found their slot full and ran again).
 int alloc_queue(fast_lsh_ctx* c, uint64_t N, uint32_t S, uint32_t T, Job* j) {
   const uint32_t cfg = c->config.queue_slot;
   uint32_t qcap = cfg == FAST_LSH_QUEUE_OFF ? 0u
-                  : cfg ? cfg : (uint32_t)std::min<uint64_t>(16384, std::max<uint64_t>(64, N / 64));
+                  : cfg ? cfg : (uint32_t)std::min<uint64_t>(32768, std::max<uint64_t>(64, N / 64));
   if ((uint64_t)T * ((N + 63) / 64) >= (1ull << 32)) qcap = 0;  // queue entries name their chunk in 32 bits
   c->last_qcap = qcap ? qcap : FAST_LSH_QUEUE_OFF;
   c->pair_redos = 0;
