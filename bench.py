@@ -242,7 +242,7 @@ def tile_roofline(work, st, tile_ms, launches):
     per member of the buckets it takes, over its kernel time per search."""
     algo = BYTES_PER_VOTED_PAIR * work["big_voted"] + BYTES_PER_MEMBER * work["big_members"]
     gbs = algo / (tile_ms / 1000.0) / 1e9
-    return {"kernel": "k_pairs_tile<17,true>", "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+    return {"kernel": "k_pairs_tile<17,true,true>", "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
             "algorithmic_bytes_per_search": algo,
             "units": {"voted_pairs": work["big_voted"], "members": work["big_members"],
