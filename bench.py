@@ -969,8 +969,8 @@ def run_fingerprints(args):
                    "top_k": top_k},
         "fingerprints_with_k_bits": full,
         "stage_ms": {k: round(x, 3) for k, x in stage_ms.items() if x},
-        "roofline": {"kernel": "k_stft", "bound": "fp32", "achieved": round(tf, 2), "peak": 157.3,
-                     "unit": "TFLOP/s (fp32 vector FMA)", "frac": round(tf / 157.3, 4), "traffic": None,
+        "roofline": {"kernel": "k_stft_mfma (with its basis rows)", "bound": "mfma", "achieved": round(tf, 2),
+                     "peak": 157.3, "unit": "TFLOP/s (fp32 MFMA)", "frac": round(tf / 157.3, 4), "traffic": None,
                      "flop_per_frame": rows * 4 * window, "frames": frames},
     }
     from oracle import fingerprint as ofp

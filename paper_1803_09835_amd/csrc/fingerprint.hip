@@ -17,11 +17,14 @@
 //                z != 0 only;
 //   binarize     coefficient c with z > 0 -> bit 2c, z < 0 -> bit 2c + 1.
 //
-// GPU form.  k_stft: a workgroup takes 256 consecutive frames and 32 bins;
-// the samples the frames cover and each wavefront's Hann-weighted cosine /
-// sine rows for its 8 bins are staged in LDS; each lane accumulates 4
-// frames (64 apart) x 8 bins (real and imaginary parts) over the window with
-// fp32 FMA.
+// GPU form.  The spectrogram is a product of the frames' samples (frames x
+// window, rows overlapping by window - hop) with the band's Hann-weighted
+// cosine and sine rows (window x 2 bins).  k_stft_mfma: a workgroup takes
+// 256 consecutive frames and 32 bins, stages their samples and the basis
+// rows in LDS, and forms the product with fp32 16 x 16 x 4 MFMA steps.
+// k_stft, the vector form for windows and hops whose staging would not fit
+// 64 KB: each lane accumulates 4 frames (64 apart) x 8 bins (real and
+// imaginary parts) over the window with fp32 FMA.
 // k_fp: one wavefront per fingerprint: the image is assembled in LDS, the
 // Haar levels run in place (every lane reads its pairs, then writes), the
 // normalized |z| of the lane's 32 consecutive coefficients are kept in
@@ -160,6 +163,90 @@ __device__ __forceinline__ void haar_axis(float* v, uint32_t lines, uint32_t lle
     __syncthreads();
   }
 }
+
+// Hann-weighted cosine and sine rows of the kept band for the matrix-core
+// form of the spectrogram: basis[yb][t][n][16], column c = 16 t + j of bin
+// group yb (32 bins) = bin 32 yb + c / 2, cos for even c, -sin for odd c, at
+// sample n of the window; zero past the window (n < wpad, the window rounded
+// up to 4) and past the band.
+__global__ __launch_bounds__(kFT) void k_stft_basis(FpArgs a, uint32_t wpad, uint32_t nyb, float* basis) {
+  const uint32_t W = a.window;
+  const uint64_t total = (uint64_t)nyb * 4 * wpad * 16;
+  for (uint64_t e = (uint64_t)blockIdx.x * kFT + threadIdx.x; e < total; e += (uint64_t)gridDim.x * kFT) {
+    const uint32_t j = (uint32_t)(e & 15), nn = (uint32_t)((e >> 4) % wpad);
+    const uint32_t t = (uint32_t)((e >> 4) / wpad % 4), yb = (uint32_t)((e >> 4) / wpad / 4);
+    const uint32_t c = 16 * t + j, kb = 32 * yb + c / 2;
+    float v = 0.0f;
+    if (nn < W && kb < a.rows) {
+      const uint32_t k = a.band_lo + kb;
+      float sn, cs;
+      sincospif(2.0f * (float)((k * nn) % W) / (float)W, &sn, &cs);
+      const float h = 0.5f * (1.0f - cospif(2.0f * (float)nn / (float)W));
+      v = (c & 1) ? -sn * h : cs * h;
+    }
+    basis[e] = v;
+  }
+}
+
+// The spectrogram on the matrix cores: per workgroup 256 consecutive frames
+// and one bin group (32 bins, 64 basis columns).  The frames' samples and
+// the group's basis rows are staged in LDS; wavefront w takes frames
+// 64 w .. 64 w + 63 as four 16-frame tiles against the four 16-column basis
+// tiles, accumulating frames x window x basis with 16 x 16 x 4 fp32 MFMA
+// steps (A: frame row i, samples n0 + k in lane i + 16 k; B: basis rows
+// n0 + k, column j in lane j + 16 k; D: row 4 (lane / 16) + r, column
+// lane % 16 in element r).  The power of a bin is re^2 + im^2 of two
+// neighbouring columns, which sit in neighbouring lanes.
+__global__ __launch_bounds__(kFT) void k_stft_mfma(FpArgs a, const float* basis, uint32_t wpad, float* spec) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  extern __shared__ float lds[];
+  const uint32_t hop = a.hop;
+  float* xs = lds;  // 255 * hop + wpad samples
+  const uint32_t span = (kFramesPerBlock - 1) * hop + wpad;
+  float* bl = xs + ((span + 3) & ~3u);  // [4][wpad][16]
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t f0 = (uint64_t)blockIdx.x * kFramesPerBlock;
+  const uint64_t s0 = f0 * hop;
+  for (uint32_t e = tid; e < span; e += kFT) xs[e] = s0 + e < a.n ? a.x[s0 + e] : 0.0f;
+  {
+    const float4* src = reinterpret_cast<const float4*>(basis + (uint64_t)blockIdx.y * 4 * wpad * 16);
+    float4* dst = reinterpret_cast<float4*>(bl);
+    for (uint32_t e = tid; e < wpad * 16; e += kFT) dst[e] = src[e];  // 4 * wpad * 16 floats
+  }
+  __syncthreads();
+  const uint32_t li = lane & 15, lk = lane >> 4;
+  const float* xw = xs + (wave * 64 + li) * hop + lk;
+  const float* bw = bl + lk * 16 + li;
+  f4 acc[4][4];
+#pragma unroll
+  for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[ft][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (uint32_t n0 = 0; n0 < wpad; n0 += 4) {
+    float av[4], bv[4];
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft) av[ft] = xw[ft * 16 * hop + n0];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) bv[t] = bw[(t * wpad + n0) * 16];
+#pragma unroll
+    for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[ft][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ft], bv[t], acc[ft][t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int ft = 0; ft < 4; ++ft)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = acc[ft][t][r];
+        const float w = __shfl_xor(v, 1, 64);
+        const uint64_t f = f0 + wave * 64 + 16 * ft + 4 * lk + r;
+        const uint32_t kb = 32 * blockIdx.y + (16 * t + li) / 2;
+        if (!(li & 1) && f < a.n_frames && kb < a.rows) spec[f * a.rows + kb] = v * v + w * w;
+      }
+}
+
 
 // One wavefront per fingerprint.  mode 0 (sample): fingerprint sample_ids[s]
 // writes its coefficients as ordered keys into keys_t[c * n_sample + s];
@@ -357,6 +444,11 @@ size_t stft_lds_bytes(uint32_t window, uint32_t hop) {
   return ((((size_t)kFramesPerBlock * hop + window + 3) & ~(size_t)3) + 4ull * window * 16) * sizeof(float);
 }
 
+size_t stft_mfma_lds_bytes(uint32_t window, uint32_t hop) {
+  const size_t wpad = (window + 3) & ~3u;
+  return (((((size_t)kFramesPerBlock - 1) * hop + wpad + 3) & ~(size_t)3) + 4 * wpad * 16) * sizeof(float);
+}
+
 }  // namespace
 
 extern "C" int fast_lsh_fingerprints(fast_lsh_ctx* c, const float* samples, uint64_t n_samples,
@@ -420,14 +512,23 @@ extern "C" int fast_lsh_fingerprints(fast_lsh_ctx* c, const float* samples, uint
   }
   float* spec;
   RC(ws<float>(c, "fp_spec", a.n_frames * rows, &spec));
-  // 1. spectrogram
-  prof_begin(c, FAST_LSH_STAGE_SPECTROGRAM);
+  // 1. spectrogram (on the matrix cores when the staged rows fit 64 KB)
   {
-    const size_t lds = stft_lds_bytes(W, a.hop);
     const dim3 grid((unsigned)((a.n_frames + kFramesPerBlock - 1) / kFramesPerBlock), (rows + 31) / 32);
-    hipLaunchKernelGGL(k_stft, grid, dim3(kFT), lds, s, a, spec);
+    const uint32_t wpad = (W + 3) & ~3u;
+    if (stft_mfma_lds_bytes(W, a.hop) <= 65536) {
+      float* basis;
+      RC(ws<float>(c, "fp_basis", (uint64_t)grid.y * 4 * wpad * 16, &basis));
+      prof_begin(c, FAST_LSH_STAGE_SPECTROGRAM);
+      hipLaunchKernelGGL(k_stft_basis, dim3(grid.y * wpad / 4), dim3(kFT), 0, s, a, wpad, grid.y, basis);
+      hipLaunchKernelGGL(k_stft_mfma, grid, dim3(kFT), stft_mfma_lds_bytes(W, a.hop), s, a, basis, wpad, spec);
+      prof_end(c);
+    } else {
+      prof_begin(c, FAST_LSH_STAGE_SPECTROGRAM);
+      hipLaunchKernelGGL(k_stft, grid, dim3(kFT), stft_lds_bytes(W, a.hop), s, a, spec);
+      prof_end(c);
+    }
   }
-  prof_end(c);
   LAUNCHCK();
   const size_t fp_lds = 4ull * (rows * (cols + kPitchPad) + 256) * sizeof(float);
   // 2. the sample's coefficients, then median and MAD per coefficient
