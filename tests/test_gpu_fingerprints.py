@@ -86,9 +86,13 @@ def test_fingerprints_match_oracle(ctx):
                                  dict(window=64, hop=4, band_lo=0, band_hi=8, fp_frames=32, time_ds=4, fp_lag=3,
                                       top_k=20),
                                  dict(window=200, hop=10, band_lo=4, band_hi=68, fp_frames=128, time_ds=4, fp_lag=10,
-                                      top_k=300)])
+                                      top_k=300),
+                                 dict(window=49, hop=51, band_lo=0, band_hi=8, fp_frames=32, time_ds=4, fp_lag=3,
+                                      top_k=20)])
 def test_fingerprints_other_shapes(ctx, prm):
-    # 16 x 64, 8 x 8 (one wave's 64 coefficients) and 64 x 32 images
+    # 16 x 64, 8 x 8 (one wave's 64 coefficients) and 64 x 32 images; window
+    # 49 at hop 51 stages more than 64 KB in the matrix-core spectrogram (the
+    # window rounds up to 52), so the vector form computes it
     spec = synth.WaveSpec(n=100 * 900, seed=12, n_sources=4, rep_min=3, rep_max=3, noise_std=1.0)
     x = synth.waveform(spec)
     p = ofp.FpParams(**prm)
