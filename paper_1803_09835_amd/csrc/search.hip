@@ -763,7 +763,7 @@ int fl_search_stations(fast_lsh_ctx* c, const fast_lsh_hash* h, uint32_t S, cons
   if (use_graph) {
     std::vector<uint64_t> key{S, N, t, h->band_rows, h->scheme, h->dim, flt->min_lag, flt->min_votes,
                               flt->occ_num, flt->occ_den, flags, j.tc.radix_variant, j.tc.bucket_chunk,
-                              c->ws_generation, (uint64_t)(uintptr_t)s};
+                              c->ws_generation, (uint64_t)(uintptr_t)s, j.pa.qcap};
     for (uint32_t st = 0; st < S; ++st) {
       key.push_back((uint64_t)(uintptr_t)f[st].indices);
       key.push_back((uint64_t)(uintptr_t)f[st].offsets);

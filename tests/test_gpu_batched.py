@@ -192,6 +192,34 @@ def test_graph_replays_match_eager(ctx):
         assert torch.equal(x, y)
 
 
+def test_graph_replays_with_queue_overflow():
+    """Graph replays whose pair launch overflows a one-entry candidate queue
+    (the chunks run again after each replay), then the queue switched off
+    (a new capture): every result equals the eager search's."""
+    c = fl.FastLSH(0)
+    try:
+        rows = synth.generate(synth.with_noise(synth.station(n=30_000, seed=122), 50, 190))
+        a, b = fl.make_hash(203, 200)
+        dev = fl.to_device_rows(rows)
+        say("[graph] eager reference, queue_slot=1")
+        c.configure(queue_slot=1)
+        ref = c.search(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
+        assert c.last_work()["pair_redos"] > 0
+        for k in range(3):
+            say(f"[graph] replay {k}, queue_slot=1")
+            got = c.search(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, graph=True)
+            assert all(torch.equal(x, y) for x, y in zip(ref[:3], got[:3])) and got[3] == ref[3], k
+            assert c.last_work()["pair_redos"] > 0
+            (dev.float() * 2).sum().item()
+        say("[graph] queue off")
+        c.configure(queue_slot=fl.QUEUE_OFF)
+        got = c.search(dev, 4096, 100, 4, fl.MINMAX, a, b, 5, 4, graph=True)
+        assert all(torch.equal(x, y) for x, y in zip(ref[:3], got[:3])) and got[3] == ref[3]
+        assert c.last_work()["pair_redos"] == 0 and c.config_used()["queue_slot"] == fl.QUEUE_OFF
+    finally:
+        c.close()
+
+
 def test_graph_batched_replays(ctx):
     stations = [synth.generate(synth.tiny_uniform(n=n, seed=1030 + n)) for n in (12_000, 30_000, 5_000)]
     for k in range(3):
