@@ -218,9 +218,13 @@ int fast_lsh_search_batched(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, uint32
  * keep_groups and the free HBM allow, otherwise after rebuilding, sorting
  * and segmenting the group's keys again.  Workspace, in bytes, is about
  *   n * (4 t + 2 t' + 1) + group_tables * n * (24 + 1) + small tables
- *   + kept groups * group_tables * n * 5,
+ *   + kept groups * group_tables * n * 5 + candidate queue,
  * with t' = t rounded up to whole 32-bit words per group of the vote filter
- * (the fast_lsh_search workspace is about n * (2 t' + 1) + 33 t n); like
+ * and the candidate queue 16 * 1024 * queue_slot bytes (512 MiB at the
+ * automatic size from n >= 2,097,152; fast_lsh_config) plus one byte per 64
+ * positions of a group's tables and per tile of the tiled pairs (the
+ * fast_lsh_search workspace is about n * (2 t' + 1) + 33 t n plus the
+ * queue); like
  * every workspace buffer it stays allocated in the context (reported by
  * fast_lsh_workspace_bytes) until the context is destroyed.
  * Requires band keys of at most 48 bits (ceil(log2 dim) * r <= 48) and does

@@ -80,6 +80,18 @@ def test_partitioned_station_months(ctx):
     assert st.n_flagged > 1000
 
 
+def test_partitioned_bursts_in_separate_partitions(ctx):
+    # seven partitions of 10,000 with bursts of repeating noise in the second
+    # and the fifth: the counting pass is taken again after each excluding
+    # partition, and the pairs are reported in three runs (partition 0,
+    # partitions 1-3, partitions 4-6), each with the exclusions of its time
+    rows = synth.generate(synth.station(n=70_000, seed=90))
+    for lo, seed in ((10_000, 91), (40_000, 92)):
+        rows[lo:lo + 8_000] = synth.generate(synth.with_noise(synth.station(n=8_000, seed=seed), 200, 190))
+    st = _compare(ctx, rows, 100, 4, fl.MINMAX, 93, 5, 4, 1, 100, 7, label="bursts in partitions 1 and 4")
+    assert st.n_flagged > 500
+
+
 def test_partitioned_edges(ctx):
     rows = synth.generate(synth.with_noise(synth.station(n=500, seed=88), 80, 190))
     _compare(ctx, rows, 20, 4, fl.MINMAX, 89, 2, 2, 1, 20, 1000, label="more partitions than fingerprints")
