@@ -274,9 +274,11 @@ int fast_lsh_copy_result(fast_lsh_ctx *ctx, uint32_t *out_i, uint32_t *out_j, ui
  *                 launch gives the queued pairs their exact key checks one
  *                 lane per pair; a workgroup whose slot fills up runs again
  *                 with the checks in place (fast_lsh_work.pair_redos).
- *                 0: automatic (n / 64, between 64 and 32768);
- *                 FAST_LSH_QUEUE_OFF: no queue, checks in place; at most
- *                 2^20.  Any value gives the same result.
+ *                 0: automatic (n / 64, between 64 and 32768; none on
+ *                 a context with an HBM budget, or when the free HBM does
+ *                 not hold it); FAST_LSH_QUEUE_OFF: no queue, checks in
+ *                 place; at most 2^20 (E_NOMEM when it does not fit).  Any
+ *                 value gives the same result.
  *                 fast_lsh_config_used reports the last search's size. */
 #define FAST_LSH_KEEP_AUTO 0xFFFFFFFFu
 #define FAST_LSH_QUEUE_OFF 0xFFFFFFFFu

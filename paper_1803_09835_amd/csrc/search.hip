@@ -273,23 +273,31 @@ int enqueue_prefix(fast_lsh_ctx* c, Job& j, hipStream_t s, bool prof, bool tune)
 // queues about 8,000 per slot on average, unevenly: at 16,384 a few chunks
 // per search found their slot full and ran again).
 int alloc_queue(fast_lsh_ctx* c, uint64_t N, uint32_t S, uint32_t T, Job* j) {
+  // (a context with an HBM budget has no automatic queue: its searches'
+  // memory stays what it was without one)
   const uint32_t cfg = c->config.queue_slot;
-  uint32_t qcap = cfg == FAST_LSH_QUEUE_OFF ? 0u
+  uint32_t qcap = cfg == FAST_LSH_QUEUE_OFF || (cfg == 0 && c->budget) ? 0u
                   : cfg ? cfg : (uint32_t)std::min<uint64_t>(32768, std::max<uint64_t>(64, N / 64));
   if ((uint64_t)T * ((N + 63) / 64) >= (1ull << 32)) qcap = 0;  // queue entries name their chunk in 32 bits
-  c->last_qcap = qcap ? qcap : FAST_LSH_QUEUE_OFF;
   c->pair_redos = 0;
-  uint4* q;
-  unsigned int *cnt, *any;
-  uint8_t* ovf;
-  unsigned long long* tally;
-  RC(ws<uint4>(c, "cand_queue", (uint64_t)kSpread * std::max(qcap, 1u), &q));
-  RC(ws<unsigned int>(c, "cand_count", kSpread + 1, &cnt));
-  any = cnt + kSpread;
-  // overflow marks of a small-bucket launch: one per 64 positions of a table
-  const uint64_t marks = (uint64_t)T * ((N + 63) / 64);
-  RC(ws<uint8_t>(c, "cand_ovf_wave", std::max<uint64_t>(marks, 1), &ovf));
-  RC(ws<unsigned long long>(c, "redo_tally", 2ull * S * kSpread, &tally));
+  uint4* q = nullptr;
+  unsigned int *cnt = nullptr, *any = nullptr;
+  uint8_t* ovf = nullptr;
+  unsigned long long* tally = nullptr;
+  if (qcap) {
+    // an automatic queue that the free HBM does not hold is left out
+    // (checks in place); a size asked for is an error
+    int rc = ws<uint4>(c, "cand_queue", (uint64_t)kSpread * qcap, &q);
+    if (rc == FAST_LSH_OK) rc = ws<unsigned int>(c, "cand_count", kSpread + 1, &cnt);
+    // overflow marks of a small-bucket launch: one per 64 positions of a table
+    const uint64_t marks = (uint64_t)T * ((N + 63) / 64);
+    if (rc == FAST_LSH_OK) rc = ws<uint8_t>(c, "cand_ovf_wave", std::max<uint64_t>(marks, 1), &ovf);
+    if (rc == FAST_LSH_OK) rc = ws<unsigned long long>(c, "redo_tally", 2ull * S * kSpread, &tally);
+    if (rc == FAST_LSH_E_NOMEM && cfg == 0) qcap = 0;
+    else RC(rc);
+    any = cnt ? cnt + kSpread : nullptr;
+  }
+  c->last_qcap = qcap ? qcap : FAST_LSH_QUEUE_OFF;
   if (j) {
     j->pa.q = q;
     j->pa.q_count = cnt;
@@ -1111,7 +1119,7 @@ int fl_search_bounded(fast_lsh_ctx* c, const fast_lsh_hash* h, const fast_lsh_fp
     fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * kSpread * sizeof(unsigned long long), 0, s);
     fill_u64(reinterpret_cast<uint64_t*>(j.work), 3 * kSpread, 0, s);
     fill_u32(&j.ctrl->out_count, 1, 0, s);
-    fill_u32(j.pa.q_count, kSpread, 0, s);
+    if (j.pa.qcap) fill_u32(j.pa.q_count, kSpread, 0, s);
     for (uint32_t g = 0; g < ngroups; ++g) {
       const uint32_t tb = g * TGm, tc = std::min(TGm, t - tb);
       if (g < kept) {  // pass 1's grouping of this group, with the final flags

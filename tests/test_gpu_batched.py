@@ -357,7 +357,7 @@ def test_bounded_keeps_what_the_budget_holds():
     sizes = {}
     for keep in (0, fl.KEEP_AUTO):
         c = fl.FastLSH(0)
-        c.configure(keep_groups=keep)
+        c.configure(keep_groups=keep, queue_slot=fl.QUEUE_OFF)  # (a budget context has no automatic queue)
         out = c.search_bounded(*args, group_tables=10)
         sizes[keep] = (c.workspace_bytes(), c.config_used()["keep_groups"])
         c.close()

@@ -273,6 +273,31 @@ def test_search_candidate_queue(qslot, v):
     c.close()
 
 
+def test_search_queue_under_budget():
+    """A context with an HBM budget searches without the automatic candidate
+    queue (checks in place, same result, the same workspace as with the
+    queue off); a queue size asked for that does not fit is E_NOMEM."""
+    rows = synth.generate(synth.with_noise(synth.station(n=30_000, seed=51), 50, 190))
+    a, b = fl.make_hash(52, fl.n_funcs(100, 4, fl.MINMAX))
+    free = fl.FastLSH(0)
+    free.configure(queue_slot=fl.QUEUE_OFF)
+    ref = free.search(fl.to_device_rows(rows), 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
+    need = free.workspace_bytes()
+    free.close()
+    c = fl.FastLSH(0, hbm_budget=need + (1 << 20))
+    try:
+        say(f"[search] budget {need + (1 << 20)} bytes, automatic queue")
+        got = c.search(fl.to_device_rows(rows), 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
+        assert all(torch.equal(x, y) for x, y in zip(ref[:3], got[:3])) and got[3] == ref[3]
+        assert c.config_used()["queue_slot"] == fl.QUEUE_OFF and c.workspace_bytes() == need
+        c.configure(queue_slot=16384)  # 256 MiB of queue
+        with pytest.raises(fl.FastLshError) as e:
+            c.search(fl.to_device_rows(rows), 4096, 100, 4, fl.MINMAX, a, b, 5, 4)
+        assert e.value.code == fl.E_NOMEM
+    finally:
+        c.close()
+
+
 def test_bounded_candidate_queue_overflow():
     """The bounded search with one queue entry per slot (second runs in
     every pair launch of both passes' groups) against the oracle."""
