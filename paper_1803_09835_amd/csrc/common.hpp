@@ -222,7 +222,8 @@ struct PairArgs {
   // adds one to cand[] of its members in [plo, phi); 2: at its first shared
   // table, a pair with exactly one member in fp[] (the partition's
   // over-threshold fingerprints) sets ex_next[] of the other; 3: the plain
-  // search restricted to pairs whose smaller id lies in [plo, phi).
+  // search restricted to pairs whose smaller id lies in [plo, phi); 4: modes
+  // 1 and 3 over all ids in one pass (before any exclusion).
   uint32_t part_mode;
   uint32_t plo, phi;
   uint32_t* cand;

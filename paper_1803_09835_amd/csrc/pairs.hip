@@ -333,6 +333,19 @@ __device__ __forceinline__ void visit_pair(const PairArgs& a, uint32_t u, uint32
     tl.hi = (uint32_t)a.station_base[st + 1];
   }
   ++tl.ev;
+  if (!FAST && a.part_mode == 4) {
+    // partitioned search, every partition counted and reported in one pass
+    // (valid while no partition excludes): at its first shared table the
+    // pair adds one to both members' counts, and it is reported as in the
+    // plain search
+    const bool lower = rx.eq_below(ro, rsw, u) != 0 && lower_in_group(a, u, i, j, rl, ry);
+    if (lower) return;
+    atomicAdd(a.cand + i, 1u);
+    atomicAdd(a.cand + j, 1u);
+    if (a.want_distinct) ++tl.nd;
+    if (rx.eq(ro, rsw) - pad >= a.need) exact_and_report(a, u, i, j);
+    return;
+  }
   if (FAST) {
     const bool cand = rx.any_equal(rv);
     if (QUEUE) {

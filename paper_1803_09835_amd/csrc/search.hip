@@ -527,9 +527,12 @@ int finish_output(fast_lsh_ctx* c, Job& j, uint64_t cnt, bool distinct, fast_lsh
 // it are counted again.  Partition p's pairs are reported with the
 // exclusions as they stand after p, and those change only at a partition
 // that excludes, so one reporting pass covers each run of partitions up to
-// the next one that excludes.  Without exclusions this is one counting and
-// one reporting pass whatever the partition count; each partition that
-// excludes adds an exclusion pass and at most one counting and one
+// the next one that excludes.  Before all this, one pass counts and
+// reports every partition at once (mode 4), which is the result when no
+// partition excludes (the usual case) whatever the partition count; when
+// some partition does, that pass's output is dropped and the scheme above
+// runs: each partition that excludes adds an exclusion pass and at most one
+// counting and one reporting pass to the first counting pass and the last
 // reporting pass.
 int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t big_count, uint64_t out_cap,
                    Ctrl* hc_out) {
@@ -545,7 +548,7 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
   RC(ws<uint8_t>(c, "part_exnext", N, &exn));
   RC(ws<unsigned long long>(c, "part_one", 1, &always));
   RC(ws<unsigned long long>(c, "part_work", 3 * kSpread, &dummy));
-  RC(ws<unsigned int>(c, "part_nfp", 1, &nfp));
+  RC(ws<unsigned int>(c, "part_nfp", std::max<uint32_t>(P, 1), &nfp));
   fill_u64(reinterpret_cast<uint64_t*>(always), 1, 1, s);  // the pair kernels always consult the exclusions
   auto lo_of = [&](uint32_t p) { return (uint32_t)(N * p / P); };
   // one pass of mode m over the pairs whose ids the mode restricts to [lo, hi)
@@ -576,7 +579,28 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
     pa.fp = fp;
     pa.ex_next = exn;
     uint32_t unreported = 0;  // first partition whose pairs are not reported yet
+    bool done = false;        // every partition's pairs are in the output
     if (flt.occ_den) {
+      // First one pass that counts and reports every partition, right while
+      // no partition excludes (the usual case); if one does, its output is
+      // dropped and the partitions are taken as below.
+      fill_u32(cand, N, 0, s);
+      RC(pass(pa, 4, 0, (uint32_t)N, j.work));
+      fill_u32(nfp, P, 0, s);
+      for (uint32_t p = 0; p < P; ++p)
+        launch_part_flag(j.flags, cand, lo_of(p), lo_of(p + 1), flt.occ_num, flt.occ_den, fp, nfp + p, s);
+      LAUNCHCK();
+      std::vector<unsigned int> hn(P, 0);
+      RC(d2h(c, hn.data(), nfp, P));
+      done = std::all_of(hn.begin(), hn.end(), [](unsigned int x) { return x == 0; });
+      if (!done) {
+        fill_u8(reinterpret_cast<uint8_t*>(j.ev), 2ull * kSpread * sizeof(unsigned long long), 0, s);
+        fill_u64(reinterpret_cast<uint64_t*>(j.work), 3 * kSpread, 0, s);
+        fill_u32(&j.ctrl->out_count, 1, 0, s);
+        fill_u8(fp, N, 0, s);
+      }
+    }
+    if (flt.occ_den && !done) {
       RC(count_from(pa, 0));
       for (uint32_t p = 0; p < P; ++p) {
         const uint32_t lo = lo_of(p), hi = lo_of(p + 1);
@@ -596,7 +620,7 @@ int run_partitions(fast_lsh_ctx* c, Job& j, const fast_lsh_filter& flt, uint32_t
         if (p + 1 < P) RC(count_from(pa, p + 1));
       }
     }
-    RC(pass(pa, 3, lo_of(unreported), (uint32_t)N, j.work));
+    if (!done) RC(pass(pa, 3, lo_of(unreported), (uint32_t)N, j.work));
     RC(d2h(c, &hc, j.ctrl));
     if (hc.out_count <= out_cap) break;
     out_cap = (uint64_t)hc.out_count + 1024;
