@@ -462,9 +462,10 @@ int fast_lsh_last_work(fast_lsh_ctx *ctx, fast_lsh_work *out);
  * all tables (no static filter), e_voted / n_distinct over the pairs the
  * partitions could report, n_flagged the fingerprints excluded at the end.
  * E_INVALID for n_partitions == 0, FAST_LSH_USE_GRAPH or bad inputs.
- * Cost: one counting and one reporting pass over all buckets when nothing
- * is excluded; each partition that excludes adds an exclusion pass and at
- * most one counting and one reporting pass. */
+ * Cost: one pass over all buckets when nothing is excluded (it counts and
+ * reports every partition); otherwise that pass, one counting and one
+ * reporting pass, and for each partition that excludes an exclusion pass
+ * and at most one more counting and reporting pass. */
 int fast_lsh_search_partitioned(fast_lsh_ctx *ctx, const fast_lsh_hash *hash, const fast_lsh_fps *fps,
                                 const fast_lsh_filter *filter, uint32_t flags, uint32_t n_partitions,
                                 uint32_t *out_i, uint32_t *out_j, uint8_t *out_votes, uint64_t capacity,
