@@ -161,9 +161,9 @@ __device__ __forceinline__ void check_candidate(const PairArgs& a, uint32_t u, u
   if (!lower_in_group(a, u, i, j, rl, rr) && upper_in_group(a, u, i, j, rl, rr)) exact_and_report(a, u, i, j);
 }
 
-// Appends the calling lane's candidate (want) of workgroup blk to the queue
-// of the workgroup's spread slot: one atomic per wavefront for all its
-// active lanes that want to.  False when the slot is full.
+// Appends the calling lane's candidate (want) of chunk blk to the queue of
+// the workgroup's spread slot: one atomic per wavefront for all its active
+// lanes that want to.  False when the slot is full.
 __device__ __forceinline__ bool enqueue_candidate(const PairArgs& a, bool want, uint32_t u, uint32_t i, uint32_t j,
                                                   uint32_t blk) {
   const uint64_t m = __ballot(want);
