@@ -725,8 +725,34 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       const uint32_t idx = idsA[xs];
       const uint32_t* rowx = rowsA + xs * rswl;
       const uint32_t* rowy = rowsB + y0 * rswl;  // stepped with y (no multiply per pair)
-      for (uint32_t y = y0; y < nbm; y += 2, rowy += 2 * rswl)
-        if (live) visit_pair<RSW, FAST, QUEUE>(a, u, idx, idsB[y], rx, rowx, rowy, rowy, rsw, pad, tl);
+      // A clean tile (one station, no member excluded anywhere, the plain
+      // search, and B's smallest id at least min_lag above A's largest: ids
+      // ascend within a bucket and B's follow A's) has every pair alive and
+      // far enough apart, so the loop skips those checks and each lane adds
+      // its pair count to the tally once.
+      const bool clean = FAST && !use_flags && a.nstation == 1 && a.part_mode == 0 &&
+                         idsB[0] - idsA[na - 1] >= a.min_lag;
+      if (clean) {
+        for (uint32_t y = y0; y < nbm; y += 2, rowy += 2 * rswl)
+          if (live) {
+            uint32_t rv[RowReg<RSW>::kW];
+            RowReg<RSW>::fetch(rowy, rv);
+            const uint32_t idy = idsB[y];
+            const bool cand = rx.any_equal(rv);
+            if (QUEUE) {
+              if (!enqueue_candidate(a, cand, u, idx, idy, tl.blk)) {
+                a.q_ovf[tl.blk] = 1;
+                *a.q_any = 1;
+              }
+            } else if (cand) {
+              check_candidate(a, u, idx, idy, rowx, rowy);
+            }
+          }
+        if (live) tl.ev += (nbm - y0 + 1) / 2;
+      } else {
+        for (uint32_t y = y0; y < nbm; y += 2, rowy += 2 * rswl)
+          if (live) visit_pair<RSW, FAST, QUEUE>(a, u, idx, idsB[y], rx, rowx, rowy, rowy, rsw, pad, tl);
+      }
     }
   } else if (diag && tb_size == kPT / 2) {
     // Diagonal tiles: the pairs {x, (x + k) mod na} for k = 1 .. na / 2 are
