@@ -168,12 +168,14 @@ __device__ __forceinline__ bool enqueue_candidate(const PairArgs& a, bool want, 
                                                   uint32_t blk) {
   const uint64_t m = __ballot(want);
   if (m == 0) return true;
+  // (the lane's own bit is read back from the ballot, so that `want` stays a
+  // lane mask and is never spilled to a vector register)
   const uint32_t lane = threadIdx.x & 63, lead = (uint32_t)__ffsll((long long)m) - 1;
   const uint32_t slot = spread_slot();
   uint32_t base = 0;
   if (lane == lead) base = atomicAdd(a.q_count + slot, (unsigned int)__popcll(m));
   base = __shfl(base, lead, 64);
-  if (!want) return true;
+  if (((m >> lane) & 1u) == 0) return true;
   const uint32_t q = base + (uint32_t)__popcll(m & __lanemask_lt());
   if (q >= a.qcap) return false;
   a.q[(uint64_t)slot * a.qcap + q] = make_uint4(i, j, u, blk);
@@ -278,7 +280,11 @@ struct RowReg {
     half2 acc = {0xFFFF, 0xFFFF};
 #pragma unroll
     for (int k = 0; k < kW; ++k) acc = __builtin_elementwise_min(acc, __builtin_bit_cast(half2, w[k] ^ other[k]));
-    return acc.x == 0 || acc.y == 0;
+    // a zero half: (v - 0x00010001) & ~v has bit 15 or 31 set exactly when
+    // some half is zero (a borrow out of a zero low half can only touch the
+    // high half's test, and then the low half already answers)
+    const uint32_t v = __builtin_bit_cast(uint32_t, acc);
+    return ((v - 0x00010001u) & ~v & 0x80008000u) != 0u;
   }
 };
 
@@ -716,7 +722,10 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
     // Full tiles off the diagonal: thread t holds left row t mod tb_size in
     // registers and takes the columns of parity t / tb_size; the lanes of a
     // wave share every column, so its id and row are one LDS broadcast.
-    const uint32_t x = threadIdx.x % tb_size, y0 = threadIdx.x / tb_size;
+    // (y0 is uniform over a wave: a scalar, so the column loop's control
+    // stays off the vector unit)
+    const uint32_t x = threadIdx.x % tb_size;
+    const uint32_t y0 = __builtin_amdgcn_readfirstlane(threadIdx.x / tb_size);
     if (__ballot(x < na)) {
       const bool live = x < na;
       const uint32_t xs = live ? x : 0u;
@@ -733,19 +742,24 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       const bool clean = FAST && !use_flags && a.nstation == 1 && a.part_mode == 0 &&
                          idsB[0] - idsA[na - 1] >= a.min_lag;
       if (clean) {
+        // (the partner's id is read only when some lane's pair passes the
+        // sub-key test, which few do)
         for (uint32_t y = y0; y < nbm; y += 2, rowy += 2 * rswl)
           if (live) {
             uint32_t rv[RowReg<RSW>::kW];
             RowReg<RSW>::fetch(rowy, rv);
-            const uint32_t idy = idsB[y];
-            const bool cand = rx.any_equal(rv);
-            if (QUEUE) {
-              if (!enqueue_candidate(a, cand, u, idx, idy, tl.blk)) {
-                a.q_ovf[tl.blk] = 1;
-                *a.q_any = 1;
+            const uint64_t m = __ballot(rx.any_equal(rv));
+            if (m != 0) {
+              const bool cand = ((m >> (threadIdx.x & 63)) & 1u) != 0;
+              const uint32_t idy = idsB[y];
+              if (QUEUE) {
+                if (!enqueue_candidate(a, cand, u, idx, idy, tl.blk)) {
+                  a.q_ovf[tl.blk] = 1;
+                  *a.q_any = 1;
+                }
+              } else if (cand) {
+                check_candidate(a, u, idx, idy, rowx, rowy);
               }
-            } else if (cand) {
-              check_candidate(a, u, idx, idy, rowx, rowy);
             }
           }
         if (live) tl.ev += (nbm - y0 + 1) / 2;
