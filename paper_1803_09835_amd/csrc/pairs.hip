@@ -789,19 +789,66 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
       // y = (x + k) mod na and its row, stepped by two rows per round
       uint32_t y = xs + k0 < na ? xs + k0 : xs + k0 - na;
       const uint32_t* rowy = rowsA + y * rswl;
-      for (uint32_t k = k0; 2 * k <= na; k += 2) {
-        if (live && !(2 * k == na && x >= k)) {
-          const uint32_t idy = idsA[y];
-          const bool fw = y > x;  // selects, not branches: one inlined visit per lane
-          visit_pair<RSW, FAST, QUEUE>(a, u, fw ? idx : idy, fw ? idy : idx, rx, fw ? rowx : rowy, fw ? rowy : rowx, rowy,
-                                rsw, pad, tl);
+      // The plain search (FAST, one station, no member excluded): every pair
+      // is alive, so the loop runs the sub-key test alone, and the lag test
+      // and the partner's id wait for the few rounds in which some lane's
+      // pair passes it.  The tally is exact without a per-pair count: the
+      // threads of the first round parity add, for their row x, the pairs
+      // {x, y > x} less those closer than min_lag (ids ascend within a
+      // bucket, so those are the next few rows).
+      const bool plain = FAST && !use_flags && a.nstation == 1 && a.part_mode == 0;
+      if (plain) {
+        if (live && k0 == 1) {
+          uint32_t close = 0;
+          for (uint32_t z = x + 1; z < na && idsA[z] - idx < a.min_lag; ++z) ++close;
+          tl.ev += na - 1 - x - close;
         }
-        // next round: two rows on, wrapping past na (selects, no branch)
-        y += 2;
-        rowy += 2 * rswl;
-        const bool wrap = y >= na;
-        y = wrap ? y - na : y;
-        rowy = wrap ? rowy - na * rswl : rowy;
+        // only y's row offset is carried (y itself is recovered in the rare
+        // path); past the tile it wraps by an unsigned minimum, oy - span
+        // being the smaller exactly when oy >= span
+        uint32_t oy = y * rswl;
+        const uint32_t span = na * rswl;
+        for (uint32_t k = k0; 2 * k <= na; k += 2) {
+          if (live) {
+            const uint32_t* ry = rowsA + oy;
+            uint32_t rv[RowReg<RSW>::kW];
+            RowReg<RSW>::fetch(ry, rv);
+            const uint64_t m = __ballot(rx.any_equal(rv));
+            if (m != 0) {
+              const uint32_t yy = oy / rswl;
+              const uint32_t idy = idsA[yy];
+              const bool fw = yy > x;
+              const uint32_t i = fw ? idx : idy, j = fw ? idy : idx;
+              const bool cand = ((m >> (threadIdx.x & 63)) & 1u) != 0 && j - i >= a.min_lag &&
+                                !(2 * k == na && x >= k);
+              if (QUEUE) {
+                if (!enqueue_candidate(a, cand, u, i, j, tl.blk)) {
+                  a.q_ovf[tl.blk] = 1;
+                  *a.q_any = 1;
+                }
+              } else if (cand) {
+                check_candidate(a, u, i, j, fw ? rowx : ry, fw ? ry : rowx);
+              }
+            }
+          }
+          oy += 2 * rswl;
+          oy = min(oy, oy - span);
+        }
+      } else {
+        for (uint32_t k = k0; 2 * k <= na; k += 2) {
+          if (live && !(2 * k == na && x >= k)) {
+            const uint32_t idy = idsA[y];
+            const bool fw = y > x;  // selects, not branches: one inlined visit per lane
+            visit_pair<RSW, FAST, QUEUE>(a, u, fw ? idx : idy, fw ? idy : idx, rx, fw ? rowx : rowy, fw ? rowy : rowx,
+                                         rowy, rsw, pad, tl);
+          }
+          // next round: two rows on, wrapping past na (selects, no branch)
+          y += 2;
+          rowy += 2 * rswl;
+          const bool wrap = y >= na;
+          y = wrap ? y - na : y;
+          rowy = wrap ? rowy - na * rswl : rowy;
+        }
       }
     }
   } else {
