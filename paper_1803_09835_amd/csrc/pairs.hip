@@ -696,22 +696,21 @@ __global__ __launch_bounds__(kPT) void k_pairs_tile(PairArgs a, const uint64_t* 
   uint32_t* idsB = diag ? idsA : idsA + tb_size;
   const uint32_t g = u / a.tables_per_group;
   const uint32_t* R = a.rows + (uint64_t)g * a.n * a.row_pitch;
-  for (uint32_t q = threadIdx.x; q < na; q += kPT) idsA[q] = bid[a0 + q];
-  if (!diag)
-    for (uint32_t q = threadIdx.x; q < nbm; q += kPT) idsB[q] = bid[b0 + q];
-  __syncthreads();
-  // members excluded by the occurrence filter stay in place, marked dead
+  // Each thread stages the rows of the ids it loads (no barrier between);
+  // members excluded by the occurrence filter stay in place, marked dead.
+  // B's members start half a block on, so that for tiles of up to kPT / 2
+  // members every thread has one load chain.
   const bool use_flags = *a.n_flagged != 0;
   for (uint32_t q = threadIdx.x; q < na; q += kPT) {
-    const uint32_t id = idsA[q];
+    const uint32_t id = bid[a0 + q];
     stage_row<RSW>(R + (uint64_t)id * a.row_pitch, rowsA + q * rswl, rsw);
-    if (use_flags && a.flags[id]) idsA[q] = kDead;
+    idsA[q] = use_flags && a.flags[id] ? kDead : id;
   }
   if (!diag)
-    for (uint32_t q = threadIdx.x; q < nbm; q += kPT) {
-      const uint32_t id = idsB[q];
+    for (uint32_t q = (threadIdx.x + kPT / 2) % kPT; q < nbm; q += kPT) {
+      const uint32_t id = bid[b0 + q];
       stage_row<RSW>(R + (uint64_t)id * a.row_pitch, rowsB + q * rswl, rsw);
-      if (use_flags && a.flags[id]) idsB[q] = kDead;
+      idsB[q] = use_flags && a.flags[id] ? kDead : id;
     }
   __syncthreads();
   const uint32_t pad = group_pad(a, u, rsw);
